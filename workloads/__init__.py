@@ -1,0 +1,11 @@
+"""Seeded synthetic inputs shared by the tests, the bench and the oracle checks.
+
+This module holds no arithmetic of the solver: it only draws right-hand sides
+and initial data (sums of Gaussian bumps evaluated on the interior grid of a
+box) and the problem lists of the benchmark workloads.
+"""
+from .gen import (bump_field, grid_axis, workload_c1, workload_c2, workload_c3,
+                  workload_c4, white_noise, random_mask)
+
+__all__ = ["bump_field", "grid_axis", "workload_c1", "workload_c2", "workload_c3",
+           "workload_c4", "white_noise", "random_mask"]

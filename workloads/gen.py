@@ -1,0 +1,78 @@
+"""Seeded input generators (numpy PCG64).
+
+Draw order for a bump sum: centres (G x d), then widths (G), then amplitudes
+(G).  "Width" is the standard deviation of the bump.  Every field is float64
+C-contiguous with shape (n,)*d, last axis fastest, evaluated at the interior
+grid points x_j = lo + j h, j = 1..n, h = (hi - lo)/(n + 1).
+"""
+import numpy as np
+
+
+def grid_axis(n, lo=-1.0, hi=1.0):
+    h = (hi - lo) / (n + 1)
+    return lo + h * np.arange(1, n + 1), h
+
+
+def bump_field(n, d, nbumps, seed, width=(0.1, 0.3), centre=(-0.6, 0.6), lo=-1.0, hi=1.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = rng.uniform(centre[0], centre[1], size=(nbumps, d))
+    w = rng.uniform(width[0], width[1], size=nbumps)
+    a = rng.standard_normal(nbumps)
+    x, h = grid_axis(n, lo, hi)
+    out = np.zeros((n,) * d)
+    for g in range(nbumps):
+        val = a[g]
+        # separable evaluation: product over axes of exp(-(x - c)^2 / (2 w^2))
+        field = np.ones((1,) * d)
+        for ax in range(d):
+            e = np.exp(-((x - c[g, ax]) ** 2) / (2.0 * w[g] ** 2))
+            shape = [1] * d
+            shape[ax] = n
+            field = field * e.reshape(shape)
+        out += val * field
+    return np.ascontiguousarray(out), h
+
+
+def white_noise(shape, seed):
+    return np.random.Generator(np.random.PCG64(seed)).standard_normal(shape)
+
+
+def random_mask(shape, seed, frac_out=0.2):
+    """uint8 mask: an L-shaped occlusion plus a few random holes (1 = inside the domain)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = np.ones(shape, dtype=np.uint8)
+    sl = tuple(slice(s // 2, s) for s in shape[:2]) + tuple(slice(None) for _ in shape[2:])
+    m[sl] = 0
+    holes = rng.random(shape) < frac_out * 0.1
+    m[holes] = 0
+    return m
+
+
+def workload_c1(seed=1000):
+    """2D, alpha = 1, 64 x 64 on (-1,1)^2, 8 bumps, widths U[0.1,0.3], amplitudes N(0,1)."""
+    f, h = bump_field(64, 2, 8, seed, width=(0.1, 0.3))
+    return {"d": 2, "n": 64, "alpha": 1.0, "h": h, "f": f}
+
+
+def workload_c2(alpha=1.0, seed=2000):
+    """2D, 1024 x 1024 on (-1,1)^2, 32 bumps, widths U[0.05,0.2], amplitudes N(0,1)."""
+    f, h = bump_field(1024, 2, 32, seed, width=(0.05, 0.2))
+    return {"d": 2, "n": 1024, "alpha": alpha, "h": h, "f": f}
+
+
+def workload_c3(k, n=256, seed0=3000):
+    """3D, 256^3 on (-1,1)^3, alpha = 1.2, right-hand side k (16 bumps, C2 distributions)."""
+    f, h = bump_field(n, 3, 16, seed0 + k, width=(0.05, 0.2))
+    return {"d": 3, "n": n, "alpha": 1.2, "h": h, "f": f}
+
+
+def workload_c4(nprob=32, seed=4000, sizes=(128, 256, 384, 512)):
+    """Batch of uneven 2D backward-Euler problems: n from sizes, alpha ~ U[0.3, 1.8]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = rng.choice(np.array(sizes), size=nprob)
+    alphas = rng.uniform(0.3, 1.8, size=nprob)
+    probs = []
+    for i in range(nprob):
+        u0, h = bump_field(int(ns[i]), 2, 8, seed + 1 + i, width=(0.1, 0.3))
+        probs.append({"d": 2, "n": int(ns[i]), "alpha": float(alphas[i]), "h": h, "u0": u0})
+    return probs
