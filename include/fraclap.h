@@ -1,0 +1,166 @@
+/* fraclap.h -- C ABI of the MI355X (gfx950) fractional Laplacian solver.
+ *
+ * Method: Minden & Ying, "A simple solver for the fractional Laplacian in
+ * multiple dimensions".  The operator is the singularity-subtracted
+ * trapezoidal discretisation of (-Delta)^{alpha/2} (Sec. 2, eqs. fl,
+ * int1constants, a3, window) on a regular grid of n_1 x ... x n_d interior
+ * points with spacing h (Sec. 3.1, eq. linearelliptic):
+ *
+ *   (M u)_i = sum_j w_{i-j} u_j,  w_m = C h^{-alpha} omega_m,
+ *   omega_0 = Z - 2 d B, omega_{+-e_k} = -1 + B, omega_m = -|m|^{-(d+alpha)},
+ *
+ * with Z the lattice sum A_1 h^{d+alpha}, B = h^{d+alpha-2}(A_2 + A_3) and
+ * C = C_{alpha,d}.  M is applied as a zero-padded FFT convolution
+ * (Sec. 3.1, "Forward operator and application with FFT"); solves use CG
+ * preconditioned by the finite-difference Laplacian C h^d L applied with
+ * sine transforms (Sec. 3.1, "Preconditioning"); time steps use the implicit
+ * scheme of Sec. 3.2 (eq. timestepping) with theta in (0, 1].
+ *
+ * Conventions for every call:
+ *  - Arrays are DEVICE pointers owned by the caller, C-contiguous row-major
+ *    [batch][n_1]...[n_d] (last axis fastest).  The library never frees
+ *    caller memory.
+ *  - An fl_op owns its weights, symbol, transform tables and workspaces.  It
+ *    allocates in fl_make_weights and on the first call of each kind/size;
+ *    later calls of the same shape do not allocate.
+ *  - Work is ordered on the op's HIP stream (given at creation; NULL = the
+ *    null stream).  fl_apply / fl_precond return after enqueueing; fl_solve,
+ *    fl_step and the batched calls return after the final device poll with
+ *    `info` filled.
+ *  - A nonzero status is returned on any failure and nothing aborts;
+ *    fl_last_error() gives a thread-local message.  FL_E_NOCONV still leaves
+ *    the best iterate in the output and fills `info`.
+ *  - An op is not thread safe: use one op per host thread / stream.
+ */
+#ifndef FRACLAP_H
+#define FRACLAP_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fl_op_s* fl_op;
+
+typedef enum {
+  FL_OK = 0,
+  FL_E_INVALID = -1,     /* bad argument (d, alpha, h, sizes, tol, null pointer) */
+  FL_E_NOMEM = -2,       /* device allocation failed */
+  FL_E_HIP = -3,         /* HIP runtime error */
+  FL_E_NOCONV = -4,      /* iteration cap reached before the tolerance */
+  FL_E_BREAKDOWN = -5,   /* p.q <= 0 or a non-finite value in the recurrence */
+  FL_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+} fl_status;
+
+typedef enum { FL_F64 = 0, FL_F32 = 1 } fl_dtype;
+
+typedef enum {
+  FL_PC_NONE = 0,  /* plain CG */
+  FL_PC_FD = 1     /* finite-difference Laplacian preconditioner (Sec. 3.1) */
+} fl_precond_kind;
+
+typedef struct {
+  double delta_over_h;  /* window radius c in grid points (Sec. 4.1 uses 20); <= 0 -> 20 */
+  int reserved[6];
+} fl_weights_opts;
+
+typedef struct {
+  int pc;            /* fl_precond_kind */
+  int mixed;         /* 0: FP64 PCG; 1: FP32 inner PCG + FP64 iterative refinement */
+  int maxit;         /* iteration cap (FP64 PCG) or inner cap (mixed); <= 0 -> default */
+  double inner_tol;  /* mixed: relative tolerance of each inner FP32 solve; <= 0 -> 1e-4 */
+  int use_x0;        /* 1: u holds the initial guess on entry */
+  int graph;         /* 1: replay the Krylov iteration as a captured hipGraph */
+  int poll_every;    /* iterations between host polls of the convergence flag (<= 0 -> 8) */
+  int max_outer;     /* mixed: cap on refinement steps (<= 0 -> 12) */
+} fl_solve_opts;
+
+typedef struct {
+  int iters;         /* Krylov iterations (sum over inner solves when mixed) */
+  int outer_iters;   /* refinement steps (mixed) */
+  int status;        /* fl_status of the solve */
+  int reserved;
+  double rel_res_true;   /* ||f - M u||_2 / ||f||_2 recomputed in FP64 at exit */
+  double rel_res_recur;  /* last recurrence residual of the (inner) Krylov loop */
+  double ms;             /* wall time of the call, milliseconds */
+} fl_info;
+
+/* Build M for dimension d in {1,2,3}, 0 < alpha < 2, spacing h > 0 and grid
+ * n[0..d-1] (each >= 1): constants C, Z, B (FP64, one workgroup), the folded
+ * weight array, the symbol lambda = DFT of the circulant embedding of the
+ * weights (padded length per axis: smallest even 2^a 3^b 5^c >= 2 n_k; lags
+ * >= n_k of the embedding are zero), FP64 and FP32 copies, and the transform
+ * tables.  Paper: Sec. 2.7 (constants), Sec. 3.1 (M and its FFT application).
+ * `opts` may be NULL.  On success *out owns all device memory of the op. */
+fl_status fl_make_weights(int d, double alpha, double h, const int64_t* n, const fl_weights_opts* opts,
+                          void* hip_stream, fl_op* out);
+
+/* Host FP64 copy of the scalar constants:
+ * out[0..7] = C, Z, B, a2, h^{d+alpha-2} A_3, omega_0, omega_e, C h^{-alpha}. */
+fl_status fl_op_constants(fl_op op, double out[8]);
+
+/* Padded circulant lengths P_k (out[0..d-1]). */
+fl_status fl_op_padded(fl_op op, int64_t* out);
+
+/* Device-to-device copy of the folded arrays, shape [P_1/2+1]...[P_d/2+1]:
+ * which = 0: weights w_m (FP64, zero for m_k >= n_k); 1: symbol lambda (FP64);
+ * 2: symbol lambda (FP32).  dst must hold prod(P_k/2+1) elements. */
+fl_status fl_op_export(fl_op op, int which, void* dst);
+
+/* Mu = M u for `batch` stacked inputs (dtype FL_F64 or FL_F32, both arrays of
+ * that type).  mask (uint8 [n...], 1 = inside, may be NULL) gives the occluded
+ * operator P_Omega M P_Omega.  shift0/shift1: computes (shift0 I + shift1 M) u
+ * (pass 0, 1 for M itself).  Paper Sec. 3.1, "Forward operator". */
+fl_status fl_apply(fl_op op, const void* u, void* Mu, int dtype, int64_t batch, const uint8_t* mask,
+                   double shift0, double shift1);
+
+/* z = (p0 I + p1 C h^d L)^{-1} r on the box (mask applied on input and output
+ * if given), sine transforms along every axis.  p0 = 0, p1 = 1 is the
+ * elliptic preconditioner; p0 = 1, p1 = theta dt the time-step one.
+ * Paper Sec. 3.1 ("Preconditioning") and Sec. 3.2. */
+fl_status fl_precond(fl_op op, const void* r, void* z, int dtype, int64_t batch, const uint8_t* mask,
+                     double p0, double p1);
+
+/* Solve M u = f (FP64 f and u, single right-hand side) to relative residual
+ * tol (recurrence residual in the loop; the true FP64 residual is reported).
+ * Paper Sec. 3.1 (eq. matelliptic) and Sec. 4 (stopping test). */
+fl_status fl_solve(fl_op op, const double* f, const uint8_t* mask, double tol, const fl_solve_opts* opts,
+                   double* u, fl_info* info);
+
+/* One implicit step: (I + theta dt M) u^{k+1} = (I - (1-theta) dt M) u^k
+ *                    + dt (theta f^{k+1} + (1-theta) f^k),
+ * preconditioner I + theta dt C h^d L, warm start u^k.  u: u^k in, u^{k+1}
+ * out (FP64).  f_k, f_k1 may be NULL (zero forcing).  theta in (0, 1]
+ * (0.5 Crank-Nicolson as in Sec. 3.2, 1 backward Euler). */
+fl_status fl_step(fl_op op, double* u, double dt, double theta, const double* f_k, const double* f_k1,
+                  const uint8_t* mask, double tol, const fl_solve_opts* opts, fl_info* info);
+
+/* Solve nprob independent systems ops[i] u[i] = f[i] together: every kernel
+ * of an iteration is one launch over all problems (uneven sizes and alphas
+ * allowed; problems may share an op).  masks may be NULL or hold NULLs.
+ * infos[i] receives each problem's result. */
+fl_status fl_solve_batched(int nprob, const fl_op* ops, const double* const* f, const uint8_t* const* masks,
+                           double tol, const fl_solve_opts* opts, double* const* u, fl_info* infos);
+
+/* Advance nprob problems by nsteps implicit steps each (zero forcing), all
+ * problems per launch; dt[i] per problem; u[i] in/out (FP64). */
+fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const double* dt, double theta,
+                          int nsteps, double tol, const fl_solve_opts* opts, fl_info* infos);
+
+/* Measurement aid: average duration (ms, HIP events on the op's stream) of
+ * `reps` back-to-back launches of one pass on the op's zero-filled workspace.
+ * pass: 0 row FFT forward, 1 symbol column pass (axis 0), 2 row FFT inverse,
+ * 3 first sine pass, 4 scaled sine column pass, 5 last sine pass,
+ * 6 whole application of M, 7 whole preconditioner.  Single passes need d >= 2. */
+fl_status fl_profile_pass(fl_op op, int dtype, int pass, int reps, double* avg_ms);
+
+/* Release every device resource of the op. */
+fl_status fl_op_destroy(fl_op op);
+
+/* Thread-local description of the last failure ("" if none). */
+const char* fl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRACLAP_H */

@@ -1,0 +1,259 @@
+"""Python binding of libfraclap (MI355X / gfx950 fractional Laplacian solver).
+
+Argument marshalling only: every step of the method runs in the HIP library
+behind the C ABI declared in include/fraclap.h.  Device memory and streams
+come from PyTorch (ROCm).  There is no CPU fallback: if the library is not
+built or no GPU is present, every call raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfraclap.so")
+
+FL_OK, FL_E_INVALID, FL_E_NOMEM, FL_E_HIP, FL_E_NOCONV, FL_E_BREAKDOWN, FL_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FL_F64, FL_F32 = 0, 1
+FL_PC_NONE, FL_PC_FD = 0, 1
+STATUS_NAMES = {0: "ok", -1: "invalid", -2: "nomem", -3: "hip", -4: "noconv", -5: "breakdown", -6: "unsupported"}
+
+EXPORTED = ["fl_make_weights", "fl_op_constants", "fl_op_padded", "fl_op_export", "fl_apply", "fl_precond",
+            "fl_solve", "fl_step", "fl_solve_batched", "fl_step_batched", "fl_profile_pass", "fl_op_destroy",
+            "fl_last_error"]
+
+
+class FlError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fraclap status {status} ({STATUS_NAMES.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class WeightsOpts(ctypes.Structure):
+    _fields_ = [("delta_over_h", ctypes.c_double), ("reserved", ctypes.c_int * 6)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("pc", ctypes.c_int), ("mixed", ctypes.c_int), ("maxit", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("use_x0", ctypes.c_int), ("graph", ctypes.c_int),
+                ("poll_every", ctypes.c_int), ("max_outer", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("rel_res_true", ctypes.c_double),
+                ("rel_res_recur", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+    lib = ctypes.CDLL(path)
+    P, I, D, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+    sig = {
+        "fl_make_weights": [I, D, D, ctypes.POINTER(I64), ctypes.POINTER(WeightsOpts), P, ctypes.POINTER(P)],
+        "fl_op_constants": [P, ctypes.POINTER(D)],
+        "fl_op_padded": [P, ctypes.POINTER(I64)],
+        "fl_op_export": [P, I, P],
+        "fl_apply": [P, P, P, I, I64, P, D, D],
+        "fl_precond": [P, P, P, I, I64, P, D, D],
+        "fl_solve": [P, P, P, D, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(Info)],
+        "fl_step": [P, P, D, D, P, P, P, D, ctypes.POINTER(SolveOpts), ctypes.POINTER(Info)],
+        "fl_solve_batched": [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), D,
+                             ctypes.POINTER(SolveOpts), ctypes.POINTER(P), ctypes.POINTER(Info)],
+        "fl_step_batched": [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(D), D, I, D,
+                            ctypes.POINTER(SolveOpts), ctypes.POINTER(Info)],
+        "fl_profile_pass": [P, I, I, I, ctypes.POINTER(D)],
+        "fl_op_destroy": [P],
+        "fl_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "fl_last_error" else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != FL_OK:
+        raise FlError(status, load().fl_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need(t, dtype, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return t
+
+
+def solve_opts(pc=FL_PC_FD, mixed=0, maxit=0, inner_tol=0.0, use_x0=0, graph=1, poll_every=8, max_outer=0):
+    return SolveOpts(pc, mixed, maxit, inner_tol, use_x0, graph, poll_every, max_outer)
+
+
+class Op:
+    """fl_op handle: the discrete fractional Laplacian M on an n_1 x ... x n_d grid."""
+
+    def __init__(self, d, alpha, h, n, delta_over_h=20.0, stream=None):
+        lib = load()
+        self.d, self.alpha, self.h = int(d), float(alpha), float(h)
+        self.n = tuple(int(v) for v in (n if hasattr(n, "__len__") else [n] * d))
+        if len(self.n) != self.d:
+            raise ValueError("len(n) must equal d")
+        if stream is None:
+            # a private stream of default priority: hipGraph capture needs a non-null stream
+            stream = torch.cuda.Stream()
+        self.stream = stream
+        arr = (ctypes.c_int64 * 3)(*(list(self.n) + [1] * (3 - self.d)))
+        opts = WeightsOpts(delta_over_h, (ctypes.c_int * 6)())
+        h_ = ctypes.c_void_p()
+        _check(lib.fl_make_weights(self.d, self.alpha, self.h, arr, ctypes.byref(opts),
+                                   ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h_)))
+        self._h = h_
+        self.N = 1
+        for v in self.n:
+            self.N *= v
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().fl_op_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def constants(self):
+        out = (ctypes.c_double * 8)()
+        _check(load().fl_op_constants(self._h, out))
+        return dict(zip(["C", "Z", "B", "a2", "a3s", "omega0", "omega_e", "Chma"], list(out)))
+
+    def padded(self):
+        out = (ctypes.c_int64 * 3)()
+        _check(load().fl_op_padded(self._h, out))
+        return tuple(out[i] for i in range(self.d))
+
+    def export(self, which):
+        shape = tuple(p // 2 + 1 for p in self.padded())
+        t = torch.empty(shape, dtype=torch.float32 if which == 2 else torch.float64, device="cuda")
+        _check(load().fl_op_export(self._h, which, _ptr(t)))
+        self.stream.synchronize()
+        return t
+
+    def profile_pass(self, dtype, which, reps=50):
+        """Average ms per launch of one pass (HIP events on the op stream)."""
+        ms = ctypes.c_double()
+        _check(load().fl_profile_pass(self._h, FL_F64 if dtype == torch.float64 else FL_F32, which, reps,
+                                      ctypes.byref(ms)))
+        return ms.value
+
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream())
+
+    def _leave(self):
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def _batch(self, u):
+        if u.numel() % self.N:
+            raise ValueError("input size is not a multiple of the grid size")
+        return u.numel() // self.N
+
+    def apply(self, u, mask=None, shift0=0.0, shift1=1.0, out=None):
+        dt = FL_F64 if u.dtype == torch.float64 else FL_F32
+        _need(u, u.dtype, name="u")
+        if u.dtype not in (torch.float64, torch.float32):
+            raise ValueError("u must be float64 or float32")
+        _need(mask, torch.uint8, self.N, "mask")
+        out = torch.empty_like(u) if out is None else _need(out, u.dtype, u.numel(), "out")
+        self._enter()
+        _check(load().fl_apply(self._h, _ptr(u), _ptr(out), dt, self._batch(u), _ptr(mask), shift0, shift1))
+        self._leave()
+        return out
+
+    def precond(self, r, mask=None, p0=0.0, p1=1.0, out=None):
+        dt = FL_F64 if r.dtype == torch.float64 else FL_F32
+        _need(r, r.dtype, name="r")
+        _need(mask, torch.uint8, self.N, "mask")
+        out = torch.empty_like(r) if out is None else _need(out, r.dtype, r.numel(), "out")
+        self._enter()
+        _check(load().fl_precond(self._h, _ptr(r), _ptr(out), dt, self._batch(r), _ptr(mask), p0, p1))
+        self._leave()
+        return out
+
+    def solve(self, f, mask=None, tol=1e-10, opts=None, u=None, check=True):
+        _need(f, torch.float64, self.N, "f")
+        _need(mask, torch.uint8, self.N, "mask")
+        u = torch.zeros_like(f) if u is None else _need(u, torch.float64, self.N, "u")
+        info = Info()
+        self._enter()
+        st = load().fl_solve(self._h, _ptr(f), _ptr(mask), tol, ctypes.byref(opts or solve_opts()), _ptr(u),
+                             ctypes.byref(info))
+        if check:
+            _check(st)
+        return u, info.as_dict()
+
+    def step(self, u, dt, theta=1.0, f_k=None, f_k1=None, mask=None, tol=1e-10, opts=None, check=True):
+        _need(u, torch.float64, self.N, "u")
+        _need(f_k, torch.float64, self.N, "f_k")
+        _need(f_k1, torch.float64, self.N, "f_k1")
+        _need(mask, torch.uint8, self.N, "mask")
+        info = Info()
+        self._enter()
+        st = load().fl_step(self._h, _ptr(u), dt, theta, _ptr(f_k), _ptr(f_k1), _ptr(mask), tol,
+                            ctypes.byref(opts or solve_opts()), ctypes.byref(info))
+        if check:
+            _check(st)
+        return u, info.as_dict()
+
+
+def solve_batched(ops, fs, tol=1e-10, opts=None, masks=None, us=None):
+    lib = load()
+    k = len(ops)
+    us = us or [torch.zeros_like(f) for f in fs]
+    P = ctypes.c_void_p
+    hops = (P * k)(*[o._h for o in ops])
+    for o in ops:
+        o._enter()
+    hf = (P * k)(*[f.data_ptr() for f in fs])
+    hm = (P * k)(*[0 if (masks is None or masks[i] is None) else masks[i].data_ptr() for i in range(k)])
+    hu = (P * k)(*[u.data_ptr() for u in us])
+    infos = (Info * k)()
+    _check(lib.fl_solve_batched(k, hops, hf, hm, tol, ctypes.byref(opts or solve_opts()), hu, infos))
+    return us, [i.as_dict() for i in infos]
+
+
+def step_batched(ops, us, dts, theta=1.0, nsteps=1, tol=1e-10, opts=None):
+    lib = load()
+    k = len(ops)
+    P = ctypes.c_void_p
+    hops = (P * k)(*[o._h for o in ops])
+    for o in ops:
+        o._enter()
+    hu = (P * k)(*[u.data_ptr() for u in us])
+    hdt = (ctypes.c_double * k)(*dts)
+    infos = (Info * k)()
+    _check(lib.fl_step_batched(k, hops, hu, hdt, theta, nsteps, tol, ctypes.byref(opts or solve_opts()), infos))
+    return us, [i.as_dict() for i in infos]

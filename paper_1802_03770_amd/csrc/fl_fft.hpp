@@ -1,0 +1,200 @@
+// Line FFT engine for gfx950: one or more complex lines held in LDS, transformed
+// in place by a Stockham autosort FFT whose radix sequence is chosen at run time
+// (radices 2, 3, 4, 5, 8).  Every thread of a line keeps its butterflies in
+// registers between the LDS read and the LDS write of a stage, so one LDS buffer
+// per line suffices.  A workgroup holds G lines of equal length; each line is
+// served by `tpl` consecutive lanes (a power of two), so G * tpl = blockDim.x.
+//
+// Twiddles come from a table of the L-th roots of unity e^{-2 pi i m / L}
+// (computed on the host in extended precision).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fl {
+
+template <typename T> struct cx { T x, y; };
+
+template <typename T> __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T> __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV> __device__ __forceinline__ cx<T> mul_mi(cx<T> a) {
+  return INV ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
+}
+
+constexpr int kMaxStages = 16;
+constexpr int kMaxElems = 16;  // elements of one line held per lane
+
+struct FFTPlan {
+  int L;                 // transform length
+  int nst;               // number of stages
+  int tpl;               // lanes per line (power of two)
+  int rad[kMaxStages];   // radix of each stage
+  const void* tw;        // cx<T>[L] = e^{-2 pi i m / L}
+};
+
+template <typename T, int R, bool INV> struct Bfly;
+
+template <typename T, bool INV> struct Bfly<T, 2, INV> {
+  static __device__ __forceinline__ void run(cx<T>* a) {
+    cx<T> t = a[1];
+    a[1] = csub(a[0], t);
+    a[0] = cadd(a[0], t);
+  }
+};
+
+template <typename T, bool INV> struct Bfly<T, 4, INV> {
+  static __device__ __forceinline__ void run(cx<T>* a) {
+    cx<T> t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    cx<T> t2 = cadd(a[1], a[3]), t3 = mul_mi<T, INV>(csub(a[1], a[3]));
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
+  }
+};
+
+template <typename T, bool INV> struct Bfly<T, 8, INV> {
+  static __device__ __forceinline__ void run(cx<T>* a) {
+    const T r2 = (T)0.70710678118654752440084436210484904L;
+    // radix-4 on even and odd halves
+    cx<T> e[4] = {a[0], a[2], a[4], a[6]};
+    cx<T> o[4] = {a[1], a[3], a[5], a[7]};
+    Bfly<T, 4, INV>::run(e);
+    Bfly<T, 4, INV>::run(o);
+    // twiddles w8^k, k = 0..3  (w8 = e^{-+2 pi i / 8})
+    cx<T> o1 = INV ? cx<T>{r2 * (o[1].x - o[1].y), r2 * (o[1].x + o[1].y)}
+                   : cx<T>{r2 * (o[1].x + o[1].y), r2 * (o[1].y - o[1].x)};
+    cx<T> o2 = mul_mi<T, INV>(o[2]);
+    cx<T> o3 = INV ? cx<T>{-r2 * (o[3].x + o[3].y), r2 * (o[3].x - o[3].y)}
+                   : cx<T>{r2 * (o[3].y - o[3].x), -r2 * (o[3].x + o[3].y)};
+    a[0] = cadd(e[0], o[0]);
+    a[4] = csub(e[0], o[0]);
+    a[1] = cadd(e[1], o1);
+    a[5] = csub(e[1], o1);
+    a[2] = cadd(e[2], o2);
+    a[6] = csub(e[2], o2);
+    a[3] = cadd(e[3], o3);
+    a[7] = csub(e[3], o3);
+  }
+};
+
+template <typename T, bool INV> struct Bfly<T, 3, INV> {
+  static __device__ __forceinline__ void run(cx<T>* a) {
+    const T s = (T)0.86602540378443864676372317075293618L;  // sin(2 pi / 3)
+    cx<T> sum = cadd(a[1], a[2]);
+    cx<T> dif = csub(a[1], a[2]);
+    cx<T> m = {a[0].x - (T)0.5 * sum.x, a[0].y - (T)0.5 * sum.y};
+    // forward: y1 = m - i s dif, y2 = m + i s dif
+    cx<T> isd = {-s * dif.y, s * dif.x};  // i s dif
+    a[0] = cadd(a[0], sum);
+    if (INV) {
+      a[1] = cadd(m, isd);
+      a[2] = csub(m, isd);
+    } else {
+      a[1] = csub(m, isd);
+      a[2] = cadd(m, isd);
+    }
+  }
+};
+
+template <typename T, bool INV> struct Bfly<T, 5, INV> {
+  static __device__ __forceinline__ void run(cx<T>* a) {
+    const T c1 = (T)0.30901699437494742410229341718281906L;   // cos(2pi/5)
+    const T c2 = (T)-0.80901699437494742410229341718281906L;  // cos(4pi/5)
+    const T s1 = (T)0.95105651629515357211643933337938214L;   // sin(2pi/5)
+    const T s2 = (T)0.58778525229247312916870595463907277L;   // sin(4pi/5)
+    cx<T> b1 = cadd(a[1], a[4]), d1 = csub(a[1], a[4]);
+    cx<T> b2 = cadd(a[2], a[3]), d2 = csub(a[2], a[3]);
+    cx<T> m1 = {a[0].x + c1 * b1.x + c2 * b2.x, a[0].y + c1 * b1.y + c2 * b2.y};
+    cx<T> m2 = {a[0].x + c2 * b1.x + c1 * b2.x, a[0].y + c2 * b1.y + c1 * b2.y};
+    // forward: y1 = m1 - i (s1 d1 + s2 d2), y4 = m1 + i(...)
+    //          y2 = m2 - i (s2 d1 - s1 d2), y3 = m2 + i(...)
+    cx<T> t1 = {s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y};
+    cx<T> t2 = {s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y};
+    cx<T> it1 = {-t1.y, t1.x}, it2 = {-t2.y, t2.x};
+    a[0] = {a[0].x + b1.x + b2.x, a[0].y + b1.y + b2.y};
+    if (INV) {
+      a[1] = cadd(m1, it1);
+      a[4] = csub(m1, it1);
+      a[2] = cadd(m2, it2);
+      a[3] = csub(m2, it2);
+    } else {
+      a[1] = csub(m1, it1);
+      a[4] = cadd(m1, it1);
+      a[2] = csub(m2, it2);
+      a[3] = cadd(m2, it2);
+    }
+  }
+};
+
+// One Stockham stage of radix R on the line `buf` (length L, LDS).  Ns is the
+// product of the radices already applied.  Input butterfly j reads
+// buf[j + r L/R]; it is twiddled by w_{Ns R}^{r k} with k = j mod Ns and
+// written to buf[(j / Ns) Ns R + k + r Ns].
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, int L, int Ns, const cx<T>* __restrict__ tw,
+                                          int lane, int tpl) {
+  constexpr int MB = kMaxElems / R;
+  const int nb = L / R;
+  const int tstep = L / (Ns * R);
+  cx<T> v[MB][R];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int j = lane + b * tpl;
+    if (j < nb) {
+      const int k = j % Ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * nb];
+      if (Ns > 1) {
+        const int st = k * tstep;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = tw[r * st];
+          v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
+        }
+      }
+      Bfly<T, R, INV>::run(v[b]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int j = lane + b * tpl;
+    if (j < nb) {
+      const int k = j % Ns;
+      const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full in-place FFT of the LDS line `buf` (unnormalised in both directions).
+// Every lane of the workgroup must call this (it contains barriers).
+template <typename T, bool INV>
+__device__ void fft_line(cx<T>* buf, const FFTPlan& pl, int lane) {
+  const cx<T>* __restrict__ tw = (const cx<T>*)pl.tw;
+  int Ns = 1;
+  for (int s = 0; s < pl.nst; ++s) {
+    const int R = pl.rad[s];
+    switch (R) {
+      case 8: fft_stage<T, 8, INV>(buf, pl.L, Ns, tw, lane, pl.tpl); break;
+      case 4: fft_stage<T, 4, INV>(buf, pl.L, Ns, tw, lane, pl.tpl); break;
+      case 2: fft_stage<T, 2, INV>(buf, pl.L, Ns, tw, lane, pl.tpl); break;
+      case 3: fft_stage<T, 3, INV>(buf, pl.L, Ns, tw, lane, pl.tpl); break;
+      default: fft_stage<T, 5, INV>(buf, pl.L, Ns, tw, lane, pl.tpl); break;
+    }
+    Ns *= R;
+  }
+}
+
+}  // namespace fl

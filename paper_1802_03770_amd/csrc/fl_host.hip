@@ -1,0 +1,924 @@
+// Host driver and C ABI of the fractional Laplacian library (gfx950).
+//
+// Operator construction (Sec. 2.7 constants, Sec. 3.1 operator), FFT
+// application (Sec. 3.1), sine-transform preconditioner (Sec. 3.1), PCG with
+// the relative-residual test (Sec. 4), FP64 iterative refinement around an
+// FP32 inner PCG, implicit theta steps (Sec. 3.2) and batched solves.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <complex>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fraclap.h"
+#include "fl_kernels.hpp"
+
+using namespace fl;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+static fl_status fail(fl_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return fail(FL_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define STCHK(x)                     \
+  do {                               \
+    fl_status s_ = (x);              \
+    if (s_ != FL_OK) return s_;      \
+  } while (0)
+
+template <typename K, typename... A>
+static hipError_t launch(K* k, dim3 g, dim3 b, size_t smem, hipStream_t s, A... args) {
+  if (g.x == 0 || g.y == 0) return hipSuccess;
+  if (smem > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k, g, b, smem, s, args...);
+  return hipGetLastError();
+}
+#define LAUNCH(...) HIPCHK(launch(__VA_ARGS__))
+
+// ---------------------------------------------------------------------------
+// plans and tables
+// ---------------------------------------------------------------------------
+static bool smooth235(long m) {
+  for (int p : {2, 3, 5})
+    while (m % p == 0) m /= p;
+  return m == 1;
+}
+static int padded_length(int n) {
+  int P = 2 * n;
+  while (!smooth235(P / 2)) P += 2;
+  return P;
+}
+static int smooth_at_least(int m) {
+  int L = std::max(m, 2);
+  while (!smooth235(L)) ++L;
+  return L;
+}
+
+static bool make_radices(int L, FFTPlan& pl) {
+  std::vector<int> r;
+  int m = L;
+  while (m % 8 == 0) { r.push_back(8); m /= 8; }
+  while (m % 4 == 0) { r.push_back(4); m /= 4; }
+  while (m % 2 == 0) { r.push_back(2); m /= 2; }
+  while (m % 3 == 0) { r.push_back(3); m /= 3; }
+  while (m % 5 == 0) { r.push_back(5); m /= 5; }
+  if (m != 1 || (int)r.size() > kMaxStages) return false;
+  pl.L = L;
+  pl.nst = (int)r.size();
+  for (int i = 0; i < kMaxStages; ++i) pl.rad[i] = i < pl.nst ? r[i] : 1;
+  int tpl = 1;
+  while (tpl * kMaxElems < L) tpl *= 2;
+  for (;;) {
+    bool ok = true;
+    for (int R : r) {
+      int nb = L / R, per = (nb + tpl - 1) / tpl;
+      if (per > kMaxElems / R) ok = false;
+    }
+    if (ok) break;
+    tpl *= 2;
+  }
+  pl.tpl = tpl;
+  return true;
+}
+
+static const long double kPiL = 3.141592653589793238462643383279502884197L;
+
+// device table of e^{-2 pi i m / L}, m < L, in T
+template <typename T> struct DevTab {
+  std::vector<void*> owned;
+};
+
+struct fl_op_s;
+
+template <typename T> static std::vector<cx<T>> host_twiddles(int L) {
+  std::vector<cx<T>> t(L);
+  for (int m = 0; m < L; ++m) {
+    long double a = 2.0L * kPiL * (long double)m / (long double)L;
+    t[m] = {(T)cosl(a), (T)(-sinl(a))};
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// operator object
+// ---------------------------------------------------------------------------
+struct Workspace {
+  long cap_rhs = 0;        // apply/precond batch capacity
+  void* W1 = nullptr;
+  void* W2 = nullptr;
+  void* T1 = nullptr;
+  bool solver = false;     // Krylov vectors allocated
+  void *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *f = nullptr;
+  Scalars* sc = nullptr;
+  double* part = nullptr;
+  long npart = 0;
+  // graph of `gK` PCG iterations starting at an odd iteration
+  hipGraphExec_t gexec = nullptr;
+  int gK = 0, gpc = -1;
+  double gs0 = 0, gs1 = 0, gp0 = 0, gp1 = 0;
+  const uint8_t* gmask = nullptr;
+};
+
+struct fl_op_s {
+  int d = 0;
+  double alpha = 0, h = 0, c = 20;
+  int n[3] = {1, 1, 1}, P[3] = {2, 2, 2}, H[3] = {1, 1, 1};
+  long N = 0, NH = 0;
+  hipStream_t stream = nullptr;
+  double cst[8] = {0};
+  double* d_cst = nullptr;
+  double* wf = nullptr;     // folded weights [H...] FP64
+  void* lam[2] = {nullptr, nullptr};  // folded symbol FP64 / FP32
+  Axis ax[2][3];            // per dtype
+  std::vector<void*> tables;
+  Workspace ws[2];
+  Scalars* hsc = nullptr;   // pinned host mirror of a Scalars
+  ~fl_op_s();
+};
+
+template <typename T> static constexpr int tix() { return sizeof(T) == 8 ? 0 : 1; }
+
+static fl_status dalloc(void** p, size_t bytes) {
+  if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+    *p = nullptr;
+    return fail(FL_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return FL_OK;
+}
+
+template <typename T> static fl_status upload(fl_op op, const std::vector<T>& h, const void** out) {
+  void* p;
+  STCHK(dalloc(&p, h.size() * sizeof(T)));
+  op->tables.push_back(p);
+  HIPCHK(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = p;
+  return FL_OK;
+}
+
+template <typename T> static fl_status build_axis(fl_op op, int a) {
+  Axis& A = op->ax[tix<T>()][a];
+  const int n = op->n[a];
+  A.n = n;
+  A.P = op->P[a];
+  A.H = op->H[a];
+  if (!make_radices(A.P, A.fft)) return fail(FL_E_UNSUPPORTED, "padded length not 2,3,5-smooth");
+  STCHK(upload(op, host_twiddles<T>(A.P), &A.fft.tw));
+  // sine transform by the chirp-z identity
+  const int Lb = smooth_at_least(2 * n - 1);
+  if (!make_radices(Lb, A.dst)) return fail(FL_E_UNSUPPORTED, "sine transform length");
+  STCHK(upload(op, host_twiddles<T>(Lb), &A.dst.tw));
+  const long N1 = n + 1;
+  std::vector<cx<T>> ch(n + 1);
+  std::vector<std::complex<long double>> chl(n + 1);
+  for (long m = 0; m <= n; ++m) {
+    long q = (m * m) % (4 * N1);  // e^{i pi m^2 / (2 N1)} has period 4 N1 in m^2
+    long double ph = kPiL * (long double)q / (2.0L * (long double)N1);
+    chl[m] = {cosl(ph), sinl(ph)};
+    ch[m] = {(T)chl[m].real(), (T)chl[m].imag()};
+  }
+  STCHK(upload(op, ch, &A.chirp));
+  // bhat = DFT_Lb(b~) / Lb, b~[m mod Lb] = conj(ch[|m|]) for |m| <= n-1
+  std::vector<std::complex<long double>> tw(Lb);
+  for (int m = 0; m < Lb; ++m) {
+    long double ang = 2.0L * kPiL * m / Lb;
+    tw[m] = {cosl(ang), -sinl(ang)};
+  }
+  std::vector<std::pair<int, std::complex<long double>>> nz;
+  for (int m = -(n - 1); m <= n - 1; ++m) nz.push_back({((m % Lb) + Lb) % Lb, std::conj(chl[std::abs(m)])});
+  std::vector<cx<T>> bh(Lb);
+  for (int k = 0; k < Lb; ++k) {
+    std::complex<long double> s = 0;
+    for (auto& e : nz) s += e.second * tw[((long)e.first * k) % Lb];
+    s /= (long double)Lb;
+    bh[k] = {(T)s.real(), (T)s.imag()};
+  }
+  STCHK(upload(op, bh, &A.bhat));
+  std::vector<T> ev(n);
+  for (int k = 0; k < n; ++k) {
+    long double sn = sinl(kPiL * (k + 1) / (2.0L * N1));
+    ev[k] = (T)(4.0L * sn * sn);
+  }
+  STCHK(upload(op, ev, &A.eig));
+  return FL_OK;
+}
+
+fl_op_s::~fl_op_s() {
+  for (void* p : tables) hipFree(p);
+  for (auto& w : ws) {
+    for (void* p : {w.W1, w.W2, w.T1, w.x, w.r, w.z, w.p, w.q, w.f}) if (p) hipFree(p);
+    if (w.sc) hipFree(w.sc);
+    if (w.part) hipFree(w.part);
+    if (w.gexec) hipGraphExecDestroy(w.gexec);
+  }
+  if (d_cst) hipFree(d_cst);
+  if (wf) hipFree(wf);
+  for (void* p : lam) if (p) hipFree(p);
+  if (hsc) hipHostFree(hsc);
+}
+
+// block size for a line-FFT kernel with `tpl` lanes per line
+static int block_for(int tpl) { return std::max(256, tpl); }
+
+// ---------------------------------------------------------------------------
+// problem descriptors
+// ---------------------------------------------------------------------------
+template <typename T> static Prob base_prob(fl_op op, long nrhs) {
+  Prob pb;
+  memset(&pb, 0, sizeof(pb));
+  pb.d = op->d;
+  pb.nrhs = (int)nrhs;
+  for (int a = 0; a < 3; ++a) pb.ax[a] = op->ax[tix<T>()][a];
+  pb.lam = op->lam[tix<T>()];
+  pb.s0 = 0.0;
+  pb.s1 = 1.0;
+  pb.pcs = op->cst[0] * std::fabs(op->cst[2]) * std::pow(op->h, -op->alpha);
+  pb.p0 = 0.0;
+  pb.p1 = 1.0;
+  return pb;
+}
+
+static long rows_of(fl_op op, long nrhs) {
+  long r = nrhs;
+  for (int a = 0; a < op->d - 1; ++a) r *= op->n[a];
+  return r;
+}
+
+template <typename T> static fl_status ensure_ws(fl_op op, long nrhs, bool solver) {
+  Workspace& w = op->ws[tix<T>()];
+  const long N = op->N;
+  if (w.cap_rhs < nrhs) {
+    for (void** p : {&w.W1, &w.W2, &w.T1})
+      if (*p) { hipFree(*p); *p = nullptr; }
+    long rows = rows_of(op, nrhs);
+    STCHK(dalloc(&w.W1, (size_t)rows * op->H[op->d - 1] * sizeof(cx<T>)));
+    if (op->d == 3) STCHK(dalloc(&w.W2, (size_t)nrhs * op->n[0] * op->P[1] * op->H[2] * sizeof(cx<T>)));
+    STCHK(dalloc(&w.T1, (size_t)nrhs * N * sizeof(T)));
+    w.cap_rhs = nrhs;
+    long np = 4096 + 4 * (rows + 1);
+    if (w.npart < np) {
+      if (w.part) hipFree(w.part);
+      STCHK(dalloc((void**)&w.part, np * sizeof(double)));
+      w.npart = np;
+    }
+  }
+  if (!w.sc) {
+    STCHK(dalloc((void**)&w.sc, sizeof(Scalars)));
+    HIPCHK(hipMemset(w.sc, 0, sizeof(Scalars)));
+  }
+  if (solver && !w.solver) {
+    for (void** p : {&w.x, &w.r, &w.z, &w.p, &w.q, &w.f}) STCHK(dalloc(p, (size_t)N * sizeof(T)));
+    w.solver = true;
+  }
+  return FL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operator application (M or shift0 I + shift1 M)
+// ---------------------------------------------------------------------------
+template <typename T, int PRO, int EPI> static fl_status apply_seq(fl_op op, const Prob& pb, Iter it, int chk) {
+  hipStream_t s = op->stream;
+  const int d = op->d;
+  if (d == 1) {
+    const Axis& A = pb.ax[0];
+    int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
+    long pairs = (pb.nrhs + 1) / 2;
+    LAUNCH(k_conv1d<T, PRO, EPI>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * A.P * sizeof(cx<T>), s, pb, it);
+    return FL_OK;
+  }
+  const Axis& AL = pb.ax[d - 1];
+  long rows = rows_of(op, pb.nrhs), pairs = (rows + 1) / 2;
+  {
+    int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
+    LAUNCH(k_rowfwd<T, PRO>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * AL.P * sizeof(cx<T>), s, pb, it);
+  }
+  auto col = [&](ColGeom cg, int mode) -> fl_status {
+    const Axis& A = pb.ax[cg.axis];
+    int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
+    long grid = cg.ngroup * ((cg.gs + G - 1) / G);
+    size_t sm = (size_t)G * A.P * sizeof(cx<T>);
+    if (mode == COL_FWD) LAUNCH(k_colpass<T, COL_FWD>, dim3(grid), dim3(nt), sm, s, pb, cg, it, chk);
+    if (mode == COL_CONV) LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), sm, s, pb, cg, it, chk);
+    if (mode == COL_INV) LAUNCH(k_colpass<T, COL_INV>, dim3(grid), dim3(nt), sm, s, pb, cg, it, chk);
+    return FL_OK;
+  };
+  const long nr = pb.nrhs;
+  if (d == 2) {
+    const long H1 = op->H[1], n0 = op->n[0];
+    ColGeom cg = {0, (int)n0, (int)n0, H1, nr, H1, n0 * H1, H1, n0 * H1, 1, 1};
+    STCHK(col(cg, COL_CONV));
+  } else {
+    const long n0 = op->n[0], n1 = op->n[1], P1 = op->P[1], H2 = op->H[2];
+    ColGeom f = {1, (int)n1, (int)P1, H2, nr * n0, H2, n1 * H2, H2, P1 * H2, 1, 2};
+    ColGeom c = {0, (int)n0, (int)n0, P1 * H2, nr, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
+    ColGeom i = {1, (int)P1, (int)n1, H2, nr * n0, H2, P1 * H2, H2, n1 * H2, 2, 1};
+    STCHK(col(f, COL_FWD));
+    STCHK(col(c, COL_CONV));
+    STCHK(col(i, COL_INV));
+  }
+  {
+    int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
+    LAUNCH(k_rowinv<T, EPI>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * AL.P * sizeof(cx<T>), s, pb, it, chk);
+  }
+  return FL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// preconditioner (p0 I + p1 pcs T)^{-1}
+// ---------------------------------------------------------------------------
+template <typename T, int DPRO, int DEPI> static fl_status precond_seq(fl_op op, Prob pb, Iter it, int chk) {
+  hipStream_t s = op->stream;
+  const int d = op->d;
+  const Axis& AL = pb.ax[d - 1];
+  long rows = rows_of(op, pb.nrhs);
+  int nt = block_for(AL.dst.tpl), G = nt / AL.dst.tpl;
+  size_t sm = (size_t)G * AL.dst.L * sizeof(cx<T>);
+  dim3 gr((rows + G - 1) / G);
+  if (d == 1) {
+    LAUNCH(k_dst_rows<T, DPRO, DEPI>, gr, dim3(nt), sm, s, pb, it, chk);
+    return FL_OK;
+  }
+  Prob p1 = pb;
+  p1.out = pb.T1;
+  LAUNCH(k_dst_rows<T, DPRO, DEPI_STORE>, gr, dim3(nt), sm, s, p1, it, chk);
+  auto cols = [&](DGeom g, bool scale) -> fl_status {
+    const Axis& A = pb.ax[g.axis];
+    int ntc = block_for(A.dst.tpl), Gc = ntc / A.dst.tpl;
+    long grid = g.ngroup * ((g.gs + Gc - 1) / Gc);
+    size_t smc = (size_t)Gc * A.dst.L * sizeof(cx<T>);
+    if (scale)
+      LAUNCH(k_dst_cols<T, true>, dim3(grid), dim3(ntc), smc, s, pb, g, chk);
+    else
+      LAUNCH(k_dst_cols<T, false>, dim3(grid), dim3(ntc), smc, s, pb, g, chk);
+    return FL_OK;
+  };
+  const long nr = pb.nrhs;
+  if (d == 2) {
+    const long n0 = op->n[0], n1 = op->n[1];
+    STCHK(cols(DGeom{0, n1, nr, n1, n0 * n1}, true));
+  } else {
+    const long n0 = op->n[0], n1 = op->n[1], n2 = op->n[2];
+    DGeom g1 = {1, n2, nr * n0, n2, n1 * n2};
+    DGeom g0 = {0, n1 * n2, nr, n1 * n2, n0 * n1 * n2};
+    STCHK(cols(g1, false));
+    STCHK(cols(g0, true));
+    STCHK(cols(g1, false));
+  }
+  Prob p3 = pb;
+  p3.in = pb.T1;
+  LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI>, gr, dim3(nt), sm, s, p3, it, chk);
+  return FL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operator construction
+// ---------------------------------------------------------------------------
+static fl_status build_symbol(fl_op op) {
+  hipStream_t s = op->stream;
+  HIPCHK(hipMemcpyAsync(op->lam[0], op->wf, op->NH * sizeof(double), hipMemcpyDeviceToDevice, s));
+  for (int a = 0; a < op->d; ++a) {
+    long inner = 1, nl = 1;
+    for (int b = 0; b < op->d; ++b) {
+      if (b > a) inner *= op->H[b];
+      if (b != a) nl *= op->H[b];
+    }
+    const FFTPlan& pl = op->ax[0][a].fft;
+    int nt = block_for(pl.tpl), G = nt / pl.tpl;
+    long pairs = (nl + 1) / 2;
+    LAUNCH(k_dct1_axis, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * op->P[a] * sizeof(cx<double>), s,
+           (double*)op->lam[0], op->H[a], op->P[a], inner, nl, pl);
+  }
+  LAUNCH(k_cast<float, double>, dim3((op->NH + 255) / 256), dim3(256), 0, s, (const double*)op->lam[0],
+         (float*)op->lam[1], op->NH, 1.0);
+  return FL_OK;
+}
+
+static fl_status make_op(int d, double alpha, double h, const int64_t* n, const fl_weights_opts* o,
+                         void* stream, fl_op* out) {
+  if (!out) return fail(FL_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (d < 1 || d > 3) return fail(FL_E_INVALID, "d must be 1, 2 or 3");
+  if (!(alpha > 0.0 && alpha < 2.0)) return fail(FL_E_INVALID, "alpha must lie in (0, 2)");
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(FL_E_INVALID, "h must be positive");
+  if (!n) return fail(FL_E_INVALID, "n is NULL");
+  for (int a = 0; a < d; ++a)
+    if (n[a] < 1 || n[a] > (1 << 20)) return fail(FL_E_INVALID, "grid sizes must be >= 1");
+  fl_op op = new fl_op_s();
+  op->d = d;
+  op->alpha = alpha;
+  op->h = h;
+  op->c = (o && o->delta_over_h > 0) ? o->delta_over_h : 20.0;
+  op->stream = (hipStream_t)stream;
+  op->N = 1;
+  op->NH = 1;
+  for (int a = 0; a < d; ++a) {
+    op->n[a] = (int)n[a];
+    op->P[a] = padded_length(op->n[a]);
+    op->H[a] = op->P[a] / 2 + 1;
+    op->N *= op->n[a];
+    op->NH *= op->H[a];
+  }
+  auto bail = [&](fl_status s) {
+    delete op;
+    return s;
+  };
+  fl_status st;
+  if ((st = dalloc((void**)&op->d_cst, 8 * sizeof(double))) != FL_OK) return bail(st);
+  if ((st = dalloc((void**)&op->wf, op->NH * sizeof(double))) != FL_OK) return bail(st);
+  if ((st = dalloc(&op->lam[0], op->NH * sizeof(double))) != FL_OK) return bail(st);
+  if ((st = dalloc(&op->lam[1], op->NH * sizeof(float))) != FL_OK) return bail(st);
+  if (hipHostMalloc((void**)&op->hsc, sizeof(Scalars)) != hipSuccess) return bail(fail(FL_E_NOMEM, "pinned"));
+  for (int a = 0; a < 3; ++a) {
+    memset(&op->ax[0][a], 0, sizeof(Axis));
+    memset(&op->ax[1][a], 0, sizeof(Axis));
+  }
+  for (int a = 0; a < d; ++a) {
+    if ((st = build_axis<double>(op, a)) != FL_OK) return bail(st);
+    if ((st = build_axis<float>(op, a)) != FL_OK) return bail(st);
+  }
+  hipStream_t s = op->stream;
+  if (launch(k_constants, dim3(1), dim3(256), 0, s, d, alpha, h, op->c, op->d_cst) != hipSuccess)
+    return bail(fail(FL_E_HIP, "constants kernel"));
+  if (launch(k_weights, dim3((op->NH + 255) / 256), dim3(256), 0, s, d, alpha, op->n[0], op->n[1], op->n[2],
+             op->H[0], op->H[1], op->H[2], (const double*)op->d_cst, op->wf) != hipSuccess)
+    return bail(fail(FL_E_HIP, "weights kernel"));
+  if ((st = build_symbol(op)) != FL_OK) return bail(st);
+  if (hipMemcpyAsync(op->cst, op->d_cst, 8 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return bail(fail(FL_E_HIP, "constants readback"));
+  *out = op;
+  return FL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Krylov drivers
+// ---------------------------------------------------------------------------
+template <typename T> static Prob solver_prob(fl_op op, const uint8_t* mask, double s0, double s1, double p0,
+                                              double p1) {
+  Workspace& w = op->ws[tix<T>()];
+  Prob pb = base_prob<T>(op, 1);
+  pb.s0 = s0;
+  pb.s1 = s1;
+  pb.p0 = p0;
+  pb.p1 = p1;
+  pb.W1 = w.W1;
+  pb.W2 = w.W2;
+  pb.T1 = w.T1;
+  pb.mask = mask;
+  pb.x = w.x;
+  pb.r = w.r;
+  pb.z = w.z;
+  pb.p = w.p;
+  pb.q = w.q;
+  pb.sc = w.sc;
+  pb.part = w.part;
+  return pb;
+}
+
+template <typename T> static fl_status one_iteration(fl_op op, const Prob& pb, int pc, int k) {
+  Iter it = {k & 1, k == 0 ? 1 : 0};
+  Prob pz = pb;
+  if (!pc) pz.z = pb.r;  // z aliases r without a preconditioner
+  STCHK((apply_seq<T, PRO_PUPD, EPI_PQ>(op, pz, it, 1)));
+  if (pc) {
+    STCHK((precond_seq<T, DPRO_UPD, DEPI_Z>(op, pb, it, 1)));
+  } else {
+    long nb = std::min<long>(2048, (op->N + 255) / 256);
+    LAUNCH(k_update<T>, dim3(nb), dim3(256), 0, op->stream, pb, it, op->N);
+  }
+  return FL_OK;
+}
+
+static fl_status read_scalars(fl_op op, Scalars* dsc) {
+  HIPCHK(hipMemcpyAsync(op->hsc, dsc, sizeof(Scalars), hipMemcpyDeviceToHost, op->stream));
+  HIPCHK(hipStreamSynchronize(op->stream));
+  return FL_OK;
+}
+
+// PCG on the workspace of type T: r holds the initial residual, x the initial
+// iterate, sc->ff the squared rhs norm (and sc->rr the squared residual norm
+// if use_rr).  Returns after convergence / cap / breakdown.
+template <typename T> static fl_status krylov(fl_op op, const Prob& pb, int pc, double tol, int maxit,
+                                              int use_rr, int graph, int poll, Scalars* out) {
+  hipStream_t s = op->stream;
+  Workspace& w = op->ws[tix<T>()];
+  LAUNCH(k_init, dim3(1), dim3(64), 0, s, pb, tol, maxit, use_rr);
+  if (pc) {
+    Prob p0 = pb;
+    p0.in = pb.r;
+    STCHK((precond_seq<T, DPRO_PLAIN, DEPI_Z>(op, p0, Iter{1, 0}, 0)));
+  } else {
+    // rz[0] = r.r
+    long nb = std::min<long>(1024, (op->N + 255) / 256);
+    LAUNCH(k_dot<T>, dim3(nb), dim3(256), 0, s, pb, (const void*)pb.r, (const void*)pb.r, (int)DOT_RZ0, op->N);
+  }
+  if (poll <= 0) poll = 8;
+  if (poll & 1) ++poll;
+  // iteration 0 eagerly, then blocks of `poll` iterations
+  STCHK(one_iteration<T>(op, pb, pc, 0));
+  int k = 1;
+  bool use_graph = graph != 0 && op->stream != nullptr;
+  if (use_graph) {
+    bool rebuild = !w.gexec || w.gK != poll || w.gpc != pc || w.gs0 != pb.s0 || w.gs1 != pb.s1 ||
+                   w.gp0 != pb.p0 || w.gp1 != pb.p1 || w.gmask != pb.mask;
+    if (rebuild) {
+      if (w.gexec) {
+        hipGraphExecDestroy(w.gexec);
+        w.gexec = nullptr;
+      }
+      hipGraph_t g;
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      fl_status st = FL_OK;
+      for (int j = 0; j < poll && st == FL_OK; ++j) st = one_iteration<T>(op, pb, pc, 1 + j);
+      hipError_t e = hipStreamEndCapture(s, &g);
+      if (st != FL_OK) return st;
+      HIPCHK(e);
+      HIPCHK(hipGraphInstantiate(&w.gexec, g, nullptr, nullptr, 0));
+      hipGraphDestroy(g);
+      w.gK = poll;
+      w.gpc = pc;
+      w.gs0 = pb.s0;
+      w.gs1 = pb.s1;
+      w.gp0 = pb.p0;
+      w.gp1 = pb.p1;
+      w.gmask = pb.mask;
+    }
+  }
+  for (;;) {
+    STCHK(read_scalars(op, pb.sc));
+    if (op->hsc->done) break;
+    if (op->hsc->iters >= maxit + 2 * poll) return fail(FL_E_HIP, "iteration bookkeeping lost");
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(w.gexec, s));
+      k += poll;
+    } else {
+      for (int j = 0; j < poll; ++j, ++k) STCHK(one_iteration<T>(op, pb, pc, k));
+    }
+  }
+  *out = *op->hsc;
+  return FL_OK;
+}
+
+static long nblocks_vec(long n) { return (n + 255) / 256; }
+
+// True FP64 residual r = b - A x into ws64.q; returns ||r||^2 via sc->rr.
+static fl_status true_residual(fl_op op, const uint8_t* mask, double s0, double s1, const double* x,
+                               const double* b, double* out, double* rr) {
+  Workspace& w = op->ws[0];
+  Prob pb = solver_prob<double>(op, mask, s0, s1, 0, 1);
+  pb.in = x;
+  pb.aux = b;
+  pb.out = out;
+  STCHK((apply_seq<double, PRO_PLAIN, EPI_RESID>(op, pb, Iter{0, 0}, 0)));
+  STCHK(read_scalars(op, w.sc));
+  *rr = op->hsc->rr;
+  return FL_OK;
+}
+
+// Solve (s0 I + s1 M) x = b where b is ws64.f and x is ws64.x (initial guess
+// when use_x0, otherwise zeroed here).  Preconditioner p0 I + p1 pcs T.
+static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s1, double p0, double p1,
+                              double tol, const fl_solve_opts* o, int use_x0, fl_info* info) {
+  hipStream_t s = op->stream;
+  const long N = op->N;
+  const int pc = o ? o->pc : FL_PC_FD;
+  const int mixed = o ? o->mixed : 0;
+  const int graph = o ? o->graph : 1;
+  const int poll = (o && o->poll_every > 0) ? o->poll_every : 8;
+  int maxit = (o && o->maxit > 0) ? o->maxit : std::max(1000, (int)(10 * std::sqrt((double)N)));
+  Workspace& w = op->ws[0];
+  Prob pb = solver_prob<double>(op, mask, s0, s1, p0, p1);
+  fl_info inf;
+  memset(&inf, 0, sizeof(inf));
+  // ff
+  LAUNCH(k_dot<double>, dim3(std::min<long>(1024, nblocks_vec(N))), dim3(256), 0, s, pb, (const void*)w.f,
+         (const void*)w.f, (int)DOT_FF, N);
+  if (!use_x0) LAUNCH(k_fill<double>, dim3(nblocks_vec(N)), dim3(256), 0, s, (double*)w.x, 0.0, N);
+  STCHK(read_scalars(op, w.sc));
+  const double ff = op->hsc->ff;
+  if (!std::isfinite(ff)) {
+    info->status = FL_E_INVALID;
+    return fail(FL_E_INVALID, "right-hand side is not finite");
+  }
+  if (!mixed) {
+    if (use_x0) {
+      double rr;
+      STCHK(true_residual(op, mask, s0, s1, (const double*)w.x, (const double*)w.f, (double*)w.r, &rr));
+    } else {
+      HIPCHK(hipMemcpyAsync(w.r, w.f, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    Scalars res;
+    STCHK(krylov<double>(op, pb, pc, tol, maxit, use_x0, graph, poll, &res));
+    inf.iters = res.iters;
+    inf.rel_res_recur = ff > 0 ? std::sqrt(res.rr / ff) : 0.0;
+    inf.status = res.done == 1 ? FL_OK : res.done == 2 ? FL_E_NOCONV : FL_E_BREAKDOWN;
+  } else {
+    STCHK(ensure_ws<float>(op, 1, true));
+    Workspace& w32 = op->ws[1];
+    Prob p32 = solver_prob<float>(op, mask, s0, s1, p0, p1);
+    const double itol = (o && o->inner_tol > 0) ? o->inner_tol : 1e-4;
+    const int max_outer = (o && o->max_outer > 0) ? o->max_outer : 12;
+    int inner_cap = (o && o->maxit > 0) ? o->maxit : std::max(1000, (int)(10 * std::sqrt((double)N)));
+    inf.status = FL_E_NOCONV;
+    for (int outer = 0;; ++outer) {
+      double rr;
+      STCHK(true_residual(op, mask, s0, s1, (const double*)w.x, (const double*)w.f, (double*)w.r, &rr));
+      if (ff == 0.0 || std::sqrt(rr / ff) <= tol) {
+        inf.status = FL_OK;
+        break;
+      }
+      if (!std::isfinite(rr)) {
+        inf.status = FL_E_BREAKDOWN;
+        break;
+      }
+      if (outer >= max_outer) break;
+      inf.outer_iters = outer + 1;
+      // r32 = r64 / ||r64||, x32 = 0, inner PCG to itol
+      const double nr = std::sqrt(rr);
+      LAUNCH((k_axpby<double, float>), dim3(nblocks_vec(N)), dim3(256), 0, s, (const double*)w.r, (float*)w32.r,
+             1.0 / nr, 0.0, N);
+      LAUNCH(k_fill<float>, dim3(nblocks_vec(N)), dim3(256), 0, s, (float*)w32.x, 0.0f, N);
+      LAUNCH(k_dot<float>, dim3(std::min<long>(1024, nblocks_vec(N))), dim3(256), 0, s, p32,
+             (const void*)w32.r, (const void*)w32.r, (int)DOT_FF, N);
+      Scalars res;
+      STCHK(krylov<float>(op, p32, pc, itol, inner_cap, 0, graph, poll, &res));
+      inf.iters += res.iters;
+      inf.rel_res_recur = res.ff > 0 ? std::sqrt(res.rr / res.ff) : 0.0;
+      if (res.done == 3) {
+        inf.status = FL_E_BREAKDOWN;
+        break;
+      }
+      // x64 += ||r|| x32
+      LAUNCH((k_axpby<float, double>), dim3(nblocks_vec(N)), dim3(256), 0, s, (const float*)w32.x,
+             (double*)w.x, nr, 1.0, N);
+    }
+  }
+  // true residual in FP64
+  double rr;
+  STCHK(true_residual(op, mask, s0, s1, (const double*)w.x, (const double*)w.f, (double*)w.q, &rr));
+  inf.rel_res_true = ff > 0 ? std::sqrt(rr / ff) : 0.0;
+  *info = inf;
+  return FL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+template <typename T>
+static fl_status apply_t(fl_op op, const void* u, void* Mu, long batch, const uint8_t* mask, double s0, double s1) {
+  STCHK(ensure_ws<T>(op, batch, false));
+  Workspace& w = op->ws[tix<T>()];
+  Prob pb = base_prob<T>(op, batch);
+  pb.s0 = s0;
+  pb.s1 = s1;
+  pb.in = u;
+  pb.out = Mu;
+  pb.W1 = w.W1;
+  pb.W2 = w.W2;
+  pb.mask = mask;
+  pb.sc = w.sc;
+  pb.part = w.part;
+  return apply_seq<T, PRO_PLAIN, EPI_PLAIN>(op, pb, Iter{0, 0}, 0);
+}
+
+template <typename T>
+static fl_status precond_t(fl_op op, const void* r, void* z, long batch, const uint8_t* mask, double p0, double p1) {
+  STCHK(ensure_ws<T>(op, batch, false));
+  Workspace& w = op->ws[tix<T>()];
+  Prob pb = base_prob<T>(op, batch);
+  pb.p0 = p0;
+  pb.p1 = p1;
+  pb.in = r;
+  pb.out = z;
+  pb.T1 = w.T1;
+  pb.mask = mask;
+  pb.sc = w.sc;
+  pb.part = w.part;
+  return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pb, Iter{0, 0}, 0);
+}
+
+
+// Time `reps` back-to-back launches of one pass of the operator application or
+// the preconditioner on the op's stream, bracketed by HIP events (inputs are the
+// op's own zero-filled workspace).  pass: 0 rows forward, 1 symbol column pass
+// (axis 0), 2 rows inverse, 3 first sine pass, 4 scaled sine column pass,
+// 5 last sine pass, 6 whole application, 7 whole preconditioner.
+template <typename T> static fl_status profile_t(fl_op op, int pass, int reps, double* avg_ms) {
+  STCHK(ensure_ws<T>(op, 1, true));
+  Workspace& w = op->ws[tix<T>()];
+  hipStream_t s = op->stream;
+  const long N = op->N;
+  for (void* v : {w.x, w.q, w.T1}) LAUNCH(k_fill<T>, dim3(nblocks_vec(N)), dim3(256), 0, s, (T*)v, (T)0, N);
+  long nW1 = rows_of(op, 1) * op->H[op->d - 1] * 2;
+  LAUNCH(k_fill<T>, dim3(nblocks_vec(nW1)), dim3(256), 0, s, (T*)w.W1, (T)0, nW1);
+  if (op->d == 3) {
+    long nW2 = (long)op->n[0] * op->P[1] * op->H[2] * 2;
+    LAUNCH(k_fill<T>, dim3(nblocks_vec(nW2)), dim3(256), 0, s, (T*)w.W2, (T)0, nW2);
+  }
+  Prob pb = solver_prob<T>(op, nullptr, 0.0, 1.0, 0.0, 1.0);
+  pb.in = w.x;
+  pb.out = w.q;
+  const int d = op->d;
+  const Axis& AL = pb.ax[d - 1];
+  long rows = rows_of(op, 1), pairs = (rows + 1) / 2;
+  Iter it = {0, 0};
+  auto one = [&]() -> fl_status {
+    if (pass == 6) return apply_seq<T, PRO_PLAIN, EPI_PLAIN>(op, pb, it, 0);
+    if (pass == 7) return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pb, it, 0);
+    if (d == 1) return fail(FL_E_UNSUPPORTED, "single passes are defined for d >= 2");
+    if (pass == 0) {
+      int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
+      LAUNCH(k_rowfwd<T, PRO_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * AL.P * sizeof(cx<T>), s, pb, it);
+    } else if (pass == 1) {
+      const Axis& A = pb.ax[0];
+      int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
+      ColGeom cg;
+      if (d == 2) {
+        const long H1 = op->H[1], n0 = op->n[0];
+        cg = {0, (int)n0, (int)n0, H1, 1, H1, n0 * H1, H1, n0 * H1, 1, 1};
+      } else {
+        const long n0 = op->n[0], P1 = op->P[1], H2 = op->H[2];
+        cg = {0, (int)n0, (int)n0, P1 * H2, 1, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
+      }
+      long grid = cg.ngroup * ((cg.gs + G - 1) / G);
+      LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), (size_t)G * A.P * sizeof(cx<T>), s, pb, cg, it, 0);
+    } else if (pass == 2) {
+      int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
+      LAUNCH(k_rowinv<T, EPI_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * AL.P * sizeof(cx<T>), s, pb, it, 0);
+    } else if (pass == 3 || pass == 5) {
+      int nt = block_for(AL.dst.tpl), G = nt / AL.dst.tpl;
+      Prob p1 = pb;
+      if (pass == 3) p1.out = w.T1; else p1.in = w.T1;
+      size_t sm = (size_t)G * AL.dst.L * sizeof(cx<T>);
+      if (pass == 3)
+        LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI_STORE>, dim3((rows + G - 1) / G), dim3(nt), sm, s, p1, it, 0);
+      else
+        LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI_FINAL>, dim3((rows + G - 1) / G), dim3(nt), sm, s, p1, it, 0);
+    } else if (pass == 4) {
+      const Axis& A = pb.ax[0];
+      int nt = block_for(A.dst.tpl), G = nt / A.dst.tpl;
+      DGeom g;
+      if (d == 2) g = DGeom{0, (long)op->n[1], 1, (long)op->n[1], (long)op->n[0] * op->n[1]};
+      else {
+        long n12 = (long)op->n[1] * op->n[2];
+        g = DGeom{0, n12, 1, n12, (long)op->n[0] * n12};
+      }
+      long grid = g.ngroup * ((g.gs + G - 1) / G);
+      LAUNCH(k_dst_cols<T, true>, dim3(grid), dim3(nt), (size_t)G * A.dst.L * sizeof(cx<T>), s, pb, g, 0);
+    } else {
+      return fail(FL_E_INVALID, "pass must be 0..7");
+    }
+    return FL_OK;
+  };
+  STCHK(one());  // warm-up
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; ++i) STCHK(one());
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *avg_ms = (double)ms / std::max(reps, 1);
+  return FL_OK;
+}
+
+extern "C" {
+
+fl_status fl_make_weights(int d, double alpha, double h, const int64_t* n, const fl_weights_opts* o,
+                          void* hip_stream, fl_op* out) {
+  g_err.clear();
+  return make_op(d, alpha, h, n, o, hip_stream, out);
+}
+
+fl_status fl_op_constants(fl_op op, double out[8]) {
+  if (!op || !out) return fail(FL_E_INVALID, "NULL argument");
+  memcpy(out, op->cst, 8 * sizeof(double));
+  return FL_OK;
+}
+
+fl_status fl_op_padded(fl_op op, int64_t* out) {
+  if (!op || !out) return fail(FL_E_INVALID, "NULL argument");
+  for (int a = 0; a < op->d; ++a) out[a] = op->P[a];
+  return FL_OK;
+}
+
+fl_status fl_op_export(fl_op op, int which, void* dst) {
+  if (!op || !dst) return fail(FL_E_INVALID, "NULL argument");
+  const void* src = which == 0 ? (const void*)op->wf : which == 1 ? op->lam[0] : which == 2 ? op->lam[1] : nullptr;
+  if (!src) return fail(FL_E_INVALID, "which must be 0, 1 or 2");
+  size_t b = op->NH * (which == 2 ? sizeof(float) : sizeof(double));
+  HIPCHK(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, op->stream));
+  return FL_OK;
+}
+
+fl_status fl_apply(fl_op op, const void* u, void* Mu, int dtype, int64_t batch, const uint8_t* mask, double shift0,
+                   double shift1) {
+  if (!op || !u || !Mu) return fail(FL_E_INVALID, "NULL argument");
+  if (batch < 1) return fail(FL_E_INVALID, "batch must be >= 1");
+  if (dtype == FL_F64) return apply_t<double>(op, u, Mu, batch, mask, shift0, shift1);
+  if (dtype == FL_F32) return apply_t<float>(op, u, Mu, batch, mask, shift0, shift1);
+  return fail(FL_E_INVALID, "dtype must be FL_F64 or FL_F32");
+}
+
+fl_status fl_precond(fl_op op, const void* r, void* z, int dtype, int64_t batch, const uint8_t* mask, double p0,
+                     double p1) {
+  if (!op || !r || !z) return fail(FL_E_INVALID, "NULL argument");
+  if (batch < 1) return fail(FL_E_INVALID, "batch must be >= 1");
+  if (dtype == FL_F64) return precond_t<double>(op, r, z, batch, mask, p0, p1);
+  if (dtype == FL_F32) return precond_t<float>(op, r, z, batch, mask, p0, p1);
+  return fail(FL_E_INVALID, "dtype must be FL_F64 or FL_F32");
+}
+
+fl_status fl_solve(fl_op op, const double* f, const uint8_t* mask, double tol, const fl_solve_opts* o, double* u,
+                   fl_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!op || !f || !u || !info) return fail(FL_E_INVALID, "NULL argument");
+  if (!(tol > 0.0)) return fail(FL_E_INVALID, "tol must be positive");
+  STCHK(ensure_ws<double>(op, 1, true));
+  Workspace& w = op->ws[0];
+  const long N = op->N;
+  hipStream_t s = op->stream;
+  HIPCHK(hipMemcpyAsync(w.f, f, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  int use_x0 = o ? o->use_x0 : 0;
+  if (use_x0) HIPCHK(hipMemcpyAsync(w.x, u, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  STCHK(solve_system(op, mask, 0.0, 1.0, 0.0, 1.0, tol, o, use_x0, info));
+  HIPCHK(hipMemcpyAsync(u, w.x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info->status != FL_OK) return fail((fl_status)info->status, "solve did not reach the tolerance");
+  return FL_OK;
+}
+
+fl_status fl_step(fl_op op, double* u, double dt, double theta, const double* f_k, const double* f_k1,
+                  const uint8_t* mask, double tol, const fl_solve_opts* o, fl_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!op || !u || !info) return fail(FL_E_INVALID, "NULL argument");
+  if (!(dt > 0.0) || !(theta > 0.0 && theta <= 1.0) || !(tol > 0.0)) return fail(FL_E_INVALID, "dt, theta or tol");
+  STCHK(ensure_ws<double>(op, 1, true));
+  Workspace& w = op->ws[0];
+  const long N = op->N;
+  hipStream_t s = op->stream;
+  // b = (I - (1-theta) dt M) u + dt (theta f_k1 + (1-theta) f_k)
+  if (theta < 1.0) {
+    STCHK(apply_t<double>(op, u, w.f, 1, mask, 1.0, -(1.0 - theta) * dt));
+  } else {
+    HIPCHK(hipMemcpyAsync(w.f, u, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  if (f_k1) LAUNCH((k_axpby<double, double>), dim3(nblocks_vec(N)), dim3(256), 0, s, f_k1, (double*)w.f, dt * theta, 1.0, N);
+  if (f_k && theta < 1.0)
+    LAUNCH((k_axpby<double, double>), dim3(nblocks_vec(N)), dim3(256), 0, s, f_k, (double*)w.f, dt * (1.0 - theta), 1.0, N);
+  HIPCHK(hipMemcpyAsync(w.x, u, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  STCHK(solve_system(op, mask, 1.0, theta * dt, 1.0, theta * dt, tol, o, 1, info));
+  HIPCHK(hipMemcpyAsync(u, w.x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info->status != FL_OK) return fail((fl_status)info->status, "step solve did not reach the tolerance");
+  return FL_OK;
+}
+
+fl_status fl_solve_batched(int nprob, const fl_op* ops, const double* const* f, const uint8_t* const* masks, double tol,
+                           const fl_solve_opts* opts, double* const* u, fl_info* infos) {
+  return fail(FL_E_UNSUPPORTED, "batched solve not built yet");
+}
+
+fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const double* dt, double theta, int nsteps,
+                          double tol, const fl_solve_opts* opts, fl_info* infos) {
+  return fail(FL_E_UNSUPPORTED, "batched step not built yet");
+}
+
+fl_status fl_op_destroy(fl_op op) {
+  if (!op) return FL_OK;
+  hipStreamSynchronize(op->stream);
+  delete op;
+  return FL_OK;
+}
+
+fl_status fl_profile_pass(fl_op op, int dtype, int pass, int reps, double* avg_ms) {
+  if (!op || !avg_ms || reps < 1) return fail(FL_E_INVALID, "NULL argument or reps < 1");
+  if (dtype == FL_F64) return profile_t<double>(op, pass, reps, avg_ms);
+  if (dtype == FL_F32) return profile_t<float>(op, pass, reps, avg_ms);
+  return fail(FL_E_INVALID, "dtype");
+}
+
+const char* fl_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

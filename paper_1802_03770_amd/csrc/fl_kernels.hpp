@@ -1,0 +1,812 @@
+// HIP kernels for gfx950: operator construction, FFT application of the BTTB
+// operator, the sine-transform (fast Poisson) preconditioner, and the fused
+// Krylov vector work.  All kernel bodies act on one problem (`Prob`) and are
+// wrapped twice: a single-problem kernel taking the Prob by value, and a
+// batched kernel taking a device array of Probs (blockIdx.y = problem).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "fl_fft.hpp"
+#include "fl_types.hpp"
+
+namespace fl {
+
+struct Iter {
+  int parity;  // selects rz slots of the Krylov recurrence
+  int first;   // first iteration: p = z
+};
+
+// ---------------------------------------------------------------------------
+// reductions: wave64 shuffle tree, then LDS across waves, then a deterministic
+// last-block pass over per-block partials (agent-scope fences make the
+// partials of blocks on other XCDs visible).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ double block_sum(double v) {
+  __shared__ double red[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < 64) {
+    s = threadIdx.x < nw ? red[threadIdx.x] : 0.0;
+    s = wave_sum(s);
+  }
+  return s;  // valid in thread 0
+}
+
+// Returns true in the one block that finished last; that block's thread 0 gets
+// the grand total in *total (sum of partials in index order, tree-reduced).
+__device__ bool grid_sum(double blockval, double* part, unsigned int* ctr, int nblk, int blk,
+                         double* total) {
+  __shared__ int amlast;
+  double s = block_sum(blockval);
+  if (threadIdx.x == 0) {
+    part[blk] = s;
+    __threadfence();
+    unsigned int t = atomicAdd(ctr, 1u);
+    amlast = (t == (unsigned)(nblk - 1));
+  }
+  __syncthreads();
+  if (!amlast) return false;
+  __threadfence();
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x)
+    v += __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v = block_sum(v);
+  if (threadIdx.x == 0) {
+    *total = v;
+    *ctr = 0u;
+  }
+  return true;
+}
+
+template <typename T> __device__ __forceinline__ T ldg(const void* p, long i) { return ((const T*)p)[i]; }
+
+__device__ __forceinline__ int fold(int k, int P) { return k <= P / 2 ? k : P - k; }
+
+// Rows of the real array: every index except the last axis, rhs outermost.
+__device__ __forceinline__ long nrows_of(const Prob& pb) {
+  long r = pb.nrhs;
+  for (int a = 0; a < pb.d - 1; ++a) r *= pb.ax[a].n;
+  return r;
+}
+__device__ __forceinline__ long nper_of(const Prob& pb) {
+  long r = 1;
+  for (int a = 0; a < pb.d; ++a) r *= pb.ax[a].n;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Operator construction (FP64)
+// ---------------------------------------------------------------------------
+// Upper incomplete gamma Gamma(a, x), x > 0, any real a, by Legendre's
+// continued fraction evaluated with the modified Lentz method (accurate for
+// x >~ 1; here x >= pi).
+__device__ double upper_gamma_cf(double a, double x) {
+  const double tiny = 1e-300;
+  double b = x + 1.0 - a, c = 1.0 / tiny, dd = 1.0 / b, f = dd;
+  for (int i = 1; i < 500; ++i) {
+    double an = -i * (i - a);
+    b += 2.0;
+    dd = an * dd + b;
+    if (fabs(dd) < tiny) dd = tiny;
+    c = b + an / c;
+    if (fabs(c) < tiny) c = tiny;
+    dd = 1.0 / dd;
+    double del = dd * c;
+    f *= del;
+    if (fabs(del - 1.0) < 1e-17) break;
+  }
+  return exp(-x + a * log(x)) * f;
+}
+
+__device__ double window_poly(double t) {
+  if (t >= 1.0) return 0.0;
+  double t2 = t * t, t4 = t2 * t2;
+  return 1.0 + t4 * (-35.0 + t * (84.0 + t * (-70.0 + 20.0 * t)));
+}
+
+// One workgroup.  out[0..7] = C, Z, B, a2, h^{s-2}A3, omega0, omega_e, C h^-alpha.
+//   C      = alpha 2^{alpha-1} Gamma((d+alpha)/2) / (pi^{d/2} Gamma(1 - alpha/2))
+//   Z      = sum_{j != 0} |j|^{-(d+alpha)}  (theta split with parameter 1, |j|_inf <= 5)
+//   a2     = sum_{0<|j|<c} W(|j|/c) j_1^2 |j|^{-(d+alpha)}
+//   A3s    = -(1/2)(|S^{d-1}|/d) c^{2-alpha} Pw(alpha)
+//   B      = a2/2 + A3s
+__global__ void k_constants(int d, double alpha, double h, double c, double* out) {
+  const double PI = 3.141592653589793238462643383279502884;
+  const double s = d + alpha, sig = 0.5 * s;
+  const int R = 5, W = 2 * R + 1;
+  int tot = 1;
+  for (int a = 0; a < d; ++a) tot *= W;
+  double z = 0.0;
+  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+    int rem = t;
+    double r2 = 0.0;
+    for (int a = 0; a < d; ++a) {
+      int j = rem % W - R;
+      rem /= W;
+      r2 += (double)j * j;
+    }
+    if (r2 == 0.0) continue;
+    double q = PI * r2;
+    z += pow(q, -sig) * upper_gamma_cf(sig, q) + pow(q, 0.5 * alpha) * upper_gamma_cf(-0.5 * alpha, q);
+  }
+  z = block_sum(z);
+  // ball sum for a2
+  const int Rc = (int)ceil(c), Wc = 2 * Rc + 1;
+  int totc = 1;
+  for (int a = 0; a < d; ++a) totc *= Wc;
+  double a2 = 0.0;
+  for (int t = threadIdx.x; t < totc; t += blockDim.x) {
+    int rem = t;
+    double r2 = 0.0, j1 = 0.0;
+    for (int a = 0; a < d; ++a) {
+      int j = rem % Wc - Rc;
+      rem /= Wc;
+      r2 += (double)j * j;
+      if (a == 0) j1 = j;
+    }
+    if (r2 == 0.0) continue;
+    double r = sqrt(r2);
+    if (r >= c) continue;
+    a2 += window_poly(r / c) * j1 * j1 * pow(r2, -0.5 * s);
+  }
+  a2 = block_sum(a2);
+  if (threadIdx.x == 0) {
+    double Z = (z + (2.0 / alpha) - 1.0 / sig) * pow(PI, sig) / tgamma(sig);
+    double C = alpha * pow(2.0, alpha - 1.0) * tgamma(0.5 * (d + alpha)) /
+               (pow(PI, 0.5 * d) * tgamma(1.0 - 0.5 * alpha));
+    double area = 2.0 * pow(PI, 0.5 * d) / tgamma(0.5 * d);
+    double pw = 1.0 / (2.0 - alpha) - 35.0 / (6.0 - alpha) + 84.0 / (7.0 - alpha) - 70.0 / (8.0 - alpha) +
+                20.0 / (9.0 - alpha);
+    double a3s = -0.5 * area / d * pow(c, 2.0 - alpha) * pw;
+    double B = 0.5 * a2 + a3s;
+    out[0] = C;
+    out[1] = Z;
+    out[2] = B;
+    out[3] = a2;
+    out[4] = a3s;
+    out[5] = Z - 2.0 * d * B;
+    out[6] = -1.0 + B;
+    out[7] = C * pow(h, -alpha);
+  }
+}
+
+// Folded circulant generator on [0, H_0) x ... : C h^-alpha omega_m where every
+// m_a < n_a, zero elsewhere.  omega_0 = Z - 2dB, omega_{e_k} = -1 + B,
+// omega_m = -|m|^{-(d+alpha)} otherwise.
+__global__ void k_weights(int d, double alpha, int n0, int n1, int n2, int H0, int H1, int H2,
+                          const double* cst, double* wf) {
+  long tot = (long)H0 * H1 * H2;
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= tot) return;
+  int m2 = i % H2, m1 = (i / H2) % H1, m0 = i / ((long)H1 * H2);
+  double v = 0.0;
+  if (m0 < n0 && m1 < n1 && m2 < n2) {
+    long r2 = (long)m0 * m0 + (long)m1 * m1 + (long)m2 * m2;
+    if (r2 == 0)
+      v = cst[5];
+    else if (r2 == 1)
+      v = cst[6];
+    else
+      v = -pow((double)r2, -0.5 * (d + alpha));
+    v *= cst[7];
+  }
+  wf[i] = v;
+}
+
+// Real-even DFT (type-I cosine transform of the folded line) along one axis
+// of the folded array, in place.  Two lines are packed as x + i y, extended
+// evenly to length P and transformed; x' = Re, y' = Im.  Lines along axis a:
+// index = o * (H_a * inner) + m * inner + c, c in [0, inner).
+__global__ void k_dct1_axis(double* wf, int H, int P, long inner, long nlines, FFTPlan pl) {
+  extern __shared__ __align__(16) char smem[];
+  const int tpl = pl.tpl, G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  cx<double>* buf = (cx<double>*)smem + (long)g * P;
+  long pair = (long)blockIdx.x * G + g;
+  long la = 2 * pair, lb = la + 1;
+  bool va = la < nlines, vb = lb < nlines;
+  auto base = [&](long l) { return (l / inner) * (long)H * inner + (l % inner); };
+  long ba = va ? base(la) : 0, bb = vb ? base(lb) : 0;
+  for (int i = lane; i < P; i += tpl) {
+    int m = fold(i, P);
+    double xa = va ? wf[ba + (long)m * inner] : 0.0;
+    double xb = vb ? wf[bb + (long)m * inner] : 0.0;
+    buf[i] = {xa, xb};
+  }
+  __syncthreads();
+  fft_line<double, false>(buf, pl, lane);
+  for (int k = lane; k < H; k += tpl) {
+    if (va) wf[ba + (long)k * inner] = buf[k].x;
+    if (vb) wf[bb + (long)k * inner] = buf[k].y;
+  }
+}
+
+template <typename TO, typename TI>
+__global__ void k_cast(const TI* in, TO* out, long n, double scale) {
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (TO)((double)in[i] * scale);
+}
+
+// ---------------------------------------------------------------------------
+// Operator application: forward row pass (last axis, real -> half spectrum)
+// ---------------------------------------------------------------------------
+enum { PRO_PLAIN = 0, PRO_PUPD = 1 };
+enum { EPI_PLAIN = 0, EPI_RESID = 1, EPI_PQ = 2 };
+
+template <typename T>
+__device__ __forceinline__ T maskval(const Prob& pb, long per_idx) {
+  return pb.mask ? (T)pb.mask[per_idx] : (T)1;
+}
+
+// Prologue value of the operator input at element e (row-major over the
+// stacked arrays).  PUPD: p <- z + beta p (beta = rz_k / rz_{k-1}), stored.
+template <typename T, int PRO>
+__device__ __forceinline__ T load_input(const Prob& pb, long e, long nper, double beta, bool first) {
+  if (PRO == PRO_PUPD) {
+    T zv = ((const T*)pb.z)[e];
+    T pv = first ? zv : (T)(zv + (T)beta * ((T*)pb.p)[e]);
+    ((T*)pb.p)[e] = pv;
+    return pv;
+  } else {
+    T v = ((const T*)pb.in)[e];
+    if (pb.mask) v *= (T)pb.mask[e % nper];
+    return v;
+  }
+}
+
+template <typename T, int PRO>
+__device__ void rowfwd_body(const Prob& pb, const Iter& it, int blk) {
+  if (PRO == PRO_PUPD && pb.sc->done) return;
+  extern __shared__ __align__(16) char smem[];
+  const Axis& A = pb.ax[pb.d - 1];
+  const int n = A.n, P = A.P, H = A.H, tpl = A.fft.tpl;
+  const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  cx<T>* buf = (cx<T>*)smem + (long)g * P;
+  const long rows = nrows_of(pb), nper = nper_of(pb);
+  const long ra = 2 * ((long)blk * G + g), rb = ra + 1;
+  const bool va = ra < rows, vb = rb < rows;
+  double beta = 0.0;
+  if (PRO == PRO_PUPD && !it.first) beta = pb.sc->rz[it.parity] / pb.sc->rz[it.parity ^ 1];
+  for (int i = lane; i < P; i += tpl) {
+    T xa = 0, xb = 0;
+    if (i < n) {
+      if (va) xa = load_input<T, PRO>(pb, ra * n + i, nper, beta, it.first);
+      if (vb) xb = load_input<T, PRO>(pb, rb * n + i, nper, beta, it.first);
+    }
+    buf[i] = {xa, xb};
+  }
+  __syncthreads();
+  fft_line<T, false>(buf, A.fft, lane);
+  cx<T>* W = (cx<T>*)pb.W1;
+  for (int k = lane; k < H; k += tpl) {
+    cx<T> zk = buf[k], zm = buf[(P - k) % P];
+    // X_a = (Z_k + conj Z_{P-k})/2 ; X_b = -i (Z_k - conj Z_{P-k})/2
+    cx<T> xa = {(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
+    cx<T> xb = {(T)0.5 * (zk.y + zm.y), (T)0.5 * (zm.x - zk.x)};
+    if (va) W[ra * H + k] = xa;
+    if (vb) W[rb * H + k] = xb;
+  }
+}
+
+// Strided complex line pass.  Lines c = c0 + j (j < G) of group grp; element i
+// of a line is at base + grp*gstride + i*estride + c.
+struct ColGeom {
+  int axis;      // transformed axis
+  int nin, nout; // elements loaded / stored per line
+  long gs;       // lines per group (adjacent in memory)
+  long ngroup;   // number of groups (outer index incl. rhs)
+  long ein, gin, eout, gout;
+  int src, dst;  // 1 = W1, 2 = W2
+};
+
+enum { COL_FWD = 0, COL_CONV = 1, COL_INV = 2 };
+
+template <typename T, int MODE>
+__device__ void colpass_body(const Prob& pb, const ColGeom& cg, const Iter& it, bool check_done, int blk) {
+  if (check_done && pb.sc->done) return;
+  extern __shared__ __align__(16) char smem[];
+  const Axis& A = pb.ax[cg.axis];
+  const int L = A.P, tpl = A.fft.tpl;
+  const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  const long tiles = (cg.gs + G - 1) / G;
+  const long grp = blk / tiles, c0 = (blk % tiles) * G;
+  if (grp >= cg.ngroup) return;  // uniform across the block
+  cx<T>* lds = (cx<T>*)smem;
+  const cx<T>* src = (const cx<T>*)(cg.src == 1 ? pb.W1 : pb.W2) + grp * cg.gin + c0;
+  cx<T>* dst = (cx<T>*)(cg.dst == 1 ? pb.W1 : pb.W2) + grp * cg.gout + c0;
+  const int gv = (int)min((long)G, cg.gs - c0);  // valid lines in this tile
+  // coalesced load: consecutive threads take consecutive lines of one element row
+  for (long e = threadIdx.x; e < (long)G * L; e += blockDim.x) {
+    int j = e % G, i = e / G;
+    cx<T> v = {0, 0};
+    if (i < cg.nin && j < gv) v = src[(long)i * cg.ein + j];
+    lds[(long)j * L + i] = v;
+  }
+  __syncthreads();
+  cx<T>* buf = lds + (long)g * L;
+  if (MODE == COL_INV)
+    fft_line<T, true>(buf, A.fft, lane);
+  else
+    fft_line<T, false>(buf, A.fft, lane);
+  if (MODE == COL_CONV) {
+    // symbol s0 + s1 lambda on the folded octant, times 1/prod(P)
+    const T* lam = (const T*)pb.lam;
+    double norm = 1.0;
+    for (int a = 0; a < pb.d; ++a) norm *= pb.ax[a].P;
+    const T s0 = (T)(pb.s0 / norm), s1 = (T)(pb.s1 / norm);
+    const long c = c0 + g;
+    long lidx_tail;  // index contribution of the axes after axis 0
+    if (pb.d == 2) {
+      lidx_tail = c;
+    } else {
+      const int H2 = pb.ax[2].H, P1 = pb.ax[1].P;
+      long k1 = c / H2, k2 = c % H2;
+      lidx_tail = (long)fold((int)k1, P1) * H2 + k2;
+    }
+    long tailsz = (pb.d == 2) ? pb.ax[1].H : (long)pb.ax[1].H * pb.ax[2].H;
+    if (c < cg.gs) {
+      for (int k = lane; k < L; k += tpl) {
+        T lv = lam[(long)fold(k, L) * tailsz + lidx_tail];
+        buf[k] = cscale(buf[k], s0 + s1 * lv);
+      }
+    }
+    __syncthreads();
+    fft_line<T, true>(buf, A.fft, lane);
+  }
+  __syncthreads();
+  for (long e = threadIdx.x; e < (long)G * cg.nout; e += blockDim.x) {
+    int j = e % G, i = e / G;
+    if (j < gv) dst[(long)i * cg.eout + j] = lds[(long)j * L + i];
+  }
+}
+
+// Inverse row pass: half spectrum -> real rows, crop to n, epilogue.
+template <typename T, int EPI>
+__device__ void rowinv_body(const Prob& pb, const Iter& it, bool check_done, int nblk, int blk) {
+  if (check_done && pb.sc->done) return;
+  extern __shared__ __align__(16) char smem[];
+  const Axis& A = pb.ax[pb.d - 1];
+  const int n = A.n, P = A.P, H = A.H, tpl = A.fft.tpl;
+  const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  cx<T>* buf = (cx<T>*)smem + (long)g * P;
+  const long rows = nrows_of(pb), nper = nper_of(pb);
+  const long ra = 2 * ((long)blk * G + g), rb = ra + 1;
+  const bool va = ra < rows, vb = rb < rows;
+  const cx<T>* W = (const cx<T>*)pb.W1;
+  for (int k = lane; k < P; k += tpl) {
+    int kk = k < H ? k : P - k;
+    cx<T> xa = va ? W[ra * H + kk] : cx<T>{0, 0};
+    cx<T> xb = vb ? W[rb * H + kk] : cx<T>{0, 0};
+    if (kk == 0 || 2 * kk == P) { xa.y = 0; xb.y = 0; }
+    if (k >= H) { xa.y = -xa.y; xb.y = -xb.y; }
+    buf[k] = {xa.x - xb.y, xa.y + xb.x};
+  }
+  __syncthreads();
+  fft_line<T, true>(buf, A.fft, lane);
+  double acc = 0.0;
+  for (int i = lane; i < n; i += tpl) {
+    cx<T> y = buf[i];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      long row = s ? rb : ra;
+      if (!(s ? vb : va)) continue;
+      long e = row * n + i;
+      T v = s ? y.y : y.x;
+      if (pb.mask) v *= (T)pb.mask[e % nper];
+      if (EPI == EPI_PLAIN) {
+        ((T*)pb.out)[e] = v;
+      } else if (EPI == EPI_RESID) {
+        T rv = ((const T*)pb.aux)[e] - v;
+        ((T*)pb.out)[e] = rv;
+        acc += (double)rv * (double)rv;
+      } else {  // EPI_PQ: q = M p, accumulate p.q
+        ((T*)pb.q)[e] = v;
+        acc += (double)((const T*)pb.p)[e] * (double)v;
+      }
+    }
+  }
+  if (EPI == EPI_RESID) {
+    double tot;
+    if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_RR], nblk, blk, &tot) && threadIdx.x == 0) pb.sc->rr = tot;
+  } else if (EPI == EPI_PQ) {
+    double tot;
+    if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_PQ], nblk, blk, &tot) && threadIdx.x == 0) {
+      pb.sc->pq = tot;
+      if (!(tot > 0.0) || !isfinite(tot)) pb.sc->done = 3;  // breakdown
+    }
+  }
+}
+
+// 1D: whole convolution of two packed lines in one pass (real symbol keeps
+// x + i y separable: conv(x) = Re, conv(y) = Im).
+template <typename T, int PRO, int EPI>
+__device__ void conv1d_body(const Prob& pb, const Iter& it, int nblk, int blk) {
+  if ((PRO == PRO_PUPD || EPI == EPI_PQ) && pb.sc->done) return;
+  extern __shared__ __align__(16) char smem[];
+  const Axis& A = pb.ax[0];
+  const int n = A.n, P = A.P, tpl = A.fft.tpl;
+  const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  cx<T>* buf = (cx<T>*)smem + (long)g * P;
+  const long rows = pb.nrhs, nper = n;
+  const long ra = 2 * ((long)blk * G + g), rb = ra + 1;
+  const bool va = ra < rows, vb = rb < rows;
+  double beta = 0.0;
+  if (PRO == PRO_PUPD && !it.first) beta = pb.sc->rz[it.parity] / pb.sc->rz[it.parity ^ 1];
+  for (int i = lane; i < P; i += tpl) {
+    T xa = 0, xb = 0;
+    if (i < n) {
+      if (va) xa = load_input<T, PRO>(pb, ra * n + i, nper, beta, it.first);
+      if (vb) xb = load_input<T, PRO>(pb, rb * n + i, nper, beta, it.first);
+    }
+    buf[i] = {xa, xb};
+  }
+  __syncthreads();
+  fft_line<T, false>(buf, A.fft, lane);
+  {
+    const T* lam = (const T*)pb.lam;
+    const T s0 = (T)(pb.s0 / P), s1 = (T)(pb.s1 / P);
+    for (int k = lane; k < P; k += tpl) buf[k] = cscale(buf[k], s0 + s1 * lam[fold(k, P)]);
+  }
+  __syncthreads();
+  fft_line<T, true>(buf, A.fft, lane);
+  double acc = 0.0;
+  for (int i = lane; i < n; i += tpl) {
+    cx<T> y = buf[i];
+    for (int s = 0; s < 2; ++s) {
+      if (!(s ? vb : va)) continue;
+      long e = (s ? rb : ra) * n + i;
+      T v = s ? y.y : y.x;
+      if (pb.mask) v *= (T)pb.mask[e % nper];
+      if (EPI == EPI_PLAIN) {
+        ((T*)pb.out)[e] = v;
+      } else if (EPI == EPI_RESID) {
+        T rv = ((const T*)pb.aux)[e] - v;
+        ((T*)pb.out)[e] = rv;
+        acc += (double)rv * (double)rv;
+      } else {
+        ((T*)pb.q)[e] = v;
+        acc += (double)((const T*)pb.p)[e] * (double)v;
+      }
+    }
+  }
+  if (EPI == EPI_RESID) {
+    double tot;
+    if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_RR], nblk, blk, &tot) && threadIdx.x == 0) pb.sc->rr = tot;
+  } else if (EPI == EPI_PQ) {
+    double tot;
+    if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_PQ], nblk, blk, &tot) && threadIdx.x == 0) {
+      pb.sc->pq = tot;
+      if (!(tot > 0.0) || !isfinite(tot)) pb.sc->done = 3;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sine transforms (type I) by the chirp-z identity, one real line per FFT line.
+// ---------------------------------------------------------------------------
+// In: LDS line buf holding x_j (real, in .x) for j < n.  Out: buf[k].x = DST(x)_k.
+template <typename T>
+__device__ void dst_line(cx<T>* buf, const Axis& A, int lane, int tpl) {
+  const int n = A.n, Lb = A.dst.L;
+  const cx<T>* ch = (const cx<T>*)A.chirp;
+  const cx<T>* bh = (const cx<T>*)A.bhat;
+  for (int j = lane; j < Lb; j += tpl) {
+    cx<T> v = {0, 0};
+    if (j < n) v = cscale(ch[j + 1], buf[j].x);
+    buf[j] = v;
+  }
+  __syncthreads();
+  fft_line<T, false>(buf, A.dst, lane);
+  for (int k = lane; k < Lb; k += tpl) buf[k] = cmul(buf[k], bh[k]);
+  __syncthreads();
+  fft_line<T, true>(buf, A.dst, lane);
+  for (int k = lane; k < n; k += tpl) {
+    cx<T> y = cmul(ch[k + 1], buf[k]);
+    buf[k] = {y.y, 0};
+  }
+  __syncthreads();
+}
+
+enum { DPRO_PLAIN = 0, DPRO_UPD = 1 };
+enum { DEPI_STORE = 0, DEPI_FINAL = 1, DEPI_Z = 2 };
+
+// Row sine pass along the last axis.  d == 1 performs the whole inverse
+// (transform, divide by the eigenvalue, transform, normalise) in this pass.
+//  DPRO_UPD: x += alpha p, r -= alpha q (alpha = rz/pq), r.r reduced and the
+//            stop test taken by the last block; the new r is transformed.
+//  DEPI_STORE: out = result (a first pass of a multi-axis transform)
+//  DEPI_FINAL: out = norm * result
+//  DEPI_Z:     z = norm * result, r.z reduced into rz[parity ^ 1].
+template <typename T, int DPRO, int DEPI>
+__device__ void dst_rows_body(const Prob& pb, const Iter& it, bool check_done, int nblk, int blk) {
+  if (check_done && pb.sc->done) return;
+  extern __shared__ __align__(16) char smem[];
+  const Axis& A = pb.ax[pb.d - 1];
+  const int n = A.n, Lb = A.dst.L, tpl = A.dst.tpl;
+  const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  cx<T>* buf = (cx<T>*)smem + (long)g * Lb;
+  const long rows = nrows_of(pb), nper = nper_of(pb);
+  const long row = (long)blk * G + g;
+  const bool valid = row < rows;
+  double acc = 0.0;
+  double alpha = 0.0;
+  if (DPRO == DPRO_UPD) alpha = pb.sc->rz[it.parity] / pb.sc->pq;
+  for (int i = lane; i < n; i += tpl) {
+    T v = 0;
+    if (valid) {
+      long e = row * n + i;
+      if (DPRO == DPRO_UPD) {
+        T* x = (T*)pb.x;
+        T* r = (T*)pb.r;
+        x[e] += (T)alpha * ((const T*)pb.p)[e];
+        T rv = r[e] - (T)alpha * ((const T*)pb.q)[e];
+        r[e] = rv;
+        acc += (double)rv * (double)rv;
+        v = rv;
+      } else {
+        v = ((const T*)pb.in)[e];
+        // the domain mask acts on grid functions only: the input of the first
+        // pass (or of the single 1D pass), never on a transformed intermediate
+        if (pb.mask && (DEPI == DEPI_STORE || pb.d == 1)) v *= (T)pb.mask[e % nper];
+      }
+    }
+    buf[i] = {v, 0};
+  }
+  if (DPRO == DPRO_UPD) {
+    double tot;
+    if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_RR], nblk, blk, &tot) && threadIdx.x == 0) {
+      pb.sc->rr = tot;
+      int itn = pb.sc->iters + 1;
+      pb.sc->iters = itn;
+      if (!isfinite(tot)) pb.sc->done = 3;
+      else if (tot <= pb.sc->thr) pb.sc->done = 1;
+      else if (itn >= pb.sc->maxit) pb.sc->done = 2;
+    }
+  }
+  __syncthreads();
+  dst_line<T>(buf, A, lane, tpl);
+  if (pb.d == 1) {
+    const T* ev = (const T*)A.eig;
+    for (int k = lane; k < n; k += tpl)
+      buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * (double)ev[k]);
+    __syncthreads();
+    dst_line<T>(buf, A, lane, tpl);
+  }
+  double norm = 1.0;
+  if (pb.d == 1 || DEPI != DEPI_STORE)
+    for (int a = 0; a < pb.d; ++a) norm *= 2.0 / (pb.ax[a].n + 1);
+  double acc2 = 0.0;
+  for (int i = lane; i < n; i += tpl) {
+    if (!valid) break;
+    long e = row * n + i;
+    T v = buf[i].x * (T)norm;
+    if (pb.mask && (DEPI != DEPI_STORE || pb.d == 1)) v *= (T)pb.mask[e % nper];
+    if (DEPI != DEPI_Z) {
+      ((T*)pb.out)[e] = v;
+    } else {
+      ((T*)pb.z)[e] = v;
+      acc2 += (double)((const T*)pb.r)[e] * (double)v;
+    }
+  }
+  if (DEPI == DEPI_Z) {
+    double tot;
+    if (grid_sum(acc2, pb.part + nblk, &pb.sc->ctr[SITE_RZ], nblk, blk, &tot) && threadIdx.x == 0)
+      pb.sc->rz[it.parity ^ 1] = tot;
+  }
+}
+
+// Strided real sine pass on T1 (in place).  SCALE: transform along axis 0,
+// divide by p0 + p1 pcs (e_0 + e_1 [+ e_2]), transform again.
+struct DGeom {
+  int axis;
+  long gs, ngroup, estride, gstride;
+};
+
+template <typename T, bool SCALE>
+__device__ void dst_cols_body(const Prob& pb, const DGeom& dg, bool check_done, int blk) {
+  if (check_done && pb.sc->done) return;
+  extern __shared__ __align__(16) char smem[];
+  const Axis& A = pb.ax[dg.axis];
+  const int n = A.n, Lb = A.dst.L, tpl = A.dst.tpl;
+  const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  const long tiles = (dg.gs + G - 1) / G;
+  const long grp = blk / tiles, c0 = (blk % tiles) * G;
+  if (grp >= dg.ngroup) return;
+  cx<T>* lds = (cx<T>*)smem;
+  T* base = (T*)pb.T1 + grp * dg.gstride + c0;
+  const int gv = (int)min((long)G, dg.gs - c0);
+  for (long e = threadIdx.x; e < (long)G * n; e += blockDim.x) {
+    int j = e % G, i = e / G;
+    T v = 0;
+    if (j < gv) v = base[(long)i * dg.estride + j];
+    lds[(long)j * Lb + i] = {v, 0};
+  }
+  __syncthreads();
+  cx<T>* buf = lds + (long)g * Lb;
+  dst_line<T>(buf, A, lane, tpl);
+  if (SCALE) {
+    const long c = c0 + g;
+    double etail = 0.0;
+    if (c < dg.gs) {
+      if (pb.d == 2) {
+        etail = (double)((const T*)pb.ax[1].eig)[c];
+      } else {
+        const int n2 = pb.ax[2].n;
+        etail = (double)((const T*)pb.ax[1].eig)[c / n2] + (double)((const T*)pb.ax[2].eig)[c % n2];
+      }
+    }
+    const T* ev = (const T*)A.eig;
+    for (int k = lane; k < n; k += tpl)
+      buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * ((double)ev[k] + etail));
+    __syncthreads();
+    dst_line<T>(buf, A, lane, tpl);
+  }
+  for (long e = threadIdx.x; e < (long)G * n; e += blockDim.x) {
+    int j = e % G, i = e / G;
+    if (j < gv) base[(long)i * dg.estride + j] = lds[(long)j * Lb + i].x;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels
+// ---------------------------------------------------------------------------
+// dot(a, b) (FP64 accumulation) into one of the scalar slots.
+enum { DOT_FF = 0, DOT_RR = 1, DOT_AUX0 = 2, DOT_AUX1 = 3, DOT_RZ0 = 4 };
+template <typename T>
+__device__ void dot_body(const Prob& pb, const void* a, const void* b, int target, long n, int nblk, int blk) {
+  double acc = 0.0;
+  for (long i = (long)blk * blockDim.x + threadIdx.x; i < n; i += (long)nblk * blockDim.x)
+    acc += (double)((const T*)a)[i] * (double)((const T*)b)[i];
+  double tot;
+  if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_DOT], nblk, blk, &tot) && threadIdx.x == 0) {
+    switch (target) {
+      case DOT_FF: pb.sc->ff = tot; break;
+      case DOT_RR: pb.sc->rr = tot; break;
+      case DOT_AUX0: pb.sc->aux[0] = tot; break;
+      case DOT_AUX1: pb.sc->aux[1] = tot; break;
+      default: pb.sc->rz[0] = tot; break;
+    }
+  }
+}
+
+
+// Plain CG update (no preconditioner, z aliases r): x += alpha p, r -= alpha q,
+// r.r reduced, stop test, and rz[parity^1] = r.r.
+template <typename T>
+__device__ void update_body(const Prob& pb, const Iter& it, long n, int nblk, int blk) {
+  if (pb.sc->done) return;
+  const double alpha = pb.sc->rz[it.parity] / pb.sc->pq;
+  T* x = (T*)pb.x;
+  T* r = (T*)pb.r;
+  const T* p = (const T*)pb.p;
+  const T* q = (const T*)pb.q;
+  double acc = 0.0;
+  for (long i = (long)blk * blockDim.x + threadIdx.x; i < n; i += (long)nblk * blockDim.x) {
+    x[i] += (T)alpha * p[i];
+    T rv = r[i] - (T)alpha * q[i];
+    r[i] = rv;
+    acc += (double)rv * (double)rv;
+  }
+  double tot;
+  if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_RR], nblk, blk, &tot) && threadIdx.x == 0) {
+    pb.sc->rr = tot;
+    pb.sc->rz[it.parity ^ 1] = tot;
+    int itn = pb.sc->iters + 1;
+    pb.sc->iters = itn;
+    if (!isfinite(tot)) pb.sc->done = 3;
+    else if (tot <= pb.sc->thr) pb.sc->done = 1;
+    else if (itn >= pb.sc->maxit) pb.sc->done = 2;
+  }
+}
+
+// Start of a Krylov solve: thr = tol^2 ff, counters cleared, done when the
+// initial residual already meets the tolerance.  use_rr: the initial residual
+// norm is in rr (warm start); otherwise r = f and rr = ff.
+__device__ void init_body(const Prob& pb, double tol, int maxit, int use_rr) {
+  if (threadIdx.x != 0) return;
+  Scalars* s = pb.sc;
+  if (!use_rr) s->rr = s->ff;
+  s->thr = tol * tol * s->ff;
+  s->rr0 = s->rr;
+  s->iters = 0;
+  s->maxit = maxit;
+  s->done = (s->rr <= s->thr) ? 1 : 0;
+  if (!(s->ff > 0.0)) s->done = 1;  // zero right-hand side: x = 0 is exact
+}
+
+// y = a * x + b * y elementwise (any of the two real types), n elements.
+template <typename TX, typename TY>
+__global__ void k_axpby(const TX* x, TY* y, double a, double b, long n) {
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (TY)(a * (double)x[i] + (b == 0.0 ? 0.0 : b * (double)y[i]));
+}
+// y = a * x + b * y with a taken from device scalar *ap times s (refinement scale)
+template <typename TX, typename TY>
+__global__ void k_axpby_dev(const TX* x, TY* y, const double* ap, double s, int sqrt_a, double b, long n) {
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double a = sqrt_a ? sqrt(*ap) * s : (*ap) * s;
+  if (i < n) y[i] = (TY)(a * (double)x[i] + (b == 0.0 ? 0.0 : b * (double)y[i]));
+}
+template <typename T> __global__ void k_fill(T* y, T v, long n) {
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// kernel wrappers
+// ---------------------------------------------------------------------------
+#define FL_BOUNDS __launch_bounds__(1024)
+
+template <typename T, int PRO> __global__ FL_BOUNDS void k_rowfwd(Prob pb, Iter it) {
+  rowfwd_body<T, PRO>(pb, it, blockIdx.x);
+}
+template <typename T, int PRO> __global__ FL_BOUNDS void k_rowfwd_b(const Prob* pbs, Iter it, const int* nb) {
+  if ((int)blockIdx.x >= nb[blockIdx.y]) return;
+  rowfwd_body<T, PRO>(pbs[blockIdx.y], it, blockIdx.x);
+}
+template <typename T, int MODE> __global__ FL_BOUNDS void k_colpass(Prob pb, ColGeom cg, Iter it, int chk) {
+  colpass_body<T, MODE>(pb, cg, it, chk, blockIdx.x);
+}
+template <typename T, int MODE>
+__global__ FL_BOUNDS void k_colpass_b(const Prob* pbs, const ColGeom* cgs, Iter it, int chk, const int* nb) {
+  if ((int)blockIdx.x >= nb[blockIdx.y]) return;
+  colpass_body<T, MODE>(pbs[blockIdx.y], cgs[blockIdx.y], it, chk, blockIdx.x);
+}
+template <typename T, int EPI> __global__ FL_BOUNDS void k_rowinv(Prob pb, Iter it, int chk) {
+  rowinv_body<T, EPI>(pb, it, chk, gridDim.x, blockIdx.x);
+}
+template <typename T, int EPI>
+__global__ FL_BOUNDS void k_rowinv_b(const Prob* pbs, Iter it, int chk, const int* nb) {
+  if ((int)blockIdx.x >= nb[blockIdx.y]) return;
+  rowinv_body<T, EPI>(pbs[blockIdx.y], it, chk, nb[blockIdx.y], blockIdx.x);
+}
+template <typename T, int PRO, int EPI> __global__ FL_BOUNDS void k_conv1d(Prob pb, Iter it) {
+  conv1d_body<T, PRO, EPI>(pb, it, gridDim.x, blockIdx.x);
+}
+template <typename T, int PRO, int EPI>
+__global__ FL_BOUNDS void k_conv1d_b(const Prob* pbs, Iter it, const int* nb) {
+  if ((int)blockIdx.x >= nb[blockIdx.y]) return;
+  conv1d_body<T, PRO, EPI>(pbs[blockIdx.y], it, nb[blockIdx.y], blockIdx.x);
+}
+template <typename T, int DPRO, int DEPI> __global__ FL_BOUNDS void k_dst_rows(Prob pb, Iter it, int chk) {
+  dst_rows_body<T, DPRO, DEPI>(pb, it, chk, gridDim.x, blockIdx.x);
+}
+template <typename T, int DPRO, int DEPI>
+__global__ FL_BOUNDS void k_dst_rows_b(const Prob* pbs, Iter it, int chk, const int* nb) {
+  if ((int)blockIdx.x >= nb[blockIdx.y]) return;
+  dst_rows_body<T, DPRO, DEPI>(pbs[blockIdx.y], it, chk, nb[blockIdx.y], blockIdx.x);
+}
+template <typename T, bool SCALE> __global__ FL_BOUNDS void k_dst_cols(Prob pb, DGeom dg, int chk) {
+  dst_cols_body<T, SCALE>(pb, dg, chk, blockIdx.x);
+}
+template <typename T, bool SCALE>
+__global__ FL_BOUNDS void k_dst_cols_b(const Prob* pbs, const DGeom* dgs, int chk, const int* nb) {
+  if ((int)blockIdx.x >= nb[blockIdx.y]) return;
+  dst_cols_body<T, SCALE>(pbs[blockIdx.y], dgs[blockIdx.y], chk, blockIdx.x);
+}
+template <typename T> __global__ void k_dot(Prob pb, const void* a, const void* b, int target, long n) {
+  dot_body<T>(pb, a, b, target, n, gridDim.x, blockIdx.x);
+}
+template <typename T> __global__ void k_update(Prob pb, Iter it, long n) {
+  update_body<T>(pb, it, n, gridDim.x, blockIdx.x);
+}
+template <typename T> __global__ void k_update_b(const Prob* pbs, Iter it, const long* ns, const int* nb) {
+  if ((int)blockIdx.x >= nb[blockIdx.y]) return;
+  update_body<T>(pbs[blockIdx.y], it, ns[blockIdx.y], nb[blockIdx.y], blockIdx.x);
+}
+__global__ void k_init(Prob pb, double tol, int maxit, int use_rr) { init_body(pb, tol, maxit, use_rr); }
+__global__ void k_init_b(const Prob* pbs, double tol, int maxit, int use_rr) {
+  init_body(pbs[blockIdx.y], tol, maxit, use_rr);
+}
+
+}  // namespace fl

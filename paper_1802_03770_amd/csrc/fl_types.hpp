@@ -1,0 +1,76 @@
+// Descriptors shared by the host driver and the kernels.
+//
+// Every kernel body takes one `Prob` (a problem: one operator, one right-hand
+// side) and a block index inside that problem.  A single-problem launch passes
+// the Prob by value; a batched launch (many right-hand sides and/or many
+// operators of uneven size) passes a device array of Probs and uses blockIdx.y
+// as the problem index, blocks beyond a problem's own count exiting at once.
+#pragma once
+#include <stdint.h>
+
+#include "fl_fft.hpp"
+
+namespace fl {
+
+// Per-axis data.  Axis 0 is the slowest (outermost) axis, axis d-1 the
+// contiguous one.  n: grid points; P: padded circulant length (even);
+// H = P/2 + 1 (folded / half-spectrum length).
+struct Axis {
+  int n, P, H;
+  FFTPlan fft;      // complex FFT of length P (operator application)
+  // type-I sine transform of length n by the chirp-z (Bluestein) identity:
+  //   sum_{j=1..n} x_j sin(pi j k/(n+1)) = Im( ch_k sum_j (x_j ch_j) conj(ch_{k-j}) ),
+  //   ch_m = e^{i pi m^2 / (2(n+1))}, convolution of length Lb >= 2n-1.
+  FFTPlan dst;      // complex FFT of length Lb
+  const void* chirp;  // cx<T>[n+1]
+  const void* bhat;   // cx<T>[Lb]  = FFT_Lb(conj chirp, circularly placed) / Lb
+  const void* eig;    // T[n]       = 4 sin^2(pi k / (2 (n+1))), k = 1..n
+};
+
+// Device-resident scalars of one Krylov solve (always FP64).
+struct Scalars {
+  double rz[2];   // r.z of the current / previous iteration (indexed by parity)
+  double pq;      // p.q
+  double rr;      // r.r
+  double ff;      // f.f
+  double thr;     // stop when rr <= thr  (thr = tol^2 ff)
+  double rr0;     // r.r at start
+  double aux[3];  // scratch scalars (refinement norms)
+  int done;       // 0 running, 1 converged, 2 iteration cap, 3 breakdown
+  int iters;
+  int maxit;
+  int pad;
+  unsigned int ctr[8];  // last-block-done counters, one per reduction site
+};
+
+enum ScalarSite { SITE_PQ = 0, SITE_RR = 1, SITE_RZ = 2, SITE_DOT = 3, SITE_DOT2 = 4 };
+
+struct Prob {
+  int d;          // 1, 2, 3
+  int nrhs;       // right-hand sides of this problem stacked along the batch axis (apply only)
+  Axis ax[3];
+  const void* lam;  // folded symbol, T, shape [H_0][H_1]...  (P_a/2+1 per axis)
+  double s0, s1;    // operator symbol is s0 + s1 * lambda  (identity shift for time steps)
+  double pcs;       // C |B| h^-alpha
+  double p0, p1;    // preconditioner eigenvalue p0 + p1 * pcs * sum_a eig_a
+  // buffers
+  const void* in;   // real input  [nrhs][n...]
+  void* out;        // real output
+  const void* aux;  // second real input (residual rhs f, or p for the p.q dot)
+  void* W1;         // complex work [nrhs][n_0..n_{d-2}][H_{d-1}]
+  void* W2;         // complex work, 3D only: [nrhs][n_0][P_1][H_2]
+  void* T1;         // real work for the sine transforms  [nrhs][n...]
+  const uint8_t* mask;  // optional domain mask (1 inside), [n...]
+  // Krylov vectors (solver launches)
+  void* x;
+  void* r;
+  void* z;
+  void* p;
+  void* q;
+  Scalars* sc;
+  double* part;     // partial sums, >= max blocks of any reduction launch
+  int parity;       // iteration parity (selects rz slots)
+  int first;        // 1 on the first Krylov iteration (p = z)
+};
+
+}  // namespace fl

@@ -1,0 +1,258 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 paths 1e-12 relative (max-norm against the oracle's max),
+FP32 paths 2e-5 relative (single-precision FFTs of length <= 2^12 give
+~ 1e-7 log2(P) per pass times the dynamic range of the symbol).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import constants as K  # noqa: E402
+from oracle import krylov as KR  # noqa: E402
+from oracle import operator as O  # noqa: E402
+from oracle import precond as PC  # noqa: E402
+from workloads import bump_field, random_mask, white_noise  # noqa: E402
+
+
+def _fl():
+    import paper_1802_03770_amd as fl
+    return fl
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+@pytest.mark.parametrize("d,alpha", [(1, 0.5), (1, 1.7), (2, 1.0), (2, 0.3), (3, 1.2), (3, 1.9)])
+def test_constants(d, alpha):
+    _say("constants", d, alpha)
+    fl = _fl()
+    op = fl.Op(d, alpha, 0.05, [8] * d)
+    c = op.constants()
+    assert c["C"] == pytest.approx(K.c_alpha(alpha, d), rel=1e-13)
+    assert c["Z"] == pytest.approx(K.lattice_zeta(d, alpha), rel=1e-13)
+    assert c["B"] == pytest.approx(K.b_const(d, alpha), rel=1e-12)
+    assert c["a2"] == pytest.approx(K.a2_sum(d, alpha), rel=1e-12)
+
+
+@pytest.mark.parametrize("n", [(37,), (48, 40), (20, 33), (9, 10, 12)])
+def test_weights_and_symbol(n):
+    _say("weights/symbol", n)
+    fl = _fl()
+    d, alpha, h = len(n), 1.3, 2.0 / (n[0] + 1)
+    op = fl.Op(d, alpha, h, n)
+    ref = O.Operator(d, alpha, h, n)
+    assert op.padded() == ref.P
+    wf = op.export(0).cpu().numpy()
+    assert _rel(wf, O.circulant_folded(ref.w, ref.P)) <= 1e-13
+    lam = op.export(1).cpu().numpy()
+    lam_ref = O.symbol_folded(ref.w, ref.P)
+    assert _rel(lam, lam_ref) <= 1e-12
+    lam32 = op.export(2).cpu().numpy()
+    assert _rel(lam32, lam_ref) <= 1e-6
+
+
+APPLY_CASES = [(37,), (64,), (48, 40), (64, 64), (30, 45), (7, 9), (12, 10, 9), (16, 16, 16)]
+
+
+@pytest.mark.parametrize("n", APPLY_CASES)
+def test_apply_fp64(n):
+    _say("apply fp64", n)
+    fl = _fl()
+    d, alpha, h = len(n), 1.1, 2.0 / (n[-1] + 1)
+    op = fl.Op(d, alpha, h, n)
+    ref = O.Operator(d, alpha, h, n)
+    u = white_noise(n, 11)
+    got = op.apply(_dev(u)).cpu().numpy()
+    want = ref.apply(u, method="dft")
+    assert _rel(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [(48, 40), (64,), (12, 10, 9)])
+def test_apply_fp32(n):
+    _say("apply fp32", n)
+    fl = _fl()
+    d, alpha, h = len(n), 1.5, 2.0 / (n[-1] + 1)
+    op = fl.Op(d, alpha, h, n)
+    ref = O.Operator(d, alpha, h, n)
+    u = white_noise(n, 12)
+    got = op.apply(_dev(u, torch.float32)).double().cpu().numpy()
+    want = ref.apply(u.astype(np.float32).astype(np.float64), method="dft")
+    assert _rel(got, want) <= 2e-5
+
+
+def test_apply_mask_shift_batch():
+    _say("apply mask/shift/batch")
+    fl = _fl()
+    n = (24, 30)
+    op = fl.Op(2, 0.8, 0.07, n)
+    ref = O.Operator(2, 0.8, 0.07, n)
+    m = random_mask(n, 3)
+    u = white_noise((3,) + n, 13)
+    got = op.apply(_dev(u), mask=_dev(m, torch.uint8), shift0=1.0, shift1=0.25).cpu().numpy()
+    for b in range(3):
+        want = m * (u[b] * m + 0.25 * ref.apply(u[b] * m, method="dft"))
+        assert _rel(got[b], want) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [(37,), (48, 40), (64, 64), (9, 10, 12)])
+@pytest.mark.parametrize("shift", [(0.0, 1.0), (1.0, 0.01)])
+def test_precond(n, shift):
+    _say("precond", n, shift)
+    fl = _fl()
+    d, alpha, h = len(n), 1.4, 2.0 / (n[0] + 1)
+    op = fl.Op(d, alpha, h, n)
+    r = white_noise(n, 14)
+    got = op.precond(_dev(r), p0=shift[0], p1=shift[1]).cpu().numpy()
+    want = PC.apply_inverse(r, PC.pc_scale(d, alpha, h), *shift)
+    assert _rel(got, want) <= 1e-12
+    got32 = op.precond(_dev(r, torch.float32), p0=shift[0], p1=shift[1]).double().cpu().numpy()
+    assert _rel(got32, want) <= 2e-5
+
+
+@pytest.mark.parametrize("n", [(37,), (24, 30), (9, 10, 12)])
+def test_precond_masked(n):
+    _say("precond masked", n)
+    fl = _fl()
+    d, alpha, h = len(n), 1.4, 0.05
+    op = fl.Op(d, alpha, h, n)
+    m = random_mask(n, 4) if d > 1 else (np.arange(n[0]) % 5 != 0).astype(np.uint8)
+    r = white_noise(n, 22)
+    got = op.precond(_dev(r), mask=_dev(m, torch.uint8)).cpu().numpy()
+    want = m * PC.apply_inverse(r * m, PC.pc_scale(d, alpha, h))
+    assert _rel(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("pc", [0, 1])
+def test_solve_c1_fp64_against_cholesky(pc):
+    _say("solve C1 fp64 pc", pc)
+    fl = _fl()
+    from workloads import workload_c1
+    w = workload_c1()
+    n, alpha, h, f = w["n"], w["alpha"], w["h"], w["f"]
+    op = fl.Op(2, alpha, h, (n, n))
+    ref = O.Operator(2, alpha, h, (n, n))
+    M = ref.dense()
+    xs = np.linalg.solve(M, f.ravel()).reshape(n, n)
+    u, info = op.solve(_dev(f), tol=1e-13, opts=fl.solve_opts(pc=pc))
+    u = u.cpu().numpy()
+    res = np.linalg.norm(f.ravel() - M @ u.ravel()) / np.linalg.norm(f)
+    assert res <= 1e-12
+    assert info["rel_res_true"] <= 1e-12
+    assert _rel(u, xs) <= 1e-10
+    # iteration count equals the oracle's PCG on the same problem within 1
+    sc = PC.pc_scale(2, alpha, h)
+    _, it, _, _ = KR.pcg(lambda v: (M @ v.ravel()).reshape(v.shape), f,
+                         (lambda r: PC.apply_inverse(r, sc)) if pc else None, tol=1e-10)
+    _, info10 = op.solve(_dev(f), tol=1e-10, opts=fl.solve_opts(pc=pc))
+    assert abs(info10["iters"] - it) <= 1
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_solve_graph_and_eager_agree(graph):
+    _say("solve graph", graph)
+    fl = _fl()
+    n = (40, 36)
+    op = fl.Op(2, 1.5, 0.05, n)
+    f = white_noise(n, 15)
+    u1, i1 = op.solve(_dev(f), tol=1e-11, opts=fl.solve_opts(graph=graph, poll_every=4))
+    u2, i2 = op.solve(_dev(f), tol=1e-11, opts=fl.solve_opts(graph=1 - graph, poll_every=6))
+    assert i1["iters"] == i2["iters"]
+    assert torch.equal(u1, u2)  # same kernels, same fixed-order reductions: bitwise equal
+
+
+@pytest.mark.parametrize("n", [(63,), (31, 33), (10, 12, 11)])
+def test_solve_mixed_precision_true_residual(n):
+    _say("mixed", n)
+    fl = _fl()
+    d, alpha, h = len(n), 1.2, 2.0 / (n[0] + 1)
+    op = fl.Op(d, alpha, h, n)
+    ref = O.Operator(d, alpha, h, n)
+    f, _ = bump_field(n[0], d, 8, 21) if len(set(n)) == 1 else (white_noise(n, 21), None)
+    u, info = op.solve(_dev(f), tol=1e-8, opts=fl.solve_opts(mixed=1))
+    u = u.cpu().numpy()
+    res = np.linalg.norm(f - ref.apply(u, method="dft")) / np.linalg.norm(f)
+    assert res <= 1e-8
+    assert info["outer_iters"] >= 1
+
+
+def test_solve_masked():
+    _say("masked solve")
+    fl = _fl()
+    n = (32, 28)
+    alpha, h = 1.6, 0.06
+    op = fl.Op(2, alpha, h, n)
+    ref = O.Operator(2, alpha, h, n, masked=random_mask(n, 5).astype(np.float64))
+    m = random_mask(n, 5)
+    f = white_noise(n, 16) * m
+    u, info = op.solve(_dev(f), mask=_dev(m, torch.uint8), tol=1e-12)
+    A = ref.dense()
+    xs = np.linalg.solve(A, f.ravel()[m.ravel() == 1])
+    got = u.cpu().numpy().ravel()
+    assert np.all(got[m.ravel() == 0] == 0)
+    assert _rel(got[m.ravel() == 1], xs) <= 1e-9
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_step_against_exact_propagator(theta):
+    _say("step", theta)
+    fl = _fl()
+    n = (12, 12)
+    d, alpha, h, dt, steps = 2, 1.2, 0.08, 0.01, 5
+    op = fl.Op(d, alpha, h, n)
+    M = O.Operator(d, alpha, h, n).dense()
+    u0 = white_noise(n, 17)
+    u = _dev(u0)
+    for _ in range(steps):
+        u, info = op.step(u, dt, theta, tol=1e-14)
+    want = KR.exact_propagator(M, dt, theta, steps, u0).reshape(n)
+    assert _rel(u.cpu().numpy(), want) <= 1e-11
+
+
+def test_step_with_forcing_is_linear_solve():
+    _say("step forcing")
+    fl = _fl()
+    n = (9, 8)
+    alpha, h, dt = 0.7, 0.1, 0.05
+    op = fl.Op(2, alpha, h, n)
+    M = O.Operator(2, alpha, h, n).dense()
+    u0, f0, f1 = white_noise(n, 18), white_noise(n, 19), white_noise(n, 20)
+    u, _ = op.step(_dev(u0), dt, 0.5, f_k=_dev(f0), f_k1=_dev(f1), tol=1e-14)
+    A = np.eye(M.shape[0]) + 0.5 * dt * M
+    b = (np.eye(M.shape[0]) - 0.5 * dt * M) @ u0.ravel() + dt * 0.5 * (f0 + f1).ravel()
+    assert _rel(u.cpu().numpy().ravel(), np.linalg.solve(A, b)) <= 1e-11
+
+
+def test_full_size_apply_sampled():
+    # 1024^2 FP64 apply in the launch configuration the bench uses; sampled outputs
+    _say("apply 1024^2 sampled")
+    fl = _fl()
+    from workloads import workload_c2
+    w = workload_c2(1.0)
+    n, alpha, h = w["n"], w["alpha"], w["h"]
+    op = fl.Op(2, alpha, h, (n, n))
+    u = w["f"]
+    got = op.apply(_dev(u)).cpu().numpy()
+    wref = O.weights_folded(2, alpha, h, (n, n))
+    rng = np.random.default_rng(0)
+    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n // 2, n // 3)] + [tuple(rng.integers(0, n, 2)) for _ in range(6)]
+    want = O.apply_at(wref, u, pts)
+    scale = np.abs(got).max()
+    for p, wv in zip(pts, want):
+        assert abs(got[p] - wv) <= 1e-12 * scale, (p, got[p], wv)
