@@ -1,9 +1,13 @@
 // Line FFT engine for gfx950: one or more complex lines held in LDS, transformed
 // in place by a Stockham autosort FFT whose radix sequence is chosen at run time
-// (radices 2, 3, 4, 5, 8).  Every thread of a line keeps its butterflies in
-// registers between the LDS read and the LDS write of a stage, so one LDS buffer
-// per line suffices.  A workgroup holds G lines of equal length; each line is
-// served by `tpl` consecutive lanes (a power of two), so G * tpl = blockDim.x.
+// (radices 2, 3, 4, 5, 8; the out-of-place variant adds odd primes 7..43).
+// Every thread of a line keeps its butterflies in registers between the LDS read
+// and the LDS write of a stage, so one LDS buffer per line suffices.  A workgroup
+// holds G lines of equal length; each line is served by `tpl` consecutive lanes
+// (a power of two), so G * tpl = blockDim.x.
+//
+// LDS lines are padded by one element every 128 bytes (Line<T>): the strided
+// writes of the first Stockham stages then spread over all banks.
 //
 // Twiddles come from a table of the L-th roots of unity e^{-2 pi i m / L}
 // (computed on the host in extended precision).
@@ -32,13 +36,35 @@ template <typename T, bool INV> __device__ __forceinline__ cx<T> mul_mi(cx<T> a)
 constexpr int kMaxStages = 16;
 constexpr int kMaxElems = 16;  // elements of one line held per lane
 
-struct FFTPlan {
-  int L;                 // transform length
-  int nst;               // number of stages
-  int tpl;               // lanes per line (power of two)
-  int rad[kMaxStages];   // radix of each stage
-  const void* tw;        // cx<T>[L] = e^{-2 pi i m / L}
+// A complex line in LDS with one padding element after every 128 bytes.
+template <typename T> struct Line {
+  static constexpr int S = sizeof(T) == 4 ? 4 : 3;  // log2(elements per 128 bytes)
+  cx<T>* p;
+  __device__ __forceinline__ cx<T>& operator[](int i) const { return p[i + (i >> S)]; }
+  // elements (including padding) one line of length L occupies
+  static __host__ __device__ constexpr int stride(int L) { return L + (L >> S) + 2; }
 };
+template <typename T> __device__ __forceinline__ Line<T> line_at(void* base, long idx, int L) {
+  return Line<T>{(cx<T>*)base + idx * (long)Line<T>::stride(L)};
+}
+
+// Radix of stage s is kRadix[(radcode >> 4 s) & 15] (no arrays in the plan, so
+// it stays in scalar registers when passed by value).
+struct FFTPlan {
+  int L;                      // transform length
+  int nst;                    // number of stages
+  int tpl;                    // lanes per line (power of two)
+  int pad;
+  unsigned long long radcode; // 4 bits per stage
+  const void* tw;             // cx<T>[L] = e^{-2 pi i m / L}
+};
+__host__ __device__ constexpr int radix_of_code(int c) {
+  return c == 0 ? 2 : c == 1 ? 3 : c == 2 ? 4 : c == 3 ? 5 : c == 4 ? 8 : c == 5 ? 7 : c == 6 ? 11 : c == 7 ? 13
+       : c == 8 ? 17 : c == 9 ? 19 : c == 10 ? 23 : c == 11 ? 29 : c == 12 ? 31 : c == 13 ? 37 : c == 14 ? 41 : 43;
+}
+__host__ __device__ __forceinline__ int stage_radix(const FFTPlan& pl, int s) {
+  return radix_of_code((int)((pl.radcode >> (4 * s)) & 15ull));
+}
 
 template <typename T, int R, bool INV> struct Bfly;
 
@@ -135,12 +161,24 @@ template <typename T, bool INV> struct Bfly<T, 5, INV> {
   }
 };
 
+// Butterfly j of a stage with stride Ns: k = j mod Ns, g = j / Ns (shift and
+// mask while Ns is a power of two, lgNs >= 0).
+__device__ __forceinline__ void split_j(int j, int Ns, int lgNs, int& g, int& k) {
+  if (lgNs >= 0) {
+    k = j & (Ns - 1);
+    g = j >> lgNs;
+  } else {
+    g = (int)((unsigned)j / (unsigned)Ns);
+    k = j - g * Ns;
+  }
+}
+
 // One Stockham stage of radix R on the line `buf` (length L, LDS).  Ns is the
 // product of the radices already applied.  Input butterfly j reads
 // buf[j + r L/R]; it is twiddled by w_{Ns R}^{r k} with k = j mod Ns and
 // written to buf[(j / Ns) Ns R + k + r Ns].
 template <typename T, int R, bool INV>
-__device__ __forceinline__ void fft_stage(cx<T>* buf, int L, int Ns, const cx<T>* __restrict__ tw,
+__device__ __forceinline__ void fft_stage(Line<T> buf, int L, int Ns, int lgNs, const cx<T>* __restrict__ tw,
                                           int lane, int tpl) {
   constexpr int MB = kMaxElems / R;
   const int nb = L / R;
@@ -150,7 +188,8 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int L, int Ns, const cx<T>
   for (int b = 0; b < MB; ++b) {
     const int j = lane + b * tpl;
     if (j < nb) {
-      const int k = j % Ns;
+      int g, k;
+      split_j(j, Ns, lgNs, g, k);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * nb];
       if (Ns > 1) {
@@ -169,8 +208,9 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int L, int Ns, const cx<T>
   for (int b = 0; b < MB; ++b) {
     const int j = lane + b * tpl;
     if (j < nb) {
-      const int k = j % Ns;
-      const int base = (j / Ns) * Ns * R + k;
+      int g, k;
+      split_j(j, Ns, lgNs, g, k);
+      const int base = g * Ns * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[b][r];
     }
@@ -178,23 +218,159 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int L, int Ns, const cx<T>
   __syncthreads();
 }
 
+__device__ __forceinline__ int next_lg(int lgNs, int R) {
+  if (lgNs < 0) return -1;
+  return R == 2 ? lgNs + 1 : R == 4 ? lgNs + 2 : R == 8 ? lgNs + 3 : -1;
+}
+
 // Full in-place FFT of the LDS line `buf` (unnormalised in both directions).
 // Every lane of the workgroup must call this (it contains barriers).
 template <typename T, bool INV>
-__device__ void fft_line(cx<T>* buf, const FFTPlan& pl, int lane) {
+__device__ __forceinline__ void fft_line(Line<T> buf, const FFTPlan pl, int lane) {
   const cx<T>* __restrict__ tw = (const cx<T>*)pl.tw;
-  int Ns = 1;
+  int Ns = 1, lg = 0;
   for (int s = 0; s < pl.nst; ++s) {
-    const int R = pl.rad[s];
+    const int R = stage_radix(pl, s);
     switch (R) {
-      case 8: fft_stage<T, 8, INV>(buf, pl.L, Ns, tw, lane, pl.tpl); break;
-      case 4: fft_stage<T, 4, INV>(buf, pl.L, Ns, tw, lane, pl.tpl); break;
-      case 2: fft_stage<T, 2, INV>(buf, pl.L, Ns, tw, lane, pl.tpl); break;
-      case 3: fft_stage<T, 3, INV>(buf, pl.L, Ns, tw, lane, pl.tpl); break;
-      default: fft_stage<T, 5, INV>(buf, pl.L, Ns, tw, lane, pl.tpl); break;
+      case 8: fft_stage<T, 8, INV>(buf, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 4: fft_stage<T, 4, INV>(buf, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 2: fft_stage<T, 2, INV>(buf, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 3: fft_stage<T, 3, INV>(buf, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      default: fft_stage<T, 5, INV>(buf, pl.L, Ns, lg, tw, lane, pl.tpl); break;
     }
+    lg = next_lg(lg, R);
     Ns *= R;
   }
+}
+
+
+// Out-of-place Stockham stage (src -> dst, one barrier), radices 2..8.
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void fft_stage_oop(Line<T> src, Line<T> dst, int L, int Ns, int lgNs,
+                                              const cx<T>* __restrict__ tw, int lane, int tpl) {
+  const int nb = L / R;
+  const int tstep = L / (Ns * R);
+  for (int j = lane; j < nb; j += tpl) {
+    int g, k;
+    split_j(j, Ns, lgNs, g, k);
+    cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+    if (Ns > 1) {
+      const int st = k * tstep;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cx<T> w = tw[r * st];
+        v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+      }
+    }
+    Bfly<T, R, INV>::run(v);
+    const int base = g * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  }
+  __syncthreads();
+}
+
+// Out-of-place radix-R stage for an odd prime R >= 7: direct DFT with the
+// conjugate-pair reduction.  With s_q = a_q + a_{R-q}, d_q = a_q - a_{R-q},
+// q = 1..(R-1)/2:
+//   y_k     = a_0 + sum_q s_q cos(2 pi q k / R) -+ i sum_q d_q sin(2 pi q k / R),
+//   y_{R-k} = the same with the opposite sign of the sine part
+// (upper sign forward).  Only s, d and the R roots live in registers; outputs
+// go straight to dst.  The roots are e^{-2 pi i m / R} = tw[m L / R].
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void fft_stage_prime_oop(Line<T> src, Line<T> dst, int L, int Ns, int lgNs,
+                                                    const cx<T>* __restrict__ tw, int lane, int tpl) {
+  constexpr int H = (R - 1) / 2;
+  const int nb = L / R;
+  const int tstep = L / (Ns * R);
+  const int cstep = L / R;
+  T cs[H + 1], sn[H + 1];
+#pragma unroll
+  for (int m = 1; m <= H; ++m) {
+    cx<T> w = tw[m * cstep];
+    cs[m] = w.x;
+    sn[m] = -w.y;
+  }
+  for (int j = lane; j < nb; j += tpl) {
+    int g, k;
+    split_j(j, Ns, lgNs, g, k);
+    const int st = k * tstep;
+    cx<T> a0 = src[j];
+    cx<T> sm[H], df[H];
+    cx<T> y0 = a0;
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+      cx<T> u = src[j + q * nb], w = src[j + (R - q) * nb];
+      if (Ns > 1) {
+        cx<T> t1 = tw[q * st], t2 = tw[(R - q) * st];
+        u = INV ? cmulc(u, t1) : cmul(u, t1);
+        w = INV ? cmulc(w, t2) : cmul(w, t2);
+      }
+      sm[q - 1] = cadd(u, w);
+      df[q - 1] = csub(u, w);
+      y0 = cadd(y0, sm[q - 1]);
+    }
+    const int base = g * Ns * R + k;
+    dst[base] = y0;
+#pragma unroll
+    for (int kk = 1; kk <= H; ++kk) {
+      cx<T> re = a0, im = {0, 0};
+#pragma unroll
+      for (int q = 1; q <= H; ++q) {
+        const int m = (q * kk) % R;
+        const T c = m <= H ? cs[m] : cs[R - m];
+        const T sg = m <= H ? sn[m] : -sn[R - m];
+        re.x += sm[q - 1].x * c;
+        re.y += sm[q - 1].y * c;
+        im.x += df[q - 1].x * sg;
+        im.y += df[q - 1].y * sg;
+      }
+      cx<T> yp = {re.x + im.y, re.y - im.x};  // re - i im
+      cx<T> ym = {re.x - im.y, re.y + im.x};  // re + i im
+      dst[base + kk * Ns] = INV ? ym : yp;
+      dst[base + (R - kk) * Ns] = INV ? yp : ym;
+    }
+  }
+  __syncthreads();
+}
+
+// Out-of-place FFT with the wide radix set (2, 3, 4, 5, 8 and odd primes
+// 7..43), ping-ponging between a and b (each of length L).  Returns the buffer
+// holding the result.  Used by the sine transforms of length 2(n+1).
+template <typename T, bool INV>
+__device__ __forceinline__ Line<T> fft_line_wide(Line<T> a, Line<T> b, const FFTPlan pl, int lane) {
+  const cx<T>* __restrict__ tw = (const cx<T>*)pl.tw;
+  int Ns = 1, lg = 0;
+  Line<T> src = a, dst = b;
+  for (int s = 0; s < pl.nst; ++s) {
+    const int R = stage_radix(pl, s);
+    switch (R) {
+      case 8: fft_stage_oop<T, 8, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 4: fft_stage_oop<T, 4, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 2: fft_stage_oop<T, 2, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 3: fft_stage_oop<T, 3, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 5: fft_stage_oop<T, 5, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 7: fft_stage_prime_oop<T, 7, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 11: fft_stage_prime_oop<T, 11, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 13: fft_stage_prime_oop<T, 13, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 17: fft_stage_prime_oop<T, 17, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 19: fft_stage_prime_oop<T, 19, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 23: fft_stage_prime_oop<T, 23, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 29: fft_stage_prime_oop<T, 29, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 31: fft_stage_prime_oop<T, 31, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 37: fft_stage_prime_oop<T, 37, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      case 41: fft_stage_prime_oop<T, 41, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+      default: fft_stage_prime_oop<T, 43, INV>(src, dst, pl.L, Ns, lg, tw, lane, pl.tpl); break;
+    }
+    lg = next_lg(lg, R);
+    Ns *= R;
+    Line<T> t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
 }
 
 }  // namespace fl

@@ -70,7 +70,8 @@ static int smooth_at_least(int m) {
   return L;
 }
 
-static bool make_radices(int L, FFTPlan& pl) {
+// Radix sequence for length L.  wide: also odd primes 7..43 (sine kernels).
+static bool make_radices(int L, FFTPlan& pl, bool wide = false) {
   std::vector<int> r;
   int m = L;
   while (m % 8 == 0) { r.push_back(8); m /= 8; }
@@ -78,21 +79,31 @@ static bool make_radices(int L, FFTPlan& pl) {
   while (m % 2 == 0) { r.push_back(2); m /= 2; }
   while (m % 3 == 0) { r.push_back(3); m /= 3; }
   while (m % 5 == 0) { r.push_back(5); m /= 5; }
+  if (wide)
+    for (int p : {7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43})
+      while (m % p == 0) { r.push_back(p); m /= p; }
   if (m != 1 || (int)r.size() > kMaxStages) return false;
   pl.L = L;
   pl.nst = (int)r.size();
-  for (int i = 0; i < kMaxStages; ++i) pl.rad[i] = i < pl.nst ? r[i] : 1;
+  pl.pad = 0;
+  pl.radcode = 0;
+  for (int i = 0; i < pl.nst; ++i) {
+    int c = 0;
+    while (radix_of_code(c) != r[i]) ++c;
+    pl.radcode |= (unsigned long long)c << (4 * i);
+  }
   int tpl = 1;
   while (tpl * kMaxElems < L) tpl *= 2;
   for (;;) {
     bool ok = true;
     for (int R : r) {
       int nb = L / R, per = (nb + tpl - 1) / tpl;
-      if (per > kMaxElems / R) ok = false;
+      if (per > std::max(1, kMaxElems / R)) ok = false;
     }
     if (ok) break;
     tpl *= 2;
   }
+  if (tpl > 256) return false;  // kernels run 256-lane workgroups
   pl.tpl = tpl;
   return true;
 }
@@ -179,11 +190,20 @@ template <typename T> static fl_status build_axis(fl_op op, int a) {
   A.H = op->H[a];
   if (!make_radices(A.P, A.fft)) return fail(FL_E_UNSUPPORTED, "padded length not 2,3,5-smooth");
   STCHK(upload(op, host_twiddles<T>(A.P), &A.fft.tw));
-  // sine transform by the chirp-z identity
-  const int Lb = smooth_at_least(2 * n - 1);
-  if (!make_radices(Lb, A.dst)) return fail(FL_E_UNSUPPORTED, "sine transform length");
+  // sine transform: direct (odd extension of length 2(n+1), two lines per FFT
+  // line) when 2(n+1) factors over the wide radix set, else the chirp-z identity
+  A.dst_direct = make_radices(2 * (n + 1), A.dst, true) ? 1 : 0;
+  const int Lb = A.dst_direct ? 2 * (n + 1) : smooth_at_least(2 * n - 1);
+  if (!A.dst_direct && !make_radices(Lb, A.dst)) return fail(FL_E_UNSUPPORTED, "sine transform length");
   STCHK(upload(op, host_twiddles<T>(Lb), &A.dst.tw));
   const long N1 = n + 1;
+  std::vector<T> ev(n);
+  for (int k = 0; k < n; ++k) {
+    long double sn = sinl(kPiL * (k + 1) / (2.0L * N1));
+    ev[k] = (T)(4.0L * sn * sn);
+  }
+  STCHK(upload(op, ev, &A.eig));
+  if (A.dst_direct) return FL_OK;
   std::vector<cx<T>> ch(n + 1);
   std::vector<std::complex<long double>> chl(n + 1);
   for (long m = 0; m <= n; ++m) {
@@ -209,12 +229,6 @@ template <typename T> static fl_status build_axis(fl_op op, int a) {
     bh[k] = {(T)s.real(), (T)s.imag()};
   }
   STCHK(upload(op, bh, &A.bhat));
-  std::vector<T> ev(n);
-  for (int k = 0; k < n; ++k) {
-    long double sn = sinl(kPiL * (k + 1) / (2.0L * N1));
-    ev[k] = (T)(4.0L * sn * sn);
-  }
-  STCHK(upload(op, ev, &A.eig));
   return FL_OK;
 }
 
@@ -233,7 +247,15 @@ fl_op_s::~fl_op_s() {
 }
 
 // block size for a line-FFT kernel with `tpl` lanes per line
-static int block_for(int tpl) { return std::max(256, tpl); }
+static int block_for(int tpl) { return 256; }
+
+// More lanes per line (fewer elements per lane) when a pass has too few lines
+// to give every CU two workgroups; the plan's tpl is the minimum.
+static int tune_tpl(int tpl0, int L, long nlines) {
+  int tpl = tpl0;
+  while (tpl < 256 && (nlines * tpl) / 256 < 512 && L / tpl >= 8) tpl *= 2;
+  return tpl;
+}
 
 // ---------------------------------------------------------------------------
 // problem descriptors
@@ -270,10 +292,10 @@ template <typename T> static fl_status ensure_ws(fl_op op, long nrhs, bool solve
     if (op->d == 3) STCHK(dalloc(&w.W2, (size_t)nrhs * op->n[0] * op->P[1] * op->H[2] * sizeof(cx<T>)));
     STCHK(dalloc(&w.T1, (size_t)nrhs * N * sizeof(T)));
     w.cap_rhs = nrhs;
-    long np = 4096 + 4 * (rows + 1);
+    long np = std::max<long>(4096, rows + 1);  // partials per site
     if (w.npart < np) {
       if (w.part) hipFree(w.part);
-      STCHK(dalloc((void**)&w.part, np * sizeof(double)));
+      STCHK(dalloc((void**)&w.part, NSITE * np * sizeof(double)));
       w.npart = np;
     }
   }
@@ -295,26 +317,32 @@ template <typename T, int PRO, int EPI> static fl_status apply_seq(fl_op op, con
   hipStream_t s = op->stream;
   const int d = op->d;
   if (d == 1) {
-    const Axis& A = pb.ax[0];
-    int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
+    Prob p1 = pb;
     long pairs = (pb.nrhs + 1) / 2;
-    LAUNCH(k_conv1d<T, PRO, EPI>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * A.P * sizeof(cx<T>), s, pb, it);
+    p1.ax[0].fft.tpl = tune_tpl(pb.ax[0].fft.tpl, pb.ax[0].P, pairs);
+    const Axis& A = p1.ax[0];
+    int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
+    LAUNCH(k_conv1d<T, PRO, EPI>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>), s, p1, it);
     return FL_OK;
   }
-  const Axis& AL = pb.ax[d - 1];
   long rows = rows_of(op, pb.nrhs), pairs = (rows + 1) / 2;
+  Prob pr = pb;  // row passes: lanes per line tuned to the number of row pairs
+  pr.ax[d - 1].fft.tpl = tune_tpl(pb.ax[d - 1].fft.tpl, pb.ax[d - 1].P, pairs);
+  const Axis& AL = pr.ax[d - 1];
   {
     int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
-    LAUNCH(k_rowfwd<T, PRO>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * AL.P * sizeof(cx<T>), s, pb, it);
+    LAUNCH(k_rowfwd<T, PRO>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pr, it);
   }
   auto col = [&](ColGeom cg, int mode) -> fl_status {
-    const Axis& A = pb.ax[cg.axis];
+    Prob pc = pb;
+    Axis& A = pc.ax[cg.axis];
+    A.fft.tpl = tune_tpl(A.fft.tpl, A.P, cg.gs * cg.ngroup);
     int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
     long grid = cg.ngroup * ((cg.gs + G - 1) / G);
-    size_t sm = (size_t)G * A.P * sizeof(cx<T>);
-    if (mode == COL_FWD) LAUNCH(k_colpass<T, COL_FWD>, dim3(grid), dim3(nt), sm, s, pb, cg, it, chk);
-    if (mode == COL_CONV) LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), sm, s, pb, cg, it, chk);
-    if (mode == COL_INV) LAUNCH(k_colpass<T, COL_INV>, dim3(grid), dim3(nt), sm, s, pb, cg, it, chk);
+    size_t sm = (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>);
+    if (mode == COL_FWD) LAUNCH(k_colpass<T, COL_FWD>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+    if (mode == COL_CONV) LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+    if (mode == COL_INV) LAUNCH(k_colpass<T, COL_INV>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
     return FL_OK;
   };
   const long nr = pb.nrhs;
@@ -333,7 +361,7 @@ template <typename T, int PRO, int EPI> static fl_status apply_seq(fl_op op, con
   }
   {
     int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
-    LAUNCH(k_rowinv<T, EPI>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * AL.P * sizeof(cx<T>), s, pb, it, chk);
+    LAUNCH(k_rowinv<T, EPI>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pr, it, chk);
   }
   return FL_OK;
 }
@@ -344,11 +372,13 @@ template <typename T, int PRO, int EPI> static fl_status apply_seq(fl_op op, con
 template <typename T, int DPRO, int DEPI> static fl_status precond_seq(fl_op op, Prob pb, Iter it, int chk) {
   hipStream_t s = op->stream;
   const int d = op->d;
-  const Axis& AL = pb.ax[d - 1];
   long rows = rows_of(op, pb.nrhs);
+  const long rlines = pb.ax[d - 1].dst_direct ? (rows + 1) / 2 : rows;  // FFT lines
+  pb.ax[d - 1].dst.tpl = tune_tpl(pb.ax[d - 1].dst.tpl, pb.ax[d - 1].dst.L, rlines);
+  const Axis& AL = pb.ax[d - 1];
   int nt = block_for(AL.dst.tpl), G = nt / AL.dst.tpl;
-  size_t sm = (size_t)G * AL.dst.L * sizeof(cx<T>);
-  dim3 gr((rows + G - 1) / G);
+  size_t sm = (size_t)G * Line<T>::stride(AL.dst.L) * sizeof(cx<T>) * (AL.dst_direct ? 2 : 1);
+  dim3 gr((rlines + G - 1) / G);
   if (d == 1) {
     LAUNCH(k_dst_rows<T, DPRO, DEPI>, gr, dim3(nt), sm, s, pb, it, chk);
     return FL_OK;
@@ -357,14 +387,17 @@ template <typename T, int DPRO, int DEPI> static fl_status precond_seq(fl_op op,
   p1.out = pb.T1;
   LAUNCH(k_dst_rows<T, DPRO, DEPI_STORE>, gr, dim3(nt), sm, s, p1, it, chk);
   auto cols = [&](DGeom g, bool scale) -> fl_status {
-    const Axis& A = pb.ax[g.axis];
-    int ntc = block_for(A.dst.tpl), Gc = ntc / A.dst.tpl;
+    Prob pc = pb;
+    Axis& A = pc.ax[g.axis];
+    const int per = A.dst_direct ? 2 : 1;  // real lines per FFT line
+    A.dst.tpl = tune_tpl(A.dst.tpl, A.dst.L, g.gs * g.ngroup / per);
+    int ntc = block_for(A.dst.tpl), Gf = ntc / A.dst.tpl, Gc = Gf * per;
     long grid = g.ngroup * ((g.gs + Gc - 1) / Gc);
-    size_t smc = (size_t)Gc * A.dst.L * sizeof(cx<T>);
+    size_t smc = (size_t)Gf * Line<T>::stride(A.dst.L) * sizeof(cx<T>) * per;
     if (scale)
-      LAUNCH(k_dst_cols<T, true>, dim3(grid), dim3(ntc), smc, s, pb, g, chk);
+      LAUNCH(k_dst_cols<T, true>, dim3(grid), dim3(ntc), smc, s, pc, g, chk);
     else
-      LAUNCH(k_dst_cols<T, false>, dim3(grid), dim3(ntc), smc, s, pb, g, chk);
+      LAUNCH(k_dst_cols<T, false>, dim3(grid), dim3(ntc), smc, s, pc, g, chk);
     return FL_OK;
   };
   const long nr = pb.nrhs;
@@ -400,7 +433,7 @@ static fl_status build_symbol(fl_op op) {
     const FFTPlan& pl = op->ax[0][a].fft;
     int nt = block_for(pl.tpl), G = nt / pl.tpl;
     long pairs = (nl + 1) / 2;
-    LAUNCH(k_dct1_axis, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * op->P[a] * sizeof(cx<double>), s,
+    LAUNCH(k_dct1_axis, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<double>::stride(op->P[a]) * sizeof(cx<double>), s,
            (double*)op->lam[0], op->H[a], op->P[a], inner, nl, pl);
   }
   LAUNCH(k_cast<float, double>, dim3((op->NH + 255) / 256), dim3(256), 0, s, (const double*)op->lam[0],
@@ -487,6 +520,7 @@ template <typename T> static Prob solver_prob(fl_op op, const uint8_t* mask, dou
   pb.q = w.q;
   pb.sc = w.sc;
   pb.part = w.part;
+  pb.pstride = w.npart;
   return pb;
 }
 
@@ -525,7 +559,7 @@ template <typename T> static fl_status krylov(fl_op op, const Prob& pb, int pc, 
   } else {
     // rz[0] = r.r
     long nb = std::min<long>(1024, (op->N + 255) / 256);
-    LAUNCH(k_dot<T>, dim3(nb), dim3(256), 0, s, pb, (const void*)pb.r, (const void*)pb.r, (int)DOT_RZ0, op->N);
+    LAUNCH(k_dot<T>, dim3(nb), dim3(256), 0, s, pb, (const void*)pb.r, (const void*)pb.r, (int)S_RZ0, op->N);
   }
   if (poll <= 0) poll = 8;
   if (poll & 1) ++poll;
@@ -562,7 +596,8 @@ template <typename T> static fl_status krylov(fl_op op, const Prob& pb, int pc, 
   for (;;) {
     STCHK(read_scalars(op, pb.sc));
     if (op->hsc->done) break;
-    if (op->hsc->iters >= maxit + 2 * poll) return fail(FL_E_HIP, "iteration bookkeeping lost");
+    if (std::max(op->hsc->itc[0], op->hsc->itc[1]) >= maxit + 2 * poll)
+      return fail(FL_E_HIP, "iteration bookkeeping lost");
     if (use_graph) {
       HIPCHK(hipGraphLaunch(w.gexec, s));
       k += poll;
@@ -571,6 +606,7 @@ template <typename T> static fl_status krylov(fl_op op, const Prob& pb, int pc, 
     }
   }
   *out = *op->hsc;
+  out->itc[0] = std::max(op->hsc->itc[0], op->hsc->itc[1]);  // iterations done
   return FL_OK;
 }
 
@@ -585,6 +621,7 @@ static fl_status true_residual(fl_op op, const uint8_t* mask, double s0, double 
   pb.aux = b;
   pb.out = out;
   STCHK((apply_seq<double, PRO_PLAIN, EPI_RESID>(op, pb, Iter{0, 0}, 0)));
+  LAUNCH(k_finalize, dim3(1), dim3(256), 0, op->stream, pb, (int)S_DOT, (int)FIN_RR);
   STCHK(read_scalars(op, w.sc));
   *rr = op->hsc->rr;
   return FL_OK;
@@ -607,7 +644,8 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
   memset(&inf, 0, sizeof(inf));
   // ff
   LAUNCH(k_dot<double>, dim3(std::min<long>(1024, nblocks_vec(N))), dim3(256), 0, s, pb, (const void*)w.f,
-         (const void*)w.f, (int)DOT_FF, N);
+         (const void*)w.f, (int)S_DOT, N);
+  LAUNCH(k_finalize, dim3(1), dim3(256), 0, s, pb, (int)S_DOT, (int)FIN_FF);
   if (!use_x0) LAUNCH(k_fill<double>, dim3(nblocks_vec(N)), dim3(256), 0, s, (double*)w.x, 0.0, N);
   STCHK(read_scalars(op, w.sc));
   const double ff = op->hsc->ff;
@@ -624,7 +662,7 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
     }
     Scalars res;
     STCHK(krylov<double>(op, pb, pc, tol, maxit, use_x0, graph, poll, &res));
-    inf.iters = res.iters;
+    inf.iters = res.itc[0];
     inf.rel_res_recur = ff > 0 ? std::sqrt(res.rr / ff) : 0.0;
     inf.status = res.done == 1 ? FL_OK : res.done == 2 ? FL_E_NOCONV : FL_E_BREAKDOWN;
   } else {
@@ -654,10 +692,11 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
              1.0 / nr, 0.0, N);
       LAUNCH(k_fill<float>, dim3(nblocks_vec(N)), dim3(256), 0, s, (float*)w32.x, 0.0f, N);
       LAUNCH(k_dot<float>, dim3(std::min<long>(1024, nblocks_vec(N))), dim3(256), 0, s, p32,
-             (const void*)w32.r, (const void*)w32.r, (int)DOT_FF, N);
+             (const void*)w32.r, (const void*)w32.r, (int)S_DOT, N);
+      LAUNCH(k_finalize, dim3(1), dim3(256), 0, s, p32, (int)S_DOT, (int)FIN_FF);
       Scalars res;
       STCHK(krylov<float>(op, p32, pc, itol, inner_cap, 0, graph, poll, &res));
-      inf.iters += res.iters;
+      inf.iters += res.itc[0];
       inf.rel_res_recur = res.ff > 0 ? std::sqrt(res.rr / res.ff) : 0.0;
       if (res.done == 3) {
         inf.status = FL_E_BREAKDOWN;
@@ -693,6 +732,7 @@ static fl_status apply_t(fl_op op, const void* u, void* Mu, long batch, const ui
   pb.mask = mask;
   pb.sc = w.sc;
   pb.part = w.part;
+  pb.pstride = w.npart;
   return apply_seq<T, PRO_PLAIN, EPI_PLAIN>(op, pb, Iter{0, 0}, 0);
 }
 
@@ -709,6 +749,7 @@ static fl_status precond_t(fl_op op, const void* r, void* z, long batch, const u
   pb.mask = mask;
   pb.sc = w.sc;
   pb.part = w.part;
+  pb.pstride = w.npart;
   return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pb, Iter{0, 0}, 0);
 }
 
@@ -737,13 +778,25 @@ template <typename T> static fl_status profile_t(fl_op op, int pass, int reps, d
   const Axis& AL = pb.ax[d - 1];
   long rows = rows_of(op, 1), pairs = (rows + 1) / 2;
   Iter it = {0, 0};
+  // same lane tuning as the solver launches
+  if (pass == 0 || pass == 2) pb.ax[d - 1].fft.tpl = tune_tpl(pb.ax[d - 1].fft.tpl, pb.ax[d - 1].P, pairs);
+  const long rlines = pb.ax[d - 1].dst_direct ? (rows + 1) / 2 : rows;
+  if (pass == 3 || pass == 5) pb.ax[d - 1].dst.tpl = tune_tpl(pb.ax[d - 1].dst.tpl, pb.ax[d - 1].dst.L, rlines);
+  if (pass == 1) {
+    long nl = d == 2 ? (long)op->H[1] : (long)op->P[1] * op->H[2];
+    pb.ax[0].fft.tpl = tune_tpl(pb.ax[0].fft.tpl, pb.ax[0].P, nl);
+  }
+  if (pass == 4) {
+    long nl = d == 2 ? (long)op->n[1] : (long)op->n[1] * op->n[2];
+    pb.ax[0].dst.tpl = tune_tpl(pb.ax[0].dst.tpl, pb.ax[0].dst.L, pb.ax[0].dst_direct ? nl / 2 : nl);
+  }
   auto one = [&]() -> fl_status {
     if (pass == 6) return apply_seq<T, PRO_PLAIN, EPI_PLAIN>(op, pb, it, 0);
     if (pass == 7) return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pb, it, 0);
     if (d == 1) return fail(FL_E_UNSUPPORTED, "single passes are defined for d >= 2");
     if (pass == 0) {
       int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
-      LAUNCH(k_rowfwd<T, PRO_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * AL.P * sizeof(cx<T>), s, pb, it);
+      LAUNCH(k_rowfwd<T, PRO_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pb, it);
     } else if (pass == 1) {
       const Axis& A = pb.ax[0];
       int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
@@ -756,22 +809,22 @@ template <typename T> static fl_status profile_t(fl_op op, int pass, int reps, d
         cg = {0, (int)n0, (int)n0, P1 * H2, 1, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
       }
       long grid = cg.ngroup * ((cg.gs + G - 1) / G);
-      LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), (size_t)G * A.P * sizeof(cx<T>), s, pb, cg, it, 0);
+      LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>), s, pb, cg, it, 0);
     } else if (pass == 2) {
       int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
-      LAUNCH(k_rowinv<T, EPI_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * AL.P * sizeof(cx<T>), s, pb, it, 0);
+      LAUNCH(k_rowinv<T, EPI_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pb, it, 0);
     } else if (pass == 3 || pass == 5) {
       int nt = block_for(AL.dst.tpl), G = nt / AL.dst.tpl;
       Prob p1 = pb;
       if (pass == 3) p1.out = w.T1; else p1.in = w.T1;
-      size_t sm = (size_t)G * AL.dst.L * sizeof(cx<T>);
+      size_t sm = (size_t)G * Line<T>::stride(AL.dst.L) * sizeof(cx<T>) * (AL.dst_direct ? 2 : 1);
       if (pass == 3)
-        LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI_STORE>, dim3((rows + G - 1) / G), dim3(nt), sm, s, p1, it, 0);
+        LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI_STORE>, dim3((rlines + G - 1) / G), dim3(nt), sm, s, p1, it, 0);
       else
-        LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI_FINAL>, dim3((rows + G - 1) / G), dim3(nt), sm, s, p1, it, 0);
+        LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI_FINAL>, dim3((rlines + G - 1) / G), dim3(nt), sm, s, p1, it, 0);
     } else if (pass == 4) {
       const Axis& A = pb.ax[0];
-      int nt = block_for(A.dst.tpl), G = nt / A.dst.tpl;
+      int nt = block_for(A.dst.tpl), Gf = nt / A.dst.tpl, G = Gf * (A.dst_direct ? 2 : 1);
       DGeom g;
       if (d == 2) g = DGeom{0, (long)op->n[1], 1, (long)op->n[1], (long)op->n[0] * op->n[1]};
       else {
@@ -779,7 +832,8 @@ template <typename T> static fl_status profile_t(fl_op op, int pass, int reps, d
         g = DGeom{0, n12, 1, n12, (long)op->n[0] * n12};
       }
       long grid = g.ngroup * ((g.gs + G - 1) / G);
-      LAUNCH(k_dst_cols<T, true>, dim3(grid), dim3(nt), (size_t)G * A.dst.L * sizeof(cx<T>), s, pb, g, 0);
+      LAUNCH(k_dst_cols<T, true>, dim3(grid), dim3(nt), (size_t)Gf * Line<T>::stride(A.dst.L) * sizeof(cx<T>) * (A.dst_direct ? 2 : 1),
+             s, pb, g, 0);
     } else {
       return fail(FL_E_INVALID, "pass must be 0..7");
     }

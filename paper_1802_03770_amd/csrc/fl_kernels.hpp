@@ -13,14 +13,12 @@
 namespace fl {
 
 struct Iter {
-  int parity;  // selects rz slots of the Krylov recurrence
-  int first;   // first iteration: p = z
+  int parity;  // iteration parity: selects the r.z slots and the counter slot
+  int first;   // first iteration: p = z, no stop test
 };
 
 // ---------------------------------------------------------------------------
-// reductions: wave64 shuffle tree, then LDS across waves, then a deterministic
-// last-block pass over per-block partials (agent-scope fences make the
-// partials of blocks on other XCDs visible).
+// reductions (wave64 shuffle tree, then LDS across waves)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -28,50 +26,52 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ double block_sum(double v) {
+// Sum over the block; the result is returned to every thread.
+__device__ __forceinline__ double block_sum_all(double v) {
   __shared__ double red[16];
+  __shared__ double tot;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   v = wave_sum(v);
   __syncthreads();
   if (lane == 0) red[w] = v;
   __syncthreads();
-  double s = 0.0;
   if (threadIdx.x < 64) {
-    s = threadIdx.x < nw ? red[threadIdx.x] : 0.0;
+    double s = threadIdx.x < nw ? red[threadIdx.x] : 0.0;
     s = wave_sum(s);
-  }
-  return s;  // valid in thread 0
-}
-
-// Returns true in the one block that finished last; that block's thread 0 gets
-// the grand total in *total (sum of partials in index order, tree-reduced).
-__device__ bool grid_sum(double blockval, double* part, unsigned int* ctr, int nblk, int blk,
-                         double* total) {
-  __shared__ int amlast;
-  double s = block_sum(blockval);
-  if (threadIdx.x == 0) {
-    part[blk] = s;
-    __threadfence();
-    unsigned int t = atomicAdd(ctr, 1u);
-    amlast = (t == (unsigned)(nblk - 1));
+    if (threadIdx.x == 0) tot = s;
   }
   __syncthreads();
-  if (!amlast) return false;
-  __threadfence();
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += blockDim.x)
-    v += __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  v = block_sum(v);
-  if (threadIdx.x == 0) {
-    *total = v;
-    *ctr = 0u;
-  }
-  return true;
+  return tot;
 }
 
-template <typename T> __device__ __forceinline__ T ldg(const void* p, long i) { return ((const T*)p)[i]; }
+// Producer side: block partial of site `site`; block 0 records the count.
+__device__ __forceinline__ void put_partial(const Prob& pb, int site, double v, int nblk, int blk) {
+  double s = block_sum_all(v);
+  if (threadIdx.x == 0) {
+    pb.part[site * pb.pstride + blk] = s;
+    if (blk == 0) pb.sc->cnt[site] = nblk;
+  }
+}
+
+// Consumer side: the grand total of a site (same fixed order in every block).
+__device__ __forceinline__ double get_total(const Prob& pb, int site) {
+  const int n = pb.sc->cnt[site];
+  const double* p = pb.part + site * pb.pstride;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+  return block_sum_all(v);
+}
 
 __device__ __forceinline__ int fold(int k, int P) { return k <= P / 2 ? k : P - k; }
+
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).  Map
+// block b to tile t so that the blocks one XCD runs concurrently take adjacent
+// tiles (strided column passes then share 128-byte lines inside one L2).
+__device__ __forceinline__ long xcd_tile(long b, long nb) {
+  if (gridDim.y != 1 || nb < 16) return b;
+  const long q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
 
 // Rows of the real array: every index except the last axis, rhs outermost.
 __device__ __forceinline__ long nrows_of(const Prob& pb) {
@@ -140,7 +140,7 @@ __global__ void k_constants(int d, double alpha, double h, double c, double* out
     double q = PI * r2;
     z += pow(q, -sig) * upper_gamma_cf(sig, q) + pow(q, 0.5 * alpha) * upper_gamma_cf(-0.5 * alpha, q);
   }
-  z = block_sum(z);
+  z = block_sum_all(z);
   // ball sum for a2
   const int Rc = (int)ceil(c), Wc = 2 * Rc + 1;
   int totc = 1;
@@ -160,7 +160,7 @@ __global__ void k_constants(int d, double alpha, double h, double c, double* out
     if (r >= c) continue;
     a2 += window_poly(r / c) * j1 * j1 * pow(r2, -0.5 * s);
   }
-  a2 = block_sum(a2);
+  a2 = block_sum_all(a2);
   if (threadIdx.x == 0) {
     double Z = (z + (2.0 / alpha) - 1.0 / sig) * pow(PI, sig) / tgamma(sig);
     double C = alpha * pow(2.0, alpha - 1.0) * tgamma(0.5 * (d + alpha)) /
@@ -208,15 +208,15 @@ __global__ void k_weights(int d, double alpha, int n0, int n1, int n2, int H0, i
 // of the folded array, in place.  Two lines are packed as x + i y, extended
 // evenly to length P and transformed; x' = Re, y' = Im.  Lines along axis a:
 // index = o * (H_a * inner) + m * inner + c, c in [0, inner).
-__global__ void k_dct1_axis(double* wf, int H, int P, long inner, long nlines, FFTPlan pl) {
+__global__ __launch_bounds__(256) void k_dct1_axis(double* wf, int H, int P, long inner, long nlines, FFTPlan pl) {
   extern __shared__ __align__(16) char smem[];
   const int tpl = pl.tpl, G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
-  cx<double>* buf = (cx<double>*)smem + (long)g * P;
+  Line<double> buf = line_at<double>(smem, g, P);
   long pair = (long)blockIdx.x * G + g;
   long la = 2 * pair, lb = la + 1;
   bool va = la < nlines, vb = lb < nlines;
-  auto base = [&](long l) { return (l / inner) * (long)H * inner + (l % inner); };
-  long ba = va ? base(la) : 0, bb = vb ? base(lb) : 0;
+  long ba = va ? (la / inner) * (long)H * inner + (la % inner) : 0;
+  long bb = vb ? (lb / inner) * (long)H * inner + (lb % inner) : 0;
   for (int i = lane; i < P; i += tpl) {
     int m = fold(i, P);
     double xa = va ? wf[ba + (long)m * inner] : 0.0;
@@ -238,18 +238,40 @@ __global__ void k_cast(const TI* in, TO* out, long n, double scale) {
 }
 
 // ---------------------------------------------------------------------------
+// Krylov bookkeeping shared by the first kernel of every iteration
+// ---------------------------------------------------------------------------
+// Stop test of iteration k (k >= 1) on the r.r left by iteration k-1's update,
+// and beta = rz_k / rz_{k-1}.  Returns true when the solve is over; block 0
+// records the status.  Every block takes the same decision (same sums).
+__device__ __forceinline__ bool iter_head(const Prob& pb, const Iter& it, int blk, double* beta) {
+  *beta = 0.0;
+  if (it.first) return false;
+  Scalars* sc = pb.sc;
+  const double rr = get_total(pb, S_RR);
+  const int itn = sc->itc[it.parity ^ 1] + 1;  // updates completed so far
+  int st = 0;
+  if (!isfinite(rr)) st = 3;
+  else if (rr <= sc->thr) st = 1;
+  else if (itn >= sc->maxit) st = 2;
+  if (blk == 0 && threadIdx.x == 0) {
+    sc->itc[it.parity] = itn;
+    sc->rr = rr;
+    if (st) sc->done = st;
+  }
+  if (st) return true;
+  const double rzn = get_total(pb, S_RZ0 + it.parity), rzo = get_total(pb, S_RZ0 + (it.parity ^ 1));
+  *beta = rzn / rzo;
+  return false;
+}
+
+// ---------------------------------------------------------------------------
 // Operator application: forward row pass (last axis, real -> half spectrum)
 // ---------------------------------------------------------------------------
 enum { PRO_PLAIN = 0, PRO_PUPD = 1 };
 enum { EPI_PLAIN = 0, EPI_RESID = 1, EPI_PQ = 2 };
 
-template <typename T>
-__device__ __forceinline__ T maskval(const Prob& pb, long per_idx) {
-  return pb.mask ? (T)pb.mask[per_idx] : (T)1;
-}
-
 // Prologue value of the operator input at element e (row-major over the
-// stacked arrays).  PUPD: p <- z + beta p (beta = rz_k / rz_{k-1}), stored.
+// stacked arrays).  PUPD: p <- z + beta p, stored.
 template <typename T, int PRO>
 __device__ __forceinline__ T load_input(const Prob& pb, long e, long nper, double beta, bool first) {
   if (PRO == PRO_PUPD) {
@@ -265,18 +287,20 @@ __device__ __forceinline__ T load_input(const Prob& pb, long e, long nper, doubl
 }
 
 template <typename T, int PRO>
-__device__ void rowfwd_body(const Prob& pb, const Iter& it, int blk) {
-  if (PRO == PRO_PUPD && pb.sc->done) return;
+__device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int blk) {
+  double beta = 0.0;
+  if (PRO == PRO_PUPD) {
+    if (pb.sc->done) return;
+    if (iter_head(pb, it, blk, &beta)) return;
+  }
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[pb.d - 1];
   const int n = A.n, P = A.P, H = A.H, tpl = A.fft.tpl;
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
-  cx<T>* buf = (cx<T>*)smem + (long)g * P;
+  Line<T> buf = line_at<T>(smem, g, P);
   const long rows = nrows_of(pb), nper = nper_of(pb);
   const long ra = 2 * ((long)blk * G + g), rb = ra + 1;
   const bool va = ra < rows, vb = rb < rows;
-  double beta = 0.0;
-  if (PRO == PRO_PUPD && !it.first) beta = pb.sc->rz[it.parity] / pb.sc->rz[it.parity ^ 1];
   for (int i = lane; i < P; i += tpl) {
     T xa = 0, xb = 0;
     if (i < n) {
@@ -312,8 +336,10 @@ struct ColGeom {
 enum { COL_FWD = 0, COL_CONV = 1, COL_INV = 2 };
 
 template <typename T, int MODE>
-__device__ void colpass_body(const Prob& pb, const ColGeom& cg, const Iter& it, bool check_done, int blk) {
+__device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, const Iter& it, bool check_done,
+                                             int blk0, int nblk) {
   if (check_done && pb.sc->done) return;
+  const long blk = xcd_tile(blk0, nblk);
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[cg.axis];
   const int L = A.P, tpl = A.fft.tpl;
@@ -321,7 +347,6 @@ __device__ void colpass_body(const Prob& pb, const ColGeom& cg, const Iter& it, 
   const long tiles = (cg.gs + G - 1) / G;
   const long grp = blk / tiles, c0 = (blk % tiles) * G;
   if (grp >= cg.ngroup) return;  // uniform across the block
-  cx<T>* lds = (cx<T>*)smem;
   const cx<T>* src = (const cx<T>*)(cg.src == 1 ? pb.W1 : pb.W2) + grp * cg.gin + c0;
   cx<T>* dst = (cx<T>*)(cg.dst == 1 ? pb.W1 : pb.W2) + grp * cg.gout + c0;
   const int gv = (int)min((long)G, cg.gs - c0);  // valid lines in this tile
@@ -330,10 +355,10 @@ __device__ void colpass_body(const Prob& pb, const ColGeom& cg, const Iter& it, 
     int j = e % G, i = e / G;
     cx<T> v = {0, 0};
     if (i < cg.nin && j < gv) v = src[(long)i * cg.ein + j];
-    lds[(long)j * L + i] = v;
+    line_at<T>(smem, j, L)[i] = v;
   }
   __syncthreads();
-  cx<T>* buf = lds + (long)g * L;
+  Line<T> buf = line_at<T>(smem, g, L);
   if (MODE == COL_INV)
     fft_line<T, true>(buf, A.fft, lane);
   else
@@ -363,22 +388,23 @@ __device__ void colpass_body(const Prob& pb, const ColGeom& cg, const Iter& it, 
     __syncthreads();
     fft_line<T, true>(buf, A.fft, lane);
   }
-  __syncthreads();
   for (long e = threadIdx.x; e < (long)G * cg.nout; e += blockDim.x) {
     int j = e % G, i = e / G;
-    if (j < gv) dst[(long)i * cg.eout + j] = lds[(long)j * L + i];
+    if (j < gv) dst[(long)i * cg.eout + j] = line_at<T>(smem, j, L)[i];
   }
 }
 
 // Inverse row pass: half spectrum -> real rows, crop to n, epilogue.
+//  EPI_PLAIN: out = y;  EPI_RESID: out = aux - y, |out|^2 partials (site S_DOT);
+//  EPI_PQ: q = y, p.q partials (site S_PQ).
 template <typename T, int EPI>
-__device__ void rowinv_body(const Prob& pb, const Iter& it, bool check_done, int nblk, int blk) {
+__device__ __forceinline__ void rowinv_body(const Prob& pb, const Iter& it, bool check_done, int nblk, int blk) {
   if (check_done && pb.sc->done) return;
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[pb.d - 1];
   const int n = A.n, P = A.P, H = A.H, tpl = A.fft.tpl;
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
-  cx<T>* buf = (cx<T>*)smem + (long)g * P;
+  Line<T> buf = line_at<T>(smem, g, P);
   const long rows = nrows_of(pb), nper = nper_of(pb);
   const long ra = 2 * ((long)blk * G + g), rb = ra + 1;
   const bool va = ra < rows, vb = rb < rows;
@@ -415,33 +441,27 @@ __device__ void rowinv_body(const Prob& pb, const Iter& it, bool check_done, int
       }
     }
   }
-  if (EPI == EPI_RESID) {
-    double tot;
-    if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_RR], nblk, blk, &tot) && threadIdx.x == 0) pb.sc->rr = tot;
-  } else if (EPI == EPI_PQ) {
-    double tot;
-    if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_PQ], nblk, blk, &tot) && threadIdx.x == 0) {
-      pb.sc->pq = tot;
-      if (!(tot > 0.0) || !isfinite(tot)) pb.sc->done = 3;  // breakdown
-    }
-  }
+  if (EPI == EPI_RESID) put_partial(pb, S_DOT, acc, nblk, blk);
+  if (EPI == EPI_PQ) put_partial(pb, S_PQ, acc, nblk, blk);
 }
 
 // 1D: whole convolution of two packed lines in one pass (real symbol keeps
 // x + i y separable: conv(x) = Re, conv(y) = Im).
 template <typename T, int PRO, int EPI>
-__device__ void conv1d_body(const Prob& pb, const Iter& it, int nblk, int blk) {
-  if ((PRO == PRO_PUPD || EPI == EPI_PQ) && pb.sc->done) return;
+__device__ __forceinline__ void conv1d_body(const Prob& pb, const Iter& it, int nblk, int blk) {
+  double beta = 0.0;
+  if (PRO == PRO_PUPD) {
+    if (pb.sc->done) return;
+    if (iter_head(pb, it, blk, &beta)) return;
+  }
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[0];
   const int n = A.n, P = A.P, tpl = A.fft.tpl;
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
-  cx<T>* buf = (cx<T>*)smem + (long)g * P;
+  Line<T> buf = line_at<T>(smem, g, P);
   const long rows = pb.nrhs, nper = n;
   const long ra = 2 * ((long)blk * G + g), rb = ra + 1;
   const bool va = ra < rows, vb = rb < rows;
-  double beta = 0.0;
-  if (PRO == PRO_PUPD && !it.first) beta = pb.sc->rz[it.parity] / pb.sc->rz[it.parity ^ 1];
   for (int i = lane; i < P; i += tpl) {
     T xa = 0, xb = 0;
     if (i < n) {
@@ -479,24 +499,17 @@ __device__ void conv1d_body(const Prob& pb, const Iter& it, int nblk, int blk) {
       }
     }
   }
-  if (EPI == EPI_RESID) {
-    double tot;
-    if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_RR], nblk, blk, &tot) && threadIdx.x == 0) pb.sc->rr = tot;
-  } else if (EPI == EPI_PQ) {
-    double tot;
-    if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_PQ], nblk, blk, &tot) && threadIdx.x == 0) {
-      pb.sc->pq = tot;
-      if (!(tot > 0.0) || !isfinite(tot)) pb.sc->done = 3;
-    }
-  }
+  if (EPI == EPI_RESID) put_partial(pb, S_DOT, acc, nblk, blk);
+  if (EPI == EPI_PQ) put_partial(pb, S_PQ, acc, nblk, blk);
 }
 
 // ---------------------------------------------------------------------------
-// Sine transforms (type I) by the chirp-z identity, one real line per FFT line.
+// Sine transforms (type I)
 // ---------------------------------------------------------------------------
-// In: LDS line buf holding x_j (real, in .x) for j < n.  Out: buf[k].x = DST(x)_k.
+// Chirp-z form, one real line per FFT line.  In: buf[j].x = x_j (j < n).
+// Out: buf[k].x = sum_j x_j sin(pi (j+1)(k+1)/(n+1)).
 template <typename T>
-__device__ void dst_line(cx<T>* buf, const Axis& A, int lane, int tpl) {
+__device__ __forceinline__ void dst_line(Line<T> buf, const Axis& A, int lane, int tpl) {
   const int n = A.n, Lb = A.dst.L;
   const cx<T>* ch = (const cx<T>*)A.chirp;
   const cx<T>* bh = (const cx<T>*)A.bhat;
@@ -517,92 +530,133 @@ __device__ void dst_line(cx<T>* buf, const Axis& A, int lane, int tpl) {
   __syncthreads();
 }
 
+// Direct form of a packed pair: the line holds the odd extension
+// (0, x_1.., x_n, 0, -x_n.., -x_1) of x_a + i x_b, length M = 2(n+1).  After the
+// FFT, S_a[k] = -Im Z_k / 2 and S_b[k] = Re Z_k / 2 for k = 1..n.
+template <typename T>
+__device__ __forceinline__ void sine_pair_put(Line<T> buf, int M, int k, T a, T b) {
+  buf[k] = {a, b};
+  buf[M - k] = {-a, -b};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> sine_pair_get(Line<T> buf, int k) {
+  cx<T> z = buf[k];
+  return {(T)-0.5 * z.y, (T)0.5 * z.x};
+}
+
 enum { DPRO_PLAIN = 0, DPRO_UPD = 1 };
 enum { DEPI_STORE = 0, DEPI_FINAL = 1, DEPI_Z = 2 };
 
 // Row sine pass along the last axis.  d == 1 performs the whole inverse
 // (transform, divide by the eigenvalue, transform, normalise) in this pass.
-//  DPRO_UPD: x += alpha p, r -= alpha q (alpha = rz/pq), r.r reduced and the
-//            stop test taken by the last block; the new r is transformed.
+//  DPRO_UPD: alpha = rz/pq; x += alpha p, r -= alpha q; r.r partials (S_RR);
+//            the new r is transformed.
 //  DEPI_STORE: out = result (a first pass of a multi-axis transform)
 //  DEPI_FINAL: out = norm * result
-//  DEPI_Z:     z = norm * result, r.z reduced into rz[parity ^ 1].
+//  DEPI_Z:     z = norm * result, r.z partials into slot parity ^ 1.
 template <typename T, int DPRO, int DEPI>
-__device__ void dst_rows_body(const Prob& pb, const Iter& it, bool check_done, int nblk, int blk) {
+__device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bool check_done, int nblk, int blk) {
   if (check_done && pb.sc->done) return;
+  double alpha = 0.0;
+  if (DPRO == DPRO_UPD) {
+    const double pq = get_total(pb, S_PQ);
+    if (!(pq > 0.0) || !isfinite(pq)) {  // breakdown: every block sees the same pq
+      if (blk == 0 && threadIdx.x == 0) {
+        pb.sc->pq = pq;
+        pb.sc->done = 3;
+      }
+      return;
+    }
+    alpha = get_total(pb, S_RZ0 + it.parity) / pq;
+  }
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[pb.d - 1];
-  const int n = A.n, Lb = A.dst.L, tpl = A.dst.tpl;
+  const int n = A.n, Lf = A.dst.L, tpl = A.dst.tpl;
+  const bool direct = A.dst_direct;
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
-  cx<T>* buf = (cx<T>*)smem + (long)g * Lb;
+  // direct: a ping-pong pair of lines per FFT line
+  Line<T> buf = line_at<T>(smem, direct ? 2 * g : g, Lf);
+  Line<T> buf2 = line_at<T>(smem, 2 * g + 1, Lf);
   const long rows = nrows_of(pb), nper = nper_of(pb);
-  const long row = (long)blk * G + g;
-  const bool valid = row < rows;
+  const long ra = ((long)blk * G + g) * (direct ? 2 : 1), rb = ra + 1;
+  const bool va = ra < rows, vb = direct && rb < rows;
   double acc = 0.0;
-  double alpha = 0.0;
-  if (DPRO == DPRO_UPD) alpha = pb.sc->rz[it.parity] / pb.sc->pq;
-  for (int i = lane; i < n; i += tpl) {
-    T v = 0;
-    if (valid) {
-      long e = row * n + i;
-      if (DPRO == DPRO_UPD) {
-        T* x = (T*)pb.x;
-        T* r = (T*)pb.r;
-        x[e] += (T)alpha * ((const T*)pb.p)[e];
-        T rv = r[e] - (T)alpha * ((const T*)pb.q)[e];
-        r[e] = rv;
-        acc += (double)rv * (double)rv;
-        v = rv;
-      } else {
-        v = ((const T*)pb.in)[e];
-        // the domain mask acts on grid functions only: the input of the first
-        // pass (or of the single 1D pass), never on a transformed intermediate
-        if (pb.mask && (DEPI == DEPI_STORE || pb.d == 1)) v *= (T)pb.mask[e % nper];
-      }
+  auto pro = [&](long e) -> T {
+    if (DPRO == DPRO_UPD) {
+      T* x = (T*)pb.x;
+      T* r = (T*)pb.r;
+      x[e] += (T)alpha * ((const T*)pb.p)[e];
+      T rv = r[e] - (T)alpha * ((const T*)pb.q)[e];
+      r[e] = rv;
+      acc += (double)rv * (double)rv;
+      return rv;
+    } else {
+      T v = ((const T*)pb.in)[e];
+      // the domain mask acts on grid functions only: the input of the first
+      // pass (or of the single 1D pass), never on a transformed intermediate
+      if (pb.mask && (DEPI == DEPI_STORE || pb.d == 1)) v *= (T)pb.mask[e % nper];
+      return v;
     }
-    buf[i] = {v, 0};
-  }
-  if (DPRO == DPRO_UPD) {
-    double tot;
-    if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_RR], nblk, blk, &tot) && threadIdx.x == 0) {
-      pb.sc->rr = tot;
-      int itn = pb.sc->iters + 1;
-      pb.sc->iters = itn;
-      if (!isfinite(tot)) pb.sc->done = 3;
-      else if (tot <= pb.sc->thr) pb.sc->done = 1;
-      else if (itn >= pb.sc->maxit) pb.sc->done = 2;
+  };
+  if (direct) {
+    for (int i = lane; i < n; i += tpl) {
+      T xa = va ? pro(ra * n + i) : (T)0;
+      T xb = vb ? pro(rb * n + i) : (T)0;
+      sine_pair_put(buf, Lf, i + 1, xa, xb);
     }
+    if (lane == 0) {
+      buf[0] = {0, 0};
+      buf[n + 1] = {0, 0};
+    }
+  } else {
+    for (int i = lane; i < n; i += tpl) buf[i] = {va ? pro(ra * n + i) : (T)0, (T)0};
   }
+  if (DPRO == DPRO_UPD) put_partial(pb, S_RR, acc, nblk, blk);
   __syncthreads();
-  dst_line<T>(buf, A, lane, tpl);
+  Line<T> res = buf;  // line holding the transform result
+  if (direct) res = fft_line_wide<T, false>(buf, buf2, A.dst, lane); else dst_line<T>(buf, A, lane, tpl);
   if (pb.d == 1) {
     const T* ev = (const T*)A.eig;
-    for (int k = lane; k < n; k += tpl)
-      buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * (double)ev[k]);
-    __syncthreads();
-    dst_line<T>(buf, A, lane, tpl);
+    if (direct) {
+      for (int k = lane + 1; k <= n; k += tpl) {
+        cx<T> sv = sine_pair_get(res, k);
+        T e = (T)(pb.p0 + pb.p1 * pb.pcs * (double)ev[k - 1]);
+        sine_pair_put(res, Lf, k, sv.x / e, sv.y / e);
+      }
+      if (lane == 0) {
+        res[0] = {0, 0};
+        res[n + 1] = {0, 0};
+      }
+      __syncthreads();
+      res = fft_line_wide<T, false>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
+    } else {
+      for (int k = lane; k < n; k += tpl)
+        buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * (double)ev[k]);
+      __syncthreads();
+      dst_line<T>(buf, A, lane, tpl);
+    }
   }
   double norm = 1.0;
   if (pb.d == 1 || DEPI != DEPI_STORE)
     for (int a = 0; a < pb.d; ++a) norm *= 2.0 / (pb.ax[a].n + 1);
   double acc2 = 0.0;
   for (int i = lane; i < n; i += tpl) {
-    if (!valid) break;
-    long e = row * n + i;
-    T v = buf[i].x * (T)norm;
-    if (pb.mask && (DEPI != DEPI_STORE || pb.d == 1)) v *= (T)pb.mask[e % nper];
-    if (DEPI != DEPI_Z) {
-      ((T*)pb.out)[e] = v;
-    } else {
-      ((T*)pb.z)[e] = v;
-      acc2 += (double)((const T*)pb.r)[e] * (double)v;
+    cx<T> sv = direct ? sine_pair_get(res, i + 1) : buf[i];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (!(s ? vb : va)) continue;
+      long e = (s ? rb : ra) * n + i;
+      T v = (s ? sv.y : sv.x) * (T)norm;
+      if (pb.mask && (DEPI != DEPI_STORE || pb.d == 1)) v *= (T)pb.mask[e % nper];
+      if (DEPI != DEPI_Z) {
+        ((T*)pb.out)[e] = v;
+      } else {
+        ((T*)pb.z)[e] = v;
+        acc2 += (double)((const T*)pb.r)[e] * (double)v;
+      }
     }
   }
-  if (DEPI == DEPI_Z) {
-    double tot;
-    if (grid_sum(acc2, pb.part + nblk, &pb.sc->ctr[SITE_RZ], nblk, blk, &tot) && threadIdx.x == 0)
-      pb.sc->rz[it.parity ^ 1] = tot;
-  }
+  if (DEPI == DEPI_Z) put_partial(pb, S_RZ0 + (it.parity ^ 1), acc2, nblk, blk);
 }
 
 // Strided real sine pass on T1 (in place).  SCALE: transform along axis 0,
@@ -612,80 +666,142 @@ struct DGeom {
   long gs, ngroup, estride, gstride;
 };
 
+template <typename T>
+__device__ __forceinline__ double eig_tail(const Prob& pb, long c) {
+  if (pb.d == 2) return (double)((const T*)pb.ax[1].eig)[c];
+  const int n2 = pb.ax[2].n;
+  return (double)((const T*)pb.ax[1].eig)[c / n2] + (double)((const T*)pb.ax[2].eig)[c % n2];
+}
+
 template <typename T, bool SCALE>
-__device__ void dst_cols_body(const Prob& pb, const DGeom& dg, bool check_done, int blk) {
+__device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, bool check_done, int blk0, int nblk) {
   if (check_done && pb.sc->done) return;
+  const long blk = xcd_tile(blk0, nblk);
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[dg.axis];
-  const int n = A.n, Lb = A.dst.L, tpl = A.dst.tpl;
-  const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  const int n = A.n, Lf = A.dst.L, tpl = A.dst.tpl;
+  const bool direct = A.dst_direct;
+  const int GF = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  const int G = direct ? 2 * GF : GF;  // real lines per block
   const long tiles = (dg.gs + G - 1) / G;
   const long grp = blk / tiles, c0 = (blk % tiles) * G;
   if (grp >= dg.ngroup) return;
-  cx<T>* lds = (cx<T>*)smem;
   T* base = (T*)pb.T1 + grp * dg.gstride + c0;
   const int gv = (int)min((long)G, dg.gs - c0);
-  for (long e = threadIdx.x; e < (long)G * n; e += blockDim.x) {
-    int j = e % G, i = e / G;
-    T v = 0;
-    if (j < gv) v = base[(long)i * dg.estride + j];
-    lds[(long)j * Lb + i] = {v, 0};
+  if (direct) {
+    // real line j is component (j & 1) of FFT line j >> 1 (ping-pong lines 2q, 2q+1)
+    for (long e = threadIdx.x; e < (long)G * n; e += blockDim.x) {
+      int j = e % G, i = e / G;
+      T v = 0;
+      if (j < gv) v = base[(long)i * dg.estride + j];
+      Line<T> ln = line_at<T>(smem, 2 * (j >> 1), Lf);
+      T* a = (T*)&ln[i + 1];
+      T* b = (T*)&ln[Lf - 1 - i];
+      a[j & 1] = v;
+      b[j & 1] = -v;
+    }
+    for (int q = threadIdx.x; q < GF; q += blockDim.x) {
+      Line<T> ln = line_at<T>(smem, 2 * q, Lf);
+      ln[0] = {0, 0};
+      ln[n + 1] = {0, 0};
+    }
+  } else {
+    for (long e = threadIdx.x; e < (long)G * n; e += blockDim.x) {
+      int j = e % G, i = e / G;
+      T v = 0;
+      if (j < gv) v = base[(long)i * dg.estride + j];
+      line_at<T>(smem, j, Lf)[i] = {v, 0};
+    }
   }
   __syncthreads();
-  cx<T>* buf = lds + (long)g * Lb;
-  dst_line<T>(buf, A, lane, tpl);
+  Line<T> buf = line_at<T>(smem, direct ? 2 * g : g, Lf);
+  Line<T> buf2 = line_at<T>(smem, 2 * g + 1, Lf);
+  Line<T> res = buf;
+  if (direct) res = fft_line_wide<T, false>(buf, buf2, A.dst, lane); else dst_line<T>(buf, A, lane, tpl);
   if (SCALE) {
-    const long c = c0 + g;
-    double etail = 0.0;
-    if (c < dg.gs) {
-      if (pb.d == 2) {
-        etail = (double)((const T*)pb.ax[1].eig)[c];
-      } else {
-        const int n2 = pb.ax[2].n;
-        etail = (double)((const T*)pb.ax[1].eig)[c / n2] + (double)((const T*)pb.ax[2].eig)[c % n2];
-      }
-    }
     const T* ev = (const T*)A.eig;
-    for (int k = lane; k < n; k += tpl)
-      buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * ((double)ev[k] + etail));
-    __syncthreads();
-    dst_line<T>(buf, A, lane, tpl);
+    if (direct) {
+      const long ca = c0 + 2 * g, cb = ca + 1;
+      const double ta = ca < dg.gs ? eig_tail<T>(pb, ca) : 0.0;
+      const double tb = cb < dg.gs ? eig_tail<T>(pb, cb) : 0.0;
+      for (int k = lane + 1; k <= n; k += tpl) {
+        cx<T> sv = sine_pair_get(res, k);
+        const double ek = (double)ev[k - 1];
+        T ea = (T)(pb.p0 + pb.p1 * pb.pcs * (ek + ta));
+        T eb = (T)(pb.p0 + pb.p1 * pb.pcs * (ek + tb));
+        sine_pair_put(res, Lf, k, sv.x / ea, sv.y / eb);
+      }
+      if (lane == 0) {
+        res[0] = {0, 0};
+        res[n + 1] = {0, 0};
+      }
+      __syncthreads();
+      res = fft_line_wide<T, false>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
+    } else {
+      const long c = c0 + g;
+      const double etail = c < dg.gs ? eig_tail<T>(pb, c) : 0.0;
+      for (int k = lane; k < n; k += tpl)
+        buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * ((double)ev[k] + etail));
+      __syncthreads();
+      dst_line<T>(buf, A, lane, tpl);
+    }
   }
+  // every FFT line of the block ends in the same member of its ping-pong pair
+  const int rsel = direct ? (res.p == buf.p ? 0 : 1) : 0;
+  __syncthreads();
   for (long e = threadIdx.x; e < (long)G * n; e += blockDim.x) {
     int j = e % G, i = e / G;
-    if (j < gv) base[(long)i * dg.estride + j] = lds[(long)j * Lb + i].x;
+    if (j >= gv) continue;
+    T v;
+    if (direct) {
+      cx<T> sv = sine_pair_get(line_at<T>(smem, 2 * (j >> 1) + rsel, Lf), i + 1);
+      v = (j & 1) ? sv.y : sv.x;
+    } else {
+      v = line_at<T>(smem, j, Lf)[i].x;
+    }
+    base[(long)i * dg.estride + j] = v;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Vector kernels
 // ---------------------------------------------------------------------------
-// dot(a, b) (FP64 accumulation) into one of the scalar slots.
-enum { DOT_FF = 0, DOT_RR = 1, DOT_AUX0 = 2, DOT_AUX1 = 3, DOT_RZ0 = 4 };
+// dot(a, b) partials (FP64 accumulation) into `site`.
 template <typename T>
-__device__ void dot_body(const Prob& pb, const void* a, const void* b, int target, long n, int nblk, int blk) {
+__device__ __forceinline__ void dot_body(const Prob& pb, const void* a, const void* b, int site, long n, int nblk,
+                                         int blk) {
   double acc = 0.0;
   for (long i = (long)blk * blockDim.x + threadIdx.x; i < n; i += (long)nblk * blockDim.x)
     acc += (double)((const T*)a)[i] * (double)((const T*)b)[i];
-  double tot;
-  if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_DOT], nblk, blk, &tot) && threadIdx.x == 0) {
-    switch (target) {
-      case DOT_FF: pb.sc->ff = tot; break;
-      case DOT_RR: pb.sc->rr = tot; break;
-      case DOT_AUX0: pb.sc->aux[0] = tot; break;
-      case DOT_AUX1: pb.sc->aux[1] = tot; break;
-      default: pb.sc->rz[0] = tot; break;
-    }
+  put_partial(pb, site, acc, nblk, blk);
+}
+
+// One workgroup: total of `site` into a scalar slot.
+enum { FIN_FF = 0, FIN_RR = 1, FIN_AUX0 = 2, FIN_AUX1 = 3 };
+__device__ __forceinline__ void finalize_body(const Prob& pb, int site, int target) {
+  double t = get_total(pb, site);
+  if (threadIdx.x == 0) {
+    if (target == FIN_FF) pb.sc->ff = t;
+    else if (target == FIN_RR) pb.sc->rr = t;
+    else if (target == FIN_AUX0) pb.sc->aux[0] = t;
+    else pb.sc->aux[1] = t;
   }
 }
 
-
-// Plain CG update (no preconditioner, z aliases r): x += alpha p, r -= alpha q,
-// r.r reduced, stop test, and rz[parity^1] = r.r.
+// Plain CG update (no preconditioner, z aliases r): alpha = r.r / p.q;
+// x += alpha p, r -= alpha q; r.r partials into S_RR and into the r.z slot.
 template <typename T>
-__device__ void update_body(const Prob& pb, const Iter& it, long n, int nblk, int blk) {
+__device__ __forceinline__ void update_body(const Prob& pb, const Iter& it, long n, int nblk, int blk) {
   if (pb.sc->done) return;
-  const double alpha = pb.sc->rz[it.parity] / pb.sc->pq;
+  const double pq = get_total(pb, S_PQ);
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (blk == 0 && threadIdx.x == 0) {
+      pb.sc->pq = pq;
+      pb.sc->done = 3;
+    }
+    return;
+  }
+  const double alpha = get_total(pb, S_RZ0 + it.parity) / pq;
   T* x = (T*)pb.x;
   T* r = (T*)pb.r;
   const T* p = (const T*)pb.p;
@@ -697,28 +813,28 @@ __device__ void update_body(const Prob& pb, const Iter& it, long n, int nblk, in
     r[i] = rv;
     acc += (double)rv * (double)rv;
   }
-  double tot;
-  if (grid_sum(acc, pb.part, &pb.sc->ctr[SITE_RR], nblk, blk, &tot) && threadIdx.x == 0) {
-    pb.sc->rr = tot;
-    pb.sc->rz[it.parity ^ 1] = tot;
-    int itn = pb.sc->iters + 1;
-    pb.sc->iters = itn;
-    if (!isfinite(tot)) pb.sc->done = 3;
-    else if (tot <= pb.sc->thr) pb.sc->done = 1;
-    else if (itn >= pb.sc->maxit) pb.sc->done = 2;
+  double s = block_sum_all(acc);
+  if (threadIdx.x == 0) {
+    pb.part[S_RR * pb.pstride + blk] = s;
+    pb.part[(S_RZ0 + (it.parity ^ 1)) * pb.pstride + blk] = s;
+    if (blk == 0) {
+      pb.sc->cnt[S_RR] = nblk;
+      pb.sc->cnt[S_RZ0 + (it.parity ^ 1)] = nblk;
+    }
   }
 }
 
 // Start of a Krylov solve: thr = tol^2 ff, counters cleared, done when the
 // initial residual already meets the tolerance.  use_rr: the initial residual
 // norm is in rr (warm start); otherwise r = f and rr = ff.
-__device__ void init_body(const Prob& pb, double tol, int maxit, int use_rr) {
+__device__ __forceinline__ void init_body(const Prob& pb, double tol, int maxit, int use_rr) {
   if (threadIdx.x != 0) return;
   Scalars* s = pb.sc;
   if (!use_rr) s->rr = s->ff;
   s->thr = tol * tol * s->ff;
   s->rr0 = s->rr;
-  s->iters = 0;
+  s->itc[0] = 0;
+  s->itc[1] = 0;
   s->maxit = maxit;
   s->done = (s->rr <= s->thr) ? 1 : 0;
   if (!(s->ff > 0.0)) s->done = 1;  // zero right-hand side: x = 0 is exact
@@ -730,13 +846,6 @@ __global__ void k_axpby(const TX* x, TY* y, double a, double b, long n) {
   long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i < n) y[i] = (TY)(a * (double)x[i] + (b == 0.0 ? 0.0 : b * (double)y[i]));
 }
-// y = a * x + b * y with a taken from device scalar *ap times s (refinement scale)
-template <typename TX, typename TY>
-__global__ void k_axpby_dev(const TX* x, TY* y, const double* ap, double s, int sqrt_a, double b, long n) {
-  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  double a = sqrt_a ? sqrt(*ap) * s : (*ap) * s;
-  if (i < n) y[i] = (TY)(a * (double)x[i] + (b == 0.0 ? 0.0 : b * (double)y[i]));
-}
 template <typename T> __global__ void k_fill(T* y, T v, long n) {
   long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i < n) y[i] = v;
@@ -745,7 +854,7 @@ template <typename T> __global__ void k_fill(T* y, T v, long n) {
 // ---------------------------------------------------------------------------
 // kernel wrappers
 // ---------------------------------------------------------------------------
-#define FL_BOUNDS __launch_bounds__(1024)
+#define FL_BOUNDS __launch_bounds__(256)
 
 template <typename T, int PRO> __global__ FL_BOUNDS void k_rowfwd(Prob pb, Iter it) {
   rowfwd_body<T, PRO>(pb, it, blockIdx.x);
@@ -755,12 +864,12 @@ template <typename T, int PRO> __global__ FL_BOUNDS void k_rowfwd_b(const Prob* 
   rowfwd_body<T, PRO>(pbs[blockIdx.y], it, blockIdx.x);
 }
 template <typename T, int MODE> __global__ FL_BOUNDS void k_colpass(Prob pb, ColGeom cg, Iter it, int chk) {
-  colpass_body<T, MODE>(pb, cg, it, chk, blockIdx.x);
+  colpass_body<T, MODE>(pb, cg, it, chk, blockIdx.x, gridDim.x);
 }
 template <typename T, int MODE>
 __global__ FL_BOUNDS void k_colpass_b(const Prob* pbs, const ColGeom* cgs, Iter it, int chk, const int* nb) {
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
-  colpass_body<T, MODE>(pbs[blockIdx.y], cgs[blockIdx.y], it, chk, blockIdx.x);
+  colpass_body<T, MODE>(pbs[blockIdx.y], cgs[blockIdx.y], it, chk, blockIdx.x, nb[blockIdx.y]);
 }
 template <typename T, int EPI> __global__ FL_BOUNDS void k_rowinv(Prob pb, Iter it, int chk) {
   rowinv_body<T, EPI>(pb, it, chk, gridDim.x, blockIdx.x);
@@ -787,20 +896,21 @@ __global__ FL_BOUNDS void k_dst_rows_b(const Prob* pbs, Iter it, int chk, const 
   dst_rows_body<T, DPRO, DEPI>(pbs[blockIdx.y], it, chk, nb[blockIdx.y], blockIdx.x);
 }
 template <typename T, bool SCALE> __global__ FL_BOUNDS void k_dst_cols(Prob pb, DGeom dg, int chk) {
-  dst_cols_body<T, SCALE>(pb, dg, chk, blockIdx.x);
+  dst_cols_body<T, SCALE>(pb, dg, chk, blockIdx.x, gridDim.x);
 }
 template <typename T, bool SCALE>
 __global__ FL_BOUNDS void k_dst_cols_b(const Prob* pbs, const DGeom* dgs, int chk, const int* nb) {
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
-  dst_cols_body<T, SCALE>(pbs[blockIdx.y], dgs[blockIdx.y], chk, blockIdx.x);
+  dst_cols_body<T, SCALE>(pbs[blockIdx.y], dgs[blockIdx.y], chk, blockIdx.x, nb[blockIdx.y]);
 }
-template <typename T> __global__ void k_dot(Prob pb, const void* a, const void* b, int target, long n) {
-  dot_body<T>(pb, a, b, target, n, gridDim.x, blockIdx.x);
+template <typename T> __global__ FL_BOUNDS void k_dot(Prob pb, const void* a, const void* b, int site, long n) {
+  dot_body<T>(pb, a, b, site, n, gridDim.x, blockIdx.x);
 }
-template <typename T> __global__ void k_update(Prob pb, Iter it, long n) {
+__global__ FL_BOUNDS void k_finalize(Prob pb, int site, int target) { finalize_body(pb, site, target); }
+template <typename T> __global__ FL_BOUNDS void k_update(Prob pb, Iter it, long n) {
   update_body<T>(pb, it, n, gridDim.x, blockIdx.x);
 }
-template <typename T> __global__ void k_update_b(const Prob* pbs, Iter it, const long* ns, const int* nb) {
+template <typename T> __global__ FL_BOUNDS void k_update_b(const Prob* pbs, Iter it, const long* ns, const int* nb) {
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
   update_body<T>(pbs[blockIdx.y], it, ns[blockIdx.y], nb[blockIdx.y], blockIdx.x);
 }

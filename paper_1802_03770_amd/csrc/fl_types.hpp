@@ -21,29 +21,33 @@ struct Axis {
   // type-I sine transform of length n by the chirp-z (Bluestein) identity:
   //   sum_{j=1..n} x_j sin(pi j k/(n+1)) = Im( ch_k sum_j (x_j ch_j) conj(ch_{k-j}) ),
   //   ch_m = e^{i pi m^2 / (2(n+1))}, convolution of length Lb >= 2n-1.
-  FFTPlan dst;      // complex FFT of length Lb
+  FFTPlan dst;      // complex FFT of length Lb (chirp-z) or 2(n+1) (direct)
+  int dst_direct;   // 1: two real lines packed as x + i y in an odd extension of
+                    //    length 2(n+1); FFT gives -2i S_x + 2 S_y
+                    // 0: one line per FFT line by the chirp-z identity
   const void* chirp;  // cx<T>[n+1]
   const void* bhat;   // cx<T>[Lb]  = FFT_Lb(conj chirp, circularly placed) / Lb
   const void* eig;    // T[n]       = 4 sin^2(pi k / (2 (n+1))), k = 1..n
 };
 
-// Device-resident scalars of one Krylov solve (always FP64).
+// Device-resident scalars of one Krylov solve (always FP64).  Reductions are
+// finished by their consumer: a producing kernel writes one partial per block
+// into part[site * pstride + block] and its block count into cnt[site]; every
+// block of the consuming kernel sums the partials in the same fixed order.
 struct Scalars {
-  double rz[2];   // r.z of the current / previous iteration (indexed by parity)
-  double pq;      // p.q
-  double rr;      // r.r
+  double pq;      // p.q (reporting)
+  double rr;      // r.r at stop / of the last finalised residual
   double ff;      // f.f
   double thr;     // stop when rr <= thr  (thr = tol^2 ff)
   double rr0;     // r.r at start
-  double aux[3];  // scratch scalars (refinement norms)
+  double aux[3];  // finalised dot products
   int done;       // 0 running, 1 converged, 2 iteration cap, 3 breakdown
-  int iters;
+  int itc[2];     // iteration counter ring (written by parity)
   int maxit;
-  int pad;
-  unsigned int ctr[8];  // last-block-done counters, one per reduction site
+  int cnt[8];     // partial counts per site
 };
 
-enum ScalarSite { SITE_PQ = 0, SITE_RR = 1, SITE_RZ = 2, SITE_DOT = 3, SITE_DOT2 = 4 };
+enum Site { S_PQ = 0, S_RR = 1, S_RZ0 = 2, S_RZ1 = 3, S_DOT = 4, S_AUX = 5, NSITE = 6 };
 
 struct Prob {
   int d;          // 1, 2, 3
@@ -68,9 +72,8 @@ struct Prob {
   void* p;
   void* q;
   Scalars* sc;
-  double* part;     // partial sums, >= max blocks of any reduction launch
-  int parity;       // iteration parity (selects rz slots)
-  int first;        // 1 on the first Krylov iteration (p = z)
+  double* part;     // partial sums: NSITE sites of pstride entries
+  long pstride;     // >= blocks of any reduction launch
 };
 
 }  // namespace fl

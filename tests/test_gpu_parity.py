@@ -111,7 +111,12 @@ def test_apply_mask_shift_batch():
         assert _rel(got[b], want) <= 1e-12
 
 
-@pytest.mark.parametrize("n", [(37,), (48, 40), (64, 64), (9, 10, 12)])
+# 2(n+1) with a prime factor > 43 (n = 46, 52) takes the chirp-z sine path,
+# the other sizes the direct odd-extension path; mixed shapes use both.
+PRECOND_CASES = [(37,), (46,), (48, 40), (46, 40), (40, 52), (64, 64), (9, 10, 12), (6, 7, 46)]
+
+
+@pytest.mark.parametrize("n", PRECOND_CASES)
 @pytest.mark.parametrize("shift", [(0.0, 1.0), (1.0, 0.01)])
 def test_precond(n, shift):
     _say("precond", n, shift)
@@ -126,7 +131,7 @@ def test_precond(n, shift):
     assert _rel(got32, want) <= 2e-5
 
 
-@pytest.mark.parametrize("n", [(37,), (24, 30), (9, 10, 12)])
+@pytest.mark.parametrize("n", [(37,), (46,), (24, 30), (46, 29), (9, 10, 12)])
 def test_precond_masked(n):
     _say("precond masked", n)
     fl = _fl()
