@@ -1,0 +1,103 @@
+// Launch sequence of the operator application (one precision per build of
+// this file: FL_T = float or double).
+#include "fl_internal.hpp"
+
+// ---------------------------------------------------------------------------
+// operator application (M or shift0 I + shift1 M)
+// ---------------------------------------------------------------------------
+template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob& pb, Iter it, int chk) {
+  hipStream_t s = op->stream;
+  const int d = op->d;
+  if (d == 1) {
+    Prob p1 = pb;
+    long pairs = (pb.nrhs + 1) / 2;
+    p1.ax[0].fft.tpl = tune_tpl(pb.ax[0].fft.tpl, pb.ax[0].P, pairs);
+    const Axis& A = p1.ax[0];
+    int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
+    LAUNCH(k_conv1d<T, PRO, EPI>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>), s, p1, it);
+    return FL_OK;
+  }
+  long rows = rows_of(op, pb.nrhs), pairs = (rows + 1) / 2;
+  Prob pr = pb;  // row passes: lanes per line tuned to the number of row pairs
+  pr.ax[d - 1].fft.tpl = tune_tpl(pb.ax[d - 1].fft.tpl, pb.ax[d - 1].P, pairs);
+  const Axis& AL = pr.ax[d - 1];
+  {
+    int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
+    LAUNCH(k_rowfwd<T, PRO>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pr, it);
+  }
+  auto col = [&](ColGeom cg, int mode) -> fl_status {
+    Prob pc = pb;
+    Axis& A = pc.ax[cg.axis];
+    A.fft.tpl = tune_tpl(A.fft.tpl, A.P, cg.gs * cg.ngroup);
+    int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
+    long grid = cg.ngroup * ((cg.gs + G - 1) / G);
+    size_t sm = (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>);
+    if (mode == COL_FWD) LAUNCH(k_colpass<T, COL_FWD>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+    if (mode == COL_CONV) LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+    if (mode == COL_INV) LAUNCH(k_colpass<T, COL_INV>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+    return FL_OK;
+  };
+  const long nr = pb.nrhs;
+  if (d == 2) {
+    const long H1 = op->H[1], n0 = op->n[0];
+    ColGeom cg = {0, (int)n0, (int)n0, H1, nr, H1, n0 * H1, H1, n0 * H1, 1, 1};
+    STCHK(col(cg, COL_CONV));
+  } else {
+    const long n0 = op->n[0], n1 = op->n[1], P1 = op->P[1], H2 = op->H[2];
+    ColGeom f = {1, (int)n1, (int)P1, H2, nr * n0, H2, n1 * H2, H2, P1 * H2, 1, 2};
+    ColGeom c = {0, (int)n0, (int)n0, P1 * H2, nr, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
+    ColGeom i = {1, (int)P1, (int)n1, H2, nr * n0, H2, P1 * H2, H2, n1 * H2, 2, 1};
+    STCHK(col(f, COL_FWD));
+    STCHK(col(c, COL_CONV));
+    STCHK(col(i, COL_INV));
+  }
+  {
+    int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
+    LAUNCH(k_rowinv<T, EPI>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pr, it, chk);
+  }
+  return FL_OK;
+}
+
+
+template fl_status apply_seq<FL_T, PRO_PLAIN, EPI_PLAIN>(fl_op, const Prob&, Iter, int);
+template fl_status apply_seq<FL_T, PRO_PLAIN, EPI_RESID>(fl_op, const Prob&, Iter, int);
+template fl_status apply_seq<FL_T, PRO_PUPD, EPI_PQ>(fl_op, const Prob&, Iter, int);
+
+// One pass of the application on the op's workspace (inputs pb.in, output
+// pb.out, work W1/W2), launched with the same lane tuning as apply_seq.
+template <typename T> fl_status launch_apply_pass(fl_op op, Prob pb, int pass) {
+  hipStream_t s = op->stream;
+  const int d = op->d;
+  long rows = rows_of(op, 1), pairs = (rows + 1) / 2;
+  Iter it = {0, 0};
+  if (d == 1) return fail(FL_E_UNSUPPORTED, "single passes are defined for d >= 2");
+  if (pass == 0 || pass == 2) {
+    pb.ax[d - 1].fft.tpl = tune_tpl(pb.ax[d - 1].fft.tpl, pb.ax[d - 1].P, pairs);
+    const Axis& AL = pb.ax[d - 1];
+    int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
+    size_t sm = (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>);
+    if (pass == 0) LAUNCH(k_rowfwd<T, PRO_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), sm, s, pb, it);
+    else LAUNCH(k_rowinv<T, EPI_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), sm, s, pb, it, 0);
+    return FL_OK;
+  }
+  if (pass == 1) {
+    ColGeom cg;
+    if (d == 2) {
+      const long H1 = op->H[1], n0 = op->n[0];
+      cg = {0, (int)n0, (int)n0, H1, 1, H1, n0 * H1, H1, n0 * H1, 1, 1};
+    } else {
+      const long n0 = op->n[0], P1 = op->P[1], H2 = op->H[2];
+      cg = {0, (int)n0, (int)n0, P1 * H2, 1, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
+    }
+    pb.ax[0].fft.tpl = tune_tpl(pb.ax[0].fft.tpl, pb.ax[0].P, cg.gs * cg.ngroup);
+    const Axis& A = pb.ax[0];
+    int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
+    long grid = cg.ngroup * ((cg.gs + G - 1) / G);
+    LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>), s, pb, cg,
+           it, 0);
+    return FL_OK;
+  }
+  return fail(FL_E_INVALID, "apply pass must be 0, 1 or 2");
+}
+template fl_status launch_apply_pass<FL_T>(fl_op, Prob, int);
+

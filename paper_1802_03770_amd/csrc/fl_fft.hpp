@@ -54,7 +54,7 @@ struct FFTPlan {
   int L;                      // transform length
   int nst;                    // number of stages
   int tpl;                    // lanes per line (power of two)
-  int pad;
+  int fixed;                  // 1: a compile-time specialisation exists for (L, tpl)
   unsigned long long radcode; // 4 bits per stage
   const void* tw;             // cx<T>[L] = e^{-2 pi i m / L}
 };
@@ -223,10 +223,194 @@ __device__ __forceinline__ int next_lg(int lgNs, int R) {
   return R == 2 ? lgNs + 1 : R == 4 ? lgNs + 2 : R == 8 ? lgNs + 3 : -1;
 }
 
+
+// ---------------------------------------------------------------------------
+// Compile-time specialised line FFTs for the lengths the workloads use.  The
+// radix order matches the run-time plan: 8s, 4, 2, 3s, 5s, then odd primes.
+// Lanes per line: the smallest power of two giving <= 8 elements per lane
+// (capped at 256) that also fits every stage.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int c_order(int q) {
+  return q == 0 ? 8 : q == 1 ? 4 : q == 2 ? 2 : q == 3 ? 3 : q == 4 ? 5 : q == 5 ? 7 : q == 6 ? 11 : q == 7 ? 13
+       : q == 8 ? 17 : q == 9 ? 19 : q == 10 ? 23 : q == 11 ? 29 : q == 12 ? 31 : q == 13 ? 37 : q == 14 ? 41 : 43;
+}
+__host__ __device__ constexpr int c_radix(int L, int s) {
+  int m = L, idx = 0;
+  for (int q = 0; q < 16; ++q) {
+    const int p = c_order(q);
+    while (m % p == 0) {
+      if (idx == s) return p;
+      m /= p;
+      ++idx;
+    }
+  }
+  return 1;
+}
+__host__ __device__ constexpr int c_nst(int L) {
+  int m = L, idx = 0;
+  for (int q = 0; q < 16; ++q) {
+    const int p = c_order(q);
+    while (m % p == 0) {
+      m /= p;
+      ++idx;
+    }
+  }
+  return idx;
+}
+__host__ __device__ constexpr int c_fixed_tpl(int L) {
+  int t = 1;
+  while (t * 8 < L && t < 256) t *= 2;
+  for (;;) {
+    bool ok = true;
+    for (int s = 0; s < c_nst(L); ++s) {
+      const int R = c_radix(L, s), nb = L / R, per = (nb + t - 1) / t;
+      const int cap = 16 / R > 1 ? 16 / R : 1;
+      if (per > cap) ok = false;
+    }
+    if (ok || t >= 256) return t;
+    t *= 2;
+  }
+}
+// lengths with a specialisation (apply / chirp-z / cosine lengths, direct sine lengths)
+__host__ __device__ constexpr bool c_is_fixed(int L) {
+  return L == 128 || L == 256 || L == 512 || L == 768 || L == 1024 || L == 2048 || L == 130 || L == 258 ||
+         L == 770 || L == 1026 || L == 2050;
+}
+
+// direct DFT of odd prime radix R on registers a[0..R-1] (conjugate-pair form)
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void bfly_prime(cx<T>* a, const T* cs, const T* sn) {
+  constexpr int H = (R - 1) / 2;
+  cx<T> sm[H], df[H];
+  cx<T> a0 = a[0], y0 = a[0];
+#pragma unroll
+  for (int q = 1; q <= H; ++q) {
+    sm[q - 1] = cadd(a[q], a[R - q]);
+    df[q - 1] = csub(a[q], a[R - q]);
+    y0 = cadd(y0, sm[q - 1]);
+  }
+#pragma unroll
+  for (int kk = 1; kk <= H; ++kk) {
+    cx<T> re = a0, im = {0, 0};
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+      const int m = (q * kk) % R;
+      const T c = m <= H ? cs[m] : cs[R - m];
+      const T sg = m <= H ? sn[m] : -sn[R - m];
+      re.x += sm[q - 1].x * c;
+      re.y += sm[q - 1].y * c;
+      im.x += df[q - 1].x * sg;
+      im.y += df[q - 1].y * sg;
+    }
+    cx<T> yp = {re.x + im.y, re.y - im.x};
+    cx<T> ym = {re.x - im.y, re.y + im.x};
+    a[kk] = INV ? ym : yp;
+    a[R - kk] = INV ? yp : ym;
+  }
+  a[0] = y0;
+}
+
+template <typename T, int R, int L, int NS, int TPL, bool INV>
+__device__ __forceinline__ void cstage(Line<T> buf, const cx<T>* __restrict__ tw, int lane) {
+  constexpr int NB = L / R;
+  constexpr int MB = (NB + TPL - 1) / TPL;
+  constexpr bool FULL = (NB % TPL) == 0;
+  constexpr int TSTEP = L / (NS * R);
+  constexpr bool PRIME = R >= 7 && R != 8;  // odd primes only
+  constexpr int H = PRIME ? (R - 1) / 2 : 1;
+  T cs[H + 1], sn[H + 1];
+  if (PRIME) {
+#pragma unroll
+    for (int m = 1; m <= H; ++m) {
+      cx<T> w = tw[m * (L / R)];
+      cs[m] = w.x;
+      sn[m] = -w.y;
+    }
+  }
+  cx<T> v[MB][R];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int j = lane + b * TPL;
+    if (FULL || j < NB) {
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * NB];
+      if (NS > 1) {
+        const int st = k * TSTEP;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = tw[r * st];
+          v[b][r] = INV ? cmulc(v[b][r], w) : cmul(v[b][r], w);
+        }
+      }
+      if constexpr (PRIME)
+        bfly_prime<T, R, INV>(v[b], cs, sn);
+      else
+        Bfly<T, R, INV>::run(v[b]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int j = lane + b * TPL;
+    if (FULL || j < NB) {
+      const int k = j % NS;
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + r * NS] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int L, int TPL, bool INV, int S, int NS>
+__device__ __forceinline__ void cstages(Line<T> buf, const cx<T>* __restrict__ tw, int lane) {
+  if constexpr (S < c_nst(L)) {
+    constexpr int R = c_radix(L, S);
+    cstage<T, R, L, NS, TPL, INV>(buf, tw, lane);
+    cstages<T, L, TPL, INV, S + 1, NS * R>(buf, tw, lane);
+  }
+}
+
+template <typename T, int L, bool INV>
+__device__ __forceinline__ void fft_fixed(Line<T> buf, const cx<T>* __restrict__ tw, int lane) {
+  cstages<T, L, c_fixed_tpl(L), INV, 0, 1>(buf, tw, lane);
+}
+
+// Dispatch to a specialisation; false when the plan has none.
+template <typename T, bool INV>
+__device__ __forceinline__ bool fft_try_fixed(Line<T> buf, const FFTPlan& pl, int lane) {
+  if (!pl.fixed) return false;
+  const cx<T>* __restrict__ tw = (const cx<T>*)pl.tw;
+  switch (pl.L) {
+    case 2048: fft_fixed<T, 2048, INV>(buf, tw, lane); return true;
+    case 1024: fft_fixed<T, 1024, INV>(buf, tw, lane); return true;
+    case 512: fft_fixed<T, 512, INV>(buf, tw, lane); return true;
+    case 256: fft_fixed<T, 256, INV>(buf, tw, lane); return true;
+    case 128: fft_fixed<T, 128, INV>(buf, tw, lane); return true;
+    case 768: fft_fixed<T, 768, INV>(buf, tw, lane); return true;
+    default: return false;
+  }
+}
+template <typename T, bool INV>
+__device__ __forceinline__ bool fft_try_fixed_wide(Line<T> buf, const FFTPlan& pl, int lane) {
+  if (!pl.fixed) return false;
+  const cx<T>* __restrict__ tw = (const cx<T>*)pl.tw;
+  switch (pl.L) {
+    case 2050: fft_fixed<T, 2050, INV>(buf, tw, lane); return true;
+    case 1026: fft_fixed<T, 1026, INV>(buf, tw, lane); return true;
+    case 770: fft_fixed<T, 770, INV>(buf, tw, lane); return true;
+    case 258: fft_fixed<T, 258, INV>(buf, tw, lane); return true;
+    case 130: fft_fixed<T, 130, INV>(buf, tw, lane); return true;
+    default: return false;
+  }
+}
+
 // Full in-place FFT of the LDS line `buf` (unnormalised in both directions).
 // Every lane of the workgroup must call this (it contains barriers).
 template <typename T, bool INV>
 __device__ __forceinline__ void fft_line(Line<T> buf, const FFTPlan pl, int lane) {
+  if (fft_try_fixed<T, INV>(buf, pl, lane)) return;
   const cx<T>* __restrict__ tw = (const cx<T>*)pl.tw;
   int Ns = 1, lg = 0;
   for (int s = 0; s < pl.nst; ++s) {
@@ -341,6 +525,7 @@ __device__ __forceinline__ void fft_stage_prime_oop(Line<T> src, Line<T> dst, in
 // holding the result.  Used by the sine transforms of length 2(n+1).
 template <typename T, bool INV>
 __device__ __forceinline__ Line<T> fft_line_wide(Line<T> a, Line<T> b, const FFTPlan pl, int lane) {
+  if (fft_try_fixed_wide<T, INV>(a, pl, lane)) return a;  // in place
   const cx<T>* __restrict__ tw = (const cx<T>*)pl.tw;
   int Ns = 1, lg = 0;
   Line<T> src = a, dst = b;

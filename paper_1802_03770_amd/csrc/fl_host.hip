@@ -15,41 +15,12 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fraclap.h"
-#include "fl_kernels.hpp"
+#define FL_MISC_KERNELS
+#include "fl_internal.hpp"
 
 using namespace fl;
 
-// ---------------------------------------------------------------------------
-// errors
-// ---------------------------------------------------------------------------
-static thread_local std::string g_err;
-static fl_status fail(fl_status s, const std::string& m) {
-  g_err = m;
-  return s;
-}
-#define HIPCHK(x)                                                                      \
-  do {                                                                                 \
-    hipError_t e_ = (x);                                                               \
-    if (e_ != hipSuccess) return fail(FL_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-#define STCHK(x)                     \
-  do {                               \
-    fl_status s_ = (x);              \
-    if (s_ != FL_OK) return s_;      \
-  } while (0)
-
-template <typename K, typename... A>
-static hipError_t launch(K* k, dim3 g, dim3 b, size_t smem, hipStream_t s, A... args) {
-  if (g.x == 0 || g.y == 0) return hipSuccess;
-  if (smem > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k, g, b, smem, s, args...);
-  return hipGetLastError();
-}
-#define LAUNCH(...) HIPCHK(launch(__VA_ARGS__))
+thread_local std::string g_err;
 
 // ---------------------------------------------------------------------------
 // plans and tables
@@ -85,7 +56,7 @@ static bool make_radices(int L, FFTPlan& pl, bool wide = false) {
   if (m != 1 || (int)r.size() > kMaxStages) return false;
   pl.L = L;
   pl.nst = (int)r.size();
-  pl.pad = 0;
+  pl.fixed = 0;
   pl.radcode = 0;
   for (int i = 0; i < pl.nst; ++i) {
     int c = 0;
@@ -105,6 +76,11 @@ static bool make_radices(int L, FFTPlan& pl, bool wide = false) {
   }
   if (tpl > 256) return false;  // kernels run 256-lane workgroups
   pl.tpl = tpl;
+  pl.fixed = 0;
+  if (c_is_fixed(L) && (wide || c_radix(L, c_nst(L) - 1) <= 8)) {
+    pl.fixed = 1;  // the device has a compile-time version with these lanes
+    pl.tpl = c_fixed_tpl(L);
+  }
   return true;
 }
 
@@ -124,62 +100,6 @@ template <typename T> static std::vector<cx<T>> host_twiddles(int L) {
     t[m] = {(T)cosl(a), (T)(-sinl(a))};
   }
   return t;
-}
-
-// ---------------------------------------------------------------------------
-// operator object
-// ---------------------------------------------------------------------------
-struct Workspace {
-  long cap_rhs = 0;        // apply/precond batch capacity
-  void* W1 = nullptr;
-  void* W2 = nullptr;
-  void* T1 = nullptr;
-  bool solver = false;     // Krylov vectors allocated
-  void *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *f = nullptr;
-  Scalars* sc = nullptr;
-  double* part = nullptr;
-  long npart = 0;
-  // graph of `gK` PCG iterations starting at an odd iteration
-  hipGraphExec_t gexec = nullptr;
-  int gK = 0, gpc = -1;
-  double gs0 = 0, gs1 = 0, gp0 = 0, gp1 = 0;
-  const uint8_t* gmask = nullptr;
-};
-
-struct fl_op_s {
-  int d = 0;
-  double alpha = 0, h = 0, c = 20;
-  int n[3] = {1, 1, 1}, P[3] = {2, 2, 2}, H[3] = {1, 1, 1};
-  long N = 0, NH = 0;
-  hipStream_t stream = nullptr;
-  double cst[8] = {0};
-  double* d_cst = nullptr;
-  double* wf = nullptr;     // folded weights [H...] FP64
-  void* lam[2] = {nullptr, nullptr};  // folded symbol FP64 / FP32
-  Axis ax[2][3];            // per dtype
-  std::vector<void*> tables;
-  Workspace ws[2];
-  Scalars* hsc = nullptr;   // pinned host mirror of a Scalars
-  ~fl_op_s();
-};
-
-template <typename T> static constexpr int tix() { return sizeof(T) == 8 ? 0 : 1; }
-
-static fl_status dalloc(void** p, size_t bytes) {
-  if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
-    *p = nullptr;
-    return fail(FL_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-  }
-  return FL_OK;
-}
-
-template <typename T> static fl_status upload(fl_op op, const std::vector<T>& h, const void** out) {
-  void* p;
-  STCHK(dalloc(&p, h.size() * sizeof(T)));
-  op->tables.push_back(p);
-  HIPCHK(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
-  *out = p;
-  return FL_OK;
 }
 
 template <typename T> static fl_status build_axis(fl_op op, int a) {
@@ -244,178 +164,6 @@ fl_op_s::~fl_op_s() {
   if (wf) hipFree(wf);
   for (void* p : lam) if (p) hipFree(p);
   if (hsc) hipHostFree(hsc);
-}
-
-// block size for a line-FFT kernel with `tpl` lanes per line
-static int block_for(int tpl) { return 256; }
-
-// More lanes per line (fewer elements per lane) when a pass has too few lines
-// to give every CU two workgroups; the plan's tpl is the minimum.
-static int tune_tpl(int tpl0, int L, long nlines) {
-  int tpl = tpl0;
-  while (tpl < 256 && (nlines * tpl) / 256 < 512 && L / tpl >= 8) tpl *= 2;
-  return tpl;
-}
-
-// ---------------------------------------------------------------------------
-// problem descriptors
-// ---------------------------------------------------------------------------
-template <typename T> static Prob base_prob(fl_op op, long nrhs) {
-  Prob pb;
-  memset(&pb, 0, sizeof(pb));
-  pb.d = op->d;
-  pb.nrhs = (int)nrhs;
-  for (int a = 0; a < 3; ++a) pb.ax[a] = op->ax[tix<T>()][a];
-  pb.lam = op->lam[tix<T>()];
-  pb.s0 = 0.0;
-  pb.s1 = 1.0;
-  pb.pcs = op->cst[0] * std::fabs(op->cst[2]) * std::pow(op->h, -op->alpha);
-  pb.p0 = 0.0;
-  pb.p1 = 1.0;
-  return pb;
-}
-
-static long rows_of(fl_op op, long nrhs) {
-  long r = nrhs;
-  for (int a = 0; a < op->d - 1; ++a) r *= op->n[a];
-  return r;
-}
-
-template <typename T> static fl_status ensure_ws(fl_op op, long nrhs, bool solver) {
-  Workspace& w = op->ws[tix<T>()];
-  const long N = op->N;
-  if (w.cap_rhs < nrhs) {
-    for (void** p : {&w.W1, &w.W2, &w.T1})
-      if (*p) { hipFree(*p); *p = nullptr; }
-    long rows = rows_of(op, nrhs);
-    STCHK(dalloc(&w.W1, (size_t)rows * op->H[op->d - 1] * sizeof(cx<T>)));
-    if (op->d == 3) STCHK(dalloc(&w.W2, (size_t)nrhs * op->n[0] * op->P[1] * op->H[2] * sizeof(cx<T>)));
-    STCHK(dalloc(&w.T1, (size_t)nrhs * N * sizeof(T)));
-    w.cap_rhs = nrhs;
-    long np = std::max<long>(4096, rows + 1);  // partials per site
-    if (w.npart < np) {
-      if (w.part) hipFree(w.part);
-      STCHK(dalloc((void**)&w.part, NSITE * np * sizeof(double)));
-      w.npart = np;
-    }
-  }
-  if (!w.sc) {
-    STCHK(dalloc((void**)&w.sc, sizeof(Scalars)));
-    HIPCHK(hipMemset(w.sc, 0, sizeof(Scalars)));
-  }
-  if (solver && !w.solver) {
-    for (void** p : {&w.x, &w.r, &w.z, &w.p, &w.q, &w.f}) STCHK(dalloc(p, (size_t)N * sizeof(T)));
-    w.solver = true;
-  }
-  return FL_OK;
-}
-
-// ---------------------------------------------------------------------------
-// operator application (M or shift0 I + shift1 M)
-// ---------------------------------------------------------------------------
-template <typename T, int PRO, int EPI> static fl_status apply_seq(fl_op op, const Prob& pb, Iter it, int chk) {
-  hipStream_t s = op->stream;
-  const int d = op->d;
-  if (d == 1) {
-    Prob p1 = pb;
-    long pairs = (pb.nrhs + 1) / 2;
-    p1.ax[0].fft.tpl = tune_tpl(pb.ax[0].fft.tpl, pb.ax[0].P, pairs);
-    const Axis& A = p1.ax[0];
-    int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
-    LAUNCH(k_conv1d<T, PRO, EPI>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>), s, p1, it);
-    return FL_OK;
-  }
-  long rows = rows_of(op, pb.nrhs), pairs = (rows + 1) / 2;
-  Prob pr = pb;  // row passes: lanes per line tuned to the number of row pairs
-  pr.ax[d - 1].fft.tpl = tune_tpl(pb.ax[d - 1].fft.tpl, pb.ax[d - 1].P, pairs);
-  const Axis& AL = pr.ax[d - 1];
-  {
-    int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
-    LAUNCH(k_rowfwd<T, PRO>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pr, it);
-  }
-  auto col = [&](ColGeom cg, int mode) -> fl_status {
-    Prob pc = pb;
-    Axis& A = pc.ax[cg.axis];
-    A.fft.tpl = tune_tpl(A.fft.tpl, A.P, cg.gs * cg.ngroup);
-    int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
-    long grid = cg.ngroup * ((cg.gs + G - 1) / G);
-    size_t sm = (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>);
-    if (mode == COL_FWD) LAUNCH(k_colpass<T, COL_FWD>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
-    if (mode == COL_CONV) LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
-    if (mode == COL_INV) LAUNCH(k_colpass<T, COL_INV>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
-    return FL_OK;
-  };
-  const long nr = pb.nrhs;
-  if (d == 2) {
-    const long H1 = op->H[1], n0 = op->n[0];
-    ColGeom cg = {0, (int)n0, (int)n0, H1, nr, H1, n0 * H1, H1, n0 * H1, 1, 1};
-    STCHK(col(cg, COL_CONV));
-  } else {
-    const long n0 = op->n[0], n1 = op->n[1], P1 = op->P[1], H2 = op->H[2];
-    ColGeom f = {1, (int)n1, (int)P1, H2, nr * n0, H2, n1 * H2, H2, P1 * H2, 1, 2};
-    ColGeom c = {0, (int)n0, (int)n0, P1 * H2, nr, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
-    ColGeom i = {1, (int)P1, (int)n1, H2, nr * n0, H2, P1 * H2, H2, n1 * H2, 2, 1};
-    STCHK(col(f, COL_FWD));
-    STCHK(col(c, COL_CONV));
-    STCHK(col(i, COL_INV));
-  }
-  {
-    int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
-    LAUNCH(k_rowinv<T, EPI>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pr, it, chk);
-  }
-  return FL_OK;
-}
-
-// ---------------------------------------------------------------------------
-// preconditioner (p0 I + p1 pcs T)^{-1}
-// ---------------------------------------------------------------------------
-template <typename T, int DPRO, int DEPI> static fl_status precond_seq(fl_op op, Prob pb, Iter it, int chk) {
-  hipStream_t s = op->stream;
-  const int d = op->d;
-  long rows = rows_of(op, pb.nrhs);
-  const long rlines = pb.ax[d - 1].dst_direct ? (rows + 1) / 2 : rows;  // FFT lines
-  pb.ax[d - 1].dst.tpl = tune_tpl(pb.ax[d - 1].dst.tpl, pb.ax[d - 1].dst.L, rlines);
-  const Axis& AL = pb.ax[d - 1];
-  int nt = block_for(AL.dst.tpl), G = nt / AL.dst.tpl;
-  size_t sm = (size_t)G * Line<T>::stride(AL.dst.L) * sizeof(cx<T>) * (AL.dst_direct ? 2 : 1);
-  dim3 gr((rlines + G - 1) / G);
-  if (d == 1) {
-    LAUNCH(k_dst_rows<T, DPRO, DEPI>, gr, dim3(nt), sm, s, pb, it, chk);
-    return FL_OK;
-  }
-  Prob p1 = pb;
-  p1.out = pb.T1;
-  LAUNCH(k_dst_rows<T, DPRO, DEPI_STORE>, gr, dim3(nt), sm, s, p1, it, chk);
-  auto cols = [&](DGeom g, bool scale) -> fl_status {
-    Prob pc = pb;
-    Axis& A = pc.ax[g.axis];
-    const int per = A.dst_direct ? 2 : 1;  // real lines per FFT line
-    A.dst.tpl = tune_tpl(A.dst.tpl, A.dst.L, g.gs * g.ngroup / per);
-    int ntc = block_for(A.dst.tpl), Gf = ntc / A.dst.tpl, Gc = Gf * per;
-    long grid = g.ngroup * ((g.gs + Gc - 1) / Gc);
-    size_t smc = (size_t)Gf * Line<T>::stride(A.dst.L) * sizeof(cx<T>) * per;
-    if (scale)
-      LAUNCH(k_dst_cols<T, true>, dim3(grid), dim3(ntc), smc, s, pc, g, chk);
-    else
-      LAUNCH(k_dst_cols<T, false>, dim3(grid), dim3(ntc), smc, s, pc, g, chk);
-    return FL_OK;
-  };
-  const long nr = pb.nrhs;
-  if (d == 2) {
-    const long n0 = op->n[0], n1 = op->n[1];
-    STCHK(cols(DGeom{0, n1, nr, n1, n0 * n1}, true));
-  } else {
-    const long n0 = op->n[0], n1 = op->n[1], n2 = op->n[2];
-    DGeom g1 = {1, n2, nr * n0, n2, n1 * n2};
-    DGeom g0 = {0, n1 * n2, nr, n1 * n2, n0 * n1 * n2};
-    STCHK(cols(g1, false));
-    STCHK(cols(g0, true));
-    STCHK(cols(g1, false));
-  }
-  Prob p3 = pb;
-  p3.in = pb.T1;
-  LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI>, gr, dim3(nt), sm, s, p3, it, chk);
-  return FL_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -501,29 +249,6 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
 // ---------------------------------------------------------------------------
 // Krylov drivers
 // ---------------------------------------------------------------------------
-template <typename T> static Prob solver_prob(fl_op op, const uint8_t* mask, double s0, double s1, double p0,
-                                              double p1) {
-  Workspace& w = op->ws[tix<T>()];
-  Prob pb = base_prob<T>(op, 1);
-  pb.s0 = s0;
-  pb.s1 = s1;
-  pb.p0 = p0;
-  pb.p1 = p1;
-  pb.W1 = w.W1;
-  pb.W2 = w.W2;
-  pb.T1 = w.T1;
-  pb.mask = mask;
-  pb.x = w.x;
-  pb.r = w.r;
-  pb.z = w.z;
-  pb.p = w.p;
-  pb.q = w.q;
-  pb.sc = w.sc;
-  pb.part = w.part;
-  pb.pstride = w.npart;
-  return pb;
-}
-
 template <typename T> static fl_status one_iteration(fl_op op, const Prob& pb, int pc, int k) {
   Iter it = {k & 1, k == 0 ? 1 : 0};
   Prob pz = pb;
@@ -610,7 +335,7 @@ template <typename T> static fl_status krylov(fl_op op, const Prob& pb, int pc, 
   return FL_OK;
 }
 
-static long nblocks_vec(long n) { return (n + 255) / 256; }
+
 
 // True FP64 residual r = b - A x into ws64.q; returns ||r||^2 via sc->rr.
 static fl_status true_residual(fl_op op, const uint8_t* mask, double s0, double s1, const double* x,
@@ -760,6 +485,7 @@ static fl_status precond_t(fl_op op, const void* r, void* z, long batch, const u
 // (axis 0), 2 rows inverse, 3 first sine pass, 4 scaled sine column pass,
 // 5 last sine pass, 6 whole application, 7 whole preconditioner.
 template <typename T> static fl_status profile_t(fl_op op, int pass, int reps, double* avg_ms) {
+  if (pass < 0 || pass > 7) return fail(FL_E_INVALID, "pass must be 0..7");
   STCHK(ensure_ws<T>(op, 1, true));
   Workspace& w = op->ws[tix<T>()];
   hipStream_t s = op->stream;
@@ -774,70 +500,11 @@ template <typename T> static fl_status profile_t(fl_op op, int pass, int reps, d
   Prob pb = solver_prob<T>(op, nullptr, 0.0, 1.0, 0.0, 1.0);
   pb.in = w.x;
   pb.out = w.q;
-  const int d = op->d;
-  const Axis& AL = pb.ax[d - 1];
-  long rows = rows_of(op, 1), pairs = (rows + 1) / 2;
-  Iter it = {0, 0};
-  // same lane tuning as the solver launches
-  if (pass == 0 || pass == 2) pb.ax[d - 1].fft.tpl = tune_tpl(pb.ax[d - 1].fft.tpl, pb.ax[d - 1].P, pairs);
-  const long rlines = pb.ax[d - 1].dst_direct ? (rows + 1) / 2 : rows;
-  if (pass == 3 || pass == 5) pb.ax[d - 1].dst.tpl = tune_tpl(pb.ax[d - 1].dst.tpl, pb.ax[d - 1].dst.L, rlines);
-  if (pass == 1) {
-    long nl = d == 2 ? (long)op->H[1] : (long)op->P[1] * op->H[2];
-    pb.ax[0].fft.tpl = tune_tpl(pb.ax[0].fft.tpl, pb.ax[0].P, nl);
-  }
-  if (pass == 4) {
-    long nl = d == 2 ? (long)op->n[1] : (long)op->n[1] * op->n[2];
-    pb.ax[0].dst.tpl = tune_tpl(pb.ax[0].dst.tpl, pb.ax[0].dst.L, pb.ax[0].dst_direct ? nl / 2 : nl);
-  }
   auto one = [&]() -> fl_status {
-    if (pass == 6) return apply_seq<T, PRO_PLAIN, EPI_PLAIN>(op, pb, it, 0);
-    if (pass == 7) return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pb, it, 0);
-    if (d == 1) return fail(FL_E_UNSUPPORTED, "single passes are defined for d >= 2");
-    if (pass == 0) {
-      int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
-      LAUNCH(k_rowfwd<T, PRO_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pb, it);
-    } else if (pass == 1) {
-      const Axis& A = pb.ax[0];
-      int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
-      ColGeom cg;
-      if (d == 2) {
-        const long H1 = op->H[1], n0 = op->n[0];
-        cg = {0, (int)n0, (int)n0, H1, 1, H1, n0 * H1, H1, n0 * H1, 1, 1};
-      } else {
-        const long n0 = op->n[0], P1 = op->P[1], H2 = op->H[2];
-        cg = {0, (int)n0, (int)n0, P1 * H2, 1, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
-      }
-      long grid = cg.ngroup * ((cg.gs + G - 1) / G);
-      LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>), s, pb, cg, it, 0);
-    } else if (pass == 2) {
-      int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
-      LAUNCH(k_rowinv<T, EPI_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pb, it, 0);
-    } else if (pass == 3 || pass == 5) {
-      int nt = block_for(AL.dst.tpl), G = nt / AL.dst.tpl;
-      Prob p1 = pb;
-      if (pass == 3) p1.out = w.T1; else p1.in = w.T1;
-      size_t sm = (size_t)G * Line<T>::stride(AL.dst.L) * sizeof(cx<T>) * (AL.dst_direct ? 2 : 1);
-      if (pass == 3)
-        LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI_STORE>, dim3((rlines + G - 1) / G), dim3(nt), sm, s, p1, it, 0);
-      else
-        LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI_FINAL>, dim3((rlines + G - 1) / G), dim3(nt), sm, s, p1, it, 0);
-    } else if (pass == 4) {
-      const Axis& A = pb.ax[0];
-      int nt = block_for(A.dst.tpl), Gf = nt / A.dst.tpl, G = Gf * (A.dst_direct ? 2 : 1);
-      DGeom g;
-      if (d == 2) g = DGeom{0, (long)op->n[1], 1, (long)op->n[1], (long)op->n[0] * op->n[1]};
-      else {
-        long n12 = (long)op->n[1] * op->n[2];
-        g = DGeom{0, n12, 1, n12, (long)op->n[0] * n12};
-      }
-      long grid = g.ngroup * ((g.gs + G - 1) / G);
-      LAUNCH(k_dst_cols<T, true>, dim3(grid), dim3(nt), (size_t)Gf * Line<T>::stride(A.dst.L) * sizeof(cx<T>) * (A.dst_direct ? 2 : 1),
-             s, pb, g, 0);
-    } else {
-      return fail(FL_E_INVALID, "pass must be 0..7");
-    }
-    return FL_OK;
+    if (pass == 6) return apply_seq<T, PRO_PLAIN, EPI_PLAIN>(op, pb, Iter{0, 0}, 0);
+    if (pass == 7) return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pb, Iter{0, 0}, 0);
+    if (pass <= 2) return launch_apply_pass<T>(op, pb, pass);
+    return launch_precond_pass<T>(op, pb, pass);
   };
   STCHK(one());  // warm-up
   hipEvent_t e0, e1;

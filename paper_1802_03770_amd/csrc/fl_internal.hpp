@@ -1,0 +1,202 @@
+// Internal declarations shared by the translation units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fraclap.h"
+#include "fl_kernels.hpp"
+
+using namespace fl;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+extern thread_local std::string g_err;
+inline fl_status fail(fl_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return fail(FL_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define STCHK(x)                     \
+  do {                               \
+    fl_status s_ = (x);              \
+    if (s_ != FL_OK) return s_;      \
+  } while (0)
+
+template <typename K, typename... A>
+inline hipError_t launch(K* k, dim3 g, dim3 b, size_t smem, hipStream_t s, A... args) {
+  if (g.x == 0 || g.y == 0) return hipSuccess;
+  if (smem > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k, g, b, smem, s, args...);
+  return hipGetLastError();
+}
+#define LAUNCH(...) HIPCHK(launch(__VA_ARGS__))
+
+// ---------------------------------------------------------------------------
+// operator object
+// ---------------------------------------------------------------------------
+struct Workspace {
+  long cap_rhs = 0;        // apply/precond batch capacity
+  void* W1 = nullptr;
+  void* W2 = nullptr;
+  void* T1 = nullptr;
+  bool solver = false;     // Krylov vectors allocated
+  void *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *f = nullptr;
+  Scalars* sc = nullptr;
+  double* part = nullptr;
+  long npart = 0;
+  // graph of `gK` PCG iterations starting at an odd iteration
+  hipGraphExec_t gexec = nullptr;
+  int gK = 0, gpc = -1;
+  double gs0 = 0, gs1 = 0, gp0 = 0, gp1 = 0;
+  const uint8_t* gmask = nullptr;
+};
+
+struct fl_op_s {
+  int d = 0;
+  double alpha = 0, h = 0, c = 20;
+  int n[3] = {1, 1, 1}, P[3] = {2, 2, 2}, H[3] = {1, 1, 1};
+  long N = 0, NH = 0;
+  hipStream_t stream = nullptr;
+  double cst[8] = {0};
+  double* d_cst = nullptr;
+  double* wf = nullptr;     // folded weights [H...] FP64
+  void* lam[2] = {nullptr, nullptr};  // folded symbol FP64 / FP32
+  Axis ax[2][3];            // per dtype
+  std::vector<void*> tables;
+  Workspace ws[2];
+  Scalars* hsc = nullptr;   // pinned host mirror of a Scalars
+  ~fl_op_s();
+};
+
+template <typename T> constexpr int tix() { return sizeof(T) == 8 ? 0 : 1; }
+
+inline fl_status dalloc(void** p, size_t bytes) {
+  if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+    *p = nullptr;
+    return fail(FL_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return FL_OK;
+}
+
+template <typename T> inline fl_status upload(fl_op op, const std::vector<T>& h, const void** out) {
+  void* p;
+  STCHK(dalloc(&p, h.size() * sizeof(T)));
+  op->tables.push_back(p);
+  HIPCHK(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = p;
+  return FL_OK;
+}
+
+// block size for a line-FFT kernel with `tpl` lanes per line
+inline int block_for(int) { return 256; }
+
+// More lanes per line (fewer elements per lane) when a pass has too few lines
+// to give every CU two workgroups; the plan's tpl is the minimum.
+inline int tune_tpl(int tpl0, int L, long nlines) {
+  if (c_is_fixed(L)) return tpl0;  // specialised lengths keep their compile-time lane count
+  int tpl = tpl0;
+  while (tpl < 256 && (nlines * tpl) / 256 < 512 && L / tpl >= 8) tpl *= 2;
+  return tpl;
+}
+
+// ---------------------------------------------------------------------------
+// problem descriptors
+// ---------------------------------------------------------------------------
+template <typename T> inline Prob base_prob(fl_op op, long nrhs) {
+  Prob pb;
+  memset(&pb, 0, sizeof(pb));
+  pb.d = op->d;
+  pb.nrhs = (int)nrhs;
+  for (int a = 0; a < 3; ++a) pb.ax[a] = op->ax[tix<T>()][a];
+  pb.lam = op->lam[tix<T>()];
+  pb.s0 = 0.0;
+  pb.s1 = 1.0;
+  pb.pcs = op->cst[0] * std::fabs(op->cst[2]) * std::pow(op->h, -op->alpha);
+  pb.p0 = 0.0;
+  pb.p1 = 1.0;
+  return pb;
+}
+
+inline long rows_of(fl_op op, long nrhs) {
+  long r = nrhs;
+  for (int a = 0; a < op->d - 1; ++a) r *= op->n[a];
+  return r;
+}
+
+template <typename T> inline fl_status ensure_ws(fl_op op, long nrhs, bool solver) {
+  Workspace& w = op->ws[tix<T>()];
+  const long N = op->N;
+  if (w.cap_rhs < nrhs) {
+    for (void** p : {&w.W1, &w.W2, &w.T1})
+      if (*p) { hipFree(*p); *p = nullptr; }
+    long rows = rows_of(op, nrhs);
+    STCHK(dalloc(&w.W1, (size_t)rows * op->H[op->d - 1] * sizeof(cx<T>)));
+    if (op->d == 3) STCHK(dalloc(&w.W2, (size_t)nrhs * op->n[0] * op->P[1] * op->H[2] * sizeof(cx<T>)));
+    STCHK(dalloc(&w.T1, (size_t)nrhs * N * sizeof(T)));
+    w.cap_rhs = nrhs;
+    long np = std::max<long>(4096, rows + 1);  // partials per site
+    if (w.npart < np) {
+      if (w.part) hipFree(w.part);
+      STCHK(dalloc((void**)&w.part, NSITE * np * sizeof(double)));
+      w.npart = np;
+    }
+  }
+  if (!w.sc) {
+    STCHK(dalloc((void**)&w.sc, sizeof(Scalars)));
+    HIPCHK(hipMemset(w.sc, 0, sizeof(Scalars)));
+  }
+  if (solver && !w.solver) {
+    for (void** p : {&w.x, &w.r, &w.z, &w.p, &w.q, &w.f}) STCHK(dalloc(p, (size_t)N * sizeof(T)));
+    w.solver = true;
+  }
+  return FL_OK;
+}
+
+template <typename T> inline Prob solver_prob(fl_op op, const uint8_t* mask, double s0, double s1, double p0,
+                                              double p1) {
+  Workspace& w = op->ws[tix<T>()];
+  Prob pb = base_prob<T>(op, 1);
+  pb.s0 = s0;
+  pb.s1 = s1;
+  pb.p0 = p0;
+  pb.p1 = p1;
+  pb.W1 = w.W1;
+  pb.W2 = w.W2;
+  pb.T1 = w.T1;
+  pb.mask = mask;
+  pb.x = w.x;
+  pb.r = w.r;
+  pb.z = w.z;
+  pb.p = w.p;
+  pb.q = w.q;
+  pb.sc = w.sc;
+  pb.part = w.part;
+  pb.pstride = w.npart;
+  return pb;
+}
+
+inline long nblocks_vec(long n) { return (n + 255) / 256; }
+
+// Launch sequences (defined per precision in fl_apply.hip / fl_precond.hip).
+template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob& pb, Iter it, int chk);
+template <typename T, int DPRO, int DEPI> fl_status precond_seq(fl_op op, Prob pb, Iter it, int chk);
+// One pass of the application (0 rows fwd, 1 symbol column pass, 2 rows inverse)
+// or of the preconditioner (3 first sine pass, 4 scaled column pass, 5 last).
+template <typename T> fl_status launch_apply_pass(fl_op op, Prob pb, int pass);
+template <typename T> fl_status launch_precond_pass(fl_op op, Prob pb, int pass);
+

@@ -85,6 +85,7 @@ __device__ __forceinline__ long nper_of(const Prob& pb) {
   return r;
 }
 
+#ifdef FL_MISC_KERNELS
 // ---------------------------------------------------------------------------
 // Operator construction (FP64)
 // ---------------------------------------------------------------------------
@@ -230,6 +231,8 @@ __global__ __launch_bounds__(256) void k_dct1_axis(double* wf, int H, int P, lon
     if (vb) wf[bb + (long)k * inner] = buf[k].y;
   }
 }
+
+#endif  // FL_MISC_KERNELS
 
 template <typename TO, typename TI>
 __global__ void k_cast(const TI* in, TO* out, long n, double scale) {
@@ -906,7 +909,9 @@ __global__ FL_BOUNDS void k_dst_cols_b(const Prob* pbs, const DGeom* dgs, int ch
 template <typename T> __global__ FL_BOUNDS void k_dot(Prob pb, const void* a, const void* b, int site, long n) {
   dot_body<T>(pb, a, b, site, n, gridDim.x, blockIdx.x);
 }
+#ifdef FL_MISC_KERNELS
 __global__ FL_BOUNDS void k_finalize(Prob pb, int site, int target) { finalize_body(pb, site, target); }
+#endif
 template <typename T> __global__ FL_BOUNDS void k_update(Prob pb, Iter it, long n) {
   update_body<T>(pb, it, n, gridDim.x, blockIdx.x);
 }
@@ -914,9 +919,11 @@ template <typename T> __global__ FL_BOUNDS void k_update_b(const Prob* pbs, Iter
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
   update_body<T>(pbs[blockIdx.y], it, ns[blockIdx.y], nb[blockIdx.y], blockIdx.x);
 }
+#ifdef FL_MISC_KERNELS
 __global__ void k_init(Prob pb, double tol, int maxit, int use_rr) { init_body(pb, tol, maxit, use_rr); }
 __global__ void k_init_b(const Prob* pbs, double tol, int maxit, int use_rr) {
   init_body(pbs[blockIdx.y], tol, maxit, use_rr);
 }
+#endif
 
 }  // namespace fl
