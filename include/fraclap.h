@@ -135,15 +135,33 @@ fl_status fl_solve(fl_op op, const double* f, const uint8_t* mask, double tol, c
 fl_status fl_step(fl_op op, double* u, double dt, double theta, const double* f_k, const double* f_k1,
                   const uint8_t* mask, double tol, const fl_solve_opts* opts, fl_info* info);
 
-/* Solve nprob independent systems ops[i] u[i] = f[i] together: every kernel
- * of an iteration is one launch over all problems (uneven sizes and alphas
- * allowed; problems may share an op).  masks may be NULL or hold NULLs.
- * infos[i] receives each problem's result. */
+/* Solve nprob independent systems ops[i] u[i] = f[i] (Sec. 3, the same PCG
+ * as fl_solve) together: every kernel of an iteration is one launch over all
+ * problems (blockIdx.y = problem), and the iteration is replayed as one
+ * captured hipGraph; a converged problem stops doing work while the others
+ * continue.  Uneven grids and alphas are allowed and problems may share an op
+ * (several right-hand sides of one operator).
+ *   ops[i]   : all of the same dimension d and created on the same stream
+ *              (otherwise FL_E_UNSUPPORTED / FL_E_INVALID)
+ *   f[i]     : device FP64, ops[i]'s grid, row-major, read only
+ *   masks    : NULL, or an array whose entries are NULL (box) or device uint8
+ *              masks of ops[i]'s grid
+ *   opts     : as for fl_solve (pc, mixed, maxit, inner_tol, use_x0, graph,
+ *              poll_every, max_outer); NULL = defaults
+ *   u[i]     : device FP64, initial guess when opts->use_x0, solution out
+ *   infos[i] : each problem's iterations, status and residuals; ms is the
+ *              wall time of the whole batch
+ * Per-problem Krylov vectors and work arrays are allocated on each call and
+ * freed before it returns.  Returns the status of a failing problem (and its
+ * infos entry says which) when any problem misses the tolerance. */
 fl_status fl_solve_batched(int nprob, const fl_op* ops, const double* const* f, const uint8_t* const* masks,
                            double tol, const fl_solve_opts* opts, double* const* u, fl_info* infos);
 
-/* Advance nprob problems by nsteps implicit steps each (zero forcing), all
- * problems per launch; dt[i] per problem; u[i] in/out (FP64). */
+/* Advance nprob problems by nsteps implicit theta steps each (Sec. 3.2, the
+ * same step as fl_step with zero forcing and no mask), every step one batched
+ * solve with warm start u^k.  dt[i] > 0 per problem; u[i] device FP64 in/out;
+ * theta in (0, 1].  infos[i]: iters and outer_iters summed over the steps,
+ * rel_res_true the largest over the steps. */
 fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const double* dt, double theta,
                           int nsteps, double tol, const fl_solve_opts* opts, fl_info* infos);
 

@@ -229,31 +229,56 @@ class Op:
         return u, info.as_dict()
 
 
-def solve_batched(ops, fs, tol=1e-10, opts=None, masks=None, us=None):
+def _batch_common(ops):
+    if not ops:
+        raise ValueError("a batch needs at least one problem")
+    st = ops[0].stream
+    if any(o.stream.cuda_stream != st.cuda_stream for o in ops):
+        raise ValueError("batched problems must share one stream: create their ops with the same stream=")
+    if any(o.d != ops[0].d for o in ops):
+        raise ValueError("batched problems must share the dimension d")
+    ops[0]._enter()
+    P = ctypes.c_void_p
+    return P, (P * len(ops))(*[o._h for o in ops])
+
+
+def solve_batched(ops, fs, tol=1e-10, opts=None, masks=None, us=None, check=True):
+    """Solve ops[i] u_i = fs[i] for every i, all problems per launch (FP64 in/out)."""
     lib = load()
     k = len(ops)
-    us = us or [torch.zeros_like(f) for f in fs]
-    P = ctypes.c_void_p
-    hops = (P * k)(*[o._h for o in ops])
-    for o in ops:
-        o._enter()
+    if len(fs) != k:
+        raise ValueError("one right-hand side per op")
+    for i, (o, f) in enumerate(zip(ops, fs)):
+        _need(f, torch.float64, o.N, f"f[{i}]")
+        if masks is not None:
+            _need(masks[i], torch.uint8, o.N, f"mask[{i}]")
+    us = us if us is not None else [torch.zeros_like(f) for f in fs]
+    for i, (o, u) in enumerate(zip(ops, us)):
+        _need(u, torch.float64, o.N, f"u[{i}]")
+    P, hops = _batch_common(ops)
     hf = (P * k)(*[f.data_ptr() for f in fs])
     hm = (P * k)(*[0 if (masks is None or masks[i] is None) else masks[i].data_ptr() for i in range(k)])
     hu = (P * k)(*[u.data_ptr() for u in us])
     infos = (Info * k)()
-    _check(lib.fl_solve_batched(k, hops, hf, hm, tol, ctypes.byref(opts or solve_opts()), hu, infos))
+    st = lib.fl_solve_batched(k, hops, hf, hm, tol, ctypes.byref(opts or solve_opts()), hu, infos)
+    if check:
+        _check(st)
     return us, [i.as_dict() for i in infos]
 
 
-def step_batched(ops, us, dts, theta=1.0, nsteps=1, tol=1e-10, opts=None):
+def step_batched(ops, us, dts, theta=1.0, nsteps=1, tol=1e-10, opts=None, check=True):
+    """Advance every problem by nsteps implicit theta steps (zero forcing), in place."""
     lib = load()
     k = len(ops)
-    P = ctypes.c_void_p
-    hops = (P * k)(*[o._h for o in ops])
-    for o in ops:
-        o._enter()
+    if len(us) != k or len(dts) != k:
+        raise ValueError("one state and one dt per op")
+    for i, (o, u) in enumerate(zip(ops, us)):
+        _need(u, torch.float64, o.N, f"u[{i}]")
+    P, hops = _batch_common(ops)
     hu = (P * k)(*[u.data_ptr() for u in us])
-    hdt = (ctypes.c_double * k)(*dts)
+    hdt = (ctypes.c_double * k)(*[float(v) for v in dts])
     infos = (Info * k)()
-    _check(lib.fl_step_batched(k, hops, hu, hdt, theta, nsteps, tol, ctypes.byref(opts or solve_opts()), infos))
+    st = lib.fl_step_batched(k, hops, hu, hdt, theta, nsteps, tol, ctypes.byref(opts or solve_opts()), infos)
+    if check:
+        _check(st)
     return us, [i.as_dict() for i in infos]

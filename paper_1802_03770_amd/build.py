@@ -27,6 +27,9 @@ UNITS = [
     ("fl_apply.hip", ["-DFL_T=double"]),
     ("fl_precond.hip", ["-DFL_T=float"]),
     ("fl_precond.hip", ["-DFL_T=double"]),
+    ("fl_batch.hip", ["-DFL_T=float"]),
+    ("fl_batch.hip", ["-DFL_T=double"]),
+    ("fl_batch.hip", ["-DFL_BATCH_HOST"]),
 ]
 
 

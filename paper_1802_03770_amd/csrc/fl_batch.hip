@@ -1,0 +1,623 @@
+// Batched Krylov driver: many problems (uneven grids, different alpha, or many
+// right-hand sides of one operator) advanced together.  Every kernel of an
+// iteration is a single launch over all problems (blockIdx.y = problem, each
+// problem with its own block count); a problem that has converged leaves its
+// blocks idle.  The iteration is captured once as a hipGraph and replayed;
+// the host polls one contiguous array of per-problem scalars.
+//
+// This file is compiled once per precision (FL_T) for the launch sequences,
+// and once with FL_BATCH_HOST for the C entry points.
+#include "fl_internal.hpp"
+#include "fl_batch.hpp"
+
+// ---------------------------------------------------------------------------
+// per-precision launch sequences
+// ---------------------------------------------------------------------------
+#ifndef FL_BATCH_HOST
+
+template <typename T> static size_t lds_fft(int L, int G) { return (size_t)G * Line<T>::stride(L) * sizeof(cx<T>); }
+
+template <typename T> fl_status bt_setup(BatchT& bt, const BatchDesc& B, const std::vector<Prob>& base) {
+  const int np = B.np, d = B.d;
+  bt.np = np;
+  bt.d = d;
+  bt.elem = sizeof(T);
+  auto mk = [&](std::vector<int>& nb) { nb.assign(np, 0); };
+  mk(bt.nb_rowfwd); mk(bt.nb_rowinv); mk(bt.nb_dstrow); mk(bt.nb_upd);
+  for (auto& v : bt.nb_col) mk(v);
+  for (auto& v : bt.nb_dcol) mk(v);
+  bt.cg.assign(3 * np, ColGeom{});
+  bt.dg.assign(2 * np, DGeom{});
+  bt.N.assign(np, 0);
+  bt.sm_row = bt.sm_dstrow = 0;
+  for (auto& s : bt.sm_col) s = 0;
+  for (auto& s : bt.sm_dcol) s = 0;
+  for (int p = 0; p < np; ++p) {
+    const Prob& pb = base[p];
+    const int* n = B.n[p].data();
+    long rows = 1, N = 1;
+    for (int a = 0; a < d - 1; ++a) rows *= n[a];
+    for (int a = 0; a < d; ++a) N *= n[a];
+    bt.N[p] = N;
+    bt.nb_upd[p] = (int)std::min<long>(2048, (N + 255) / 256);
+    const Axis& AL = pb.ax[d - 1];
+    long pairs = (rows + 1) / 2;
+    {
+      int G = 256 / AL.fft.tpl;
+      bt.nb_rowfwd[p] = bt.nb_rowinv[p] = (int)((pairs + G - 1) / G);
+      bt.sm_row = std::max(bt.sm_row, lds_fft<T>(AL.P, G));
+    }
+    if (d == 2) {
+      const long H1 = pb.ax[1].H, n0 = n[0];
+      ColGeom c = {0, (int)n0, (int)n0, H1, 1, H1, n0 * H1, H1, n0 * H1, 1, 1};
+      bt.cg[p] = c;
+    } else if (d == 3) {
+      const long n0 = n[0], n1 = n[1], P1 = pb.ax[1].P, H2 = pb.ax[2].H;
+      bt.cg[p] = ColGeom{1, (int)n1, (int)P1, H2, n0, H2, n1 * H2, H2, P1 * H2, 1, 2};
+      bt.cg[np + p] = ColGeom{0, (int)n0, (int)n0, P1 * H2, 1, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
+      bt.cg[2 * np + p] = ColGeom{1, (int)P1, (int)n1, H2, n0, H2, P1 * H2, H2, n1 * H2, 2, 1};
+    }
+    const int ncol = d == 3 ? 3 : (d == 2 ? 1 : 0);
+    for (int r = 0; r < ncol; ++r) {
+      const ColGeom& c = bt.cg[r * np + p];
+      const Axis& A = pb.ax[c.axis];
+      int G = 256 / A.fft.tpl;
+      bt.nb_col[r][p] = (int)(c.ngroup * ((c.gs + G - 1) / G));
+      bt.sm_col[r] = std::max(bt.sm_col[r], lds_fft<T>(A.P, G));
+    }
+    // sine transforms
+    {
+      const long rl = AL.dst_direct ? (rows + 1) / 2 : rows;
+      int G = 256 / AL.dst.tpl;
+      bt.nb_dstrow[p] = (int)((rl + G - 1) / G);
+      bt.sm_dstrow = std::max(bt.sm_dstrow, lds_fft<T>(AL.dst.L, G) * (AL.dst_direct ? 2 : 1));
+    }
+    if (d == 2) {
+      bt.dg[p] = DGeom{0, (long)n[1], 1, (long)n[1], (long)n[0] * n[1]};
+    } else if (d == 3) {
+      bt.dg[p] = DGeom{1, (long)n[2], (long)n[0], (long)n[2], (long)n[1] * n[2]};
+      bt.dg[np + p] = DGeom{0, (long)n[1] * n[2], 1, (long)n[1] * n[2], (long)n[0] * n[1] * n[2]};
+    }
+    const int ndc = d == 3 ? 2 : (d == 2 ? 1 : 0);
+    for (int r = 0; r < ndc; ++r) {
+      const DGeom& g = bt.dg[r * np + p];
+      const Axis& A = pb.ax[g.axis];
+      const int per = A.dst_direct ? 2 : 1;
+      int Gf = 256 / A.dst.tpl, G = Gf * per;
+      bt.nb_dcol[r][p] = (int)(g.ngroup * ((g.gs + G - 1) / G));
+      bt.sm_dcol[r] = std::max(bt.sm_dcol[r], lds_fft<T>(A.dst.L, Gf) * per);
+    }
+  }
+  return FL_OK;
+}
+
+static int vmax(const std::vector<int>& v) {
+  int m = 0;
+  for (int x : v) m = std::max(m, x);
+  return m;
+}
+
+// Batched operator application with prologue PRO / epilogue EPI over the Prob
+// array `pbs` (device).
+template <typename T, int PRO, int EPI> fl_status bt_apply(BatchT& bt, const Prob* pbs, Iter it, int chk,
+                                                          hipStream_t s) {
+  const int np = bt.np, d = bt.d;
+  if (d == 1) {
+    LAUNCH(k_conv1d_b<T, PRO, EPI>, dim3(vmax(bt.nb_rowfwd), np), dim3(256), bt.sm_row, s, pbs, it,
+           (const int*)bt.d_nb_rowfwd);
+    return FL_OK;
+  }
+  LAUNCH(k_rowfwd_b<T, PRO>, dim3(vmax(bt.nb_rowfwd), np), dim3(256), bt.sm_row, s, pbs, it,
+         (const int*)bt.d_nb_rowfwd);
+  if (d == 2) {
+    LAUNCH(k_colpass_b<T, COL_CONV>, dim3(vmax(bt.nb_col[0]), np), dim3(256), bt.sm_col[0], s, pbs,
+           (const ColGeom*)bt.d_cg, it, chk, (const int*)bt.d_nb_col[0]);
+  } else {
+    LAUNCH(k_colpass_b<T, COL_FWD>, dim3(vmax(bt.nb_col[0]), np), dim3(256), bt.sm_col[0], s, pbs,
+           (const ColGeom*)bt.d_cg, it, chk, (const int*)bt.d_nb_col[0]);
+    LAUNCH(k_colpass_b<T, COL_CONV>, dim3(vmax(bt.nb_col[1]), np), dim3(256), bt.sm_col[1], s, pbs,
+           (const ColGeom*)bt.d_cg + np, it, chk, (const int*)bt.d_nb_col[1]);
+    LAUNCH(k_colpass_b<T, COL_INV>, dim3(vmax(bt.nb_col[2]), np), dim3(256), bt.sm_col[2], s, pbs,
+           (const ColGeom*)bt.d_cg + 2 * np, it, chk, (const int*)bt.d_nb_col[2]);
+  }
+  LAUNCH(k_rowinv_b<T, EPI>, dim3(vmax(bt.nb_rowinv), np), dim3(256), bt.sm_row, s, pbs, it, chk,
+         (const int*)bt.d_nb_rowinv);
+  return FL_OK;
+}
+
+// Batched preconditioner.  pfirst: Prob array of the first pass (reads `in`,
+// writes `out` = T1); plast: Prob array of the last pass (reads `in` = T1).
+template <typename T, int DPRO, int DEPI> fl_status bt_precond(BatchT& bt, const Prob* pfirst, const Prob* plast,
+                                                              Iter it, int chk, hipStream_t s) {
+  const int np = bt.np, d = bt.d;
+  dim3 gr(vmax(bt.nb_dstrow), np);
+  if (d == 1) {
+    LAUNCH(k_dst_rows_b<T, DPRO, DEPI>, gr, dim3(256), bt.sm_dstrow, s, pfirst, it, chk, (const int*)bt.d_nb_dstrow);
+    return FL_OK;
+  }
+  LAUNCH(k_dst_rows_b<T, DPRO, DEPI_STORE>, gr, dim3(256), bt.sm_dstrow, s, pfirst, it, chk,
+         (const int*)bt.d_nb_dstrow);
+  if (d == 2) {
+    LAUNCH(k_dst_cols_b<T, true>, dim3(vmax(bt.nb_dcol[0]), np), dim3(256), bt.sm_dcol[0], s, plast,
+           (const DGeom*)bt.d_dg, chk, (const int*)bt.d_nb_dcol[0]);
+  } else {
+    LAUNCH(k_dst_cols_b<T, false>, dim3(vmax(bt.nb_dcol[0]), np), dim3(256), bt.sm_dcol[0], s, plast,
+           (const DGeom*)bt.d_dg, chk, (const int*)bt.d_nb_dcol[0]);
+    LAUNCH(k_dst_cols_b<T, true>, dim3(vmax(bt.nb_dcol[1]), np), dim3(256), bt.sm_dcol[1], s, plast,
+           (const DGeom*)bt.d_dg + np, chk, (const int*)bt.d_nb_dcol[1]);
+    LAUNCH(k_dst_cols_b<T, false>, dim3(vmax(bt.nb_dcol[0]), np), dim3(256), bt.sm_dcol[0], s, plast,
+           (const DGeom*)bt.d_dg, chk, (const int*)bt.d_nb_dcol[0]);
+  }
+  LAUNCH(k_dst_rows_b<T, DPRO_PLAIN, DEPI>, gr, dim3(256), bt.sm_dstrow, s, plast, it, chk,
+         (const int*)bt.d_nb_dstrow);
+  return FL_OK;
+}
+
+template <typename T> fl_status bt_iteration(BatchT& bt, int pc, int k, hipStream_t s) {
+  Iter it = {k & 1, k == 0 ? 1 : 0};
+  const Prob* pi = (const Prob*)bt.d_iter;
+  STCHK((bt_apply<T, PRO_PUPD, EPI_PQ>(bt, pc ? pi : (const Prob*)bt.d_iter_nopc, it, 1, s)));
+  if (pc) {
+    STCHK((bt_precond<T, DPRO_UPD, DEPI_Z>(bt, pi, pi, it, 1, s)));
+  } else {
+    LAUNCH(k_update_b<T>, dim3(vmax(bt.nb_upd), bt.np), dim3(256), 0, s, pi, it, (const long*)bt.d_N,
+           (const int*)bt.d_nb_upd);
+  }
+  return FL_OK;
+}
+
+template <typename T> fl_status bt_initial_precond(BatchT& bt, int pc, hipStream_t s) {
+  if (pc) {
+    STCHK((bt_precond<T, DPRO_PLAIN, DEPI_Z>(bt, (const Prob*)bt.d_pc0, (const Prob*)bt.d_iter, Iter{1, 0}, 0, s)));
+  }
+  return FL_OK;
+}
+
+template <typename T> fl_status bt_resid(BatchT& bt, const Prob* pbs, hipStream_t s) {
+  return bt_apply<T, PRO_PLAIN, EPI_RESID>(bt, pbs, Iter{0, 0}, 0, s);
+}
+
+template <typename T> fl_status bt_apply_plain(BatchT& bt, const Prob* pbs, hipStream_t s) {
+  return bt_apply<T, PRO_PLAIN, EPI_PLAIN>(bt, pbs, Iter{0, 0}, 0, s);
+}
+
+template fl_status bt_setup<FL_T>(BatchT&, const BatchDesc&, const std::vector<Prob>&);
+template fl_status bt_iteration<FL_T>(BatchT&, int, int, hipStream_t);
+template fl_status bt_initial_precond<FL_T>(BatchT&, int, hipStream_t);
+template fl_status bt_resid<FL_T>(BatchT&, const Prob*, hipStream_t);
+template fl_status bt_apply_plain<FL_T>(BatchT&, const Prob*, hipStream_t);
+
+#else  // FL_BATCH_HOST
+// ---------------------------------------------------------------------------
+// host logic and C entry points
+// ---------------------------------------------------------------------------
+
+struct ProbBufs {
+  void *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *f = nullptr;
+  void *W1 = nullptr, *W2 = nullptr, *T1 = nullptr;
+};
+
+struct Batch {
+  BatchDesc desc;
+  std::vector<fl_op> ops;
+  std::vector<ProbBufs> b64, b32;
+  Scalars* sc64 = nullptr;
+  Scalars* sc32 = nullptr;
+  double* part64 = nullptr;
+  double* part32 = nullptr;
+  long pstride = 0;
+  BatchT t64, t32;
+  std::vector<void*> owned;
+  std::vector<Scalars> hsc;
+  Scalars* hpin = nullptr;
+  hipGraphExec_t g[2] = {nullptr, nullptr};
+  int gpc[2] = {-1, -1};
+  ~Batch() {
+    for (void* p : owned) (void)hipFree(p);
+    for (auto& e : g) if (e) (void)hipGraphExecDestroy(e);
+    if (hpin) (void)hipHostFree(hpin);
+  }
+  fl_status alloc(void** p, size_t bytes) {
+    STCHK(dalloc(p, bytes));
+    owned.push_back(*p);
+    return FL_OK;
+  }
+};
+
+template <typename T> static fl_status alloc_bufs(Batch& bt, std::vector<ProbBufs>& bufs, bool with_f) {
+  const int np = bt.desc.np, d = bt.desc.d;
+  bufs.assign(np, ProbBufs{});
+  for (int p = 0; p < np; ++p) {
+    fl_op op = bt.ops[p];
+    const long N = op->N;
+    ProbBufs& b = bufs[p];
+    for (void** v : {&b.x, &b.r, &b.z, &b.p, &b.q}) STCHK(bt.alloc(v, N * sizeof(T)));
+    if (with_f) STCHK(bt.alloc(&b.f, N * sizeof(T)));
+    long rows = rows_of(op, 1);
+    STCHK(bt.alloc(&b.W1, (size_t)rows * op->H[d - 1] * sizeof(cx<T>)));
+    if (d == 3) STCHK(bt.alloc(&b.W2, (size_t)op->n[0] * op->P[1] * op->H[2] * sizeof(cx<T>)));
+    STCHK(bt.alloc(&b.T1, N * sizeof(T)));
+  }
+  return FL_OK;
+}
+
+template <typename T> static Prob make_prob(Batch& bt, int p, const ProbBufs& b, Scalars* sc, double* part,
+                                            double s0, double s1, double p0, double p1, const uint8_t* mask) {
+  Prob pb = base_prob<T>(bt.ops[p], 1);
+  pb.s0 = s0;
+  pb.s1 = s1;
+  pb.p0 = p0;
+  pb.p1 = p1;
+  pb.W1 = b.W1;
+  pb.W2 = b.W2;
+  pb.T1 = b.T1;
+  pb.mask = mask;
+  pb.x = b.x;
+  pb.r = b.r;
+  pb.z = b.z;
+  pb.p = b.p;
+  pb.q = b.q;
+  pb.sc = sc + p;
+  pb.part = part + (size_t)p * NSITE * bt.pstride;
+  pb.pstride = bt.pstride;
+  return pb;
+}
+
+static fl_status upload_vec(Batch& bt, const void* h, size_t bytes, void** d) {
+  STCHK(bt.alloc(d, bytes));
+  HIPCHK(hipMemcpy(*d, h, bytes, hipMemcpyHostToDevice));
+  return FL_OK;
+}
+
+// Device arrays of the launch geometry and of the Prob roles for one precision.
+template <typename T> static fl_status build_roles(Batch& bt, BatchT& t, std::vector<ProbBufs>& bufs, Scalars* sc,
+                                                   double* part, const std::vector<double>& s0,
+                                                   const std::vector<double>& s1, const std::vector<double>& p0,
+                                                   const std::vector<double>& p1, const uint8_t* const* masks) {
+  const int np = bt.desc.np;
+  std::vector<Prob> iter(np), iter_nopc(np), pc0(np), res(np);
+  for (int p = 0; p < np; ++p) {
+    const uint8_t* m = masks ? masks[p] : nullptr;
+    Prob pb = make_prob<T>(bt, p, bufs[p], sc, part, s0[p], s1[p], p0[p], p1[p], m);
+    iter[p] = pb;
+    iter[p].in = pb.T1;
+    iter[p].out = pb.T1;
+    iter_nopc[p] = pb;
+    iter_nopc[p].z = pb.r;  // z aliases r without a preconditioner
+    pc0[p] = pb;
+    pc0[p].in = pb.r;
+    pc0[p].out = pb.T1;
+    res[p] = pb;  // residual r = f - A x: in = x, aux = f, out = r
+    res[p].in = pb.x;
+    res[p].aux = bufs[p].f;
+    res[p].out = pb.r;
+  }
+  STCHK((bt_setup<T>(t, bt.desc, iter)));
+  STCHK(upload_vec(bt, iter.data(), np * sizeof(Prob), &t.d_iter));
+  STCHK(upload_vec(bt, iter_nopc.data(), np * sizeof(Prob), &t.d_iter_nopc));
+  STCHK(upload_vec(bt, pc0.data(), np * sizeof(Prob), &t.d_pc0));
+  STCHK(upload_vec(bt, res.data(), np * sizeof(Prob), &t.d_res));
+  t.h_iter = iter;
+  t.h_res = res;
+  STCHK(upload_vec(bt, t.cg.data(), t.cg.size() * sizeof(ColGeom), &t.d_cg));
+  STCHK(upload_vec(bt, t.dg.data(), t.dg.size() * sizeof(DGeom), &t.d_dg));
+  STCHK(upload_vec(bt, t.nb_rowfwd.data(), np * sizeof(int), &t.d_nb_rowfwd));
+  STCHK(upload_vec(bt, t.nb_rowinv.data(), np * sizeof(int), &t.d_nb_rowinv));
+  STCHK(upload_vec(bt, t.nb_dstrow.data(), np * sizeof(int), &t.d_nb_dstrow));
+  STCHK(upload_vec(bt, t.nb_upd.data(), np * sizeof(int), &t.d_nb_upd));
+  for (int r = 0; r < 3; ++r) STCHK(upload_vec(bt, t.nb_col[r].data(), np * sizeof(int), &t.d_nb_col[r]));
+  for (int r = 0; r < 2; ++r) STCHK(upload_vec(bt, t.nb_dcol[r].data(), np * sizeof(int), &t.d_nb_dcol[r]));
+  STCHK(upload_vec(bt, t.N.data(), np * sizeof(long), &t.d_N));
+  return FL_OK;
+}
+
+static fl_status read_all(Batch& bt, Scalars* dsc, hipStream_t s) {
+  const int np = bt.desc.np;
+  HIPCHK(hipMemcpyAsync(bt.hpin, dsc, np * sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  bt.hsc.assign(bt.hpin, bt.hpin + np);
+  return FL_OK;
+}
+
+// per-problem vector launches (setup and refinement; not in the iteration)
+template <typename T> static fl_status per_dot(Batch& bt, BatchT& t, int p, const void* a, const void* b, int target,
+                                               hipStream_t s) {
+  const Prob& pb = t.h_iter[p];
+  const long N = bt.ops[p]->N;
+  LAUNCH(k_dot<T>, dim3(std::min<long>(1024, nblocks_vec(N))), dim3(256), 0, s, pb, a, b, (int)S_DOT, N);
+  LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, pb, (int)S_DOT, target);
+  return FL_OK;
+}
+
+// Batched Krylov solve on precision T: r holds the initial residuals, x the
+// initial iterates, sc[p].ff the squared rhs norms (and sc[p].rr the squared
+// residual norms if use_rr).
+template <typename T> static fl_status bt_krylov(Batch& bt, BatchT& t, Scalars* dsc, int pc, double tol, int maxit,
+                                                 int use_rr, int graph, int poll, hipStream_t s, int gslot) {
+  const int np = bt.desc.np;
+  LAUNCH(k_init_b<>, dim3(1, np), dim3(64), 0, s, (const Prob*)t.d_iter, tol, maxit, use_rr);
+  if (pc) {
+    STCHK(bt_initial_precond<T>(t, pc, s));
+  } else {
+    for (int p = 0; p < np; ++p) {
+      const Prob& pb = t.h_iter[p];
+      const long N = bt.ops[p]->N;
+      LAUNCH(k_dot<T>, dim3(std::min<long>(1024, nblocks_vec(N))), dim3(256), 0, s, pb, (const void*)pb.r,
+             (const void*)pb.r, (int)S_RZ0, N);
+    }
+  }
+  if (poll <= 0) poll = 8;
+  if (poll & 1) ++poll;
+  STCHK(bt_iteration<T>(t, pc, 0, s));
+  bool use_graph = graph && s != nullptr;
+  if (use_graph && (!bt.g[gslot] || bt.gpc[gslot] != pc)) {
+    if (bt.g[gslot]) (void)hipGraphExecDestroy(bt.g[gslot]);
+    bt.g[gslot] = nullptr;
+    hipGraph_t g;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    fl_status st = FL_OK;
+    for (int j = 0; j < poll && st == FL_OK; ++j) st = bt_iteration<T>(t, pc, 1 + j, s);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != FL_OK) return st;
+    HIPCHK(e);
+    HIPCHK(hipGraphInstantiate(&bt.g[gslot], g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    bt.gpc[gslot] = pc;
+  }
+  int k = 1;
+  for (;;) {
+    STCHK(read_all(bt, dsc, s));
+    bool all = true;
+    int mx = 0;
+    for (auto& sc : bt.hsc) {
+      all = all && sc.done;
+      mx = std::max(mx, std::max(sc.itc[0], sc.itc[1]));
+    }
+    if (all) break;
+    if (mx >= maxit + 2 * poll) return fail(FL_E_HIP, "batched iteration bookkeeping lost");
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(bt.g[gslot], s));
+      k += poll;
+    } else {
+      for (int j = 0; j < poll; ++j, ++k) STCHK(bt_iteration<T>(t, pc, k, s));
+    }
+  }
+  return FL_OK;
+}
+
+// Build a batch (allocations, geometry, roles) for problems with the given
+// shifts (s0 I + s1 M, preconditioner p0 I + p1 pcs T).
+static fl_status make_batch(Batch& bt, int nprob, const fl_op* ops, const uint8_t* const* masks,
+                            const std::vector<double>& s1, const std::vector<double>& p1, double s0, double p0,
+                            bool mixed) {
+  if (nprob < 1 || !ops) return fail(FL_E_INVALID, "nprob must be >= 1");
+  const int d = ops[0]->d;
+  bt.desc.np = nprob;
+  bt.desc.d = d;
+  bt.desc.n.assign(nprob, {1, 1, 1});
+  bt.ops.assign(ops, ops + nprob);
+  hipStream_t s = ops[0]->stream;
+  long maxrows = 0;
+  for (int p = 0; p < nprob; ++p) {
+    if (!ops[p]) return fail(FL_E_INVALID, "NULL op in batch");
+    if (ops[p]->d != d) return fail(FL_E_UNSUPPORTED, "a batch must share the dimension d");
+    if (ops[p]->stream != s) return fail(FL_E_INVALID, "a batch must share one stream");
+    for (int a = 0; a < 3; ++a) bt.desc.n[p][a] = ops[p]->n[a];
+    maxrows = std::max(maxrows, rows_of(ops[p], 1));
+  }
+  bt.pstride = std::max<long>(4096, maxrows + 1);
+  STCHK(alloc_bufs<double>(bt, bt.b64, true));
+  STCHK(bt.alloc((void**)&bt.sc64, nprob * sizeof(Scalars)));
+  STCHK(bt.alloc((void**)&bt.part64, (size_t)nprob * NSITE * bt.pstride * sizeof(double)));
+  HIPCHK(hipMemset(bt.sc64, 0, nprob * sizeof(Scalars)));
+  std::vector<double> s0v(nprob, s0), p0v(nprob, p0);
+  STCHK(build_roles<double>(bt, bt.t64, bt.b64, bt.sc64, bt.part64, s0v, s1, p0v, p1, masks));
+  if (mixed) {
+    STCHK(alloc_bufs<float>(bt, bt.b32, false));
+    STCHK(bt.alloc((void**)&bt.sc32, nprob * sizeof(Scalars)));
+    STCHK(bt.alloc((void**)&bt.part32, (size_t)nprob * NSITE * bt.pstride * sizeof(double)));
+    HIPCHK(hipMemset(bt.sc32, 0, nprob * sizeof(Scalars)));
+    STCHK(build_roles<float>(bt, bt.t32, bt.b32, bt.sc32, bt.part32, s0v, s1, p0v, p1, masks));
+  }
+  if (hipHostMalloc((void**)&bt.hpin, nprob * sizeof(Scalars)) != hipSuccess) return fail(FL_E_NOMEM, "pinned");
+  return FL_OK;
+}
+
+// Solve A_p x_p = f_p for every problem: f in b64[p].f, x in b64[p].x (initial
+// guess when use_x0).  FP64 PCG, or FP32 PCG with FP64 refinement.
+static fl_status batch_solve(Batch& bt, double tol, const fl_solve_opts* o, int use_x0, std::vector<fl_info>& out) {
+  const int np = bt.desc.np;
+  hipStream_t s = bt.ops[0]->stream;
+  const int pc = o ? o->pc : FL_PC_FD;
+  const int mixed = o ? o->mixed : 0;
+  const int graph = o ? o->graph : 1;
+  const int poll = (o && o->poll_every > 0) ? o->poll_every : 8;
+  long Nmax = 0;
+  for (auto op : bt.ops) Nmax = std::max(Nmax, op->N);
+  const int maxit = (o && o->maxit > 0) ? o->maxit : std::max(1000, (int)(10 * std::sqrt((double)Nmax)));
+  out.assign(np, fl_info{});
+  // ff and initial residuals
+  for (int p = 0; p < np; ++p) {
+    ProbBufs& b = bt.b64[p];
+    const long N = bt.ops[p]->N;
+    if (!use_x0) LAUNCH(k_fill<double>, dim3(nblocks_vec(N)), dim3(256), 0, s, (double*)b.x, 0.0, N);
+    STCHK(per_dot<double>(bt, bt.t64, p, b.f, b.f, FIN_FF, s));
+  }
+  auto residuals = [&](std::vector<double>& rr) -> fl_status {
+    STCHK(bt_resid<double>(bt.t64, (const Prob*)bt.t64.d_res, s));
+    for (int p = 0; p < np; ++p) LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, bt.t64.h_iter[p], (int)S_DOT, (int)FIN_RR);
+    STCHK(read_all(bt, bt.sc64, s));
+    rr.resize(np);
+    for (int p = 0; p < np; ++p) rr[p] = bt.hsc[p].rr;
+    return FL_OK;
+  };
+  std::vector<double> rr, ff(np);
+  STCHK(read_all(bt, bt.sc64, s));
+  for (int p = 0; p < np; ++p) ff[p] = bt.hsc[p].ff;
+  if (!mixed) {
+    if (use_x0) {
+      STCHK(residuals(rr));
+    } else {
+      for (int p = 0; p < np; ++p)
+        HIPCHK(hipMemcpyAsync(bt.b64[p].r, bt.b64[p].f, bt.ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    STCHK(bt_krylov<double>(bt, bt.t64, bt.sc64, pc, tol, maxit, use_x0, graph, poll, s, 0));
+    for (int p = 0; p < np; ++p) {
+      const Scalars& sc = bt.hsc[p];
+      out[p].iters = std::max(sc.itc[0], sc.itc[1]);
+      out[p].rel_res_recur = ff[p] > 0 ? std::sqrt(sc.rr / ff[p]) : 0.0;
+      out[p].status = sc.done == 1 ? FL_OK : sc.done == 2 ? FL_E_NOCONV : FL_E_BREAKDOWN;
+    }
+  } else {
+    const double itol = (o && o->inner_tol > 0) ? o->inner_tol : 1e-4;
+    const int max_outer = (o && o->max_outer > 0) ? o->max_outer : 12;
+    std::vector<char> active(np, 1);
+    for (int p = 0; p < np; ++p) out[p].status = FL_E_NOCONV;
+    for (int outer = 0;; ++outer) {
+      STCHK(residuals(rr));
+      bool any = false;
+      for (int p = 0; p < np; ++p) {
+        if (!active[p]) continue;
+        if (ff[p] == 0.0 || std::sqrt(rr[p] / ff[p]) <= tol) {
+          active[p] = 0;
+          out[p].status = FL_OK;
+        } else if (!std::isfinite(rr[p])) {
+          active[p] = 0;
+          out[p].status = FL_E_BREAKDOWN;
+        } else {
+          any = true;
+        }
+      }
+      if (!any || outer >= max_outer) break;
+      // inner right-hand sides r32 = r64/||r64|| (zero for finished problems)
+      for (int p = 0; p < np; ++p) {
+        const long N = bt.ops[p]->N;
+        const double sc = active[p] ? 1.0 / std::sqrt(rr[p]) : 0.0;
+        LAUNCH((k_axpby<double, float>), dim3(nblocks_vec(N)), dim3(256), 0, s, (const double*)bt.b64[p].r,
+               (float*)bt.b32[p].r, sc, 0.0, N);
+        LAUNCH(k_fill<float>, dim3(nblocks_vec(N)), dim3(256), 0, s, (float*)bt.b32[p].x, 0.0f, N);
+        STCHK(per_dot<float>(bt, bt.t32, p, bt.b32[p].r, bt.b32[p].r, FIN_FF, s));
+        if (active[p]) out[p].outer_iters = outer + 1;
+      }
+      STCHK(bt_krylov<float>(bt, bt.t32, bt.sc32, pc, itol, maxit, 0, graph, poll, s, 1));
+      for (int p = 0; p < np; ++p) {
+        const Scalars& sc = bt.hsc[p];
+        if (!active[p]) continue;
+        out[p].iters += std::max(sc.itc[0], sc.itc[1]);
+        out[p].rel_res_recur = sc.ff > 0 ? std::sqrt(sc.rr / sc.ff) : 0.0;
+        const long N = bt.ops[p]->N;
+        LAUNCH((k_axpby<float, double>), dim3(nblocks_vec(N)), dim3(256), 0, s, (const float*)bt.b32[p].x,
+               (double*)bt.b64[p].x, std::sqrt(rr[p]), 1.0, N);
+      }
+    }
+  }
+  // true residuals (FP64) into q
+  {
+    std::vector<Prob> tr = bt.t64.h_res;
+    for (int p = 0; p < np; ++p) tr[p].out = bt.b64[p].q;
+    void* d;
+    STCHK(upload_vec(bt, tr.data(), np * sizeof(Prob), &d));
+    STCHK(bt_resid<double>(bt.t64, (const Prob*)d, s));
+    for (int p = 0; p < np; ++p) LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, bt.t64.h_iter[p], (int)S_DOT, (int)FIN_RR);
+    STCHK(read_all(bt, bt.sc64, s));
+    for (int p = 0; p < np; ++p) out[p].rel_res_true = ff[p] > 0 ? std::sqrt(bt.hsc[p].rr / ff[p]) : 0.0;
+  }
+  return FL_OK;
+}
+
+extern "C" {
+
+fl_status fl_solve_batched(int nprob, const fl_op* ops, const double* const* f, const uint8_t* const* masks,
+                           double tol, const fl_solve_opts* opts, double* const* u, fl_info* infos) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (nprob < 1 || !ops || !f || !u || !infos) return fail(FL_E_INVALID, "NULL argument");
+  if (!(tol > 0.0)) return fail(FL_E_INVALID, "tol must be positive");
+  for (int p = 0; p < nprob; ++p)
+    if (!ops[p] || !f[p] || !u[p]) return fail(FL_E_INVALID, "NULL problem entry");
+  Batch bt;
+  std::vector<double> s1(nprob, 1.0), p1(nprob, 1.0);
+  STCHK(make_batch(bt, nprob, ops, masks, s1, p1, 0.0, 0.0, opts && opts->mixed));
+  hipStream_t s = ops[0]->stream;
+  const int use_x0 = opts ? opts->use_x0 : 0;
+  for (int p = 0; p < nprob; ++p) {
+    HIPCHK(hipMemcpyAsync(bt.b64[p].f, f[p], ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (use_x0) HIPCHK(hipMemcpyAsync(bt.b64[p].x, u[p], ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  std::vector<fl_info> out;
+  STCHK(batch_solve(bt, tol, opts, use_x0, out));
+  for (int p = 0; p < nprob; ++p)
+    HIPCHK(hipMemcpyAsync(u[p], bt.b64[p].x, ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  fl_status worst = FL_OK;
+  for (int p = 0; p < nprob; ++p) {
+    infos[p] = out[p];
+    infos[p].ms = ms;
+    if (out[p].status != FL_OK) worst = (fl_status)out[p].status;
+  }
+  if (worst != FL_OK) return fail(worst, "a batched problem did not reach the tolerance");
+  return FL_OK;
+}
+
+fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const double* dt, double theta, int nsteps,
+                          double tol, const fl_solve_opts* opts, fl_info* infos) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (nprob < 1 || !ops || !u || !dt || !infos) return fail(FL_E_INVALID, "NULL argument");
+  if (!(theta > 0.0 && theta <= 1.0) || !(tol > 0.0) || nsteps < 0) return fail(FL_E_INVALID, "theta, tol or nsteps");
+  for (int p = 0; p < nprob; ++p)
+    if (!ops[p] || !u[p] || !(dt[p] > 0.0)) return fail(FL_E_INVALID, "bad problem entry");
+  Batch bt;
+  std::vector<double> s1(nprob), p1(nprob);
+  for (int p = 0; p < nprob; ++p) s1[p] = p1[p] = theta * dt[p];
+  STCHK(make_batch(bt, nprob, ops, nullptr, s1, p1, 1.0, 1.0, opts && opts->mixed));
+  hipStream_t s = ops[0]->stream;
+  // explicit part (I - (1-theta) dt M) u for theta < 1: a second role with that shift
+  std::vector<Prob> rhs;
+  void* d_rhs = nullptr;
+  if (theta < 1.0) {
+    rhs = bt.t64.h_res;
+    for (int p = 0; p < nprob; ++p) {
+      rhs[p].s0 = 1.0;
+      rhs[p].s1 = -(1.0 - theta) * dt[p];
+      rhs[p].in = bt.b64[p].x;
+      rhs[p].out = bt.b64[p].f;
+    }
+    STCHK(upload_vec(bt, rhs.data(), nprob * sizeof(Prob), &d_rhs));
+  }
+  for (int p = 0; p < nprob; ++p) {
+    HIPCHK(hipMemcpyAsync(bt.b64[p].x, u[p], ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    infos[p] = fl_info{};
+  }
+  fl_status worst = FL_OK;
+  for (int k = 0; k < nsteps; ++k) {
+    // right-hand side b = u^k (backward Euler) or (I - (1-theta) dt M) u^k; warm start x = u^k
+    if (theta < 1.0) {
+      STCHK(bt_apply_plain<double>(bt.t64, (const Prob*)d_rhs, s));
+    } else {
+      for (int p = 0; p < nprob; ++p)
+        HIPCHK(hipMemcpyAsync(bt.b64[p].f, bt.b64[p].x, ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    std::vector<fl_info> out;
+    STCHK(batch_solve(bt, tol, opts, 1, out));
+    for (int p = 0; p < nprob; ++p) {
+      infos[p].iters += out[p].iters;
+      infos[p].outer_iters += out[p].outer_iters;
+      infos[p].rel_res_true = std::max(infos[p].rel_res_true, out[p].rel_res_true);
+      infos[p].rel_res_recur = out[p].rel_res_recur;
+      if (out[p].status != FL_OK) {
+        infos[p].status = out[p].status;
+        worst = (fl_status)out[p].status;
+      }
+    }
+  }
+  for (int p = 0; p < nprob; ++p)
+    HIPCHK(hipMemcpyAsync(u[p], bt.b64[p].x, ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int p = 0; p < nprob; ++p) infos[p].ms = ms;
+  if (worst != FL_OK) return fail(worst, "a batched step did not reach the tolerance");
+  return FL_OK;
+}
+
+}  // extern "C"
+#endif  // FL_BATCH_HOST

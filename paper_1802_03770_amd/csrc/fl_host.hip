@@ -276,7 +276,7 @@ template <typename T> static fl_status krylov(fl_op op, const Prob& pb, int pc, 
                                               int use_rr, int graph, int poll, Scalars* out) {
   hipStream_t s = op->stream;
   Workspace& w = op->ws[tix<T>()];
-  LAUNCH(k_init, dim3(1), dim3(64), 0, s, pb, tol, maxit, use_rr);
+  LAUNCH(k_init<>, dim3(1), dim3(64), 0, s, pb, tol, maxit, use_rr);
   if (pc) {
     Prob p0 = pb;
     p0.in = pb.r;
@@ -346,7 +346,7 @@ static fl_status true_residual(fl_op op, const uint8_t* mask, double s0, double 
   pb.aux = b;
   pb.out = out;
   STCHK((apply_seq<double, PRO_PLAIN, EPI_RESID>(op, pb, Iter{0, 0}, 0)));
-  LAUNCH(k_finalize, dim3(1), dim3(256), 0, op->stream, pb, (int)S_DOT, (int)FIN_RR);
+  LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, op->stream, pb, (int)S_DOT, (int)FIN_RR);
   STCHK(read_scalars(op, w.sc));
   *rr = op->hsc->rr;
   return FL_OK;
@@ -370,7 +370,7 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
   // ff
   LAUNCH(k_dot<double>, dim3(std::min<long>(1024, nblocks_vec(N))), dim3(256), 0, s, pb, (const void*)w.f,
          (const void*)w.f, (int)S_DOT, N);
-  LAUNCH(k_finalize, dim3(1), dim3(256), 0, s, pb, (int)S_DOT, (int)FIN_FF);
+  LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, pb, (int)S_DOT, (int)FIN_FF);
   if (!use_x0) LAUNCH(k_fill<double>, dim3(nblocks_vec(N)), dim3(256), 0, s, (double*)w.x, 0.0, N);
   STCHK(read_scalars(op, w.sc));
   const double ff = op->hsc->ff;
@@ -418,7 +418,7 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
       LAUNCH(k_fill<float>, dim3(nblocks_vec(N)), dim3(256), 0, s, (float*)w32.x, 0.0f, N);
       LAUNCH(k_dot<float>, dim3(std::min<long>(1024, nblocks_vec(N))), dim3(256), 0, s, p32,
              (const void*)w32.r, (const void*)w32.r, (int)S_DOT, N);
-      LAUNCH(k_finalize, dim3(1), dim3(256), 0, s, p32, (int)S_DOT, (int)FIN_FF);
+      LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, p32, (int)S_DOT, (int)FIN_FF);
       Scalars res;
       STCHK(krylov<float>(op, p32, pc, itol, inner_cap, 0, graph, poll, &res));
       inf.iters += res.itc[0];
@@ -614,16 +614,6 @@ fl_status fl_step(fl_op op, double* u, double dt, double theta, const double* f_
   info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (info->status != FL_OK) return fail((fl_status)info->status, "step solve did not reach the tolerance");
   return FL_OK;
-}
-
-fl_status fl_solve_batched(int nprob, const fl_op* ops, const double* const* f, const uint8_t* const* masks, double tol,
-                           const fl_solve_opts* opts, double* const* u, fl_info* infos) {
-  return fail(FL_E_UNSUPPORTED, "batched solve not built yet");
-}
-
-fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const double* dt, double theta, int nsteps,
-                          double tol, const fl_solve_opts* opts, fl_info* infos) {
-  return fail(FL_E_UNSUPPORTED, "batched step not built yet");
 }
 
 fl_status fl_op_destroy(fl_op op) {

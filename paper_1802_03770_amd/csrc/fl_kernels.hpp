@@ -909,9 +909,11 @@ __global__ FL_BOUNDS void k_dst_cols_b(const Prob* pbs, const DGeom* dgs, int ch
 template <typename T> __global__ FL_BOUNDS void k_dot(Prob pb, const void* a, const void* b, int site, long n) {
   dot_body<T>(pb, a, b, site, n, gridDim.x, blockIdx.x);
 }
-#ifdef FL_MISC_KERNELS
-__global__ FL_BOUNDS void k_finalize(Prob pb, int site, int target) { finalize_body(pb, site, target); }
-#endif
+// (small solver kernels are templates so that every translation unit that
+// launches them carries its own instance)
+template <int = 0> __global__ FL_BOUNDS void k_finalize(Prob pb, int site, int target) {
+  finalize_body(pb, site, target);
+}
 template <typename T> __global__ FL_BOUNDS void k_update(Prob pb, Iter it, long n) {
   update_body<T>(pb, it, n, gridDim.x, blockIdx.x);
 }
@@ -919,11 +921,11 @@ template <typename T> __global__ FL_BOUNDS void k_update_b(const Prob* pbs, Iter
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
   update_body<T>(pbs[blockIdx.y], it, ns[blockIdx.y], nb[blockIdx.y], blockIdx.x);
 }
-#ifdef FL_MISC_KERNELS
-__global__ void k_init(Prob pb, double tol, int maxit, int use_rr) { init_body(pb, tol, maxit, use_rr); }
-__global__ void k_init_b(const Prob* pbs, double tol, int maxit, int use_rr) {
+template <int = 0> __global__ void k_init(Prob pb, double tol, int maxit, int use_rr) {
+  init_body(pb, tol, maxit, use_rr);
+}
+template <int = 0> __global__ void k_init_b(const Prob* pbs, double tol, int maxit, int use_rr) {
   init_body(pbs[blockIdx.y], tol, maxit, use_rr);
 }
-#endif
 
 }  // namespace fl
