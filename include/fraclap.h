@@ -55,8 +55,11 @@ typedef enum {
 typedef enum { FL_F64 = 0, FL_F32 = 1 } fl_dtype;
 
 typedef enum {
-  FL_PC_NONE = 0,  /* plain CG */
-  FL_PC_FD = 1     /* finite-difference Laplacian preconditioner (Sec. 3.1) */
+  FL_PC_NONE = 0,     /* plain CG */
+  FL_PC_FD = 1,       /* finite-difference Laplacian preconditioner (Sec. 3.1) */
+  FL_PC_SPECTRAL = 3  /* not in the paper: the sine basis of the FD preconditioner with the
+                         operator's own diagonal in that basis as eigenvalues, i.e. the best
+                         approximation of M diagonalised by the type-I sine transform */
 } fl_precond_kind;
 
 typedef struct {
@@ -104,7 +107,9 @@ fl_status fl_op_padded(fl_op op, int64_t* out);
 
 /* Device-to-device copy of the folded arrays, shape [P_1/2+1]...[P_d/2+1]:
  * which = 0: weights w_m (FP64, zero for m_k >= n_k); 1: symbol lambda (FP64);
- * 2: symbol lambda (FP32).  dst must hold prod(P_k/2+1) elements. */
+ * 2: symbol lambda (FP32).  dst must hold prod(P_k/2+1) elements.
+ * which = 3 / 4: the sine-basis diagonal tau (FP64 / FP32, shape [n_1]..[n_d],
+ * index k_a - 1; see fl_precond_spectral), prod(n_k) elements. */
 fl_status fl_op_export(fl_op op, int which, void* dst);
 
 /* Mu = M u for `batch` stacked inputs (dtype FL_F64 or FL_F32, both arrays of
@@ -120,6 +125,16 @@ fl_status fl_apply(fl_op op, const void* u, void* Mu, int dtype, int64_t batch, 
  * Paper Sec. 3.1 ("Preconditioning") and Sec. 3.2. */
 fl_status fl_precond(fl_op op, const void* r, void* z, int dtype, int64_t batch, const uint8_t* mask,
                      double p0, double p1);
+
+/* As fl_precond with the sine-basis diagonal of M in place of the FD
+ * Laplacian: z = (p0 I + p1 Q diag(tau) Q^T)^{-1} r, where Q is the
+ * orthonormal type-I sine transform on the box and tau_k = (Q^T M Q)_kk,
+ * computed once per op in FP64 (about 2 n^{d+1} flops) on first use.  Not in
+ * the paper: it keeps the paper's fast sine-transform solve (Sec. 3.1) and
+ * replaces the Laplacian's eigenvalues by the operator's own.  Same layout,
+ * masking and errors as fl_precond. */
+fl_status fl_precond_spectral(fl_op op, const void* r, void* z, int dtype, int64_t batch, const uint8_t* mask,
+                              double p0, double p1);
 
 /* Solve M u = f (FP64 f and u, single right-hand side) to relative residual
  * tol (recurrence residual in the loop; the true FP64 residual is reported).

@@ -15,11 +15,11 @@ LIB_PATH = os.path.join(_HERE, "libfraclap.so")
 
 FL_OK, FL_E_INVALID, FL_E_NOMEM, FL_E_HIP, FL_E_NOCONV, FL_E_BREAKDOWN, FL_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FL_F64, FL_F32 = 0, 1
-FL_PC_NONE, FL_PC_FD = 0, 1
+FL_PC_NONE, FL_PC_FD, FL_PC_SPECTRAL = 0, 1, 3
 STATUS_NAMES = {0: "ok", -1: "invalid", -2: "nomem", -3: "hip", -4: "noconv", -5: "breakdown", -6: "unsupported"}
 
 EXPORTED = ["fl_make_weights", "fl_op_constants", "fl_op_padded", "fl_op_export", "fl_apply", "fl_precond",
-            "fl_solve", "fl_step", "fl_solve_batched", "fl_step_batched", "fl_profile_pass", "fl_op_destroy",
+            "fl_precond_spectral", "fl_solve", "fl_step", "fl_solve_batched", "fl_step_batched", "fl_profile_pass", "fl_op_destroy",
             "fl_last_error"]
 
 
@@ -67,6 +67,7 @@ def load(path=LIB_PATH):
         "fl_op_export": [P, I, P],
         "fl_apply": [P, P, P, I, I64, P, D, D],
         "fl_precond": [P, P, P, I, I64, P, D, D],
+        "fl_precond_spectral": [P, P, P, I, I64, P, D, D],
         "fl_solve": [P, P, P, D, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(Info)],
         "fl_step": [P, P, D, D, P, P, P, D, ctypes.POINTER(SolveOpts), ctypes.POINTER(Info)],
         "fl_solve_batched": [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), D,
@@ -193,15 +194,27 @@ class Op:
         self._leave()
         return out
 
-    def precond(self, r, mask=None, p0=0.0, p1=1.0, out=None):
+    def precond(self, r, mask=None, p0=0.0, p1=1.0, out=None, kind=FL_PC_FD):
+        """z = (p0 I + p1 P)^{-1} r; P the FD Laplacian preconditioner or (kind =
+        FL_PC_SPECTRAL) the sine-basis diagonal of M."""
         dt = FL_F64 if r.dtype == torch.float64 else FL_F32
         _need(r, r.dtype, name="r")
         _need(mask, torch.uint8, self.N, "mask")
         out = torch.empty_like(r) if out is None else _need(out, r.dtype, r.numel(), "out")
+        fn = {FL_PC_FD: load().fl_precond, FL_PC_SPECTRAL: load().fl_precond_spectral}.get(kind)
+        if fn is None:
+            raise ValueError("kind must be FL_PC_FD or FL_PC_SPECTRAL")
         self._enter()
-        _check(load().fl_precond(self._h, _ptr(r), _ptr(out), dt, self._batch(r), _ptr(mask), p0, p1))
+        _check(fn(self._h, _ptr(r), _ptr(out), dt, self._batch(r), _ptr(mask), p0, p1))
         self._leave()
         return out
+
+    def tau(self, dtype=torch.float64):
+        """Sine-basis diagonal of M, shape n (index k - 1)."""
+        t = torch.empty(self.n, dtype=dtype, device="cuda")
+        _check(load().fl_op_export(self._h, 3 if dtype == torch.float64 else 4, _ptr(t)))
+        self.stream.synchronize()
+        return t
 
     def solve(self, f, mask=None, tol=1e-10, opts=None, u=None, check=True):
         _need(f, torch.float64, self.N, "f")

@@ -210,6 +210,7 @@ struct Batch {
   std::vector<void*> owned;
   std::vector<Scalars> hsc;
   Scalars* hpin = nullptr;
+  int pc = FL_PC_FD;
   hipGraphExec_t g[2] = {nullptr, nullptr};
   int gpc[2] = {-1, -1};
   ~Batch() {
@@ -244,6 +245,10 @@ template <typename T> static fl_status alloc_bufs(Batch& bt, std::vector<ProbBuf
 template <typename T> static Prob make_prob(Batch& bt, int p, const ProbBufs& b, Scalars* sc, double* part,
                                             double s0, double s1, double p0, double p1, const uint8_t* mask) {
   Prob pb = base_prob<T>(bt.ops[p], 1);
+  if (bt.pc == FL_PC_SPECTRAL) {  // table built in make_batch
+    pb.tau = bt.ops[p]->tau[tix<T>()];
+    pb.pcs = 1.0;
+  }
   pb.s0 = s0;
   pb.s1 = s1;
   pb.p0 = p0;
@@ -389,8 +394,15 @@ template <typename T> static fl_status bt_krylov(Batch& bt, BatchT& t, Scalars* 
 // shifts (s0 I + s1 M, preconditioner p0 I + p1 pcs T).
 static fl_status make_batch(Batch& bt, int nprob, const fl_op* ops, const uint8_t* const* masks,
                             const std::vector<double>& s1, const std::vector<double>& p1, double s0, double p0,
-                            bool mixed) {
+                            const fl_solve_opts* o) {
   if (nprob < 1 || !ops) return fail(FL_E_INVALID, "nprob must be >= 1");
+  const bool mixed = o && o->mixed;
+  bt.pc = o ? o->pc : FL_PC_FD;
+  if (bt.pc != FL_PC_NONE && bt.pc != FL_PC_FD && bt.pc != FL_PC_SPECTRAL)
+    return fail(FL_E_INVALID, "unknown preconditioner");
+  if (bt.pc == FL_PC_SPECTRAL)
+    for (int p = 0; p < nprob; ++p)
+      if (ops[p]) STCHK(build_tau(ops[p]));
   const int d = ops[0]->d;
   bt.desc.np = nprob;
   bt.desc.d = d;
@@ -536,7 +548,7 @@ fl_status fl_solve_batched(int nprob, const fl_op* ops, const double* const* f, 
     if (!ops[p] || !f[p] || !u[p]) return fail(FL_E_INVALID, "NULL problem entry");
   Batch bt;
   std::vector<double> s1(nprob, 1.0), p1(nprob, 1.0);
-  STCHK(make_batch(bt, nprob, ops, masks, s1, p1, 0.0, 0.0, opts && opts->mixed));
+  STCHK(make_batch(bt, nprob, ops, masks, s1, p1, 0.0, 0.0, opts));
   hipStream_t s = ops[0]->stream;
   const int use_x0 = opts ? opts->use_x0 : 0;
   for (int p = 0; p < nprob; ++p) {
@@ -569,7 +581,7 @@ fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const d
   Batch bt;
   std::vector<double> s1(nprob), p1(nprob);
   for (int p = 0; p < nprob; ++p) s1[p] = p1[p] = theta * dt[p];
-  STCHK(make_batch(bt, nprob, ops, nullptr, s1, p1, 1.0, 1.0, opts && opts->mixed));
+  STCHK(make_batch(bt, nprob, ops, nullptr, s1, p1, 1.0, 1.0, opts));
   hipStream_t s = ops[0]->stream;
   // explicit part (I - (1-theta) dt M) u for theta < 1: a second role with that shift
   std::vector<Prob> rhs;

@@ -246,6 +246,53 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
   return FL_OK;
 }
 
+// Sine-basis diagonal of M: tau_k = sum_m w_m prod_a G_a(k_a, m_a), one FP64
+// mode product per axis (w already carries C h^-alpha), then an FP32 copy.
+fl_status build_tau(fl_op op) {
+  if (op->tau[0]) return FL_OK;
+  hipStream_t s = op->stream;
+  const int d = op->d;
+  const long N = op->N;
+  void *X = nullptr, *Y = nullptr, *G = nullptr, *t32 = nullptr;
+  int nmax = 1;
+  for (int a = 0; a < d; ++a) nmax = std::max(nmax, op->n[a]);
+  STCHK(dalloc(&X, N * sizeof(double)));
+  op->tables.push_back(X);
+  STCHK(dalloc(&Y, N * sizeof(double)));
+  op->tables.push_back(Y);
+  STCHK(dalloc(&G, (size_t)nmax * nmax * sizeof(double)));
+  op->tables.push_back(G);
+  STCHK(dalloc(&t32, N * sizeof(float)));
+  op->tables.push_back(t32);
+  LAUNCH(k_weight_block, dim3(nblocks_vec(N)), dim3(256), 0, s, (const double*)op->wf, (double*)X, op->n[0],
+         op->n[1], op->n[2], op->H[1], op->H[2]);
+  for (int a = 0; a < d; ++a) {
+    const int na = op->n[a];
+    long Aa = 1, Ba = 1;
+    for (int b = 0; b < d; ++b) {
+      if (b < a) Aa *= op->n[b];
+      if (b > a) Ba *= op->n[b];
+    }
+    LAUNCH(k_sine_corr, dim3(nblocks_vec((long)na * na)), dim3(256), 0, s, (double*)G, na);
+    if (Ba > 1) {
+      // Y_i(k, j) = sum_m G(k, m) X_i(m, j), one product per leading index i
+      if (Aa > 65535) return fail(FL_E_UNSUPPORTED, "grid too large for the diagonal table");
+      LAUNCH(k_gemm_f64, dim3((Ba + 63) / 64, (na + 63) / 64, Aa), dim3(256), 0, s, na, (int)Ba, na,
+             (const double*)G, (long)na, 1L, 0L, (const double*)X, Ba, 1L, na * Ba, (double*)Y, Ba, 1L, na * Ba);
+    } else {
+      // last axis: Y(i, k) = sum_m X(i, m) G(k, m)
+      LAUNCH(k_gemm_f64, dim3((na + 63) / 64, (Aa + 63) / 64, 1), dim3(256), 0, s, (int)Aa, na, na,
+             (const double*)X, (long)na, 1L, 0L, (const double*)G, 1L, (long)na, 0L, (double*)Y, (long)na, 1L, 0L);
+    }
+    std::swap(X, Y);
+  }
+  LAUNCH(k_cast<float, double>, dim3(nblocks_vec(N)), dim3(256), 0, s, (const double*)X, (float*)t32, N, 1.0);
+  HIPCHK(hipStreamSynchronize(s));
+  op->tau[0] = X;
+  op->tau[1] = t32;
+  return FL_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Krylov drivers
 // ---------------------------------------------------------------------------
@@ -359,12 +406,14 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
   hipStream_t s = op->stream;
   const long N = op->N;
   const int pc = o ? o->pc : FL_PC_FD;
+  if (pc != FL_PC_NONE && pc != FL_PC_FD && pc != FL_PC_SPECTRAL) return fail(FL_E_INVALID, "unknown preconditioner");
   const int mixed = o ? o->mixed : 0;
   const int graph = o ? o->graph : 1;
   const int poll = (o && o->poll_every > 0) ? o->poll_every : 8;
   int maxit = (o && o->maxit > 0) ? o->maxit : std::max(1000, (int)(10 * std::sqrt((double)N)));
   Workspace& w = op->ws[0];
   Prob pb = solver_prob<double>(op, mask, s0, s1, p0, p1);
+  STCHK(set_precond<double>(op, pb, pc));
   fl_info inf;
   memset(&inf, 0, sizeof(inf));
   // ff
@@ -394,6 +443,7 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
     STCHK(ensure_ws<float>(op, 1, true));
     Workspace& w32 = op->ws[1];
     Prob p32 = solver_prob<float>(op, mask, s0, s1, p0, p1);
+    STCHK(set_precond<float>(op, p32, pc));
     const double itol = (o && o->inner_tol > 0) ? o->inner_tol : 1e-4;
     const int max_outer = (o && o->max_outer > 0) ? o->max_outer : 12;
     int inner_cap = (o && o->maxit > 0) ? o->maxit : std::max(1000, (int)(10 * std::sqrt((double)N)));
@@ -462,10 +512,12 @@ static fl_status apply_t(fl_op op, const void* u, void* Mu, long batch, const ui
 }
 
 template <typename T>
-static fl_status precond_t(fl_op op, const void* r, void* z, long batch, const uint8_t* mask, double p0, double p1) {
+static fl_status precond_t(fl_op op, const void* r, void* z, long batch, const uint8_t* mask, double p0, double p1,
+                           int kind) {
   STCHK(ensure_ws<T>(op, batch, false));
   Workspace& w = op->ws[tix<T>()];
   Prob pb = base_prob<T>(op, batch);
+  STCHK(set_precond<T>(op, pb, kind));
   pb.p0 = p0;
   pb.p1 = p1;
   pb.in = r;
@@ -544,8 +596,14 @@ fl_status fl_op_padded(fl_op op, int64_t* out) {
 
 fl_status fl_op_export(fl_op op, int which, void* dst) {
   if (!op || !dst) return fail(FL_E_INVALID, "NULL argument");
+  if (which == 3 || which == 4) {
+    STCHK(build_tau(op));
+    HIPCHK(hipMemcpyAsync(dst, op->tau[which - 3], op->N * (which == 4 ? sizeof(float) : sizeof(double)),
+                          hipMemcpyDeviceToDevice, op->stream));
+    return FL_OK;
+  }
   const void* src = which == 0 ? (const void*)op->wf : which == 1 ? op->lam[0] : which == 2 ? op->lam[1] : nullptr;
-  if (!src) return fail(FL_E_INVALID, "which must be 0, 1 or 2");
+  if (!src) return fail(FL_E_INVALID, "which must be 0..4");
   size_t b = op->NH * (which == 2 ? sizeof(float) : sizeof(double));
   HIPCHK(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, op->stream));
   return FL_OK;
@@ -564,8 +622,17 @@ fl_status fl_precond(fl_op op, const void* r, void* z, int dtype, int64_t batch,
                      double p1) {
   if (!op || !r || !z) return fail(FL_E_INVALID, "NULL argument");
   if (batch < 1) return fail(FL_E_INVALID, "batch must be >= 1");
-  if (dtype == FL_F64) return precond_t<double>(op, r, z, batch, mask, p0, p1);
-  if (dtype == FL_F32) return precond_t<float>(op, r, z, batch, mask, p0, p1);
+  if (dtype == FL_F64) return precond_t<double>(op, r, z, batch, mask, p0, p1, FL_PC_FD);
+  if (dtype == FL_F32) return precond_t<float>(op, r, z, batch, mask, p0, p1, FL_PC_FD);
+  return fail(FL_E_INVALID, "dtype must be FL_F64 or FL_F32");
+}
+
+fl_status fl_precond_spectral(fl_op op, const void* r, void* z, int dtype, int64_t batch, const uint8_t* mask, double p0,
+                     double p1) {
+  if (!op || !r || !z) return fail(FL_E_INVALID, "NULL argument");
+  if (batch < 1) return fail(FL_E_INVALID, "batch must be >= 1");
+  if (dtype == FL_F64) return precond_t<double>(op, r, z, batch, mask, p0, p1, FL_PC_SPECTRAL);
+  if (dtype == FL_F32) return precond_t<float>(op, r, z, batch, mask, p0, p1, FL_PC_SPECTRAL);
   return fail(FL_E_INVALID, "dtype must be FL_F64 or FL_F32");
 }
 

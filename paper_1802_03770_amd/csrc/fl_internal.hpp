@@ -76,6 +76,7 @@ struct fl_op_s {
   double* d_cst = nullptr;
   double* wf = nullptr;     // folded weights [H...] FP64
   void* lam[2] = {nullptr, nullptr};  // folded symbol FP64 / FP32
+  void* tau[2] = {nullptr, nullptr};  // sine-basis diagonal [n...] FP64 / FP32 (built on first use)
   Axis ax[2][3];            // per dtype
   std::vector<void*> tables;
   Workspace ws[2];
@@ -191,6 +192,22 @@ template <typename T> inline Prob solver_prob(fl_op op, const uint8_t* mask, dou
 }
 
 inline long nblocks_vec(long n) { return (n + 255) / 256; }
+
+// Sine-basis diagonal table of the operator (built once per op, in fl_host.hip).
+fl_status build_tau(fl_op op);
+
+// Select the preconditioner of a solver Prob: the FD Laplacian keeps pcs =
+// C|B|h^-alpha; the sine-basis diagonal sets the table and pcs = 1.
+template <typename T> inline fl_status set_precond(fl_op op, Prob& pb, int pc) {
+  if (pc == FL_PC_SPECTRAL) {
+    STCHK(build_tau(op));
+    pb.tau = op->tau[tix<T>()];
+    pb.pcs = 1.0;
+  } else {
+    pb.tau = nullptr;
+  }
+  return FL_OK;
+}
 
 // Launch sequences (defined per precision in fl_apply.hip / fl_precond.hip).
 template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob& pb, Iter it, int chk);

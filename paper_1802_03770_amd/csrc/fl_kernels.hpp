@@ -232,6 +232,76 @@ __global__ __launch_bounds__(256) void k_dct1_axis(double* wf, int H, int P, lon
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sine-basis diagonal of the operator (FP64): m_k = sum_m w_m prod_a G_a(k_a, m_a)
+// ---------------------------------------------------------------------------
+// G(k, m) = c_m sum_{i=1}^{n-m} q_k(i) q_k(i+m) with the orthonormal sine
+// vectors q_k, in closed form; row k-1, column m; c_0 = 1, c_m = 2.
+__global__ void k_sine_corr(double* G, int n) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)n * n) return;
+  const int k = (int)(idx / n) + 1, m = (int)(idx % n);
+  const double th = M_PI * k / (n + 1);
+  const double sgn = (k & 1) ? -1.0 : 1.0;  // cos((n+1) theta) = (-1)^k
+  const double sm = 0.5 * ((n - m) * cos(m * th) - sgn * sin((n - m) * th) / sin(th));
+  G[idx] = (2.0 / (n + 1)) * sm * (m == 0 ? 1.0 : 2.0);
+}
+
+// X[i0][i1][i2] = wf[i0][i1][i2] on the n-block of the folded [H0][H1][H2] weights.
+__global__ void k_weight_block(const double* wf, double* X, int n0, int n1, int n2, int H1, int H2) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long N = (long)n0 * n1 * n2;
+  if (idx >= N) return;
+  const int i2 = (int)(idx % n2);
+  const long t = idx / n2;
+  const int i1 = (int)(t % n1), i0 = (int)(t / n1);
+  X[idx] = wf[((long)i0 * H1 + i1) * H2 + i2];
+}
+
+// Strided batched FP64 product C_b[i][j] = sum_m A_b[i][m] B_b[m][j] (64 x 64
+// output tile per block, fixed summation order).
+__global__ __launch_bounds__(256) void k_gemm_f64(int M, int N, int K, const double* A, long sai, long sam, long sab,
+                                                  const double* B, long sbm, long sbj, long sbb, double* C, long sci,
+                                                  long scj, long scb) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  A += blockIdx.z * sab;
+  B += blockIdx.z * sbb;
+  C += blockIdx.z * scb;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int r = e / 16, ka = e % 16;
+      As[ka][r] = (i0 + r < M && k0 + ka < K) ? A[(long)(i0 + r) * sai + (long)(k0 + ka) * sam] : 0.0;
+      const int c = e % 64, kb = e / 64;
+      Bs[kb][c] = (k0 + kb < K && j0 + c < N) ? B[(long)(k0 + kb) * sbm + (long)(j0 + c) * sbj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[kk][ty + 16 * q];
+        b[q] = Bs[kk][tx + 16 * q];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + ty + 16 * p, j = j0 + tx + 16 * q;
+      if (i < M && j < N) C[(long)i * sci + (long)j * scj] = acc[p][q];
+    }
+}
 #endif  // FL_MISC_KERNELS
 
 template <typename TO, typename TI>
@@ -621,9 +691,10 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   if (pb.d == 1) {
     const T* ev = (const T*)A.eig;
     if (direct) {
+      const T* tau = (const T*)pb.tau;
       for (int k = lane + 1; k <= n; k += tpl) {
         cx<T> sv = sine_pair_get(res, k);
-        T e = (T)(pb.p0 + pb.p1 * pb.pcs * (double)ev[k - 1]);
+        T e = (T)(pb.p0 + pb.p1 * pb.pcs * (double)(tau ? tau[k - 1] : ev[k - 1]));
         sine_pair_put(res, Lf, k, sv.x / e, sv.y / e);
       }
       if (lane == 0) {
@@ -633,8 +704,9 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
       __syncthreads();
       res = fft_line_wide<T, false>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
     } else {
+      const T* tau = (const T*)pb.tau;
       for (int k = lane; k < n; k += tpl)
-        buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * (double)ev[k]);
+        buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * (double)(tau ? tau[k] : ev[k]));
       __syncthreads();
       dst_line<T>(buf, A, lane, tpl);
     }
@@ -723,15 +795,26 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   if (direct) res = fft_line_wide<T, false>(buf, buf2, A.dst, lane); else dst_line<T>(buf, A, lane, tpl);
   if (SCALE) {
     const T* ev = (const T*)A.eig;
+    // sine-basis diagonal: mode (k, c) of the axis-0 pass is table entry (k-1) gs + c
+    const T* tau = (const T*)pb.tau;
     if (direct) {
       const long ca = c0 + 2 * g, cb = ca + 1;
-      const double ta = ca < dg.gs ? eig_tail<T>(pb, ca) : 0.0;
-      const double tb = cb < dg.gs ? eig_tail<T>(pb, cb) : 0.0;
+      const bool oka = ca < dg.gs, okb = cb < dg.gs;
+      const double ta = (oka && !tau) ? eig_tail<T>(pb, ca) : 0.0;
+      const double tb = (okb && !tau) ? eig_tail<T>(pb, cb) : 0.0;
       for (int k = lane + 1; k <= n; k += tpl) {
         cx<T> sv = sine_pair_get(res, k);
-        const double ek = (double)ev[k - 1];
-        T ea = (T)(pb.p0 + pb.p1 * pb.pcs * (ek + ta));
-        T eb = (T)(pb.p0 + pb.p1 * pb.pcs * (ek + tb));
+        double la, lb;
+        if (tau) {
+          la = oka ? (double)tau[(long)(k - 1) * dg.gs + ca] : 1.0;
+          lb = okb ? (double)tau[(long)(k - 1) * dg.gs + cb] : 1.0;
+        } else {
+          const double ek = (double)ev[k - 1];
+          la = ek + ta;
+          lb = ek + tb;
+        }
+        T ea = (T)(pb.p0 + pb.p1 * pb.pcs * la);
+        T eb = (T)(pb.p0 + pb.p1 * pb.pcs * lb);
         sine_pair_put(res, Lf, k, sv.x / ea, sv.y / eb);
       }
       if (lane == 0) {
@@ -742,9 +825,12 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
       res = fft_line_wide<T, false>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
     } else {
       const long c = c0 + g;
-      const double etail = c < dg.gs ? eig_tail<T>(pb, c) : 0.0;
-      for (int k = lane; k < n; k += tpl)
-        buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * ((double)ev[k] + etail));
+      const bool ok = c < dg.gs;
+      const double etail = (ok && !tau) ? eig_tail<T>(pb, c) : 0.0;
+      for (int k = lane; k < n; k += tpl) {
+        const double lv = tau ? (ok ? (double)tau[(long)k * dg.gs + c] : 1.0) : (double)ev[k] + etail;
+        buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * lv);
+      }
       __syncthreads();
       dst_line<T>(buf, A, lane, tpl);
     }

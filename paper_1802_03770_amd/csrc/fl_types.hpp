@@ -55,8 +55,10 @@ struct Prob {
   Axis ax[3];
   const void* lam;  // folded symbol, T, shape [H_0][H_1]...  (P_a/2+1 per axis)
   double s0, s1;    // operator symbol is s0 + s1 * lambda  (identity shift for time steps)
-  double pcs;       // C |B| h^-alpha
-  double p0, p1;    // preconditioner eigenvalue p0 + p1 * pcs * sum_a eig_a
+  double pcs;       // C |B| h^-alpha (FD Laplacian) or 1 (sine-basis diagonal)
+  double p0, p1;    // preconditioner eigenvalue p0 + p1 * pcs * (sum_a eig_a  or  tau[k])
+  const void* tau;  // null: FD Laplacian eigenvalues; else the operator's own diagonal in the
+                    // sine basis, T, [n_0][n_1][n_2] indexed by k_a - 1
   // buffers
   const void* in;   // real input  [nrhs][n...]
   void* out;        // real output
