@@ -71,6 +71,8 @@ def main():
         "fp64_cg": fl.solve_opts(pc=fl.FL_PC_NONE, mixed=0),
         "f32_pcg": fl.solve_opts(pc=fl.FL_PC_FD, mixed=1),
         "f32_cg": fl.solve_opts(pc=fl.FL_PC_NONE, mixed=1),
+        "fp64_spectral": fl.solve_opts(pc=fl.FL_PC_SPECTRAL, mixed=0),
+        "f32_spectral": fl.solve_opts(pc=fl.FL_PC_SPECTRAL, mixed=1),
     }
     if args.only:
         configs = {k: v for k, v in configs.items() if k in args.only.split(",")}
