@@ -41,6 +41,7 @@ extern "C" {
 #endif
 
 typedef struct fl_op_s* fl_op;
+typedef struct fl_net_s* fl_net;
 
 typedef enum {
   FL_OK = 0,
@@ -57,6 +58,9 @@ typedef enum { FL_F64 = 0, FL_F32 = 1 } fl_dtype;
 typedef enum {
   FL_PC_NONE = 0,     /* plain CG */
   FL_PC_FD = 1,       /* finite-difference Laplacian preconditioner (Sec. 3.1) */
+  FL_PC_LEARNED = 2,  /* not in the paper: flexible CG with z = B (r + s N(r/s, alpha)), N the network
+                         opts->net, B the FL_PC_SPECTRAL inverse, s = RMS(r); the FD preconditioner is the
+                         fallback (d = 2, no mask) */
   FL_PC_SPECTRAL = 3  /* not in the paper: the sine basis of the FD preconditioner with the
                          operator's own diagonal in that basis as eigenvalues, i.e. the best
                          approximation of M diagonalised by the type-I sine transform */
@@ -76,13 +80,14 @@ typedef struct {
   int graph;         /* 1: replay the Krylov iteration as a captured hipGraph */
   int poll_every;    /* iterations between host polls of the convergence flag (<= 0 -> 8) */
   int max_outer;     /* mixed: cap on refinement steps (<= 0 -> 12) */
+  fl_net net;        /* FL_PC_LEARNED: the trained network (same stream as the op); else ignored */
 } fl_solve_opts;
 
 typedef struct {
   int iters;         /* Krylov iterations (sum over inner solves when mixed) */
   int outer_iters;   /* refinement steps (mixed) */
   int status;        /* fl_status of the solve */
-  int reserved;
+  int fell_back;     /* FL_PC_LEARNED: 1 if the FD preconditioner took over in some inner solve */
   double rel_res_true;   /* ||f - M u||_2 / ||f||_2 recomputed in FP64 at exit */
   double rel_res_recur;  /* last recurrence residual of the (inner) Krylov loop */
   double ms;             /* wall time of the call, milliseconds */
@@ -179,6 +184,46 @@ fl_status fl_solve_batched(int nprob, const fl_op* ops, const double* const* f, 
  * rel_res_true the largest over the steps. */
 fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const double* dt, double theta,
                           int nsteps, double tol, const fl_solve_opts* opts, fl_info* infos);
+
+/* ---- learned preconditioner (not in the paper) ----
+ * A multilevel convolutional network N(x, alpha) on an H x W grid (H, W
+ * multiples of 8): 3x3 convolutions with 32 channels on 4 levels (2x2 average
+ * pooling, nearest upsampling, additive skips, ReLU), BF16 activations with
+ * FP32 accumulation, FP32 master parameters.  Parameter vector (FP32,
+ * fl_net_nparams() entries): per layer W[tap = 3 ky + kx][ci][co] then b[co],
+ * layers cin (2 -> 32; input channels x and alpha - 1), d1, d2, d3, b3, u2,
+ * u1, u0 (32 -> 32), out (32 -> 1).  Inside flexible CG (FL_PC_LEARNED) the
+ * preconditioner is z = B (r + s N(r/s, alpha)), B the FL_PC_SPECTRAL inverse
+ * and s the RMS of r.  All arrays are device arrays on the net's stream. */
+
+/* New network with zero parameters (call fl_net_set_params before use). */
+fl_status fl_net_create(void* hip_stream, fl_net* out);
+/* Number of FP32 parameters. */
+int64_t fl_net_nparams(void);
+/* Copy in / out the FP32 parameter vector; set also clears the Adam moments. */
+fl_status fl_net_set_params(fl_net net, const float* params);
+fl_status fl_net_get_params(fl_net net, float* params);
+/* y = N(x, alpha[b]) for batch images x[b] (FP32 [batch][H][W]); alpha is a
+ * host array of batch values. */
+fl_status fl_net_forward(fl_net net, const float* x, const double* alpha, float* y, int batch, int H, int W);
+/* grad = d/dtheta sum(gy * N(x, alpha)) (FP32, fl_net_nparams() entries). */
+fl_status fl_net_grad(fl_net net, const float* x, const double* alpha, const float* gy, float* grad, int batch,
+                      int H, int W);
+/* `steps` Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the loss
+ * mean over the minibatch of ||N(R_i, A_i) - T_i||^2 / (H W); minibatch k
+ * takes pairs idx[k*batch .. k*batch+batch-1] (host array, each < npairs).
+ * R, T: FP32 [npairs][H][W]; A: FP32 [npairs] (device).  losses (host,
+ * `steps` entries) receives the loss of each minibatch before its update. */
+fl_status fl_net_train(fl_net net, const float* R, const float* T, const float* A, int npairs, int H, int W,
+                       const int* idx, int steps, int batch, double lr, float* losses);
+/* Training pairs from errors e_k = e[k * e_stride] - e_sub[k] (FP64 grids of
+ * the op, d = 2; e_stride 0 repeats one array, e_sub may be NULL): r = M e,
+ * s = RMS(r), R = r / s and T = (D e - r) / s with D = Q diag(tau) Q^T (the
+ * operator diagonal in the sine basis), written zero-padded into the
+ * Hp x Wp grid (R, T: FP32 [count][Hp][Wp], Hp >= n_0, Wp >= n_1). */
+fl_status fl_learned_pairs(fl_op op, const double* e, int64_t e_stride, const double* e_sub, int count, float* R,
+                           float* T, int Hp, int Wp);
+fl_status fl_net_destroy(fl_net net);
 
 /* Measurement aid: average duration (ms, HIP events on the op's stream) of
  * `reps` back-to-back launches of one pass on the op's zero-filled workspace.

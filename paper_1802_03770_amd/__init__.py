@@ -15,12 +15,13 @@ LIB_PATH = os.path.join(_HERE, "libfraclap.so")
 
 FL_OK, FL_E_INVALID, FL_E_NOMEM, FL_E_HIP, FL_E_NOCONV, FL_E_BREAKDOWN, FL_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FL_F64, FL_F32 = 0, 1
-FL_PC_NONE, FL_PC_FD, FL_PC_SPECTRAL = 0, 1, 3
+FL_PC_NONE, FL_PC_FD, FL_PC_LEARNED, FL_PC_SPECTRAL = 0, 1, 2, 3
 STATUS_NAMES = {0: "ok", -1: "invalid", -2: "nomem", -3: "hip", -4: "noconv", -5: "breakdown", -6: "unsupported"}
 
 EXPORTED = ["fl_make_weights", "fl_op_constants", "fl_op_padded", "fl_op_export", "fl_apply", "fl_precond",
             "fl_precond_spectral", "fl_solve", "fl_step", "fl_solve_batched", "fl_step_batched", "fl_profile_pass", "fl_op_destroy",
-            "fl_last_error"]
+            "fl_last_error", "fl_net_create", "fl_net_nparams", "fl_net_set_params", "fl_net_get_params",
+            "fl_net_forward", "fl_net_grad", "fl_net_train", "fl_learned_pairs", "fl_net_destroy"]
 
 
 class FlError(RuntimeError):
@@ -36,16 +37,16 @@ class WeightsOpts(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("pc", ctypes.c_int), ("mixed", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("use_x0", ctypes.c_int), ("graph", ctypes.c_int),
-                ("poll_every", ctypes.c_int), ("max_outer", ctypes.c_int)]
+                ("poll_every", ctypes.c_int), ("max_outer", ctypes.c_int), ("net", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
-                ("reserved", ctypes.c_int), ("rel_res_true", ctypes.c_double),
+                ("fell_back", ctypes.c_int), ("rel_res_true", ctypes.c_double),
                 ("rel_res_recur", ctypes.c_double), ("ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -77,11 +78,20 @@ def load(path=LIB_PATH):
         "fl_profile_pass": [P, I, I, I, ctypes.POINTER(D)],
         "fl_op_destroy": [P],
         "fl_last_error": [],
+        "fl_net_create": [P, ctypes.POINTER(P)],
+        "fl_net_nparams": [],
+        "fl_net_set_params": [P, P],
+        "fl_net_get_params": [P, P],
+        "fl_net_forward": [P, P, ctypes.POINTER(D), P, I, I, I],
+        "fl_net_grad": [P, P, ctypes.POINTER(D), P, P, I, I, I],
+        "fl_net_train": [P, P, P, P, I, I, I, ctypes.POINTER(I), I, I, D, ctypes.POINTER(ctypes.c_float)],
+        "fl_learned_pairs": [P, P, I64, P, I, P, P, I, I],
+        "fl_net_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
-        fn.restype = ctypes.c_char_p if name == "fl_last_error" else ctypes.c_int
+        fn.restype = {"fl_last_error": ctypes.c_char_p, "fl_net_nparams": ctypes.c_int64}.get(name, ctypes.c_int)
     _lib = lib
     return lib
 
@@ -109,8 +119,14 @@ def _need(t, dtype, numel=None, name="tensor"):
     return t
 
 
-def solve_opts(pc=FL_PC_FD, mixed=0, maxit=0, inner_tol=0.0, use_x0=0, graph=1, poll_every=8, max_outer=0):
-    return SolveOpts(pc, mixed, maxit, inner_tol, use_x0, graph, poll_every, max_outer)
+def solve_opts(pc=FL_PC_FD, mixed=0, maxit=0, inner_tol=0.0, use_x0=0, graph=1, poll_every=8, max_outer=0,
+               net=None):
+    """Solver options; net is a Net (needed for pc=FL_PC_LEARNED)."""
+    o = SolveOpts(pc, mixed, maxit, inner_tol, use_x0, graph, poll_every, max_outer, None)
+    if net is not None:
+        o.net = net._h.value
+        o._keep = net  # keep the network alive as long as the options
+    return o
 
 
 class Op:
@@ -295,3 +311,110 @@ def step_batched(ops, us, dts, theta=1.0, nsteps=1, tol=1e-10, opts=None, check=
     if check:
         _check(st)
     return us, [i.as_dict() for i in infos]
+
+
+class Net:
+    """fl_net handle: the learned preconditioner's network (parameters on the device)."""
+
+    def __init__(self, stream=None, params=None):
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.Stream()
+        self.stream = stream
+        h_ = ctypes.c_void_p()
+        _check(lib.fl_net_create(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h_)))
+        self._h = h_
+        self.nparams = int(lib.fl_net_nparams())
+        if params is not None:
+            self.set_params(params)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().fl_net_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream())
+
+    def _leave(self):
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def set_params(self, params):
+        p = torch.as_tensor(params, dtype=torch.float32).to("cuda").contiguous()
+        _need(p, torch.float32, self.nparams, "params")
+        self._enter()
+        _check(load().fl_net_set_params(self._h, _ptr(p)))
+
+    def get_params(self):
+        p = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        self._enter()
+        _check(load().fl_net_get_params(self._h, _ptr(p)))
+        return p
+
+    def forward(self, x, alpha):
+        """y = N(x, alpha) for x FP32 [B, H, W] (device); alpha: float or list of B floats."""
+        _need(x, torch.float32, name="x")
+        if x.dim() == 2:
+            x = x[None]
+        B, H, W = x.shape
+        al = [float(alpha)] * B if not hasattr(alpha, "__len__") else [float(a) for a in alpha]
+        y = torch.empty_like(x)
+        self._enter()
+        _check(load().fl_net_forward(self._h, _ptr(x), (ctypes.c_double * B)(*al), _ptr(y), B, H, W))
+        self._leave()
+        return y
+
+    def grad(self, x, alpha, gy):
+        """d/dtheta sum(gy * N(x, alpha)) as an FP32 device vector."""
+        _need(x, torch.float32, name="x")
+        _need(gy, torch.float32, x.numel(), "gy")
+        B, H, W = x.shape
+        al = [float(alpha)] * B if not hasattr(alpha, "__len__") else [float(a) for a in alpha]
+        g = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        self._enter()
+        _check(load().fl_net_grad(self._h, _ptr(x), (ctypes.c_double * B)(*al), _ptr(gy), _ptr(g), B, H, W))
+        self._leave()
+        return g
+
+    def train(self, R, T, A, idx, batch, lr=1e-3):
+        """Adam steps over minibatches idx (int array [steps, batch]); returns the loss per step."""
+        _need(R, torch.float32, name="R")
+        _need(T, torch.float32, R.numel(), "T")
+        _need(A, torch.float32, R.shape[0], "A")
+        import numpy as np
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).reshape(-1, batch))
+        steps = idx.shape[0]
+        losses = (ctypes.c_float * max(steps, 1))()
+        npairs, H, W = R.shape
+        self._enter()
+        _check(load().fl_net_train(self._h, _ptr(R), _ptr(T), _ptr(A), npairs, H, W,
+                                   idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), steps, batch, lr, losses))
+        return [losses[i] for i in range(steps)]
+
+
+def learned_pairs(op, e, e_sub=None, Hp=None, Wp=None):
+    """Training pairs (R, T) of the learned preconditioner from FP64 errors
+    e - e_sub: e is one grid (repeated) or [count, n0, n1]; e_sub None or [count, n0, n1]."""
+    _need(e, torch.float64, name="e")
+    if e.numel() == op.N and e_sub is not None:
+        stride, count = 0, e_sub.numel() // op.N
+    else:
+        stride, count = op.N, e.numel() // op.N
+    if count < 1 or e.numel() % op.N:
+        raise ValueError("e must hold grids of the op")
+    if e_sub is not None:
+        _need(e_sub, torch.float64, count * op.N, "e_sub")
+    Hp = Hp or (op.n[0] + 7) // 8 * 8
+    Wp = Wp or (op.n[1] + 7) // 8 * 8
+    R = torch.empty((count, Hp, Wp), dtype=torch.float32, device="cuda")
+    T = torch.empty_like(R)
+    op._enter()
+    _check(load().fl_learned_pairs(op._h, _ptr(e), stride, _ptr(e_sub), count, _ptr(R), _ptr(T), Hp, Wp))
+    op._leave()
+    return R, T

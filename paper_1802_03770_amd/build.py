@@ -4,6 +4,7 @@ The library is split into translation units compiled in parallel: the host
 driver and C ABI, and the operator-application and preconditioner launch
 sequences once per precision (explicit template instantiations).
 """
+import hashlib
 import os
 import subprocess
 import sys
@@ -30,6 +31,7 @@ UNITS = [
     ("fl_batch.hip", ["-DFL_T=float"]),
     ("fl_batch.hip", ["-DFL_T=double"]),
     ("fl_batch.hip", ["-DFL_BATCH_HOST"]),
+    ("fl_net.hip", []),
 ]
 
 
@@ -41,23 +43,49 @@ def _run(cmd):
     return r
 
 
-def build(verbose=False, jobs=None):
+def _unit_key(src, defs):
+    h = hashlib.sha1()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith(".hpp") or name == src:
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    with open(os.path.join(ROOT, "include", "fraclap.h"), "rb") as f:
+        h.update(f.read())
+    h.update(" ".join(FLAGS + defs).encode())
+    return h.hexdigest()[:16]
+
+
+def build(verbose=False, jobs=None, reuse=False):
+    """Compile every unit and link the library.  reuse=True (development
+    only) keeps objects in _build/ and recompiles only units whose sources or
+    headers changed."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmpdir = tempfile.mkdtemp(prefix="fraclap_build_")
-    cmds = []
+    cache = os.path.join(HERE, "_build")
+    cmds, objs = [], []
     for i, (src, defs) in enumerate(UNITS):
-        obj = os.path.join(tmpdir, f"u{i}.o")
-        cmds.append((obj, [hipcc] + FLAGS + defs + ["-c", os.path.join(CSRC, src), "-o", obj]))
+        if reuse:
+            os.makedirs(cache, exist_ok=True)
+            obj = os.path.join(cache, f"{os.path.splitext(src)[0]}_{_unit_key(src, defs)}.o")
+            objs.append(obj)
+            if os.path.exists(obj):
+                continue
+        else:
+            obj = os.path.join(tmpdir, f"u{i}.o")
+            objs.append(obj)
+        cmds.append((obj, [hipcc] + FLAGS + defs + ["-c", os.path.join(CSRC, src), "-o", obj + ".part"]))
     if verbose:
         for _, c in cmds:
             print(" ".join(c), flush=True)
-    with ThreadPoolExecutor(max_workers=jobs or min(len(cmds), os.cpu_count() or 4)) as ex:
-        list(ex.map(lambda oc: _run(oc[1]), cmds))
+    if cmds:
+        with ThreadPoolExecutor(max_workers=jobs or min(len(cmds), os.cpu_count() or 4)) as ex:
+            list(ex.map(lambda oc: (_run(oc[1]), os.replace(oc[0] + ".part", oc[0])), cmds))
     tmp = LIB + ".tmp"
-    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + [o for o, _ in cmds] + ["-o", tmp])
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp])
     os.replace(tmp, LIB)
-    for o, _ in cmds:
-        os.remove(o)
+    if not reuse:
+        for o in objs:
+            os.remove(o)
     os.rmdir(tmpdir)
     return LIB
 

@@ -62,6 +62,7 @@ template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob
 template fl_status apply_seq<FL_T, PRO_PLAIN, EPI_PLAIN>(fl_op, const Prob&, Iter, int);
 template fl_status apply_seq<FL_T, PRO_PLAIN, EPI_RESID>(fl_op, const Prob&, Iter, int);
 template fl_status apply_seq<FL_T, PRO_PUPD, EPI_PQ>(fl_op, const Prob&, Iter, int);
+template fl_status apply_seq<FL_T, PRO_PLAIN, EPI_PQ>(fl_op, const Prob&, Iter, int);
 
 // One pass of the application on the op's workspace (inputs pb.in, output
 // pb.out, work W1/W2), launched with the same lane tuning as apply_seq.

@@ -398,6 +398,7 @@ static fl_status make_batch(Batch& bt, int nprob, const fl_op* ops, const uint8_
   if (nprob < 1 || !ops) return fail(FL_E_INVALID, "nprob must be >= 1");
   const bool mixed = o && o->mixed;
   bt.pc = o ? o->pc : FL_PC_FD;
+  if (bt.pc == FL_PC_LEARNED) return fail(FL_E_UNSUPPORTED, "batched solves take FL_PC_NONE, FD or SPECTRAL");
   if (bt.pc != FL_PC_NONE && bt.pc != FL_PC_FD && bt.pc != FL_PC_SPECTRAL)
     return fail(FL_E_INVALID, "unknown preconditioner");
   if (bt.pc == FL_PC_SPECTRAL)

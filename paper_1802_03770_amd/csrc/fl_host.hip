@@ -406,7 +406,13 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
   hipStream_t s = op->stream;
   const long N = op->N;
   const int pc = o ? o->pc : FL_PC_FD;
-  if (pc != FL_PC_NONE && pc != FL_PC_FD && pc != FL_PC_SPECTRAL) return fail(FL_E_INVALID, "unknown preconditioner");
+  if (pc != FL_PC_NONE && pc != FL_PC_FD && pc != FL_PC_SPECTRAL && pc != FL_PC_LEARNED)
+    return fail(FL_E_INVALID, "unknown preconditioner");
+  fl_net net = o ? o->net : nullptr;
+  if (pc == FL_PC_LEARNED) {
+    if (mask) return fail(FL_E_UNSUPPORTED, "the learned preconditioner is built for the box (no mask)");
+    STCHK(learned_prepare(op, net, 0));
+  }
   const int mixed = o ? o->mixed : 0;
   const int graph = o ? o->graph : 1;
   const int poll = (o && o->poll_every > 0) ? o->poll_every : 8;
@@ -434,11 +440,26 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
     } else {
       HIPCHK(hipMemcpyAsync(w.r, w.f, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    Scalars res;
-    STCHK(krylov<double>(op, pb, pc, tol, maxit, use_x0, graph, poll, &res));
-    inf.iters = res.itc[0];
-    inf.rel_res_recur = ff > 0 ? std::sqrt(res.rr / ff) : 0.0;
-    inf.status = res.done == 1 ? FL_OK : res.done == 2 ? FL_E_NOCONV : FL_E_BREAKDOWN;
+    if (pc == FL_PC_LEARNED) {
+      double rr0 = ff;
+      if (use_x0) {
+        STCHK(read_scalars(op, w.sc));
+        rr0 = op->hsc->rr;
+      }
+      int its = 0, stt = 0, fb = 0;
+      double rrf = 0.0;
+      STCHK(learned_fcg<double>(op, net, pb, tol, maxit, ff, rr0, &its, &rrf, &stt, &fb));
+      inf.iters = its;
+      inf.fell_back = fb;
+      inf.rel_res_recur = ff > 0 ? std::sqrt(rrf / ff) : 0.0;
+      inf.status = stt == 1 ? FL_OK : stt == 2 ? FL_E_NOCONV : FL_E_BREAKDOWN;
+    } else {
+      Scalars res;
+      STCHK(krylov<double>(op, pb, pc, tol, maxit, use_x0, graph, poll, &res));
+      inf.iters = res.itc[0];
+      inf.rel_res_recur = ff > 0 ? std::sqrt(res.rr / ff) : 0.0;
+      inf.status = res.done == 1 ? FL_OK : res.done == 2 ? FL_E_NOCONV : FL_E_BREAKDOWN;
+    }
   } else {
     STCHK(ensure_ws<float>(op, 1, true));
     Workspace& w32 = op->ws[1];
@@ -470,7 +491,20 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
              (const void*)w32.r, (const void*)w32.r, (int)S_DOT, N);
       LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, p32, (int)S_DOT, (int)FIN_FF);
       Scalars res;
-      STCHK(krylov<float>(op, p32, pc, itol, inner_cap, 0, graph, poll, &res));
+      if (pc == FL_PC_LEARNED) {
+        STCHK(read_scalars(op, w32.sc));
+        const double ff32 = op->hsc->ff;
+        int its = 0, stt = 0, fb = 0;
+        double rrf = 0.0;
+        STCHK(learned_fcg<float>(op, net, p32, itol, inner_cap, ff32, ff32, &its, &rrf, &stt, &fb));
+        res.itc[0] = its;
+        res.rr = rrf;
+        res.ff = ff32;
+        res.done = stt;
+        inf.fell_back |= fb;
+      } else {
+        STCHK(krylov<float>(op, p32, pc, itol, inner_cap, 0, graph, poll, &res));
+      }
       inf.iters += res.itc[0];
       inf.rel_res_recur = res.ff > 0 ? std::sqrt(res.rr / res.ff) : 0.0;
       if (res.done == 3) {
@@ -661,6 +695,7 @@ fl_status fl_step(fl_op op, double* u, double dt, double theta, const double* f_
   auto t0 = std::chrono::steady_clock::now();
   if (!op || !u || !info) return fail(FL_E_INVALID, "NULL argument");
   if (!(dt > 0.0) || !(theta > 0.0 && theta <= 1.0) || !(tol > 0.0)) return fail(FL_E_INVALID, "dt, theta or tol");
+  if (o && o->pc == FL_PC_LEARNED) return fail(FL_E_UNSUPPORTED, "the learned preconditioner is trained for M, not steps");
   STCHK(ensure_ws<double>(op, 1, true));
   Workspace& w = op->ws[0];
   const long N = op->N;

@@ -209,6 +209,15 @@ template <typename T> inline fl_status set_precond(fl_op op, Prob& pb, int pc) {
   return FL_OK;
 }
 
+// Learned preconditioner (fl_net.hip): scratch on op's grid, then flexible CG
+// on the workspace Prob pb (r: initial residual, x: initial iterate).  status:
+// 1 converged, 2 iteration cap, 3 breakdown; fell_back: the FD preconditioner
+// took over.
+fl_status learned_prepare(fl_op op, fl_net net, size_t elem);
+template <typename T>
+fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxit, double ff, double rr0, int* iters,
+                      double* rr_out, int* status, int* fell_back);
+
 // Launch sequences (defined per precision in fl_apply.hip / fl_precond.hip).
 template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob& pb, Iter it, int chk);
 template <typename T, int DPRO, int DEPI> fl_status precond_seq(fl_op op, Prob pb, Iter it, int chk);

@@ -695,7 +695,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
       for (int k = lane + 1; k <= n; k += tpl) {
         cx<T> sv = sine_pair_get(res, k);
         T e = (T)(pb.p0 + pb.p1 * pb.pcs * (double)(tau ? tau[k - 1] : ev[k - 1]));
-        sine_pair_put(res, Lf, k, sv.x / e, sv.y / e);
+        sine_pair_put(res, Lf, k, pb.pmul ? sv.x * e : sv.x / e, pb.pmul ? sv.y * e : sv.y / e);
       }
       if (lane == 0) {
         res[0] = {0, 0};
@@ -706,7 +706,10 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
     } else {
       const T* tau = (const T*)pb.tau;
       for (int k = lane; k < n; k += tpl)
-        buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * (double)(tau ? tau[k] : ev[k]));
+      {
+        const T e = (T)(pb.p0 + pb.p1 * pb.pcs * (double)(tau ? tau[k] : ev[k]));
+        buf[k].x = pb.pmul ? buf[k].x * e : buf[k].x / e;
+      }
       __syncthreads();
       dst_line<T>(buf, A, lane, tpl);
     }
@@ -815,7 +818,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
         }
         T ea = (T)(pb.p0 + pb.p1 * pb.pcs * la);
         T eb = (T)(pb.p0 + pb.p1 * pb.pcs * lb);
-        sine_pair_put(res, Lf, k, sv.x / ea, sv.y / eb);
+        sine_pair_put(res, Lf, k, pb.pmul ? sv.x * ea : sv.x / ea, pb.pmul ? sv.y * eb : sv.y / eb);
       }
       if (lane == 0) {
         res[0] = {0, 0};
@@ -829,7 +832,8 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
       const double etail = (ok && !tau) ? eig_tail<T>(pb, c) : 0.0;
       for (int k = lane; k < n; k += tpl) {
         const double lv = tau ? (ok ? (double)tau[(long)k * dg.gs + c] : 1.0) : (double)ev[k] + etail;
-        buf[k].x = buf[k].x / (T)(pb.p0 + pb.p1 * pb.pcs * lv);
+        const T e = (T)(pb.p0 + pb.p1 * pb.pcs * lv);
+        buf[k].x = pb.pmul ? buf[k].x * e : buf[k].x / e;
       }
       __syncthreads();
       dst_line<T>(buf, A, lane, tpl);

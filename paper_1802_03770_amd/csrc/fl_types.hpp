@@ -59,6 +59,8 @@ struct Prob {
   double p0, p1;    // preconditioner eigenvalue p0 + p1 * pcs * (sum_a eig_a  or  tau[k])
   const void* tau;  // null: FD Laplacian eigenvalues; else the operator's own diagonal in the
                     // sine basis, T, [n_0][n_1][n_2] indexed by k_a - 1
+  int pmul;         // 1: multiply by the eigenvalue instead of dividing (the operator
+                    //    diagonalised by the sine transform, not its inverse)
   // buffers
   const void* in;   // real input  [nrhs][n...]
   void* out;        // real output

@@ -1,0 +1,210 @@
+"""GPU parity of the learned preconditioner's network (BF16 activations, FP32
+accumulation) against the FP64 numpy oracle (oracle/net.py), of its training
+pairs against the oracle's operator and sine-basis diagonal, and the ablation:
+what the trained network gains inside flexible CG over the same solver
+without it.
+
+Tolerances: the network keeps activations in BF16 (8-bit significand, unit
+roundoff 2^-9 ~ 2e-3) through nine layers, so outputs and gradients are
+compared in relative l2 norm against the FP64 oracle at 3e-2 (outputs), 5e-2
+(the whole gradient: the reverse pass also stores its gradients in BF16, 18
+roundings deep) and 1e-1 per layer's gradient (the coarse levels of small
+test grids sum few pixels, where single ReLU flips from BF16 rounding show),
+with a cosine similarity above 0.998.  An indexing error shows as an O(1)
+error in the layer it touches.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import net as NN  # noqa: E402
+from oracle import operator as O  # noqa: E402
+from oracle import precond as PC  # noqa: E402
+from oracle import spectral as SP  # noqa: E402
+from workloads import bump_field, power_law_field  # noqa: E402
+
+
+def _fl():
+    import paper_1802_03770_amd as fl
+    return fl
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rl2(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _params(seed):
+    th = NN.init_params(seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 50))
+    P = NN.unpack(th)
+    for name, (w, b) in P.items():  # nonzero biases, output layer at full scale
+        b[:] = 0.1 * rng.standard_normal(b.shape)
+    P["out"][0][:] *= 10.0
+    return th
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 16, 24), (1, 8, 8), (3, 64, 72), (1, 128, 64)])
+def test_net_forward_against_oracle(B, H, W):
+    _say("net forward", B, H, W)
+    fl = _fl()
+    th = _params(3)
+    rng = np.random.Generator(np.random.PCG64(B * 1000 + H + W))
+    x = rng.standard_normal((B, H, W))
+    al = rng.uniform(0.2, 1.9, size=B)
+    net = fl.Net(params=th)
+    y = net.forward(torch.from_numpy(x.astype(np.float32)).cuda(), list(al)).cpu().numpy()
+    want = NN.forward(th.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64), al)
+    assert _rl2(y, want) <= 3e-2, _rl2(y, want)
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 16, 24), (1, 32, 32)])
+def test_net_grad_against_oracle(B, H, W):
+    _say("net grad", B, H, W)
+    fl = _fl()
+    th = _params(4)
+    rng = np.random.Generator(np.random.PCG64(7 + H))
+    x = rng.standard_normal((B, H, W)).astype(np.float32)
+    gy = rng.standard_normal((B, H, W)).astype(np.float32)
+    al = rng.uniform(0.2, 1.9, size=B)
+    net = fl.Net(params=th)
+    g = net.grad(torch.from_numpy(x).cuda(), list(al), torch.from_numpy(gy).cuda()).cpu().numpy()
+    want = NN.grad(th.astype(np.float32).astype(np.float64), x.astype(np.float64), al, gy.astype(np.float64))
+    o = 0
+    for name, ci, co in NN.LAYERS:
+        nw = 9 * ci * co
+        for part, m in (("W", nw), ("b", co)):
+            err = _rl2(g[o:o + m], want[o:o + m])
+            assert err <= 1e-1, (name, part, err)
+            o += m
+    cos = float(g @ want / (np.linalg.norm(g) * np.linalg.norm(want)))
+    assert cos >= 0.998
+    assert _rl2(g, want) <= 5e-2
+
+
+def test_net_params_roundtrip_and_zero_output():
+    fl = _fl()
+    th = NN.init_params(1).astype(np.float32)
+    net = fl.Net(params=th)
+    assert np.array_equal(net.get_params().cpu().numpy(), th)
+    z = th.copy()
+    z[-(9 * 32 + 1):] = 0.0  # output layer zero: N = 0
+    net.set_params(z)
+    y = net.forward(torch.ones((1, 16, 16), dtype=torch.float32, device="cuda"), 1.0)
+    assert torch.count_nonzero(y).item() == 0
+
+
+def test_learned_pairs_against_oracle():
+    _say("learned pairs")
+    fl = _fl()
+    n, alpha = (24, 30), 1.3
+    h = 2.0 / 31
+    op = fl.Op(2, alpha, h, n)
+    ref = O.Operator(2, alpha, h, n)
+    e = np.stack([power_law_field(n, 11), power_law_field(n, 12)])
+    sub = np.stack([np.zeros(n), 0.5 * power_law_field(n, 13)])
+    R, T = fl.learned_pairs(op, torch.from_numpy(e).cuda(), e_sub=torch.from_numpy(sub).cuda())
+    assert R.shape == (2, 24, 32)
+    m = SP.tau_eigenvalues(2, alpha, n) * ref.C * h ** -alpha
+    Q0 = PC.sine_matrix(n[0]) * math.sqrt(2 / (n[0] + 1))
+    Q1 = PC.sine_matrix(n[1]) * math.sqrt(2 / (n[1] + 1))
+    for k in range(2):
+        ek = e[k] - sub[k]
+        r = ref.apply(ek)
+        De = Q0 @ ((Q0.T @ ek @ Q1) * m) @ Q1.T
+        s = np.sqrt((r * r).mean())
+        got_R, got_T = R[k].cpu().numpy(), T[k].cpu().numpy()
+        assert np.all(got_R[:, 30:] == 0) and np.all(got_T[:, 30:] == 0)
+        assert _rl2(got_R[:, :30], r / s) <= 1e-6
+        assert _rl2(got_T[:, :30], (De - r) / s) <= 1e-5
+
+
+def test_learned_fcg_falls_back_to_fd():
+    # a network whose output is a large negative constant makes r.z < 0 on a
+    # positive residual: the solver must switch to the FD preconditioner
+    _say("learned fallback")
+    fl = _fl()
+    n, alpha = 32, 1.0
+    h = 2.0 / (n + 1)
+    s = torch.cuda.Stream()
+    op = fl.Op(2, alpha, h, (n, n), stream=s)
+    th = np.zeros(NN.nparams(), dtype=np.float32)
+    th[-1] = -1000.0
+    net = fl.Net(stream=s, params=th)
+    f = torch.ones((n, n), dtype=torch.float64, device="cuda")
+    u, info = op.solve(f, tol=1e-10, opts=fl.solve_opts(pc=fl.FL_PC_LEARNED, net=net))
+    assert info["fell_back"] == 1
+    M = O.Operator(2, alpha, h, (n, n)).dense()
+    res = np.linalg.norm(1.0 - M @ u.cpu().numpy().ravel()) / n
+    assert res <= 1e-9
+
+
+def test_learned_rejects_masks_steps_and_3d():
+    fl = _fl()
+    s = torch.cuda.Stream()
+    op = fl.Op(2, 1.0, 0.1, (16, 16), stream=s)
+    net = fl.Net(stream=s, params=np.zeros(NN.nparams(), dtype=np.float32))
+    f = torch.ones((16, 16), dtype=torch.float64, device="cuda")
+    mk = torch.ones((16, 16), dtype=torch.uint8, device="cuda")
+    with pytest.raises(fl.FlError):
+        op.solve(f, mask=mk, opts=fl.solve_opts(pc=fl.FL_PC_LEARNED, net=net))
+    with pytest.raises(fl.FlError):
+        op.step(f.clone(), 1e-3, opts=fl.solve_opts(pc=fl.FL_PC_LEARNED, net=net))
+    with pytest.raises(fl.FlError):
+        op.solve(f, opts=fl.solve_opts(pc=fl.FL_PC_LEARNED))  # no network
+    op3 = fl.Op(3, 1.0, 0.1, (8, 8, 8), stream=s)
+    with pytest.raises(fl.FlError):
+        op3.solve(torch.ones((8, 8, 8), dtype=torch.float64, device="cuda"),
+                  opts=fl.solve_opts(pc=fl.FL_PC_LEARNED, net=net))
+
+
+def test_training_and_ablation():
+    # Train on solver-generated pairs at 64^2 (a few hundred Adam steps) and
+    # compare, on a right-hand side outside the training set, flexible CG with
+    # the trained network against the same solver with N = 0 (the spectral
+    # preconditioner alone) and against the FD preconditioner.
+    _say("training + ablation")
+    fl = _fl()
+    from paper_1802_03770_amd import learned as L
+    from workloads import learned_training_plan
+    s = torch.cuda.Stream()
+    plan = learned_training_plan(nalpha=24, n=64, seed=777)
+    R, T, A = L.make_pairs(plan, iters=6, fields=6, stream=s)
+    assert R.shape == (24 * 12, 64, 64)
+    net, losses = L.train(R, T, A, steps=400, batch=8, lr=2e-3, seed=3, stream=s)
+    first, last = np.mean(losses[:20]), np.mean(losses[-20:])
+    _say("loss", first, "->", last)
+    assert last < 0.5 * first
+    zero = fl.Net(stream=s, params=np.zeros(NN.nparams(), dtype=np.float32))
+    out = {}
+    for alpha in (0.6, 1.0, 1.5):
+        n = 64
+        f_np, h = bump_field(n, 2, 32, 99, width=(0.05, 0.2))
+        op = fl.Op(2, alpha, h, (n, n), stream=s)
+        f = torch.from_numpy(f_np).cuda()
+        M = O.Operator(2, alpha, h, (n, n)).dense()
+        its = {}
+        for name, opts in (("learned", fl.solve_opts(pc=fl.FL_PC_LEARNED, net=net)),
+                           ("spectral_fcg", fl.solve_opts(pc=fl.FL_PC_LEARNED, net=zero)),
+                           ("fd", fl.solve_opts(pc=fl.FL_PC_FD))):
+            u, info = op.solve(f, tol=1e-10, opts=opts)
+            res = np.linalg.norm(f_np.ravel() - M @ u.cpu().numpy().ravel()) / np.linalg.norm(f_np)
+            assert res <= 1e-9, (name, res)
+            its[name] = info["iters"]
+        out[alpha] = its
+    _say("iterations", out)
+    assert sum(v["learned"] for v in out.values()) < sum(v["spectral_fcg"] for v in out.values())
+    for v in out.values():
+        assert v["learned"] <= v["spectral_fcg"]
+        assert v["spectral_fcg"] < v["fd"]

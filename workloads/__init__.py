@@ -2,10 +2,10 @@
 
 This module holds no arithmetic of the solver: it only draws right-hand sides
 and initial data (sums of Gaussian bumps evaluated on the interior grid of a
-box) and the problem lists of the benchmark workloads.
+box, random fields), and the problem lists of the benchmark workloads.
 """
-from .gen import (bump_field, grid_axis, workload_c1, workload_c2, workload_c3,
-                  workload_c4, white_noise, random_mask)
+from .gen import (bump_field, grid_axis, learned_training_plan, power_law_field, random_mask,
+                  white_noise, workload_c1, workload_c2, workload_c3, workload_c4)
 
 __all__ = ["bump_field", "grid_axis", "workload_c1", "workload_c2", "workload_c3",
-           "workload_c4", "white_noise", "random_mask"]
+           "workload_c4", "white_noise", "random_mask", "power_law_field", "learned_training_plan"]

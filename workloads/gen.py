@@ -76,3 +76,33 @@ def workload_c4(nprob=32, seed=4000, sizes=(128, 256, 384, 512)):
         u0, h = bump_field(int(ns[i]), 2, 8, seed + 1 + i, width=(0.1, 0.3))
         probs.append({"d": 2, "n": int(ns[i]), "alpha": float(alphas[i]), "h": h, "u0": u0})
     return probs
+
+
+def power_law_field(shape, seed, slope=(0.0, 3.0)):
+    """Gaussian random field with a random spectral slope: white noise on the
+    doubled periodic box, amplitudes scaled by (1 + |k|)^-beta with beta drawn
+    from U[slope], cropped to `shape` and normalised to unit l2 norm.  Draw
+    order: beta, then the noise."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    beta = rng.uniform(slope[0], slope[1])
+    big = tuple(2 * v for v in shape)
+    w = rng.standard_normal(big)
+    kk = 0.0
+    for a, v in enumerate(big):
+        k = np.fft.fftfreq(v) * v
+        sh = [1] * len(big)
+        sh[a] = v
+        kk = kk + (k.reshape(sh)) ** 2
+    amp = (1.0 + np.sqrt(kk)) ** (-beta)
+    f = np.fft.ifftn(np.fft.fftn(w) * amp).real[tuple(slice(0, v) for v in shape)]
+    return np.ascontiguousarray(f / np.linalg.norm(f))
+
+
+def learned_training_plan(nalpha=100, n=256, seed=5000, lo=0.2, hi=1.9):
+    """Problems of the learned-preconditioner training set: alpha ~ U[lo, hi]
+    on an n x n grid of (-1,1)^2, each with a bump right-hand side (32 bumps,
+    C2's distributions) and random-field seeds."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    alphas = rng.uniform(lo, hi, size=nalpha)
+    return [{"n": n, "alpha": float(a), "rhs_seed": seed + 1 + i, "field_seed": seed + 100000 + 1000 * i}
+            for i, a in enumerate(alphas)]
