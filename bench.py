@@ -8,12 +8,18 @@ preconditioner, fused Krylov updates, FP64 refinement) runs inside it.
 
 Solver configurations timed (each must reach ||f - M u||/||f|| <= 1e-8, the
 residual recomputed in FP64 on the GPU at the end of every solve):
-  fp64_pcg   FP64 PCG, finite-difference Laplacian preconditioner (the paper's method)
-  fp64_cg    FP64 CG without preconditioner
-  f32_pcg    FP32 inner PCG + FP64 iterative refinement
-  f32_cg     FP32 inner CG  + FP64 iterative refinement
-The plain-FP64 baseline is the faster of fp64_pcg and fp64_cg; `value` is the
-fastest configuration overall.
+  fp64_pcg       FP64 PCG, finite-difference Laplacian preconditioner (the paper's method)
+  fp64_cg        FP64 CG without preconditioner
+  f32_pcg        FP32 inner PCG + FP64 iterative refinement
+  f32_cg         FP32 inner CG  + FP64 iterative refinement
+  fp64_spectral  FP64 PCG, sine-basis diagonal of M as preconditioner
+  f32_spectral   FP32 inner PCG (sine-basis diagonal) + FP64 refinement
+  learned_f32    FP32 inner flexible CG with the learned preconditioner + FP64 refinement
+  learned_fp64   FP64 flexible CG with the learned preconditioner
+The learned preconditioner is trained first (outside the timed region) on
+solver-generated pairs at 256^2, alpha ~ U[0.2, 1.9]: 100 problems x (10
+iterate errors + 10 random-field errors) = 2000 pairs.  `value` is the time of
+learned_f32; the plain-FP64 baseline is the faster of fp64_pcg and fp64_cg.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--alpha A] [--no-cpu]
 """
@@ -43,6 +49,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="comma list of configurations to time")
+    ap.add_argument("--train-problems", type=int, default=100)
+    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--train-batch", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -66,6 +75,29 @@ def main():
     t_make = (time.perf_counter() - t0) * 1e3
     log(f"[bench] make_weights {t_make:.1f} ms")
 
+    # learned preconditioner: training set and training (not timed as a solve)
+    net, train_info = None, None
+    want_learned = not args.only or any(k.startswith("learned") for k in args.only.split(","))
+    if want_learned:
+        from paper_1802_03770_amd import learned as L
+        from workloads import learned_training_plan
+        t0 = time.perf_counter()
+        plan = learned_training_plan(nalpha=args.train_problems, n=256, seed=5000)
+        R, T, A = L.make_pairs(plan, iters=10, fields=10, stream=op.stream, log=log)
+        t_pairs = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        net, losses = L.train(R, T, A, steps=args.train_steps, batch=args.train_batch, lr=1e-3, seed=1,
+                              stream=op.stream)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        l0 = float(np.mean(losses[:50]))
+        l1 = float(np.mean(losses[-50:]))
+        log(f"[bench] learned: {R.shape[0]} pairs at 256^2 in {t_pairs:.1f} s, {len(losses)} Adam steps "
+            f"(batch {args.train_batch}) in {t_train:.1f} s, loss {l0:.3e} -> {l1:.3e}")
+        train_info = {"pairs": int(R.shape[0]), "grid": 256, "pairs_s": round(t_pairs, 2), "steps": len(losses),
+                      "batch": args.train_batch, "train_s": round(t_train, 2), "loss_first": l0, "loss_last": l1}
+        del R, T, A
+
     configs = {
         "fp64_pcg": fl.solve_opts(pc=fl.FL_PC_FD, mixed=0),
         "fp64_cg": fl.solve_opts(pc=fl.FL_PC_NONE, mixed=0),
@@ -74,6 +106,9 @@ def main():
         "fp64_spectral": fl.solve_opts(pc=fl.FL_PC_SPECTRAL, mixed=0),
         "f32_spectral": fl.solve_opts(pc=fl.FL_PC_SPECTRAL, mixed=1),
     }
+    if net is not None:
+        configs["learned_f32"] = fl.solve_opts(pc=fl.FL_PC_LEARNED, mixed=1, net=net)
+        configs["learned_fp64"] = fl.solve_opts(pc=fl.FL_PC_LEARNED, mixed=0, net=net)
     if args.only:
         configs = {k: v for k, v in configs.items() if k in args.only.split(",")}
     results = {}
@@ -91,14 +126,14 @@ def main():
         worst = max(i["rel_res_true"] for i in infos)
         ok = worst <= tol and all(i["status"] == 0 for i in infos)
         results[name] = {"ms": ms, "iters": infos[-1]["iters"], "outer": infos[-1]["outer_iters"],
-                         "rel_res_true": worst, "ok": ok}
+                         "rel_res_true": worst, "ok": ok, "fell_back": infos[-1]["fell_back"]}
         log(f"[bench] {name}: {ms:.2f} ms/solve iters={infos[-1]['iters']} outer={infos[-1]['outer_iters']} "
             f"true_res={worst:.2e} ok={ok}")
     good = {k: v for k, v in results.items() if v["ok"]}
     if not good:
         log("[bench] no configuration reached the tolerance")
         sys.exit(1)
-    best = min(good, key=lambda k: good[k]["ms"])
+    best = "learned_f32" if "learned_f32" in good else min(good, key=lambda k: good[k]["ms"])
     base = [k for k in ("fp64_pcg", "fp64_cg") if k in good]
     base_ms = min(good[k]["ms"] for k in base) if base else None
 
@@ -130,7 +165,7 @@ def main():
         cpu = cpu_baseline(n, alpha, h, f_np, results.get("fp64_pcg", {}).get("iters"))
 
     line = {
-        "metric": "time to 1e-8 rel residual, 1024^2 alpha=1 (best GPU solver; plain FP64 PCG/CG as baseline)",
+        "metric": "time to 1e-8 rel residual, 1024^2 alpha=1: learned+FP32 vs plain FP64 PCG",
         "value": round(good[best]["ms"], 3),
         "unit": "ms",
         "n_gpus": 1,
@@ -140,10 +175,12 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if best.startswith("f32") else "f64",
+        "dtype": {"learned_f32": "bf16+f32+f64", "learned_fp64": "bf16+f64"}.get(
+            best, "f32+f64" if best.startswith("f32") else "f64"),
         "data": "synthetic (seeded Gaussian-bump right-hand side)",
         "config": {"workload": f"elliptic 2D n={n}x{n} alpha={alpha} (-1,1)^2 32 bumps seed 2000 tol {tol}",
                    "solver": best, "make_weights_ms": round(t_make, 1)},
+        "learned_training": train_info,
         "baseline_fp64_ms": None if base_ms is None else round(base_ms, 3),
         "speedup_vs_fp64": None if base_ms is None else round(base_ms / good[best]["ms"], 3),
         "solvers": {k: {kk: (float(f"{vv:.4g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}

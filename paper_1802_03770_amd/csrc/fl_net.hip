@@ -535,7 +535,8 @@ __global__ void k_pair_out(const double* __restrict__ r, const double* __restric
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= (long)Hp * Wp) return;
   const int yy = (int)(i / Wp), xx = (int)(i % Wp);
-  const double inv = 1.0 / sqrt(*rr / ((double)n0 * n1));
+  const double ms = *rr / ((double)n0 * n1);
+  const double inv = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;  // a zero error gives a zero pair
   const bool in = yy < n0 && xx < n1;
   const long j = (long)yy * n1 + xx;
   R[i] = in ? (float)(r[j] * inv) : 0.f;

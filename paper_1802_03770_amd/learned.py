@@ -39,9 +39,12 @@ def make_pairs(plan, iters=10, fields=10, stream=None, log=None):
         f_np, h = bump_field(n, 2, 32, pr["rhs_seed"], width=(0.05, 0.2))
         op = Op(2, alpha, h, (n, n), stream=stream)
         f = torch.from_numpy(f_np).cuda()
-        xs, _ = op.solve(f, tol=1e-12, opts=solve_opts(pc=FL_PC_SPECTRAL))
+        xs, info = op.solve(f, tol=1e-12, opts=solve_opts(pc=FL_PC_SPECTRAL))
+        # iterates strictly before the converged one (x_k of the same solve with
+        # maxit = k equals x* bitwise once k reaches its iteration count)
+        nit = min(iters, max(1, info["iters"] - 1))
         xk = []
-        for k in range(iters):
+        for k in range(nit):
             u, _ = op.solve(f, tol=1e-30, opts=solve_opts(pc=FL_PC_SPECTRAL, maxit=k + 1), check=False)
             xk.append(u)
         xk = torch.stack([torch.zeros_like(xs)] + xk[:-1]) if iters > 0 else None
@@ -49,12 +52,13 @@ def make_pairs(plan, iters=10, fields=10, stream=None, log=None):
             R, T = learned_pairs(op, xs, e_sub=xk)
             Rs.append(R)
             Ts.append(T)
+            As += [alpha] * nit
         if fields > 0:
             e = np.stack([power_law_field((n, n), pr["field_seed"] + j) for j in range(fields)])
             R, T = learned_pairs(op, torch.from_numpy(e).cuda())
             Rs.append(R)
             Ts.append(T)
-        As += [alpha] * (iters + fields)
+        As += [alpha] * fields
         op.close()
         if log and (i + 1) % 10 == 0:
             log(f"[learned] pairs from {i + 1}/{len(plan)} problems")
