@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="comma list of configurations to time")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 3D and uneven-batch workloads")
+    ap.add_argument("--c4-steps", type=int, default=200)
     ap.add_argument("--train-problems", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--train-batch", type=int, default=16)
@@ -73,7 +75,7 @@ def main():
     op = fl.Op(2, alpha, h, (n, n))
     torch.cuda.synchronize()
     t_make = (time.perf_counter() - t0) * 1e3
-    log(f"[bench] make_weights {t_make:.1f} ms")
+    log(f"[bench] make_weights {t_make:.1f} ms (sine-transform plans, autotuned: {op.plan()})")
 
     # learned preconditioner: training set and training (not timed as a solve)
     net, train_info = None, None
@@ -155,10 +157,29 @@ def main():
         gbs = nbytes / (ms * 1e-3) / 1e9
         prof[name] = {"ms": ms, "bytes": nbytes, "GBps": gbs}
         log(f"[bench] pass {name}: {ms * 1e3:.1f} us  {gbs:.0f} GB/s (algorithmic)")
-    dom = max(("f32_sine_col_scale", "f32_fft_col_conv"), key=lambda k: prof[k]["ms"])
+    cands = ["f32_sine_col_scale", "f32_fft_col_conv"]
+    if net is not None:
+        # network layers at the solver grid (BF16 NHWC activations, 32 channels):
+        # level-0 conv reads a0 (64 B/px) and the coarse c1 (16 B/px), writes c0 (64 B/px)
+        for name, which, nbytes in (("net_conv_l0", 1, 144 * n * n), ("net_in_layer", 2, 68 * n * n),
+                                    ("net_out_layer", 3, 68 * n * n), ("net_forward", 0, None)):
+            ms = net.profile(which, n, n, reps=20)
+            prof[name] = {"ms": ms, "bytes": nbytes, "GBps": (nbytes / (ms * 1e-3) / 1e9) if nbytes else None}
+            gb = f"{prof[name]['GBps']:.0f} GB/s (algorithmic)" if nbytes else ""
+            log(f"[bench] pass {name}: {ms * 1e3:.1f} us  {gb}")
+        cands.append("net_conv_l0")
+    dom = max(cands, key=lambda k: prof[k]["ms"])
     roof = {"bound": "hbm", "achieved": round(prof[dom]["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(prof[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
             "avg_us": round(prof[dom]["ms"] * 1e3, 2), "bytes_per_launch": prof[dom]["bytes"]}
+    if dom == "net_conv_l0":
+        tf = 2 * 9 * 32 * 32 * n * n / (prof[dom]["ms"] * 1e-3) / 1e12
+        roof["mfma_bf16_tflops"] = round(tf, 1)
+        roof["mfma_frac"] = round(tf / 2500.0, 4)
+
+    batched = None
+    if not args.no_batched:
+        batched = batched_workloads(fl, torch, args)
 
     cpu = None
     if not args.no_cpu:
@@ -179,17 +200,86 @@ def main():
             best, "f32+f64" if best.startswith("f32") else "f64"),
         "data": "synthetic (seeded Gaussian-bump right-hand side)",
         "config": {"workload": f"elliptic 2D n={n}x{n} alpha={alpha} (-1,1)^2 32 bumps seed 2000 tol {tol}",
-                   "solver": best, "make_weights_ms": round(t_make, 1)},
+                   "solver": best, "make_weights_ms": round(t_make, 1), "sine_plans": op.plan()},
         "learned_training": train_info,
         "baseline_fp64_ms": None if base_ms is None else round(base_ms, 3),
         "speedup_vs_fp64": None if base_ms is None else round(base_ms / good[best]["ms"], 3),
         "solvers": {k: {kk: (float(f"{vv:.4g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in results.items()},
         "passes_us": {k: round(v["ms"] * 1e3, 2) for k, v in prof.items()},
+        "passes_GBps": {k: round(v["GBps"], 1) for k, v in prof.items() if v["GBps"]},
         "roofline": roof,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def batched_workloads(fl, torch, args):
+    """The batched row of the hot path on its two workloads (one launch per
+    pass over all problems, captured iteration graphs):
+      c3: d=3, 256^3, alpha=1.2, 16 right-hand sides of one operator, FP32
+          inner PCG + FP64 refinement to 1e-8 (FD preconditioner, and the
+          sine-basis diagonal with its one-off table build timed apart);
+      c4: 32 uneven 2D backward-Euler problems (n in {128,256,384,512},
+          alpha ~ U[0.3,1.8]), dt = 1e-3, `c4_steps` steps, tol 1e-10."""
+    from workloads import workload_c3, workload_c4
+    out = {}
+    s = torch.cuda.Stream()
+    # c4
+    probs = workload_c4(32)
+    t0 = time.perf_counter()
+    ops = [fl.Op(2, p["alpha"], p["h"], (p["n"], p["n"]), stream=s) for p in probs]
+    torch.cuda.synchronize()
+    t_make = time.perf_counter() - t0
+    opts = fl.solve_opts(pc=fl.FL_PC_SPECTRAL)
+    us = [torch.from_numpy(p["u0"]).cuda() for p in probs]
+    fl.step_batched(ops, [u.clone() for u in us], [1e-3] * 32, theta=1.0, nsteps=2, tol=1e-10, opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos = fl.step_batched(ops, us, [1e-3] * 32, theta=1.0, nsteps=args.c4_steps, tol=1e-10, opts=opts)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    unk = sum(p["n"] ** 2 for p in probs)
+    out["c4"] = {"workload": "32 uneven 2D backward-Euler problems, n in {128,256,384,512}, dt=1e-3",
+                 "steps": args.c4_steps, "ms_total": round(ms, 1), "ms_per_step": round(ms / args.c4_steps, 3),
+                 "unknown_steps_per_s": round(unk * args.c4_steps / (ms * 1e-3), 1),
+                 "iters_per_step_mean": round(sum(i["iters"] for i in infos) / (32 * args.c4_steps), 2),
+                 "max_rel_res_true": max(i["rel_res_true"] for i in infos), "make_weights_s": round(t_make, 2),
+                 "preconditioner": "sine-basis diagonal"}
+    log(f"[bench] c4: {args.c4_steps} steps of 32 uneven problems in {ms:.1f} ms ({ms / args.c4_steps:.2f} ms/step), "
+        f"mean iters/step {out['c4']['iters_per_step_mean']}, max true res {out['c4']['max_rel_res_true']:.1e}")
+    for o in ops:
+        o.close()
+    del ops, us
+    # c3
+    w0 = workload_c3(0)
+    t0 = time.perf_counter()
+    op = fl.Op(3, w0["alpha"], w0["h"], (w0["n"],) * 3, stream=s)
+    torch.cuda.synchronize()
+    t_make = time.perf_counter() - t0
+    fs = [torch.from_numpy(workload_c3(k)["f"]).cuda() for k in range(16)]
+    c3 = {"workload": "3D 256^3 alpha=1.2, 16 right-hand sides, FP32 inner + FP64 refinement, tol 1e-8",
+          "make_weights_s": round(t_make, 2)}
+    for name, pc in (("fd", fl.FL_PC_FD), ("spectral", fl.FL_PC_SPECTRAL)):
+        opts = fl.solve_opts(pc=pc, mixed=1)
+        if pc == fl.FL_PC_SPECTRAL:
+            t0 = time.perf_counter()
+            op.tau()
+            c3["tau_build_s"] = round(time.perf_counter() - t0, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, infos = fl.solve_batched([op] * 16, fs, tol=1e-8, opts=opts)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        c3[name] = {"ms": round(ms, 1), "ms_per_rhs": round(ms / 16, 2),
+                    "iters_mean": round(sum(i["iters"] for i in infos) / 16, 1),
+                    "max_rel_res_true": max(i["rel_res_true"] for i in infos)}
+        log(f"[bench] c3 {name}: 16 x 256^3 in {ms:.1f} ms, mean iters {c3[name]['iters_mean']}, "
+            f"max true res {c3[name]['max_rel_res_true']:.1e}")
+    out["c3"] = c3
+    op.close()
+    return out
 
 
 def cpu_baseline(n, alpha, h, f, iters):

@@ -68,7 +68,11 @@ typedef enum {
 
 typedef struct {
   double delta_over_h;  /* window radius c in grid points (Sec. 4.1 uses 20); <= 0 -> 20 */
-  int reserved[6];
+  int dst_mode;         /* sine-transform plan per axis: 0 = autotune (time the preconditioner with both
+                           forms when the op is built and keep the faster, per precision); 1 = direct odd
+                           extension of length 2(n+1) when it factors over radices <= 43, else chirp-z;
+                           2 = chirp-z with a 5-smooth length >= 2n-1 */
+  int reserved[5];
 } fl_weights_opts;
 
 typedef struct {
@@ -109,6 +113,11 @@ fl_status fl_op_constants(fl_op op, double out[8]);
 
 /* Padded circulant lengths P_k (out[0..d-1]). */
 fl_status fl_op_padded(fl_op op, int64_t* out);
+
+/* Sine-transform plans chosen for the op: out[3 p + a] = 1 (direct) or 2
+ * (chirp-z) and out[6 + 3 p + a] = its FFT length, for precision p (0 FP64,
+ * 1 FP32) and axis a < d; 12 entries. */
+fl_status fl_op_plan(fl_op op, int64_t* out);
 
 /* Device-to-device copy of the folded arrays, shape [P_1/2+1]...[P_d/2+1]:
  * which = 0: weights w_m (FP64, zero for m_k >= n_k); 1: symbol lambda (FP64);
@@ -223,6 +232,11 @@ fl_status fl_net_train(fl_net net, const float* R, const float* T, const float* 
  * Hp x Wp grid (R, T: FP32 [count][Hp][Wp], Hp >= n_0, Wp >= n_1). */
 fl_status fl_learned_pairs(fl_op op, const double* e, int64_t e_stride, const double* e_sub, int count, float* R,
                            float* T, int Hp, int Wp);
+/* Measurement aid: average duration (ms, HIP events on the net's stream) of
+ * `reps` launches on a 1 x H x W input: which = 0 the whole forward pass,
+ * 1 the level-0 32 -> 32 convolution (MFMA, skip-add staging), 2 the input
+ * layer, 3 the output layer. */
+fl_status fl_net_profile(fl_net net, int which, int H, int W, int reps, double* avg_ms);
 fl_status fl_net_destroy(fl_net net);
 
 /* Measurement aid: average duration (ms, HIP events on the op's stream) of

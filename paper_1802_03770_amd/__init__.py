@@ -18,10 +18,10 @@ FL_F64, FL_F32 = 0, 1
 FL_PC_NONE, FL_PC_FD, FL_PC_LEARNED, FL_PC_SPECTRAL = 0, 1, 2, 3
 STATUS_NAMES = {0: "ok", -1: "invalid", -2: "nomem", -3: "hip", -4: "noconv", -5: "breakdown", -6: "unsupported"}
 
-EXPORTED = ["fl_make_weights", "fl_op_constants", "fl_op_padded", "fl_op_export", "fl_apply", "fl_precond",
+EXPORTED = ["fl_make_weights", "fl_op_constants", "fl_op_padded", "fl_op_plan", "fl_op_export", "fl_apply", "fl_precond",
             "fl_precond_spectral", "fl_solve", "fl_step", "fl_solve_batched", "fl_step_batched", "fl_profile_pass", "fl_op_destroy",
             "fl_last_error", "fl_net_create", "fl_net_nparams", "fl_net_set_params", "fl_net_get_params",
-            "fl_net_forward", "fl_net_grad", "fl_net_train", "fl_learned_pairs", "fl_net_destroy"]
+            "fl_net_forward", "fl_net_grad", "fl_net_train", "fl_learned_pairs", "fl_net_profile", "fl_net_destroy"]
 
 
 class FlError(RuntimeError):
@@ -31,7 +31,7 @@ class FlError(RuntimeError):
 
 
 class WeightsOpts(ctypes.Structure):
-    _fields_ = [("delta_over_h", ctypes.c_double), ("reserved", ctypes.c_int * 6)]
+    _fields_ = [("delta_over_h", ctypes.c_double), ("dst_mode", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -65,6 +65,7 @@ def load(path=LIB_PATH):
         "fl_make_weights": [I, D, D, ctypes.POINTER(I64), ctypes.POINTER(WeightsOpts), P, ctypes.POINTER(P)],
         "fl_op_constants": [P, ctypes.POINTER(D)],
         "fl_op_padded": [P, ctypes.POINTER(I64)],
+        "fl_op_plan": [P, ctypes.POINTER(I64)],
         "fl_op_export": [P, I, P],
         "fl_apply": [P, P, P, I, I64, P, D, D],
         "fl_precond": [P, P, P, I, I64, P, D, D],
@@ -86,6 +87,7 @@ def load(path=LIB_PATH):
         "fl_net_grad": [P, P, ctypes.POINTER(D), P, P, I, I, I],
         "fl_net_train": [P, P, P, P, I, I, I, ctypes.POINTER(I), I, I, D, ctypes.POINTER(ctypes.c_float)],
         "fl_learned_pairs": [P, P, I64, P, I, P, P, I, I],
+        "fl_net_profile": [P, I, I, I, I, ctypes.POINTER(D)],
         "fl_net_destroy": [P],
     }
     for name, args in sig.items():
@@ -132,7 +134,7 @@ def solve_opts(pc=FL_PC_FD, mixed=0, maxit=0, inner_tol=0.0, use_x0=0, graph=1, 
 class Op:
     """fl_op handle: the discrete fractional Laplacian M on an n_1 x ... x n_d grid."""
 
-    def __init__(self, d, alpha, h, n, delta_over_h=20.0, stream=None):
+    def __init__(self, d, alpha, h, n, delta_over_h=20.0, stream=None, dst_mode=0):
         lib = load()
         self.d, self.alpha, self.h = int(d), float(alpha), float(h)
         self.n = tuple(int(v) for v in (n if hasattr(n, "__len__") else [n] * d))
@@ -143,7 +145,7 @@ class Op:
             stream = torch.cuda.Stream()
         self.stream = stream
         arr = (ctypes.c_int64 * 3)(*(list(self.n) + [1] * (3 - self.d)))
-        opts = WeightsOpts(delta_over_h, (ctypes.c_int * 6)())
+        opts = WeightsOpts(delta_over_h, dst_mode, (ctypes.c_int * 5)())
         h_ = ctypes.c_void_p()
         _check(lib.fl_make_weights(self.d, self.alpha, self.h, arr, ctypes.byref(opts),
                                    ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h_)))
@@ -172,6 +174,13 @@ class Op:
         out = (ctypes.c_int64 * 3)()
         _check(load().fl_op_padded(self._h, out))
         return tuple(out[i] for i in range(self.d))
+
+    def plan(self):
+        """Sine-transform plan per precision: {"f64": [(form, length) per axis], "f32": [...]}, form 1 direct, 2 chirp-z."""
+        out = (ctypes.c_int64 * 12)()
+        _check(load().fl_op_plan(self._h, out))
+        return {p: [(int(out[3 * i + a]), int(out[6 + 3 * i + a])) for a in range(self.d)]
+                for i, p in enumerate(("f64", "f32"))}
 
     def export(self, which):
         shape = tuple(p // 2 + 1 for p in self.padded())
@@ -381,6 +390,12 @@ class Net:
         _check(load().fl_net_grad(self._h, _ptr(x), (ctypes.c_double * B)(*al), _ptr(gy), _ptr(g), B, H, W))
         self._leave()
         return g
+
+    def profile(self, which, H, W, reps=20):
+        """Average ms per launch (HIP events on the net stream): 0 forward, 1 level-0 conv, 2 input, 3 output layer."""
+        ms = ctypes.c_double()
+        _check(load().fl_net_profile(self._h, which, H, W, reps, ctypes.byref(ms)))
+        return ms.value
 
     def train(self, R, T, A, idx, batch, lr=1e-3):
         """Adam steps over minibatches idx (int array [steps, batch]); returns the loss per step."""

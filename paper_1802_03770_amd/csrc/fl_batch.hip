@@ -211,6 +211,7 @@ struct Batch {
   std::vector<Scalars> hsc;
   Scalars* hpin = nullptr;
   int pc = FL_PC_FD;
+  void* d_true = nullptr;
   hipGraphExec_t g[2] = {nullptr, nullptr};
   int gpc[2] = {-1, -1};
   ~Batch() {
@@ -526,11 +527,12 @@ static fl_status batch_solve(Batch& bt, double tol, const fl_solve_opts* o, int 
   }
   // true residuals (FP64) into q
   {
-    std::vector<Prob> tr = bt.t64.h_res;
-    for (int p = 0; p < np; ++p) tr[p].out = bt.b64[p].q;
-    void* d;
-    STCHK(upload_vec(bt, tr.data(), np * sizeof(Prob), &d));
-    STCHK(bt_resid<double>(bt.t64, (const Prob*)d, s));
+    if (!bt.d_true) {  // residual role writing q, built once per batch
+      std::vector<Prob> tr = bt.t64.h_res;
+      for (int p = 0; p < np; ++p) tr[p].out = bt.b64[p].q;
+      STCHK(upload_vec(bt, tr.data(), np * sizeof(Prob), &bt.d_true));
+    }
+    STCHK(bt_resid<double>(bt.t64, (const Prob*)bt.d_true, s));
     for (int p = 0; p < np; ++p) LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, bt.t64.h_iter[p], (int)S_DOT, (int)FIN_RR);
     STCHK(read_all(bt, bt.sc64, s));
     for (int p = 0; p < np; ++p) out[p].rel_res_true = ff[p] > 0 ? std::sqrt(bt.hsc[p].rr / ff[p]) : 0.0;

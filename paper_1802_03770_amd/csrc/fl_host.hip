@@ -102,7 +102,7 @@ template <typename T> static std::vector<cx<T>> host_twiddles(int L) {
   return t;
 }
 
-template <typename T> static fl_status build_axis(fl_op op, int a) {
+template <typename T> static fl_status build_axis(fl_op op, int a, int form) {
   Axis& A = op->ax[tix<T>()][a];
   const int n = op->n[a];
   A.n = n;
@@ -112,7 +112,8 @@ template <typename T> static fl_status build_axis(fl_op op, int a) {
   STCHK(upload(op, host_twiddles<T>(A.P), &A.fft.tw));
   // sine transform: direct (odd extension of length 2(n+1), two lines per FFT
   // line) when 2(n+1) factors over the wide radix set, else the chirp-z identity
-  A.dst_direct = make_radices(2 * (n + 1), A.dst, true) ? 1 : 0;
+  A.dst_direct = (form != 2 && make_radices(2 * (n + 1), A.dst, true)) ? 1 : 0;
+  op->dst_form[tix<T>()][a] = A.dst_direct ? 1 : 2;
   const int Lb = A.dst_direct ? 2 * (n + 1) : smooth_at_least(2 * n - 1);
   if (!A.dst_direct && !make_radices(Lb, A.dst)) return fail(FL_E_UNSUPPORTED, "sine transform length");
   STCHK(upload(op, host_twiddles<T>(Lb), &A.dst.tw));
@@ -189,6 +190,25 @@ static fl_status build_symbol(fl_op op) {
   return FL_OK;
 }
 
+template <typename T> static fl_status profile_t(fl_op op, int pass, int reps, double* avg_ms);
+
+// Autotuner of the sine-transform plan: where some axis admits the direct odd
+// extension, time the whole preconditioner with the direct plans and with the
+// chirp-z plans (same workspace, HIP events on the op stream) and keep the
+// faster for this precision.
+template <typename T> static fl_status autotune_dst(fl_op op) {
+  bool any = false;
+  for (int a = 0; a < op->d; ++a) any = any || op->dst_form[tix<T>()][a] == 1;
+  if (!any) return FL_OK;
+  double t_direct = 0.0, t_chirp = 0.0;
+  STCHK(profile_t<T>(op, 7, 4, &t_direct));
+  for (int a = 0; a < op->d; ++a) STCHK(build_axis<T>(op, a, 2));
+  STCHK(profile_t<T>(op, 7, 4, &t_chirp));
+  if (t_direct <= t_chirp)
+    for (int a = 0; a < op->d; ++a) STCHK(build_axis<T>(op, a, 1));
+  return FL_OK;
+}
+
 static fl_status make_op(int d, double alpha, double h, const int64_t* n, const fl_weights_opts* o,
                          void* stream, fl_op* out) {
   if (!out) return fail(FL_E_INVALID, "out is NULL");
@@ -228,9 +248,10 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
     memset(&op->ax[0][a], 0, sizeof(Axis));
     memset(&op->ax[1][a], 0, sizeof(Axis));
   }
+  op->dst_mode = (o && o->dst_mode >= 0 && o->dst_mode <= 2) ? o->dst_mode : 0;
   for (int a = 0; a < d; ++a) {
-    if ((st = build_axis<double>(op, a)) != FL_OK) return bail(st);
-    if ((st = build_axis<float>(op, a)) != FL_OK) return bail(st);
+    if ((st = build_axis<double>(op, a, op->dst_mode == 2 ? 2 : 1)) != FL_OK) return bail(st);
+    if ((st = build_axis<float>(op, a, op->dst_mode == 2 ? 2 : 1)) != FL_OK) return bail(st);
   }
   hipStream_t s = op->stream;
   if (launch(k_constants, dim3(1), dim3(256), 0, s, d, alpha, h, op->c, op->d_cst) != hipSuccess)
@@ -242,6 +263,10 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
   if (hipMemcpyAsync(op->cst, op->d_cst, 8 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return bail(fail(FL_E_HIP, "constants readback"));
+  if (op->dst_mode == 0) {
+    if ((st = autotune_dst<double>(op)) != FL_OK) return bail(st);
+    if ((st = autotune_dst<float>(op)) != FL_OK) return bail(st);
+  }
   *out = op;
   return FL_OK;
 }
@@ -625,6 +650,17 @@ fl_status fl_op_constants(fl_op op, double out[8]) {
 fl_status fl_op_padded(fl_op op, int64_t* out) {
   if (!op || !out) return fail(FL_E_INVALID, "NULL argument");
   for (int a = 0; a < op->d; ++a) out[a] = op->P[a];
+  return FL_OK;
+}
+
+fl_status fl_op_plan(fl_op op, int64_t* out) {
+  if (!op || !out) return fail(FL_E_INVALID, "NULL argument");
+  for (int i = 0; i < 12; ++i) out[i] = 0;
+  for (int p = 0; p < 2; ++p)
+    for (int a = 0; a < op->d; ++a) {
+      out[3 * p + a] = op->dst_form[p][a];
+      out[6 + 3 * p + a] = op->ax[p][a].dst.L;
+    }
   return FL_OK;
 }
 

@@ -1043,6 +1043,49 @@ fl_status fl_learned_pairs(fl_op op, const double* e, int64_t e_stride, const do
   return FL_OK;
 }
 
+fl_status fl_net_profile(fl_net net, int which, int H, int W, int reps, double* avg_ms) {
+  if (!net || !avg_ms || reps < 1) return fail(FL_E_INVALID, "NULL argument or reps < 1");
+  if (which < 0 || which > 3) return fail(FL_E_INVALID, "which must be 0..3");
+  STCHK(check_grid(1, H, W));
+  STCHK(net_reserve(net, 1, H, W));
+  STCHK(net_alphas(net, 1));
+  hipStream_t s = net->stream;
+  const long px = (long)H * W;
+  LAUNCH(k_fill<float>, dim3(nblocks_vec(px)), dim3(256), 0, s, net->xb, 0.5f, px);
+  LAUNCH(k_fill<float>, dim3(1), dim3(256), 0, s, net->ab, 1.0f, 1L);
+  STCHK(net_forward(net, net->xb, net->ab, 1, H, W));
+  auto one = [&]() -> fl_status {
+    u16** a = net->act;
+    if (which == 0) return net_forward(net, net->xb, net->ab, 1, H, W);
+    if (which == 1) {
+      Stage st = {a[A0], a[C1], nullptr};
+      LAUNCH((k_conv32<SM_UPADD, EPI_RELU>), dim3(conv_blocks(1, H, W)), dim3(256), 0, s, st,
+             (const u16*)(net->fw + LU0 * PACK), (const float*)(net->th + OFF_L32 + LU0 * L32SZ + L32W), a[C0], 1, H, W);
+      return FL_OK;
+    }
+    if (which == 2) {
+      LAUNCH(k_cin_fwd, dim3(nblocks_vec(px)), dim3(256), 0, s, (const float*)net->xb, (const float*)net->ab,
+             (const float*)net->th, a[A0], 1, H, W);
+      return FL_OK;
+    }
+    LAUNCH(k_cout_fwd, dim3(nblocks_vec(px)), dim3(256), 0, s, (const u16*)a[C0], (const float*)net->th, net->y, 1, H, W);
+    return FL_OK;
+  };
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; ++i) STCHK(one());
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = (double)ms / reps;
+  return FL_OK;
+}
+
 fl_status fl_net_destroy(fl_net net) {
   if (!net) return FL_OK;
   if (net->stream) (void)hipStreamSynchronize(net->stream);

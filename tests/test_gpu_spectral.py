@@ -151,3 +151,35 @@ def test_full_size_tau_sampled():
     for k0, k1 in [(0, 0), (0, 1), (5, 700), (1023, 1023), (511, 3)]:
         want = C * h ** -alpha * float(G[k0] @ om @ G[k1])
         assert abs(got[k0, k1] - want) <= 1e-11 * abs(got).max(), (k0, k1)
+
+
+@pytest.mark.parametrize("n", [(37,), (64, 64), (48, 40), (9, 10, 12), (1024,)])
+@pytest.mark.parametrize("mode", [1, 2])
+def test_precond_both_sine_plans(n, mode):
+    # the two sine-transform plans the autotuner chooses between: direct odd
+    # extension (mode 1, where 2(n+1) factors over radices <= 43) and chirp-z
+    _say("sine plan", mode, n)
+    fl = _fl()
+    from oracle import precond as PCO
+    d, alpha = len(n), 1.1
+    h = 2.0 / (max(n) + 1)
+    op = fl.Op(d, alpha, h, n, dst_mode=mode)
+    plan = op.plan()
+    if mode == 2:
+        assert all(f == 2 for f, _ in plan["f64"] + plan["f32"])
+    r = white_noise(n, 8)
+    want = PCO.apply_inverse(r, PCO.pc_scale(d, alpha, h))
+    assert _rel(op.precond(_dev(r)).cpu().numpy(), want) <= 1e-12
+    assert _rel(op.precond(_dev(r, torch.float32)).cpu().numpy(), want) <= 2e-5
+    m = SP.tau_eigenvalues(d, alpha, n)
+    want_s = SP.apply_tau_inverse(r, m, O.Operator(d, alpha, h, n).C * h ** -alpha)
+    assert _rel(op.precond(_dev(r), kind=fl.FL_PC_SPECTRAL).cpu().numpy(), want_s) <= 1e-12
+
+
+def test_autotuned_plan_is_recorded():
+    fl = _fl()
+    op = fl.Op(2, 1.0, 2.0 / 1025, (1024, 1024))
+    plan = op.plan()
+    for p in ("f64", "f32"):
+        for form, L in plan[p]:
+            assert (form, L) in ((1, 2050), (2, 2048)), plan

@@ -19,18 +19,17 @@ def bump_field(n, d, nbumps, seed, width=(0.1, 0.3), centre=(-0.6, 0.6), lo=-1.0
     w = rng.uniform(width[0], width[1], size=nbumps)
     a = rng.standard_normal(nbumps)
     x, h = grid_axis(n, lo, hi)
-    out = np.zeros((n,) * d)
-    for g in range(nbumps):
-        val = a[g]
-        # separable evaluation: product over axes of exp(-(x - c)^2 / (2 w^2))
-        field = np.ones((1,) * d)
-        for ax in range(d):
-            e = np.exp(-((x - c[g, ax]) ** 2) / (2.0 * w[g] ** 2))
-            shape = [1] * d
-            shape[ax] = n
-            field = field * e.reshape(shape)
-        out += val * field
-    return np.ascontiguousarray(out), h
+    # separable evaluation: bump g is a_g prod_ax exp(-(x - c_{g,ax})^2 / (2 w_g^2));
+    # the sum over bumps is a product of per-axis factor matrices E[ax][g, i]
+    E = [np.exp(-((x[None, :] - c[:, ax:ax + 1]) ** 2) / (2.0 * w[:, None] ** 2)) for ax in range(d)]
+    acc = a[:, None] * E[0]  # [G, n]
+    for ax in range(1, d):
+        acc = (acc[:, :, None] * E[ax][:, None, :]).reshape(nbumps, -1) if ax < d - 1 else acc
+    if d == 1:
+        out = acc.sum(axis=0)
+    else:
+        out = acc.T @ E[d - 1]  # [prod n_{<d-1}, n]
+    return np.ascontiguousarray(out.reshape((n,) * d)), h
 
 
 def white_noise(shape, seed):
