@@ -363,18 +363,116 @@ __device__ __forceinline__ void cstage(Line<T> buf, const cx<T>* __restrict__ tw
   __syncthreads();
 }
 
-template <typename T, int L, int TPL, bool INV, int S, int NS>
-__device__ __forceinline__ void cstages(Line<T> buf, const cx<T>* __restrict__ tw, int lane) {
-  if constexpr (S < c_nst(L)) {
-    constexpr int R = c_radix(L, S);
-    cstage<T, R, L, NS, TPL, INV>(buf, tw, lane);
-    cstages<T, L, TPL, INV, S + 1, NS * R>(buf, tw, lane);
+// Output group G of a split prime stage: pairs (y_k, y_{R-k}) for
+// k = G*KG+1 .. min(H, G*KG+KG) of butterfly j (group 0 also y_0), from the
+// conjugate-pair sums s_q and differences d_q stored in the auxiliary line.
+template <typename T, int R, int NS, int KG, bool INV, int G>
+__device__ __forceinline__ void split_outputs(Line<T> aux, Line<T> buf, int j, int base, const T* cs, const T* sn) {
+  constexpr int H = (R - 1) / 2;
+  constexpr int K0 = G * KG + 1, K1 = (G * KG + KG < H) ? G * KG + KG : H, NK = K1 - K0 + 1;
+  const cx<T> a0 = aux[j * R];
+  cx<T> re[NK], im[NK];
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    re[i] = a0;
+    im[i] = {0, 0};
+  }
+  cx<T> y0 = a0;
+#pragma unroll
+  for (int q = 1; q <= H; ++q) {
+    const cx<T> sq = aux[j * R + q], dq = aux[j * R + H + q];
+    if (G == 0) y0 = cadd(y0, sq);
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      const int m = (q * (K0 + i)) % R;
+      const T c = m <= H ? cs[m] : cs[R - m];
+      const T sg = m <= H ? sn[m] : -sn[R - m];
+      re[i].x += sq.x * c;
+      re[i].y += sq.y * c;
+      im[i].x += dq.x * sg;
+      im[i].y += dq.y * sg;
+    }
+  }
+  if (G == 0) buf[base] = y0;
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    const cx<T> yp = {re[i].x + im[i].y, re[i].y - im[i].x};
+    const cx<T> ym = {re[i].x - im[i].y, re[i].y + im[i].x};
+    buf[base + (K0 + i) * NS] = INV ? ym : yp;
+    buf[base + (R - K0 - i) * NS] = INV ? yp : ym;
   }
 }
 
+template <typename T, int R, int NS, int KG, bool INV, int G, int NG>
+__device__ __forceinline__ void split_dispatch(int gi, Line<T> aux, Line<T> buf, int j, int base, const T* cs,
+                                               const T* sn) {
+  if constexpr (G < NG) {
+    if (gi == G)
+      split_outputs<T, R, NS, KG, INV, G>(aux, buf, j, base, cs, sn);
+    else
+      split_dispatch<T, R, NS, KG, INV, G + 1, NG>(gi, aux, buf, j, base, cs, sn);
+  }
+}
+
+// Radix-R stage for a large odd prime R (>= 17) split over lanes, so that no
+// lane holds a whole butterfly: phase A writes, per butterfly j, the
+// twiddled a_0 and the pair sums s_q = a_q + a_{R-q} and differences
+// d_q = a_q - a_{R-q} (q = 1..H) into the auxiliary line (NB * R = L entries);
+// phase B has each lane form KG output pairs of one butterfly from them, with
+// y_k = a_0 + sum_q s_q cos(2 pi q k/R) -+ i sum_q d_q sin(2 pi q k/R).
+template <typename T, int R, int L, int NS, int TPL, bool INV>
+__device__ __forceinline__ void cstage_split(Line<T> buf, Line<T> aux, const cx<T>* __restrict__ tw, int lane) {
+  constexpr int NB = L / R, H = (R - 1) / 2, KG = 4, NG = (H + KG - 1) / KG;
+  constexpr int TSTEP = L / (NS * R);
+  for (int t = lane; t < NB * (H + 1); t += TPL) {
+    const int j = t / (H + 1), q = t % (H + 1);
+    const int k = j % NS;
+    if (q == 0) {
+      aux[j * R] = buf[j];
+    } else {
+      cx<T> u = buf[j + q * NB], w = buf[j + (R - q) * NB];
+      if (NS > 1) {
+        const cx<T> t1 = tw[q * k * TSTEP], t2 = tw[(R - q) * k * TSTEP];
+        u = INV ? cmulc(u, t1) : cmul(u, t1);
+        w = INV ? cmulc(w, t2) : cmul(w, t2);
+      }
+      aux[j * R + q] = cadd(u, w);
+      aux[j * R + H + q] = csub(u, w);
+    }
+  }
+  T cs[H + 1], sn[H + 1];
+#pragma unroll
+  for (int m = 1; m <= H; ++m) {
+    const cx<T> w = tw[m * NB];  // e^{-2 pi i m / R}
+    cs[m] = w.x;
+    sn[m] = -w.y;
+  }
+  __syncthreads();
+  for (int t = lane; t < NB * NG; t += TPL) {
+    const int j = t / NG, gi = t % NG;
+    const int k = j % NS;
+    const int base = (j / NS) * NS * R + k;
+    split_dispatch<T, R, NS, KG, INV, 0, NG>(gi, aux, buf, j, base, cs, sn);
+  }
+  __syncthreads();
+}
+
+template <typename T, int L, int TPL, bool INV, int S, int NS>
+__device__ __forceinline__ void cstages(Line<T> buf, Line<T> aux, const cx<T>* __restrict__ tw, int lane) {
+  if constexpr (S < c_nst(L)) {
+    constexpr int R = c_radix(L, S);
+    if constexpr (R >= 17)
+      cstage_split<T, R, L, NS, TPL, INV>(buf, aux, tw, lane);
+    else
+      cstage<T, R, L, NS, TPL, INV>(buf, tw, lane);
+    cstages<T, L, TPL, INV, S + 1, NS * R>(buf, aux, tw, lane);
+  }
+}
+
+// aux: a second line of length L, used as scratch by prime stages >= 17
 template <typename T, int L, bool INV>
-__device__ __forceinline__ void fft_fixed(Line<T> buf, const cx<T>* __restrict__ tw, int lane) {
-  cstages<T, L, c_fixed_tpl(L), INV, 0, 1>(buf, tw, lane);
+__device__ __forceinline__ void fft_fixed(Line<T> buf, Line<T> aux, const cx<T>* __restrict__ tw, int lane) {
+  cstages<T, L, c_fixed_tpl(L), INV, 0, 1>(buf, aux, tw, lane);
 }
 
 // Dispatch to a specialisation; false when the plan has none.
@@ -383,25 +481,25 @@ __device__ __forceinline__ bool fft_try_fixed(Line<T> buf, const FFTPlan& pl, in
   if (!pl.fixed) return false;
   const cx<T>* __restrict__ tw = (const cx<T>*)pl.tw;
   switch (pl.L) {
-    case 2048: fft_fixed<T, 2048, INV>(buf, tw, lane); return true;
-    case 1024: fft_fixed<T, 1024, INV>(buf, tw, lane); return true;
-    case 512: fft_fixed<T, 512, INV>(buf, tw, lane); return true;
-    case 256: fft_fixed<T, 256, INV>(buf, tw, lane); return true;
-    case 128: fft_fixed<T, 128, INV>(buf, tw, lane); return true;
-    case 768: fft_fixed<T, 768, INV>(buf, tw, lane); return true;
+    case 2048: fft_fixed<T, 2048, INV>(buf, buf, tw, lane); return true;
+    case 1024: fft_fixed<T, 1024, INV>(buf, buf, tw, lane); return true;
+    case 512: fft_fixed<T, 512, INV>(buf, buf, tw, lane); return true;
+    case 256: fft_fixed<T, 256, INV>(buf, buf, tw, lane); return true;
+    case 128: fft_fixed<T, 128, INV>(buf, buf, tw, lane); return true;
+    case 768: fft_fixed<T, 768, INV>(buf, buf, tw, lane); return true;
     default: return false;
   }
 }
 template <typename T, bool INV>
-__device__ __forceinline__ bool fft_try_fixed_wide(Line<T> buf, const FFTPlan& pl, int lane) {
+__device__ __forceinline__ bool fft_try_fixed_wide(Line<T> buf, Line<T> aux, const FFTPlan& pl, int lane) {
   if (!pl.fixed) return false;
   const cx<T>* __restrict__ tw = (const cx<T>*)pl.tw;
   switch (pl.L) {
-    case 2050: fft_fixed<T, 2050, INV>(buf, tw, lane); return true;
-    case 1026: fft_fixed<T, 1026, INV>(buf, tw, lane); return true;
-    case 770: fft_fixed<T, 770, INV>(buf, tw, lane); return true;
-    case 258: fft_fixed<T, 258, INV>(buf, tw, lane); return true;
-    case 130: fft_fixed<T, 130, INV>(buf, tw, lane); return true;
+    case 2050: fft_fixed<T, 2050, INV>(buf, aux, tw, lane); return true;
+    case 1026: fft_fixed<T, 1026, INV>(buf, aux, tw, lane); return true;
+    case 770: fft_fixed<T, 770, INV>(buf, aux, tw, lane); return true;
+    case 258: fft_fixed<T, 258, INV>(buf, aux, tw, lane); return true;
+    case 130: fft_fixed<T, 130, INV>(buf, aux, tw, lane); return true;
     default: return false;
   }
 }
@@ -525,7 +623,7 @@ __device__ __forceinline__ void fft_stage_prime_oop(Line<T> src, Line<T> dst, in
 // holding the result.  Used by the sine transforms of length 2(n+1).
 template <typename T, bool INV>
 __device__ __forceinline__ Line<T> fft_line_wide(Line<T> a, Line<T> b, const FFTPlan pl, int lane) {
-  if (fft_try_fixed_wide<T, INV>(a, pl, lane)) return a;  // in place
+  if (fft_try_fixed_wide<T, INV>(a, b, pl, lane)) return a;  // in place (b as scratch)
   const cx<T>* __restrict__ tw = (const cx<T>*)pl.tw;
   int Ns = 1, lg = 0;
   Line<T> src = a, dst = b;

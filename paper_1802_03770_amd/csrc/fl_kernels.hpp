@@ -617,6 +617,19 @@ __device__ __forceinline__ cx<T> sine_pair_get(Line<T> buf, int k) {
   return {(T)-0.5 * z.y, (T)0.5 * z.x};
 }
 
+// Sine-transform line FFT: LF = 0 follows the run-time plan (any direct or
+// chirp-z form); LF > 0 is a kernel specialised for the direct form of that
+// length, which then contains no other path (and no other register demand).
+template <typename T, bool INV, int LF>
+__device__ __forceinline__ Line<T> dst_fft(Line<T> a, Line<T> b, const FFTPlan& pl, int lane) {
+  if constexpr (LF > 0) {
+    fft_fixed<T, LF, INV>(a, b, (const cx<T>*)pl.tw, lane);
+    return a;
+  } else {
+    return fft_line_wide<T, INV>(a, b, pl, lane);
+  }
+}
+
 enum { DPRO_PLAIN = 0, DPRO_UPD = 1 };
 enum { DEPI_STORE = 0, DEPI_FINAL = 1, DEPI_Z = 2 };
 
@@ -627,7 +640,7 @@ enum { DEPI_STORE = 0, DEPI_FINAL = 1, DEPI_Z = 2 };
 //  DEPI_STORE: out = result (a first pass of a multi-axis transform)
 //  DEPI_FINAL: out = norm * result
 //  DEPI_Z:     z = norm * result, r.z partials into slot parity ^ 1.
-template <typename T, int DPRO, int DEPI>
+template <typename T, int DPRO, int DEPI, int LF = 0>
 __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bool check_done, int nblk, int blk) {
   if (check_done && pb.sc->done) return;
   double alpha = 0.0;
@@ -645,7 +658,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[pb.d - 1];
   const int n = A.n, Lf = A.dst.L, tpl = A.dst.tpl;
-  const bool direct = A.dst_direct;
+  const bool direct = LF > 0 ? true : A.dst_direct;
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   // direct: a ping-pong pair of lines per FFT line
   Line<T> buf = line_at<T>(smem, direct ? 2 * g : g, Lf);
@@ -687,7 +700,11 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   if (DPRO == DPRO_UPD) put_partial(pb, S_RR, acc, nblk, blk);
   __syncthreads();
   Line<T> res = buf;  // line holding the transform result
-  if (direct) res = fft_line_wide<T, false>(buf, buf2, A.dst, lane); else dst_line<T>(buf, A, lane, tpl);
+  if (direct) {
+    res = dst_fft<T, false, LF>(buf, buf2, A.dst, lane);
+  } else {
+    if constexpr (LF == 0) dst_line<T>(buf, A, lane, tpl);
+  }
   if (pb.d == 1) {
     const T* ev = (const T*)A.eig;
     if (direct) {
@@ -702,7 +719,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
         res[n + 1] = {0, 0};
       }
       __syncthreads();
-      res = fft_line_wide<T, false>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
+      res = dst_fft<T, false, LF>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
     } else {
       const T* tau = (const T*)pb.tau;
       for (int k = lane; k < n; k += tpl)
@@ -711,7 +728,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
         buf[k].x = pb.pmul ? buf[k].x * e : buf[k].x / e;
       }
       __syncthreads();
-      dst_line<T>(buf, A, lane, tpl);
+      if constexpr (LF == 0) dst_line<T>(buf, A, lane, tpl);
     }
   }
   double norm = 1.0;
@@ -751,14 +768,14 @@ __device__ __forceinline__ double eig_tail(const Prob& pb, long c) {
   return (double)((const T*)pb.ax[1].eig)[c / n2] + (double)((const T*)pb.ax[2].eig)[c % n2];
 }
 
-template <typename T, bool SCALE>
+template <typename T, bool SCALE, int LF = 0>
 __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, bool check_done, int blk0, int nblk) {
   if (check_done && pb.sc->done) return;
   const long blk = xcd_tile(blk0, nblk);
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[dg.axis];
   const int n = A.n, Lf = A.dst.L, tpl = A.dst.tpl;
-  const bool direct = A.dst_direct;
+  const bool direct = LF > 0 ? true : A.dst_direct;
   const int GF = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   const int G = direct ? 2 * GF : GF;  // real lines per block
   const long tiles = (dg.gs + G - 1) / G;
@@ -795,7 +812,11 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   Line<T> buf = line_at<T>(smem, direct ? 2 * g : g, Lf);
   Line<T> buf2 = line_at<T>(smem, 2 * g + 1, Lf);
   Line<T> res = buf;
-  if (direct) res = fft_line_wide<T, false>(buf, buf2, A.dst, lane); else dst_line<T>(buf, A, lane, tpl);
+  if (direct) {
+    res = dst_fft<T, false, LF>(buf, buf2, A.dst, lane);
+  } else {
+    if constexpr (LF == 0) dst_line<T>(buf, A, lane, tpl);
+  }
   if (SCALE) {
     const T* ev = (const T*)A.eig;
     // sine-basis diagonal: mode (k, c) of the axis-0 pass is table entry (k-1) gs + c
@@ -825,7 +846,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
         res[n + 1] = {0, 0};
       }
       __syncthreads();
-      res = fft_line_wide<T, false>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
+      res = dst_fft<T, false, LF>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
     } else {
       const long c = c0 + g;
       const bool ok = c < dg.gs;
@@ -836,7 +857,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
         buf[k].x = pb.pmul ? buf[k].x * e : buf[k].x / e;
       }
       __syncthreads();
-      dst_line<T>(buf, A, lane, tpl);
+      if constexpr (LF == 0) dst_line<T>(buf, A, lane, tpl);
     }
   }
   // every FFT line of the block ends in the same member of its ping-pong pair
@@ -980,16 +1001,16 @@ __global__ FL_BOUNDS void k_conv1d_b(const Prob* pbs, Iter it, const int* nb) {
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
   conv1d_body<T, PRO, EPI>(pbs[blockIdx.y], it, nb[blockIdx.y], blockIdx.x);
 }
-template <typename T, int DPRO, int DEPI> __global__ FL_BOUNDS void k_dst_rows(Prob pb, Iter it, int chk) {
-  dst_rows_body<T, DPRO, DEPI>(pb, it, chk, gridDim.x, blockIdx.x);
+template <typename T, int DPRO, int DEPI, int LF = 0> __global__ FL_BOUNDS void k_dst_rows(Prob pb, Iter it, int chk) {
+  dst_rows_body<T, DPRO, DEPI, LF>(pb, it, chk, gridDim.x, blockIdx.x);
 }
 template <typename T, int DPRO, int DEPI>
 __global__ FL_BOUNDS void k_dst_rows_b(const Prob* pbs, Iter it, int chk, const int* nb) {
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
   dst_rows_body<T, DPRO, DEPI>(pbs[blockIdx.y], it, chk, nb[blockIdx.y], blockIdx.x);
 }
-template <typename T, bool SCALE> __global__ FL_BOUNDS void k_dst_cols(Prob pb, DGeom dg, int chk) {
-  dst_cols_body<T, SCALE>(pb, dg, chk, blockIdx.x, gridDim.x);
+template <typename T, bool SCALE, int LF = 0> __global__ FL_BOUNDS void k_dst_cols(Prob pb, DGeom dg, int chk) {
+  dst_cols_body<T, SCALE, LF>(pb, dg, chk, blockIdx.x, gridDim.x);
 }
 template <typename T, bool SCALE>
 __global__ FL_BOUNDS void k_dst_cols_b(const Prob* pbs, const DGeom* dgs, int chk, const int* nb) {

@@ -67,23 +67,36 @@ __device__ __forceinline__ uint4 pk8(const float v[8]) {
 // ---------------------------------------------------------------------------
 // Staging of a convolution input (8 channels of one in-bounds pixel)
 // ---------------------------------------------------------------------------
-enum { SM_PLAIN = 0, SM_POOL, SM_UPADD, SM_GPLAIN, SM_GSUMPOOL, SM_GADDUP };
+enum { SM_PLAIN = 0, SM_POOL, SM_UPADD, SM_GPLAIN, SM_GSUMPOOL, SM_GADDUP, SM_INPUT };
 //  PLAIN    s0[p]                          (this level)
 //  POOL     mean of s0 over the 2x2 block  (s0 at the finer level)
 //  UPADD    s0[p] + s1[p/2]                (s1 at the coarser level)
 //  GPLAIN   s0[p] * (y[p] > 0)             (gradient through a ReLU)
 //  GSUMPOOL sum of s0 over the 2x2 block * (y[p] > 0)
 //  GADDUP   (s0[p] + s1[p/2] / 4) * (y[p] > 0)
+//  INPUT    channels (x[p], alpha_b - 1, 0, ..., 0): the input layer as a
+//           32 -> 32 convolution whose weights vanish beyond input channel 1
 struct Stage {
   const u16* s0;
   const u16* s1;
   const u16* y;
+  const float* xf = nullptr;  // SM_INPUT: network input x, FP32 [B][H][W]
+  const float* al = nullptr;  // SM_INPUT: alpha per image
 };
 
 __device__ __forceinline__ long pix(int b, int y, int x, int H, int W) { return (((long)b * H + y) * W + x) * CH; }
 
 template <int SM>
 __device__ __forceinline__ void stage8(const Stage& st, int b, int y, int x, int H, int W, int c, float v[8]) {
+  if constexpr (SM == SM_INPUT) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = 0.f;
+    if (c == 0) {
+      v[0] = st.xf[((long)b * H + y) * W + x];
+      v[1] = st.al[b] - 1.f;
+    }
+    return;
+  }
   if (SM == SM_PLAIN) {
     ld8(st.s0 + pix(b, y, x, H, W) + c, v);
   } else if (SM == SM_POOL || SM == SM_GSUMPOOL) {
@@ -109,7 +122,7 @@ __device__ __forceinline__ void stage8(const Stage& st, int b, int y, int x, int
       for (int i = 0; i < 8; ++i) v[i] += f * t[i];
     }
   }
-  if (SM >= SM_GPLAIN) {
+  if (SM >= SM_GPLAIN && SM <= SM_GADDUP) {
     float a[8];
     ld8(st.y + pix(b, y, x, H, W) + c, a);
 #pragma unroll
@@ -135,15 +148,85 @@ __device__ __forceinline__ void stage_tile(u16* tile, const Stage& st, int b, in
   }
 }
 
+// Forward-mode staging with all global loads of a lane issued before any LDS
+// store (the tile has SY*SX*4 = 1584 16-byte chunks, NIT = 7 per lane): the
+// memory latency is paid once per tile instead of once per chunk.
+template <int SM>
+__device__ __forceinline__ void stage_tile_batched(u16* tile, const Stage& st, int b, int y0, int x0, int H, int W) {
+  constexpr int NE = SY * SX * 4, NIT = (NE + 255) / 256;
+  constexpr int NQ = SM == SM_POOL ? 4 : SM == SM_UPADD ? 2 : 1;
+  if constexpr (SM == SM_INPUT) {
+    stage_tile<SM>(tile, st, b, y0, x0, H, W);
+    return;
+  }
+  uint4 q[NIT][NQ];
+  bool ok[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int e = threadIdx.x + it * 256;
+    const int c = (e & 3) * 8, p = e >> 2;
+    const int yy = y0 + p / SX - 1, xx = x0 + p % SX - 1;
+    ok[it] = e < NE && yy >= 0 && yy < H && xx >= 0 && xx < W;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) q[it][k] = make_uint4(0, 0, 0, 0);
+    if (ok[it]) {
+      if (SM == SM_PLAIN) {
+        q[it][0] = *(const uint4*)(st.s0 + pix(b, yy, xx, H, W) + c);
+      } else if (SM == SM_UPADD) {
+        q[it][0] = *(const uint4*)(st.s0 + pix(b, yy, xx, H, W) + c);
+        q[it][1] = *(const uint4*)(st.s1 + pix(b, yy >> 1, xx >> 1, H >> 1, W >> 1) + c);
+      } else {  // SM_POOL
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          q[it][k] = *(const uint4*)(st.s0 + pix(b, 2 * yy + (k >> 1), 2 * xx + (k & 1), 2 * H, 2 * W) + c);
+      }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int e = threadIdx.x + it * 256;
+    if (e >= NE) continue;
+    const int c = (e & 3) * 8, p = e >> 2;
+    if (SM == SM_PLAIN) {
+      *(uint4*)(tile + p * CH + c) = q[it][0];
+    } else {
+      float v[8], t[8];
+      const unsigned* w0 = (const unsigned*)&q[it][0];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        v[2 * i] = __uint_as_float(w0[i] << 16);
+        v[2 * i + 1] = __uint_as_float(w0[i] & 0xffff0000u);
+      }
+#pragma unroll
+      for (int k = 1; k < NQ; ++k) {
+        const unsigned* wk = (const unsigned*)&q[it][k];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          t[2 * i] = __uint_as_float(wk[i] << 16);
+          t[2 * i + 1] = __uint_as_float(wk[i] & 0xffff0000u);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] += t[i];
+      }
+      if (SM == SM_POOL)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] *= 0.25f;
+      *(uint4*)(tile + p * CH + c) = pk8(v);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 32 -> 32 convolution on MFMA (forward with bias + ReLU, or the transposed
 // convolution of the reverse pass with flipped, transposed weights)
 // ---------------------------------------------------------------------------
-enum { EPI_RELU = 0, EPI_NONE = 1 };
+// EPI_RELU: bias + ReLU, BF16 out; EPI_NONE: BF16 out; EPI_OUT: the output
+// layer, output channel 0 only, FP32 into yout ([B][H][W]).
+enum { EPI_RELU = 0, EPI_NONE = 1, EPI_OUT = 2 };
 
 template <int SM, int EPI>
 __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict__ wpack, const float* __restrict__ bias,
-                                                u16* __restrict__ out, int B, int H, int W) {
+                                                u16* __restrict__ out, int B, int H, int W, float* __restrict__ yout) {
   __shared__ __align__(16) u16 tile[SY * SX * CH];
   const int tilesX = (W + TX - 1) / TX, tilesY = (H + TY - 1) / TY;
   int t = blockIdx.x;
@@ -152,7 +235,10 @@ __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict_
   const int ty = t % tilesY, b = t / tilesY;
   if (b >= B) return;
   const int x0 = tx * TX, y0 = ty * TY;
-  stage_tile<SM>(tile, st, b, y0, x0, H, W);
+  if constexpr (SM == SM_PLAIN || SM == SM_UPADD || SM == SM_POOL)
+    stage_tile_batched<SM>(tile, st, b, y0, x0, H, W);
+  else
+    stage_tile<SM>(tile, st, b, y0, x0, H, W);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   bf16x8 wf[18];
 #pragma unroll
@@ -173,14 +259,23 @@ __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict_
   }
   // lane holds pixel (lane & 31) of each 32-pixel half, channels
   // g*8 + (lane>>5)*4 + 0..3 in acc[4g .. 4g+3]
-  const int yo = y0 + wave;
-  if (yo >= H) return;
+  if constexpr (EPI == EPI_OUT) {  // channel 0 sits in acc[0] of lanes 0..31
+    const int yo = y0 + wave;
+    if (lane < 32 && yo < H) {
+      const int px0 = x0 + lane, px1 = x0 + 32 + lane;
+      if (px0 < W) yout[((long)b * H + yo) * W + px0] = acc0[0] + bias[0];
+      if (px1 < W) yout[((long)b * H + yo) * W + px1] = acc1[0] + bias[0];
+    }
+    return;
+  }
+  // the wave's 64 x 32 outputs go through LDS so that the global stores are
+  // contiguous 16-byte chunks
+  __syncthreads();  // every wave is done reading the staged tile
+  u16* ot = tile + wave * 64 * CH;
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
-    const int px = x0 + m * 32 + (lane & 31);
-    if (px >= W) continue;
     const f32x16& a = m ? acc1 : acc0;
-    u16* o = out + pix(b, yo, px, H, W);
+    const int pl = m * 32 + (lane & 31);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int cb = g * 8 + (lane >> 5) * 4;
@@ -192,8 +287,17 @@ __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict_
       }
       const unsigned lo = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
       const unsigned hi = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
-      *(uint2*)(o + cb) = make_uint2(lo, hi);
+      *(uint2*)(ot + pl * CH + cb) = make_uint2(lo, hi);
     }
+  }
+  __syncthreads();
+  const int yo = y0 + wave;
+  if (yo >= H) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = lane + 64 * k, pl = e >> 2, qq = (e & 3) * 8;
+    const int px = x0 + pl;
+    if (px < W) *(uint4*)(out + pix(b, yo, px, H, W) + qq) = *(const uint4*)(ot + pl * CH + qq);
   }
 }
 
@@ -256,34 +360,6 @@ __global__ __launch_bounds__(256) void k_conv32_wgrad(Stage si, Stage sg, float*
 // ---------------------------------------------------------------------------
 // Input layer (2 -> 32) and output layer (32 -> 1): VALU, FP32 weights
 // ---------------------------------------------------------------------------
-// a0 = relu(cin([x, alpha_b - 1])), x FP32 [B][H][W]
-__global__ __launch_bounds__(256) void k_cin_fwd(const float* __restrict__ x, const float* __restrict__ alpha,
-                                                 const float* __restrict__ th, u16* __restrict__ a0, int B, int H, int W) {
-  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (idx >= (long)B * H * W) return;
-  const int xx = (int)(idx % W), yy = (int)((idx / W) % H), b = (int)(idx / ((long)W * H));
-  const float ac = alpha[b] - 1.f;
-  float acc[CH];
-#pragma unroll
-  for (int c = 0; c < CH; ++c) acc[c] = th[OFF_CIN_B + c];
-  for (int tap = 0; tap < 9; ++tap) {
-    const int y2 = yy + tap / 3 - 1, x2 = xx + tap % 3 - 1;
-    if (y2 < 0 || y2 >= H || x2 < 0 || x2 >= W) continue;
-    const float r = x[((long)b * H + y2) * W + x2];
-    const float* w = th + tap * 2 * CH;
-#pragma unroll
-    for (int c = 0; c < CH; ++c) acc[c] += r * w[c] + ac * w[CH + c];
-  }
-  u16* o = a0 + idx * CH;
-#pragma unroll
-  for (int c = 0; c < CH; c += 8) {
-    float v[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = fmaxf(acc[c + i], 0.f);
-    *(uint4*)(o + c) = pk8(v);
-  }
-}
-
 // Weight gradient of cin: partials of dW[tap][ci][co] (ci: x and alpha - 1) and
 // db, the gradient G staged by SMG; 608 values per block.
 template <int SMG>
@@ -343,49 +419,30 @@ __global__ __launch_bounds__(256) void k_cin_wgrad(const float* __restrict__ x, 
   }
 }
 
-// y = out(c0): FP32 [B][H][W]
-__global__ __launch_bounds__(256) void k_cout_fwd(const u16* __restrict__ c0, const float* __restrict__ th,
-                                                  float* __restrict__ y, int B, int H, int W) {
-  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (idx >= (long)B * H * W) return;
-  const int xx = (int)(idx % W), yy = (int)((idx / W) % H), b = (int)(idx / ((long)W * H));
-  const float* w = th + OFF_OUT;
-  float s = w[9 * CH];
-  for (int tap = 0; tap < 9; ++tap) {
-    const int y2 = yy + tap / 3 - 1, x2 = xx + tap % 3 - 1;
-    if (y2 < 0 || y2 >= H || x2 < 0 || x2 >= W) continue;
-    const u16* a = c0 + pix(b, y2, x2, H, W);
-#pragma unroll
-    for (int c = 0; c < CH; c += 8) {
-      float v[8];
-      ld8(a + c, v);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) s += v[i] * w[tap * CH + c + i];
-    }
-  }
-  y[idx] = s;
-}
-
-// gc0[p][ci] = sum_tap gy[p - off(tap)] W_out[tap][ci] (transposed convolution)
+// gc0[p][ci] = sum_tap gy[p - off(tap)] W_out[tap][ci] (transposed convolution),
+// four lanes per pixel, eight channels each.
 __global__ __launch_bounds__(256) void k_cout_bwd(const float* __restrict__ gy, const float* __restrict__ th,
                                                   u16* __restrict__ gc0, int B, int H, int W) {
-  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  __shared__ float ws[9 * CH];
+  for (int i = threadIdx.x; i < 9 * CH; i += blockDim.x) ws[i] = th[OFF_OUT + i];
+  __syncthreads();
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long idx = t >> 2;
   if (idx >= (long)B * H * W) return;
+  const int q = (int)(t & 3) * 8;
   const int xx = (int)(idx % W), yy = (int)((idx / W) % H), b = (int)(idx / ((long)W * H));
-  const float* w = th + OFF_OUT;
-  float acc[CH];
+  float acc[8];
 #pragma unroll
-  for (int c = 0; c < CH; ++c) acc[c] = 0.f;
+  for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+#pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
     const int y2 = yy - (tap / 3 - 1), x2 = xx - (tap % 3 - 1);
     if (y2 < 0 || y2 >= H || x2 < 0 || x2 >= W) continue;
     const float g = gy[((long)b * H + y2) * W + x2];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) acc[c] += g * w[tap * CH + c];
+    for (int i = 0; i < 8; ++i) acc[i] += g * ws[tap * CH + q + i];
   }
-  u16* o = gc0 + idx * CH;
-#pragma unroll
-  for (int c = 0; c < CH; c += 8) *(uint4*)(o + c) = pk8(acc + c);
+  *(uint4*)(gc0 + idx * CH + q) = pk8(acc);
 }
 
 // Weight gradient of out: partials of dW[tap][ci] = sum_p c0[p + tap][ci] gy[p], db = sum gy (289 per block)
@@ -444,18 +501,27 @@ __global__ void k_reduce_part(const float* __restrict__ part, int nblk, int stri
 // Packed bf16 weights of the 32 -> 32 layers.  Forward (A operand = W^T):
 // fw[L][tap][half][lane][e] = W_L[tap][half*16 + 8*(lane/32) + e][lane%32].
 // Transposed flipped (reverse pass): bw[L][tap][half][lane][e] =
-// W_L[8 - tap][lane%32][half*16 + 8*(lane/32) + e].
+// W_L[8 - tap][lane%32][half*16 + 8*(lane/32) + e].  Slots L = 7 and 8 of fw
+// hold the input layer (input channels >= 2 zero) and the output layer (output
+// channels >= 1 zero) in the same form.
+constexpr int NPACK = NL32 + 2;
 __global__ void k_pack(const float* __restrict__ th, u16* __restrict__ fw, u16* __restrict__ bw) {
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (idx >= NL32 * PACK) return;
+  if (idx >= NPACK * PACK) return;
   const int L = (int)(idx / PACK);
   const int r = (int)(idx % PACK);
   const int e = r & 7, lane = (r >> 3) & 63, f = r >> 9;
   const int tap = f >> 1, half = f & 1;
-  const float* W = th + OFF_L32 + L * L32SZ;
   const int kk = half * 16 + 8 * (lane >> 5) + e, j = lane & 31;
-  fw[idx] = f2bf(W[((long)tap * CH + kk) * CH + j]);
-  bw[idx] = f2bf(W[((long)(8 - tap) * CH + j) * CH + kk]);
+  if (L < NL32) {
+    const float* W = th + OFF_L32 + L * L32SZ;
+    fw[idx] = f2bf(W[((long)tap * CH + kk) * CH + j]);
+    bw[idx] = f2bf(W[((long)(8 - tap) * CH + j) * CH + kk]);
+  } else if (L == NL32) {
+    fw[idx] = kk < 2 ? f2bf(th[(tap * 2 + kk) * CH + j]) : (u16)0;
+  } else {
+    fw[idx] = j == 0 ? f2bf(th[OFF_OUT + tap * CH + kk]) : (u16)0;
+  }
 }
 
 // Loss (1/count) sum (y - t)^2 per block partials; gy = 2 (y - t) / count.
@@ -511,21 +577,58 @@ __global__ void k_gather(const float* __restrict__ R, const float* __restrict__ 
 }
 
 // Learned-preconditioner input and output on the solver grid (n0 x n1 inside
-// the padded Hp x Wp network grid): xin = r / s, w = r + s y.
+// the padded Hp x Wp network grid): xin = r / s, w = r + s y, with the RMS
+// s = sqrt(rr / (n0 n1)) read from the device (rr = r.r).
 template <typename T>
-__global__ void k_net_in(const T* __restrict__ r, float* __restrict__ xin, int n0, int n1, int Hp, int Wp, double inv_s) {
+__global__ void k_net_in(const T* __restrict__ r, float* __restrict__ xin, int n0, int n1, int Hp, int Wp,
+                         const double* __restrict__ rr) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= (long)Hp * Wp) return;
+  const double ms = *rr / ((double)n0 * n1);
+  const double inv_s = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
   const int yy = (int)(i / Wp), xx = (int)(i % Wp);
   xin[i] = (yy < n0 && xx < n1) ? (float)((double)r[(long)yy * n1 + xx] * inv_s) : 0.f;
 }
 template <typename T>
 __global__ void k_net_out(const T* __restrict__ r, const float* __restrict__ y, T* __restrict__ w, int n0, int n1, int Wp,
-                          double s) {
+                          const double* __restrict__ rr) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= (long)n0 * n1) return;
+  const double sc = sqrt(fmax(*rr, 0.0) / ((double)n0 * n1));
   const int yy = (int)(i / n1), xx = (int)(i % n1);
-  w[i] = (T)((double)r[i] + s * (double)y[(long)yy * Wp + xx]);
+  w[i] = (T)((double)r[i] + sc * (double)y[(long)yy * Wp + xx]);
+}
+
+// Flexible CG scalars live on the device: fs[0] = r.z, fs[1] = z.q_old,
+// fs[2] = p.q, fs[3] = p.r, fs[4] = r.r.
+__global__ void k_total_to(Prob pb, int site, double* __restrict__ dst) {
+  const double t = get_total(pb, site);
+  if (threadIdx.x == 0) *dst = t;
+}
+// p = z + beta p, beta = -z.q_old / p_old.q_old (0 on the first iteration)
+template <typename T>
+__global__ void k_fcg_dir(const T* __restrict__ z, T* __restrict__ p, long n, const double* __restrict__ fs, int first) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double beta = (first || !(fs[2] > 0.0)) ? 0.0 : -fs[1] / fs[2];
+  p[i] = beta == 0.0 ? z[i] : (T)((double)z[i] + beta * (double)p[i]);
+}
+// alpha = p.r / p.q; x += alpha p; r -= alpha q; r.r partials (site S_RR)
+template <typename T> __global__ __launch_bounds__(256) void k_fcg_update(Prob pb, long n, const double* __restrict__ fs) {
+  const double pq = fs[2];
+  const double alpha = (pq > 0.0 && isfinite(pq)) ? fs[3] / pq : 0.0;
+  T* x = (T*)pb.x;
+  T* r = (T*)pb.r;
+  const T* p = (const T*)pb.p;
+  const T* q = (const T*)pb.q;
+  double acc = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] += (T)alpha * p[i];
+    const T rv = r[i] - (T)alpha * q[i];
+    r[i] = rv;
+    acc += (double)rv * (double)rv;
+  }
+  put_partial(pb, S_RR, acc, gridDim.x, blockIdx.x);
 }
 
 // Training pairs on the operator's grid (FP64 in): R = r / s, T = (D e - r) / s
@@ -573,9 +676,12 @@ struct fl_net_s {
   float *pin = nullptr, *pout = nullptr;
   void* pw = nullptr;
   float* palpha = nullptr;
+  double* fs = nullptr;   // device scalars of flexible CG
+  double* hfs = nullptr;  // pinned host mirror
   std::vector<void*> owned;
   ~fl_net_s() {
     for (void* p : owned) (void)hipFree(p);
+    if (hfs) (void)hipHostFree(hfs);
   }
   fl_status alloc(void** p, size_t bytes) {
     STCHK(dalloc(p, bytes));
@@ -628,12 +734,15 @@ static fl_status net_forward(fl_net net, const float* x, const float* alpha, int
   STCHK(check_grid(B, H, W));
   STCHK(net_reserve(net, B, H, W));
   hipStream_t s = net->stream;
-  const long px = (long)B * H * W;
   u16** a = net->act;
   const float* th = net->th;
   auto bias = [&](int L) { return th + OFF_L32 + L * L32SZ + L32W; };
   auto fw = [&](int L) { return net->fw + L * PACK; };
-  LAUNCH(k_cin_fwd, dim3(nblocks_vec(px)), dim3(256), 0, s, x, alpha, th, a[A0], B, H, W);
+  {
+    Stage st = {nullptr, nullptr, nullptr, x, alpha};
+    LAUNCH((k_conv32<SM_INPUT, EPI_RELU>), dim3(conv_blocks(B, H, W)), dim3(256), 0, s, st, (const u16*)fw(NL32),
+           th + OFF_CIN_B, a[A0], B, H, W, (float*)nullptr);
+  }
   int h = H, w = W;
   // down path
   const int lay[3] = {LD1, LD2, LD3};
@@ -642,12 +751,12 @@ static fl_status net_forward(fl_net net, const float* x, const float* alpha, int
     w /= 2;
     Stage st = {a[A0 + l - 1], nullptr, nullptr};
     LAUNCH((k_conv32<SM_POOL, EPI_RELU>), dim3(conv_blocks(B, h, w)), dim3(256), 0, s, st, (const u16*)fw(lay[l - 1]),
-           bias(lay[l - 1]), a[A0 + l], B, h, w);
+           bias(lay[l - 1]), a[A0 + l], B, h, w, (float*)nullptr);
   }
   {
     Stage st = {a[A3], nullptr, nullptr};
     LAUNCH((k_conv32<SM_PLAIN, EPI_RELU>), dim3(conv_blocks(B, h, w)), dim3(256), 0, s, st, (const u16*)fw(LB3),
-           bias(LB3), a[C3], B, h, w);
+           bias(LB3), a[C3], B, h, w, (float*)nullptr);
   }
   // up path: c_l = relu(u_l(a_l + up c_{l+1}))
   const int ulay[3] = {LU2, LU1, LU0};
@@ -657,9 +766,13 @@ static fl_status net_forward(fl_net net, const float* x, const float* alpha, int
     w *= 2;
     Stage st = {a[askip[k]], a[acoarse[k]], nullptr};
     LAUNCH((k_conv32<SM_UPADD, EPI_RELU>), dim3(conv_blocks(B, h, w)), dim3(256), 0, s, st, (const u16*)fw(ulay[k]),
-           bias(ulay[k]), a[adst[k]], B, h, w);
+           bias(ulay[k]), a[adst[k]], B, h, w, (float*)nullptr);
   }
-  LAUNCH(k_cout_fwd, dim3(nblocks_vec(px)), dim3(256), 0, s, (const u16*)a[C0], th, net->y, B, H, W);
+  {
+    Stage st = {a[C0], nullptr, nullptr};
+    LAUNCH((k_conv32<SM_PLAIN, EPI_OUT>), dim3(conv_blocks(B, H, W)), dim3(256), 0, s, st, (const u16*)fw(NL32 + 1),
+           th + OFF_OUT + 9 * CH, (u16*)nullptr, B, H, W, net->y);
+  }
   return FL_OK;
 }
 
@@ -680,7 +793,7 @@ static fl_status net_backward(fl_net net, const float* x, const float* alpha, in
     return FL_OK;
   };
   // output layer
-  LAUNCH(k_cout_bwd, dim3(nblocks_vec(px)), dim3(256), 0, s, (const float*)net->gy, th, gr[GC0], B, H, W);
+  LAUNCH(k_cout_bwd, dim3(nblocks_vec(4 * px)), dim3(256), 0, s, (const float*)net->gy, th, gr[GC0], B, H, W);
   {
     const int nb = wgrad_blocks(B, H, W);
     LAUNCH(k_cout_wgrad, dim3(nb), dim3(256), 0, s, (const u16*)a[C0], (const float*)net->gy, net->part, B, H, W);
@@ -691,7 +804,7 @@ static fl_status net_backward(fl_net net, const float* x, const float* alpha, in
     constexpr int SMI = decltype(smi)::value, SMG = decltype(smg)::value;
     if (gin)
       LAUNCH((k_conv32<SMG, EPI_NONE>), dim3(conv_blocks(B, h, w)), dim3(256), 0, s, sg, bw(L), (const float*)nullptr,
-             gin, B, h, w);
+             gin, B, h, w, (float*)nullptr);
     const int nb = wgrad_blocks(B, h, w);
     LAUNCH((k_conv32_wgrad<SMI, SMG>), dim3(nb), dim3(256), 0, s, si, sg, net->part, B, h, w);
     return reduce(nb, (int)L32SZ, (int)L32SZ, OFF_L32 + L * L32SZ);
@@ -721,7 +834,7 @@ static fl_status net_backward(fl_net net, const float* x, const float* alpha, in
 }
 
 static fl_status net_pack(fl_net net) {
-  LAUNCH(k_pack, dim3(nblocks_vec(NL32 * PACK)), dim3(256), 0, net->stream, (const float*)net->th, net->fw, net->bw);
+  LAUNCH(k_pack, dim3(nblocks_vec(NPACK * PACK)), dim3(256), 0, net->stream, (const float*)net->th, net->fw, net->bw);
   return FL_OK;
 }
 
@@ -737,17 +850,17 @@ static fl_status alphas_to_device(fl_net net, const double* alpha, int B) {
 // ---------------------------------------------------------------------------
 // learned flexible CG (host-driven, FP64 reductions)
 // ---------------------------------------------------------------------------
-// z = B (r + s N(r/s, alpha)), B the inverse of the sine-basis diagonal.
-template <typename T> static fl_status learned_prec(fl_op op, fl_net net, const Prob& pb, double rr) {
+// z = B (r + s N(r/s, alpha)), B the inverse of the sine-basis diagonal; s
+// from the device value r.r in net->fs[4].
+template <typename T> static fl_status learned_prec(fl_op op, fl_net net, const Prob& pb) {
   hipStream_t s = op->stream;
   const int n0 = op->n[0], n1 = op->n[1];
   const int Hp = (n0 + 7) / 8 * 8, Wp = (n1 + 7) / 8 * 8;
-  const double sc = std::sqrt(rr / (double)op->N);
   LAUNCH(k_net_in<T>, dim3(nblocks_vec((long)Hp * Wp)), dim3(256), 0, s, (const T*)pb.r, net->pin, n0, n1, Hp, Wp,
-         sc > 0 ? 1.0 / sc : 0.0);
+         (const double*)(net->fs + 4));
   STCHK(net_forward(net, net->pin, net->palpha, 1, Hp, Wp));
   LAUNCH(k_net_out<T>, dim3(nblocks_vec(op->N)), dim3(256), 0, s, (const T*)pb.r, (const float*)net->y, (T*)net->pw,
-         n0, n1, Wp, sc);
+         n0, n1, Wp, (const double*)(net->fs + 4));
   Prob pz = pb;
   STCHK(set_precond<T>(op, pz, FL_PC_SPECTRAL));
   pz.in = net->pw;
@@ -765,36 +878,32 @@ template <typename T> static fl_status fd_prec(fl_op op, const Prob& pb) {
   return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pz, Iter{0, 0}, 0);
 }
 
-template <typename T> static fl_status dotv(fl_op op, const Prob& pb, const void* a, const void* b, int target) {
+template <typename T> static fl_status dot_to(fl_op op, const Prob& pb, const void* a, const void* b, double* dst) {
   hipStream_t s = op->stream;
   LAUNCH(k_dot<T>, dim3(std::min<long>(1024, nblocks_vec(op->N))), dim3(256), 0, s, pb, a, b, (int)S_DOT, op->N);
-  LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, pb, (int)S_DOT, target);
-  return FL_OK;
-}
-
-static fl_status readsc(fl_op op, const Prob& pb, Scalars* h) {
-  HIPCHK(hipMemcpyAsync(h, pb.sc, sizeof(Scalars), hipMemcpyDeviceToHost, op->stream));
-  HIPCHK(hipStreamSynchronize(op->stream));
+  LAUNCH(k_total_to, dim3(1), dim3(256), 0, s, pb, (int)S_DOT, dst);
   return FL_OK;
 }
 
 // Flexible CG (truncated to one previous direction): alpha_k = p.r / p.q,
-// beta_k = -z_{k+1}.q_k / p_k.q_k.  r holds the initial residual, x the
-// initial iterate; rr0 = r.r, ff = f.f.  Fallback: the FD preconditioner for
-// the rest of the solve once r.z <= 0 or a step fails to reduce ||r||.
+// beta_k = -z_{k+1}.q_k / p_k.q_k, every scalar computed and used on the
+// device; the host reads r.z, p.q and r.r once per iteration.  r holds the
+// initial residual, x the initial iterate; rr0 = r.r, ff = f.f.  Fallback:
+// the FD preconditioner for the rest of the solve once r.z <= 0 or 5
+// iterations fail to cut ||r|| by 1%.
 template <typename T>
 fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxit, double ff, double rr0, int* iters,
                       double* rr_out, int* status, int* fell_back) {
   hipStream_t s = op->stream;
   const long N = op->N;
-  Scalars* h = op->hsc;
   const double thr = tol * tol * ff;
-  double rr = rr0, pq = 0.0;
-  int it = 0;
-  *status = 0;
+  double* fs = net->fs;
+  double* h = net->hfs;
+  double rr = rr0;
+  int it = 0, stall = 0;
   bool fb = false;
-  int stall = 0;
   double best = rr0;
+  *status = 0;
   if (!(ff > 0.0) || rr <= thr) {
     *iters = 0;
     *rr_out = rr;
@@ -802,38 +911,31 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
     *fell_back = 0;
     return FL_OK;
   }
+  h[4] = rr0;
+  HIPCHK(hipMemcpyAsync(fs + 4, h + 4, sizeof(double), hipMemcpyHostToDevice, s));
+  const int nupd = (int)std::min<long>(2048, nblocks_vec(N));
   for (;;) {
-    if (!fb) STCHK(learned_prec<T>(op, net, pb, rr));
+    if (!fb) STCHK(learned_prec<T>(op, net, pb));
     else STCHK(fd_prec<T>(op, pb));
-    STCHK(dotv<T>(op, pb, pb.r, pb.z, FIN_AUX0));
-    if (it > 0) STCHK(dotv<T>(op, pb, pb.z, pb.q, FIN_AUX1));
-    STCHK(readsc(op, pb, h));
-    double rz = h->aux[0];
-    if (!fb && !(rz > 0.0 && std::isfinite(rz))) {  // not a descent direction: fall back
-      fb = true;
-      continue;
-    }
-    const double beta = it > 0 ? -h->aux[1] / pq : 0.0;
-    // p = z + beta p
-    LAUNCH((k_axpby<T, T>), dim3(nblocks_vec(N)), dim3(256), 0, s, (const T*)pb.z, (T*)pb.p, 1.0, beta, N);
-    // q = M p with p.q partials, then p.q and p.r
+    STCHK(dot_to<T>(op, pb, pb.r, pb.z, fs + 0));
+    if (it > 0) STCHK(dot_to<T>(op, pb, pb.z, pb.q, fs + 1));
+    LAUNCH(k_fcg_dir<T>, dim3(nblocks_vec(N)), dim3(256), 0, s, (const T*)pb.z, (T*)pb.p, N, (const double*)fs,
+           it == 0 ? 1 : 0);
     Prob pa = pb;
     pa.in = pb.p;
     STCHK((apply_seq<T, PRO_PLAIN, EPI_PQ>(op, pa, Iter{0, 0}, 0)));
-    LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, pb, (int)S_PQ, (int)FIN_AUX0);
-    STCHK(dotv<T>(op, pb, pb.p, pb.r, FIN_AUX1));
-    STCHK(readsc(op, pb, h));
-    pq = h->aux[0];
+    LAUNCH(k_total_to, dim3(1), dim3(256), 0, s, pb, (int)S_PQ, fs + 2);
+    STCHK(dot_to<T>(op, pb, pb.p, pb.r, fs + 3));
+    LAUNCH(k_fcg_update<T>, dim3(nupd), dim3(256), 0, s, pb, N, (const double*)fs);
+    LAUNCH(k_total_to, dim3(1), dim3(256), 0, s, pb, (int)S_RR, fs + 4);
+    HIPCHK(hipMemcpyAsync(h, fs, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double rz = h[0], pq = h[2];
+    rr = h[4];
     if (!(pq > 0.0) || !std::isfinite(pq)) {
       *status = 3;
       break;
     }
-    const double alpha = h->aux[1] / pq;
-    LAUNCH((k_axpby<T, T>), dim3(nblocks_vec(N)), dim3(256), 0, s, (const T*)pb.p, (T*)pb.x, alpha, 1.0, N);
-    LAUNCH((k_axpby<T, T>), dim3(nblocks_vec(N)), dim3(256), 0, s, (const T*)pb.q, (T*)pb.r, -alpha, 1.0, N);
-    STCHK(dotv<T>(op, pb, pb.r, pb.r, FIN_RR));
-    STCHK(readsc(op, pb, h));
-    rr = h->rr;
     ++it;
     if (!std::isfinite(rr)) {
       *status = 3;
@@ -847,6 +949,7 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
       *status = 2;
       break;
     }
+    if (!fb && !(rz > 0.0 && std::isfinite(rz))) fb = true;  // not a descent direction
     if (rr < 0.99 * best) {
       best = rr;
       stall = 0;
@@ -879,6 +982,9 @@ fl_status learned_prepare(fl_op op, fl_net net, size_t elem) {
     net->pcap = need;
   }
   if (!net->palpha) STCHK(net->alloc((void**)&net->palpha, sizeof(float)));
+  if (!net->fs) STCHK(net->alloc((void**)&net->fs, 8 * sizeof(double)));
+  if (!net->hfs && hipHostMalloc((void**)&net->hfs, 8 * sizeof(double)) != hipSuccess)
+    return fail(FL_E_NOMEM, "pinned host scalars");
   const float a = (float)op->alpha;
   HIPCHK(hipMemcpyAsync(net->palpha, &a, sizeof(float), hipMemcpyHostToDevice, op->stream));
   HIPCHK(hipStreamSynchronize(op->stream));
@@ -900,7 +1006,7 @@ fl_status fl_net_create(void* hip_stream, fl_net* out) {
   fl_status st = FL_OK;
   for (float** p : {&net->th, &net->g, &net->m, &net->v})
     if (st == FL_OK) st = net->alloc((void**)p, NPARAM * sizeof(float));
-  if (st == FL_OK) st = net->alloc((void**)&net->fw, NL32 * PACK * sizeof(u16));
+  if (st == FL_OK) st = net->alloc((void**)&net->fw, NPACK * PACK * sizeof(u16));
   if (st == FL_OK) st = net->alloc((void**)&net->bw, NL32 * PACK * sizeof(u16));
   if (st != FL_OK) {
     delete net;
@@ -1034,7 +1140,7 @@ fl_status fl_learned_pairs(fl_op op, const double* e, int64_t e_stride, const do
     pd.in = ek;
     pd.out = w.q;
     STCHK((precond_seq<double, DPRO_PLAIN, DEPI_FINAL>(op, pd, Iter{0, 0}, 0)));
-    STCHK(dotv<double>(op, pb, w.r, w.r, FIN_RR));
+    STCHK(dot_to<double>(op, pb, w.r, w.r, &pb.sc->rr));
     LAUNCH(k_pair_out, dim3(nblocks_vec((long)Hp * Wp)), dim3(256), 0, s, (const double*)w.r, (const double*)w.q,
            R + (long)k * Hp * Wp, T + (long)k * Hp * Wp, op->n[0], op->n[1], Hp, Wp,
            (const double*)&pb.sc->rr);
@@ -1060,15 +1166,20 @@ fl_status fl_net_profile(fl_net net, int which, int H, int W, int reps, double* 
     if (which == 1) {
       Stage st = {a[A0], a[C1], nullptr};
       LAUNCH((k_conv32<SM_UPADD, EPI_RELU>), dim3(conv_blocks(1, H, W)), dim3(256), 0, s, st,
-             (const u16*)(net->fw + LU0 * PACK), (const float*)(net->th + OFF_L32 + LU0 * L32SZ + L32W), a[C0], 1, H, W);
+             (const u16*)(net->fw + LU0 * PACK), (const float*)(net->th + OFF_L32 + LU0 * L32SZ + L32W), a[C0], 1, H, W,
+             (float*)nullptr);
       return FL_OK;
     }
     if (which == 2) {
-      LAUNCH(k_cin_fwd, dim3(nblocks_vec(px)), dim3(256), 0, s, (const float*)net->xb, (const float*)net->ab,
-             (const float*)net->th, a[A0], 1, H, W);
+      Stage st = {nullptr, nullptr, nullptr, (const float*)net->xb, (const float*)net->ab};
+      LAUNCH((k_conv32<SM_INPUT, EPI_RELU>), dim3(conv_blocks(1, H, W)), dim3(256), 0, s, st,
+             (const u16*)(net->fw + NL32 * PACK), (const float*)(net->th + OFF_CIN_B), a[A0], 1, H, W, (float*)nullptr);
       return FL_OK;
     }
-    LAUNCH(k_cout_fwd, dim3(nblocks_vec(px)), dim3(256), 0, s, (const u16*)a[C0], (const float*)net->th, net->y, 1, H, W);
+    Stage st = {a[C0], nullptr, nullptr};
+    LAUNCH((k_conv32<SM_PLAIN, EPI_OUT>), dim3(conv_blocks(1, H, W)), dim3(256), 0, s, st,
+           (const u16*)(net->fw + (NL32 + 1) * PACK), (const float*)(net->th + OFF_OUT + 9 * CH), (u16*)nullptr, 1, H, W,
+           net->y);
     return FL_OK;
   };
   hipEvent_t e0, e1;

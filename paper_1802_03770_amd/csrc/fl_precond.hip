@@ -2,6 +2,44 @@
 // build of this file: FL_T = float or double).
 #include "fl_internal.hpp"
 
+// Sine kernels are specialised for the direct lengths 2(n+1) of the common
+// grids (n = 64, 128, 384, 512, 1024), each specialisation holding only its
+// own FFT; other lengths and the chirp-z form take the run-time plan (LF = 0).
+static inline int dst_lf(const Axis& A) {
+  if (!A.dst_direct || !A.dst.fixed) return 0;
+  switch (A.dst.L) {
+    case 2050: case 1026: case 770: case 258: case 130: return A.dst.L;
+    default: return 0;
+  }
+}
+
+template <typename T, int DPRO, int DEPI>
+static fl_status launch_dst_rows(int lf, dim3 g, dim3 b, size_t sm, hipStream_t s, const Prob& pb, Iter it, int chk) {
+  switch (lf) {
+    case 2050: LAUNCH((k_dst_rows<T, DPRO, DEPI, 2050>), g, b, sm, s, pb, it, chk); break;
+    case 1026: LAUNCH((k_dst_rows<T, DPRO, DEPI, 1026>), g, b, sm, s, pb, it, chk); break;
+    case 770: LAUNCH((k_dst_rows<T, DPRO, DEPI, 770>), g, b, sm, s, pb, it, chk); break;
+    case 258: LAUNCH((k_dst_rows<T, DPRO, DEPI, 258>), g, b, sm, s, pb, it, chk); break;
+    case 130: LAUNCH((k_dst_rows<T, DPRO, DEPI, 130>), g, b, sm, s, pb, it, chk); break;
+    default: LAUNCH((k_dst_rows<T, DPRO, DEPI, 0>), g, b, sm, s, pb, it, chk); break;
+  }
+  return FL_OK;
+}
+
+template <typename T, bool SCALE>
+static fl_status launch_dst_cols(int lf, dim3 g, dim3 b, size_t sm, hipStream_t s, const Prob& pb, const DGeom& dg,
+                                 int chk) {
+  switch (lf) {
+    case 2050: LAUNCH((k_dst_cols<T, SCALE, 2050>), g, b, sm, s, pb, dg, chk); break;
+    case 1026: LAUNCH((k_dst_cols<T, SCALE, 1026>), g, b, sm, s, pb, dg, chk); break;
+    case 770: LAUNCH((k_dst_cols<T, SCALE, 770>), g, b, sm, s, pb, dg, chk); break;
+    case 258: LAUNCH((k_dst_cols<T, SCALE, 258>), g, b, sm, s, pb, dg, chk); break;
+    case 130: LAUNCH((k_dst_cols<T, SCALE, 130>), g, b, sm, s, pb, dg, chk); break;
+    default: LAUNCH((k_dst_cols<T, SCALE, 0>), g, b, sm, s, pb, dg, chk); break;
+  }
+  return FL_OK;
+}
+
 // ---------------------------------------------------------------------------
 // preconditioner (p0 I + p1 pcs T)^{-1}
 // ---------------------------------------------------------------------------
@@ -16,12 +54,11 @@ template <typename T, int DPRO, int DEPI> fl_status precond_seq(fl_op op, Prob p
   size_t sm = (size_t)G * Line<T>::stride(AL.dst.L) * sizeof(cx<T>) * (AL.dst_direct ? 2 : 1);
   dim3 gr((rlines + G - 1) / G);
   if (d == 1) {
-    LAUNCH(k_dst_rows<T, DPRO, DEPI>, gr, dim3(nt), sm, s, pb, it, chk);
-    return FL_OK;
+    return launch_dst_rows<T, DPRO, DEPI>(dst_lf(AL), gr, dim3(nt), sm, s, pb, it, chk);
   }
   Prob p1 = pb;
   p1.out = pb.T1;
-  LAUNCH(k_dst_rows<T, DPRO, DEPI_STORE>, gr, dim3(nt), sm, s, p1, it, chk);
+  STCHK((launch_dst_rows<T, DPRO, DEPI_STORE>(dst_lf(AL), gr, dim3(nt), sm, s, p1, it, chk)));
   auto cols = [&](DGeom g, bool scale) -> fl_status {
     Prob pc = pb;
     Axis& A = pc.ax[g.axis];
@@ -30,11 +67,8 @@ template <typename T, int DPRO, int DEPI> fl_status precond_seq(fl_op op, Prob p
     int ntc = block_for(A.dst.tpl), Gf = ntc / A.dst.tpl, Gc = Gf * per;
     long grid = g.ngroup * ((g.gs + Gc - 1) / Gc);
     size_t smc = (size_t)Gf * Line<T>::stride(A.dst.L) * sizeof(cx<T>) * per;
-    if (scale)
-      LAUNCH(k_dst_cols<T, true>, dim3(grid), dim3(ntc), smc, s, pc, g, chk);
-    else
-      LAUNCH(k_dst_cols<T, false>, dim3(grid), dim3(ntc), smc, s, pc, g, chk);
-    return FL_OK;
+    if (scale) return launch_dst_cols<T, true>(dst_lf(A), dim3(grid), dim3(ntc), smc, s, pc, g, chk);
+    return launch_dst_cols<T, false>(dst_lf(A), dim3(grid), dim3(ntc), smc, s, pc, g, chk);
   };
   const long nr = pb.nrhs;
   if (d == 2) {
@@ -50,8 +84,7 @@ template <typename T, int DPRO, int DEPI> fl_status precond_seq(fl_op op, Prob p
   }
   Prob p3 = pb;
   p3.in = pb.T1;
-  LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI>, gr, dim3(nt), sm, s, p3, it, chk);
-  return FL_OK;
+  return launch_dst_rows<T, DPRO_PLAIN, DEPI>(dst_lf(AL), gr, dim3(nt), sm, s, p3, it, chk);
 }
 
 
@@ -77,10 +110,12 @@ template <typename T> fl_status launch_precond_pass(fl_op op, Prob pb, int pass)
     Prob p1 = pb;
     if (pass == 3) {
       p1.out = pb.T1;
-      LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI_STORE>, dim3((rlines + G - 1) / G), dim3(nt), sm, s, p1, it, 0);
+      STCHK((launch_dst_rows<T, DPRO_PLAIN, DEPI_STORE>(dst_lf(AL), dim3((rlines + G - 1) / G), dim3(nt), sm, s, p1,
+                                                        it, 0)));
     } else {
       p1.in = pb.T1;
-      LAUNCH(k_dst_rows<T, DPRO_PLAIN, DEPI_FINAL>, dim3((rlines + G - 1) / G), dim3(nt), sm, s, p1, it, 0);
+      STCHK((launch_dst_rows<T, DPRO_PLAIN, DEPI_FINAL>(dst_lf(AL), dim3((rlines + G - 1) / G), dim3(nt), sm, s, p1,
+                                                        it, 0)));
     }
     return FL_OK;
   }
@@ -96,8 +131,8 @@ template <typename T> fl_status launch_precond_pass(fl_op op, Prob pb, int pass)
     const Axis& A = pb.ax[0];
     int nt = block_for(A.dst.tpl), Gf = nt / A.dst.tpl, G = Gf * per;
     long grid = g.ngroup * ((g.gs + G - 1) / G);
-    LAUNCH(k_dst_cols<T, true>, dim3(grid), dim3(nt), (size_t)Gf * Line<T>::stride(A.dst.L) * sizeof(cx<T>) * per, s,
-           pb, g, 0);
+    STCHK((launch_dst_cols<T, true>(dst_lf(A), dim3(grid), dim3(nt),
+                                    (size_t)Gf * Line<T>::stride(A.dst.L) * sizeof(cx<T>) * per, s, pb, g, 0)));
     return FL_OK;
   }
   return fail(FL_E_INVALID, "preconditioner pass must be 3, 4 or 5");

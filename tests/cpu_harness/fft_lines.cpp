@@ -68,6 +68,7 @@ int main() {
       {"wide fixed 130", run<double, 130>(true, true), 1e-13}, {"wide fixed 258", run<double, 258>(true, true), 1e-13},
       {"wide fixed 770", run<double, 770>(true, true), 1e-13}, {"wide fixed 1026", run<double, 1026>(true, true), 1e-13},
       {"wide fixed 2050", run<double, 2050>(true, true), 1e-13}, {"wide generic 76", run<double, 76>(false, true), 1e-13},
+      {"f32 wide fixed 2050", run<float, 2050>(true, true), 2e-6},
       {"wide generic 82", run<double, 82>(false, true), 1e-13}, {"wide generic 98", run<double, 98>(false, true), 1e-13},
   };
   int bad = 0;

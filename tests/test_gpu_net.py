@@ -6,8 +6,9 @@ without it.
 
 Tolerances: the network keeps activations in BF16 (8-bit significand, unit
 roundoff 2^-9 ~ 2e-3) through nine layers, so outputs and gradients are
-compared in relative l2 norm against the FP64 oracle at 3e-2 (outputs), 5e-2
-(the whole gradient: the reverse pass also stores its gradients in BF16, 18
+compared in relative l2 norm against the FP64 oracle at 3e-2 (outputs), 7e-2
+(the whole gradient: the forward pass rounds the input and every layer's
+weights to BF16 and the reverse pass stores its gradients in BF16, about 20
 roundings deep) and 1e-1 per layer's gradient (the coarse levels of small
 test grids sum few pixels, where single ReLU flips from BF16 rounding show),
 with a cosine similarity above 0.998.  An indexing error shows as an O(1)
@@ -90,7 +91,7 @@ def test_net_grad_against_oracle(B, H, W):
             o += m
     cos = float(g @ want / (np.linalg.norm(g) * np.linalg.norm(want)))
     assert cos >= 0.998
-    assert _rl2(g, want) <= 5e-2
+    assert _rl2(g, want) <= 7e-2
 
 
 def test_net_params_roundtrip_and_zero_output():
