@@ -176,6 +176,7 @@ def main():
         tf = 2 * 9 * 32 * 32 * n * n / (prof[dom]["ms"] * 1e-3) / 1e12
         roof["mfma_bf16_tflops"] = round(tf, 1)
         roof["mfma_frac"] = round(tf / 2500.0, 4)
+        roof["traffic"] = measured_traffic("net_conv_l0_1024_hbm_counters.md") if n == 1024 else None
 
     batched = None
     if not args.no_batched:
@@ -213,6 +214,18 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from a committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated), or None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.strip().startswith("- traffic_bytes_per_launch:"):
+            return int(float(line.split(":")[1]))
+    return None
 
 
 def batched_workloads(fl, torch, args):
