@@ -72,7 +72,9 @@ typedef struct {
                            forms when the op is built and keep the faster, per precision); 1 = direct odd
                            extension of length 2(n+1) when it factors over radices <= 43, else chirp-z;
                            2 = chirp-z with a 5-smooth length >= 2n-1 */
-  int reserved[5];
+  int col_lanes;        /* symbol column pass at lengths 1024 and 2048: 0 = autotune, -1 = run-time plan,
+                           64 or 128 = lanes per column of the specialised kernel */
+  int reserved[4];
 } fl_weights_opts;
 
 typedef struct {
@@ -114,9 +116,10 @@ fl_status fl_op_constants(fl_op op, double out[8]);
 /* Padded circulant lengths P_k (out[0..d-1]). */
 fl_status fl_op_padded(fl_op op, int64_t* out);
 
-/* Sine-transform plans chosen for the op: out[3 p + a] = 1 (direct) or 2
- * (chirp-z) and out[6 + 3 p + a] = its FFT length, for precision p (0 FP64,
- * 1 FP32) and axis a < d; 12 entries. */
+/* Plans chosen for the op (14 entries), per precision p (0 FP64, 1 FP32):
+ * out[3 p + a] = 1 (direct) or 2 (chirp-z) sine transform along axis a < d,
+ * out[6 + 3 p + a] = its FFT length, out[12 + p] = lanes per column of the
+ * symbol column pass (0: run-time plan; 64 or 128: specialised kernel). */
 fl_status fl_op_plan(fl_op op, int64_t* out);
 
 /* Device-to-device copy of the folded arrays, shape [P_1/2+1]...[P_d/2+1]:

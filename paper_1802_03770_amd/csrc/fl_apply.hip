@@ -2,6 +2,38 @@
 // this file: FL_T = float or double).
 #include "fl_internal.hpp"
 
+// The symbol column pass: lengths 1024 and 2048 (grids of 512 and 1024) can run
+// a specialised kernel with fewer lanes per column (64 or 128), i.e. 4 or 2
+// adjacent columns per block; the autotuner sets A.col_tplf (0 = the run-time
+// plan, which every other length follows).
+template <typename T> static fl_status launch_col_conv(const Prob& pc, const ColGeom& cg, Iter it, int chk,
+                                                        hipStream_t s) {
+  const Axis& A = pc.ax[cg.axis];
+  int lf = 0, tplf = 0;
+  if (A.fft.fixed && (A.P == 2048 || A.P == 1024) && (A.col_tplf == 64 || A.col_tplf == 128)) {
+    lf = A.P;
+    tplf = A.col_tplf;
+    // FP64 at 2048 with 64 lanes would need 4 x 37 KB of LDS: keep 128
+    if (lf == 2048 && sizeof(T) == 8) tplf = 128;
+    if (lf == 1024) tplf = 64;
+  }
+  Prob pl = pc;
+  if (!lf) pl.ax[cg.axis].fft.tpl = tune_tpl(A.fft.tpl, A.P, cg.gs * cg.ngroup);
+  const int tpl = lf ? tplf : pl.ax[cg.axis].fft.tpl;
+  const int nt = block_for(tpl), G = nt / tpl;
+  const long grid = cg.ngroup * ((cg.gs + G - 1) / G);
+  const size_t sm = (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>);
+  if (lf == 2048 && tplf == 64)
+    LAUNCH((k_colpass<T, COL_CONV, 2048, 64>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
+  else if (lf == 2048)
+    LAUNCH((k_colpass<T, COL_CONV, 2048, 128>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
+  else if (lf == 1024)
+    LAUNCH((k_colpass<T, COL_CONV, 1024, 64>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
+  else
+    LAUNCH((k_colpass<T, COL_CONV>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
+  return FL_OK;
+}
+
 // ---------------------------------------------------------------------------
 // operator application (M or shift0 I + shift1 M)
 // ---------------------------------------------------------------------------
@@ -28,12 +60,12 @@ template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob
   auto col = [&](ColGeom cg, int mode) -> fl_status {
     Prob pc = pb;
     Axis& A = pc.ax[cg.axis];
+    if (mode == COL_CONV) return launch_col_conv<T>(pc, cg, it, chk, s);
     A.fft.tpl = tune_tpl(A.fft.tpl, A.P, cg.gs * cg.ngroup);
     int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
     long grid = cg.ngroup * ((cg.gs + G - 1) / G);
     size_t sm = (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>);
     if (mode == COL_FWD) LAUNCH(k_colpass<T, COL_FWD>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
-    if (mode == COL_CONV) LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
     if (mode == COL_INV) LAUNCH(k_colpass<T, COL_INV>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
     return FL_OK;
   };
@@ -90,13 +122,7 @@ template <typename T> fl_status launch_apply_pass(fl_op op, Prob pb, int pass) {
       const long n0 = op->n[0], P1 = op->P[1], H2 = op->H[2];
       cg = {0, (int)n0, (int)n0, P1 * H2, 1, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
     }
-    pb.ax[0].fft.tpl = tune_tpl(pb.ax[0].fft.tpl, pb.ax[0].P, cg.gs * cg.ngroup);
-    const Axis& A = pb.ax[0];
-    int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
-    long grid = cg.ngroup * ((cg.gs + G - 1) / G);
-    LAUNCH(k_colpass<T, COL_CONV>, dim3(grid), dim3(nt), (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>), s, pb, cg,
-           it, 0);
-    return FL_OK;
+    return launch_col_conv<T>(pb, cg, it, 0, s);
   }
   return fail(FL_E_INVALID, "apply pass must be 0, 1 or 2");
 }

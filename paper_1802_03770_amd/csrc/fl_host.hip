@@ -196,6 +196,34 @@ template <typename T> static fl_status profile_t(fl_op op, int pass, int reps, d
 // extension, time the whole preconditioner with the direct plans and with the
 // chirp-z plans (same workspace, HIP events on the op stream) and keep the
 // faster for this precision.
+// Autotuner of the symbol column pass (lengths 1024 and 2048 along axis 0 of
+// a 2D grid): time the pass with the run-time plan and with 64 and 128 lanes
+// per column, keep the fastest for this precision.
+template <typename T> static fl_status autotune_col(fl_op op) {
+  Axis& A = op->ax[tix<T>()][0];
+  if (op->d != 2 || !A.fft.fixed || (A.P != 2048 && A.P != 1024)) return FL_OK;
+  if (op->col_lanes != 0) {  // forced
+    A.col_tplf = op->col_lanes > 0 ? op->col_lanes : 0;
+    return FL_OK;
+  }
+  const int opts[3] = {0, 64, 128};
+  double best = 1e30;
+  int pick = 0;
+  for (int o : opts) {
+    if (o == 128 && (A.P == 1024)) continue;
+    if (o == 64 && A.P == 2048 && sizeof(T) == 8) continue;
+    A.col_tplf = o;
+    double ms = 0.0;
+    STCHK(profile_t<T>(op, 1, 5, &ms));
+    if (ms < best) {
+      best = ms;
+      pick = o;
+    }
+  }
+  A.col_tplf = pick;
+  return FL_OK;
+}
+
 template <typename T> static fl_status autotune_dst(fl_op op) {
   bool any = false;
   for (int a = 0; a < op->d; ++a) any = any || op->dst_form[tix<T>()][a] == 1;
@@ -249,6 +277,7 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
     memset(&op->ax[1][a], 0, sizeof(Axis));
   }
   op->dst_mode = (o && o->dst_mode >= 0 && o->dst_mode <= 2) ? o->dst_mode : 0;
+  op->col_lanes = (o && (o->col_lanes == -1 || o->col_lanes == 64 || o->col_lanes == 128)) ? o->col_lanes : 0;
   for (int a = 0; a < d; ++a) {
     if ((st = build_axis<double>(op, a, op->dst_mode == 2 ? 2 : 1)) != FL_OK) return bail(st);
     if ((st = build_axis<float>(op, a, op->dst_mode == 2 ? 2 : 1)) != FL_OK) return bail(st);
@@ -267,6 +296,8 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
     if ((st = autotune_dst<double>(op)) != FL_OK) return bail(st);
     if ((st = autotune_dst<float>(op)) != FL_OK) return bail(st);
   }
+  if ((st = autotune_col<double>(op)) != FL_OK) return bail(st);
+  if ((st = autotune_col<float>(op)) != FL_OK) return bail(st);
   *out = op;
   return FL_OK;
 }
@@ -655,12 +686,14 @@ fl_status fl_op_padded(fl_op op, int64_t* out) {
 
 fl_status fl_op_plan(fl_op op, int64_t* out) {
   if (!op || !out) return fail(FL_E_INVALID, "NULL argument");
-  for (int i = 0; i < 12; ++i) out[i] = 0;
-  for (int p = 0; p < 2; ++p)
+  for (int i = 0; i < 14; ++i) out[i] = 0;
+  for (int p = 0; p < 2; ++p) {
     for (int a = 0; a < op->d; ++a) {
       out[3 * p + a] = op->dst_form[p][a];
       out[6 + 3 * p + a] = op->ax[p][a].dst.L;
     }
+    out[12 + p] = op->ax[p][0].col_tplf;
+  }
   return FL_OK;
 }
 

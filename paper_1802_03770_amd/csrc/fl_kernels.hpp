@@ -408,14 +408,25 @@ struct ColGeom {
 
 enum { COL_FWD = 0, COL_CONV = 1, COL_INV = 2 };
 
-template <typename T, int MODE>
+// Column line FFT: LF = 0 follows the run-time plan; LF > 0 is a kernel
+// specialised for that length with TPLF lanes per line (fewer lanes than the
+// row passes use, so that a block holds several adjacent columns).
+template <typename T, bool INV, int LF, int TPLF>
+__device__ __forceinline__ void col_fft(Line<T> buf, const FFTPlan& pl, int lane) {
+  if constexpr (LF > 0)
+    cstages<T, LF, TPLF, INV, 0, 1>(buf, buf, (const cx<T>*)pl.tw, lane);
+  else
+    fft_line<T, INV>(buf, pl, lane);
+}
+
+template <typename T, int MODE, int LF = 0, int TPLF = 0>
 __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, const Iter& it, bool check_done,
                                              int blk0, int nblk) {
   if (check_done && pb.sc->done) return;
   const long blk = xcd_tile(blk0, nblk);
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[cg.axis];
-  const int L = A.P, tpl = A.fft.tpl;
+  const int L = LF > 0 ? LF : A.P, tpl = LF > 0 ? TPLF : A.fft.tpl;
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   const long tiles = (cg.gs + G - 1) / G;
   const long grp = blk / tiles, c0 = (blk % tiles) * G;
@@ -432,34 +443,32 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
   }
   __syncthreads();
   Line<T> buf = line_at<T>(smem, g, L);
-  if (MODE == COL_INV)
-    fft_line<T, true>(buf, A.fft, lane);
-  else
-    fft_line<T, false>(buf, A.fft, lane);
+  col_fft<T, MODE == COL_INV, LF, TPLF>(buf, A.fft, lane);
   if (MODE == COL_CONV) {
-    // symbol s0 + s1 lambda on the folded octant, times 1/prod(P)
+    // symbol s0 + s1 lambda on the folded octant, times 1/prod(P); consecutive
+    // threads take consecutive lines of one frequency (adjacent symbol entries)
     const T* lam = (const T*)pb.lam;
     double norm = 1.0;
     for (int a = 0; a < pb.d; ++a) norm *= pb.ax[a].P;
     const T s0 = (T)(pb.s0 / norm), s1 = (T)(pb.s1 / norm);
-    const long c = c0 + g;
-    long lidx_tail;  // index contribution of the axes after axis 0
-    if (pb.d == 2) {
-      lidx_tail = c;
-    } else {
-      const int H2 = pb.ax[2].H, P1 = pb.ax[1].P;
-      long k1 = c / H2, k2 = c % H2;
-      lidx_tail = (long)fold((int)k1, P1) * H2 + k2;
-    }
-    long tailsz = (pb.d == 2) ? pb.ax[1].H : (long)pb.ax[1].H * pb.ax[2].H;
-    if (c < cg.gs) {
-      for (int k = lane; k < L; k += tpl) {
-        T lv = lam[(long)fold(k, L) * tailsz + lidx_tail];
-        buf[k] = cscale(buf[k], s0 + s1 * lv);
+    const long tailsz = (pb.d == 2) ? pb.ax[1].H : (long)pb.ax[1].H * pb.ax[2].H;
+    for (long e = threadIdx.x; e < (long)G * L; e += blockDim.x) {
+      const int j = (int)(e % G), k = (int)(e / G);
+      if (j >= gv) continue;
+      const long c = c0 + j;
+      long lidx_tail;  // index contribution of the axes after axis 0
+      if (pb.d == 2) {
+        lidx_tail = c;
+      } else {
+        const int H2 = pb.ax[2].H, P1 = pb.ax[1].P;
+        lidx_tail = (long)fold((int)(c / H2), P1) * H2 + c % H2;
       }
+      const T lv = lam[(long)fold(k, L) * tailsz + lidx_tail];
+      Line<T> ln = line_at<T>(smem, j, L);
+      ln[k] = cscale(ln[k], s0 + s1 * lv);
     }
     __syncthreads();
-    fft_line<T, true>(buf, A.fft, lane);
+    col_fft<T, true, LF, TPLF>(buf, A.fft, lane);
   }
   for (long e = threadIdx.x; e < (long)G * cg.nout; e += blockDim.x) {
     int j = e % G, i = e / G;
@@ -977,8 +986,9 @@ template <typename T, int PRO> __global__ FL_BOUNDS void k_rowfwd_b(const Prob* 
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
   rowfwd_body<T, PRO>(pbs[blockIdx.y], it, blockIdx.x);
 }
-template <typename T, int MODE> __global__ FL_BOUNDS void k_colpass(Prob pb, ColGeom cg, Iter it, int chk) {
-  colpass_body<T, MODE>(pb, cg, it, chk, blockIdx.x, gridDim.x);
+template <typename T, int MODE, int LF = 0, int TPLF = 0>
+__global__ FL_BOUNDS void k_colpass(Prob pb, ColGeom cg, Iter it, int chk) {
+  colpass_body<T, MODE, LF, TPLF>(pb, cg, it, chk, blockIdx.x, gridDim.x);
 }
 template <typename T, int MODE>
 __global__ FL_BOUNDS void k_colpass_b(const Prob* pbs, const ColGeom* cgs, Iter it, int chk, const int* nb) {

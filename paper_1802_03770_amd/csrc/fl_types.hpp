@@ -22,6 +22,8 @@ struct Axis {
   //   sum_{j=1..n} x_j sin(pi j k/(n+1)) = Im( ch_k sum_j (x_j ch_j) conj(ch_{k-j}) ),
   //   ch_m = e^{i pi m^2 / (2(n+1))}, convolution of length Lb >= 2n-1.
   FFTPlan dst;      // complex FFT of length Lb (chirp-z) or 2(n+1) (direct)
+  int col_tplf;     // lanes per line of the specialised symbol column pass (lengths
+                    // 1024, 2048): 0 = run-time plan, else 64 or 128 (autotuned)
   int dst_direct;   // 1: two real lines packed as x + i y in an odd extension of
                     //    length 2(n+1); FFT gives -2i S_x + 2 S_y
                     // 0: one line per FFT line by the chirp-z identity

@@ -261,3 +261,27 @@ def test_full_size_apply_sampled():
     scale = np.abs(got).max()
     for p, wv in zip(pts, want):
         assert abs(got[p] - wv) <= 1e-12 * scale, (p, got[p], wv)
+
+
+@pytest.mark.parametrize("n,lanes", [(512, -1), (512, 64), (1024, -1), (1024, 64), (1024, 128)])
+def test_apply_specialised_column_pass(n, lanes):
+    # the symbol column pass at lengths 1024 and 2048 in each of the forms the
+    # autotuner chooses from; sampled outputs against the oracle's direct sums
+    _say("column pass", n, lanes)
+    fl = _fl()
+    alpha = 1.3
+    h = 2.0 / (n + 1)
+    op = fl.Op(2, alpha, h, (n, n), col_lanes=lanes)
+    assert op.plan()["col_lanes"]["f32"] == (0 if lanes < 0 else lanes)
+    u, _ = bump_field(n, 2, 16, 7, width=(0.05, 0.2))
+    u = u + 0.1 * white_noise((n, n), 3)
+    w = O.weights_folded(2, alpha, h, (n, n))
+    rng = np.random.default_rng(n + lanes)
+    pts = [(0, 0), (n - 1, n - 1), (n // 2, 7)] + [tuple(rng.integers(0, n, 2)) for _ in range(5)]
+    want = O.apply_at(w, u, pts)
+    g64 = op.apply(_dev(u)).cpu().numpy()
+    g32 = op.apply(_dev(u, torch.float32)).cpu().numpy()
+    scale = np.abs(g64).max()
+    for p_, wv in zip(pts, want):
+        assert abs(g64[p_] - wv) <= 1e-12 * scale, (p_, g64[p_], wv)
+        assert abs(g32[p_] - wv) <= 2e-5 * scale, (p_, g32[p_], wv)
