@@ -74,7 +74,8 @@ typedef struct {
                            2 = chirp-z with a 5-smooth length >= 2n-1 */
   int col_lanes;        /* symbol column pass at lengths 1024 and 2048: 0 = autotune, -1 = run-time plan,
                            64 or 128 = lanes per column of the specialised kernel */
-  int reserved[4];
+  int sine_col_lanes;   /* sine column pass at direct length 2050: 0 = autotune, -1 = plan, 128 = forced */
+  int reserved[3];
 } fl_weights_opts;
 
 typedef struct {
@@ -116,10 +117,11 @@ fl_status fl_op_constants(fl_op op, double out[8]);
 /* Padded circulant lengths P_k (out[0..d-1]). */
 fl_status fl_op_padded(fl_op op, int64_t* out);
 
-/* Plans chosen for the op (14 entries), per precision p (0 FP64, 1 FP32):
+/* Plans chosen for the op (16 entries), per precision p (0 FP64, 1 FP32):
  * out[3 p + a] = 1 (direct) or 2 (chirp-z) sine transform along axis a < d,
  * out[6 + 3 p + a] = its FFT length, out[12 + p] = lanes per column of the
- * symbol column pass (0: run-time plan; 64 or 128: specialised kernel). */
+ * symbol column pass (0: run-time plan; 64 or 128: specialised kernel),
+ * out[14 + p] = lanes per FFT line of the sine column pass (0: plan; 128). */
 fl_status fl_op_plan(fl_op op, int64_t* out);
 
 /* Device-to-device copy of the folded arrays, shape [P_1/2+1]...[P_d/2+1]:

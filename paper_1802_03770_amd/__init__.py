@@ -32,7 +32,7 @@ class FlError(RuntimeError):
 
 class WeightsOpts(ctypes.Structure):
     _fields_ = [("delta_over_h", ctypes.c_double), ("dst_mode", ctypes.c_int), ("col_lanes", ctypes.c_int),
-                ("reserved", ctypes.c_int * 4)]
+                ("sine_col_lanes", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -135,7 +135,7 @@ def solve_opts(pc=FL_PC_FD, mixed=0, maxit=0, inner_tol=0.0, use_x0=0, graph=1, 
 class Op:
     """fl_op handle: the discrete fractional Laplacian M on an n_1 x ... x n_d grid."""
 
-    def __init__(self, d, alpha, h, n, delta_over_h=20.0, stream=None, dst_mode=0, col_lanes=0):
+    def __init__(self, d, alpha, h, n, delta_over_h=20.0, stream=None, dst_mode=0, col_lanes=0, sine_col_lanes=0):
         lib = load()
         self.d, self.alpha, self.h = int(d), float(alpha), float(h)
         self.n = tuple(int(v) for v in (n if hasattr(n, "__len__") else [n] * d))
@@ -146,7 +146,7 @@ class Op:
             stream = torch.cuda.Stream()
         self.stream = stream
         arr = (ctypes.c_int64 * 3)(*(list(self.n) + [1] * (3 - self.d)))
-        opts = WeightsOpts(delta_over_h, dst_mode, col_lanes, (ctypes.c_int * 4)())
+        opts = WeightsOpts(delta_over_h, dst_mode, col_lanes, sine_col_lanes, (ctypes.c_int * 3)())
         h_ = ctypes.c_void_p()
         _check(lib.fl_make_weights(self.d, self.alpha, self.h, arr, ctypes.byref(opts),
                                    ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h_)))
@@ -179,11 +179,12 @@ class Op:
     def plan(self):
         """Plans: {"f64"/"f32": [(sine form, length) per axis], "col_lanes": lanes per column of the symbol pass};
         sine form 1 direct, 2 chirp-z; col lanes 0 = run-time plan."""
-        out = (ctypes.c_int64 * 14)()
+        out = (ctypes.c_int64 * 16)()
         _check(load().fl_op_plan(self._h, out))
         plan = {p: [(int(out[3 * i + a]), int(out[6 + 3 * i + a])) for a in range(self.d)]
                 for i, p in enumerate(("f64", "f32"))}
         plan["col_lanes"] = {"f64": int(out[12]), "f32": int(out[13])}
+        plan["sine_col_lanes"] = {"f64": int(out[14]), "f32": int(out[15])}
         return plan
 
     def export(self, which):

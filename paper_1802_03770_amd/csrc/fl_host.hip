@@ -224,6 +224,24 @@ template <typename T> static fl_status autotune_col(fl_op op) {
   return FL_OK;
 }
 
+// Autotuner of the sine column pass at direct length 2050 (grids of 1024):
+// the plan's lanes per FFT line or 128 (two FFT lines per block), per precision.
+template <typename T> static fl_status autotune_dcol(fl_op op) {
+  Axis& A = op->ax[tix<T>()][0];
+  if (op->d != 2 || !A.dst_direct || !A.dst.fixed || A.dst.L != 2050) return FL_OK;
+  if (op->sine_col_lanes != 0) {  // forced
+    A.dcol_tplf = op->sine_col_lanes > 0 ? 128 : 0;
+    return FL_OK;
+  }
+  double t0 = 0.0, t1 = 0.0;
+  A.dcol_tplf = 0;
+  STCHK(profile_t<T>(op, 4, 5, &t0));
+  A.dcol_tplf = 128;
+  STCHK(profile_t<T>(op, 4, 5, &t1));
+  A.dcol_tplf = t1 < t0 ? 128 : 0;
+  return FL_OK;
+}
+
 template <typename T> static fl_status autotune_dst(fl_op op) {
   bool any = false;
   for (int a = 0; a < op->d; ++a) any = any || op->dst_form[tix<T>()][a] == 1;
@@ -278,6 +296,7 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
   }
   op->dst_mode = (o && o->dst_mode >= 0 && o->dst_mode <= 2) ? o->dst_mode : 0;
   op->col_lanes = (o && (o->col_lanes == -1 || o->col_lanes == 64 || o->col_lanes == 128)) ? o->col_lanes : 0;
+  op->sine_col_lanes = (o && (o->sine_col_lanes == -1 || o->sine_col_lanes == 128)) ? o->sine_col_lanes : 0;
   for (int a = 0; a < d; ++a) {
     if ((st = build_axis<double>(op, a, op->dst_mode == 2 ? 2 : 1)) != FL_OK) return bail(st);
     if ((st = build_axis<float>(op, a, op->dst_mode == 2 ? 2 : 1)) != FL_OK) return bail(st);
@@ -298,6 +317,8 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
   }
   if ((st = autotune_col<double>(op)) != FL_OK) return bail(st);
   if ((st = autotune_col<float>(op)) != FL_OK) return bail(st);
+  if ((st = autotune_dcol<double>(op)) != FL_OK) return bail(st);
+  if ((st = autotune_dcol<float>(op)) != FL_OK) return bail(st);
   *out = op;
   return FL_OK;
 }
@@ -686,13 +707,14 @@ fl_status fl_op_padded(fl_op op, int64_t* out) {
 
 fl_status fl_op_plan(fl_op op, int64_t* out) {
   if (!op || !out) return fail(FL_E_INVALID, "NULL argument");
-  for (int i = 0; i < 14; ++i) out[i] = 0;
+  for (int i = 0; i < 16; ++i) out[i] = 0;
   for (int p = 0; p < 2; ++p) {
     for (int a = 0; a < op->d; ++a) {
       out[3 * p + a] = op->dst_form[p][a];
       out[6 + 3 * p + a] = op->ax[p][a].dst.L;
     }
     out[12 + p] = op->ax[p][0].col_tplf;
+    out[14 + p] = op->ax[p][0].dcol_tplf;
   }
   return FL_OK;
 }

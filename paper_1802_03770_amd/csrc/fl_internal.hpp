@@ -71,6 +71,7 @@ struct fl_op_s {
   double alpha = 0, h = 0, c = 20;
   int dst_mode = 0;         // 0 autotune, 1 direct when possible, 2 chirp-z
   int col_lanes = 0;        // 0 autotune, -1 run-time plan, 64 / 128 forced
+  int sine_col_lanes = 0;   // 0 autotune, -1 plan, 128 forced
   int dst_form[2][3] = {};  // chosen per precision and axis: 1 direct, 2 chirp-z
   int n[3] = {1, 1, 1}, P[3] = {2, 2, 2}, H[3] = {1, 1, 1};
   long N = 0, NH = 0;

@@ -629,10 +629,10 @@ __device__ __forceinline__ cx<T> sine_pair_get(Line<T> buf, int k) {
 // Sine-transform line FFT: LF = 0 follows the run-time plan (any direct or
 // chirp-z form); LF > 0 is a kernel specialised for the direct form of that
 // length, which then contains no other path (and no other register demand).
-template <typename T, bool INV, int LF>
+template <typename T, bool INV, int LF, int TPLF = 0>
 __device__ __forceinline__ Line<T> dst_fft(Line<T> a, Line<T> b, const FFTPlan& pl, int lane) {
   if constexpr (LF > 0) {
-    fft_fixed<T, LF, INV>(a, b, (const cx<T>*)pl.tw, lane);
+    cstages<T, LF, (TPLF > 0 ? TPLF : c_fixed_tpl(LF)), INV, 0, 1>(a, b, (const cx<T>*)pl.tw, lane);
     return a;
   } else {
     return fft_line_wide<T, INV>(a, b, pl, lane);
@@ -777,13 +777,13 @@ __device__ __forceinline__ double eig_tail(const Prob& pb, long c) {
   return (double)((const T*)pb.ax[1].eig)[c / n2] + (double)((const T*)pb.ax[2].eig)[c % n2];
 }
 
-template <typename T, bool SCALE, int LF = 0>
+template <typename T, bool SCALE, int LF = 0, int TPLF = 0>
 __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, bool check_done, int blk0, int nblk) {
   if (check_done && pb.sc->done) return;
   const long blk = xcd_tile(blk0, nblk);
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[dg.axis];
-  const int n = A.n, Lf = A.dst.L, tpl = A.dst.tpl;
+  const int n = A.n, Lf = LF > 0 ? LF : A.dst.L, tpl = (LF > 0 && TPLF > 0) ? TPLF : A.dst.tpl;
   const bool direct = LF > 0 ? true : A.dst_direct;
   const int GF = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   const int G = direct ? 2 * GF : GF;  // real lines per block
@@ -822,7 +822,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   Line<T> buf2 = line_at<T>(smem, 2 * g + 1, Lf);
   Line<T> res = buf;
   if (direct) {
-    res = dst_fft<T, false, LF>(buf, buf2, A.dst, lane);
+    res = dst_fft<T, false, LF, TPLF>(buf, buf2, A.dst, lane);
   } else {
     if constexpr (LF == 0) dst_line<T>(buf, A, lane, tpl);
   }
@@ -855,7 +855,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
         res[n + 1] = {0, 0};
       }
       __syncthreads();
-      res = dst_fft<T, false, LF>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
+      res = dst_fft<T, false, LF, TPLF>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
     } else {
       const long c = c0 + g;
       const bool ok = c < dg.gs;
@@ -1019,8 +1019,9 @@ __global__ FL_BOUNDS void k_dst_rows_b(const Prob* pbs, Iter it, int chk, const 
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
   dst_rows_body<T, DPRO, DEPI>(pbs[blockIdx.y], it, chk, nb[blockIdx.y], blockIdx.x);
 }
-template <typename T, bool SCALE, int LF = 0> __global__ FL_BOUNDS void k_dst_cols(Prob pb, DGeom dg, int chk) {
-  dst_cols_body<T, SCALE, LF>(pb, dg, chk, blockIdx.x, gridDim.x);
+template <typename T, bool SCALE, int LF = 0, int TPLF = 0>
+__global__ FL_BOUNDS void k_dst_cols(Prob pb, DGeom dg, int chk) {
+  dst_cols_body<T, SCALE, LF, TPLF>(pb, dg, chk, blockIdx.x, gridDim.x);
 }
 template <typename T, bool SCALE>
 __global__ FL_BOUNDS void k_dst_cols_b(const Prob* pbs, const DGeom* dgs, int chk, const int* nb) {

@@ -28,7 +28,11 @@ static fl_status launch_dst_rows(int lf, dim3 g, dim3 b, size_t sm, hipStream_t 
 
 template <typename T, bool SCALE>
 static fl_status launch_dst_cols(int lf, dim3 g, dim3 b, size_t sm, hipStream_t s, const Prob& pb, const DGeom& dg,
-                                 int chk) {
+                                 int chk, int tplf = 0) {
+  if (lf == 2050 && tplf == 128) {
+    LAUNCH((k_dst_cols<T, SCALE, 2050, 128>), g, b, sm, s, pb, dg, chk);
+    return FL_OK;
+  }
   switch (lf) {
     case 2050: LAUNCH((k_dst_cols<T, SCALE, 2050>), g, b, sm, s, pb, dg, chk); break;
     case 1026: LAUNCH((k_dst_cols<T, SCALE, 1026>), g, b, sm, s, pb, dg, chk); break;
@@ -63,12 +67,13 @@ template <typename T, int DPRO, int DEPI> fl_status precond_seq(fl_op op, Prob p
     Prob pc = pb;
     Axis& A = pc.ax[g.axis];
     const int per = A.dst_direct ? 2 : 1;  // real lines per FFT line
-    A.dst.tpl = tune_tpl(A.dst.tpl, A.dst.L, g.gs * g.ngroup / per);
+    const int lf = dst_lf(A), tplf = (lf == 2050 && A.dcol_tplf == 128) ? 128 : 0;
+    A.dst.tpl = tplf ? tplf : tune_tpl(A.dst.tpl, A.dst.L, g.gs * g.ngroup / per);
     int ntc = block_for(A.dst.tpl), Gf = ntc / A.dst.tpl, Gc = Gf * per;
     long grid = g.ngroup * ((g.gs + Gc - 1) / Gc);
     size_t smc = (size_t)Gf * Line<T>::stride(A.dst.L) * sizeof(cx<T>) * per;
-    if (scale) return launch_dst_cols<T, true>(dst_lf(A), dim3(grid), dim3(ntc), smc, s, pc, g, chk);
-    return launch_dst_cols<T, false>(dst_lf(A), dim3(grid), dim3(ntc), smc, s, pc, g, chk);
+    if (scale) return launch_dst_cols<T, true>(lf, dim3(grid), dim3(ntc), smc, s, pc, g, chk, tplf);
+    return launch_dst_cols<T, false>(lf, dim3(grid), dim3(ntc), smc, s, pc, g, chk, tplf);
   };
   const long nr = pb.nrhs;
   if (d == 2) {
@@ -127,12 +132,13 @@ template <typename T> fl_status launch_precond_pass(fl_op op, Prob pb, int pass)
       g = DGeom{0, n12, 1, n12, (long)op->n[0] * n12};
     }
     const int per = pb.ax[0].dst_direct ? 2 : 1;
-    pb.ax[0].dst.tpl = tune_tpl(pb.ax[0].dst.tpl, pb.ax[0].dst.L, g.gs * g.ngroup / per);
+    const int lf = dst_lf(pb.ax[0]), tplf = (lf == 2050 && pb.ax[0].dcol_tplf == 128) ? 128 : 0;
+    pb.ax[0].dst.tpl = tplf ? tplf : tune_tpl(pb.ax[0].dst.tpl, pb.ax[0].dst.L, g.gs * g.ngroup / per);
     const Axis& A = pb.ax[0];
     int nt = block_for(A.dst.tpl), Gf = nt / A.dst.tpl, G = Gf * per;
     long grid = g.ngroup * ((g.gs + G - 1) / G);
-    STCHK((launch_dst_cols<T, true>(dst_lf(A), dim3(grid), dim3(nt),
-                                    (size_t)Gf * Line<T>::stride(A.dst.L) * sizeof(cx<T>) * per, s, pb, g, 0)));
+    STCHK((launch_dst_cols<T, true>(lf, dim3(grid), dim3(nt),
+                                    (size_t)Gf * Line<T>::stride(A.dst.L) * sizeof(cx<T>) * per, s, pb, g, 0, tplf)));
     return FL_OK;
   }
   return fail(FL_E_INVALID, "preconditioner pass must be 3, 4 or 5");

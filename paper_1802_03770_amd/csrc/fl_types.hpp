@@ -24,6 +24,8 @@ struct Axis {
   FFTPlan dst;      // complex FFT of length Lb (chirp-z) or 2(n+1) (direct)
   int col_tplf;     // lanes per line of the specialised symbol column pass (lengths
                     // 1024, 2048): 0 = run-time plan, else 64 or 128 (autotuned)
+  int dcol_tplf;    // lanes per FFT line of the sine column pass at direct length
+                    // 2050: 0 = the plan's lanes, else 128 (autotuned)
   int dst_direct;   // 1: two real lines packed as x + i y in an odd extension of
                     //    length 2(n+1); FFT gives -2i S_x + 2 S_y
                     // 0: one line per FFT line by the chirp-z identity

@@ -183,3 +183,24 @@ def test_autotuned_plan_is_recorded():
     for p in ("f64", "f32"):
         for form, L in plan[p]:
             assert (form, L) in ((1, 2050), (2, 2048)), plan
+
+
+@pytest.mark.parametrize("lanes", [-1, 128])
+def test_precond_full_size_sine_column_forms(lanes):
+    # 1024^2 (direct length 2050) with the plan's lanes and with 128 lanes per
+    # FFT line in the sine column pass; whole result against the oracle's dense
+    # sine matrices (FD) and its sine-basis diagonal (spectral)
+    _say("1024^2 sine column lanes", lanes)
+    fl = _fl()
+    from oracle import precond as PCO
+    n, alpha = 1024, 1.0
+    h = 2.0 / (n + 1)
+    op = fl.Op(2, alpha, h, (n, n), sine_col_lanes=lanes, dst_mode=1)
+    assert op.plan()["sine_col_lanes"]["f32"] == (128 if lanes > 0 else 0)
+    r = white_noise((n, n), 21)
+    want = PCO.apply_inverse(r, PCO.pc_scale(2, alpha, h))
+    assert _rel(op.precond(_dev(r)).cpu().numpy(), want) <= 1e-12
+    assert _rel(op.precond(_dev(r, torch.float32)).cpu().numpy(), want) <= 2e-5
+    m = SP.tau_eigenvalues(2, alpha, (n, n))
+    want_s = SP.apply_tau_inverse(r, m, K.c_alpha(alpha, 2) * h ** -alpha)
+    assert _rel(op.precond(_dev(r), kind=fl.FL_PC_SPECTRAL).cpu().numpy(), want_s) <= 1e-12
