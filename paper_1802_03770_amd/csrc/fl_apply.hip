@@ -16,6 +16,9 @@ template <typename T> static fl_status launch_col_conv(const Prob& pc, const Col
     // FP64 at 2048 with 64 lanes would need 4 x 37 KB of LDS: keep 128
     if (lf == 2048 && sizeof(T) == 8) tplf = 128;
     if (lf == 1024) tplf = 64;
+  } else if (fft_lf(A) == 512 || fft_lf(A) == 256) {
+    lf = A.P;  // the plan's lanes, compile-time
+    tplf = c_fixed_tpl(lf);
   }
   Prob pl = pc;
   if (!lf) pl.ax[cg.axis].fft.tpl = tune_tpl(A.fft.tpl, A.P, cg.gs * cg.ngroup);
@@ -29,8 +32,36 @@ template <typename T> static fl_status launch_col_conv(const Prob& pc, const Col
     LAUNCH((k_colpass<T, COL_CONV, 2048, 128>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
   else if (lf == 1024)
     LAUNCH((k_colpass<T, COL_CONV, 1024, 64>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
+  else if (lf == 512)
+    LAUNCH((k_colpass<T, COL_CONV, 512, c_fixed_tpl(512)>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
+  else if (lf == 256)
+    LAUNCH((k_colpass<T, COL_CONV, 256, c_fixed_tpl(256)>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
   else
     LAUNCH((k_colpass<T, COL_CONV>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
+  return FL_OK;
+}
+
+// Row passes with the length specialisation of the last axis (fft_lf).
+template <typename T, int PRO>
+static fl_status launch_rowfwd(int lf, dim3 g, dim3 b, size_t sm, hipStream_t s, const Prob& pb, Iter it) {
+  switch (lf) {
+    case 2048: LAUNCH((k_rowfwd<T, PRO, 2048>), g, b, sm, s, pb, it); break;
+    case 1024: LAUNCH((k_rowfwd<T, PRO, 1024>), g, b, sm, s, pb, it); break;
+    case 512: LAUNCH((k_rowfwd<T, PRO, 512>), g, b, sm, s, pb, it); break;
+    case 256: LAUNCH((k_rowfwd<T, PRO, 256>), g, b, sm, s, pb, it); break;
+    default: LAUNCH((k_rowfwd<T, PRO>), g, b, sm, s, pb, it); break;
+  }
+  return FL_OK;
+}
+template <typename T, int EPI>
+static fl_status launch_rowinv(int lf, dim3 g, dim3 b, size_t sm, hipStream_t s, const Prob& pb, Iter it, int chk) {
+  switch (lf) {
+    case 2048: LAUNCH((k_rowinv<T, EPI, 2048>), g, b, sm, s, pb, it, chk); break;
+    case 1024: LAUNCH((k_rowinv<T, EPI, 1024>), g, b, sm, s, pb, it, chk); break;
+    case 512: LAUNCH((k_rowinv<T, EPI, 512>), g, b, sm, s, pb, it, chk); break;
+    case 256: LAUNCH((k_rowinv<T, EPI, 256>), g, b, sm, s, pb, it, chk); break;
+    default: LAUNCH((k_rowinv<T, EPI>), g, b, sm, s, pb, it, chk); break;
+  }
   return FL_OK;
 }
 
@@ -55,7 +86,8 @@ template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob
   const Axis& AL = pr.ax[d - 1];
   {
     int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
-    LAUNCH(k_rowfwd<T, PRO>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pr, it);
+    STCHK((launch_rowfwd<T, PRO>(fft_lf(AL), dim3((pairs + G - 1) / G), dim3(nt),
+                                  (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pr, it)));
   }
   auto col = [&](ColGeom cg, int mode) -> fl_status {
     Prob pc = pb;
@@ -65,8 +97,17 @@ template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob
     int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
     long grid = cg.ngroup * ((cg.gs + G - 1) / G);
     size_t sm = (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>);
-    if (mode == COL_FWD) LAUNCH(k_colpass<T, COL_FWD>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
-    if (mode == COL_INV) LAUNCH(k_colpass<T, COL_INV>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+    const int lf = fft_lf(A);
+    if (mode == COL_FWD) {
+      if (lf == 512) LAUNCH((k_colpass<T, COL_FWD, 512, c_fixed_tpl(512)>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+      else if (lf == 256) LAUNCH((k_colpass<T, COL_FWD, 256, c_fixed_tpl(256)>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+      else LAUNCH(k_colpass<T, COL_FWD>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+    }
+    if (mode == COL_INV) {
+      if (lf == 512) LAUNCH((k_colpass<T, COL_INV, 512, c_fixed_tpl(512)>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+      else if (lf == 256) LAUNCH((k_colpass<T, COL_INV, 256, c_fixed_tpl(256)>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+      else LAUNCH(k_colpass<T, COL_INV>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+    }
     return FL_OK;
   };
   const long nr = pb.nrhs;
@@ -85,7 +126,8 @@ template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob
   }
   {
     int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
-    LAUNCH(k_rowinv<T, EPI>, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pr, it, chk);
+    STCHK((launch_rowinv<T, EPI>(fft_lf(AL), dim3((pairs + G - 1) / G), dim3(nt),
+                                  (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>), s, pr, it, chk)));
   }
   return FL_OK;
 }
@@ -109,8 +151,8 @@ template <typename T> fl_status launch_apply_pass(fl_op op, Prob pb, int pass) {
     const Axis& AL = pb.ax[d - 1];
     int nt = block_for(AL.fft.tpl), G = nt / AL.fft.tpl;
     size_t sm = (size_t)G * Line<T>::stride(AL.P) * sizeof(cx<T>);
-    if (pass == 0) LAUNCH(k_rowfwd<T, PRO_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), sm, s, pb, it);
-    else LAUNCH(k_rowinv<T, EPI_PLAIN>, dim3((pairs + G - 1) / G), dim3(nt), sm, s, pb, it, 0);
+    if (pass == 0) STCHK((launch_rowfwd<T, PRO_PLAIN>(fft_lf(AL), dim3((pairs + G - 1) / G), dim3(nt), sm, s, pb, it)));
+    else STCHK((launch_rowinv<T, EPI_PLAIN>(fft_lf(AL), dim3((pairs + G - 1) / G), dim3(nt), sm, s, pb, it, 0)));
     return FL_OK;
   }
   if (pass == 1) {

@@ -57,10 +57,13 @@ template <typename T> fl_status bt_setup(BatchT& bt, const BatchDesc& B, const s
       bt.cg[np + p] = ColGeom{0, (int)n0, (int)n0, P1 * H2, 1, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
       bt.cg[2 * np + p] = ColGeom{1, (int)P1, (int)n1, H2, n0, H2, P1 * H2, H2, n1 * H2, 2, 1};
     }
+    bt.lf_rowfft = (p == 0 || bt.lf_rowfft == fft_lf(AL)) ? fft_lf(AL) : 0;
     const int ncol = d == 3 ? 3 : (d == 2 ? 1 : 0);
     for (int r = 0; r < ncol; ++r) {
       const ColGeom& c = bt.cg[r * np + p];
       const Axis& A = pb.ax[c.axis];
+      const int lfc = (fft_lf(A) == 512 || fft_lf(A) == 256) ? fft_lf(A) : 0;
+      bt.lf_col[r] = (p == 0 || bt.lf_col[r] == lfc) ? lfc : 0;
       int G = 256 / A.fft.tpl;
       bt.nb_col[r][p] = (int)(c.ngroup * ((c.gs + G - 1) / G));
       bt.sm_col[r] = std::max(bt.sm_col[r], lds_fft<T>(A.P, G));
@@ -78,10 +81,12 @@ template <typename T> fl_status bt_setup(BatchT& bt, const BatchDesc& B, const s
       bt.dg[p] = DGeom{1, (long)n[2], (long)n[0], (long)n[2], (long)n[1] * n[2]};
       bt.dg[np + p] = DGeom{0, (long)n[1] * n[2], 1, (long)n[1] * n[2], (long)n[0] * n[1] * n[2]};
     }
+    bt.lf_row = (p == 0 || bt.lf_row == dst_lf(AL)) ? dst_lf(AL) : 0;
     const int ndc = d == 3 ? 2 : (d == 2 ? 1 : 0);
     for (int r = 0; r < ndc; ++r) {
       const DGeom& g = bt.dg[r * np + p];
       const Axis& A = pb.ax[g.axis];
+      bt.lf_dcol[r] = (p == 0 || bt.lf_dcol[r] == dst_lf(A)) ? dst_lf(A) : 0;
       const int per = A.dst_direct ? 2 : 1;
       int Gf = 256 / A.dst.tpl, G = Gf * per;
       bt.nb_dcol[r][p] = (int)(g.ngroup * ((g.gs + G - 1) / G));
@@ -107,50 +112,111 @@ template <typename T, int PRO, int EPI> fl_status bt_apply(BatchT& bt, const Pro
            (const int*)bt.d_nb_rowfwd);
     return FL_OK;
   }
-  LAUNCH(k_rowfwd_b<T, PRO>, dim3(vmax(bt.nb_rowfwd), np), dim3(256), bt.sm_row, s, pbs, it,
-         (const int*)bt.d_nb_rowfwd);
-  if (d == 2) {
-    LAUNCH(k_colpass_b<T, COL_CONV>, dim3(vmax(bt.nb_col[0]), np), dim3(256), bt.sm_col[0], s, pbs,
-           (const ColGeom*)bt.d_cg, it, chk, (const int*)bt.d_nb_col[0]);
-  } else {
-    LAUNCH(k_colpass_b<T, COL_FWD>, dim3(vmax(bt.nb_col[0]), np), dim3(256), bt.sm_col[0], s, pbs,
-           (const ColGeom*)bt.d_cg, it, chk, (const int*)bt.d_nb_col[0]);
-    LAUNCH(k_colpass_b<T, COL_CONV>, dim3(vmax(bt.nb_col[1]), np), dim3(256), bt.sm_col[1], s, pbs,
-           (const ColGeom*)bt.d_cg + np, it, chk, (const int*)bt.d_nb_col[1]);
-    LAUNCH(k_colpass_b<T, COL_INV>, dim3(vmax(bt.nb_col[2]), np), dim3(256), bt.sm_col[2], s, pbs,
-           (const ColGeom*)bt.d_cg + 2 * np, it, chk, (const int*)bt.d_nb_col[2]);
+  const int* nbf = (const int*)bt.d_nb_rowfwd;
+  const dim3 gf(vmax(bt.nb_rowfwd), np);
+  switch (bt.lf_rowfft) {
+    case 2048: LAUNCH((k_rowfwd_b<T, PRO, 2048>), gf, dim3(256), bt.sm_row, s, pbs, it, nbf); break;
+    case 1024: LAUNCH((k_rowfwd_b<T, PRO, 1024>), gf, dim3(256), bt.sm_row, s, pbs, it, nbf); break;
+    case 512: LAUNCH((k_rowfwd_b<T, PRO, 512>), gf, dim3(256), bt.sm_row, s, pbs, it, nbf); break;
+    case 256: LAUNCH((k_rowfwd_b<T, PRO, 256>), gf, dim3(256), bt.sm_row, s, pbs, it, nbf); break;
+    default: LAUNCH((k_rowfwd_b<T, PRO>), gf, dim3(256), bt.sm_row, s, pbs, it, nbf); break;
   }
-  LAUNCH(k_rowinv_b<T, EPI>, dim3(vmax(bt.nb_rowinv), np), dim3(256), bt.sm_row, s, pbs, it, chk,
-         (const int*)bt.d_nb_rowinv);
+  auto col = [&](int r, int mode) -> fl_status {
+    const dim3 g(vmax(bt.nb_col[r]), np);
+    const ColGeom* cg = (const ColGeom*)bt.d_cg + r * np;
+    const int* nb = (const int*)bt.d_nb_col[r];
+    const int lf = bt.lf_col[r];
+#define FL_COLB(M)                                                                                      \
+  switch (lf) {                                                                                         \
+    case 512: LAUNCH((k_colpass_b<T, M, 512>), g, dim3(256), bt.sm_col[r], s, pbs, cg, it, chk, nb); break; \
+    case 256: LAUNCH((k_colpass_b<T, M, 256>), g, dim3(256), bt.sm_col[r], s, pbs, cg, it, chk, nb); break; \
+    default: LAUNCH((k_colpass_b<T, M>), g, dim3(256), bt.sm_col[r], s, pbs, cg, it, chk, nb); break;       \
+  }
+    if (mode == COL_FWD) { FL_COLB(COL_FWD) }
+    else if (mode == COL_CONV) { FL_COLB(COL_CONV) }
+    else { FL_COLB(COL_INV) }
+#undef FL_COLB
+    return FL_OK;
+  };
+  if (d == 2) {
+    STCHK(col(0, COL_CONV));
+  } else {
+    STCHK(col(0, COL_FWD));
+    STCHK(col(1, COL_CONV));
+    STCHK(col(2, COL_INV));
+  }
+  const int* nbi = (const int*)bt.d_nb_rowinv;
+  const dim3 gi(vmax(bt.nb_rowinv), np);
+  switch (bt.lf_rowfft) {
+    case 2048: LAUNCH((k_rowinv_b<T, EPI, 2048>), gi, dim3(256), bt.sm_row, s, pbs, it, chk, nbi); break;
+    case 1024: LAUNCH((k_rowinv_b<T, EPI, 1024>), gi, dim3(256), bt.sm_row, s, pbs, it, chk, nbi); break;
+    case 512: LAUNCH((k_rowinv_b<T, EPI, 512>), gi, dim3(256), bt.sm_row, s, pbs, it, chk, nbi); break;
+    case 256: LAUNCH((k_rowinv_b<T, EPI, 256>), gi, dim3(256), bt.sm_row, s, pbs, it, chk, nbi); break;
+    default: LAUNCH((k_rowinv_b<T, EPI>), gi, dim3(256), bt.sm_row, s, pbs, it, chk, nbi); break;
+  }
   return FL_OK;
 }
 
 // Batched preconditioner.  pfirst: Prob array of the first pass (reads `in`,
 // writes `out` = T1); plast: Prob array of the last pass (reads `in` = T1).
+// Sine-kernel launches with the length specialisation every problem shares.
+template <typename T, int DPRO, int DEPI>
+static fl_status bt_dst_rows(int lf, dim3 g, size_t sm, hipStream_t s, const Prob* pbs, Iter it, int chk, const int* nb) {
+  switch (lf) {
+    case 2050: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, 2050>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
+    case 1026: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, 1026>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
+    case 770: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, 770>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
+    case 258: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, 258>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
+    case 130: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, 130>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
+    case -512: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, -512>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
+    case -256: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, -256>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
+    case -1024: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, -1024>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
+    default: LAUNCH((k_dst_rows_b<T, DPRO, DEPI>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
+  }
+  return FL_OK;
+}
+template <typename T, bool SCALE>
+static fl_status bt_dst_cols(int lf, dim3 g, size_t sm, hipStream_t s, const Prob* pbs, const DGeom* dgs, int chk,
+                        const int* nb) {
+  switch (lf) {
+    case 2050: LAUNCH((k_dst_cols_b<T, SCALE, 2050>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
+    case 1026: LAUNCH((k_dst_cols_b<T, SCALE, 1026>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
+    case 770: LAUNCH((k_dst_cols_b<T, SCALE, 770>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
+    case 258: LAUNCH((k_dst_cols_b<T, SCALE, 258>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
+    case 130: LAUNCH((k_dst_cols_b<T, SCALE, 130>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
+    case -512: LAUNCH((k_dst_cols_b<T, SCALE, -512>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
+    case -256: LAUNCH((k_dst_cols_b<T, SCALE, -256>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
+    case -1024: LAUNCH((k_dst_cols_b<T, SCALE, -1024>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
+    default: LAUNCH((k_dst_cols_b<T, SCALE>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
+  }
+  return FL_OK;
+}
+
 template <typename T, int DPRO, int DEPI> fl_status bt_precond(BatchT& bt, const Prob* pfirst, const Prob* plast,
                                                               Iter it, int chk, hipStream_t s) {
   const int np = bt.np, d = bt.d;
   dim3 gr(vmax(bt.nb_dstrow), np);
+  const int* nbr = (const int*)bt.d_nb_dstrow;
   if (d == 1) {
-    LAUNCH(k_dst_rows_b<T, DPRO, DEPI>, gr, dim3(256), bt.sm_dstrow, s, pfirst, it, chk, (const int*)bt.d_nb_dstrow);
+    LAUNCH((k_dst_rows_b<T, DPRO, DEPI>), gr, dim3(256), bt.sm_dstrow, s, pfirst, it, chk, nbr);
     return FL_OK;
   }
-  LAUNCH(k_dst_rows_b<T, DPRO, DEPI_STORE>, gr, dim3(256), bt.sm_dstrow, s, pfirst, it, chk,
-         (const int*)bt.d_nb_dstrow);
+  STCHK((bt_dst_rows<T, DPRO, DEPI_STORE>(bt.lf_row, gr, bt.sm_dstrow, s, pfirst, it, chk, nbr)));
+  const DGeom* dg = (const DGeom*)bt.d_dg;
+  auto cols = [&](int r, bool scale) -> fl_status {
+    dim3 g(vmax(bt.nb_dcol[r]), np);
+    const int* nb = (const int*)bt.d_nb_dcol[r];
+    if (scale) return bt_dst_cols<T, true>(bt.lf_dcol[r], g, bt.sm_dcol[r], s, plast, dg + r * np, chk, nb);
+    return bt_dst_cols<T, false>(bt.lf_dcol[r], g, bt.sm_dcol[r], s, plast, dg + r * np, chk, nb);
+  };
   if (d == 2) {
-    LAUNCH(k_dst_cols_b<T, true>, dim3(vmax(bt.nb_dcol[0]), np), dim3(256), bt.sm_dcol[0], s, plast,
-           (const DGeom*)bt.d_dg, chk, (const int*)bt.d_nb_dcol[0]);
+    STCHK(cols(0, true));
   } else {
-    LAUNCH(k_dst_cols_b<T, false>, dim3(vmax(bt.nb_dcol[0]), np), dim3(256), bt.sm_dcol[0], s, plast,
-           (const DGeom*)bt.d_dg, chk, (const int*)bt.d_nb_dcol[0]);
-    LAUNCH(k_dst_cols_b<T, true>, dim3(vmax(bt.nb_dcol[1]), np), dim3(256), bt.sm_dcol[1], s, plast,
-           (const DGeom*)bt.d_dg + np, chk, (const int*)bt.d_nb_dcol[1]);
-    LAUNCH(k_dst_cols_b<T, false>, dim3(vmax(bt.nb_dcol[0]), np), dim3(256), bt.sm_dcol[0], s, plast,
-           (const DGeom*)bt.d_dg, chk, (const int*)bt.d_nb_dcol[0]);
+    STCHK(cols(0, false));
+    STCHK(cols(1, true));
+    STCHK(cols(0, false));
   }
-  LAUNCH(k_dst_rows_b<T, DPRO_PLAIN, DEPI>, gr, dim3(256), bt.sm_dstrow, s, plast, it, chk,
-         (const int*)bt.d_nb_dstrow);
-  return FL_OK;
+  return bt_dst_rows<T, DPRO_PLAIN, DEPI>(bt.lf_row, gr, bt.sm_dstrow, s, plast, it, chk, nbr);
 }
 
 template <typename T> fl_status bt_iteration(BatchT& bt, int pc, int k, hipStream_t s) {

@@ -21,6 +21,10 @@ struct BatchT {
   std::vector<DGeom> dg;    // [2][np]: column passes of the sine transform
   std::vector<long> N;
   size_t sm_row = 0, sm_dstrow = 0, sm_col[3] = {0, 0, 0}, sm_dcol[2] = {0, 0};
+  // sine-kernel length specialisation shared by every problem (0: mixed plans)
+  int lf_row = 0, lf_dcol[2] = {0, 0};
+  // FFT row / column kernel length specialisation shared by every problem
+  int lf_rowfft = 0, lf_col[3] = {0, 0, 0};
   // Prob roles (device arrays of np entries, host copies)
   //  iter: Krylov iteration (in = out = T1);  iter_nopc: z aliases r;
   //  pc0:  first preconditioner pass of the start (in = r);

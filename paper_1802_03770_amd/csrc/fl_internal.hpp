@@ -110,6 +110,34 @@ template <typename T> inline fl_status upload(fl_op op, const std::vector<T>& h,
 // block size for a line-FFT kernel with `tpl` lanes per line
 inline int block_for(int) { return 256; }
 
+// Length specialisation of the sine kernels along an axis: the direct lengths
+// 2(n+1) of the common grids (n = 64, 128, 384, 512, 1024), or minus the FFT
+// length of a chirp-z plan of length 256, 512 or 1024; 0 = the run-time plan.
+inline int dst_lf(const Axis& A) {
+  if (!A.dst.fixed) return 0;
+  if (A.dst_direct) {
+    switch (A.dst.L) {
+      case 2050: case 1026: case 770: case 258: case 130: return A.dst.L;
+      default: return 0;
+    }
+  }
+  switch (A.dst.L) {
+    case 1024: case 512: case 256: return -A.dst.L;
+    default: return 0;
+  }
+}
+
+// Length specialisation of the FFT row and column kernels of the application:
+// the padded lengths 256..2048 of the common grids (lanes c_fixed_tpl(P));
+// 0 = the run-time plan.
+inline int fft_lf(const Axis& A) {
+  if (!A.fft.fixed) return 0;
+  switch (A.P) {
+    case 2048: case 1024: case 512: case 256: return A.P;
+    default: return 0;
+  }
+}
+
 // More lanes per line (fewer elements per lane) when a pass has too few lines
 // to give every CU two workgroups; the plan's tpl is the minimum.
 inline int tune_tpl(int tpl0, int L, long nlines) {

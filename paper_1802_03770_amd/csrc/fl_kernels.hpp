@@ -359,7 +359,15 @@ __device__ __forceinline__ T load_input(const Prob& pb, long e, long nper, doubl
   }
 }
 
-template <typename T, int PRO>
+// Row line FFT: LF = 0 follows the run-time plan; LF > 0 is a kernel
+// specialised for that padded length (lanes c_fixed_tpl(LF)).
+template <typename T, bool INV, int LF>
+__device__ __forceinline__ void row_fft(Line<T> buf, const FFTPlan& pl, int lane) {
+  if constexpr (LF > 0) fft_fixed<T, LF, INV>(buf, buf, (const cx<T>*)pl.tw, lane);
+  else fft_line<T, INV>(buf, pl, lane);
+}
+
+template <typename T, int PRO, int LF = 0>
 __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int blk) {
   double beta = 0.0;
   if (PRO == PRO_PUPD) {
@@ -368,7 +376,7 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
   }
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[pb.d - 1];
-  const int n = A.n, P = A.P, H = A.H, tpl = A.fft.tpl;
+  const int n = A.n, P = LF > 0 ? LF : A.P, H = A.H, tpl = LF > 0 ? c_fixed_tpl(LF) : A.fft.tpl;
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   Line<T> buf = line_at<T>(smem, g, P);
   const long rows = nrows_of(pb), nper = nper_of(pb);
@@ -383,7 +391,7 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
     buf[i] = {xa, xb};
   }
   __syncthreads();
-  fft_line<T, false>(buf, A.fft, lane);
+  row_fft<T, false, LF>(buf, A.fft, lane);
   cx<T>* W = (cx<T>*)pb.W1;
   for (int k = lane; k < H; k += tpl) {
     cx<T> zk = buf[k], zm = buf[(P - k) % P];
@@ -479,12 +487,12 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
 // Inverse row pass: half spectrum -> real rows, crop to n, epilogue.
 //  EPI_PLAIN: out = y;  EPI_RESID: out = aux - y, |out|^2 partials (site S_DOT);
 //  EPI_PQ: q = y, p.q partials (site S_PQ).
-template <typename T, int EPI>
+template <typename T, int EPI, int LF = 0>
 __device__ __forceinline__ void rowinv_body(const Prob& pb, const Iter& it, bool check_done, int nblk, int blk) {
   if (check_done && pb.sc->done) return;
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[pb.d - 1];
-  const int n = A.n, P = A.P, H = A.H, tpl = A.fft.tpl;
+  const int n = A.n, P = LF > 0 ? LF : A.P, H = A.H, tpl = LF > 0 ? c_fixed_tpl(LF) : A.fft.tpl;
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   Line<T> buf = line_at<T>(smem, g, P);
   const long rows = nrows_of(pb), nper = nper_of(pb);
@@ -500,7 +508,7 @@ __device__ __forceinline__ void rowinv_body(const Prob& pb, const Iter& it, bool
     buf[k] = {xa.x - xb.y, xa.y + xb.x};
   }
   __syncthreads();
-  fft_line<T, true>(buf, A.fft, lane);
+  row_fft<T, true, LF>(buf, A.fft, lane);
   double acc = 0.0;
   for (int i = lane; i < n; i += tpl) {
     cx<T> y = buf[i];
@@ -589,10 +597,11 @@ __device__ __forceinline__ void conv1d_body(const Prob& pb, const Iter& it, int 
 // Sine transforms (type I)
 // ---------------------------------------------------------------------------
 // Chirp-z form, one real line per FFT line.  In: buf[j].x = x_j (j < n).
-// Out: buf[k].x = sum_j x_j sin(pi (j+1)(k+1)/(n+1)).
-template <typename T>
+// Out: buf[k].x = sum_j x_j sin(pi (j+1)(k+1)/(n+1)).  CL > 0: the FFT length
+// is the compile-time CL (lanes c_fixed_tpl(CL)), else the run-time plan.
+template <typename T, int CL = 0>
 __device__ __forceinline__ void dst_line(Line<T> buf, const Axis& A, int lane, int tpl) {
-  const int n = A.n, Lb = A.dst.L;
+  const int n = A.n, Lb = CL > 0 ? CL : A.dst.L;
   const cx<T>* ch = (const cx<T>*)A.chirp;
   const cx<T>* bh = (const cx<T>*)A.bhat;
   for (int j = lane; j < Lb; j += tpl) {
@@ -601,10 +610,12 @@ __device__ __forceinline__ void dst_line(Line<T> buf, const Axis& A, int lane, i
     buf[j] = v;
   }
   __syncthreads();
-  fft_line<T, false>(buf, A.dst, lane);
+  if constexpr (CL > 0) fft_fixed<T, CL, false>(buf, buf, (const cx<T>*)A.dst.tw, lane);
+  else fft_line<T, false>(buf, A.dst, lane);
   for (int k = lane; k < Lb; k += tpl) buf[k] = cmul(buf[k], bh[k]);
   __syncthreads();
-  fft_line<T, true>(buf, A.dst, lane);
+  if constexpr (CL > 0) fft_fixed<T, CL, true>(buf, buf, (const cx<T>*)A.dst.tw, lane);
+  else fft_line<T, true>(buf, A.dst, lane);
   for (int k = lane; k < n; k += tpl) {
     cx<T> y = cmul(ch[k + 1], buf[k]);
     buf[k] = {y.y, 0};
@@ -628,11 +639,15 @@ __device__ __forceinline__ cx<T> sine_pair_get(Line<T> buf, int k) {
 
 // Sine-transform line FFT: LF = 0 follows the run-time plan (any direct or
 // chirp-z form); LF > 0 is a kernel specialised for the direct form of that
-// length, which then contains no other path (and no other register demand).
+// length, which then contains no other path (and no other register demand);
+// LF < 0 is a kernel specialised for the chirp-z form with FFT length -LF,
+// which never takes the direct form.
 template <typename T, bool INV, int LF, int TPLF = 0>
 __device__ __forceinline__ Line<T> dst_fft(Line<T> a, Line<T> b, const FFTPlan& pl, int lane) {
   if constexpr (LF > 0) {
     cstages<T, LF, (TPLF > 0 ? TPLF : c_fixed_tpl(LF)), INV, 0, 1>(a, b, (const cx<T>*)pl.tw, lane);
+    return a;
+  } else if constexpr (LF < 0) {
     return a;
   } else {
     return fft_line_wide<T, INV>(a, b, pl, lane);
@@ -666,8 +681,9 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   }
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[pb.d - 1];
-  const int n = A.n, Lf = A.dst.L, tpl = A.dst.tpl;
-  const bool direct = LF > 0 ? true : A.dst_direct;
+  constexpr int CL = LF < 0 ? -LF : 0;  // chirp-z FFT length of a chirp specialisation
+  const int n = A.n, Lf = CL > 0 ? CL : A.dst.L, tpl = CL > 0 ? c_fixed_tpl(CL) : A.dst.tpl;
+  const bool direct = LF > 0 ? true : (LF < 0 ? false : A.dst_direct);
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   // direct: a ping-pong pair of lines per FFT line
   Line<T> buf = line_at<T>(smem, direct ? 2 * g : g, Lf);
@@ -712,7 +728,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   if (direct) {
     res = dst_fft<T, false, LF>(buf, buf2, A.dst, lane);
   } else {
-    if constexpr (LF == 0) dst_line<T>(buf, A, lane, tpl);
+    if constexpr (LF <= 0) dst_line<T, CL>(buf, A, lane, tpl);
   }
   if (pb.d == 1) {
     const T* ev = (const T*)A.eig;
@@ -737,7 +753,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
         buf[k].x = pb.pmul ? buf[k].x * e : buf[k].x / e;
       }
       __syncthreads();
-      if constexpr (LF == 0) dst_line<T>(buf, A, lane, tpl);
+      if constexpr (LF <= 0) dst_line<T, CL>(buf, A, lane, tpl);
     }
   }
   double norm = 1.0;
@@ -783,8 +799,10 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   const long blk = xcd_tile(blk0, nblk);
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[dg.axis];
-  const int n = A.n, Lf = LF > 0 ? LF : A.dst.L, tpl = (LF > 0 && TPLF > 0) ? TPLF : A.dst.tpl;
-  const bool direct = LF > 0 ? true : A.dst_direct;
+  constexpr int CL = LF < 0 ? -LF : 0;  // chirp-z FFT length of a chirp specialisation
+  const int n = A.n, Lf = LF > 0 ? LF : (CL > 0 ? CL : A.dst.L);
+  const int tpl = (LF > 0 && TPLF > 0) ? TPLF : (CL > 0 ? c_fixed_tpl(CL) : A.dst.tpl);
+  const bool direct = LF > 0 ? true : (LF < 0 ? false : A.dst_direct);
   const int GF = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   const int G = direct ? 2 * GF : GF;  // real lines per block
   const long tiles = (dg.gs + G - 1) / G;
@@ -824,7 +842,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   if (direct) {
     res = dst_fft<T, false, LF, TPLF>(buf, buf2, A.dst, lane);
   } else {
-    if constexpr (LF == 0) dst_line<T>(buf, A, lane, tpl);
+    if constexpr (LF <= 0) dst_line<T, CL>(buf, A, lane, tpl);
   }
   if (SCALE) {
     const T* ev = (const T*)A.eig;
@@ -866,7 +884,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
         buf[k].x = pb.pmul ? buf[k].x * e : buf[k].x / e;
       }
       __syncthreads();
-      if constexpr (LF == 0) dst_line<T>(buf, A, lane, tpl);
+      if constexpr (LF <= 0) dst_line<T, CL>(buf, A, lane, tpl);
     }
   }
   // every FFT line of the block ends in the same member of its ping-pong pair
@@ -979,29 +997,31 @@ template <typename T> __global__ void k_fill(T* y, T v, long n) {
 // ---------------------------------------------------------------------------
 #define FL_BOUNDS __launch_bounds__(256)
 
-template <typename T, int PRO> __global__ FL_BOUNDS void k_rowfwd(Prob pb, Iter it) {
-  rowfwd_body<T, PRO>(pb, it, blockIdx.x);
+template <typename T, int PRO, int LF = 0> __global__ FL_BOUNDS void k_rowfwd(Prob pb, Iter it) {
+  rowfwd_body<T, PRO, LF>(pb, it, blockIdx.x);
 }
-template <typename T, int PRO> __global__ FL_BOUNDS void k_rowfwd_b(const Prob* pbs, Iter it, const int* nb) {
+template <typename T, int PRO, int LF = 0>
+__global__ FL_BOUNDS void k_rowfwd_b(const Prob* pbs, Iter it, const int* nb) {
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
-  rowfwd_body<T, PRO>(pbs[blockIdx.y], it, blockIdx.x);
+  rowfwd_body<T, PRO, LF>(pbs[blockIdx.y], it, blockIdx.x);
 }
 template <typename T, int MODE, int LF = 0, int TPLF = 0>
 __global__ FL_BOUNDS void k_colpass(Prob pb, ColGeom cg, Iter it, int chk) {
   colpass_body<T, MODE, LF, TPLF>(pb, cg, it, chk, blockIdx.x, gridDim.x);
 }
-template <typename T, int MODE>
+template <typename T, int MODE, int LF = 0>
 __global__ FL_BOUNDS void k_colpass_b(const Prob* pbs, const ColGeom* cgs, Iter it, int chk, const int* nb) {
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
-  colpass_body<T, MODE>(pbs[blockIdx.y], cgs[blockIdx.y], it, chk, blockIdx.x, nb[blockIdx.y]);
+  colpass_body<T, MODE, LF, (LF > 0 ? c_fixed_tpl(LF) : 0)>(pbs[blockIdx.y], cgs[blockIdx.y], it, chk, blockIdx.x,
+                                                             nb[blockIdx.y]);
 }
-template <typename T, int EPI> __global__ FL_BOUNDS void k_rowinv(Prob pb, Iter it, int chk) {
-  rowinv_body<T, EPI>(pb, it, chk, gridDim.x, blockIdx.x);
+template <typename T, int EPI, int LF = 0> __global__ FL_BOUNDS void k_rowinv(Prob pb, Iter it, int chk) {
+  rowinv_body<T, EPI, LF>(pb, it, chk, gridDim.x, blockIdx.x);
 }
-template <typename T, int EPI>
+template <typename T, int EPI, int LF = 0>
 __global__ FL_BOUNDS void k_rowinv_b(const Prob* pbs, Iter it, int chk, const int* nb) {
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
-  rowinv_body<T, EPI>(pbs[blockIdx.y], it, chk, nb[blockIdx.y], blockIdx.x);
+  rowinv_body<T, EPI, LF>(pbs[blockIdx.y], it, chk, nb[blockIdx.y], blockIdx.x);
 }
 template <typename T, int PRO, int EPI> __global__ FL_BOUNDS void k_conv1d(Prob pb, Iter it) {
   conv1d_body<T, PRO, EPI>(pb, it, gridDim.x, blockIdx.x);
@@ -1014,19 +1034,19 @@ __global__ FL_BOUNDS void k_conv1d_b(const Prob* pbs, Iter it, const int* nb) {
 template <typename T, int DPRO, int DEPI, int LF = 0> __global__ FL_BOUNDS void k_dst_rows(Prob pb, Iter it, int chk) {
   dst_rows_body<T, DPRO, DEPI, LF>(pb, it, chk, gridDim.x, blockIdx.x);
 }
-template <typename T, int DPRO, int DEPI>
+template <typename T, int DPRO, int DEPI, int LF = 0>
 __global__ FL_BOUNDS void k_dst_rows_b(const Prob* pbs, Iter it, int chk, const int* nb) {
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
-  dst_rows_body<T, DPRO, DEPI>(pbs[blockIdx.y], it, chk, nb[blockIdx.y], blockIdx.x);
+  dst_rows_body<T, DPRO, DEPI, LF>(pbs[blockIdx.y], it, chk, nb[blockIdx.y], blockIdx.x);
 }
 template <typename T, bool SCALE, int LF = 0, int TPLF = 0>
 __global__ FL_BOUNDS void k_dst_cols(Prob pb, DGeom dg, int chk) {
   dst_cols_body<T, SCALE, LF, TPLF>(pb, dg, chk, blockIdx.x, gridDim.x);
 }
-template <typename T, bool SCALE>
+template <typename T, bool SCALE, int LF = 0>
 __global__ FL_BOUNDS void k_dst_cols_b(const Prob* pbs, const DGeom* dgs, int chk, const int* nb) {
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
-  dst_cols_body<T, SCALE>(pbs[blockIdx.y], dgs[blockIdx.y], chk, blockIdx.x, nb[blockIdx.y]);
+  dst_cols_body<T, SCALE, LF>(pbs[blockIdx.y], dgs[blockIdx.y], chk, blockIdx.x, nb[blockIdx.y]);
 }
 template <typename T> __global__ FL_BOUNDS void k_dot(Prob pb, const void* a, const void* b, int site, long n) {
   dot_body<T>(pb, a, b, site, n, gridDim.x, blockIdx.x);

@@ -2,17 +2,8 @@
 // build of this file: FL_T = float or double).
 #include "fl_internal.hpp"
 
-// Sine kernels are specialised for the direct lengths 2(n+1) of the common
-// grids (n = 64, 128, 384, 512, 1024), each specialisation holding only its
-// own FFT; other lengths and the chirp-z form take the run-time plan (LF = 0).
-static inline int dst_lf(const Axis& A) {
-  if (!A.dst_direct || !A.dst.fixed) return 0;
-  switch (A.dst.L) {
-    case 2050: case 1026: case 770: case 258: case 130: return A.dst.L;
-    default: return 0;
-  }
-}
-
+// Sine kernels are specialised per length (dst_lf): each specialisation holds
+// only its own FFT; other lengths take the run-time plan (LF = 0).
 template <typename T, int DPRO, int DEPI>
 static fl_status launch_dst_rows(int lf, dim3 g, dim3 b, size_t sm, hipStream_t s, const Prob& pb, Iter it, int chk) {
   switch (lf) {
@@ -21,6 +12,9 @@ static fl_status launch_dst_rows(int lf, dim3 g, dim3 b, size_t sm, hipStream_t 
     case 770: LAUNCH((k_dst_rows<T, DPRO, DEPI, 770>), g, b, sm, s, pb, it, chk); break;
     case 258: LAUNCH((k_dst_rows<T, DPRO, DEPI, 258>), g, b, sm, s, pb, it, chk); break;
     case 130: LAUNCH((k_dst_rows<T, DPRO, DEPI, 130>), g, b, sm, s, pb, it, chk); break;
+    case -512: LAUNCH((k_dst_rows<T, DPRO, DEPI, -512>), g, b, sm, s, pb, it, chk); break;
+    case -256: LAUNCH((k_dst_rows<T, DPRO, DEPI, -256>), g, b, sm, s, pb, it, chk); break;
+    case -1024: LAUNCH((k_dst_rows<T, DPRO, DEPI, -1024>), g, b, sm, s, pb, it, chk); break;
     default: LAUNCH((k_dst_rows<T, DPRO, DEPI, 0>), g, b, sm, s, pb, it, chk); break;
   }
   return FL_OK;
@@ -39,6 +33,9 @@ static fl_status launch_dst_cols(int lf, dim3 g, dim3 b, size_t sm, hipStream_t 
     case 770: LAUNCH((k_dst_cols<T, SCALE, 770>), g, b, sm, s, pb, dg, chk); break;
     case 258: LAUNCH((k_dst_cols<T, SCALE, 258>), g, b, sm, s, pb, dg, chk); break;
     case 130: LAUNCH((k_dst_cols<T, SCALE, 130>), g, b, sm, s, pb, dg, chk); break;
+    case -512: LAUNCH((k_dst_cols<T, SCALE, -512>), g, b, sm, s, pb, dg, chk); break;
+    case -256: LAUNCH((k_dst_cols<T, SCALE, -256>), g, b, sm, s, pb, dg, chk); break;
+    case -1024: LAUNCH((k_dst_cols<T, SCALE, -1024>), g, b, sm, s, pb, dg, chk); break;
     default: LAUNCH((k_dst_cols<T, SCALE, 0>), g, b, sm, s, pb, dg, chk); break;
   }
   return FL_OK;
