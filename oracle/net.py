@@ -2,10 +2,10 @@
 oracle of its forward pass, parameter gradient and Adam step.  Test
 infrastructure only.  Not in the paper (a builder's design).
 
-The network N(x, alpha) maps a normalised residual x (one channel, H x W, H and
-W multiples of 8) to a correction y of the same shape.  Layers, with ReLU after
-every convolution but the last, 2x2 average pooling `pool` and nearest 2x
-upsampling `up`:
+The network N(x, alpha) maps a normalised residual x (one channel on a 2D grid
+H x W or a 3D grid D x H x W, every side a multiple of 8) to a correction y of
+the same shape.  Layers, with ReLU after every convolution but the last,
+average pooling over 2 x 2 (x 2) blocks `pool` and nearest 2x upsampling `up`:
 
     x0 = [x, (alpha - 1)]                     2 channels
     a0 = relu(cin(x0))                        32 channels, H x W
@@ -18,10 +18,12 @@ upsampling `up`:
     c0 = relu(u0(a0 + up c1))                 H
     y  = out(c0)                              1 channel
 
-Every convolution is 3 x 3 with zero padding, conv(x)[p, co] = b[co] +
-sum_{ky,kx,ci} x[p + (ky-1, kx-1), ci] W[3 ky + kx, ci, co].  The flat
-parameter vector holds, in this order, W then b of cin (W: 9 x 2 x 32), of d1,
-d2, d3, b3, u2, u1, u0 (9 x 32 x 32 each) and of out (9 x 32, bias 1).
+Every convolution is 3 x 3 (2D) or 3 x 3 x 3 (3D) with zero padding,
+conv(x)[p, co] = b[co] + sum_{k,ci} x[p + k - 1, ci] W[t(k), ci, co], the tap
+index t(k) row-major over the offsets k in {0,1,2}^d (t = 3 ky + kx in 2D,
+9 kz + 3 ky + kx in 3D).  With K = 3^d taps, the flat parameter vector holds,
+in this order, W then b of cin (W: K x 2 x 32), of d1, d2, d3, b3, u2, u1, u0
+(K x 32 x 32 each) and of out (K x 32, bias 1).
 
 The learned preconditioner is z = B (r + s N(r / s, alpha)) with s the RMS of r
 and B the inverse of the sine-basis diagonal of M; N is trained so that
@@ -39,77 +41,104 @@ LAYERS = [("cin", 2, C), ("d1", C, C), ("d2", C, C), ("d3", C, C), ("b3", C, C),
           ("u2", C, C), ("u1", C, C), ("u0", C, C), ("out", C, 1)]
 
 
-def param_shapes():
-    return [(name, (9, ci, co), (co,)) for name, ci, co in LAYERS]
+def taps(d=2):
+    return 3 ** d
 
 
-def nparams():
-    return sum(9 * ci * co + co for _, ci, co in LAYERS)
+def param_shapes(d=2):
+    K = taps(d)
+    return [(name, (K, ci, co), (co,)) for name, ci, co in LAYERS]
 
 
-def unpack(theta):
+def nparams(d=2):
+    return sum(taps(d) * ci * co + co for _, ci, co in LAYERS)
+
+
+def unpack(theta, d=2):
     out, o = {}, 0
-    for name, ws, bs in param_shapes():
+    for name, ws, bs in param_shapes(d):
         nw, nb = int(np.prod(ws)), int(np.prod(bs))
         out[name] = (theta[o:o + nw].reshape(ws), theta[o + nw:o + nw + nb])
         o += nw + nb
     return out
 
 
-def init_params(seed):
+def init_params(seed, d=2):
     """He-uniform weights, zero biases, last layer scaled by 0.1 (seeded numpy draw)."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    K = taps(d)
     parts = []
     for name, ci, co in LAYERS:
-        lim = np.sqrt(6.0 / (9 * ci))
-        w = rng.uniform(-lim, lim, size=(9, ci, co))
+        lim = np.sqrt(6.0 / (K * ci))
+        w = rng.uniform(-lim, lim, size=(K, ci, co))
         if name == "out":
             w *= 0.1
         parts += [w.ravel(), np.zeros(co)]
     return np.concatenate(parts)
 
 
+def _offsets(d):
+    """Tap offsets k in {0,1,2}^d in tap-index order (row-major)."""
+    return list(np.ndindex(*(3,) * d))
+
+
+def _window(xp, k, S):
+    return xp[(slice(None),) + tuple(slice(k[i], k[i] + S[i]) for i in range(len(S))) + (slice(None),)]
+
+
 def conv(x, W, b):
-    """x [B, H, W, ci] -> [B, H, W, co], 3x3, zero padding (cross-correlation)."""
-    Bn, H, Wd, _ = x.shape
-    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
-    y = np.broadcast_to(b, (Bn, H, Wd, W.shape[2])).copy()
-    for ky in range(3):
-        for kx in range(3):
-            y += np.tensordot(xp[:, ky:ky + H, kx:kx + Wd, :], W[3 * ky + kx], axes=([3], [0]))
+    """x [B, *S, ci] -> [B, *S, co], 3^d taps, zero padding (cross-correlation)."""
+    S = x.shape[1:-1]
+    d = len(S)
+    xp = np.pad(x, ((0, 0),) + ((1, 1),) * d + ((0, 0),))
+    y = np.broadcast_to(b, x.shape[:-1] + (W.shape[2],)).copy()
+    for t, k in enumerate(_offsets(d)):
+        y += np.tensordot(_window(xp, k, S), W[t], axes=([d + 1], [0]))
     return y
 
 
 def conv_grads(x, W, g):
     """Given upstream g = dL/dy: (dL/dx, dL/dW, dL/db) of y = conv(x, W, b)."""
-    Bn, H, Wd, _ = x.shape
-    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
+    S = x.shape[1:-1]
+    d = len(S)
+    xp = np.pad(x, ((0, 0),) + ((1, 1),) * d + ((0, 0),))
     dxp = np.zeros_like(xp)
     dW = np.zeros_like(W)
-    for ky in range(3):
-        for kx in range(3):
-            xs = xp[:, ky:ky + H, kx:kx + Wd, :]
-            dW[3 * ky + kx] = np.tensordot(xs, g, axes=([0, 1, 2], [0, 1, 2]))
-            dxp[:, ky:ky + H, kx:kx + Wd, :] += np.tensordot(g, W[3 * ky + kx], axes=([3], [1]))
-    return dxp[:, 1:-1, 1:-1, :], dW, g.sum(axis=(0, 1, 2))
+    ax = list(range(d + 1))
+    for t, k in enumerate(_offsets(d)):
+        dW[t] = np.tensordot(_window(xp, k, S), g, axes=(ax, ax))
+        _window(dxp, k, S)[...] += np.tensordot(g, W[t], axes=([d + 1], [1]))
+    inner = (slice(None),) + (slice(1, -1),) * d + (slice(None),)
+    return dxp[inner], dW, g.sum(axis=tuple(ax))
+
+
+def _blocks(x):
+    """[B, *S, c] -> [B, S_0/2, 2, S_1/2, 2, ..., c] and the axes of the 2s."""
+    S = x.shape[1:-1]
+    shp = [x.shape[0]]
+    for v in S:
+        shp += [v // 2, 2]
+    return x.reshape(shp + [x.shape[-1]]), tuple(2 + 2 * i for i in range(len(S)))
 
 
 def pool(x):
-    Bn, H, Wd, c = x.shape
-    return x.reshape(Bn, H // 2, 2, Wd // 2, 2, c).mean(axis=(2, 4))
-
-
-def pool_adjoint(g):
-    return np.repeat(np.repeat(g, 2, axis=1), 2, axis=2) / 4.0
+    xb, ax = _blocks(x)
+    return xb.mean(axis=ax)
 
 
 def up(x):
-    return np.repeat(np.repeat(x, 2, axis=1), 2, axis=2)
+    for i in range(x.ndim - 2):
+        x = np.repeat(x, 2, axis=1 + i)
+    return x
+
+
+def pool_adjoint(g):
+    return up(g) / 2.0 ** (g.ndim - 2)
 
 
 def up_adjoint(g):
-    Bn, H, Wd, c = g.shape
-    return g.reshape(Bn, H // 2, 2, Wd // 2, 2, c).sum(axis=(2, 4))
+    gb, ax = _blocks(g)
+    return gb.sum(axis=ax)
 
 
 def relu(x):
@@ -117,11 +146,12 @@ def relu(x):
 
 
 def forward(theta, x, alpha, keep=False):
-    """x [B, H, W], alpha [B] -> y [B, H, W] (and the activations if keep)."""
-    P = unpack(np.asarray(theta, dtype=np.float64))
+    """x [B, *S], alpha [B] -> y [B, *S] (and the activations if keep); d = len(S)."""
     x = np.asarray(x, dtype=np.float64)
-    al = np.asarray(alpha, dtype=np.float64).reshape(-1, 1, 1, 1)
-    x0 = np.concatenate([x[..., None], np.broadcast_to(al - 1.0, x[..., None].shape)], axis=3)
+    d = x.ndim - 1
+    P = unpack(np.asarray(theta, dtype=np.float64), d)
+    al = np.asarray(alpha, dtype=np.float64).reshape((-1,) + (1,) * (d + 1))
+    x0 = np.concatenate([x[..., None], np.broadcast_to(al - 1.0, x[..., None].shape)], axis=d + 1)
     act = {"x0": x0}
     act["a0"] = relu(conv(x0, *P["cin"]))
     act["p1"] = pool(act["a0"])
@@ -143,7 +173,7 @@ def forward(theta, x, alpha, keep=False):
 
 def grad(theta, x, alpha, gy):
     """Parameter gradient of sum(gy * N(x, alpha)) (reverse pass, layer by layer)."""
-    P = unpack(np.asarray(theta, dtype=np.float64))
+    P = unpack(np.asarray(theta, dtype=np.float64), np.ndim(x) - 1)
     _, A = forward(theta, x, alpha, keep=True)
     G = {}
     g = np.asarray(gy, dtype=np.float64)[..., None]
@@ -166,16 +196,14 @@ def grad(theta, x, alpha, gy):
 
 
 def loss(theta, x, alpha, t):
-    """Training loss: mean over the batch of ||N(x) - t||^2 / (H W)."""
+    """Training loss: mean over the batch of ||N(x) - t||^2 / (number of grid points)."""
     y = forward(theta, x, alpha)
-    Bn = y.shape[0]
-    return float(((y - t) ** 2).sum() / (Bn * y.shape[1] * y.shape[2]))
+    return float(((y - t) ** 2).sum() / y.size)
 
 
 def loss_grad(theta, x, alpha, t):
     y = forward(theta, x, alpha)
-    Bn, H, Wd = y.shape
-    return grad(theta, x, alpha, 2.0 * (y - t) / (Bn * H * Wd))
+    return grad(theta, x, alpha, 2.0 * (y - t) / y.size)
 
 
 def adam_step(theta, g, m, v, k, lr, b1=0.9, b2=0.999, eps=1e-8):
