@@ -54,6 +54,10 @@ def main():
     ap.add_argument("--train-problems", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--train-batch", type=int, default=16)
+    ap.add_argument("--no-learned-3d", action="store_true", help="skip the 3D learned-preconditioner workload")
+    ap.add_argument("--train3d-problems", type=int, default=40)
+    ap.add_argument("--train3d-n", type=int, default=32)
+    ap.add_argument("--train3d-steps", type=int, default=600)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -181,6 +185,9 @@ def main():
     batched = None
     if not args.no_batched:
         batched = batched_workloads(fl, torch, args)
+    learned3d = None
+    if not args.no_learned_3d:
+        learned3d = learned_3d_workload(fl, torch, args)
 
     cpu = None
     if not args.no_cpu:
@@ -211,6 +218,7 @@ def main():
         "passes_GBps": {k: round(v["GBps"], 1) for k, v in prof.items() if v["GBps"]},
         "roofline": roof,
         "batched": batched,
+        "learned_3d": learned3d,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -291,6 +299,66 @@ def batched_workloads(fl, torch, args):
         log(f"[bench] c3 {name}: 16 x 256^3 in {ms:.1f} ms, mean iters {c3[name]['iters_mean']}, "
             f"max true res {c3[name]['max_rel_res_true']:.1e}")
     out["c3"] = c3
+    op.close()
+    return out
+
+
+def learned_3d_workload(fl, torch, args):
+    """The learned preconditioner in 3D (3 x 3 x 3 kernels): trained on
+    solver-generated pairs at `train3d_n`^3 (alpha ~ U[0.2, 1.9]; 5 iterate
+    errors + 5 random-field errors per problem), evaluated in flexible CG at
+    128^3, alpha = 1.5, 16-bump right-hand side, tol 1e-8, against FD PCG and
+    the spectral preconditioner alone (FP64 and FP32 + FP64 refinement).
+    Each solve is timed over 2 runs after 1 warm-up."""
+    import numpy as np
+
+    from paper_1802_03770_amd import learned as L
+    from workloads import bump_field, learned_training_plan
+    s = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    plan = learned_training_plan(nalpha=args.train3d_problems, n=args.train3d_n, seed=5600, d=3)
+    R, T, A = L.make_pairs(plan, iters=5, fields=5, stream=s)
+    t_pairs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, losses = L.train(R, T, A, steps=args.train3d_steps, batch=4, lr=2e-3, seed=2, stream=s)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    l0, l1 = float(np.mean(losses[:20])), float(np.mean(losses[-20:]))
+    log(f"[bench] learned 3d: {R.shape[0]} pairs at {args.train3d_n}^3 in {t_pairs:.1f} s, {len(losses)} Adam steps "
+        f"(batch 4) in {t_train:.1f} s, loss {l0:.3e} -> {l1:.3e}")
+    out = {"workload": "3D 128^3 alpha=1.5 (-1,1)^3, 16 bumps seed 5500, tol 1e-8",
+           "training": {"pairs": int(R.shape[0]), "grid": args.train3d_n, "pairs_s": round(t_pairs, 2),
+                        "steps": len(losses), "batch": 4, "train_s": round(t_train, 2), "loss_first": l0,
+                        "loss_last": l1}}
+    del R, T, A
+    n, alpha = 128, 1.5
+    f_np, h = bump_field(n, 3, 16, 5500, width=(0.05, 0.2))
+    f = torch.from_numpy(f_np).cuda()
+    op = fl.Op(3, alpha, h, (n,) * 3, stream=s)
+    configs = {
+        "fp64_pcg": fl.solve_opts(pc=fl.FL_PC_FD, mixed=0),
+        "f32_pcg": fl.solve_opts(pc=fl.FL_PC_FD, mixed=1),
+        "fp64_spectral": fl.solve_opts(pc=fl.FL_PC_SPECTRAL, mixed=0),
+        "f32_spectral": fl.solve_opts(pc=fl.FL_PC_SPECTRAL, mixed=1),
+        "learned_f32": fl.solve_opts(pc=fl.FL_PC_LEARNED, mixed=1, net=net),
+        "learned_fp64": fl.solve_opts(pc=fl.FL_PC_LEARNED, mixed=0, net=net),
+    }
+    res = {}
+    for name, opts in configs.items():
+        op.solve(f, tol=1e-8, opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [op.solve(f, tol=1e-8, opts=opts)[1] for _ in range(2)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / 2
+        worst = max(i["rel_res_true"] for i in infos)
+        res[name] = {"ms": round(ms, 3), "iters": infos[-1]["iters"], "outer": infos[-1]["outer_iters"],
+                     "rel_res_true": float(f"{worst:.3g}"), "ok": bool(worst <= 1e-8),
+                     "fell_back": infos[-1]["fell_back"]}
+        log(f"[bench] learned 3d {name}: {ms:.2f} ms/solve iters={infos[-1]['iters']} "
+            f"outer={infos[-1]['outer_iters']} true_res={worst:.2e}")
+    out["solvers"] = res
+    out["net_forward_ms"] = round(net.profile(0, n, n, reps=5, D=n), 3)
     op.close()
     return out
 

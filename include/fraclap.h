@@ -59,8 +59,8 @@ typedef enum {
   FL_PC_NONE = 0,     /* plain CG */
   FL_PC_FD = 1,       /* finite-difference Laplacian preconditioner (Sec. 3.1) */
   FL_PC_LEARNED = 2,  /* not in the paper: flexible CG with z = B (r + s N(r/s, alpha)), N the network
-                         opts->net, B the FL_PC_SPECTRAL inverse, s = RMS(r); the FD preconditioner is the
-                         fallback (d = 2, no mask) */
+                         opts->net (of the op's dimension), B the FL_PC_SPECTRAL inverse, s = RMS(r); the FD
+                         preconditioner is the fallback (d = 2 or 3, no mask) */
   FL_PC_SPECTRAL = 3  /* not in the paper: the sine basis of the FD preconditioner with the
                          operator's own diagonal in that basis as eigenvalues, i.e. the best
                          approximation of M diagonalised by the type-I sine transform */
@@ -200,48 +200,55 @@ fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const d
                           int nsteps, double tol, const fl_solve_opts* opts, fl_info* infos);
 
 /* ---- learned preconditioner (not in the paper) ----
- * A multilevel convolutional network N(x, alpha) on an H x W grid (H, W
- * multiples of 8): 3x3 convolutions with 32 channels on 4 levels (2x2 average
- * pooling, nearest upsampling, additive skips, ReLU), BF16 activations with
+ * A multilevel convolutional network N(x, alpha) on a 2D grid H x W (d = 2)
+ * or a 3D grid D x H x W (d = 3), every side a multiple of 8: 3 x 3 (x 3)
+ * convolutions with 32 channels on 4 levels (average pooling over 2 x 2 (x 2)
+ * blocks, nearest upsampling, additive skips, ReLU), BF16 activations with
  * FP32 accumulation, FP32 master parameters.  Parameter vector (FP32,
- * fl_net_nparams() entries): per layer W[tap = 3 ky + kx][ci][co] then b[co],
+ * fl_net_nparams(d) entries): per layer W[tap][ci][co] then b[co], with
+ * K = 3^d taps, tap = 9 kz + 3 ky + kx (kz absent in 2D) over the offsets,
  * layers cin (2 -> 32; input channels x and alpha - 1), d1, d2, d3, b3, u2,
  * u1, u0 (32 -> 32), out (32 -> 1).  Inside flexible CG (FL_PC_LEARNED) the
  * preconditioner is z = B (r + s N(r/s, alpha)), B the FL_PC_SPECTRAL inverse
- * and s the RMS of r.  All arrays are device arrays on the net's stream. */
+ * and s the RMS of r; the op's grid is zero-padded to multiples of 8 for the
+ * network.  All arrays are device arrays on the net's stream; grids are
+ * [batch][D][H][W] with D = 1 for a 2D network. */
 
-/* New network with zero parameters (call fl_net_set_params before use). */
-fl_status fl_net_create(void* hip_stream, fl_net* out);
-/* Number of FP32 parameters. */
-int64_t fl_net_nparams(void);
+/* New network for d = 2 or 3 with zero parameters (call fl_net_set_params
+ * before use). */
+fl_status fl_net_create(int d, void* hip_stream, fl_net* out);
+/* Number of FP32 parameters of a network for d (65633 for d = 2, 196385 for
+ * d = 3; 0 otherwise). */
+int64_t fl_net_nparams(int d);
 /* Copy in / out the FP32 parameter vector; set also clears the Adam moments. */
 fl_status fl_net_set_params(fl_net net, const float* params);
 fl_status fl_net_get_params(fl_net net, float* params);
-/* y = N(x, alpha[b]) for batch images x[b] (FP32 [batch][H][W]); alpha is a
+/* y = N(x, alpha[b]) for batch grids x[b] (FP32 [batch][D][H][W]); alpha is a
  * host array of batch values. */
-fl_status fl_net_forward(fl_net net, const float* x, const double* alpha, float* y, int batch, int H, int W);
-/* grad = d/dtheta sum(gy * N(x, alpha)) (FP32, fl_net_nparams() entries). */
+fl_status fl_net_forward(fl_net net, const float* x, const double* alpha, float* y, int batch, int D, int H, int W);
+/* grad = d/dtheta sum(gy * N(x, alpha)) (FP32, fl_net_nparams(d) entries). */
 fl_status fl_net_grad(fl_net net, const float* x, const double* alpha, const float* gy, float* grad, int batch,
-                      int H, int W);
+                      int D, int H, int W);
 /* `steps` Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the loss
- * mean over the minibatch of ||N(R_i, A_i) - T_i||^2 / (H W); minibatch k
+ * mean over the minibatch of ||N(R_i, A_i) - T_i||^2 / (D H W); minibatch k
  * takes pairs idx[k*batch .. k*batch+batch-1] (host array, each < npairs).
- * R, T: FP32 [npairs][H][W]; A: FP32 [npairs] (device).  losses (host,
+ * R, T: FP32 [npairs][D][H][W]; A: FP32 [npairs] (device).  losses (host,
  * `steps` entries) receives the loss of each minibatch before its update. */
-fl_status fl_net_train(fl_net net, const float* R, const float* T, const float* A, int npairs, int H, int W,
+fl_status fl_net_train(fl_net net, const float* R, const float* T, const float* A, int npairs, int D, int H, int W,
                        const int* idx, int steps, int batch, double lr, float* losses);
 /* Training pairs from errors e_k = e[k * e_stride] - e_sub[k] (FP64 grids of
- * the op, d = 2; e_stride 0 repeats one array, e_sub may be NULL): r = M e,
- * s = RMS(r), R = r / s and T = (D e - r) / s with D = Q diag(tau) Q^T (the
- * operator diagonal in the sine basis), written zero-padded into the
- * Hp x Wp grid (R, T: FP32 [count][Hp][Wp], Hp >= n_0, Wp >= n_1). */
+ * the op, d = 2 or 3; e_stride 0 repeats one array, e_sub may be NULL):
+ * r = M e, s = RMS(r), R = r / s and T = (D e - r) / s with D = Q diag(tau) Q^T
+ * (the operator diagonal in the sine basis), written zero-padded into the
+ * Dp x Hp x Wp grid (R, T: FP32 [count][Dp][Hp][Wp]; d = 2: Dp = 1,
+ * Hp >= n_0, Wp >= n_1; d = 3: Dp >= n_0, Hp >= n_1, Wp >= n_2). */
 fl_status fl_learned_pairs(fl_op op, const double* e, int64_t e_stride, const double* e_sub, int count, float* R,
-                           float* T, int Hp, int Wp);
+                           float* T, int Dp, int Hp, int Wp);
 /* Measurement aid: average duration (ms, HIP events on the net's stream) of
- * `reps` launches on a 1 x H x W input: which = 0 the whole forward pass,
+ * `reps` launches on a 1 x D x H x W input: which = 0 the whole forward pass,
  * 1 the level-0 32 -> 32 convolution (MFMA, skip-add staging), 2 the input
  * layer, 3 the output layer. */
-fl_status fl_net_profile(fl_net net, int which, int H, int W, int reps, double* avg_ms);
+fl_status fl_net_profile(fl_net net, int which, int D, int H, int W, int reps, double* avg_ms);
 fl_status fl_net_destroy(fl_net net);
 
 /* Measurement aid: average duration (ms, HIP events on the op's stream) of

@@ -80,15 +80,15 @@ def load(path=LIB_PATH):
         "fl_profile_pass": [P, I, I, I, ctypes.POINTER(D)],
         "fl_op_destroy": [P],
         "fl_last_error": [],
-        "fl_net_create": [P, ctypes.POINTER(P)],
-        "fl_net_nparams": [],
+        "fl_net_create": [I, P, ctypes.POINTER(P)],
+        "fl_net_nparams": [I],
         "fl_net_set_params": [P, P],
         "fl_net_get_params": [P, P],
-        "fl_net_forward": [P, P, ctypes.POINTER(D), P, I, I, I],
-        "fl_net_grad": [P, P, ctypes.POINTER(D), P, P, I, I, I],
-        "fl_net_train": [P, P, P, P, I, I, I, ctypes.POINTER(I), I, I, D, ctypes.POINTER(ctypes.c_float)],
-        "fl_learned_pairs": [P, P, I64, P, I, P, P, I, I],
-        "fl_net_profile": [P, I, I, I, I, ctypes.POINTER(D)],
+        "fl_net_forward": [P, P, ctypes.POINTER(D), P, I, I, I, I],
+        "fl_net_grad": [P, P, ctypes.POINTER(D), P, P, I, I, I, I],
+        "fl_net_train": [P, P, P, P, I, I, I, I, ctypes.POINTER(I), I, I, D, ctypes.POINTER(ctypes.c_float)],
+        "fl_learned_pairs": [P, P, I64, P, I, P, P, I, I, I],
+        "fl_net_profile": [P, I, I, I, I, I, ctypes.POINTER(D)],
         "fl_net_destroy": [P],
     }
     for name, args in sig.items():
@@ -328,17 +328,19 @@ def step_batched(ops, us, dts, theta=1.0, nsteps=1, tol=1e-10, opts=None, check=
 
 
 class Net:
-    """fl_net handle: the learned preconditioner's network (parameters on the device)."""
+    """fl_net handle: the learned preconditioner's network for d = 2 (3 x 3
+    kernels) or d = 3 (3 x 3 x 3), parameters on the device."""
 
-    def __init__(self, stream=None, params=None):
+    def __init__(self, stream=None, params=None, d=2):
         lib = load()
         if stream is None:
             stream = torch.cuda.Stream()
         self.stream = stream
+        self.d = int(d)
         h_ = ctypes.c_void_p()
-        _check(lib.fl_net_create(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h_)))
+        _check(lib.fl_net_create(self.d, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h_)))
         self._h = h_
-        self.nparams = int(lib.fl_net_nparams())
+        self.nparams = int(lib.fl_net_nparams(self.d))
         if params is not None:
             self.set_params(params)
 
@@ -359,6 +361,15 @@ class Net:
     def _leave(self):
         torch.cuda.current_stream().wait_stream(self.stream)
 
+    def _grid(self, x):
+        """(batch, D, H, W) of x [B, H, W] (2D) or [B, D, H, W] (3D); an unbatched grid gains B = 1."""
+        if x.dim() == self.d:
+            x = x[None]
+        if x.dim() != self.d + 1:
+            raise ValueError(f"a {self.d}D network takes [B, {'D, ' if self.d == 3 else ''}H, W] grids")
+        dims = tuple(x.shape)
+        return x, (dims if self.d == 3 else (dims[0], 1) + dims[1:])
+
     def set_params(self, params):
         p = torch.as_tensor(params, dtype=torch.float32).to("cuda").contiguous()
         _need(p, torch.float32, self.nparams, "params")
@@ -372,15 +383,13 @@ class Net:
         return p
 
     def forward(self, x, alpha):
-        """y = N(x, alpha) for x FP32 [B, H, W] (device); alpha: float or list of B floats."""
+        """y = N(x, alpha) for x FP32 [B, (D,) H, W] (device); alpha: float or list of B floats."""
         _need(x, torch.float32, name="x")
-        if x.dim() == 2:
-            x = x[None]
-        B, H, W = x.shape
+        x, (B, D, H, W) = self._grid(x)
         al = [float(alpha)] * B if not hasattr(alpha, "__len__") else [float(a) for a in alpha]
         y = torch.empty_like(x)
         self._enter()
-        _check(load().fl_net_forward(self._h, _ptr(x), (ctypes.c_double * B)(*al), _ptr(y), B, H, W))
+        _check(load().fl_net_forward(self._h, _ptr(x), (ctypes.c_double * B)(*al), _ptr(y), B, D, H, W))
         self._leave()
         return y
 
@@ -388,18 +397,18 @@ class Net:
         """d/dtheta sum(gy * N(x, alpha)) as an FP32 device vector."""
         _need(x, torch.float32, name="x")
         _need(gy, torch.float32, x.numel(), "gy")
-        B, H, W = x.shape
+        x, (B, D, H, W) = self._grid(x)
         al = [float(alpha)] * B if not hasattr(alpha, "__len__") else [float(a) for a in alpha]
         g = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
         self._enter()
-        _check(load().fl_net_grad(self._h, _ptr(x), (ctypes.c_double * B)(*al), _ptr(gy), _ptr(g), B, H, W))
+        _check(load().fl_net_grad(self._h, _ptr(x), (ctypes.c_double * B)(*al), _ptr(gy), _ptr(g), B, D, H, W))
         self._leave()
         return g
 
-    def profile(self, which, H, W, reps=20):
+    def profile(self, which, H, W, reps=20, D=1):
         """Average ms per launch (HIP events on the net stream): 0 forward, 1 level-0 conv, 2 input, 3 output layer."""
         ms = ctypes.c_double()
-        _check(load().fl_net_profile(self._h, which, H, W, reps, ctypes.byref(ms)))
+        _check(load().fl_net_profile(self._h, which, D, H, W, reps, ctypes.byref(ms)))
         return ms.value
 
     def train(self, R, T, A, idx, batch, lr=1e-3):
@@ -411,16 +420,22 @@ class Net:
         idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).reshape(-1, batch))
         steps = idx.shape[0]
         losses = (ctypes.c_float * max(steps, 1))()
-        npairs, H, W = R.shape
+        _, (npairs, D, H, W) = self._grid(R)
         self._enter()
-        _check(load().fl_net_train(self._h, _ptr(R), _ptr(T), _ptr(A), npairs, H, W,
+        _check(load().fl_net_train(self._h, _ptr(R), _ptr(T), _ptr(A), npairs, D, H, W,
                                    idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), steps, batch, lr, losses))
         return [losses[i] for i in range(steps)]
 
 
-def learned_pairs(op, e, e_sub=None, Hp=None, Wp=None):
+def padded_grid(op):
+    """The op's grid rounded up to multiples of 8 per side (the network grid)."""
+    return tuple((v + 7) // 8 * 8 for v in op.n)
+
+
+def learned_pairs(op, e, e_sub=None, padded=None):
     """Training pairs (R, T) of the learned preconditioner from FP64 errors
-    e - e_sub: e is one grid (repeated) or [count, n0, n1]; e_sub None or [count, n0, n1]."""
+    e - e_sub: e is one grid (repeated) or [count, *n]; e_sub None or [count, *n].
+    R, T: FP32 [count, *padded] (default: padded_grid(op))."""
     _need(e, torch.float64, name="e")
     if e.numel() == op.N and e_sub is not None:
         stride, count = 0, e_sub.numel() // op.N
@@ -430,11 +445,13 @@ def learned_pairs(op, e, e_sub=None, Hp=None, Wp=None):
         raise ValueError("e must hold grids of the op")
     if e_sub is not None:
         _need(e_sub, torch.float64, count * op.N, "e_sub")
-    Hp = Hp or (op.n[0] + 7) // 8 * 8
-    Wp = Wp or (op.n[1] + 7) // 8 * 8
-    R = torch.empty((count, Hp, Wp), dtype=torch.float32, device="cuda")
+    pad = tuple(padded) if padded is not None else padded_grid(op)
+    if len(pad) != op.d:
+        raise ValueError("padded grid must have one side per axis")
+    R = torch.empty((count,) + pad, dtype=torch.float32, device="cuda")
     T = torch.empty_like(R)
+    Dp, Hp, Wp = pad if op.d == 3 else (1,) + pad
     op._enter()
-    _check(load().fl_learned_pairs(op._h, _ptr(e), stride, _ptr(e_sub), count, _ptr(R), _ptr(T), Hp, Wp))
+    _check(load().fl_learned_pairs(op._h, _ptr(e), stride, _ptr(e_sub), count, _ptr(R), _ptr(T), Dp, Hp, Wp))
     op._leave()
     return R, T

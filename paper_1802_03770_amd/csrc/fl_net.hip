@@ -4,18 +4,24 @@
 // operator's sine-basis diagonal, s the RMS of r, and the FD Laplacian
 // preconditioner (Sec. 3.1) as the fallback.  Not in the paper.
 //
-// Network (H, W multiples of 8; ReLU after every convolution but the last;
-// 2x2 average pooling, nearest 2x upsampling, additive skips):
+// Network on a 2D grid H x W or a 3D grid D x H x W (every side a multiple of
+// 8; ReLU after every convolution but the last; average pooling over 2 x 2
+// (x 2) blocks, nearest 2x upsampling, additive skips):
 //   a0 = relu(cin([x, alpha-1]))   a1 = relu(d1(pool a0))   a2 = relu(d2(pool a1))
 //   a3 = relu(d3(pool a2))         c3 = relu(b3(a3))        c2 = relu(u2(a2 + up c3))
 //   c1 = relu(u1(a1 + up c2))      c0 = relu(u0(a0 + up c1)) y = out(c0)
-// 3x3 zero-padded cross-correlations; parameters W[tap = 3 ky + kx][ci][co]
-// then b[co] per layer in the order cin, d1, d2, d3, b3, u2, u1, u0, out.
+// Zero-padded cross-correlations with K = 9 KD taps (KD = 1: 3 x 3, KD = 3:
+// 3 x 3 x 3), tap = 9 kz + 3 ky + kx row-major over the offsets; parameters
+// W[tap][ci][co] then b[co] per layer in the order cin, d1, d2, d3, b3, u2,
+// u1, u0, out.
 //
-// Layout: activations NHWC bf16 [B][H][W][32]; input and output FP32 [B][H][W].
-// The 32 -> 32 convolutions are implicit GEMMs on v_mfma_f32_32x32x16_bf16:
-// D[co][pixel] = sum_k W^T[co][k] X[k][pixel], k = (tap, ci), a 64-wide wave
-// computing 2 x 32 pixels of one output row against all 32 output channels.
+// Layout: activations channel-last bf16 [B][D][H][W][32] (D = 1 in 2D); input
+// and output FP32 [B][D][H][W].  The 32 -> 32 convolutions are implicit GEMMs
+// on v_mfma_f32_32x32x16_bf16: D[co][pixel] = sum_k W^T[co][k] X[k][pixel],
+// k = (tap, ci), a 64-wide wave computing 2 x 32 pixels of one output row
+// against all 32 output channels; in 3D a block accumulates the three input
+// slices z-1, z, z+1 of its output slice one after another (one staged slice
+// and the nine in-plane taps of that slice at a time).
 #include <type_traits>
 
 #include "fl_internal.hpp"
@@ -27,17 +33,26 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16;
 
 constexpr int CH = 32;
-constexpr int NL32 = 7;                      // 32 -> 32 layers d1 d2 d3 b3 u2 u1 u0
-constexpr long L32W = 9 * CH * CH;           // weights per 32 -> 32 layer
-constexpr long OFF_CIN_B = 9 * 2 * CH;       // 576
-constexpr long OFF_L32 = OFF_CIN_B + CH;     // 608
-constexpr long L32SZ = L32W + CH;            // 9248
-constexpr long OFF_OUT = OFF_L32 + NL32 * L32SZ;  // 65344
-constexpr long NPARAM = OFF_OUT + 9 * CH + 1;     // 65633
-constexpr long PACK = 18 * 64 * 8;           // packed bf16 per layer (18 fragments x 64 lanes x 8)
+constexpr int NL32 = 7;  // 32 -> 32 layers d1 d2 d3 b3 u2 u1 u0
 enum { LD1 = 0, LD2, LD3, LB3, LU2, LU1, LU0 };
 
-// Tile of one conv block: 4 output rows x 64 output columns.
+// Parameter layout of a network with K = 9 KD taps per kernel.
+template <int KD> struct PL {
+  static constexpr int K = 9 * KD;
+  static constexpr long L32W = (long)K * CH * CH;        // weights per 32 -> 32 layer
+  static constexpr long OFF_CIN_B = (long)K * 2 * CH;    // bias of the input layer
+  static constexpr long OFF_L32 = OFF_CIN_B + CH;        // first 32 -> 32 layer
+  static constexpr long L32SZ = L32W + CH;               // weights + bias per 32 -> 32 layer
+  static constexpr long OFF_OUT = OFF_L32 + NL32 * L32SZ;  // output layer
+  static constexpr long NPARAM = OFF_OUT + (long)K * CH + 1;
+  static constexpr long PACK = 2L * K * 64 * 8;  // packed bf16 per layer (2K fragments x 64 lanes x 8)
+  static constexpr long CIN_PV = (long)K * 2 * CH + CH;  // input-layer gradient values
+  static constexpr long OUT_PV = (long)K * CH + 1;       // output-layer gradient values
+};
+// 2D sizes: 65633 parameters (3 x 3 kernels); 3D: 196385 (3 x 3 x 3)
+static_assert(PL<1>::NPARAM == 65633 && PL<3>::NPARAM == 196385, "parameter layout");
+
+// Tile of one conv block: 4 output rows x 64 output columns of one slice.
 constexpr int TY = 4, TX = 64, SY = TY + 2, SX = TX + 2;
 
 __device__ __forceinline__ float bf2f(u16 v) { return __uint_as_float((unsigned)v << 16); }
@@ -68,78 +83,96 @@ __device__ __forceinline__ uint4 pk8(const float v[8]) {
 // Staging of a convolution input (8 channels of one in-bounds pixel)
 // ---------------------------------------------------------------------------
 enum { SM_PLAIN = 0, SM_POOL, SM_UPADD, SM_GPLAIN, SM_GSUMPOOL, SM_GADDUP, SM_INPUT };
-//  PLAIN    s0[p]                          (this level)
-//  POOL     mean of s0 over the 2x2 block  (s0 at the finer level)
-//  UPADD    s0[p] + s1[p/2]                (s1 at the coarser level)
-//  GPLAIN   s0[p] * (y[p] > 0)             (gradient through a ReLU)
-//  GSUMPOOL sum of s0 over the 2x2 block * (y[p] > 0)
-//  GADDUP   (s0[p] + s1[p/2] / 4) * (y[p] > 0)
+//  PLAIN    s0[p]                                  (this level)
+//  POOL     mean of s0 over the 2 x 2 (x 2) block  (s0 at the finer level)
+//  UPADD    s0[p] + s1[p/2]                        (s1 at the coarser level)
+//  GPLAIN   s0[p] * (y[p] > 0)                     (gradient through a ReLU)
+//  GSUMPOOL sum of s0 over the block * (y[p] > 0)
+//  GADDUP   (s0[p] + s1[p/2] / 2^d) * (y[p] > 0)
 //  INPUT    channels (x[p], alpha_b - 1, 0, ..., 0): the input layer as a
 //           32 -> 32 convolution whose weights vanish beyond input channel 1
 struct Stage {
   const u16* s0;
   const u16* s1;
   const u16* y;
-  const float* xf = nullptr;  // SM_INPUT: network input x, FP32 [B][H][W]
+  const float* xf = nullptr;  // SM_INPUT: network input x, FP32 [B][D][H][W]
   const float* al = nullptr;  // SM_INPUT: alpha per image
 };
 
-__device__ __forceinline__ long pix(int b, int y, int x, int H, int W) { return (((long)b * H + y) * W + x) * CH; }
+// Grid of one level: D = 1 for 2D networks.
+struct Dims {
+  int B, D, H, W;
+};
+__device__ __forceinline__ long pix(const Dims& g, int b, int z, int y, int x) {
+  return ((((long)b * g.D + z) * g.H + y) * g.W + x) * CH;
+}
+// the finer (pooling source) and coarser (upsampling source) level
+template <int KD> __device__ __forceinline__ Dims finer(const Dims& g) {
+  return Dims{g.B, KD == 3 ? 2 * g.D : 1, 2 * g.H, 2 * g.W};
+}
+template <int KD> __device__ __forceinline__ Dims coarser(const Dims& g) {
+  return Dims{g.B, KD == 3 ? g.D / 2 : 1, g.H / 2, g.W / 2};
+}
 
-template <int SM>
-__device__ __forceinline__ void stage8(const Stage& st, int b, int y, int x, int H, int W, int c, float v[8]) {
+template <int SM, int KD>
+__device__ __forceinline__ void stage8(const Stage& st, const Dims& g, int b, int z, int y, int x, int c, float v[8]) {
+  constexpr int NB = KD == 3 ? 8 : 4;  // pixels per pooling block
   if constexpr (SM == SM_INPUT) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = 0.f;
     if (c == 0) {
-      v[0] = st.xf[((long)b * H + y) * W + x];
+      v[0] = st.xf[(((long)b * g.D + z) * g.H + y) * g.W + x];
       v[1] = st.al[b] - 1.f;
     }
     return;
   }
   if (SM == SM_PLAIN) {
-    ld8(st.s0 + pix(b, y, x, H, W) + c, v);
+    ld8(st.s0 + pix(g, b, z, y, x) + c, v);
   } else if (SM == SM_POOL || SM == SM_GSUMPOOL) {
+    const Dims f = finer<KD>(g);
     float t[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = 0.f;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ld8(st.s0 + pix(b, 2 * y + (q >> 1), 2 * x + (q & 1), 2 * H, 2 * W) + c, t);
+    for (int q = 0; q < NB; ++q) {
+      const int zf = KD == 3 ? 2 * z + (q >> 2) : 0;
+      ld8(st.s0 + pix(f, b, zf, 2 * y + ((q >> 1) & 1), 2 * x + (q & 1)) + c, t);
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] += t[i];
     }
     if (SM == SM_POOL)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] *= 0.25f;
+      for (int i = 0; i < 8; ++i) v[i] *= 1.f / NB;
   } else {
-    ld8(st.s0 + pix(b, y, x, H, W) + c, v);
+    ld8(st.s0 + pix(g, b, z, y, x) + c, v);
     if (SM == SM_UPADD || SM == SM_GADDUP) {
       float t[8];
-      ld8(st.s1 + pix(b, y >> 1, x >> 1, H >> 1, W >> 1) + c, t);
-      const float f = SM == SM_UPADD ? 1.f : 0.25f;
+      ld8(st.s1 + pix(coarser<KD>(g), b, KD == 3 ? z >> 1 : 0, y >> 1, x >> 1) + c, t);
+      const float f = SM == SM_UPADD ? 1.f : 1.f / NB;
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] += f * t[i];
     }
   }
   if (SM >= SM_GPLAIN && SM <= SM_GADDUP) {
     float a[8];
-    ld8(st.y + pix(b, y, x, H, W) + c, a);
+    ld8(st.y + pix(g, b, z, y, x) + c, a);
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = a[i] > 0.f ? v[i] : 0.f;
   }
 }
 
-// Stage rows y0-1 .. y0+TY and columns x0-1 .. x0+TX of image b into LDS
-// ([SY][SX][32] bf16), zero outside the image.
-template <int SM>
-__device__ __forceinline__ void stage_tile(u16* tile, const Stage& st, int b, int y0, int x0, int H, int W) {
+// Stage rows y0-1 .. y0+TY and columns x0-1 .. x0+TX of slice z of image b
+// into LDS ([SY][SX][32] bf16), zero outside the grid (a slice z outside
+// 0..D-1 stages zeros).
+template <int SM, int KD>
+__device__ __forceinline__ void stage_tile(u16* tile, const Stage& st, const Dims& g, int b, int z, int y0, int x0) {
+  const bool zin = z >= 0 && z < g.D;
   for (int e = threadIdx.x; e < SY * SX * 4; e += blockDim.x) {
     const int c = (e & 3) * 8, p = e >> 2;
     const int yy = y0 + p / SX - 1, xx = x0 + p % SX - 1;
     float v[8];
-    if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-      stage8<SM>(st, b, yy, xx, H, W, c, v);
+    if (zin && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W) {
+      stage8<SM, KD>(st, g, b, z, yy, xx, c, v);
     } else {
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] = 0.f;
@@ -150,35 +183,36 @@ __device__ __forceinline__ void stage_tile(u16* tile, const Stage& st, int b, in
 
 // Forward-mode staging with all global loads of a lane issued before any LDS
 // store (the tile has SY*SX*4 = 1584 16-byte chunks, NIT = 7 per lane): the
-// memory latency is paid once per tile instead of once per chunk.
-template <int SM>
-__device__ __forceinline__ void stage_tile_batched(u16* tile, const Stage& st, int b, int y0, int x0, int H, int W) {
+// memory latency is paid once per tile instead of once per chunk.  Plain and
+// skip-add staging, and 2D pooling (3D pooling reads 8 pixels per chunk and
+// takes stage_tile).
+template <int SM, int KD>
+__device__ __forceinline__ void stage_tile_batched(u16* tile, const Stage& st, const Dims& g, int b, int z, int y0,
+                                                   int x0) {
   constexpr int NE = SY * SX * 4, NIT = (NE + 255) / 256;
   constexpr int NQ = SM == SM_POOL ? 4 : SM == SM_UPADD ? 2 : 1;
-  if constexpr (SM == SM_INPUT) {
-    stage_tile<SM>(tile, st, b, y0, x0, H, W);
-    return;
-  }
+  static_assert(SM == SM_PLAIN || SM == SM_UPADD || (SM == SM_POOL && KD == 1), "batched staging modes");
+  const bool zin = z >= 0 && z < g.D;
+  const Dims gf = finer<KD>(g), gc = coarser<KD>(g);
   uint4 q[NIT][NQ];
-  bool ok[NIT];
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int e = threadIdx.x + it * 256;
     const int c = (e & 3) * 8, p = e >> 2;
     const int yy = y0 + p / SX - 1, xx = x0 + p % SX - 1;
-    ok[it] = e < NE && yy >= 0 && yy < H && xx >= 0 && xx < W;
+    const bool ok = zin && e < NE && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W;
 #pragma unroll
     for (int k = 0; k < NQ; ++k) q[it][k] = make_uint4(0, 0, 0, 0);
-    if (ok[it]) {
-      if (SM == SM_PLAIN) {
-        q[it][0] = *(const uint4*)(st.s0 + pix(b, yy, xx, H, W) + c);
-      } else if (SM == SM_UPADD) {
-        q[it][0] = *(const uint4*)(st.s0 + pix(b, yy, xx, H, W) + c);
-        q[it][1] = *(const uint4*)(st.s1 + pix(b, yy >> 1, xx >> 1, H >> 1, W >> 1) + c);
-      } else {  // SM_POOL
+    if (ok) {
+      if constexpr (SM == SM_PLAIN) {
+        q[it][0] = *(const uint4*)(st.s0 + pix(g, b, z, yy, xx) + c);
+      } else if constexpr (SM == SM_UPADD) {
+        q[it][0] = *(const uint4*)(st.s0 + pix(g, b, z, yy, xx) + c);
+        q[it][1] = *(const uint4*)(st.s1 + pix(gc, b, KD == 3 ? z >> 1 : 0, yy >> 1, xx >> 1) + c);
+      } else {  // SM_POOL, 2D
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          q[it][k] = *(const uint4*)(st.s0 + pix(b, 2 * yy + (k >> 1), 2 * xx + (k & 1), 2 * H, 2 * W) + c);
+          q[it][k] = *(const uint4*)(st.s0 + pix(gf, b, 0, 2 * yy + (k >> 1), 2 * xx + (k & 1)) + c);
       }
     }
   }
@@ -216,55 +250,69 @@ __device__ __forceinline__ void stage_tile_batched(u16* tile, const Stage& st, i
   }
 }
 
+// Decode a tile index of a level: (b, z, tile row, tile column).
+__device__ __forceinline__ void tile_of(long t, const Dims& g, int& b, int& z, int& y0, int& x0) {
+  const int tilesX = (g.W + TX - 1) / TX, tilesY = (g.H + TY - 1) / TY;
+  x0 = (int)(t % tilesX) * TX;
+  t /= tilesX;
+  y0 = (int)(t % tilesY) * TY;
+  t /= tilesY;
+  z = (int)(t % g.D);
+  b = (int)(t / g.D);
+}
+
 // ---------------------------------------------------------------------------
 // 32 -> 32 convolution on MFMA (forward with bias + ReLU, or the transposed
 // convolution of the reverse pass with flipped, transposed weights)
 // ---------------------------------------------------------------------------
 // EPI_RELU: bias + ReLU, BF16 out; EPI_NONE: BF16 out; EPI_OUT: the output
-// layer, output channel 0 only, FP32 into yout ([B][H][W]).
+// layer, output channel 0 only, FP32 into yout ([B][D][H][W]).
 enum { EPI_RELU = 0, EPI_NONE = 1, EPI_OUT = 2 };
 
-template <int SM, int EPI>
+template <int SM, int EPI, int KD>
 __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict__ wpack, const float* __restrict__ bias,
-                                                u16* __restrict__ out, int B, int H, int W, float* __restrict__ yout) {
+                                                u16* __restrict__ out, Dims g, float* __restrict__ yout) {
   __shared__ __align__(16) u16 tile[SY * SX * CH];
-  const int tilesX = (W + TX - 1) / TX, tilesY = (H + TY - 1) / TY;
-  int t = blockIdx.x;
-  const int tx = t % tilesX;
-  t /= tilesX;
-  const int ty = t % tilesY, b = t / tilesY;
-  if (b >= B) return;
-  const int x0 = tx * TX, y0 = ty * TY;
-  if constexpr (SM == SM_PLAIN || SM == SM_UPADD || SM == SM_POOL)
-    stage_tile_batched<SM>(tile, st, b, y0, x0, H, W);
-  else
-    stage_tile<SM>(tile, st, b, y0, x0, H, W);
+  int b, z, y0, x0;
+  tile_of(blockIdx.x, g, b, z, y0, x0);
+  if (b >= g.B) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  bf16x8 wf[18];
-#pragma unroll
-  for (int f = 0; f < 18; ++f) wf[f] = *(const bf16x8*)(wpack + ((long)f * 64 + lane) * 8);
-  __syncthreads();
   f32x16 acc0 = {}, acc1 = {};
+#pragma unroll 1
+  for (int kz = 0; kz < KD; ++kz) {
+    const int zi = z + kz - (KD == 3 ? 1 : 0);
+    if (zi < 0 || zi >= g.D) continue;  // zero slice (uniform over the block)
+    if (kz > 0) __syncthreads();         // every wave is done with the previous slice
+    if constexpr (SM == SM_PLAIN || SM == SM_UPADD || (SM == SM_POOL && KD == 1))
+      stage_tile_batched<SM, KD>(tile, st, g, b, zi, y0, x0);
+    else
+      stage_tile<SM, KD>(tile, st, g, b, zi, y0, x0);
+    bf16x8 wf[18];
 #pragma unroll
-  for (int tap = 0; tap < 9; ++tap) {
-    const int ky = tap / 3, kx = tap % 3;
+    for (int f = 0; f < 18; ++f) wf[f] = *(const bf16x8*)(wpack + ((long)(kz * 18 + f) * 64 + lane) * 8);
+    __syncthreads();
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const u16* p0 = tile + ((wave + ky) * SX + (lane & 31) + kx) * CH + half * 16 + (lane >> 5) * 8;
-      const bf16x8 b0 = *(const bf16x8*)p0;
-      const bf16x8 b1 = *(const bf16x8*)(p0 + 32 * CH);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[tap * 2 + half], b0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[tap * 2 + half], b1, acc1, 0, 0, 0);
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap % 3;
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const u16* p0 = tile + ((wave + ky) * SX + (lane & 31) + kx) * CH + half * 16 + (lane >> 5) * 8;
+        const bf16x8 b0 = *(const bf16x8*)p0;
+        const bf16x8 b1 = *(const bf16x8*)(p0 + 32 * CH);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[tap * 2 + half], b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[tap * 2 + half], b1, acc1, 0, 0, 0);
+      }
     }
   }
   // lane holds pixel (lane & 31) of each 32-pixel half, channels
   // g*8 + (lane>>5)*4 + 0..3 in acc[4g .. 4g+3]
   if constexpr (EPI == EPI_OUT) {  // channel 0 sits in acc[0] of lanes 0..31
     const int yo = y0 + wave;
-    if (lane < 32 && yo < H) {
+    if (lane < 32 && yo < g.H) {
+      const long row = (((long)b * g.D + z) * g.H + yo) * g.W;
       const int px0 = x0 + lane, px1 = x0 + 32 + lane;
-      if (px0 < W) yout[((long)b * H + yo) * W + px0] = acc0[0] + bias[0];
-      if (px1 < W) yout[((long)b * H + yo) * W + px1] = acc1[0] + bias[0];
+      if (px0 < g.W) yout[row + px0] = acc0[0] + bias[0];
+      if (px1 < g.W) yout[row + px1] = acc1[0] + bias[0];
     }
     return;
   }
@@ -277,12 +325,12 @@ __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict_
     const f32x16& a = m ? acc1 : acc0;
     const int pl = m * 32 + (lane & 31);
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int cb = g * 8 + (lane >> 5) * 4;
+    for (int q = 0; q < 4; ++q) {
+      const int cb = q * 8 + (lane >> 5) * 4;
       float v[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        v[i] = a[4 * g + i];
+        v[i] = a[4 * q + i];
         if (EPI == EPI_RELU) v[i] = fmaxf(v[i] + bias[cb + i], 0.f);
       }
       const unsigned lo = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
@@ -292,49 +340,53 @@ __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict_
   }
   __syncthreads();
   const int yo = y0 + wave;
-  if (yo >= H) return;
+  if (yo >= g.H) return;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = lane + 64 * k, pl = e >> 2, qq = (e & 3) * 8;
     const int px = x0 + pl;
-    if (px < W) *(uint4*)(out + pix(b, yo, px, H, W) + qq) = *(const uint4*)(ot + pl * CH + qq);
+    if (px < g.W) *(uint4*)(out + pix(g, b, z, yo, px) + qq) = *(const uint4*)(ot + pl * CH + qq);
+  }
+}
+
+// Stage the gradient G of the output slice z (TY x TX pixels, no halo).
+template <int SMG, int KD>
+__device__ __forceinline__ void stage_grad(u16* gt, const Stage& sg, const Dims& g, int b, int z, int y0, int x0) {
+  for (int e = threadIdx.x; e < TY * TX * 4; e += blockDim.x) {
+    const int c = (e & 3) * 8, p = e >> 2;
+    const int yy = y0 + p / TX, xx = x0 + p % TX;
+    float v[8];
+    if (yy < g.H && xx < g.W) {
+      stage8<SMG, KD>(sg, g, b, z, yy, xx, c, v);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = 0.f;
+    }
+    *(uint4*)(gt + p * CH + c) = pk8(v);
   }
 }
 
 // Weight gradient of a 32 -> 32 layer: per-block partials of
 // dW[tap][ci][co] = sum_p X[p + tap][ci] G[p][co] and db[co] = sum_p G[p][co]
 // (X staged by SMI, G by SMG), FP32 accumulation; blocks stride over tiles.
-template <int SMI, int SMG>
-__global__ __launch_bounds__(256) void k_conv32_wgrad(Stage si, Stage sg, float* __restrict__ part, int B, int H,
-                                                      int W) {
+// blockIdx.y = kz: the block accumulates the nine taps of input slice
+// z + kz - 1 (3D) into rows kz*288 .. of its partial (stride L32SZ).
+template <int SMI, int SMG, int KD>
+__global__ __launch_bounds__(256) void k_conv32_wgrad(Stage si, Stage sg, float* __restrict__ part, Dims g) {
   __shared__ __align__(16) u16 xt[SY * SX * CH];
   __shared__ __align__(16) u16 gt[TY * TX * CH];
   const int co = threadIdx.x & 31, grp = threadIdx.x >> 5;  // 8 groups of 36 (tap, ci)
-  const int tilesX = (W + TX - 1) / TX, tilesY = (H + TY - 1) / TY;
-  const int ntiles = B * tilesY * tilesX;
+  const int kz = blockIdx.y;
+  const long ntiles = (long)g.B * g.D * ((g.H + TY - 1) / TY) * ((g.W + TX - 1) / TX);
   float acc[36];
 #pragma unroll
   for (int j = 0; j < 36; ++j) acc[j] = 0.f;
   float accb = 0.f;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int u = t;
-    const int tx = u % tilesX;
-    u /= tilesX;
-    const int ty = u % tilesY, b = u / tilesY;
-    const int x0 = tx * TX, y0 = ty * TY;
-    stage_tile<SMI>(xt, si, b, y0, x0, H, W);
-    for (int e = threadIdx.x; e < TY * TX * 4; e += blockDim.x) {
-      const int c = (e & 3) * 8, p = e >> 2;
-      const int yy = y0 + p / TX, xx = x0 + p % TX;
-      float v[8];
-      if (yy < H && xx < W) {
-        stage8<SMG>(sg, b, yy, xx, H, W, c, v);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = 0.f;
-      }
-      *(uint4*)(gt + p * CH + c) = pk8(v);
-    }
+  for (long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int b, z, y0, x0;
+    tile_of(t, g, b, z, y0, x0);
+    stage_tile<SMI, KD>(xt, si, g, b, z + kz - (KD == 3 ? 1 : 0), y0, x0);
+    stage_grad<SMG, KD>(gt, sg, g, b, z, y0, x0);
     __syncthreads();
     for (int p = 0; p < TY * TX; ++p) {
       const int ly = p / TX, lx = p % TX;
@@ -348,52 +400,40 @@ __global__ __launch_bounds__(256) void k_conv32_wgrad(Stage si, Stage sg, float*
     }
     __syncthreads();
   }
-  float* o = part + (long)blockIdx.x * L32SZ;
+  float* o = part + (long)blockIdx.x * PL<KD>::L32SZ;
 #pragma unroll
   for (int j = 0; j < 36; ++j) {
     const int q = grp * 36 + j;
-    o[(long)q * CH + co] = acc[j];
+    o[((long)kz * 288 + q) * CH + co] = acc[j];
   }
-  if (grp == 0) o[L32W + co] = accb;
+  if (kz == 0 && grp == 0) o[PL<KD>::L32W + co] = accb;
 }
 
 // ---------------------------------------------------------------------------
 // Input layer (2 -> 32) and output layer (32 -> 1): VALU, FP32 weights
 // ---------------------------------------------------------------------------
 // Weight gradient of cin: partials of dW[tap][ci][co] (ci: x and alpha - 1) and
-// db, the gradient G staged by SMG; 608 values per block.
-template <int SMG>
+// db, the gradient G staged by SMG; blockIdx.y = kz as in k_conv32_wgrad
+// (576 values per kz, then the 32 biases; stride CIN_PV).
+template <int SMG, int KD>
 __global__ __launch_bounds__(256) void k_cin_wgrad(const float* __restrict__ x, const float* __restrict__ alpha, Stage sg,
-                                                   float* __restrict__ part, int B, int H, int W) {
+                                                   float* __restrict__ part, Dims g) {
   __shared__ __align__(16) u16 gt[TY * TX * CH];
   __shared__ float xs[SY * SX][2];
-  const int tilesX = (W + TX - 1) / TX, tilesY = (H + TY - 1) / TY;
-  const int ntiles = B * tilesY * tilesX;
+  const int kz = blockIdx.y;
+  const long ntiles = (long)g.B * g.D * ((g.H + TY - 1) / TY) * ((g.W + TX - 1) / TX);
   float acc[3] = {0.f, 0.f, 0.f};
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int u = t;
-    const int tx = u % tilesX;
-    u /= tilesX;
-    const int ty = u % tilesY, b = u / tilesY;
-    const int x0 = tx * TX, y0 = ty * TY;
+  for (long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int b, z, y0, x0;
+    tile_of(t, g, b, z, y0, x0);
+    const int zi = z + kz - (KD == 3 ? 1 : 0);
     for (int p = threadIdx.x; p < SY * SX; p += blockDim.x) {
       const int yy = y0 + p / SX - 1, xx = x0 + p % SX - 1;
-      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-      xs[p][0] = in ? x[((long)b * H + yy) * W + xx] : 0.f;
+      const bool in = zi >= 0 && zi < g.D && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W;
+      xs[p][0] = in ? x[(((long)b * g.D + zi) * g.H + yy) * g.W + xx] : 0.f;
       xs[p][1] = in ? alpha[b] - 1.f : 0.f;
     }
-    for (int e = threadIdx.x; e < TY * TX * 4; e += blockDim.x) {
-      const int c = (e & 3) * 8, p = e >> 2;
-      const int yy = y0 + p / TX, xx = x0 + p % TX;
-      float v[8];
-      if (yy < H && xx < W) {
-        stage8<SMG>(sg, b, yy, xx, H, W, c, v);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = 0.f;
-      }
-      *(uint4*)(gt + p * CH + c) = pk8(v);
-    }
+    stage_grad<SMG, KD>(gt, sg, g, b, z, y0, x0);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -412,58 +452,65 @@ __global__ __launch_bounds__(256) void k_cin_wgrad(const float* __restrict__ x, 
     }
     __syncthreads();
   }
+  float* o = part + (long)blockIdx.x * PL<KD>::CIN_PV;
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     const int e = threadIdx.x + r * 256;
-    if (e < 608) part[(long)blockIdx.x * 608 + e] = acc[r];
+    if (e < 576) o[(long)kz * 576 + e] = acc[r];
+    else if (e < 608 && kz == 0) o[PL<KD>::OFF_CIN_B + (e - 576)] = acc[r];
   }
 }
 
 // gc0[p][ci] = sum_tap gy[p - off(tap)] W_out[tap][ci] (transposed convolution),
 // four lanes per pixel, eight channels each.
-__global__ __launch_bounds__(256) void k_cout_bwd(const float* __restrict__ gy, const float* __restrict__ th,
-                                                  u16* __restrict__ gc0, int B, int H, int W) {
-  __shared__ float ws[9 * CH];
-  for (int i = threadIdx.x; i < 9 * CH; i += blockDim.x) ws[i] = th[OFF_OUT + i];
+template <int KD>
+__global__ __launch_bounds__(256) void k_cout_bwd(const float* __restrict__ gy, const float* __restrict__ wout,
+                                                  u16* __restrict__ gc0, Dims g) {
+  constexpr int K = 9 * KD;
+  __shared__ float ws[K * CH];
+  for (int i = threadIdx.x; i < K * CH; i += blockDim.x) ws[i] = wout[i];
   __syncthreads();
   const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long idx = t >> 2;
-  if (idx >= (long)B * H * W) return;
+  if (idx >= (long)g.B * g.D * g.H * g.W) return;
   const int q = (int)(t & 3) * 8;
-  const int xx = (int)(idx % W), yy = (int)((idx / W) % H), b = (int)(idx / ((long)W * H));
+  const int xx = (int)(idx % g.W), yy = (int)((idx / g.W) % g.H);
+  const long bz = idx / ((long)g.W * g.H);  // b * D + z
+  const int zz = (int)(bz % g.D);
   float acc[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) acc[i] = 0.f;
 #pragma unroll
-  for (int tap = 0; tap < 9; ++tap) {
-    const int y2 = yy - (tap / 3 - 1), x2 = xx - (tap % 3 - 1);
-    if (y2 < 0 || y2 >= H || x2 < 0 || x2 >= W) continue;
-    const float g = gy[((long)b * H + y2) * W + x2];
+  for (int tap = 0; tap < K; ++tap) {
+    const int z2 = zz - (KD == 3 ? tap / 9 - 1 : 0);
+    const int y2 = yy - ((tap % 9) / 3 - 1), x2 = xx - (tap % 3 - 1);
+    if (z2 < 0 || z2 >= g.D || y2 < 0 || y2 >= g.H || x2 < 0 || x2 >= g.W) continue;
+    const float gv = gy[((bz + (z2 - zz)) * g.H + y2) * g.W + x2];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] += g * ws[tap * CH + q + i];
+    for (int i = 0; i < 8; ++i) acc[i] += gv * ws[tap * CH + q + i];
   }
   *(uint4*)(gc0 + idx * CH + q) = pk8(acc);
 }
 
-// Weight gradient of out: partials of dW[tap][ci] = sum_p c0[p + tap][ci] gy[p], db = sum gy (289 per block)
+// Weight gradient of out: partials of dW[tap][ci] = sum_p c0[p + tap][ci] gy[p]
+// and db = sum gy; blockIdx.y = kz (288 values per kz, then the bias; stride
+// OUT_PV).
+template <int KD>
 __global__ __launch_bounds__(256) void k_cout_wgrad(const u16* __restrict__ c0, const float* __restrict__ gy,
-                                                    float* __restrict__ part, int B, int H, int W) {
+                                                    float* __restrict__ part, Dims g) {
   __shared__ __align__(16) u16 xt[SY * SX * CH];
   __shared__ float gs[TY * TX];
-  const int tilesX = (W + TX - 1) / TX, tilesY = (H + TY - 1) / TY;
-  const int ntiles = B * tilesY * tilesX;
+  const int kz = blockIdx.y;
+  const long ntiles = (long)g.B * g.D * ((g.H + TY - 1) / TY) * ((g.W + TX - 1) / TX);
   Stage st = {c0, nullptr, nullptr};
   float acc[2] = {0.f, 0.f};
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int u = t;
-    const int tx = u % tilesX;
-    u /= tilesX;
-    const int ty = u % tilesY, b = u / tilesY;
-    const int x0 = tx * TX, y0 = ty * TY;
-    stage_tile<SM_PLAIN>(xt, st, b, y0, x0, H, W);
+  for (long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int b, z, y0, x0;
+    tile_of(t, g, b, z, y0, x0);
+    stage_tile<SM_PLAIN, KD>(xt, st, g, b, z + kz - (KD == 3 ? 1 : 0), y0, x0);
     for (int p = threadIdx.x; p < TY * TX; p += blockDim.x) {
       const int yy = y0 + p / TX, xx = x0 + p % TX;
-      gs[p] = (yy < H && xx < W) ? gy[((long)b * H + yy) * W + xx] : 0.f;
+      gs[p] = (yy < g.H && xx < g.W) ? gy[(((long)b * g.D + z) * g.H + yy) * g.W + xx] : 0.f;
     }
     __syncthreads();
 #pragma unroll
@@ -482,10 +529,12 @@ __global__ __launch_bounds__(256) void k_cout_wgrad(const u16* __restrict__ c0, 
     }
     __syncthreads();
   }
+  float* o = part + (long)blockIdx.x * PL<KD>::OUT_PV;
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
     const int e = threadIdx.x + r * 256;
-    if (e < 289) part[(long)blockIdx.x * 289 + e] = acc[r];
+    if (e < 288) o[(long)kz * 288 + e] = acc[r];
+    else if (e == 288 && kz == 0) o[(long)9 * KD * CH] = acc[r];
   }
 }
 
@@ -501,26 +550,28 @@ __global__ void k_reduce_part(const float* __restrict__ part, int nblk, int stri
 // Packed bf16 weights of the 32 -> 32 layers.  Forward (A operand = W^T):
 // fw[L][tap][half][lane][e] = W_L[tap][half*16 + 8*(lane/32) + e][lane%32].
 // Transposed flipped (reverse pass): bw[L][tap][half][lane][e] =
-// W_L[8 - tap][lane%32][half*16 + 8*(lane/32) + e].  Slots L = 7 and 8 of fw
-// hold the input layer (input channels >= 2 zero) and the output layer (output
-// channels >= 1 zero) in the same form.
+// W_L[K-1-tap][lane%32][half*16 + 8*(lane/32) + e] (reversing the tap index
+// reverses every offset).  Slots L = 7 and 8 of fw hold the input layer
+// (input channels >= 2 zero) and the output layer (output channels >= 1 zero)
+// in the same form.
 constexpr int NPACK = NL32 + 2;
-__global__ void k_pack(const float* __restrict__ th, u16* __restrict__ fw, u16* __restrict__ bw) {
+template <int KD> __global__ void k_pack(const float* __restrict__ th, u16* __restrict__ fw, u16* __restrict__ bw) {
+  using P = PL<KD>;
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (idx >= NPACK * PACK) return;
-  const int L = (int)(idx / PACK);
-  const int r = (int)(idx % PACK);
+  if (idx >= NPACK * P::PACK) return;
+  const int L = (int)(idx / P::PACK);
+  const int r = (int)(idx % P::PACK);
   const int e = r & 7, lane = (r >> 3) & 63, f = r >> 9;
   const int tap = f >> 1, half = f & 1;
   const int kk = half * 16 + 8 * (lane >> 5) + e, j = lane & 31;
   if (L < NL32) {
-    const float* W = th + OFF_L32 + L * L32SZ;
+    const float* W = th + P::OFF_L32 + L * P::L32SZ;
     fw[idx] = f2bf(W[((long)tap * CH + kk) * CH + j]);
-    bw[idx] = f2bf(W[((long)(8 - tap) * CH + j) * CH + kk]);
+    bw[idx] = f2bf(W[((long)(P::K - 1 - tap) * CH + j) * CH + kk]);
   } else if (L == NL32) {
     fw[idx] = kk < 2 ? f2bf(th[(tap * 2 + kk) * CH + j]) : (u16)0;
   } else {
-    fw[idx] = j == 0 ? f2bf(th[OFF_OUT + tap * CH + kk]) : (u16)0;
+    fw[idx] = j == 0 ? f2bf(th[P::OFF_OUT + tap * CH + kk]) : (u16)0;
   }
 }
 
@@ -576,27 +627,31 @@ __global__ void k_gather(const float* __restrict__ R, const float* __restrict__ 
   if (i % npix == 0) a[k] = A[idx[k]];
 }
 
-// Learned-preconditioner input and output on the solver grid (n0 x n1 inside
-// the padded Hp x Wp network grid): xin = r / s, w = r + s y, with the RMS
-// s = sqrt(rr / (n0 n1)) read from the device (rr = r.r).
+// Learned-preconditioner input and output on the solver grid m0 x m1 x m2
+// (m0 = 1 in 2D) inside the padded network grid P0 x P1 x P2: xin = r / s,
+// w = r + s y, with the RMS s = sqrt(rr / N) read from the device (rr = r.r).
+struct PadGrid {
+  int m0, m1, m2, P0, P1, P2;
+};
 template <typename T>
-__global__ void k_net_in(const T* __restrict__ r, float* __restrict__ xin, int n0, int n1, int Hp, int Wp,
-                         const double* __restrict__ rr) {
+__global__ void k_net_in(const T* __restrict__ r, float* __restrict__ xin, PadGrid q, const double* __restrict__ rr) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= (long)Hp * Wp) return;
-  const double ms = *rr / ((double)n0 * n1);
+  if (i >= (long)q.P0 * q.P1 * q.P2) return;
+  const double ms = *rr / ((double)q.m0 * q.m1 * q.m2);
   const double inv_s = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
-  const int yy = (int)(i / Wp), xx = (int)(i % Wp);
-  xin[i] = (yy < n0 && xx < n1) ? (float)((double)r[(long)yy * n1 + xx] * inv_s) : 0.f;
+  const int xx = (int)(i % q.P2), yy = (int)((i / q.P2) % q.P1), zz = (int)(i / ((long)q.P1 * q.P2));
+  const bool in = zz < q.m0 && yy < q.m1 && xx < q.m2;
+  xin[i] = in ? (float)((double)r[((long)zz * q.m1 + yy) * q.m2 + xx] * inv_s) : 0.f;
 }
 template <typename T>
-__global__ void k_net_out(const T* __restrict__ r, const float* __restrict__ y, T* __restrict__ w, int n0, int n1, int Wp,
+__global__ void k_net_out(const T* __restrict__ r, const float* __restrict__ y, T* __restrict__ w, PadGrid q,
                           const double* __restrict__ rr) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= (long)n0 * n1) return;
-  const double sc = sqrt(fmax(*rr, 0.0) / ((double)n0 * n1));
-  const int yy = (int)(i / n1), xx = (int)(i % n1);
-  w[i] = (T)((double)r[i] + sc * (double)y[(long)yy * Wp + xx]);
+  const long N = (long)q.m0 * q.m1 * q.m2;
+  if (i >= N) return;
+  const double sc = sqrt(fmax(*rr, 0.0) / (double)N);
+  const int xx = (int)(i % q.m2), yy = (int)((i / q.m2) % q.m1), zz = (int)(i / ((long)q.m1 * q.m2));
+  w[i] = (T)((double)r[i] + sc * (double)y[((long)zz * q.P1 + yy) * q.P2 + xx]);
 }
 
 // Flexible CG scalars live on the device: fs[0] = r.z, fs[1] = z.q_old,
@@ -632,16 +687,16 @@ template <typename T> __global__ __launch_bounds__(256) void k_fcg_update(Prob p
 }
 
 // Training pairs on the operator's grid (FP64 in): R = r / s, T = (D e - r) / s
-// with r = M e, s = RMS(r); the pair written into the padded Hp x Wp grid.
+// with r = M e, s = RMS(r); the pair written into the padded network grid.
 __global__ void k_pair_out(const double* __restrict__ r, const double* __restrict__ De, float* __restrict__ R,
-                           float* __restrict__ Tt, int n0, int n1, int Hp, int Wp, const double* __restrict__ rr) {
+                           float* __restrict__ Tt, PadGrid q, const double* __restrict__ rr) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= (long)Hp * Wp) return;
-  const int yy = (int)(i / Wp), xx = (int)(i % Wp);
-  const double ms = *rr / ((double)n0 * n1);
+  if (i >= (long)q.P0 * q.P1 * q.P2) return;
+  const int xx = (int)(i % q.P2), yy = (int)((i / q.P2) % q.P1), zz = (int)(i / ((long)q.P1 * q.P2));
+  const double ms = *rr / ((double)q.m0 * q.m1 * q.m2);
   const double inv = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;  // a zero error gives a zero pair
-  const bool in = yy < n0 && xx < n1;
-  const long j = (long)yy * n1 + xx;
+  const bool in = zz < q.m0 && yy < q.m1 && xx < q.m2;
+  const long j = ((long)zz * q.m1 + yy) * q.m2 + xx;
   R[i] = in ? (float)(r[j] * inv) : 0.f;
   Tt[i] = in ? (float)((De[j] - r[j]) * inv) : 0.f;
 }
@@ -655,10 +710,12 @@ using namespace fln;
 // ---------------------------------------------------------------------------
 struct fl_net_s {
   hipStream_t stream = nullptr;
+  int kd = 1;              // kernel depth: 1 (2D network) or 3 (3D network)
+  long nparam = 0, pack = 0;
   float *th = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
   u16 *fw = nullptr, *bw = nullptr;
   int step = 0;
-  // activations and gradients for capacity B x H x W (level 0 pixels)
+  // activations and gradients for capacity B x D x H x W (level 0 pixels)
   long cap = 0;
   u16* act[8] = {};   // a0 a1 a2 a3 c3 c2 c1 c0
   u16* grd[8] = {};   // gc0 gs0 gs1 gs2 ga3 gp3 gp2 gp1
@@ -693,14 +750,18 @@ struct fl_net_s {
 enum { A0 = 0, A1, A2, A3, C3, C2, C1, C0 };
 enum { GC0 = 0, GS0, GS1, GS2, GA3, GP3, GP2, GP1 };
 
-static fl_status net_reserve(fl_net net, int B, int H, int W) {
-  const long px = (long)B * H * W;
+// level-0 pixels shrink by 2^d per level
+static int lvl_shift(const fl_net net) { return net->kd == 3 ? 3 : 2; }
+
+static fl_status net_reserve(fl_net net, int B, int D, int H, int W) {
+  const long px = (long)B * D * H * W;
   if (px <= net->cap) return FL_OK;
   const int lvl_of_act[8] = {0, 1, 2, 3, 3, 2, 1, 0};
   const int lvl_of_grd[8] = {0, 0, 1, 2, 3, 3, 2, 1};
+  const int sh = lvl_shift(net);
   for (int i = 0; i < 8; ++i) {
-    STCHK(net->alloc((void**)&net->act[i], (size_t)(px >> (2 * lvl_of_act[i])) * CH * sizeof(u16)));
-    STCHK(net->alloc((void**)&net->grd[i], (size_t)(px >> (2 * lvl_of_grd[i])) * CH * sizeof(u16)));
+    STCHK(net->alloc((void**)&net->act[i], (size_t)(px >> (sh * lvl_of_act[i])) * CH * sizeof(u16)));
+    STCHK(net->alloc((void**)&net->grd[i], (size_t)(px >> (sh * lvl_of_grd[i])) * CH * sizeof(u16)));
   }
   for (float** p : {&net->y, &net->gy, &net->xb, &net->tb}) STCHK(net->alloc((void**)p, px * sizeof(float)));
   net->cap = px;
@@ -721,93 +782,104 @@ static fl_status net_part(fl_net net, long n) {
   return FL_OK;
 }
 
-static int conv_blocks(int B, int H, int W) { return B * ((H + TY - 1) / TY) * ((W + TX - 1) / TX); }
+static int conv_blocks(const Dims& g) { return g.B * g.D * ((g.H + TY - 1) / TY) * ((g.W + TX - 1) / TX); }
 
-static fl_status check_grid(int B, int H, int W) {
+// 2D networks take D = 1; 3D networks a depth that is a multiple of 8 too
+static fl_status check_grid(const fl_net net, int B, int D, int H, int W) {
   if (B < 1 || H < 8 || W < 8) return fail(FL_E_INVALID, "network grid must be at least 8 x 8");
   if (H % 8 || W % 8) return fail(FL_E_INVALID, "network grid sides must be multiples of 8");
+  if (net->kd == 1 && D != 1) return fail(FL_E_INVALID, "a 2D network takes D = 1");
+  if (net->kd == 3 && (D < 8 || D % 8)) return fail(FL_E_INVALID, "a 3D network needs a depth multiple of 8");
   return FL_OK;
 }
 
-// forward pass on x (FP32 [B][H][W]) and alphas (device FP32 [B]) into net->y
-static fl_status net_forward(fl_net net, const float* x, const float* alpha, int B, int H, int W) {
-  STCHK(check_grid(B, H, W));
-  STCHK(net_reserve(net, B, H, W));
+// forward pass on x (FP32 [B][D][H][W]) and alphas (device FP32 [B]) into net->y
+template <int KD> static fl_status net_forward_t(fl_net net, const float* x, const float* alpha, Dims g0) {
+  using P = PL<KD>;
   hipStream_t s = net->stream;
   u16** a = net->act;
   const float* th = net->th;
-  auto bias = [&](int L) { return th + OFF_L32 + L * L32SZ + L32W; };
-  auto fw = [&](int L) { return net->fw + L * PACK; };
+  auto bias = [&](int L) { return th + P::OFF_L32 + L * P::L32SZ + P::L32W; };
+  auto fw = [&](int L) { return (const u16*)(net->fw + L * P::PACK); };
+  auto half = [](Dims g) { return Dims{g.B, KD == 3 ? g.D / 2 : 1, g.H / 2, g.W / 2}; };
+  auto dbl = [](Dims g) { return Dims{g.B, KD == 3 ? g.D * 2 : 1, g.H * 2, g.W * 2}; };
   {
     Stage st = {nullptr, nullptr, nullptr, x, alpha};
-    LAUNCH((k_conv32<SM_INPUT, EPI_RELU>), dim3(conv_blocks(B, H, W)), dim3(256), 0, s, st, (const u16*)fw(NL32),
-           th + OFF_CIN_B, a[A0], B, H, W, (float*)nullptr);
+    LAUNCH((k_conv32<SM_INPUT, EPI_RELU, KD>), dim3(conv_blocks(g0)), dim3(256), 0, s, st, fw(NL32),
+           th + P::OFF_CIN_B, a[A0], g0, (float*)nullptr);
   }
-  int h = H, w = W;
+  Dims g = g0;
   // down path
   const int lay[3] = {LD1, LD2, LD3};
   for (int l = 1; l <= 3; ++l) {
-    h /= 2;
-    w /= 2;
+    g = half(g);
     Stage st = {a[A0 + l - 1], nullptr, nullptr};
-    LAUNCH((k_conv32<SM_POOL, EPI_RELU>), dim3(conv_blocks(B, h, w)), dim3(256), 0, s, st, (const u16*)fw(lay[l - 1]),
-           bias(lay[l - 1]), a[A0 + l], B, h, w, (float*)nullptr);
+    LAUNCH((k_conv32<SM_POOL, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(lay[l - 1]),
+           bias(lay[l - 1]), a[A0 + l], g, (float*)nullptr);
   }
   {
     Stage st = {a[A3], nullptr, nullptr};
-    LAUNCH((k_conv32<SM_PLAIN, EPI_RELU>), dim3(conv_blocks(B, h, w)), dim3(256), 0, s, st, (const u16*)fw(LB3),
-           bias(LB3), a[C3], B, h, w, (float*)nullptr);
+    LAUNCH((k_conv32<SM_PLAIN, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(LB3), bias(LB3), a[C3],
+           g, (float*)nullptr);
   }
   // up path: c_l = relu(u_l(a_l + up c_{l+1}))
   const int ulay[3] = {LU2, LU1, LU0};
   const int adst[3] = {C2, C1, C0}, askip[3] = {A2, A1, A0}, acoarse[3] = {C3, C2, C1};
   for (int k = 0; k < 3; ++k) {
-    h *= 2;
-    w *= 2;
+    g = dbl(g);
     Stage st = {a[askip[k]], a[acoarse[k]], nullptr};
-    LAUNCH((k_conv32<SM_UPADD, EPI_RELU>), dim3(conv_blocks(B, h, w)), dim3(256), 0, s, st, (const u16*)fw(ulay[k]),
-           bias(ulay[k]), a[adst[k]], B, h, w, (float*)nullptr);
+    LAUNCH((k_conv32<SM_UPADD, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(ulay[k]), bias(ulay[k]),
+           a[adst[k]], g, (float*)nullptr);
   }
   {
     Stage st = {a[C0], nullptr, nullptr};
-    LAUNCH((k_conv32<SM_PLAIN, EPI_OUT>), dim3(conv_blocks(B, H, W)), dim3(256), 0, s, st, (const u16*)fw(NL32 + 1),
-           th + OFF_OUT + 9 * CH, (u16*)nullptr, B, H, W, net->y);
+    LAUNCH((k_conv32<SM_PLAIN, EPI_OUT, KD>), dim3(conv_blocks(g0)), dim3(256), 0, s, st, fw(NL32 + 1),
+           th + P::OFF_OUT + P::K * CH, (u16*)nullptr, g0, net->y);
   }
   return FL_OK;
 }
 
+static fl_status net_forward(fl_net net, const float* x, const float* alpha, int B, int D, int H, int W) {
+  STCHK(check_grid(net, B, D, H, W));
+  STCHK(net_reserve(net, B, D, H, W));
+  const Dims g{B, D, H, W};
+  return net->kd == 3 ? net_forward_t<3>(net, x, alpha, g) : net_forward_t<1>(net, x, alpha, g);
+}
+
 // reverse pass from net->gy (dL/dy) into net->g (parameter gradient), after net_forward on the same input
-static fl_status net_backward(fl_net net, const float* x, const float* alpha, int B, int H, int W) {
+template <int KD> static fl_status net_backward_t(fl_net net, const float* x, const float* alpha, Dims g0) {
+  using P = PL<KD>;
   hipStream_t s = net->stream;
-  const long px = (long)B * H * W;
+  const long px = (long)g0.B * g0.D * g0.H * g0.W;
   u16** a = net->act;
   u16** gr = net->grd;
   const float* th = net->th;
-  auto bw = [&](int L) { return (const u16*)(net->bw + L * PACK); };
+  auto bw = [&](int L) { return (const u16*)(net->bw + L * P::PACK); };
   const int maxblk = 1024;
-  STCHK(net_part(net, (long)maxblk * L32SZ));
-  auto wgrad_blocks = [&](int b, int h, int w) { return std::min(maxblk, conv_blocks(b, h, w)); };
-  auto reduce = [&](int nblk, int stride, int nval, long off) -> fl_status {
-    LAUNCH(k_reduce_part, dim3((nval + 255) / 256), dim3(256), 0, s, (const float*)net->part, nblk, stride, nval,
-           net->g + off);
+  STCHK(net_part(net, (long)maxblk * P::L32SZ));
+  auto wgrad_blocks = [&](const Dims& g) { return std::min(maxblk, conv_blocks(g)); };
+  auto reduce = [&](int nblk, long stride, long nval, long off) -> fl_status {
+    LAUNCH(k_reduce_part, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, s, (const float*)net->part, nblk,
+           (int)stride, (int)nval, net->g + off);
     return FL_OK;
   };
   // output layer
-  LAUNCH(k_cout_bwd, dim3(nblocks_vec(4 * px)), dim3(256), 0, s, (const float*)net->gy, th, gr[GC0], B, H, W);
+  LAUNCH(k_cout_bwd<KD>, dim3(nblocks_vec(4 * px)), dim3(256), 0, s, (const float*)net->gy, th + P::OFF_OUT, gr[GC0],
+         g0);
   {
-    const int nb = wgrad_blocks(B, H, W);
-    LAUNCH(k_cout_wgrad, dim3(nb), dim3(256), 0, s, (const u16*)a[C0], (const float*)net->gy, net->part, B, H, W);
-    STCHK(reduce(nb, 289, 289, OFF_OUT));
+    const int nb = wgrad_blocks(g0);
+    LAUNCH(k_cout_wgrad<KD>, dim3(nb, KD), dim3(256), 0, s, (const u16*)a[C0], (const float*)net->gy, net->part, g0);
+    STCHK(reduce(nb, P::OUT_PV, P::OUT_PV, P::OFF_OUT));
   }
   // one 32 -> 32 layer: reverse convolution into gin (if any) and weight gradient
-  auto layer = [&](int L, auto smi, auto smg, Stage si, Stage sg, u16* gin, int h, int w) -> fl_status {
+  auto layer = [&](int L, auto smi, auto smg, Stage si, Stage sg, u16* gin, Dims g) -> fl_status {
     constexpr int SMI = decltype(smi)::value, SMG = decltype(smg)::value;
     if (gin)
-      LAUNCH((k_conv32<SMG, EPI_NONE>), dim3(conv_blocks(B, h, w)), dim3(256), 0, s, sg, bw(L), (const float*)nullptr,
-             gin, B, h, w, (float*)nullptr);
-    const int nb = wgrad_blocks(B, h, w);
-    LAUNCH((k_conv32_wgrad<SMI, SMG>), dim3(nb), dim3(256), 0, s, si, sg, net->part, B, h, w);
-    return reduce(nb, (int)L32SZ, (int)L32SZ, OFF_L32 + L * L32SZ);
+      LAUNCH((k_conv32<SMG, EPI_NONE, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, sg, bw(L), (const float*)nullptr,
+             gin, g, (float*)nullptr);
+    const int nb = wgrad_blocks(g);
+    LAUNCH((k_conv32_wgrad<SMI, SMG, KD>), dim3(nb, KD), dim3(256), 0, s, si, sg, net->part, g);
+    return reduce(nb, P::L32SZ, P::L32SZ, P::OFF_L32 + L * P::L32SZ);
   };
   using IP = std::integral_constant<int, SM_PLAIN>;
   using IPO = std::integral_constant<int, SM_POOL>;
@@ -815,26 +887,37 @@ static fl_status net_backward(fl_net net, const float* x, const float* alpha, in
   using GP = std::integral_constant<int, SM_GPLAIN>;
   using GS = std::integral_constant<int, SM_GSUMPOOL>;
   using GA = std::integral_constant<int, SM_GADDUP>;
-  const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
+  auto half = [](Dims g) { return Dims{g.B, KD == 3 ? g.D / 2 : 1, g.H / 2, g.W / 2}; };
+  const Dims g1 = half(g0), g2 = half(g1), g3 = half(g2);
   // u0: c0 = relu(u0(a0 + up c1))
-  STCHK(layer(LU0, IU{}, GP{}, Stage{a[A0], a[C1], nullptr}, Stage{gr[GC0], nullptr, a[C0]}, gr[GS0], H, W));
-  STCHK(layer(LU1, IU{}, GS{}, Stage{a[A1], a[C2], nullptr}, Stage{gr[GS0], nullptr, a[C1]}, gr[GS1], H1, W1));
-  STCHK(layer(LU2, IU{}, GS{}, Stage{a[A2], a[C3], nullptr}, Stage{gr[GS1], nullptr, a[C2]}, gr[GS2], H2, W2));
-  STCHK(layer(LB3, IP{}, GS{}, Stage{a[A3], nullptr, nullptr}, Stage{gr[GS2], nullptr, a[C3]}, gr[GA3], H3, W3));
-  STCHK(layer(LD3, IPO{}, GP{}, Stage{a[A2], nullptr, nullptr}, Stage{gr[GA3], nullptr, a[A3]}, gr[GP3], H3, W3));
-  STCHK(layer(LD2, IPO{}, GA{}, Stage{a[A1], nullptr, nullptr}, Stage{gr[GS2], gr[GP3], a[A2]}, gr[GP2], H2, W2));
-  STCHK(layer(LD1, IPO{}, GA{}, Stage{a[A0], nullptr, nullptr}, Stage{gr[GS1], gr[GP2], a[A1]}, gr[GP1], H1, W1));
+  STCHK(layer(LU0, IU{}, GP{}, Stage{a[A0], a[C1], nullptr}, Stage{gr[GC0], nullptr, a[C0]}, gr[GS0], g0));
+  STCHK(layer(LU1, IU{}, GS{}, Stage{a[A1], a[C2], nullptr}, Stage{gr[GS0], nullptr, a[C1]}, gr[GS1], g1));
+  STCHK(layer(LU2, IU{}, GS{}, Stage{a[A2], a[C3], nullptr}, Stage{gr[GS1], nullptr, a[C2]}, gr[GS2], g2));
+  STCHK(layer(LB3, IP{}, GS{}, Stage{a[A3], nullptr, nullptr}, Stage{gr[GS2], nullptr, a[C3]}, gr[GA3], g3));
+  STCHK(layer(LD3, IPO{}, GP{}, Stage{a[A2], nullptr, nullptr}, Stage{gr[GA3], nullptr, a[A3]}, gr[GP3], g3));
+  STCHK(layer(LD2, IPO{}, GA{}, Stage{a[A1], nullptr, nullptr}, Stage{gr[GS2], gr[GP3], a[A2]}, gr[GP2], g2));
+  STCHK(layer(LD1, IPO{}, GA{}, Stage{a[A0], nullptr, nullptr}, Stage{gr[GS1], gr[GP2], a[A1]}, gr[GP1], g1));
   {
-    const int nb = wgrad_blocks(B, H, W);
+    const int nb = wgrad_blocks(g0);
     Stage sg = {gr[GS0], gr[GP1], a[A0]};
-    LAUNCH(k_cin_wgrad<SM_GADDUP>, dim3(nb), dim3(256), 0, s, x, alpha, sg, net->part, B, H, W);
-    STCHK(reduce(nb, 608, 608, 0));
+    LAUNCH((k_cin_wgrad<SM_GADDUP, KD>), dim3(nb, KD), dim3(256), 0, s, x, alpha, sg, net->part, g0);
+    STCHK(reduce(nb, P::CIN_PV, P::CIN_PV, 0));
   }
   return FL_OK;
 }
 
+static fl_status net_backward(fl_net net, const float* x, const float* alpha, int B, int D, int H, int W) {
+  const Dims g{B, D, H, W};
+  return net->kd == 3 ? net_backward_t<3>(net, x, alpha, g) : net_backward_t<1>(net, x, alpha, g);
+}
+
 static fl_status net_pack(fl_net net) {
-  LAUNCH(k_pack, dim3(nblocks_vec(NPACK * PACK)), dim3(256), 0, net->stream, (const float*)net->th, net->fw, net->bw);
+  if (net->kd == 3)
+    LAUNCH(k_pack<3>, dim3(nblocks_vec(NPACK * net->pack)), dim3(256), 0, net->stream, (const float*)net->th, net->fw,
+           net->bw);
+  else
+    LAUNCH(k_pack<1>, dim3(nblocks_vec(NPACK * net->pack)), dim3(256), 0, net->stream, (const float*)net->th, net->fw,
+           net->bw);
   return FL_OK;
 }
 
@@ -847,6 +930,21 @@ static fl_status alphas_to_device(fl_net net, const double* alpha, int B) {
   return FL_OK;
 }
 
+// The op's grid inside the padded network grid (each side rounded up to a
+// multiple of 8; D = 1 for 2D).
+static PadGrid pad_grid(fl_op op) {
+  PadGrid q;
+  if (op->d == 3) {
+    q = {op->n[0], op->n[1], op->n[2], 0, 0, 0};
+  } else {
+    q = {1, op->n[0], op->n[1], 0, 0, 0};
+  }
+  q.P0 = op->d == 3 ? (q.m0 + 7) / 8 * 8 : 1;
+  q.P1 = (q.m1 + 7) / 8 * 8;
+  q.P2 = (q.m2 + 7) / 8 * 8;
+  return q;
+}
+
 // ---------------------------------------------------------------------------
 // learned flexible CG (host-driven, FP64 reductions)
 // ---------------------------------------------------------------------------
@@ -854,13 +952,13 @@ static fl_status alphas_to_device(fl_net net, const double* alpha, int B) {
 // from the device value r.r in net->fs[4].
 template <typename T> static fl_status learned_prec(fl_op op, fl_net net, const Prob& pb) {
   hipStream_t s = op->stream;
-  const int n0 = op->n[0], n1 = op->n[1];
-  const int Hp = (n0 + 7) / 8 * 8, Wp = (n1 + 7) / 8 * 8;
-  LAUNCH(k_net_in<T>, dim3(nblocks_vec((long)Hp * Wp)), dim3(256), 0, s, (const T*)pb.r, net->pin, n0, n1, Hp, Wp,
+  const PadGrid q = pad_grid(op);
+  const long np = (long)q.P0 * q.P1 * q.P2;
+  LAUNCH(k_net_in<T>, dim3(nblocks_vec(np)), dim3(256), 0, s, (const T*)pb.r, net->pin, q,
          (const double*)(net->fs + 4));
-  STCHK(net_forward(net, net->pin, net->palpha, 1, Hp, Wp));
-  LAUNCH(k_net_out<T>, dim3(nblocks_vec(op->N)), dim3(256), 0, s, (const T*)pb.r, (const float*)net->y, (T*)net->pw,
-         n0, n1, Wp, (const double*)(net->fs + 4));
+  STCHK(net_forward(net, net->pin, net->palpha, 1, q.P0, q.P1, q.P2));
+  LAUNCH(k_net_out<T>, dim3(nblocks_vec(op->N)), dim3(256), 0, s, (const T*)pb.r, (const float*)net->y, (T*)net->pw, q,
+         (const double*)(net->fs + 4));
   Prob pz = pb;
   STCHK(set_precond<T>(op, pz, FL_PC_SPECTRAL));
   pz.in = net->pw;
@@ -971,13 +1069,15 @@ template fl_status learned_fcg<double>(fl_op, fl_net, const Prob&, double, int, 
 // scratch of the learned preconditioner on op's grid
 fl_status learned_prepare(fl_op op, fl_net net, size_t elem) {
   if (!net) return fail(FL_E_INVALID, "the learned preconditioner needs opts->net");
-  if (op->d != 2) return fail(FL_E_UNSUPPORTED, "the learned preconditioner is built for d = 2");
+  if (op->d != 2 && op->d != 3) return fail(FL_E_UNSUPPORTED, "the learned preconditioner is built for d = 2, 3");
+  if ((op->d == 3) != (net->kd == 3)) return fail(FL_E_INVALID, "the network and the op differ in dimension");
   if (net->stream != op->stream) return fail(FL_E_INVALID, "net and op must share one stream");
-  const int Hp = (op->n[0] + 7) / 8 * 8, Wp = (op->n[1] + 7) / 8 * 8;
-  STCHK(check_grid(1, Hp, Wp));
-  const long need = std::max<long>((long)Hp * Wp, op->N);
+  const PadGrid q = pad_grid(op);
+  const long np = (long)q.P0 * q.P1 * q.P2;
+  STCHK(check_grid(net, 1, q.P0, q.P1, q.P2));
+  const long need = std::max<long>(np, op->N);
   if (net->pcap < need) {
-    STCHK(net->alloc((void**)&net->pin, (size_t)Hp * Wp * sizeof(float)));
+    STCHK(net->alloc((void**)&net->pin, (size_t)np * sizeof(float)));
     STCHK(net->alloc(&net->pw, (size_t)op->N * sizeof(double)));
     net->pcap = need;
   }
@@ -988,8 +1088,34 @@ fl_status learned_prepare(fl_op op, fl_net net, size_t elem) {
   const float a = (float)op->alpha;
   HIPCHK(hipMemcpyAsync(net->palpha, &a, sizeof(float), hipMemcpyHostToDevice, op->stream));
   HIPCHK(hipStreamSynchronize(op->stream));
-  STCHK(net_reserve(net, 1, Hp, Wp));
+  STCHK(net_reserve(net, 1, q.P0, q.P1, q.P2));
   (void)elem;
+  return FL_OK;
+}
+
+// one profiled launch (fl_net_profile)
+template <int KD> static fl_status profile_one(fl_net net, int which, Dims g) {
+  using P = PL<KD>;
+  hipStream_t s = net->stream;
+  u16** a = net->act;
+  if (which == 0) return net_forward(net, net->xb, net->ab, g.B, g.D, g.H, g.W);
+  if (which == 1) {
+    Stage st = {a[A0], a[C1], nullptr};
+    LAUNCH((k_conv32<SM_UPADD, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st,
+           (const u16*)(net->fw + LU0 * P::PACK), (const float*)(net->th + P::OFF_L32 + LU0 * P::L32SZ + P::L32W),
+           a[C0], g, (float*)nullptr);
+    return FL_OK;
+  }
+  if (which == 2) {
+    Stage st = {nullptr, nullptr, nullptr, (const float*)net->xb, (const float*)net->ab};
+    LAUNCH((k_conv32<SM_INPUT, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st,
+           (const u16*)(net->fw + NL32 * P::PACK), (const float*)(net->th + P::OFF_CIN_B), a[A0], g, (float*)nullptr);
+    return FL_OK;
+  }
+  Stage st = {a[C0], nullptr, nullptr};
+  LAUNCH((k_conv32<SM_PLAIN, EPI_OUT, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st,
+         (const u16*)(net->fw + (NL32 + 1) * P::PACK), (const float*)(net->th + P::OFF_OUT + P::K * CH),
+         (u16*)nullptr, g, net->y);
   return FL_OK;
 }
 
@@ -998,22 +1124,26 @@ fl_status learned_prepare(fl_op op, fl_net net, size_t elem) {
 // ---------------------------------------------------------------------------
 extern "C" {
 
-fl_status fl_net_create(void* hip_stream, fl_net* out) {
+fl_status fl_net_create(int d, void* hip_stream, fl_net* out) {
   if (!out) return fail(FL_E_INVALID, "out is NULL");
   *out = nullptr;
+  if (d != 2 && d != 3) return fail(FL_E_INVALID, "d must be 2 or 3");
   fl_net net = new fl_net_s();
   net->stream = (hipStream_t)hip_stream;
+  net->kd = d == 3 ? 3 : 1;
+  net->nparam = d == 3 ? PL<3>::NPARAM : PL<1>::NPARAM;
+  net->pack = d == 3 ? PL<3>::PACK : PL<1>::PACK;
   fl_status st = FL_OK;
   for (float** p : {&net->th, &net->g, &net->m, &net->v})
-    if (st == FL_OK) st = net->alloc((void**)p, NPARAM * sizeof(float));
-  if (st == FL_OK) st = net->alloc((void**)&net->fw, NPACK * PACK * sizeof(u16));
-  if (st == FL_OK) st = net->alloc((void**)&net->bw, NL32 * PACK * sizeof(u16));
+    if (st == FL_OK) st = net->alloc((void**)p, net->nparam * sizeof(float));
+  if (st == FL_OK) st = net->alloc((void**)&net->fw, NPACK * net->pack * sizeof(u16));
+  if (st == FL_OK) st = net->alloc((void**)&net->bw, NL32 * net->pack * sizeof(u16));
   if (st != FL_OK) {
     delete net;
     return st;
   }
   for (float* p : {net->th, net->m, net->v})
-    if (hipMemsetAsync(p, 0, NPARAM * sizeof(float), net->stream) != hipSuccess) {
+    if (hipMemsetAsync(p, 0, net->nparam * sizeof(float), net->stream) != hipSuccess) {
       delete net;
       return fail(FL_E_HIP, "clearing the parameters failed");
     }
@@ -1025,13 +1155,13 @@ fl_status fl_net_create(void* hip_stream, fl_net* out) {
   return FL_OK;
 }
 
-int64_t fl_net_nparams(void) { return NPARAM; }
+int64_t fl_net_nparams(int d) { return d == 3 ? PL<3>::NPARAM : d == 2 ? PL<1>::NPARAM : 0; }
 
 fl_status fl_net_set_params(fl_net net, const float* params) {
   if (!net || !params) return fail(FL_E_INVALID, "NULL argument");
-  HIPCHK(hipMemcpyAsync(net->th, params, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, net->stream));
-  HIPCHK(hipMemsetAsync(net->m, 0, NPARAM * sizeof(float), net->stream));
-  HIPCHK(hipMemsetAsync(net->v, 0, NPARAM * sizeof(float), net->stream));
+  HIPCHK(hipMemcpyAsync(net->th, params, net->nparam * sizeof(float), hipMemcpyDeviceToDevice, net->stream));
+  HIPCHK(hipMemsetAsync(net->m, 0, net->nparam * sizeof(float), net->stream));
+  HIPCHK(hipMemsetAsync(net->v, 0, net->nparam * sizeof(float), net->stream));
   net->step = 0;
   STCHK(net_pack(net));
   HIPCHK(hipStreamSynchronize(net->stream));
@@ -1040,45 +1170,45 @@ fl_status fl_net_set_params(fl_net net, const float* params) {
 
 fl_status fl_net_get_params(fl_net net, float* params) {
   if (!net || !params) return fail(FL_E_INVALID, "NULL argument");
-  HIPCHK(hipMemcpyAsync(params, net->th, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, net->stream));
+  HIPCHK(hipMemcpyAsync(params, net->th, net->nparam * sizeof(float), hipMemcpyDeviceToDevice, net->stream));
   HIPCHK(hipStreamSynchronize(net->stream));
   return FL_OK;
 }
 
-fl_status fl_net_forward(fl_net net, const float* x, const double* alpha, float* y, int batch, int H, int W) {
+fl_status fl_net_forward(fl_net net, const float* x, const double* alpha, float* y, int batch, int D, int H, int W) {
   if (!net || !x || !alpha || !y) return fail(FL_E_INVALID, "NULL argument");
-  STCHK(check_grid(batch, H, W));
+  STCHK(check_grid(net, batch, D, H, W));
   STCHK(alphas_to_device(net, alpha, batch));
-  STCHK(net_forward(net, x, net->ab, batch, H, W));
-  HIPCHK(hipMemcpyAsync(y, net->y, (size_t)batch * H * W * sizeof(float), hipMemcpyDeviceToDevice, net->stream));
+  STCHK(net_forward(net, x, net->ab, batch, D, H, W));
+  HIPCHK(hipMemcpyAsync(y, net->y, (size_t)batch * D * H * W * sizeof(float), hipMemcpyDeviceToDevice, net->stream));
   HIPCHK(hipStreamSynchronize(net->stream));
   return FL_OK;
 }
 
-fl_status fl_net_grad(fl_net net, const float* x, const double* alpha, const float* gy, float* grad, int batch, int H,
-                      int W) {
+fl_status fl_net_grad(fl_net net, const float* x, const double* alpha, const float* gy, float* grad, int batch, int D,
+                      int H, int W) {
   if (!net || !x || !alpha || !gy || !grad) return fail(FL_E_INVALID, "NULL argument");
-  STCHK(check_grid(batch, H, W));
+  STCHK(check_grid(net, batch, D, H, W));
   STCHK(alphas_to_device(net, alpha, batch));
-  STCHK(net_forward(net, x, net->ab, batch, H, W));
-  HIPCHK(hipMemcpyAsync(net->gy, gy, (size_t)batch * H * W * sizeof(float), hipMemcpyDeviceToDevice, net->stream));
-  STCHK(net_backward(net, x, net->ab, batch, H, W));
-  HIPCHK(hipMemcpyAsync(grad, net->g, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, net->stream));
+  STCHK(net_forward(net, x, net->ab, batch, D, H, W));
+  HIPCHK(hipMemcpyAsync(net->gy, gy, (size_t)batch * D * H * W * sizeof(float), hipMemcpyDeviceToDevice, net->stream));
+  STCHK(net_backward(net, x, net->ab, batch, D, H, W));
+  HIPCHK(hipMemcpyAsync(grad, net->g, net->nparam * sizeof(float), hipMemcpyDeviceToDevice, net->stream));
   HIPCHK(hipStreamSynchronize(net->stream));
   return FL_OK;
 }
 
-fl_status fl_net_train(fl_net net, const float* R, const float* T, const float* A, int npairs, int H, int W,
+fl_status fl_net_train(fl_net net, const float* R, const float* T, const float* A, int npairs, int D, int H, int W,
                        const int* idx, int steps, int batch, double lr, float* losses) {
   if (!net || !R || !T || !A || !idx || !losses) return fail(FL_E_INVALID, "NULL argument");
   if (npairs < 1 || steps < 0 || !(lr > 0.0)) return fail(FL_E_INVALID, "npairs, steps or lr");
-  STCHK(check_grid(batch, H, W));
+  STCHK(check_grid(net, batch, D, H, W));
   for (long i = 0; i < (long)steps * batch; ++i)
     if (idx[i] < 0 || idx[i] >= npairs) return fail(FL_E_INVALID, "minibatch index out of range");
   hipStream_t s = net->stream;
-  STCHK(net_reserve(net, batch, H, W));
+  STCHK(net_reserve(net, batch, D, H, W));
   STCHK(net_alphas(net, batch));
-  const long npix = (long)H * W, n = (long)batch * npix;
+  const long npix = (long)D * H * W, n = (long)batch * npix;
   if (net->idx_cap < steps * batch) {
     STCHK(net->alloc((void**)&net->idx, (size_t)std::max(1, steps * batch) * sizeof(int)));
     net->idx_cap = steps * batch;
@@ -1094,16 +1224,16 @@ fl_status fl_net_train(fl_net net, const float* R, const float* T, const float* 
   for (int k = 0; k < steps; ++k) {
     LAUNCH(k_gather, dim3(nblocks_vec(n)), dim3(256), 0, s, R, T, A, (const int*)net->idx + (long)k * batch, net->xb,
            net->tb, net->ab, batch, npix);
-    STCHK(net_forward(net, net->xb, net->ab, batch, H, W));
+    STCHK(net_forward(net, net->xb, net->ab, batch, D, H, W));
     LAUNCH(k_loss, dim3(lblk), dim3(256), 0, s, (const float*)net->y, (const float*)net->tb, net->gy, net->lpart, n,
            1.0 / (double)n);
     LAUNCH(k_sum_to, dim3(1), dim3(1), 0, s, (const double*)net->lpart, lblk, net->losses + k);
-    STCHK(net_backward(net, net->xb, net->ab, batch, H, W));
+    STCHK(net_backward(net, net->xb, net->ab, batch, D, H, W));
     ++net->step;
     const double c1 = 1.0 / (1.0 - std::pow((double)b1, net->step));
     const double c2 = 1.0 / (1.0 - std::pow((double)b2, net->step));
-    LAUNCH(k_adam, dim3(nblocks_vec(NPARAM)), dim3(256), 0, s, net->th, (const float*)net->g, net->m, net->v, NPARAM,
-           (float)lr, b1, b2, 1e-8f, (float)c1, (float)c2);
+    LAUNCH(k_adam, dim3(nblocks_vec(net->nparam)), dim3(256), 0, s, net->th, (const float*)net->g, net->m, net->v,
+           net->nparam, (float)lr, b1, b2, 1e-8f, (float)c1, (float)c2);
     STCHK(net_pack(net));
   }
   HIPCHK(hipMemcpyAsync(losses, net->losses, (size_t)steps * sizeof(float), hipMemcpyDeviceToHost, s));
@@ -1112,11 +1242,17 @@ fl_status fl_net_train(fl_net net, const float* R, const float* T, const float* 
 }
 
 fl_status fl_learned_pairs(fl_op op, const double* e, int64_t e_stride, const double* e_sub, int count, float* R,
-                           float* T, int Hp, int Wp) {
+                           float* T, int Dp, int Hp, int Wp) {
   if (!op || !e || !R || !T) return fail(FL_E_INVALID, "NULL argument");
   if (e_stride != 0 && e_stride != op->N) return fail(FL_E_INVALID, "e_stride must be 0 or the grid size");
-  if (op->d != 2) return fail(FL_E_UNSUPPORTED, "training pairs are built for d = 2");
-  if (count < 1 || Hp < op->n[0] || Wp < op->n[1]) return fail(FL_E_INVALID, "count or padded grid");
+  if (op->d != 2 && op->d != 3) return fail(FL_E_UNSUPPORTED, "training pairs are built for d = 2, 3");
+  PadGrid q = pad_grid(op);
+  q.P0 = Dp;
+  q.P1 = Hp;
+  q.P2 = Wp;
+  if (count < 1 || Dp < q.m0 || Hp < q.m1 || Wp < q.m2 || (op->d == 2 && Dp != 1))
+    return fail(FL_E_INVALID, "count or padded grid");
+  const long np = (long)Dp * Hp * Wp;
   hipStream_t s = op->stream;
   const long N = op->N;
   STCHK(ensure_ws<double>(op, 1, true));
@@ -1141,47 +1277,26 @@ fl_status fl_learned_pairs(fl_op op, const double* e, int64_t e_stride, const do
     pd.out = w.q;
     STCHK((precond_seq<double, DPRO_PLAIN, DEPI_FINAL>(op, pd, Iter{0, 0}, 0)));
     STCHK(dot_to<double>(op, pb, w.r, w.r, &pb.sc->rr));
-    LAUNCH(k_pair_out, dim3(nblocks_vec((long)Hp * Wp)), dim3(256), 0, s, (const double*)w.r, (const double*)w.q,
-           R + (long)k * Hp * Wp, T + (long)k * Hp * Wp, op->n[0], op->n[1], Hp, Wp,
-           (const double*)&pb.sc->rr);
+    LAUNCH(k_pair_out, dim3(nblocks_vec(np)), dim3(256), 0, s, (const double*)w.r, (const double*)w.q, R + (long)k * np,
+           T + (long)k * np, q, (const double*)&pb.sc->rr);
   }
   HIPCHK(hipStreamSynchronize(s));
   return FL_OK;
 }
 
-fl_status fl_net_profile(fl_net net, int which, int H, int W, int reps, double* avg_ms) {
+fl_status fl_net_profile(fl_net net, int which, int D, int H, int W, int reps, double* avg_ms) {
   if (!net || !avg_ms || reps < 1) return fail(FL_E_INVALID, "NULL argument or reps < 1");
   if (which < 0 || which > 3) return fail(FL_E_INVALID, "which must be 0..3");
-  STCHK(check_grid(1, H, W));
-  STCHK(net_reserve(net, 1, H, W));
+  STCHK(check_grid(net, 1, D, H, W));
+  STCHK(net_reserve(net, 1, D, H, W));
   STCHK(net_alphas(net, 1));
   hipStream_t s = net->stream;
-  const long px = (long)H * W;
+  const long px = (long)D * H * W;
   LAUNCH(k_fill<float>, dim3(nblocks_vec(px)), dim3(256), 0, s, net->xb, 0.5f, px);
   LAUNCH(k_fill<float>, dim3(1), dim3(256), 0, s, net->ab, 1.0f, 1L);
-  STCHK(net_forward(net, net->xb, net->ab, 1, H, W));
-  auto one = [&]() -> fl_status {
-    u16** a = net->act;
-    if (which == 0) return net_forward(net, net->xb, net->ab, 1, H, W);
-    if (which == 1) {
-      Stage st = {a[A0], a[C1], nullptr};
-      LAUNCH((k_conv32<SM_UPADD, EPI_RELU>), dim3(conv_blocks(1, H, W)), dim3(256), 0, s, st,
-             (const u16*)(net->fw + LU0 * PACK), (const float*)(net->th + OFF_L32 + LU0 * L32SZ + L32W), a[C0], 1, H, W,
-             (float*)nullptr);
-      return FL_OK;
-    }
-    if (which == 2) {
-      Stage st = {nullptr, nullptr, nullptr, (const float*)net->xb, (const float*)net->ab};
-      LAUNCH((k_conv32<SM_INPUT, EPI_RELU>), dim3(conv_blocks(1, H, W)), dim3(256), 0, s, st,
-             (const u16*)(net->fw + NL32 * PACK), (const float*)(net->th + OFF_CIN_B), a[A0], 1, H, W, (float*)nullptr);
-      return FL_OK;
-    }
-    Stage st = {a[C0], nullptr, nullptr};
-    LAUNCH((k_conv32<SM_PLAIN, EPI_OUT>), dim3(conv_blocks(1, H, W)), dim3(256), 0, s, st,
-           (const u16*)(net->fw + (NL32 + 1) * PACK), (const float*)(net->th + OFF_OUT + 9 * CH), (u16*)nullptr, 1, H, W,
-           net->y);
-    return FL_OK;
-  };
+  STCHK(net_forward(net, net->xb, net->ab, 1, D, H, W));
+  const Dims g{1, D, H, W};
+  auto one = [&]() { return net->kd == 3 ? profile_one<3>(net, which, g) : profile_one<1>(net, which, g); };
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

@@ -14,14 +14,16 @@ import torch
 from . import (FL_PC_SPECTRAL, Net, Op, learned_pairs, solve_opts)
 
 
-def init_params(seed=0):
-    """He-uniform weights, zero biases, output layer scaled by 0.1 (seeded host draw)."""
+def init_params(seed=0, d=2):
+    """He-uniform weights, zero biases, output layer scaled by 0.1 (seeded host draw);
+    3^d taps per kernel."""
     rng = np.random.Generator(np.random.PCG64(seed))
     layers = [("cin", 2, 32)] + [(k, 32, 32) for k in ("d1", "d2", "d3", "b3", "u2", "u1", "u0")] + [("out", 32, 1)]
+    K = 3 ** d
     parts = []
     for name, ci, co in layers:
-        lim = np.sqrt(6.0 / (9 * ci))
-        w = rng.uniform(-lim, lim, size=(9, ci, co))
+        lim = np.sqrt(6.0 / (K * ci))
+        w = rng.uniform(-lim, lim, size=(K, ci, co))
         if name == "out":
             w *= 0.1
         parts += [w.ravel(), np.zeros(co)]
@@ -30,14 +32,14 @@ def init_params(seed=0):
 
 def make_pairs(plan, iters=10, fields=10, stream=None, log=None):
     """Training set (R, T, A) on the device from a list of problems
-    ({"n", "alpha", "rhs_seed", "field_seed"}), all on one n x n grid."""
+    ({"n", "alpha", "rhs_seed", "field_seed"}, "d" 2 or 3), all on one n^d grid."""
     from workloads import bump_field, power_law_field
     stream = stream or torch.cuda.Stream()
     Rs, Ts, As = [], [], []
     for i, pr in enumerate(plan):
-        n, alpha = pr["n"], pr["alpha"]
-        f_np, h = bump_field(n, 2, 32, pr["rhs_seed"], width=(0.05, 0.2))
-        op = Op(2, alpha, h, (n, n), stream=stream)
+        n, alpha, d = pr["n"], pr["alpha"], pr.get("d", 2)
+        f_np, h = bump_field(n, d, 32 if d == 2 else 16, pr["rhs_seed"], width=(0.05, 0.2))
+        op = Op(d, alpha, h, (n,) * d, stream=stream)
         f = torch.from_numpy(f_np).cuda()
         xs, info = op.solve(f, tol=1e-12, opts=solve_opts(pc=FL_PC_SPECTRAL))
         # iterates strictly before the converged one (x_k of the same solve with
@@ -54,7 +56,7 @@ def make_pairs(plan, iters=10, fields=10, stream=None, log=None):
             Ts.append(T)
             As += [alpha] * nit
         if fields > 0:
-            e = np.stack([power_law_field((n, n), pr["field_seed"] + j) for j in range(fields)])
+            e = np.stack([power_law_field((n,) * d, pr["field_seed"] + j) for j in range(fields)])
             R, T = learned_pairs(op, torch.from_numpy(e).cuda())
             Rs.append(R)
             Ts.append(T)
@@ -68,8 +70,10 @@ def make_pairs(plan, iters=10, fields=10, stream=None, log=None):
 
 def train(R, T, A, steps=2000, batch=16, lr=1e-3, seed=0, params=None, stream=None, lr_decay_at=0.7):
     """Train a Net on the pairs (minibatch indices drawn on the host from a
-    seeded generator); lr drops 10x after `lr_decay_at` of the steps."""
-    net = Net(stream=stream, params=init_params(seed) if params is None else params)
+    seeded generator); lr drops 10x after `lr_decay_at` of the steps.  The
+    network's dimension follows the pairs: R [npairs, H, W] or [npairs, D, H, W]."""
+    d = R.dim() - 1
+    net = Net(stream=stream, params=init_params(seed, d) if params is None else params, d=d)
     rng = np.random.Generator(np.random.PCG64(seed + 1))
     idx = rng.integers(0, R.shape[0], size=(steps, batch))
     k1 = int(steps * lr_decay_at)

@@ -97,11 +97,11 @@ def power_law_field(shape, seed, slope=(0.0, 3.0)):
     return np.ascontiguousarray(f / np.linalg.norm(f))
 
 
-def learned_training_plan(nalpha=100, n=256, seed=5000, lo=0.2, hi=1.9):
+def learned_training_plan(nalpha=100, n=256, seed=5000, lo=0.2, hi=1.9, d=2):
     """Problems of the learned-preconditioner training set: alpha ~ U[lo, hi]
-    on an n x n grid of (-1,1)^2, each with a bump right-hand side (32 bumps,
-    C2's distributions) and random-field seeds."""
+    on an n^d grid of (-1,1)^d, each with a bump right-hand side (32 bumps in
+    2D with C2's distributions, 16 in 3D with C3's) and random-field seeds."""
     rng = np.random.Generator(np.random.PCG64(seed))
     alphas = rng.uniform(lo, hi, size=nalpha)
-    return [{"n": n, "alpha": float(a), "rhs_seed": seed + 1 + i, "field_seed": seed + 100000 + 1000 * i}
+    return [{"n": n, "d": d, "alpha": float(a), "rhs_seed": seed + 1 + i, "field_seed": seed + 100000 + 1000 * i}
             for i, a in enumerate(alphas)]
