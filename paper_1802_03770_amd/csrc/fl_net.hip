@@ -82,21 +82,17 @@ __device__ __forceinline__ uint4 pk8(const float v[8]) {
 // ---------------------------------------------------------------------------
 // Staging of a convolution input (8 channels of one in-bounds pixel)
 // ---------------------------------------------------------------------------
-enum { SM_PLAIN = 0, SM_POOL, SM_UPADD, SM_GPLAIN, SM_GSUMPOOL, SM_GADDUP, SM_INPUT };
+enum { SM_PLAIN = 0, SM_POOL, SM_UPADD, SM_GPLAIN, SM_GSUMPOOL, SM_GADDUP };
 //  PLAIN    s0[p]                                  (this level)
 //  POOL     mean of s0 over the 2 x 2 (x 2) block  (s0 at the finer level)
 //  UPADD    s0[p] + s1[p/2]                        (s1 at the coarser level)
 //  GPLAIN   s0[p] * (y[p] > 0)                     (gradient through a ReLU)
 //  GSUMPOOL sum of s0 over the block * (y[p] > 0)
 //  GADDUP   (s0[p] + s1[p/2] / 2^d) * (y[p] > 0)
-//  INPUT    channels (x[p], alpha_b - 1, 0, ..., 0): the input layer as a
-//           32 -> 32 convolution whose weights vanish beyond input channel 1
 struct Stage {
   const u16* s0;
   const u16* s1;
   const u16* y;
-  const float* xf = nullptr;  // SM_INPUT: network input x, FP32 [B][D][H][W]
-  const float* al = nullptr;  // SM_INPUT: alpha per image
 };
 
 // Grid of one level: D = 1 for 2D networks.
@@ -117,15 +113,6 @@ template <int KD> __device__ __forceinline__ Dims coarser(const Dims& g) {
 template <int SM, int KD>
 __device__ __forceinline__ void stage8(const Stage& st, const Dims& g, int b, int z, int y, int x, int c, float v[8]) {
   constexpr int NB = KD == 3 ? 8 : 4;  // pixels per pooling block
-  if constexpr (SM == SM_INPUT) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = 0.f;
-    if (c == 0) {
-      v[0] = st.xf[(((long)b * g.D + z) * g.H + y) * g.W + x];
-      v[1] = st.al[b] - 1.f;
-    }
-    return;
-  }
   if (SM == SM_PLAIN) {
     ld8(st.s0 + pix(g, b, z, y, x) + c, v);
   } else if (SM == SM_POOL || SM == SM_GSUMPOOL) {
@@ -265,13 +252,52 @@ __device__ __forceinline__ void tile_of(long t, const Dims& g, int& b, int& z, i
 // 32 -> 32 convolution on MFMA (forward with bias + ReLU, or the transposed
 // convolution of the reverse pass with flipped, transposed weights)
 // ---------------------------------------------------------------------------
-// EPI_RELU: bias + ReLU, BF16 out; EPI_NONE: BF16 out; EPI_OUT: the output
-// layer, output channel 0 only, FP32 into yout ([B][D][H][W]).
-enum { EPI_RELU = 0, EPI_NONE = 1, EPI_OUT = 2 };
+// EPI_RELU: bias + ReLU, BF16 out; EPI_NONE: BF16 out.
+enum { EPI_RELU = 0, EPI_NONE = 1 };
+
+// Output tile of a 32-channel layer: lane holds pixel (lane & 31) of each
+// 32-pixel half of its wave's row, channels q*8 + (lane>>5)*4 + 0..3 in
+// acc[4q .. 4q+3].  The wave's 64 x 32 outputs go through LDS (`tile`, free
+// once every wave has passed a barrier after its last read) so that the
+// global stores are contiguous 16-byte chunks.
+template <int EPI>
+__device__ __forceinline__ void store_rows(const f32x16& acc0, const f32x16& acc1, u16* tile,
+                                           const float* __restrict__ bias, u16* __restrict__ out, const Dims& g, int b,
+                                           int z, int y0, int x0) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  u16* ot = tile + wave * 64 * CH;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const f32x16& a = m ? acc1 : acc0;
+    const int pl = m * 32 + (lane & 31);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int cb = q * 8 + (lane >> 5) * 4;
+      float v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        v[i] = a[4 * q + i];
+        if (EPI == EPI_RELU) v[i] = fmaxf(v[i] + bias[cb + i], 0.f);
+      }
+      const unsigned lo = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+      const unsigned hi = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+      *(uint2*)(ot + pl * CH + cb) = make_uint2(lo, hi);
+    }
+  }
+  __syncthreads();
+  const int yo = y0 + wave;
+  if (yo >= g.H) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = lane + 64 * k, pl = e >> 2, qq = (e & 3) * 8;
+    const int px = x0 + pl;
+    if (px < g.W) *(uint4*)(out + pix(g, b, z, yo, px) + qq) = *(const uint4*)(ot + pl * CH + qq);
+  }
+}
 
 template <int SM, int EPI, int KD>
 __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict__ wpack, const float* __restrict__ bias,
-                                                u16* __restrict__ out, Dims g, float* __restrict__ yout) {
+                                                u16* __restrict__ out, Dims g) {
   __shared__ __align__(16) u16 tile[SY * SX * CH];
   int b, z, y0, x0;
   tile_of(blockIdx.x, g, b, z, y0, x0);
@@ -304,49 +330,124 @@ __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict_
       }
     }
   }
-  // lane holds pixel (lane & 31) of each 32-pixel half, channels
-  // g*8 + (lane>>5)*4 + 0..3 in acc[4g .. 4g+3]
-  if constexpr (EPI == EPI_OUT) {  // channel 0 sits in acc[0] of lanes 0..31
-    const int yo = y0 + wave;
-    if (lane < 32 && yo < g.H) {
-      const long row = (((long)b * g.D + z) * g.H + yo) * g.W;
-      const int px0 = x0 + lane, px1 = x0 + 32 + lane;
-      if (px0 < g.W) yout[row + px0] = acc0[0] + bias[0];
-      if (px1 < g.W) yout[row + px1] = acc1[0] + bias[0];
-    }
-    return;
-  }
-  // the wave's 64 x 32 outputs go through LDS so that the global stores are
-  // contiguous 16-byte chunks
   __syncthreads();  // every wave is done reading the staged tile
-  u16* ot = tile + wave * 64 * CH;
+  store_rows<EPI>(acc0, acc1, tile, bias, out, g, b, z, y0, x0);
+}
+
+// Input layer (2 -> 32) on MFMA with (tap, input channel) packed into K:
+// k = 2 tap + ci runs over the 2K values of the stencil, padded to a multiple
+// of 16 (2 MFMA steps in 2D, 4 in 3D).  The A fragments (slot NL32 of the
+// packed weights) hold W^T[co][k]; each lane gathers its B fragment
+// X[k][pixel] from the staged (x, alpha - 1) slices.  Bias + ReLU, BF16 out.
+template <int KD>
+__global__ __launch_bounds__(256) void k_cin_mfma(const float* __restrict__ x, const float* __restrict__ alpha,
+                                                  const u16* __restrict__ wpack, const float* __restrict__ bias,
+                                                  u16* __restrict__ out, Dims g) {
+  constexpr int K = 9 * KD, S = (2 * K + 15) / 16;
+  __shared__ __align__(16) u16 tile[SY * SX * CH];  // output staging
+  __shared__ unsigned xin[KD][SY * SX];             // bf16 pair (x, alpha - 1) per pixel
+  int b, z, y0, x0;
+  tile_of(blockIdx.x, g, b, z, y0, x0);
+  if (b >= g.B) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const unsigned am1 = (unsigned)f2bf(alpha[b] - 1.f) << 16;
+  for (int e = threadIdx.x; e < KD * SY * SX; e += blockDim.x) {
+    const int kz = e / (SY * SX), p = e % (SY * SX);
+    const int zi = z + kz - (KD == 3 ? 1 : 0), yy = y0 + p / SX - 1, xx = x0 + p % SX - 1;
+    const bool in = zi >= 0 && zi < g.D && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W;
+    xin[kz][p] = in ? ((unsigned)f2bf(x[(((long)b * g.D + zi) * g.H + yy) * g.W + xx]) | am1) : 0u;
+  }
+  bf16x8 wf[S];
 #pragma unroll
-  for (int m = 0; m < 2; ++m) {
-    const f32x16& a = m ? acc1 : acc0;
-    const int pl = m * 32 + (lane & 31);
+  for (int st = 0; st < S; ++st) wf[st] = *(const bf16x8*)(wpack + ((long)st * 64 + lane) * 8);
+  __syncthreads();
+  f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int cb = q * 8 + (lane >> 5) * 4;
-      float v[4];
+  for (int st = 0; st < S; ++st) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int px = h * 32 + (lane & 31);
+      unsigned w[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        v[i] = a[4 * q + i];
-        if (EPI == EPI_RELU) v[i] = fmaxf(v[i] + bias[cb + i], 0.f);
+        unsigned v2[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int k = st * 16 + 8 * (lane >> 5) + 2 * i + j;
+          v2[j] = 0;
+          if (k < 2 * K) {
+            const int tap = k >> 1, kz = tap / 9, ky = (tap % 9) / 3, kx = tap % 3;
+            const unsigned pr = xin[kz][(wave + ky) * SX + px + kx];
+            v2[j] = (k & 1) ? (pr >> 16) : (pr & 0xffffu);
+          }
+        }
+        w[i] = v2[0] | (v2[1] << 16);
       }
-      const unsigned lo = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
-      const unsigned hi = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
-      *(uint2*)(ot + pl * CH + cb) = make_uint2(lo, hi);
+      const bf16x8 bfr = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+      if (h == 0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[st], bfr, acc0, 0, 0, 0);
+      else acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[st], bfr, acc1, 0, 0, 0);
     }
   }
-  __syncthreads();
-  const int yo = y0 + wave;
-  if (yo >= g.H) return;
+  store_rows<EPI_RELU>(acc0, acc1, tile, bias, out, g, b, z, y0, x0);
+}
+
+// Output layer (32 -> 1): per slice, Z[q][m] = sum_ci c0[q][ci] W[9 kz + m][ci]
+// for every pixel q of the staged halo tile and the nine in-plane taps m, on
+// MFMA with the taps as rows (slot NL32 + 1 of the packed weights: fragment
+// 2 kz + s holds W[9 kz + m][16 s + ...] in row m < 9); then each thread sums
+// y[p] += sum_m Z[p + offset(m)][m] for its output pixel.  FP32 out.
+template <int KD>
+__global__ __launch_bounds__(256) void k_out_mfma(const u16* __restrict__ c0, const u16* __restrict__ wpack,
+                                                  const float* __restrict__ bias, Dims g, float* __restrict__ yout) {
+  constexpr int NQ = SY * SX, NCH = (NQ + 31) / 32;
+  __shared__ __align__(16) u16 tile[SY * SX * CH];
+  __shared__ float zt[NQ][9];
+  int b, z, y0, x0;
+  tile_of(blockIdx.x, g, b, z, y0, x0);
+  if (b >= g.B) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ly = threadIdx.x / TX, lx = threadIdx.x % TX;  // this thread's output pixel
+  const Stage st = {c0, nullptr, nullptr};
+  float yacc = 0.f;
+#pragma unroll 1
+  for (int kz = 0; kz < KD; ++kz) {
+    const int zi = z + kz - (KD == 3 ? 1 : 0);
+    if (zi < 0 || zi >= g.D) continue;  // zero slice (uniform over the block)
+    if (kz > 0) __syncthreads();         // every thread is done with the previous slice
+    stage_tile_batched<SM_PLAIN, KD>(tile, st, g, b, zi, y0, x0);
+    const bf16x8 a0 = *(const bf16x8*)(wpack + ((long)(kz * 2) * 64 + lane) * 8);
+    const bf16x8 a1 = *(const bf16x8*)(wpack + ((long)(kz * 2 + 1) * 64 + lane) * 8);
+    __syncthreads();
+    for (int ch = wave; ch < NCH; ch += 4) {
+      const int q = ch * 32 + (lane & 31);
+      bf16x8 b0 = {}, b1 = {};
+      if (q < NQ) {
+        const u16* p0 = tile + q * CH + (lane >> 5) * 8;
+        b0 = *(const bf16x8*)p0;
+        b1 = *(const bf16x8*)(p0 + 16);
+      }
+      f32x16 d = {};
+      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, d, 0, 0, 0);
+      // rows (taps) of lane l: 8 (r/4) + 4 (l/32) + r%4 -> lanes < 32 hold
+      // m = 0..3 (r = 0..3) and 8 (r = 4); lanes >= 32 hold m = 4..7
+      if (q < NQ) {
+        if (lane < 32) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int e = lane + 64 * k, pl = e >> 2, qq = (e & 3) * 8;
-    const int px = x0 + pl;
-    if (px < g.W) *(uint4*)(out + pix(g, b, z, yo, px) + qq) = *(const uint4*)(ot + pl * CH + qq);
+          for (int r = 0; r < 4; ++r) zt[q][r] = d[r];
+          zt[q][8] = d[4];
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) zt[q][4 + r] = d[r];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 9; ++m) yacc += zt[(ly + m / 3) * SX + lx + m % 3][m];
   }
+  const int yo = y0 + ly, xo = x0 + lx;
+  if (yo < g.H && xo < g.W) yout[(((long)b * g.D + z) * g.H + yo) * g.W + xo] = yacc + bias[0];
 }
 
 // Stage the gradient G of the output slice z (TY x TX pixels, no halo).
@@ -551,9 +652,9 @@ __global__ void k_reduce_part(const float* __restrict__ part, int nblk, int stri
 // fw[L][tap][half][lane][e] = W_L[tap][half*16 + 8*(lane/32) + e][lane%32].
 // Transposed flipped (reverse pass): bw[L][tap][half][lane][e] =
 // W_L[K-1-tap][lane%32][half*16 + 8*(lane/32) + e] (reversing the tap index
-// reverses every offset).  Slots L = 7 and 8 of fw hold the input layer
-// (input channels >= 2 zero) and the output layer (output channels >= 1 zero)
-// in the same form.
+// reverses every offset).  Slot L = 7 of fw holds the input layer with
+// (tap, ci) packed into K (k_cin_mfma), slot 8 the output layer with the
+// in-plane taps as rows (k_out_mfma).
 constexpr int NPACK = NL32 + 2;
 template <int KD> __global__ void k_pack(const float* __restrict__ th, u16* __restrict__ fw, u16* __restrict__ bw) {
   using P = PL<KD>;
@@ -568,10 +669,12 @@ template <int KD> __global__ void k_pack(const float* __restrict__ th, u16* __re
     const float* W = th + P::OFF_L32 + L * P::L32SZ;
     fw[idx] = f2bf(W[((long)tap * CH + kk) * CH + j]);
     bw[idx] = f2bf(W[((long)(P::K - 1 - tap) * CH + j) * CH + kk]);
-  } else if (L == NL32) {
-    fw[idx] = kk < 2 ? f2bf(th[(tap * 2 + kk) * CH + j]) : (u16)0;
-  } else {
-    fw[idx] = j == 0 ? f2bf(th[P::OFF_OUT + tap * CH + kk]) : (u16)0;
+  } else if (L == NL32) {  // input layer, K-packed: fragment f = step, k = 16 f + ... = 2 tap + ci
+    const int k = f * 16 + 8 * (lane >> 5) + e;
+    fw[idx] = k < 2 * P::K ? f2bf(th[(long)k * CH + j]) : (u16)0;
+  } else {  // output layer, taps as rows: fragment f = 2 kz + s, row m = lane % 32, k = ci
+    const int kz = f >> 1, m = lane & 31, ci = (f & 1) * 16 + 8 * (lane >> 5) + e;
+    fw[idx] = (kz < KD && m < 9) ? f2bf(th[P::OFF_OUT + (long)(kz * 9 + m) * CH + ci]) : (u16)0;
   }
 }
 
@@ -803,11 +906,7 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
   auto fw = [&](int L) { return (const u16*)(net->fw + L * P::PACK); };
   auto half = [](Dims g) { return Dims{g.B, KD == 3 ? g.D / 2 : 1, g.H / 2, g.W / 2}; };
   auto dbl = [](Dims g) { return Dims{g.B, KD == 3 ? g.D * 2 : 1, g.H * 2, g.W * 2}; };
-  {
-    Stage st = {nullptr, nullptr, nullptr, x, alpha};
-    LAUNCH((k_conv32<SM_INPUT, EPI_RELU, KD>), dim3(conv_blocks(g0)), dim3(256), 0, s, st, fw(NL32),
-           th + P::OFF_CIN_B, a[A0], g0, (float*)nullptr);
-  }
+  LAUNCH(k_cin_mfma<KD>, dim3(conv_blocks(g0)), dim3(256), 0, s, x, alpha, fw(NL32), th + P::OFF_CIN_B, a[A0], g0);
   Dims g = g0;
   // down path
   const int lay[3] = {LD1, LD2, LD3};
@@ -815,12 +914,12 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
     g = half(g);
     Stage st = {a[A0 + l - 1], nullptr, nullptr};
     LAUNCH((k_conv32<SM_POOL, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(lay[l - 1]),
-           bias(lay[l - 1]), a[A0 + l], g, (float*)nullptr);
+           bias(lay[l - 1]), a[A0 + l], g);
   }
   {
     Stage st = {a[A3], nullptr, nullptr};
     LAUNCH((k_conv32<SM_PLAIN, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(LB3), bias(LB3), a[C3],
-           g, (float*)nullptr);
+           g);
   }
   // up path: c_l = relu(u_l(a_l + up c_{l+1}))
   const int ulay[3] = {LU2, LU1, LU0};
@@ -829,13 +928,10 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
     g = dbl(g);
     Stage st = {a[askip[k]], a[acoarse[k]], nullptr};
     LAUNCH((k_conv32<SM_UPADD, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(ulay[k]), bias(ulay[k]),
-           a[adst[k]], g, (float*)nullptr);
+           a[adst[k]], g);
   }
-  {
-    Stage st = {a[C0], nullptr, nullptr};
-    LAUNCH((k_conv32<SM_PLAIN, EPI_OUT, KD>), dim3(conv_blocks(g0)), dim3(256), 0, s, st, fw(NL32 + 1),
-           th + P::OFF_OUT + P::K * CH, (u16*)nullptr, g0, net->y);
-  }
+  LAUNCH(k_out_mfma<KD>, dim3(conv_blocks(g0)), dim3(256), 0, s, (const u16*)a[C0], fw(NL32 + 1),
+         th + P::OFF_OUT + P::K * CH, g0, net->y);
   return FL_OK;
 }
 
@@ -876,7 +972,7 @@ template <int KD> static fl_status net_backward_t(fl_net net, const float* x, co
     constexpr int SMI = decltype(smi)::value, SMG = decltype(smg)::value;
     if (gin)
       LAUNCH((k_conv32<SMG, EPI_NONE, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, sg, bw(L), (const float*)nullptr,
-             gin, g, (float*)nullptr);
+             gin, g);
     const int nb = wgrad_blocks(g);
     LAUNCH((k_conv32_wgrad<SMI, SMG, KD>), dim3(nb, KD), dim3(256), 0, s, si, sg, net->part, g);
     return reduce(nb, P::L32SZ, P::L32SZ, P::OFF_L32 + L * P::L32SZ);
@@ -1103,19 +1199,16 @@ template <int KD> static fl_status profile_one(fl_net net, int which, Dims g) {
     Stage st = {a[A0], a[C1], nullptr};
     LAUNCH((k_conv32<SM_UPADD, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st,
            (const u16*)(net->fw + LU0 * P::PACK), (const float*)(net->th + P::OFF_L32 + LU0 * P::L32SZ + P::L32W),
-           a[C0], g, (float*)nullptr);
+           a[C0], g);
     return FL_OK;
   }
   if (which == 2) {
-    Stage st = {nullptr, nullptr, nullptr, (const float*)net->xb, (const float*)net->ab};
-    LAUNCH((k_conv32<SM_INPUT, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st,
-           (const u16*)(net->fw + NL32 * P::PACK), (const float*)(net->th + P::OFF_CIN_B), a[A0], g, (float*)nullptr);
+    LAUNCH(k_cin_mfma<KD>, dim3(conv_blocks(g)), dim3(256), 0, s, (const float*)net->xb, (const float*)net->ab,
+           (const u16*)(net->fw + NL32 * P::PACK), (const float*)(net->th + P::OFF_CIN_B), a[A0], g);
     return FL_OK;
   }
-  Stage st = {a[C0], nullptr, nullptr};
-  LAUNCH((k_conv32<SM_PLAIN, EPI_OUT, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st,
-         (const u16*)(net->fw + (NL32 + 1) * P::PACK), (const float*)(net->th + P::OFF_OUT + P::K * CH),
-         (u16*)nullptr, g, net->y);
+  LAUNCH(k_out_mfma<KD>, dim3(conv_blocks(g)), dim3(256), 0, s, (const u16*)a[C0],
+         (const u16*)(net->fw + (NL32 + 1) * P::PACK), (const float*)(net->th + P::OFF_OUT + P::K * CH), g, net->y);
   return FL_OK;
 }
 
