@@ -21,7 +21,14 @@ solver-generated pairs at 256^2, alpha ~ U[0.2, 1.9]: 100 problems x (10
 iterate errors + 10 random-field errors) = 2000 pairs.  `value` is the time of
 learned_f32; the plain-FP64 baseline is the faster of fp64_pcg and fp64_cg.
 
+Reported beside it (not part of `value`): per-pass timings and the roofline
+of the dominant kernel; the batched workloads (16 x 256^3 right-hand sides,
+32 uneven 2D backward-Euler problems x 200 steps); the learned preconditioner
+in 3D (trained at 32^3, evaluated at 128^3, alpha = 1.5); the oracle's FP64
+PCG timed on the host for a bounded sample.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--alpha A] [--no-cpu]
+                       [--no-batched] [--no-learned-3d]
 """
 import argparse
 import json
