@@ -758,21 +758,55 @@ __global__ void k_net_out(const T* __restrict__ r, const float* __restrict__ y, 
 }
 
 // Flexible CG scalars live on the device: fs[0] = r.z, fs[1] = z.q_old,
-// fs[2] = p.q, fs[3] = p.r, fs[4] = r.r.
+// fs[2] = p.q, fs[3] = p.r, fs[4] = r.r, fs[5] = done flag (1 once r.r is
+// below the threshold or p.q broke down: later updates are no-ops).
 __global__ void k_total_to(Prob pb, int site, double* __restrict__ dst) {
   const double t = get_total(pb, site);
   if (threadIdx.x == 0) *dst = t;
 }
-// p = z + beta p, beta = -z.q_old / p_old.q_old (0 on the first iteration)
-template <typename T>
-__global__ void k_fcg_dir(const T* __restrict__ z, T* __restrict__ p, long n, const double* __restrict__ fs, int first) {
-  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double beta = (first || !(fs[2] > 0.0)) ? 0.0 : -fs[1] / fs[2];
-  p[i] = beta == 0.0 ? z[i] : (T)((double)z[i] + beta * (double)p[i]);
+// partials of r.z (site S_RZ0) and, after the first iteration, z.q_old (S_RZ1)
+template <typename T> __global__ __launch_bounds__(256) void k_fcg_dots(Prob pb, long n, int with_q) {
+  const T* z = (const T*)pb.z;
+  const T* r = (const T*)pb.r;
+  const T* q = (const T*)pb.q;
+  double a = 0.0, c = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double zi = (double)z[i];
+    a += zi * (double)r[i];
+    if (with_q) c += zi * (double)q[i];
+  }
+  put_partial(pb, S_RZ0, a, gridDim.x, blockIdx.x);
+  put_partial(pb, S_RZ1, c, gridDim.x, blockIdx.x);
 }
-// alpha = p.r / p.q; x += alpha p; r -= alpha q; r.r partials (site S_RR)
+// totals of two sites into fs[i0], fs[i1] (one workgroup)
+__global__ void k_totals2(Prob pb, int s0, int s1, double* __restrict__ fs, int i0, int i1) {
+  const double t0 = get_total(pb, s0);
+  const double t1 = get_total(pb, s1);
+  if (threadIdx.x == 0) {
+    fs[i0] = t0;
+    fs[i1] = t1;
+  }
+}
+// p = z + beta p, beta = -z.q_old / p_old.q_old (0 on the first iteration);
+// p.r partials (site S_DOT)
+template <typename T>
+__global__ __launch_bounds__(256) void k_fcg_dir(Prob pb, long n, const double* __restrict__ fs, int first) {
+  const double beta = (first || !(fs[2] > 0.0)) ? 0.0 : -fs[1] / fs[2];
+  const T* z = (const T*)pb.z;
+  const T* r = (const T*)pb.r;
+  T* p = (T*)pb.p;
+  double acc = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const T pv = beta == 0.0 ? z[i] : (T)((double)z[i] + beta * (double)p[i]);
+    p[i] = pv;
+    acc += (double)pv * (double)r[i];
+  }
+  put_partial(pb, S_DOT, acc, gridDim.x, blockIdx.x);
+}
+// alpha = p.r / p.q; x += alpha p; r -= alpha q; r.r partials (site S_RR).
+// Nothing happens once the done flag is set (a speculative iteration).
 template <typename T> __global__ __launch_bounds__(256) void k_fcg_update(Prob pb, long n, const double* __restrict__ fs) {
+  if (fs[5] != 0.0) return;  // uniform over the grid
   const double pq = fs[2];
   const double alpha = (pq > 0.0 && isfinite(pq)) ? fs[3] / pq : 0.0;
   T* x = (T*)pb.x;
@@ -787,6 +821,15 @@ template <typename T> __global__ __launch_bounds__(256) void k_fcg_update(Prob p
     acc += (double)rv * (double)rv;
   }
   put_partial(pb, S_RR, acc, gridDim.x, blockIdx.x);
+}
+// r.r into fs[4] and the done flag (converged, non-finite, or p.q breakdown)
+__global__ void k_fcg_check(Prob pb, double* __restrict__ fs, double thr) {
+  const double rr = get_total(pb, S_RR);
+  if (threadIdx.x == 0 && fs[5] == 0.0) {
+    fs[4] = rr;
+    const double pq = fs[2];
+    if (rr <= thr || !isfinite(rr) || !(pq > 0.0) || !isfinite(pq)) fs[5] = 1.0;
+  }
 }
 
 // Training pairs on the operator's grid (FP64 in): R = r / s, T = (D e - r) / s
@@ -837,11 +880,14 @@ struct fl_net_s {
   void* pw = nullptr;
   float* palpha = nullptr;
   double* fs = nullptr;   // device scalars of flexible CG
-  double* hfs = nullptr;  // pinned host mirror
+  double* hfs = nullptr;  // pinned host mirror: a seed slot and a ring of two iterations
+  hipEvent_t ev[2] = {nullptr, nullptr};
   std::vector<void*> owned;
   ~fl_net_s() {
     for (void* p : owned) (void)hipFree(p);
     if (hfs) (void)hipHostFree(hfs);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
   }
   fl_status alloc(void** p, size_t bytes) {
     STCHK(dalloc(p, bytes));
@@ -1081,10 +1127,15 @@ template <typename T> static fl_status dot_to(fl_op op, const Prob& pb, const vo
 
 // Flexible CG (truncated to one previous direction): alpha_k = p.r / p.q,
 // beta_k = -z_{k+1}.q_k / p_k.q_k, every scalar computed and used on the
-// device; the host reads r.z, p.q and r.r once per iteration.  r holds the
-// initial residual, x the initial iterate; rr0 = r.r, ff = f.f.  Fallback:
-// the FD preconditioner for the rest of the solve once r.z <= 0 or 5
-// iterations fail to cut ||r|| by 1%.
+// device; the host reads r.z, p.q and r.r of each iteration (a copy into a
+// pinned ring, one event per slot).  While the observed contraction of r.r
+// predicts that iteration k will not converge, iteration k+1 is enqueued
+// before k is read, so the GPU does not wait for the host.  If k converges
+// anyway, the device done flag turns the update of k+1 into a no-op and x, r
+// stay those of iteration k.  r holds the initial residual, x the initial
+// iterate; rr0 = r.r, ff = f.f.  Fallback: the FD preconditioner once
+// r.z <= 0 or 5 iterations fail to cut ||r|| by 1% (from the next iteration
+// enqueued).
 template <typename T>
 fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxit, double ff, double rr0, int* iters,
                       double* rr_out, int* status, int* fell_back) {
@@ -1092,7 +1143,6 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
   const long N = op->N;
   const double thr = tol * tol * ff;
   double* fs = net->fs;
-  double* h = net->hfs;
   double rr = rr0;
   int it = 0, stall = 0;
   bool fb = false;
@@ -1105,27 +1155,48 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
     *fell_back = 0;
     return FL_OK;
   }
+  double* h = net->hfs;  // [8] seed, then the ring [2][8]
   h[4] = rr0;
-  HIPCHK(hipMemcpyAsync(fs + 4, h + 4, sizeof(double), hipMemcpyHostToDevice, s));
+  h[5] = 0.0;
+  HIPCHK(hipMemcpyAsync(fs + 4, h + 4, 2 * sizeof(double), hipMemcpyHostToDevice, s));
   const int nupd = (int)std::min<long>(2048, nblocks_vec(N));
-  for (;;) {
-    if (!fb) STCHK(learned_prec<T>(op, net, pb));
+  const int ndot = (int)std::min<long>(1024, nblocks_vec(N));
+  auto enqueue = [&](int k, bool use_fd) -> fl_status {
+    if (!use_fd) STCHK(learned_prec<T>(op, net, pb));
     else STCHK(fd_prec<T>(op, pb));
-    STCHK(dot_to<T>(op, pb, pb.r, pb.z, fs + 0));
-    if (it > 0) STCHK(dot_to<T>(op, pb, pb.z, pb.q, fs + 1));
-    LAUNCH(k_fcg_dir<T>, dim3(nblocks_vec(N)), dim3(256), 0, s, (const T*)pb.z, (T*)pb.p, N, (const double*)fs,
-           it == 0 ? 1 : 0);
+    LAUNCH(k_fcg_dots<T>, dim3(ndot), dim3(256), 0, s, pb, N, k > 0 ? 1 : 0);
+    LAUNCH(k_totals2, dim3(1), dim3(256), 0, s, pb, (int)S_RZ0, (int)S_RZ1, fs, 0, 1);
+    LAUNCH(k_fcg_dir<T>, dim3(ndot), dim3(256), 0, s, pb, N, (const double*)fs, k == 0 ? 1 : 0);
     Prob pa = pb;
     pa.in = pb.p;
     STCHK((apply_seq<T, PRO_PLAIN, EPI_PQ>(op, pa, Iter{0, 0}, 0)));
-    LAUNCH(k_total_to, dim3(1), dim3(256), 0, s, pb, (int)S_PQ, fs + 2);
-    STCHK(dot_to<T>(op, pb, pb.p, pb.r, fs + 3));
+    LAUNCH(k_totals2, dim3(1), dim3(256), 0, s, pb, (int)S_PQ, (int)S_DOT, fs, 2, 3);
     LAUNCH(k_fcg_update<T>, dim3(nupd), dim3(256), 0, s, pb, N, (const double*)fs);
-    LAUNCH(k_total_to, dim3(1), dim3(256), 0, s, pb, (int)S_RR, fs + 4);
-    HIPCHK(hipMemcpyAsync(h, fs, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    const double rz = h[0], pq = h[2];
-    rr = h[4];
+    LAUNCH(k_fcg_check, dim3(1), dim3(256), 0, s, pb, fs, thr);
+    HIPCHK(hipMemcpyAsync(h + 8 + 8 * (k & 1), fs, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(net->ev[k & 1], s));
+    return FL_OK;
+  };
+  int enq = 0;
+  double rr_before = rr0;  // r.r one iteration before the last one read
+  for (;;) {
+    if (enq == it) {  // the iteration to read next is not in flight yet
+      STCHK(enqueue(enq, fb));
+      ++enq;
+    }
+    if (enq == it + 1 && enq < maxit) {  // speculate on the next one?
+      // predicted r.r after the iteration in flight: the last contraction again
+      const bool ahead = it == 0 || rr * (rr / std::max(rr_before, 1e-300)) > 4.0 * thr;
+      if (ahead) {
+        STCHK(enqueue(enq, fb));
+        ++enq;
+      }
+    }
+    HIPCHK(hipEventSynchronize(net->ev[it & 1]));
+    const double* hk = h + 8 + 8 * (it & 1);
+    const double rz = hk[0], pq = hk[2];
+    rr_before = rr;
+    rr = hk[4];
     if (!(pq > 0.0) || !std::isfinite(pq)) {
       *status = 3;
       break;
@@ -1151,6 +1222,7 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
       fb = true;  // stagnation: judge with the FD preconditioner
     }
   }
+  HIPCHK(hipStreamSynchronize(s));  // the speculative iteration has drained
   *iters = it;
   *rr_out = rr;
   *fell_back = fb ? 1 : 0;
@@ -1179,8 +1251,10 @@ fl_status learned_prepare(fl_op op, fl_net net, size_t elem) {
   }
   if (!net->palpha) STCHK(net->alloc((void**)&net->palpha, sizeof(float)));
   if (!net->fs) STCHK(net->alloc((void**)&net->fs, 8 * sizeof(double)));
-  if (!net->hfs && hipHostMalloc((void**)&net->hfs, 8 * sizeof(double)) != hipSuccess)
+  if (!net->hfs && hipHostMalloc((void**)&net->hfs, 24 * sizeof(double)) != hipSuccess)
     return fail(FL_E_NOMEM, "pinned host scalars");
+  for (hipEvent_t& e : net->ev)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   const float a = (float)op->alpha;
   HIPCHK(hipMemcpyAsync(net->palpha, &a, sizeof(float), hipMemcpyHostToDevice, op->stream));
   HIPCHK(hipStreamSynchronize(op->stream));
