@@ -260,10 +260,14 @@ enum { EPI_RELU = 0, EPI_NONE = 1 };
 // acc[4q .. 4q+3].  The wave's 64 x 32 outputs go through LDS (`tile`, free
 // once every wave has passed a barrier after its last read) so that the
 // global stores are contiguous 16-byte chunks.
+// pout (2D only, else nullptr): also the 2 x 2 average of the tile into the
+// coarser level (2 x 32 pooled pixels; tiles start on even rows and columns,
+// H and W are even): the mean of four BF16 outputs in FP32, rounded to BF16,
+// as pooling staging would compute it from `out`.
 template <int EPI>
 __device__ __forceinline__ void store_rows(const f32x16& acc0, const f32x16& acc1, u16* tile,
                                            const float* __restrict__ bias, u16* __restrict__ out, const Dims& g, int b,
-                                           int z, int y0, int x0) {
+                                           int z, int y0, int x0, u16* __restrict__ pout = nullptr) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   u16* ot = tile + wave * 64 * CH;
 #pragma unroll
@@ -285,6 +289,25 @@ __device__ __forceinline__ void store_rows(const f32x16& acc0, const f32x16& acc
     }
   }
   __syncthreads();
+  if (pout) {  // one 8-channel chunk of one pooled pixel per thread
+    const Dims gc{g.B, 1, g.H / 2, g.W / 2};
+    const int q = (threadIdx.x & 3) * 8, pc = (threadIdx.x >> 2) & 31, wr = threadIdx.x >> 7;
+    const int px = x0 / 2 + pc, py = y0 / 2 + wr;
+    if (px < gc.W && py < gc.H) {
+      float v[8], t[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = 0.f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        ld8(tile + ((2 * wr + (k >> 1)) * 64 + 2 * pc + (k & 1)) * CH + q, t);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] += t[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] *= 0.25f;
+      *(uint4*)(pout + pix(gc, b, 0, py, px) + q) = pk8(v);
+    }
+  }
   const int yo = y0 + wave;
   if (yo >= g.H) return;
 #pragma unroll
@@ -297,7 +320,7 @@ __device__ __forceinline__ void store_rows(const f32x16& acc0, const f32x16& acc
 
 template <int SM, int EPI, int KD>
 __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict__ wpack, const float* __restrict__ bias,
-                                                u16* __restrict__ out, Dims g) {
+                                                u16* __restrict__ out, Dims g, u16* __restrict__ pout) {
   __shared__ __align__(16) u16 tile[SY * SX * CH];
   int b, z, y0, x0;
   tile_of(blockIdx.x, g, b, z, y0, x0);
@@ -331,7 +354,7 @@ __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict_
     }
   }
   __syncthreads();  // every wave is done reading the staged tile
-  store_rows<EPI>(acc0, acc1, tile, bias, out, g, b, z, y0, x0);
+  store_rows<EPI>(acc0, acc1, tile, bias, out, g, b, z, y0, x0, pout);
 }
 
 // Input layer (2 -> 32) on MFMA with (tap, input channel) packed into K:
@@ -342,7 +365,7 @@ __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict_
 template <int KD>
 __global__ __launch_bounds__(256) void k_cin_mfma(const float* __restrict__ x, const float* __restrict__ alpha,
                                                   const u16* __restrict__ wpack, const float* __restrict__ bias,
-                                                  u16* __restrict__ out, Dims g) {
+                                                  u16* __restrict__ out, Dims g, u16* __restrict__ pout) {
   constexpr int K = 9 * KD, S = (2 * K + 15) / 16;
   __shared__ __align__(16) u16 tile[SY * SX * CH];  // output staging
   __shared__ unsigned xin[KD][SY * SX];             // bf16 pair (x, alpha - 1) per pixel
@@ -388,7 +411,7 @@ __global__ __launch_bounds__(256) void k_cin_mfma(const float* __restrict__ x, c
       else acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[st], bfr, acc1, 0, 0, 0);
     }
   }
-  store_rows<EPI_RELU>(acc0, acc1, tile, bias, out, g, b, z, y0, x0);
+  store_rows<EPI_RELU>(acc0, acc1, tile, bias, out, g, b, z, y0, x0, pout);
 }
 
 // Output layer (32 -> 1): per slice, Z[q][m] = sum_ci c0[q][ci] W[9 kz + m][ci]
@@ -865,6 +888,7 @@ struct fl_net_s {
   long cap = 0;
   u16* act[8] = {};   // a0 a1 a2 a3 c3 c2 c1 c0
   u16* grd[8] = {};   // gc0 gs0 gs1 gs2 ga3 gp3 gp2 gp1
+  u16* pool[4] = {};  // 2D: pool[l] = pool a[l-1] at level l (1..3)
   float *y = nullptr, *gy = nullptr, *xb = nullptr, *tb = nullptr, *ab = nullptr;
   int ab_cap = 0;
   float* part = nullptr;
@@ -876,7 +900,7 @@ struct fl_net_s {
   int idx_cap = 0;
   // learned-preconditioner scratch on a solver grid
   long pcap = 0;
-  float *pin = nullptr, *pout = nullptr;
+  float* pin = nullptr;  // network input on the padded grid
   void* pw = nullptr;
   float* palpha = nullptr;
   double* fs = nullptr;   // device scalars of flexible CG
@@ -912,6 +936,8 @@ static fl_status net_reserve(fl_net net, int B, int D, int H, int W) {
     STCHK(net->alloc((void**)&net->act[i], (size_t)(px >> (sh * lvl_of_act[i])) * CH * sizeof(u16)));
     STCHK(net->alloc((void**)&net->grd[i], (size_t)(px >> (sh * lvl_of_grd[i])) * CH * sizeof(u16)));
   }
+  if (net->kd == 1)
+    for (int l = 1; l <= 3; ++l) STCHK(net->alloc((void**)&net->pool[l], (size_t)(px >> (2 * l)) * CH * sizeof(u16)));
   for (float** p : {&net->y, &net->gy, &net->xb, &net->tb}) STCHK(net->alloc((void**)p, px * sizeof(float)));
   net->cap = px;
   return FL_OK;
@@ -952,20 +978,31 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
   auto fw = [&](int L) { return (const u16*)(net->fw + L * P::PACK); };
   auto half = [](Dims g) { return Dims{g.B, KD == 3 ? g.D / 2 : 1, g.H / 2, g.W / 2}; };
   auto dbl = [](Dims g) { return Dims{g.B, KD == 3 ? g.D * 2 : 1, g.H * 2, g.W * 2}; };
-  LAUNCH(k_cin_mfma<KD>, dim3(conv_blocks(g0)), dim3(256), 0, s, x, alpha, fw(NL32), th + P::OFF_CIN_B, a[A0], g0);
+  // 2D: every layer of the down path also writes the pooled input of the
+  // next one (p[l] = pool a[l-1]); 3D pools in the staging of the next layer
+  u16* const* pl = net->pool;
+  LAUNCH(k_cin_mfma<KD>, dim3(conv_blocks(g0)), dim3(256), 0, s, x, alpha, fw(NL32), th + P::OFF_CIN_B, a[A0], g0,
+         KD == 1 ? pl[1] : (u16*)nullptr);
   Dims g = g0;
   // down path
   const int lay[3] = {LD1, LD2, LD3};
   for (int l = 1; l <= 3; ++l) {
     g = half(g);
-    Stage st = {a[A0 + l - 1], nullptr, nullptr};
-    LAUNCH((k_conv32<SM_POOL, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(lay[l - 1]),
-           bias(lay[l - 1]), a[A0 + l], g);
+    u16* po = (KD == 1 && l < 3) ? pl[l + 1] : (u16*)nullptr;
+    if constexpr (KD == 1) {
+      Stage st = {pl[l], nullptr, nullptr};
+      LAUNCH((k_conv32<SM_PLAIN, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(lay[l - 1]),
+             bias(lay[l - 1]), a[A0 + l], g, po);
+    } else {
+      Stage st = {a[A0 + l - 1], nullptr, nullptr};
+      LAUNCH((k_conv32<SM_POOL, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(lay[l - 1]),
+             bias(lay[l - 1]), a[A0 + l], g, po);
+    }
   }
   {
     Stage st = {a[A3], nullptr, nullptr};
     LAUNCH((k_conv32<SM_PLAIN, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(LB3), bias(LB3), a[C3],
-           g);
+           g, (u16*)nullptr);
   }
   // up path: c_l = relu(u_l(a_l + up c_{l+1}))
   const int ulay[3] = {LU2, LU1, LU0};
@@ -974,7 +1011,7 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
     g = dbl(g);
     Stage st = {a[askip[k]], a[acoarse[k]], nullptr};
     LAUNCH((k_conv32<SM_UPADD, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(ulay[k]), bias(ulay[k]),
-           a[adst[k]], g);
+           a[adst[k]], g, (u16*)nullptr);
   }
   LAUNCH(k_out_mfma<KD>, dim3(conv_blocks(g0)), dim3(256), 0, s, (const u16*)a[C0], fw(NL32 + 1),
          th + P::OFF_OUT + P::K * CH, g0, net->y);
@@ -1018,7 +1055,7 @@ template <int KD> static fl_status net_backward_t(fl_net net, const float* x, co
     constexpr int SMI = decltype(smi)::value, SMG = decltype(smg)::value;
     if (gin)
       LAUNCH((k_conv32<SMG, EPI_NONE, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, sg, bw(L), (const float*)nullptr,
-             gin, g);
+             gin, g, (u16*)nullptr);
     const int nb = wgrad_blocks(g);
     LAUNCH((k_conv32_wgrad<SMI, SMG, KD>), dim3(nb, KD), dim3(256), 0, s, si, sg, net->part, g);
     return reduce(nb, P::L32SZ, P::L32SZ, P::OFF_L32 + L * P::L32SZ);
@@ -1273,12 +1310,12 @@ template <int KD> static fl_status profile_one(fl_net net, int which, Dims g) {
     Stage st = {a[A0], a[C1], nullptr};
     LAUNCH((k_conv32<SM_UPADD, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st,
            (const u16*)(net->fw + LU0 * P::PACK), (const float*)(net->th + P::OFF_L32 + LU0 * P::L32SZ + P::L32W),
-           a[C0], g);
+           a[C0], g, (u16*)nullptr);
     return FL_OK;
   }
   if (which == 2) {
     LAUNCH(k_cin_mfma<KD>, dim3(conv_blocks(g)), dim3(256), 0, s, (const float*)net->xb, (const float*)net->ab,
-           (const u16*)(net->fw + NL32 * P::PACK), (const float*)(net->th + P::OFF_CIN_B), a[A0], g);
+           (const u16*)(net->fw + NL32 * P::PACK), (const float*)(net->th + P::OFF_CIN_B), a[A0], g, (u16*)nullptr);
     return FL_OK;
   }
   LAUNCH(k_out_mfma<KD>, dim3(conv_blocks(g)), dim3(256), 0, s, (const u16*)a[C0],
