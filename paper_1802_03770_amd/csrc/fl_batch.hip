@@ -101,6 +101,9 @@ static int vmax(const std::vector<int>& v) {
   for (int x : v) m = std::max(m, x);
   return m;
 }
+// grid width of the column passes: a multiple of 8, so that their XCD-aware
+// tile mapping holds for every problem (blocks beyond a problem's count exit)
+static int vmax8(const std::vector<int>& v) { return (vmax(v) + 7) & ~7; }
 
 // Batched operator application with prologue PRO / epilogue EPI over the Prob
 // array `pbs` (device).
@@ -122,7 +125,7 @@ template <typename T, int PRO, int EPI> fl_status bt_apply(BatchT& bt, const Pro
     default: LAUNCH((k_rowfwd_b<T, PRO>), gf, dim3(256), bt.sm_row, s, pbs, it, nbf); break;
   }
   auto col = [&](int r, int mode) -> fl_status {
-    const dim3 g(vmax(bt.nb_col[r]), np);
+    const dim3 g(vmax8(bt.nb_col[r]), np);
     const ColGeom* cg = (const ColGeom*)bt.d_cg + r * np;
     const int* nb = (const int*)bt.d_nb_col[r];
     const int lf = bt.lf_col[r];
@@ -204,7 +207,7 @@ template <typename T, int DPRO, int DEPI> fl_status bt_precond(BatchT& bt, const
   STCHK((bt_dst_rows<T, DPRO, DEPI_STORE>(bt.lf_row, gr, bt.sm_dstrow, s, pfirst, it, chk, nbr)));
   const DGeom* dg = (const DGeom*)bt.d_dg;
   auto cols = [&](int r, bool scale) -> fl_status {
-    dim3 g(vmax(bt.nb_dcol[r]), np);
+    dim3 g(vmax8(bt.nb_dcol[r]), np);
     const int* nb = (const int*)bt.d_nb_dcol[r];
     if (scale) return bt_dst_cols<T, true>(bt.lf_dcol[r], g, bt.sm_dcol[r], s, plast, dg + r * np, chk, nb);
     return bt_dst_cols<T, false>(bt.lf_dcol[r], g, bt.sm_dcol[r], s, plast, dg + r * np, chk, nb);

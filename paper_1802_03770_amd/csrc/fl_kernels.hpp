@@ -66,9 +66,11 @@ __device__ __forceinline__ int fold(int k, int P) { return k <= P / 2 ? k : P - 
 
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).  Map
 // block b to tile t so that the blocks one XCD runs concurrently take adjacent
-// tiles (strided column passes then share 128-byte lines inside one L2).
+// tiles (strided column passes then share 128-byte lines inside one L2).  A
+// batched launch (gridDim.y problems) keeps the XCD of block b equal to b mod 8
+// when gridDim.x is a multiple of 8, so the same mapping holds per problem.
 __device__ __forceinline__ long xcd_tile(long b, long nb) {
-  if (gridDim.y != 1 || nb < 16) return b;
+  if ((gridDim.y != 1 && (gridDim.x & 7) != 0) || nb < 16) return b;
   const long q = nb >> 3, r = nb & 7, x = b & 7;
   return x * q + (x < r ? x : r) + (b >> 3);
 }
