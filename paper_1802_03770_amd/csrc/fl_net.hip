@@ -473,6 +473,23 @@ __global__ __launch_bounds__(256) void k_out_mfma(const u16* __restrict__ c0, co
   if (yo < g.H && xo < g.W) yout[(((long)b * g.D + z) * g.H + yo) * g.W + xo] = yacc + bias[0];
 }
 
+// Pooled activation of a level (3D down path): one 8-channel chunk of one
+// coarse pixel per thread, the mean over the 2 x 2 x 2 block exactly as the
+// pooling staging forms it.
+template <int KD> __global__ __launch_bounds__(256) void k_pool(const u16* __restrict__ src, u16* __restrict__ dst, Dims gc) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= (long)gc.B * gc.D * gc.H * gc.W * 4) return;
+  const int c = (int)(t & 3) * 8;
+  const long v = t >> 2;
+  const int x = (int)(v % gc.W), y = (int)((v / gc.W) % gc.H);
+  const long bz = v / ((long)gc.W * gc.H);
+  const int z = (int)(bz % gc.D), b = (int)(bz / gc.D);
+  const Stage st = {src, nullptr, nullptr};
+  float r[8];
+  stage8<SM_POOL, KD>(st, gc, b, z, y, x, c, r);
+  *(uint4*)(dst + pix(gc, b, z, y, x) + c) = pk8(r);
+}
+
 // Stage the gradient G of the output slice z (TY x TX pixels, no halo).
 template <int SMG, int KD>
 __device__ __forceinline__ void stage_grad(u16* gt, const Stage& sg, const Dims& g, int b, int z, int y0, int x0) {
@@ -888,7 +905,7 @@ struct fl_net_s {
   long cap = 0;
   u16* act[8] = {};   // a0 a1 a2 a3 c3 c2 c1 c0
   u16* grd[8] = {};   // gc0 gs0 gs1 gs2 ga3 gp3 gp2 gp1
-  u16* pool[4] = {};  // 2D: pool[l] = pool a[l-1] at level l (1..3)
+  u16* pool[4] = {};  // pool[l] = pool a[l-1] at level l (1..3)
   float *y = nullptr, *gy = nullptr, *xb = nullptr, *tb = nullptr, *ab = nullptr;
   int ab_cap = 0;
   float* part = nullptr;
@@ -936,8 +953,7 @@ static fl_status net_reserve(fl_net net, int B, int D, int H, int W) {
     STCHK(net->alloc((void**)&net->act[i], (size_t)(px >> (sh * lvl_of_act[i])) * CH * sizeof(u16)));
     STCHK(net->alloc((void**)&net->grd[i], (size_t)(px >> (sh * lvl_of_grd[i])) * CH * sizeof(u16)));
   }
-  if (net->kd == 1)
-    for (int l = 1; l <= 3; ++l) STCHK(net->alloc((void**)&net->pool[l], (size_t)(px >> (2 * l)) * CH * sizeof(u16)));
+  for (int l = 1; l <= 3; ++l) STCHK(net->alloc((void**)&net->pool[l], (size_t)(px >> (sh * l)) * CH * sizeof(u16)));
   for (float** p : {&net->y, &net->gy, &net->xb, &net->tb}) STCHK(net->alloc((void**)p, px * sizeof(float)));
   net->cap = px;
   return FL_OK;
@@ -978,8 +994,8 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
   auto fw = [&](int L) { return (const u16*)(net->fw + L * P::PACK); };
   auto half = [](Dims g) { return Dims{g.B, KD == 3 ? g.D / 2 : 1, g.H / 2, g.W / 2}; };
   auto dbl = [](Dims g) { return Dims{g.B, KD == 3 ? g.D * 2 : 1, g.H * 2, g.W * 2}; };
-  // 2D: every layer of the down path also writes the pooled input of the
-  // next one (p[l] = pool a[l-1]); 3D pools in the staging of the next layer
+  // pooled inputs of the down path, p[l] = pool a[l-1]: in 2D every layer
+  // writes the next one's from its output tile, in 3D k_pool forms it
   u16* const* pl = net->pool;
   LAUNCH(k_cin_mfma<KD>, dim3(conv_blocks(g0)), dim3(256), 0, s, x, alpha, fw(NL32), th + P::OFF_CIN_B, a[A0], g0,
          KD == 1 ? pl[1] : (u16*)nullptr);
@@ -989,15 +1005,12 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
   for (int l = 1; l <= 3; ++l) {
     g = half(g);
     u16* po = (KD == 1 && l < 3) ? pl[l + 1] : (u16*)nullptr;
-    if constexpr (KD == 1) {
-      Stage st = {pl[l], nullptr, nullptr};
-      LAUNCH((k_conv32<SM_PLAIN, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(lay[l - 1]),
-             bias(lay[l - 1]), a[A0 + l], g, po);
-    } else {
-      Stage st = {a[A0 + l - 1], nullptr, nullptr};
-      LAUNCH((k_conv32<SM_POOL, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(lay[l - 1]),
-             bias(lay[l - 1]), a[A0 + l], g, po);
-    }
+    if constexpr (KD == 3)
+      LAUNCH(k_pool<KD>, dim3(nblocks_vec((long)g.B * g.D * g.H * g.W * 4)), dim3(256), 0, s,
+             (const u16*)a[A0 + l - 1], pl[l], g);
+    Stage st = {pl[l], nullptr, nullptr};
+    LAUNCH((k_conv32<SM_PLAIN, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(lay[l - 1]),
+           bias(lay[l - 1]), a[A0 + l], g, po);
   }
   {
     Stage st = {a[A3], nullptr, nullptr};
