@@ -57,7 +57,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="comma list of configurations to time")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 3D and uneven-batch workloads")
-    ap.add_argument("--c4-steps", type=int, default=200)
+    ap.add_argument("--uneven-steps", type=int, default=200)
     ap.add_argument("--train-problems", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--train-batch", type=int, default=16)
@@ -246,16 +246,16 @@ def measured_traffic(name):
 def batched_workloads(fl, torch, args):
     """The batched row of the hot path on its two workloads (one launch per
     pass over all problems, captured iteration graphs):
-      c3: d=3, 256^3, alpha=1.2, 16 right-hand sides of one operator, FP32
+      rhs16_256cubed: d=3, 256^3, alpha=1.2, 16 right-hand sides of one operator, FP32
           inner PCG + FP64 refinement to 1e-8 (FD preconditioner, and the
           sine-basis diagonal with its one-off table build timed apart);
-      c4: 32 uneven 2D backward-Euler problems (n in {128,256,384,512},
-          alpha ~ U[0.3,1.8]), dt = 1e-3, `c4_steps` steps, tol 1e-10."""
-    from workloads import workload_c3, workload_c4
+      uneven_2d_steps: 32 uneven 2D backward-Euler problems (n in {128,256,384,512},
+          alpha ~ U[0.3,1.8]), dt = 1e-3, `uneven_steps` steps, tol 1e-10."""
+    from workloads import workload_rhs_256cubed, workload_uneven_steps
     out = {}
     s = torch.cuda.Stream()
-    # c4
-    probs = workload_c4(32)
+    # uneven 2D steps
+    probs = workload_uneven_steps(32)
     t0 = time.perf_counter()
     ops = [fl.Op(2, p["alpha"], p["h"], (p["n"], p["n"]), stream=s) for p in probs]
     torch.cuda.synchronize()
@@ -265,47 +265,47 @@ def batched_workloads(fl, torch, args):
     fl.step_batched(ops, [u.clone() for u in us], [1e-3] * 32, theta=1.0, nsteps=2, tol=1e-10, opts=opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, infos = fl.step_batched(ops, us, [1e-3] * 32, theta=1.0, nsteps=args.c4_steps, tol=1e-10, opts=opts)
+    _, infos = fl.step_batched(ops, us, [1e-3] * 32, theta=1.0, nsteps=args.uneven_steps, tol=1e-10, opts=opts)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
     unk = sum(p["n"] ** 2 for p in probs)
-    out["c4"] = {"workload": "32 uneven 2D backward-Euler problems, n in {128,256,384,512}, dt=1e-3",
-                 "steps": args.c4_steps, "ms_total": round(ms, 1), "ms_per_step": round(ms / args.c4_steps, 3),
-                 "unknown_steps_per_s": round(unk * args.c4_steps / (ms * 1e-3), 1),
-                 "iters_per_step_mean": round(sum(i["iters"] for i in infos) / (32 * args.c4_steps), 2),
+    out["uneven_2d_steps"] = {"workload": "32 uneven 2D backward-Euler problems, n in {128,256,384,512}, dt=1e-3",
+                 "steps": args.uneven_steps, "ms_total": round(ms, 1), "ms_per_step": round(ms / args.uneven_steps, 3),
+                 "unknown_steps_per_s": round(unk * args.uneven_steps / (ms * 1e-3), 1),
+                 "iters_per_step_mean": round(sum(i["iters"] for i in infos) / (32 * args.uneven_steps), 2),
                  "max_rel_res_true": max(i["rel_res_true"] for i in infos), "make_weights_s": round(t_make, 2),
                  "preconditioner": "sine-basis diagonal"}
-    log(f"[bench] c4: {args.c4_steps} steps of 32 uneven problems in {ms:.1f} ms ({ms / args.c4_steps:.2f} ms/step), "
-        f"mean iters/step {out['c4']['iters_per_step_mean']}, max true res {out['c4']['max_rel_res_true']:.1e}")
+    log(f"[bench] uneven 2D: {args.uneven_steps} steps of 32 uneven problems in {ms:.1f} ms ({ms / args.uneven_steps:.2f} ms/step), "
+        f"mean iters/step {out['uneven_2d_steps']['iters_per_step_mean']}, max true res {out['uneven_2d_steps']['max_rel_res_true']:.1e}")
     for o in ops:
         o.close()
     del ops, us
-    # c3
-    w0 = workload_c3(0)
+    # 16 right-hand sides at 256^3
+    w0 = workload_rhs_256cubed(0)
     t0 = time.perf_counter()
     op = fl.Op(3, w0["alpha"], w0["h"], (w0["n"],) * 3, stream=s)
     torch.cuda.synchronize()
     t_make = time.perf_counter() - t0
-    fs = [torch.from_numpy(workload_c3(k)["f"]).cuda() for k in range(16)]
-    c3 = {"workload": "3D 256^3 alpha=1.2, 16 right-hand sides, FP32 inner + FP64 refinement, tol 1e-8",
+    fs = [torch.from_numpy(workload_rhs_256cubed(k)["f"]).cuda() for k in range(16)]
+    b3d = {"workload": "3D 256^3 alpha=1.2, 16 right-hand sides, FP32 inner + FP64 refinement, tol 1e-8",
           "make_weights_ms": round(t_make * 1e3, 1)}
     for name, pc in (("fd", fl.FL_PC_FD), ("spectral", fl.FL_PC_SPECTRAL)):
         opts = fl.solve_opts(pc=pc, mixed=1)
         if pc == fl.FL_PC_SPECTRAL:
             t0 = time.perf_counter()
             op.tau()
-            c3["tau_build_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+            b3d["tau_build_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, infos = fl.solve_batched([op] * 16, fs, tol=1e-8, opts=opts)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
-        c3[name] = {"ms": round(ms, 1), "ms_per_rhs": round(ms / 16, 2),
+        b3d[name] = {"ms": round(ms, 1), "ms_per_rhs": round(ms / 16, 2),
                     "iters_mean": round(sum(i["iters"] for i in infos) / 16, 1),
                     "max_rel_res_true": max(i["rel_res_true"] for i in infos)}
-        log(f"[bench] c3 {name}: 16 x 256^3 in {ms:.1f} ms, mean iters {c3[name]['iters_mean']}, "
-            f"max true res {c3[name]['max_rel_res_true']:.1e}")
-    out["c3"] = c3
+        log(f"[bench] 256^3 x16 {name}: 16 x 256^3 in {ms:.1f} ms, mean iters {b3d[name]['iters_mean']}, "
+            f"max true res {b3d[name]['max_rel_res_true']:.1e}")
+    out["rhs16_256cubed"] = b3d
     op.close()
     return out
 

@@ -164,8 +164,8 @@ def test_step_batched_c4_sizes_sampled():
     # at sampled points with the oracle's direct sums
     _say("batched step at 128..512 sampled")
     fl = _fl()
-    from workloads import workload_c4
-    probs = workload_c4(nprob=6)
+    from workloads import workload_uneven_steps
+    probs = workload_uneven_steps(nprob=6)
     sizes = sorted({p["n"] for p in probs})
     probs = [next(p for p in probs if p["n"] == n) for n in sizes] + probs[:2]
     s = torch.cuda.Stream()

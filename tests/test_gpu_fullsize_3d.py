@@ -24,7 +24,7 @@ from oracle import constants as K  # noqa: E402
 from oracle import operator as O  # noqa: E402
 from oracle import precond as PC  # noqa: E402
 from oracle import spectral as SP  # noqa: E402
-from workloads import white_noise, workload_c3  # noqa: E402
+from workloads import white_noise, workload_rhs_256cubed  # noqa: E402
 
 N3, ALPHA = 256, 1.2
 POINTS = [(0, 0, 0), (255, 255, 255), (128, 3, 250), (17, 200, 64), (255, 0, 129)]
@@ -93,7 +93,7 @@ def test_precond_256cubed(setup):
 def test_batched_256cubed_sampled_residual(setup, pc):
     fl, op, ref, h = setup
     _say("batched 256^3 pc", pc)
-    fs = [workload_c3(k)["f"] for k in range(2)]
+    fs = [workload_rhs_256cubed(k)["f"] for k in range(2)]
     assert fs[0].shape == (N3,) * 3
     us, infos = fl.solve_batched([op, op], [_dev(f) for f in fs], tol=1e-8, opts=fl.solve_opts(pc=pc, mixed=1))
     for f, u, inf in zip(fs, us, infos):

@@ -148,8 +148,8 @@ def test_precond_masked(n):
 def test_solve_c1_fp64_against_cholesky(pc):
     _say("solve C1 fp64 pc", pc)
     fl = _fl()
-    from workloads import workload_c1
-    w = workload_c1()
+    from workloads import workload_elliptic_64
+    w = workload_elliptic_64()
     n, alpha, h, f = w["n"], w["alpha"], w["h"], w["f"]
     op = fl.Op(2, alpha, h, (n, n))
     ref = O.Operator(2, alpha, h, (n, n))
@@ -248,8 +248,8 @@ def test_full_size_apply_sampled():
     # 1024^2 FP64 apply in the launch configuration the bench uses; sampled outputs
     _say("apply 1024^2 sampled")
     fl = _fl()
-    from workloads import workload_c2
-    w = workload_c2(1.0)
+    from workloads import workload_elliptic_1024
+    w = workload_elliptic_1024(1.0)
     n, alpha, h = w["n"], w["alpha"], w["h"]
     op = fl.Op(2, alpha, h, (n, n))
     u = w["f"]

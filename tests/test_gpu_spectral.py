@@ -79,8 +79,8 @@ def test_precond_spectral(n, shift):
 def test_solve_spectral_against_dense(mixed):
     _say("solve spectral mixed", mixed)
     fl = _fl()
-    from workloads import workload_c1
-    w = workload_c1()
+    from workloads import workload_elliptic_64
+    w = workload_elliptic_64()
     n, alpha, h, f = w["n"], w["alpha"], w["h"], w["f"]
     op = fl.Op(2, alpha, h, (n, n))
     ref = O.Operator(2, alpha, h, (n, n))

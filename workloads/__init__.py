@@ -5,7 +5,7 @@ and initial data (sums of Gaussian bumps evaluated on the interior grid of a
 box, random fields), and the problem lists of the benchmark workloads.
 """
 from .gen import (bump_field, grid_axis, learned_training_plan, power_law_field, random_mask,
-                  white_noise, workload_c1, workload_c2, workload_c3, workload_c4)
+                  white_noise, workload_elliptic_64, workload_elliptic_1024, workload_rhs_256cubed, workload_uneven_steps)
 
-__all__ = ["bump_field", "grid_axis", "workload_c1", "workload_c2", "workload_c3",
-           "workload_c4", "white_noise", "random_mask", "power_law_field", "learned_training_plan"]
+__all__ = ["bump_field", "grid_axis", "workload_elliptic_64", "workload_elliptic_1024", "workload_rhs_256cubed",
+           "workload_uneven_steps", "white_noise", "random_mask", "power_law_field", "learned_training_plan"]

@@ -47,25 +47,25 @@ def random_mask(shape, seed, frac_out=0.2):
     return m
 
 
-def workload_c1(seed=1000):
+def workload_elliptic_64(seed=1000):
     """2D, alpha = 1, 64 x 64 on (-1,1)^2, 8 bumps, widths U[0.1,0.3], amplitudes N(0,1)."""
     f, h = bump_field(64, 2, 8, seed, width=(0.1, 0.3))
     return {"d": 2, "n": 64, "alpha": 1.0, "h": h, "f": f}
 
 
-def workload_c2(alpha=1.0, seed=2000):
+def workload_elliptic_1024(alpha=1.0, seed=2000):
     """2D, 1024 x 1024 on (-1,1)^2, 32 bumps, widths U[0.05,0.2], amplitudes N(0,1)."""
     f, h = bump_field(1024, 2, 32, seed, width=(0.05, 0.2))
     return {"d": 2, "n": 1024, "alpha": alpha, "h": h, "f": f}
 
 
-def workload_c3(k, n=256, seed0=3000):
-    """3D, 256^3 on (-1,1)^3, alpha = 1.2, right-hand side k (16 bumps, C2 distributions)."""
+def workload_rhs_256cubed(k, n=256, seed0=3000):
+    """3D, 256^3 on (-1,1)^3, alpha = 1.2, right-hand side k (16 bumps, widths U[0.05,0.2], amplitudes N(0,1))."""
     f, h = bump_field(n, 3, 16, seed0 + k, width=(0.05, 0.2))
     return {"d": 3, "n": n, "alpha": 1.2, "h": h, "f": f}
 
 
-def workload_c4(nprob=32, seed=4000, sizes=(128, 256, 384, 512)):
+def workload_uneven_steps(nprob=32, seed=4000, sizes=(128, 256, 384, 512)):
     """Batch of uneven 2D backward-Euler problems: n from sizes, alpha ~ U[0.3, 1.8]."""
     rng = np.random.Generator(np.random.PCG64(seed))
     ns = rng.choice(np.array(sizes), size=nprob)
@@ -100,7 +100,7 @@ def power_law_field(shape, seed, slope=(0.0, 3.0)):
 def learned_training_plan(nalpha=100, n=256, seed=5000, lo=0.2, hi=1.9, d=2):
     """Problems of the learned-preconditioner training set: alpha ~ U[lo, hi]
     on an n^d grid of (-1,1)^d, each with a bump right-hand side (32 bumps in
-    2D with C2's distributions, 16 in 3D with C3's) and random-field seeds."""
+    2D, 16 in 3D; widths U[0.05,0.2], amplitudes N(0,1)) and random-field seeds."""
     rng = np.random.Generator(np.random.PCG64(seed))
     alphas = rng.uniform(lo, hi, size=nalpha)
     return [{"n": n, "d": d, "alpha": float(a), "rhs_seed": seed + 1 + i, "field_seed": seed + 100000 + 1000 * i}
