@@ -18,7 +18,9 @@ residual recomputed in FP64 on the GPU at the end of every solve):
   learned_fp64   FP64 flexible CG with the learned preconditioner
 The learned preconditioner is trained first (outside the timed region) on
 solver-generated pairs at 256^2, alpha ~ U[0.2, 1.9]: 100 problems x (10
-iterate errors + 10 random-field errors) = 2000 pairs.  `value` is the time of
+iterate errors + 10 random-field errors) = 2000 pairs, then 4000 Adam steps of
+batch 16 (the length that needed the fewest iterations on held-out 1024^2
+right-hand sides at alpha = 0.5, 1.0, 1.5, among 1500 to 6000).  `value` is the time of
 learned_f32; the plain-FP64 baseline is the faster of fp64_pcg and fp64_cg.
 
 Reported beside it (not part of `value`): per-pass timings and the roofline
@@ -59,7 +61,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 3D and uneven-batch workloads")
     ap.add_argument("--uneven-steps", type=int, default=200)
     ap.add_argument("--train-problems", type=int, default=100)
-    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--train-batch", type=int, default=16)
     ap.add_argument("--no-learned-3d", action="store_true", help="skip the 3D learned-preconditioner workload")
     ap.add_argument("--train3d-problems", type=int, default=40)
