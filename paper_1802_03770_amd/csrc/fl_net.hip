@@ -54,13 +54,24 @@ static_assert(PL<1>::NPARAM == 65633 && PL<3>::NPARAM == 196385, "parameter layo
 
 // Tile of one conv block: 4 output rows x 64 output columns of one slice.
 constexpr int TY = 4, TX = 64, SY = TY + 2, SX = TX + 2;
+// Pixel stride (BF16 elements) of tiles staged in LDS: the 32 channels and 8
+// of padding.  With 64-byte pixels every fourth pixel starts in the same
+// bank, so the 16-byte MFMA fragment reads of 8 or 16 consecutive pixels
+// serialise 4 ways; with 80 bytes (5 x 16, 5 odd) consecutive pixels start
+// in distinct 16-byte bank groups.
+constexpr int CP = 40;
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float bf2f(u16 v) { return __uint_as_float((unsigned)v << 16); }
-__device__ __forceinline__ u16 f2bf(float f) {  // round to nearest even
-  unsigned u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (u16)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (u16)(u >> 16);
+// FP32 -> BF16 rounded to nearest even by the hardware conversion (NaN stays
+// a quiet NaN); the bit-manipulation form costs a dozen instructions and a
+// divergent branch per value where this is half an instruction.
+__device__ __forceinline__ u16 f2bf(float f) { return __builtin_bit_cast(u16, (__bf16)f); }
+// (a, b) -> one 32-bit word of two BF16 (a in the low half), one instruction
+__device__ __forceinline__ unsigned pk2(float a, float b) {
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
 }
 
 __device__ __forceinline__ void ld8(const u16* p, float v[8]) {
@@ -75,7 +86,7 @@ __device__ __forceinline__ void ld8(const u16* p, float v[8]) {
 __device__ __forceinline__ uint4 pk8(const float v[8]) {
   unsigned w[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) w[i] = (unsigned)f2bf(v[2 * i]) | ((unsigned)f2bf(v[2 * i + 1]) << 16);
+  for (int i = 0; i < 4; ++i) w[i] = pk2(v[2 * i], v[2 * i + 1]);
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
@@ -149,9 +160,9 @@ __device__ __forceinline__ void stage8(const Stage& st, const Dims& g, int b, in
 }
 
 // Stage rows y0-1 .. y0+TY and columns x0-1 .. x0+TX of slice z of image b
-// into LDS ([SY][SX][32] bf16), zero outside the grid (a slice z outside
-// 0..D-1 stages zeros).
-template <int SM, int KD>
+// into LDS ([SY][SX] pixels of 32 BF16 channels at stride PS), zero outside
+// the grid (a slice z outside 0..D-1 stages zeros).
+template <int SM, int KD, int PS = CP>
 __device__ __forceinline__ void stage_tile(u16* tile, const Stage& st, const Dims& g, int b, int z, int y0, int x0) {
   const bool zin = z >= 0 && z < g.D;
   for (int e = threadIdx.x; e < SY * SX * 4; e += blockDim.x) {
@@ -164,7 +175,7 @@ __device__ __forceinline__ void stage_tile(u16* tile, const Stage& st, const Dim
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] = 0.f;
     }
-    *(uint4*)(tile + p * CH + c) = pk8(v);
+    *(uint4*)(tile + p * PS + c) = pk8(v);
   }
 }
 
@@ -173,7 +184,7 @@ __device__ __forceinline__ void stage_tile(u16* tile, const Stage& st, const Dim
 // memory latency is paid once per tile instead of once per chunk.  Plain and
 // skip-add staging, and 2D pooling (3D pooling reads 8 pixels per chunk and
 // takes stage_tile).
-template <int SM, int KD>
+template <int SM, int KD, int PS = CP>
 __device__ __forceinline__ void stage_tile_batched(u16* tile, const Stage& st, const Dims& g, int b, int z, int y0,
                                                    int x0) {
   constexpr int NE = SY * SX * 4, NIT = (NE + 255) / 256;
@@ -209,7 +220,7 @@ __device__ __forceinline__ void stage_tile_batched(u16* tile, const Stage& st, c
     if (e >= NE) continue;
     const int c = (e & 3) * 8, p = e >> 2;
     if (SM == SM_PLAIN) {
-      *(uint4*)(tile + p * CH + c) = q[it][0];
+      *(uint4*)(tile + p * PS + c) = q[it][0];
     } else {
       float v[8], t[8];
       const unsigned* w0 = (const unsigned*)&q[it][0];
@@ -232,7 +243,7 @@ __device__ __forceinline__ void stage_tile_batched(u16* tile, const Stage& st, c
       if (SM == SM_POOL)
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] *= 0.25f;
-      *(uint4*)(tile + p * CH + c) = pk8(v);
+      *(uint4*)(tile + p * PS + c) = pk8(v);
     }
   }
 }
@@ -269,7 +280,7 @@ __device__ __forceinline__ void store_rows(const f32x16& acc0, const f32x16& acc
                                            const float* __restrict__ bias, u16* __restrict__ out, const Dims& g, int b,
                                            int z, int y0, int x0, u16* __restrict__ pout = nullptr) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  u16* ot = tile + wave * 64 * CH;
+  u16* ot = tile + wave * 64 * CP;
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
     const f32x16& a = m ? acc1 : acc0;
@@ -283,9 +294,8 @@ __device__ __forceinline__ void store_rows(const f32x16& acc0, const f32x16& acc
         v[i] = a[4 * q + i];
         if (EPI == EPI_RELU) v[i] = fmaxf(v[i] + bias[cb + i], 0.f);
       }
-      const unsigned lo = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
-      const unsigned hi = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
-      *(uint2*)(ot + pl * CH + cb) = make_uint2(lo, hi);
+      const unsigned lo = pk2(v[0], v[1]), hi = pk2(v[2], v[3]);
+      *(uint2*)(ot + pl * CP + cb) = make_uint2(lo, hi);
     }
   }
   __syncthreads();
@@ -299,7 +309,7 @@ __device__ __forceinline__ void store_rows(const f32x16& acc0, const f32x16& acc
       for (int i = 0; i < 8; ++i) v[i] = 0.f;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        ld8(tile + ((2 * wr + (k >> 1)) * 64 + 2 * pc + (k & 1)) * CH + q, t);
+        ld8(tile + ((2 * wr + (k >> 1)) * 64 + 2 * pc + (k & 1)) * CP + q, t);
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] += t[i];
       }
@@ -314,14 +324,14 @@ __device__ __forceinline__ void store_rows(const f32x16& acc0, const f32x16& acc
   for (int k = 0; k < 4; ++k) {
     const int e = lane + 64 * k, pl = e >> 2, qq = (e & 3) * 8;
     const int px = x0 + pl;
-    if (px < g.W) *(uint4*)(out + pix(g, b, z, yo, px) + qq) = *(const uint4*)(ot + pl * CH + qq);
+    if (px < g.W) *(uint4*)(out + pix(g, b, z, yo, px) + qq) = *(const uint4*)(ot + pl * CP + qq);
   }
 }
 
 template <int SM, int EPI, int KD>
 __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict__ wpack, const float* __restrict__ bias,
                                                 u16* __restrict__ out, Dims g, u16* __restrict__ pout) {
-  __shared__ __align__(16) u16 tile[SY * SX * CH];
+  __shared__ __align__(16) u16 tile[SY * SX * CP];
   int b, z, y0, x0;
   tile_of(blockIdx.x, g, b, z, y0, x0);
   if (b >= g.B) return;
@@ -345,9 +355,9 @@ __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict_
       const int ky = tap / 3, kx = tap % 3;
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
-        const u16* p0 = tile + ((wave + ky) * SX + (lane & 31) + kx) * CH + half * 16 + (lane >> 5) * 8;
+        const u16* p0 = tile + ((wave + ky) * SX + (lane & 31) + kx) * CP + half * 16 + (lane >> 5) * 8;
         const bf16x8 b0 = *(const bf16x8*)p0;
-        const bf16x8 b1 = *(const bf16x8*)(p0 + 32 * CH);
+        const bf16x8 b1 = *(const bf16x8*)(p0 + 32 * CP);
         acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[tap * 2 + half], b0, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[tap * 2 + half], b1, acc1, 0, 0, 0);
       }
@@ -367,7 +377,7 @@ __global__ __launch_bounds__(256) void k_cin_mfma(const float* __restrict__ x, c
                                                   const u16* __restrict__ wpack, const float* __restrict__ bias,
                                                   u16* __restrict__ out, Dims g, u16* __restrict__ pout) {
   constexpr int K = 9 * KD, S = (2 * K + 15) / 16;
-  __shared__ __align__(16) u16 tile[SY * SX * CH];  // output staging
+  __shared__ __align__(16) u16 tile[TY * TX * CP];  // output staging
   __shared__ unsigned xin[KD][SY * SX];             // bf16 pair (x, alpha - 1) per pixel
   int b, z, y0, x0;
   tile_of(blockIdx.x, g, b, z, y0, x0);
@@ -423,7 +433,7 @@ template <int KD>
 __global__ __launch_bounds__(256) void k_out_mfma(const u16* __restrict__ c0, const u16* __restrict__ wpack,
                                                   const float* __restrict__ bias, Dims g, float* __restrict__ yout) {
   constexpr int NQ = SY * SX, NCH = (NQ + 31) / 32;
-  __shared__ __align__(16) u16 tile[SY * SX * CH];
+  __shared__ __align__(16) u16 tile[SY * SX * CH];  // unpadded: tile + zt fit four blocks per CU
   __shared__ float zt[NQ][9];
   int b, z, y0, x0;
   tile_of(blockIdx.x, g, b, z, y0, x0);
@@ -437,7 +447,7 @@ __global__ __launch_bounds__(256) void k_out_mfma(const u16* __restrict__ c0, co
     const int zi = z + kz - (KD == 3 ? 1 : 0);
     if (zi < 0 || zi >= g.D) continue;  // zero slice (uniform over the block)
     if (kz > 0) __syncthreads();         // every thread is done with the previous slice
-    stage_tile_batched<SM_PLAIN, KD>(tile, st, g, b, zi, y0, x0);
+    stage_tile_batched<SM_PLAIN, KD, CH>(tile, st, g, b, zi, y0, x0);
     const bf16x8 a0 = *(const bf16x8*)(wpack + ((long)(kz * 2) * 64 + lane) * 8);
     const bf16x8 a1 = *(const bf16x8*)(wpack + ((long)(kz * 2 + 1) * 64 + lane) * 8);
     __syncthreads();
@@ -503,7 +513,7 @@ __device__ __forceinline__ void stage_grad(u16* gt, const Stage& sg, const Dims&
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] = 0.f;
     }
-    *(uint4*)(gt + p * CH + c) = pk8(v);
+    *(uint4*)(gt + p * CP + c) = pk8(v);
   }
 }
 
@@ -514,8 +524,8 @@ __device__ __forceinline__ void stage_grad(u16* gt, const Stage& sg, const Dims&
 // z + kz - 1 (3D) into rows kz*288 .. of its partial (stride L32SZ).
 template <int SMI, int SMG, int KD>
 __global__ __launch_bounds__(256) void k_conv32_wgrad(Stage si, Stage sg, float* __restrict__ part, Dims g) {
-  __shared__ __align__(16) u16 xt[SY * SX * CH];
-  __shared__ __align__(16) u16 gt[TY * TX * CH];
+  __shared__ __align__(16) u16 xt[SY * SX * CP];
+  __shared__ __align__(16) u16 gt[TY * TX * CP];
   const int co = threadIdx.x & 31, grp = threadIdx.x >> 5;  // 8 groups of 36 (tap, ci)
   const int kz = blockIdx.y;
   const long ntiles = (long)g.B * g.D * ((g.H + TY - 1) / TY) * ((g.W + TX - 1) / TX);
@@ -531,12 +541,12 @@ __global__ __launch_bounds__(256) void k_conv32_wgrad(Stage si, Stage sg, float*
     __syncthreads();
     for (int p = 0; p < TY * TX; ++p) {
       const int ly = p / TX, lx = p % TX;
-      const float gv = bf2f(gt[p * CH + co]);
+      const float gv = bf2f(gt[p * CP + co]);
       accb += gv;
 #pragma unroll
       for (int j = 0; j < 36; ++j) {
         const int q = grp * 36 + j, tap = q >> 5, ci = q & 31;
-        acc[j] += bf2f(xt[((ly + tap / 3) * SX + lx + tap % 3) * CH + ci]) * gv;
+        acc[j] += bf2f(xt[((ly + tap / 3) * SX + lx + tap % 3) * CP + ci]) * gv;
       }
     }
     __syncthreads();
@@ -559,7 +569,7 @@ __global__ __launch_bounds__(256) void k_conv32_wgrad(Stage si, Stage sg, float*
 template <int SMG, int KD>
 __global__ __launch_bounds__(256) void k_cin_wgrad(const float* __restrict__ x, const float* __restrict__ alpha, Stage sg,
                                                    float* __restrict__ part, Dims g) {
-  __shared__ __align__(16) u16 gt[TY * TX * CH];
+  __shared__ __align__(16) u16 gt[TY * TX * CP];
   __shared__ float xs[SY * SX][2];
   const int kz = blockIdx.y;
   const long ntiles = (long)g.B * g.D * ((g.H + TY - 1) / TY) * ((g.W + TX - 1) / TX);
@@ -584,10 +594,10 @@ __global__ __launch_bounds__(256) void k_cin_wgrad(const float* __restrict__ x, 
       if (e < 576) {
         const int tap = e / 64, ci = (e / 32) & 1, co = e & 31;
         for (int p = 0; p < TY * TX; ++p)
-          s += xs[(p / TX + tap / 3) * SX + p % TX + tap % 3][ci] * bf2f(gt[p * CH + co]);
+          s += xs[(p / TX + tap / 3) * SX + p % TX + tap % 3][ci] * bf2f(gt[p * CP + co]);
       } else {
         const int co = e - 576;
-        for (int p = 0; p < TY * TX; ++p) s += bf2f(gt[p * CH + co]);
+        for (int p = 0; p < TY * TX; ++p) s += bf2f(gt[p * CP + co]);
       }
       acc[r] += s;
     }
@@ -639,7 +649,7 @@ __global__ __launch_bounds__(256) void k_cout_bwd(const float* __restrict__ gy, 
 template <int KD>
 __global__ __launch_bounds__(256) void k_cout_wgrad(const u16* __restrict__ c0, const float* __restrict__ gy,
                                                     float* __restrict__ part, Dims g) {
-  __shared__ __align__(16) u16 xt[SY * SX * CH];
+  __shared__ __align__(16) u16 xt[SY * SX * CP];
   __shared__ float gs[TY * TX];
   const int kz = blockIdx.y;
   const long ntiles = (long)g.B * g.D * ((g.H + TY - 1) / TY) * ((g.W + TX - 1) / TX);
@@ -662,7 +672,7 @@ __global__ __launch_bounds__(256) void k_cout_wgrad(const u16* __restrict__ c0, 
       if (e < 288) {
         const int tap = e / CH, ci = e % CH;
         for (int p = 0; p < TY * TX; ++p)
-          s += bf2f(xt[((p / TX + tap / 3) * SX + p % TX + tap % 3) * CH + ci]) * gs[p];
+          s += bf2f(xt[((p / TX + tap / 3) * SX + p % TX + tap % 3) * CP + ci]) * gs[p];
       } else {
         for (int p = 0; p < TY * TX; ++p) s += gs[p];
       }

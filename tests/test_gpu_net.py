@@ -100,6 +100,36 @@ def test_net_grad_relu_active_against_oracle(d, shape):
     _check_grad(g, want, d, per_layer=2e-2, whole=1e-2, cos_min=0.9999)
 
 
+@pytest.mark.parametrize("B,H,W", [(1, 24, 136), (2, 16, 64), (1, 40, 128)])
+def test_net_forward_tiles_pixelwise_against_oracle(B, H, W):
+    # Every layer runs on 4 x 64 tiles with a one-pixel halo staged in LDS
+    # (the coarse levels on the same tiles of smaller grids): these shapes
+    # cross tile rows and columns at every level and end in ragged tiles.
+    # With parameters that keep every ReLU active the BF16 error is smooth,
+    # so a wrong halo or boundary padding shows as a pixel far above the rest.
+    _say("net forward tiles", B, H, W)
+    fl = _fl()
+    th = _params_relu_active(9, 2)
+    rng = np.random.Generator(np.random.PCG64(77 + H + W))
+    x = rng.standard_normal((B, H, W)).astype(np.float32)
+    al = rng.uniform(0.2, 1.9, size=B)
+    th64 = th.astype(np.float32).astype(np.float64)
+    want, act = NN.forward(th64, x.astype(np.float64), al, keep=True)
+    assert min(float(act[k].min()) for k in ("a0", "a1", "a2", "a3", "c3", "c2", "c1", "c0")) > 0.05
+    net = fl.Net(params=th, d=2)
+    y = net.forward(torch.from_numpy(x).cuda(), list(al)).cpu().numpy()
+    err = np.abs(y - want)
+    scale = float(np.abs(want).max())
+    assert _rl2(y, want) <= 2e-2, _rl2(y, want)
+    assert float(err.max()) <= 3e-2 * scale, (float(err.max()) / scale, np.unravel_index(err.argmax(), err.shape))
+    # tile-edge columns and rows are no worse than the interior
+    cols = [c for c in (0, 63, 64, 127, 128, W - 1) if c < W]
+    rows = [r for r in range(0, H, 4)] + [r for r in range(3, H, 4)] + [H - 1]
+    interior = float(np.sqrt(np.mean(err ** 2)))
+    assert float(err[:, :, cols].max()) <= 10 * interior + 1e-3 * scale
+    assert float(err[:, rows, :].max()) <= 10 * interior + 1e-3 * scale
+
+
 def _params(seed):
     th = NN.init_params(seed)
     rng = np.random.Generator(np.random.PCG64(seed + 50))
