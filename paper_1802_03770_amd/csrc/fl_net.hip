@@ -180,50 +180,59 @@ __device__ __forceinline__ void stage_tile(u16* tile, const Stage& st, const Dim
 }
 
 // Forward-mode staging with all global loads of a lane issued before any LDS
-// store (the tile has SY*SX*4 = 1584 16-byte chunks, NIT = 7 per lane): the
-// memory latency is paid once per tile instead of once per chunk.  Plain and
-// skip-add staging, and 2D pooling (3D pooling reads 8 pixels per chunk and
-// takes stage_tile).
+// store: the memory latency is paid once per tile instead of once per chunk.
+// Plain and skip-add staging, and 2D pooling (3D pooling reads 8 pixels per
+// chunk and takes stage_tile).  The 256 threads take one staged row per step
+// (64 pixels x 4 chunks of 8 channels: columns x0 .. x0+TX-1), so the row's
+// address is uniform across the block and a lane's column offset is fixed;
+// a last step takes the two halo columns x0-1 and x0+TX of every row
+// (threads 0 .. 8 SY - 1).
 template <int SM, int KD, int PS = CP>
 __device__ __forceinline__ void stage_tile_batched(u16* tile, const Stage& st, const Dims& g, int b, int z, int y0,
                                                    int x0) {
-  constexpr int NE = SY * SX * 4, NIT = (NE + 255) / 256;
   constexpr int NQ = SM == SM_POOL ? 4 : SM == SM_UPADD ? 2 : 1;
   static_assert(SM == SM_PLAIN || SM == SM_UPADD || (SM == SM_POOL && KD == 1), "batched staging modes");
+  static_assert(TX * 4 == 256 && 8 * SY <= 256, "one staged row per step of 256 threads");
+  const int t = threadIdx.x, c = (t & 3) * 8;
   const bool zin = z >= 0 && z < g.D;
   const Dims gf = finer<KD>(g), gc = coarser<KD>(g);
-  uint4 q[NIT][NQ];
+  const int xm = x0 + (t >> 2);                                // column of the row steps
+  const int hr = t >> 3, hs = (t >> 2) & 1;                    // halo step: row, side
+  const int xh = hs ? x0 + TX : x0 - 1;
+  // pixel (y, x) of slice zz of a level d, this lane's 8 channels
+  auto at = [&](const u16* base, const Dims& d, int zz, int y, int x) {
+    return (const uint4*)(base + (((long)b * d.D + zz) * d.H + y) * (long)d.W * CH + (unsigned)(x * CH + c));
+  };
+  uint4 q[SY + 1][NQ];
 #pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int e = threadIdx.x + it * 256;
-    const int c = (e & 3) * 8, p = e >> 2;
-    const int yy = y0 + p / SX - 1, xx = x0 + p % SX - 1;
-    const bool ok = zin && e < NE && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W;
+  for (int r = 0; r <= SY; ++r) {
+    const bool halo = r == SY;
+    const int yy = y0 - 1 + (halo ? hr : r), xx = halo ? xh : xm;
+    const bool ok = zin && (!halo || t < 8 * SY) && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W;
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) q[it][k] = make_uint4(0, 0, 0, 0);
+    for (int k = 0; k < NQ; ++k) q[r][k] = make_uint4(0, 0, 0, 0);
     if (ok) {
       if constexpr (SM == SM_PLAIN) {
-        q[it][0] = *(const uint4*)(st.s0 + pix(g, b, z, yy, xx) + c);
+        q[r][0] = *at(st.s0, g, z, yy, xx);
       } else if constexpr (SM == SM_UPADD) {
-        q[it][0] = *(const uint4*)(st.s0 + pix(g, b, z, yy, xx) + c);
-        q[it][1] = *(const uint4*)(st.s1 + pix(gc, b, KD == 3 ? z >> 1 : 0, yy >> 1, xx >> 1) + c);
+        q[r][0] = *at(st.s0, g, z, yy, xx);
+        q[r][1] = *at(st.s1, gc, KD == 3 ? z >> 1 : 0, yy >> 1, xx >> 1);
       } else {  // SM_POOL, 2D
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          q[it][k] = *(const uint4*)(st.s0 + pix(gf, b, 0, 2 * yy + (k >> 1), 2 * xx + (k & 1)) + c);
+        for (int k = 0; k < 4; ++k) q[r][k] = *at(st.s0, gf, 0, 2 * yy + (k >> 1), 2 * xx + (k & 1));
       }
     }
   }
 #pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int e = threadIdx.x + it * 256;
-    if (e >= NE) continue;
-    const int c = (e & 3) * 8, p = e >> 2;
+  for (int r = 0; r <= SY; ++r) {
+    const bool halo = r == SY;
+    if (halo && t >= 8 * SY) continue;
+    const int p = halo ? hr * SX + (hs ? SX - 1 : 0) : r * SX + 1 + (t >> 2);
     if (SM == SM_PLAIN) {
-      *(uint4*)(tile + p * PS + c) = q[it][0];
+      *(uint4*)(tile + p * PS + c) = q[r][0];
     } else {
-      float v[8], t[8];
-      const unsigned* w0 = (const unsigned*)&q[it][0];
+      float v[8], u[8];
+      const unsigned* w0 = (const unsigned*)&q[r][0];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         v[2 * i] = __uint_as_float(w0[i] << 16);
@@ -231,14 +240,14 @@ __device__ __forceinline__ void stage_tile_batched(u16* tile, const Stage& st, c
       }
 #pragma unroll
       for (int k = 1; k < NQ; ++k) {
-        const unsigned* wk = (const unsigned*)&q[it][k];
+        const unsigned* wk = (const unsigned*)&q[r][k];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          t[2 * i] = __uint_as_float(wk[i] << 16);
-          t[2 * i + 1] = __uint_as_float(wk[i] & 0xffff0000u);
+          u[2 * i] = __uint_as_float(wk[i] << 16);
+          u[2 * i + 1] = __uint_as_float(wk[i] & 0xffff0000u);
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] += t[i];
+        for (int i = 0; i < 8; ++i) v[i] += u[i];
       }
       if (SM == SM_POOL)
 #pragma unroll
@@ -246,6 +255,15 @@ __device__ __forceinline__ void stage_tile_batched(u16* tile, const Stage& st, c
       *(uint4*)(tile + p * PS + c) = pk8(v);
     }
   }
+}
+
+// Tile of the block in a launch over conv_grid (x: tile column, y: tile row,
+// z: image * D + slice): no division on the tile index.
+template <int KD> __device__ __forceinline__ void tile_here(const Dims& g, int& b, int& z, int& y0, int& x0) {
+  x0 = blockIdx.x * TX;
+  y0 = blockIdx.y * TY;
+  z = KD == 3 ? (int)(blockIdx.z % (unsigned)g.D) : 0;
+  b = KD == 3 ? (int)(blockIdx.z / (unsigned)g.D) : (int)blockIdx.z;
 }
 
 // Decode a tile index of a level: (b, z, tile row, tile column).
@@ -333,7 +351,7 @@ __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict_
                                                 u16* __restrict__ out, Dims g, u16* __restrict__ pout) {
   __shared__ __align__(16) u16 tile[SY * SX * CP];
   int b, z, y0, x0;
-  tile_of(blockIdx.x, g, b, z, y0, x0);
+  tile_here<KD>(g, b, z, y0, x0);
   if (b >= g.B) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   f32x16 acc0 = {}, acc1 = {};
@@ -380,7 +398,7 @@ __global__ __launch_bounds__(256) void k_cin_mfma(const float* __restrict__ x, c
   __shared__ __align__(16) u16 tile[TY * TX * CP];  // output staging
   __shared__ unsigned xin[KD][SY * SX];             // bf16 pair (x, alpha - 1) per pixel
   int b, z, y0, x0;
-  tile_of(blockIdx.x, g, b, z, y0, x0);
+  tile_here<KD>(g, b, z, y0, x0);
   if (b >= g.B) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const unsigned am1 = (unsigned)f2bf(alpha[b] - 1.f) << 16;
@@ -436,7 +454,7 @@ __global__ __launch_bounds__(256) void k_out_mfma(const u16* __restrict__ c0, co
   __shared__ __align__(16) u16 tile[SY * SX * CH];  // unpadded: tile + zt fit four blocks per CU
   __shared__ float zt[NQ][9];
   int b, z, y0, x0;
-  tile_of(blockIdx.x, g, b, z, y0, x0);
+  tile_here<KD>(g, b, z, y0, x0);
   if (b >= g.B) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ly = threadIdx.x / TX, lx = threadIdx.x % TX;  // this thread's output pixel
@@ -465,14 +483,10 @@ __global__ __launch_bounds__(256) void k_out_mfma(const u16* __restrict__ c0, co
       // rows (taps) of lane l: 8 (r/4) + 4 (l/32) + r%4 -> lanes < 32 hold
       // m = 0..3 (r = 0..3) and 8 (r = 4); lanes >= 32 hold m = 4..7
       if (q < NQ) {
-        if (lane < 32) {
+        const int m0 = (lane >> 5) * 4;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) zt[q][r] = d[r];
-          zt[q][8] = d[4];
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) zt[q][4 + r] = d[r];
-        }
+        for (int r = 0; r < 4; ++r) zt[q][m0 + r] = d[r];
+        if (lane < 32) zt[q][8] = d[4];
       }
     }
     __syncthreads();
@@ -984,6 +998,7 @@ static fl_status net_part(fl_net net, long n) {
 }
 
 static int conv_blocks(const Dims& g) { return g.B * g.D * ((g.H + TY - 1) / TY) * ((g.W + TX - 1) / TX); }
+static dim3 conv_grid(const Dims& g) { return dim3((g.W + TX - 1) / TX, (g.H + TY - 1) / TY, g.B * g.D); }
 
 // 2D networks take D = 1; 3D networks a depth that is a multiple of 8 too
 static fl_status check_grid(const fl_net net, int B, int D, int H, int W) {
@@ -1007,7 +1022,7 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
   // pooled inputs of the down path, p[l] = pool a[l-1]: in 2D every layer
   // writes the next one's from its output tile, in 3D k_pool forms it
   u16* const* pl = net->pool;
-  LAUNCH(k_cin_mfma<KD>, dim3(conv_blocks(g0)), dim3(256), 0, s, x, alpha, fw(NL32), th + P::OFF_CIN_B, a[A0], g0,
+  LAUNCH(k_cin_mfma<KD>, conv_grid(g0), dim3(256), 0, s, x, alpha, fw(NL32), th + P::OFF_CIN_B, a[A0], g0,
          KD == 1 ? pl[1] : (u16*)nullptr);
   Dims g = g0;
   // down path
@@ -1019,12 +1034,12 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
       LAUNCH(k_pool<KD>, dim3(nblocks_vec((long)g.B * g.D * g.H * g.W * 4)), dim3(256), 0, s,
              (const u16*)a[A0 + l - 1], pl[l], g);
     Stage st = {pl[l], nullptr, nullptr};
-    LAUNCH((k_conv32<SM_PLAIN, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(lay[l - 1]),
+    LAUNCH((k_conv32<SM_PLAIN, EPI_RELU, KD>), conv_grid(g), dim3(256), 0, s, st, fw(lay[l - 1]),
            bias(lay[l - 1]), a[A0 + l], g, po);
   }
   {
     Stage st = {a[A3], nullptr, nullptr};
-    LAUNCH((k_conv32<SM_PLAIN, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(LB3), bias(LB3), a[C3],
+    LAUNCH((k_conv32<SM_PLAIN, EPI_RELU, KD>), conv_grid(g), dim3(256), 0, s, st, fw(LB3), bias(LB3), a[C3],
            g, (u16*)nullptr);
   }
   // up path: c_l = relu(u_l(a_l + up c_{l+1}))
@@ -1033,10 +1048,10 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
   for (int k = 0; k < 3; ++k) {
     g = dbl(g);
     Stage st = {a[askip[k]], a[acoarse[k]], nullptr};
-    LAUNCH((k_conv32<SM_UPADD, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st, fw(ulay[k]), bias(ulay[k]),
+    LAUNCH((k_conv32<SM_UPADD, EPI_RELU, KD>), conv_grid(g), dim3(256), 0, s, st, fw(ulay[k]), bias(ulay[k]),
            a[adst[k]], g, (u16*)nullptr);
   }
-  LAUNCH(k_out_mfma<KD>, dim3(conv_blocks(g0)), dim3(256), 0, s, (const u16*)a[C0], fw(NL32 + 1),
+  LAUNCH(k_out_mfma<KD>, conv_grid(g0), dim3(256), 0, s, (const u16*)a[C0], fw(NL32 + 1),
          th + P::OFF_OUT + P::K * CH, g0, net->y);
   return FL_OK;
 }
@@ -1077,7 +1092,7 @@ template <int KD> static fl_status net_backward_t(fl_net net, const float* x, co
   auto layer = [&](int L, auto smi, auto smg, Stage si, Stage sg, u16* gin, Dims g) -> fl_status {
     constexpr int SMI = decltype(smi)::value, SMG = decltype(smg)::value;
     if (gin)
-      LAUNCH((k_conv32<SMG, EPI_NONE, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, sg, bw(L), (const float*)nullptr,
+      LAUNCH((k_conv32<SMG, EPI_NONE, KD>), conv_grid(g), dim3(256), 0, s, sg, bw(L), (const float*)nullptr,
              gin, g, (u16*)nullptr);
     const int nb = wgrad_blocks(g);
     LAUNCH((k_conv32_wgrad<SMI, SMG, KD>), dim3(nb, KD), dim3(256), 0, s, si, sg, net->part, g);
@@ -1331,17 +1346,17 @@ template <int KD> static fl_status profile_one(fl_net net, int which, Dims g) {
   if (which == 0) return net_forward(net, net->xb, net->ab, g.B, g.D, g.H, g.W);
   if (which == 1) {
     Stage st = {a[A0], a[C1], nullptr};
-    LAUNCH((k_conv32<SM_UPADD, EPI_RELU, KD>), dim3(conv_blocks(g)), dim3(256), 0, s, st,
+    LAUNCH((k_conv32<SM_UPADD, EPI_RELU, KD>), conv_grid(g), dim3(256), 0, s, st,
            (const u16*)(net->fw + LU0 * P::PACK), (const float*)(net->th + P::OFF_L32 + LU0 * P::L32SZ + P::L32W),
            a[C0], g, (u16*)nullptr);
     return FL_OK;
   }
   if (which == 2) {
-    LAUNCH(k_cin_mfma<KD>, dim3(conv_blocks(g)), dim3(256), 0, s, (const float*)net->xb, (const float*)net->ab,
+    LAUNCH(k_cin_mfma<KD>, conv_grid(g), dim3(256), 0, s, (const float*)net->xb, (const float*)net->ab,
            (const u16*)(net->fw + NL32 * P::PACK), (const float*)(net->th + P::OFF_CIN_B), a[A0], g, (u16*)nullptr);
     return FL_OK;
   }
-  LAUNCH(k_out_mfma<KD>, dim3(conv_blocks(g)), dim3(256), 0, s, (const u16*)a[C0],
+  LAUNCH(k_out_mfma<KD>, conv_grid(g), dim3(256), 0, s, (const u16*)a[C0],
          (const u16*)(net->fw + (NL32 + 1) * P::PACK), (const float*)(net->th + P::OFF_OUT + P::K * CH), g, net->y);
   return FL_OK;
 }
