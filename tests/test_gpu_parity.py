@@ -195,6 +195,9 @@ def test_solve_mixed_precision_true_residual(n):
     res = np.linalg.norm(f - ref.apply(u, method="dft")) / np.linalg.norm(f)
     assert res <= 1e-8
     assert info["outer_iters"] >= 1
+    # the reported true residual is that of the returned u (the refinement
+    # loop's last FP64 evaluation), here against the oracle's direct sums
+    assert abs(info["rel_res_true"] - res) <= 1e-3 * res + 1e-13, (info["rel_res_true"], res)
 
 
 def test_solve_masked():
@@ -212,6 +215,15 @@ def test_solve_masked():
     got = u.cpu().numpy().ravel()
     assert np.all(got[m.ravel() == 0] == 0)
     assert _rel(got[m.ravel() == 1], xs) <= 1e-9
+    # mixed precision on the mask: the reported true residual is that of the
+    # returned u on the domain (f vanishes off the mask)
+    u2, info2 = op.solve(_dev(f), mask=_dev(m, torch.uint8), tol=1e-9, opts=fl.solve_opts(mixed=1))
+    g2 = u2.cpu().numpy().ravel()
+    assert np.all(g2[m.ravel() == 0] == 0)
+    fd = f.ravel()[m.ravel() == 1]
+    res2 = np.linalg.norm(fd - A @ g2[m.ravel() == 1]) / np.linalg.norm(fd)
+    assert res2 <= 1e-9 and info2["outer_iters"] >= 1
+    assert abs(info2["rel_res_true"] - res2) <= 1e-3 * res2 + 1e-13, (info2["rel_res_true"], res2)
 
 
 @pytest.mark.parametrize("theta", [0.5, 1.0])
