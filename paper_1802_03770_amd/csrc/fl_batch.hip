@@ -535,6 +535,9 @@ static fl_status batch_solve(Batch& bt, double tol, const fl_solve_opts* o, int 
     return FL_OK;
   };
   std::vector<double> rr, ff(np);
+  // the mixed loop ends with the true FP64 residuals of the returned x in rr:
+  // its last evaluation precedes every exit, and finished problems keep x
+  bool have_final = false;
   STCHK(read_all(bt, bt.sc64, s));
   for (int p = 0; p < np; ++p) ff[p] = bt.hsc[p].ff;
   if (!mixed) {
@@ -552,6 +555,7 @@ static fl_status batch_solve(Batch& bt, double tol, const fl_solve_opts* o, int 
       out[p].status = sc.done == 1 ? FL_OK : sc.done == 2 ? FL_E_NOCONV : FL_E_BREAKDOWN;
     }
   } else {
+    have_final = true;
     const double itol = (o && o->inner_tol > 0) ? o->inner_tol : 1e-4;
     const int max_outer = (o && o->max_outer > 0) ? o->max_outer : 12;
     std::vector<char> active(np, 1);
@@ -595,7 +599,9 @@ static fl_status batch_solve(Batch& bt, double tol, const fl_solve_opts* o, int 
     }
   }
   // true residuals (FP64) into q
-  {
+  if (have_final) {
+    for (int p = 0; p < np; ++p) out[p].rel_res_true = ff[p] > 0 ? std::sqrt(rr[p] / ff[p]) : 0.0;
+  } else {
     if (!bt.d_true) {  // residual role writing q, built once per batch
       std::vector<Prob> tr = bt.t64.h_res;
       for (int p = 0; p < np; ++p) tr[p].out = bt.b64[p].q;
