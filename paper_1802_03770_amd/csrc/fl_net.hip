@@ -109,7 +109,12 @@ struct Stage {
 // Grid of one level: D = 1 for 2D networks.
 struct Dims {
   int B, D, H, W;
+  // inference inside flexible CG: the device done flag; a forward kernel
+  // returns at once when it is set (an iteration enqueued ahead of the host's
+  // convergence test is then nearly free)
+  const double* stop = nullptr;
 };
+__device__ __forceinline__ bool stopped(const Dims& g) { return g.stop && *g.stop != 0.0; }
 __device__ __forceinline__ long pix(const Dims& g, int b, int z, int y, int x) {
   return ((((long)b * g.D + z) * g.H + y) * g.W + x) * CH;
 }
@@ -350,6 +355,7 @@ template <int SM, int EPI, int KD>
 __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict__ wpack, const float* __restrict__ bias,
                                                 u16* __restrict__ out, Dims g, u16* __restrict__ pout) {
   __shared__ __align__(16) u16 tile[SY * SX * CP];
+  if (stopped(g)) return;
   int b, z, y0, x0;
   tile_here<KD>(g, b, z, y0, x0);
   if (b >= g.B) return;
@@ -397,6 +403,7 @@ __global__ __launch_bounds__(256) void k_cin_mfma(const float* __restrict__ x, c
   constexpr int K = 9 * KD, S = (2 * K + 15) / 16;
   __shared__ __align__(16) u16 tile[TY * TX * CP];  // output staging
   __shared__ unsigned xin[KD][SY * SX];             // bf16 pair (x, alpha - 1) per pixel
+  if (stopped(g)) return;
   int b, z, y0, x0;
   tile_here<KD>(g, b, z, y0, x0);
   if (b >= g.B) return;
@@ -453,6 +460,7 @@ __global__ __launch_bounds__(256) void k_out_mfma(const u16* __restrict__ c0, co
   constexpr int NQ = SY * SX, NCH = (NQ + 31) / 32;
   __shared__ __align__(16) u16 tile[SY * SX * CH];  // unpadded: tile + zt fit four blocks per CU
   __shared__ float zt[NQ][9];
+  if (stopped(g)) return;
   int b, z, y0, x0;
   tile_here<KD>(g, b, z, y0, x0);
   if (b >= g.B) return;
@@ -501,6 +509,7 @@ __global__ __launch_bounds__(256) void k_out_mfma(const u16* __restrict__ c0, co
 // coarse pixel per thread, the mean over the 2 x 2 x 2 block exactly as the
 // pooling staging forms it.
 template <int KD> __global__ __launch_bounds__(256) void k_pool(const u16* __restrict__ src, u16* __restrict__ dst, Dims gc) {
+  if (stopped(gc)) return;
   const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (t >= (long)gc.B * gc.D * gc.H * gc.W * 4) return;
   const int c = (int)(t & 3) * 8;
@@ -802,6 +811,7 @@ struct PadGrid {
 };
 template <typename T>
 __global__ void k_net_in(const T* __restrict__ r, float* __restrict__ xin, PadGrid q, const double* __restrict__ rr) {
+  if (rr[1] != 0.0) return;  // flexible CG already done (rr[1] is its flag)
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= (long)q.P0 * q.P1 * q.P2) return;
   const double ms = *rr / ((double)q.m0 * q.m1 * q.m2);
@@ -813,6 +823,7 @@ __global__ void k_net_in(const T* __restrict__ r, float* __restrict__ xin, PadGr
 template <typename T>
 __global__ void k_net_out(const T* __restrict__ r, const float* __restrict__ y, T* __restrict__ w, PadGrid q,
                           const double* __restrict__ rr) {
+  if (rr[1] != 0.0) return;  // flexible CG already done
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long N = (long)q.m0 * q.m1 * q.m2;
   if (i >= N) return;
@@ -892,7 +903,10 @@ __global__ void k_fcg_check(Prob pb, double* __restrict__ fs, double thr) {
   if (threadIdx.x == 0 && fs[5] == 0.0) {
     fs[4] = rr;
     const double pq = fs[2];
-    if (rr <= thr || !isfinite(rr) || !(pq > 0.0) || !isfinite(pq)) fs[5] = 1.0;
+    if (rr <= thr || !isfinite(rr) || !(pq > 0.0) || !isfinite(pq)) {
+      fs[5] = 1.0;
+      pb.sc->done = 1;  // the sine and FFT passes of later iterations return at once
+    }
   }
 }
 
@@ -1017,8 +1031,8 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
   const float* th = net->th;
   auto bias = [&](int L) { return th + P::OFF_L32 + L * P::L32SZ + P::L32W; };
   auto fw = [&](int L) { return (const u16*)(net->fw + L * P::PACK); };
-  auto half = [](Dims g) { return Dims{g.B, KD == 3 ? g.D / 2 : 1, g.H / 2, g.W / 2}; };
-  auto dbl = [](Dims g) { return Dims{g.B, KD == 3 ? g.D * 2 : 1, g.H * 2, g.W * 2}; };
+  auto half = [](Dims g) { return Dims{g.B, KD == 3 ? g.D / 2 : 1, g.H / 2, g.W / 2, g.stop}; };
+  auto dbl = [](Dims g) { return Dims{g.B, KD == 3 ? g.D * 2 : 1, g.H * 2, g.W * 2, g.stop}; };
   // pooled inputs of the down path, p[l] = pool a[l-1]: in 2D every layer
   // writes the next one's from its output tile, in 3D k_pool forms it
   u16* const* pl = net->pool;
@@ -1056,10 +1070,11 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
   return FL_OK;
 }
 
-static fl_status net_forward(fl_net net, const float* x, const float* alpha, int B, int D, int H, int W) {
+static fl_status net_forward(fl_net net, const float* x, const float* alpha, int B, int D, int H, int W,
+                             const double* stop = nullptr) {
   STCHK(check_grid(net, B, D, H, W));
   STCHK(net_reserve(net, B, D, H, W));
-  const Dims g{B, D, H, W};
+  const Dims g{B, D, H, W, stop};
   return net->kd == 3 ? net_forward_t<3>(net, x, alpha, g) : net_forward_t<1>(net, x, alpha, g);
 }
 
@@ -1173,7 +1188,7 @@ template <typename T> static fl_status learned_prec(fl_op op, fl_net net, const 
   const long np = (long)q.P0 * q.P1 * q.P2;
   LAUNCH(k_net_in<T>, dim3(nblocks_vec(np)), dim3(256), 0, s, (const T*)pb.r, net->pin, q,
          (const double*)(net->fs + 4));
-  STCHK(net_forward(net, net->pin, net->palpha, 1, q.P0, q.P1, q.P2));
+  STCHK(net_forward(net, net->pin, net->palpha, 1, q.P0, q.P1, q.P2, net->fs + 5));
   LAUNCH(k_net_out<T>, dim3(nblocks_vec(op->N)), dim3(256), 0, s, (const T*)pb.r, (const float*)net->y, (T*)net->pw, q,
          (const double*)(net->fs + 4));
   Prob pz = pb;
@@ -1181,7 +1196,7 @@ template <typename T> static fl_status learned_prec(fl_op op, fl_net net, const 
   pz.in = net->pw;
   pz.out = pb.z;
   pz.mask = nullptr;
-  return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pz, Iter{0, 0}, 0);
+  return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pz, Iter{0, 0}, 1);
 }
 
 template <typename T> static fl_status fd_prec(fl_op op, const Prob& pb) {
@@ -1190,7 +1205,7 @@ template <typename T> static fl_status fd_prec(fl_op op, const Prob& pb) {
   pz.pcs = op->cst[0] * std::fabs(op->cst[2]) * std::pow(op->h, -op->alpha);
   pz.in = pb.r;
   pz.out = pb.z;
-  return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pz, Iter{0, 0}, 0);
+  return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pz, Iter{0, 0}, 1);
 }
 
 template <typename T> static fl_status dot_to(fl_op op, const Prob& pb, const void* a, const void* b, double* dst) {
@@ -1234,6 +1249,8 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
   h[4] = rr0;
   h[5] = 0.0;
   HIPCHK(hipMemcpyAsync(fs + 4, h + 4, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+  // the passes of an iteration check pb.sc->done (set with fs[5] by k_fcg_check)
+  HIPCHK(hipMemsetAsync(&pb.sc->done, 0, sizeof(pb.sc->done), s));
   const int nupd = (int)std::min<long>(2048, nblocks_vec(N));
   const int ndot = (int)std::min<long>(1024, nblocks_vec(N));
   auto enqueue = [&](int k, bool use_fd) -> fl_status {
@@ -1244,7 +1261,7 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
     LAUNCH(k_fcg_dir<T>, dim3(ndot), dim3(256), 0, s, pb, N, (const double*)fs, k == 0 ? 1 : 0);
     Prob pa = pb;
     pa.in = pb.p;
-    STCHK((apply_seq<T, PRO_PLAIN, EPI_PQ>(op, pa, Iter{0, 0}, 0)));
+    STCHK((apply_seq<T, PRO_PLAIN, EPI_PQ>(op, pa, Iter{0, 0}, 1)));
     LAUNCH(k_totals2, dim3(1), dim3(256), 0, s, pb, (int)S_PQ, (int)S_DOT, fs, 2, 3);
     LAUNCH(k_fcg_update<T>, dim3(nupd), dim3(256), 0, s, pb, N, (const double*)fs);
     LAUNCH(k_fcg_check, dim3(1), dim3(256), 0, s, pb, fs, thr);
