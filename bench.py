@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--train3d-problems", type=int, default=40)
     ap.add_argument("--train3d-n", type=int, default=32)
     ap.add_argument("--train3d-steps", type=int, default=600)
+    ap.add_argument("--passes-3d", type=int, default=256,
+                    help="also time every pass of the 3D application and preconditioner at this n^3 (0: skip)")
+    ap.add_argument("--pass-reps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -169,11 +172,19 @@ def main():
     }
     prof = {}
     for name, (dt, pid, nbytes) in passes.items():
-        ms = op.profile_pass(dt, pid, reps=50)
+        ms = op.profile_pass(dt, pid, reps=args.pass_reps)
         gbs = nbytes / (ms * 1e-3) / 1e9
         prof[name] = {"ms": ms, "bytes": nbytes, "GBps": gbs}
         log(f"[bench] pass {name}: {ms * 1e3:.1f} us  {gbs:.0f} GB/s (algorithmic)")
-    cands = ["f32_sine_col_scale", "f32_fft_col_conv"]
+    passes3d = passes_3d(fl, torch, args.passes_3d, args.pass_reps) if args.passes_3d > 0 else None
+    # Kernels that the timed solver (learned + FP32 refinement) launches once
+    # per inner iteration: the FP32 application (row forward, symbol column
+    # pass, row inverse), the FP32 sine passes (first / last row pass are two
+    # kernels of equal shape; the scaled column pass) and, with a network, its
+    # layers.  The FP64 passes run once per refinement step only.  The
+    # roofline object reports the kernel with the largest time per solve.
+    per_iter = {"f32_sine_col_scale": 1, "f32_fft_col_conv": 1, "f32_fft_row_fwd": 1, "f32_fft_row_inv": 1,
+                "f32_sine_row": 1}
     if net is not None:
         # network layers at the solver grid (BF16 NHWC activations, 32 channels):
         # level-0 conv reads a0 (64 B/px) and the coarse c1 (16 B/px), writes c0 (64 B/px)
@@ -183,26 +194,24 @@ def main():
             prof[name] = {"ms": ms, "bytes": nbytes, "GBps": (nbytes / (ms * 1e-3) / 1e9) if nbytes else None}
             gb = f"{prof[name]['GBps']:.0f} GB/s (algorithmic)" if nbytes else ""
             log(f"[bench] pass {name}: {ms * 1e3:.1f} us  {gb}")
-        cands.append("net_conv_l0")
-    # The learned solve runs the level-0 convolution and the FP32 sine column
-    # pass once per inner iteration each, at nearly the same duration; the
-    # roofline object reports the convolution (the kernel the learned
-    # preconditioner adds, with HBM counters), and `roofline_next` the slowest
-    # of the other candidates by the same algorithmic measure.
-    dom = "net_conv_l0" if net is not None else max(cands, key=lambda k: prof[k]["ms"])
+        per_iter.update({"net_conv_l0": 1, "net_in_layer": 1, "net_out_layer": 1})
+    iters_best = results.get(best, {}).get("iters") or 1
+    per_solve = {k: prof[k]["ms"] * c * iters_best for k, c in per_iter.items()}
+    ranked = sorted(per_solve, key=lambda k: -per_solve[k])
+    dom = ranked[0]
 
     def hbm_roof(k):
-        return {"bound": "hbm", "achieved": round(prof[k]["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(prof[k]["GBps"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": k,
-                "avg_us": round(prof[k]["ms"] * 1e3, 2), "bytes_per_launch": prof[k]["bytes"]}
+        r = {"bound": "hbm", "achieved": round(prof[k]["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(prof[k]["GBps"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f"{k}_{n}_hbm_counters.md"),
+             "kernel": k, "avg_us": round(prof[k]["ms"] * 1e3, 2), "bytes_per_launch": prof[k]["bytes"],
+             "ms_per_solve": round(per_solve[k], 4)}
+        if k == "net_conv_l0":
+            tf = 2 * 9 * 32 * 32 * n * n / (prof[k]["ms"] * 1e-3) / 1e12
+            r["mfma_bf16_tflops"] = round(tf, 1)
+            r["mfma_frac"] = round(tf / 2500.0, 4)
+        return r
     roof = hbm_roof(dom)
-    others = [k for k in cands if k != dom]
-    roof_next = hbm_roof(max(others, key=lambda k: prof[k]["ms"])) if others else None
-    if dom == "net_conv_l0":
-        tf = 2 * 9 * 32 * 32 * n * n / (prof[dom]["ms"] * 1e-3) / 1e12
-        roof["mfma_bf16_tflops"] = round(tf, 1)
-        roof["mfma_frac"] = round(tf / 2500.0, 4)
-        roof["traffic"] = measured_traffic("net_conv_l0_1024_hbm_counters.md") if n == 1024 else None
+    roof_next = hbm_roof(ranked[1]) if len(ranked) > 1 else None
 
     batched = None
     if not args.no_batched:
@@ -234,17 +243,53 @@ def main():
         "learned_training": train_info,
         "baseline_fp64_ms": None if base_ms is None else round(base_ms, 3),
         "speedup_vs_fp64": None if base_ms is None else round(base_ms / good[best]["ms"], 3),
+        # the network's own contribution: learned + FP32 against the same
+        # refinement loop with the sine-basis diagonal alone (N = 0)
+        "learned_vs_spectral": (round(good["learned_f32"]["ms"] / good["f32_spectral"]["ms"], 3)
+                                if "learned_f32" in good and "f32_spectral" in good else None),
         "solvers": {k: {kk: (float(f"{vv:.4g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in results.items()},
         "passes_us": {k: round(v["ms"] * 1e3, 2) for k, v in prof.items()},
         "passes_GBps": {k: round(v["GBps"], 1) for k, v in prof.items() if v["GBps"]},
         "roofline": roof,
         "roofline_next": roof_next,
+        "passes_3d": passes3d,
         "batched": batched,
         "learned_3d": learned3d,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def passes_3d(fl, torch, n, reps):
+    """Time the passes of the FP32 and FP64 application and preconditioner on
+    an n^3 grid (alpha = 1.2), HIP events on the op's stream.  Algorithmic
+    bytes per launch (P = padded length, H = P/2 + 1, b = bytes per real):
+      rows forward  n^3 b + n^2 H 2b          (real in, half spectrum out)
+      axis-1 pair   2 (n^2 H + n P H) 2b      (forward and inverse, W1 <-> W2)
+      axis-0 conv   2 n P H 2b + H^3 b        (W2 in place, folded symbol)
+      rows inverse  n^2 H 2b + n^3 b
+      sine passes   2 n^3 b each (first, middle pair, scaled column, last)."""
+    op = fl.Op(3, 1.2, 2.0 / (n + 1), (n,) * 3)
+    P = op.padded()[0]
+    H = P // 2 + 1
+    out = {}
+    for dt, tag, b in ((torch.float32, "f32", 4), (torch.float64, "f64", 8)):
+        rows = n ** 3 * b + n * n * H * 2 * b
+        conv = 2 * n * P * H * 2 * b + H ** 3 * b
+        pair = 2 * (n * n * H + n * P * H) * 2 * b
+        sine = 2 * n ** 3 * b
+        for name, pid, nbytes in ((f"{tag}_rows_fwd", 0, rows), (f"{tag}_col0_conv", 1, conv),
+                                  (f"{tag}_rows_inv", 2, rows), (f"{tag}_apply", 6, 2 * rows + conv + pair),
+                                  (f"{tag}_sine_first", 3, sine), (f"{tag}_sine_col0_scale", 4, sine),
+                                  (f"{tag}_sine_last", 5, sine), (f"{tag}_precond", 7, 5 * sine)):
+            ms = op.profile_pass(dt, pid, reps=max(3, reps // 5))
+            out[name] = {"us": round(ms * 1e3, 2), "bytes": nbytes,
+                         "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                         "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            log(f"[bench] 3d {n}^3 pass {name}: {ms * 1e3:.1f} us  {out[name]['GBps']:.0f} GB/s (algorithmic)")
+    op.close()
+    return {"n": n, "passes": out}
 
 
 def measured_traffic(name):
@@ -349,47 +394,58 @@ def learned_3d_workload(fl, torch, args):
     l0, l1 = float(np.mean(losses[:20])), float(np.mean(losses[-20:]))
     log(f"[bench] learned 3d: {R.shape[0]} pairs at {args.train3d_n}^3 in {t_pairs:.1f} s, {len(losses)} Adam steps "
         f"(batch 4) in {t_train:.1f} s, loss {l0:.3e} -> {l1:.3e}")
-    out = {"workload": "3D 128^3 alpha=1.5 (-1,1)^3, 16 bumps seed 5500, tol 1e-8",
+    out = {"workload": "evaluated at 128^3 alpha=1.5 (16 bumps seed 5500) and 256^3 alpha=1.2 (the first of "
+                       "the 16 right-hand sides at 256^3)",
            "training": {"pairs": int(R.shape[0]), "grid": args.train3d_n, "pairs_s": round(t_pairs, 2),
                         "steps": len(losses), "batch": 4, "train_s": round(t_train, 2), "loss_first": l0,
                         "loss_last": l1}}
     del R, T, A
-    n, alpha = 128, 1.5
-    f_np, h = bump_field(n, 3, 16, 5500, width=(0.05, 0.2))
-    f = torch.from_numpy(f_np).cuda()
-    op = fl.Op(3, alpha, h, (n,) * 3, stream=s)
-    configs = {
-        "fp64_pcg": fl.solve_opts(pc=fl.FL_PC_FD, mixed=0),
-        "f32_pcg": fl.solve_opts(pc=fl.FL_PC_FD, mixed=1),
-        "fp64_spectral": fl.solve_opts(pc=fl.FL_PC_SPECTRAL, mixed=0),
-        "f32_spectral": fl.solve_opts(pc=fl.FL_PC_SPECTRAL, mixed=1),
-        "learned_f32": fl.solve_opts(pc=fl.FL_PC_LEARNED, mixed=1, net=net),
-        "learned_fp64": fl.solve_opts(pc=fl.FL_PC_LEARNED, mixed=0, net=net),
-    }
-    res = {}
-    for name, opts in configs.items():
-        op.solve(f, tol=1e-8, opts=opts)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        infos = [op.solve(f, tol=1e-8, opts=opts)[1] for _ in range(2)]
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / 2
-        worst = max(i["rel_res_true"] for i in infos)
-        res[name] = {"ms": round(ms, 3), "iters": infos[-1]["iters"], "outer": infos[-1]["outer_iters"],
-                     "rel_res_true": float(f"{worst:.3g}"), "ok": bool(worst <= 1e-8),
-                     "fell_back": infos[-1]["fell_back"]}
-        log(f"[bench] learned 3d {name}: {ms:.2f} ms/solve iters={infos[-1]['iters']} "
-            f"outer={infos[-1]['outer_iters']} true_res={worst:.2e}")
-    out["solvers"] = res
-    out["net_forward_ms"] = round(net.profile(0, n, n, reps=5, D=n), 3)
-    op.close()
+    from workloads import workload_rhs_256cubed
+    w256 = workload_rhs_256cubed(0)
+    evals = [("128cubed", 128, 1.5, bump_field(128, 3, 16, 5500, width=(0.05, 0.2)), 2),
+             ("256cubed", 256, w256["alpha"], (w256["f"], w256["h"]), 1)]
+    for key, n, alpha, (f_np, h), reps in evals:
+        f = torch.from_numpy(f_np).cuda()
+        op = fl.Op(3, alpha, h, (n,) * 3, stream=s)
+        configs = {
+            "fp64_pcg": fl.solve_opts(pc=fl.FL_PC_FD, mixed=0),
+            "f32_pcg": fl.solve_opts(pc=fl.FL_PC_FD, mixed=1),
+            "fp64_spectral": fl.solve_opts(pc=fl.FL_PC_SPECTRAL, mixed=0),
+            "f32_spectral": fl.solve_opts(pc=fl.FL_PC_SPECTRAL, mixed=1),
+            "learned_f32": fl.solve_opts(pc=fl.FL_PC_LEARNED, mixed=1, net=net),
+            "learned_fp64": fl.solve_opts(pc=fl.FL_PC_LEARNED, mixed=0, net=net),
+        }
+        res = {}
+        for name, opts in configs.items():
+            op.solve(f, tol=1e-8, opts=opts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos = [op.solve(f, tol=1e-8, opts=opts)[1] for _ in range(reps)]
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            worst = max(i["rel_res_true"] for i in infos)
+            res[name] = {"ms": round(ms, 3), "iters": infos[-1]["iters"], "outer": infos[-1]["outer_iters"],
+                         "rel_res_true": float(f"{worst:.3g}"), "ok": bool(worst <= 1e-8),
+                         "fell_back": infos[-1]["fell_back"]}
+            log(f"[bench] learned 3d {key} {name}: {ms:.2f} ms/solve iters={infos[-1]['iters']} "
+                f"outer={infos[-1]['outer_iters']} true_res={worst:.2e}")
+        ev = {"workload": f"3D {n}^3 alpha={alpha} (-1,1)^3, tol 1e-8", "solvers": res,
+              "net_forward_ms": round(net.profile(0, n, n, reps=3, D=n), 3)}
+        if res["learned_f32"]["ok"] and res["fp64_pcg"]["ok"]:
+            ev["learned_f32_vs_fp64_pcg_speedup"] = round(res["fp64_pcg"]["ms"] / res["learned_f32"]["ms"], 3)
+        out[key] = ev
+        op.close()
+        del f
     return out
 
 
 def cpu_baseline(n, alpha, h, f, iters):
-    """Oracle FP64 PCG timed on the host for a bounded sample, extrapolated."""
-    import numpy as np
-
+    """The oracle's FP64 PCG (explicit-DFT application, dense sine-matrix
+    preconditioner) timed on the host for a bounded number of its own
+    iterations and scaled to the iteration count of the solve; and, beside it,
+    the paper's method with a library FFT (scipy.fft) solved in full."""
+    from oracle import cpu_fft as CF
+    from oracle import krylov as KR
     from oracle import operator as O
     from oracle import precond as PC
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -399,20 +455,26 @@ def cpu_baseline(n, alpha, h, f, iters):
     lam = ref.lam_full
     t_sym = time.perf_counter() - t0
     sc = PC.pc_scale(2, alpha, h)
-    k = 3
-    r = f.copy()
+    k = 16
     t0 = time.perf_counter()
-    for _ in range(k):
-        z = PC.apply_inverse(r, sc)
-        q = O.apply_dft(lam, z)
-        r = r - 1e-3 * q
+    KR.pcg(lambda v: O.apply_dft(lam, v), f, lambda r: PC.apply_inverse(r, sc), tol=1e-30, maxit=k)
     t_it = (time.perf_counter() - t0) / k
     it = iters or 100
     est_ms = (t_sym + it * t_it) * 1e3
-    log(f"[bench] oracle: symbol {t_sym:.1f} s, {t_it:.2f} s per PCG iteration -> {est_ms / 1e3:.0f} s est.")
+    log(f"[bench] oracle: symbol {t_sym:.1f} s, {t_it:.2f} s per PCG iteration ({k} timed) -> {est_ms / 1e3:.0f} s "
+        f"for {it} iterations")
+    t0 = time.perf_counter()
+    cs = CF.FFTSolver(2, alpha, h, (n, n), workers=threads)
+    _, it_fft, res_fft, _ = cs.solve(f, tol=1e-8)
+    t_fft = (time.perf_counter() - t0) * 1e3
+    log(f"[bench] scipy.fft FP64 PCG: {t_fft / 1e3:.2f} s, {it_fft} iterations, recurrence residual {res_fft:.1e}")
     return {"value": round(est_ms, 1), "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": f"{k} oracle PCG iterations (naive-DFT apply + dense sine preconditioner) at {n}^2 "
-                      f"plus the symbol, extrapolated to {it} iterations (the GPU FP64 PCG count)"}
+            "sample": f"{k} iterations of the oracle's FP64 PCG (explicit-DFT apply, dense sine-matrix "
+                      f"preconditioner) at {n}^2 timed, plus its symbol, scaled to {it} iterations (the FP64 "
+                      f"PCG count on the GPU, equal to the oracle's within one)",
+            "paper_method_scipy_fft": {"ms": round(t_fft, 1), "iters": it_fft, "workers": threads,
+                                       "what": "FP64 PCG, FD preconditioner, scipy.fft transforms, full solve "
+                                               "to 1e-8"}}
 
 
 if __name__ == "__main__":

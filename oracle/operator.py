@@ -157,6 +157,18 @@ def apply_dft(lam_full, u):
     return y[tuple(slice(0, v) for v in n)].real
 
 
+def apply_fft(lam_full, u):
+    """The same product as apply_dft with numpy's FFT (a library transform)
+    in place of the explicit DFT matrices; for long sequences of
+    applications (many time steps) where the matrix form is too slow."""
+    P = lam_full.shape
+    n = u.shape
+    x = np.zeros(P)
+    x[tuple(slice(0, v) for v in n)] = u
+    y = np.fft.ifftn(np.fft.fftn(x) * lam_full)
+    return y[tuple(slice(0, v) for v in n)].real
+
+
 class Operator:
     """Bundle of the oracle's M for one (d, alpha, h, n): weights, symbol, apply."""
 
@@ -182,6 +194,8 @@ class Operator:
         N = int(np.prod(self.n))
         if method == "dense" or (method == "auto" and N <= 4096):
             y = apply_dense(self.w, u)
+        elif method == "fft":
+            y = apply_fft(self.lam_full, u)
         else:
             y = apply_dft(self.lam_full, u)
         if self.mask is not None:
@@ -204,3 +218,26 @@ def grid_points(n, lo=-1.0, hi=1.0):
 
 def all_lags(n):
     return list(itertools.product(*[range(v) for v in n]))
+
+
+def apply_line(w, u, lead):
+    """(M u)_i for every i on one line of the last axis, the leading indices
+    fixed at `lead`, by direct summation over all j (the definition,
+    reordered): with m the lag along the last axis,
+
+        A[m, j_last] = sum_{j_lead} w[|lead - j_lead|, m] u[j_lead, j_last],
+        (M u)_{lead, i} = sum_{j_last} A[|i - j_last|, j_last].
+
+    The inner sum over the leading axes is one matrix product."""
+    n = u.shape
+    d = len(n)
+    lead = tuple(int(v) for v in lead)
+    if len(lead) != d - 1:
+        raise ValueError("lead must fix every axis but the last")
+    lags = np.meshgrid(*[np.abs(np.arange(n[a]) - lead[a]) for a in range(d - 1)], indexing="ij")
+    G = w[tuple(lags)] if d > 1 else w[None, :]          # [n_0..n_{d-2}, n_last] (lag m last)
+    G2 = G.reshape(-1, n[-1])
+    U2 = np.asarray(u, dtype=np.float64).reshape(-1, n[-1])
+    A = G2.T @ U2                                        # [m, j_last]
+    i = np.arange(n[-1])
+    return A[np.abs(i[:, None] - i[None, :]), i[None, :]].sum(axis=1)

@@ -171,10 +171,20 @@ inline long rows_of(fl_op op, long nrhs) {
   return r;
 }
 
+// A captured iteration graph holds the workspace pointers by value: every
+// reallocation below invalidates it.
+inline void drop_graph(Workspace& w) {
+  if (w.gexec) {
+    (void)hipGraphExecDestroy(w.gexec);
+    w.gexec = nullptr;
+  }
+}
+
 template <typename T> inline fl_status ensure_ws(fl_op op, long nrhs, bool solver) {
   Workspace& w = op->ws[tix<T>()];
   const long N = op->N;
   if (w.cap_rhs < nrhs) {
+    drop_graph(w);
     for (void** p : {&w.W1, &w.W2, &w.T1})
       if (*p) { hipFree(*p); *p = nullptr; }
     long rows = rows_of(op, nrhs);
@@ -194,6 +204,7 @@ template <typename T> inline fl_status ensure_ws(fl_op op, long nrhs, bool solve
     HIPCHK(hipMemset(w.sc, 0, sizeof(Scalars)));
   }
   if (solver && !w.solver) {
+    drop_graph(w);
     for (void** p : {&w.x, &w.r, &w.z, &w.p, &w.q, &w.f}) STCHK(dalloc(p, (size_t)N * sizeof(T)));
     w.solver = true;
   }

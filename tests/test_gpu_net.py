@@ -426,3 +426,84 @@ def test_training_and_ablation_3d():
     for v in out.values():
         assert v["spectral_fcg"] < v["fd"]
         assert v["learned"] <= v["spectral_fcg"] + 1
+
+
+def _adam_problem(d, shape, seed):
+    th = _params_relu_active(seed, d)
+    rng = np.random.Generator(np.random.PCG64(seed + 900))
+    R = rng.standard_normal(shape).astype(np.float32)
+    T = (0.3 * rng.standard_normal(shape)).astype(np.float32)
+    A = rng.uniform(0.2, 1.9, size=shape[0]).astype(np.float32)
+    return th, R, T, A
+
+
+@pytest.mark.parametrize("d,shape", [(2, (2, 16, 24)), (3, (2, 8, 8, 16))])
+def test_adam_steps_against_oracle_with_device_gradients(d, shape):
+    # Three Adam steps of fl_net_train on one fixed minibatch.  Before each
+    # step the same gradient is taken through fl_net_grad (same kernels, same
+    # fixed-order reductions, the loss gradient 2 (y - t) / n formed in FP32
+    # as the training step forms it), and the oracle's adam_step is fed that
+    # gradient: the parameters after every step must agree to FP32 rounding.
+    # This pins the update, both moments and the bias corrections by step
+    # number, independently of the BF16 gradient error.
+    _say("adam vs oracle (device gradients)", d, shape)
+    fl = _fl()
+    th0, R, T, A = _adam_problem(d, shape, 21 + d)
+    B = shape[0]
+    lr = 1e-3
+    net = fl.Net(params=th0, d=d)
+    Rd, Td, Ad = (torch.from_numpy(v).cuda() for v in (R, T, A))
+    n = R.size
+    th = th0.astype(np.float32).astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for k in range(1, 4):
+        y = net.forward(Rd, [float(a) for a in A]).cpu().numpy()
+        gy = np.float32(2.0 / n) * (y - T)
+        g = net.grad(Rd, [float(a) for a in A], torch.from_numpy(gy).cuda()).cpu().numpy().astype(np.float64)
+        net.train(Rd, Td, Ad, np.arange(B).reshape(1, B), batch=B, lr=lr)
+        got = net.get_params().cpu().numpy().astype(np.float64)
+        th, m, v = NN.adam_step(th, g, m, v, k, lr)
+        step = np.abs(got - th)
+        assert float(step.max()) <= 2e-3 * lr + 1e-6 * float(np.abs(th).max()), (k, float(step.max()))
+
+
+@pytest.mark.parametrize("d,shape", [(2, (2, 16, 24)), (3, (2, 8, 8, 16))])
+def test_adam_trajectory_against_oracle(d, shape):
+    # Three training steps from fixed parameters on a fixed minibatch, against
+    # the oracle run end to end (its own FP64 forward, loss gradient, reverse
+    # pass and adam_step).  Adam divides each coordinate's step by its own
+    # gradient scale, so a coordinate whose gradient is below the BF16
+    # gradient error can step the other way; the comparison is therefore on
+    # the whole step theta_3 - theta_0 per layer (relative l2) and on the
+    # fraction of coordinates that moved in the oracle's direction.
+    _say("adam trajectory vs oracle", d, shape)
+    fl = _fl()
+    th0, R, T, A = _adam_problem(d, shape, 41 + d)
+    B = shape[0]
+    lr = 1e-3
+    net = fl.Net(params=th0, d=d)
+    Rd, Td, Ad = (torch.from_numpy(v).cuda() for v in (R, T, A))
+    net.train(Rd, Td, Ad, np.tile(np.arange(B), (3, 1)), batch=B, lr=lr)
+    got = net.get_params().cpu().numpy().astype(np.float64)
+    th = th0.astype(np.float32).astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    x64, t64, a64 = R.astype(np.float64), T.astype(np.float64), A.astype(np.float64)
+    for k in range(1, 4):
+        g = NN.loss_grad(th, x64, a64, t64)
+        th, m, v = NN.adam_step(th, g, m, v, k, lr)
+    th0_64 = th0.astype(np.float32).astype(np.float64)
+    dg, dw = got - th0_64, th - th0_64
+    assert _rl2(dg, dw) <= 0.3, _rl2(dg, dw)
+    # coordinates whose gradient stands clear of the BF16 gradient error
+    # (above 5% of the RMS gradient of its layer) move the oracle's way
+    g0 = NN.loss_grad(th0_64, x64, a64, t64)
+    o, strong = 0, np.zeros(g0.size, dtype=bool)
+    for name, ci, co in NN.LAYERS:
+        for m_ in (3 ** d * ci * co, co):
+            seg = g0[o:o + m_]
+            strong[o:o + m_] = np.abs(seg) > 0.05 * np.sqrt(np.mean(seg ** 2))
+            o += m_
+    agree = float(np.mean(np.sign(dg[strong]) == np.sign(dw[strong])))
+    assert agree >= 0.99, agree

@@ -297,3 +297,27 @@ def test_apply_specialised_column_pass(n, lanes):
     for p_, wv in zip(pts, want):
         assert abs(g64[p_] - wv) <= 1e-12 * scale, (p_, g64[p_], wv)
         assert abs(g32[p_] - wv) <= 2e-5 * scale, (p_, g32[p_], wv)
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_solve_after_batched_apply_reuses_no_stale_graph(mixed):
+    # a batched application or preconditioner grows the op's workspace; the
+    # next solve must not replay an iteration graph captured on the old
+    # buffers (it is rebuilt), and must give the eager solve's result
+    _say("solve / batched apply / solve", mixed)
+    fl = _fl()
+    n = (40, 36)
+    op = fl.Op(2, 1.3, 0.05, n)
+    f = _dev(white_noise(n, 31))
+    opts = fl.solve_opts(mixed=mixed, graph=1, poll_every=4)
+    u1, _ = op.solve(f, tol=1e-10, opts=opts)
+    for dt in (torch.float64, torch.float32):
+        ub = _dev(white_noise((5,) + n, 32), dt)
+        op.apply(ub)
+        op.precond(ub)
+    u2, i2 = op.solve(f, tol=1e-10, opts=opts)
+    u3, i3 = op.solve(f, tol=1e-10, opts=fl.solve_opts(mixed=mixed, graph=0, poll_every=4))
+    torch.cuda.synchronize()
+    assert i2["iters"] == i3["iters"]
+    assert torch.equal(u2, u3)
+    assert torch.equal(u1, u2)

@@ -104,6 +104,31 @@ def test_apply_at_matches_dense():
     assert np.allclose(got, [full[p] for p in pts], rtol=1e-13, atol=1e-13)
 
 
+@pytest.mark.parametrize("n", [(13,), (9, 11), (5, 6, 7)])
+def test_apply_fft_matches_dense(n):
+    rng = np.random.default_rng(7 + len(n))
+    op = O.Operator(len(n), 0.8, 0.1, n)
+    u = rng.standard_normal(n)
+    full = O.apply_dense(op.w, u)
+    got = op.apply(u, method="fft")
+    assert np.abs(got - full).max() <= 1e-13 * np.abs(full).max()
+
+
+@pytest.mark.parametrize("n", [(13,), (9, 11), (5, 6, 7)])
+def test_apply_line_matches_dense(n):
+    # the line form of the direct sum against the dense matrix product, on
+    # every line of small 1D/2D/3D grids (a wrong lag or a transposed
+    # contraction shows on all of them)
+    rng = np.random.default_rng(len(n))
+    op = O.Operator(len(n), 1.3, 0.1, n)
+    u = rng.standard_normal(n)
+    full = O.apply_dense(op.w, u)
+    import itertools
+    for lead in itertools.product(*[range(v) for v in n[:-1]]):
+        got = O.apply_line(op.w, u, lead)
+        assert np.allclose(got, full[lead], rtol=1e-13, atol=1e-13), lead
+
+
 @pytest.mark.parametrize("n", [(12,), (6, 7), (3, 4, 5)])
 @pytest.mark.parametrize("alpha", [0.2, 1.0, 1.9])
 def test_symmetric_positive_definite(n, alpha):
