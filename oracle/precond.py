@@ -72,3 +72,65 @@ def fd_matrix(n, scale, shift0=0.0, shift1=1.0):
             kr = np.kron(kr, o)
         A += kr
     return shift0 * np.eye(N) + shift1 * scale * A
+
+
+# ---------------------------------------------------------------------------
+# Occluded domains (Sec. 3.1 "Preconditioning" and Sec. 4.4): on a grid
+# domain Omega inside the box the preconditioner is the same FD Laplacian
+# with homogeneous Dirichlet data outside Omega, i.e. the principal submatrix
+# L_Omega of the box matrix on the points of Omega.  The paper applies its
+# inverse with a sparse Cholesky factorisation; here a sparse LU of the
+# submatrix (scipy), the same exact inverse.
+# ---------------------------------------------------------------------------
+def fd_matrix_sparse(n, scale, shift0=0.0, shift1=1.0):
+    """shift0 I + shift1 scale T as a scipy sparse matrix (Kronecker sum)."""
+    import scipy.sparse as sp
+    N = int(np.prod(n))
+    A = sp.csr_matrix((N, N))
+    for a, v in enumerate(n):
+        t = sp.diags([-np.ones(v - 1), 2.0 * np.ones(v), -np.ones(v - 1)], [-1, 0, 1])
+        kr = None
+        for b, m in enumerate(n):
+            o = t if b == a else sp.identity(m)
+            kr = o if kr is None else sp.kron(kr, o)
+        A = A + kr
+    return (shift0 * sp.identity(N) + shift1 * scale * A).tocsc()
+
+
+def apply_inverse_masked(r, mask, scale, shift0=0.0, shift1=1.0):
+    """z = (shift0 I + shift1 scale T)_Omega^{-1} r on Omega (mask 1), z = 0 off it."""
+    import scipy.sparse.linalg as spl
+    n = r.shape
+    m = np.asarray(mask).reshape(-1).astype(bool)
+    A = fd_matrix_sparse(n, scale, shift0, shift1)[m][:, m]
+    z = np.zeros(int(np.prod(n)))
+    z[m] = spl.splu(A.tocsc()).solve(np.asarray(r, dtype=np.float64).reshape(-1)[m])
+    return z.reshape(n)
+
+
+# ---------------------------------------------------------------------------
+# M~ (Sec. 3.1, the alternative preconditioner): M restricted to the sparsity
+# pattern of L, M~_ij = M_ij where L_ij != 0 (i = j or |i - j|_1 = 1), else 0.
+# With the weights of M, omega_0 = Z - 2dB and omega_{e_k} = -1 + B, and the
+# shift sum S = 2d I - T of the stencil, M~ = C h^-alpha (omega_0 I +
+# omega_e S) = q0 I + q1 T with q0 = C h^-alpha (Z - 2d), q1 = C h^-alpha (1 - B).
+# ---------------------------------------------------------------------------
+def mtilde_matrix(M, n):
+    """M~ from a dense M on the grid n: entries off the FD pattern set to 0."""
+    pattern = fd_matrix(n, 1.0) != 0.0
+    return np.where(pattern, M, 0.0)
+
+
+def mtilde_parts(d, alpha, h, c=20.0):
+    """(q0, q1) with M~ = q0 I + q1 T on the box."""
+    Ch = K.c_alpha(alpha, d) * h ** (-alpha)
+    return Ch * (K.lattice_zeta(d, alpha) - 2.0 * d), Ch * (1.0 - K.b_const(d, alpha, c))
+
+
+def apply_mtilde_inverse(r, d, alpha, h, shift0=0.0, shift1=1.0, mask=None, c=20.0):
+    """z = (shift0 I + shift1 M~)^{-1} r on the box (dense sine transforms) or,
+    with a mask, on Omega (sparse LU of the submatrix)."""
+    q0, q1 = mtilde_parts(d, alpha, h, c)
+    if mask is not None:
+        return apply_inverse_masked(r, mask, q1, shift0 + shift1 * q0, shift1)
+    return apply_inverse(r, q1, shift0 + shift1 * q0, shift1)

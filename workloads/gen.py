@@ -105,3 +105,27 @@ def learned_training_plan(nalpha=100, n=256, seed=5000, lo=0.2, hi=1.9, d=2):
     alphas = rng.uniform(lo, hi, size=nalpha)
     return [{"n": n, "d": d, "alpha": float(a), "rhs_seed": seed + 1 + i, "field_seed": seed + 100000 + 1000 * i}
             for i, a in enumerate(alphas)]
+
+
+def l_shape_mask(n):
+    """uint8 mask of the L-shaped domain on an n x n grid of [0,1]^2 (n odd,
+    h = 1/(n+1)): the (n+1)/2 x (n+1)/2 block of points in one corner,
+    x_i, y_j <= 1/2 (1-based i, j <= (n+1)/2), is removed.  n = 127 leaves
+    127^2 - 64^2 = 12033 points."""
+    m = np.ones((n, n), dtype=np.uint8)
+    q = (n + 1) // 2
+    m[:q, :q] = 0
+    return m
+
+
+def octagon_mask(n):
+    """uint8 mask of the octagon with vertices on the grid: the square [0,1]^2
+    with its four corners cut along the lines x + y = 1/4 (and mirror images),
+    points on a cut line removed.  1-based i, j: a point is outside when
+    i + j <= (n+1)/4 or one of its three mirror images is.  n = 127 leaves
+    127^2 - 4 * 496 = 14145 points."""
+    i = np.arange(1, n + 1)
+    I, J = np.meshgrid(i, i, indexing="ij")
+    c = (n + 1) / 4.0
+    out = (I + J <= c) | ((n + 1 - I) + J <= c) | (I + (n + 1 - J) <= c) | ((n + 1 - I) + (n + 1 - J) <= c)
+    return (~out).astype(np.uint8)
