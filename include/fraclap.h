@@ -61,9 +61,16 @@ typedef enum {
   FL_PC_LEARNED = 2,  /* not in the paper: flexible CG with z = B (r + s N(r/s, alpha)), N the network
                          opts->net (of the op's dimension), B the FL_PC_SPECTRAL inverse, s = RMS(r); the FD
                          preconditioner is the fallback (d = 2 or 3, no mask) */
-  FL_PC_SPECTRAL = 3  /* not in the paper: the sine basis of the FD preconditioner with the
+  FL_PC_SPECTRAL = 3, /* not in the paper: the sine basis of the FD preconditioner with the
                          operator's own diagonal in that basis as eigenvalues, i.e. the best
                          approximation of M diagonalised by the type-I sine transform */
+  FL_PC_MTILDE = 4,   /* M~ (Sec. 3.1, the alternative the paper mentions): M restricted to the
+                         sparsity pattern of L, M~ = C h^-alpha [(Z - 2d) I + (1 - B) T], T the
+                         (2d+1)-point Laplacian; sine transforms on the box, exact on a mask */
+  FL_PC_FD_BOX = 5,   /* on a mask: P_Omega (C h^d L_box)^{-1} P_Omega, the box inverse restricted to
+                         the domain (not the paper's operator; on the box the same as FL_PC_FD) */
+  FL_PC_AUTO = 6      /* the paper's rule (Sec. 4.1, 4.2): no preconditioner for alpha < 1, FL_PC_FD
+                         otherwise */
 } fl_precond_kind;
 
 typedef struct {
@@ -138,12 +145,27 @@ fl_status fl_op_export(fl_op op, int which, void* dst);
 fl_status fl_apply(fl_op op, const void* u, void* Mu, int dtype, int64_t batch, const uint8_t* mask,
                    double shift0, double shift1);
 
-/* z = (p0 I + p1 C h^d L)^{-1} r on the box (mask applied on input and output
- * if given), sine transforms along every axis.  p0 = 0, p1 = 1 is the
- * elliptic preconditioner; p0 = 1, p1 = theta dt the time-step one.
- * Paper Sec. 3.1 ("Preconditioning") and Sec. 3.2. */
+/* z = (p0 I + p1 C h^d L)^{-1} r, sine transforms along every axis.  p0 = 0,
+ * p1 = 1 is the elliptic preconditioner; p0 = 1, p1 = theta dt the time-step
+ * one.  Paper Sec. 3.1 ("Preconditioning") and Sec. 3.2.
+ * With a mask (uint8 [n...], 1 = inside the domain Omega) the inverse is the
+ * exact one on Omega, (p0 I + p1 C h^d L)_Omega^{-1} with zero data outside
+ * Omega (the paper's L_Omega^{-1}, Sec. 4.4, there by sparse Cholesky): the
+ * box inverse corrected by a capacitance matrix on the k exterior points next
+ * to Omega (two box solves and a k x k product per application).  The
+ * correction is built on the first call for a mask (k box solves in FP64 and
+ * a k x k inversion; checksum of the mask's points and the pointer identify
+ * it) and reused while mask and (p0, p1) stay the same; k <= 8192, else
+ * FL_E_UNSUPPORTED.  z is zero outside Omega. */
 fl_status fl_precond(fl_op op, const void* r, void* z, int dtype, int64_t batch, const uint8_t* mask,
                      double p0, double p1);
+
+/* The preconditioner of any kind: FL_PC_FD (as fl_precond), FL_PC_SPECTRAL
+ * (as fl_precond_spectral), FL_PC_MTILDE ((p0 I + p1 M~)^{-1}, exact on a mask
+ * as for FL_PC_FD) or FL_PC_FD_BOX (P_Omega (p0 I + p1 C h^d L_box)^{-1}
+ * P_Omega).  Same layout and errors as fl_precond. */
+fl_status fl_precond_any(fl_op op, int kind, const void* r, void* z, int dtype, int64_t batch,
+                          const uint8_t* mask, double p0, double p1);
 
 /* As fl_precond with the sine-basis diagonal of M in place of the FD
  * Laplacian: z = (p0 I + p1 Q diag(tau) Q^T)^{-1} r, where Q is the
@@ -157,7 +179,10 @@ fl_status fl_precond_spectral(fl_op op, const void* r, void* z, int dtype, int64
 
 /* Solve M u = f (FP64 f and u, single right-hand side) to relative residual
  * tol (recurrence residual in the loop; the true FP64 residual is reported).
- * Paper Sec. 3.1 (eq. matelliptic) and Sec. 4 (stopping test). */
+ * Paper Sec. 3.1 (eq. matelliptic) and Sec. 4 (stopping test).  With a mask
+ * the system is P_Omega M P_Omega u = P_Omega f on Omega (f is restricted to
+ * Omega; u is zero outside it), Sec. 4.4; FL_PC_FD and FL_PC_MTILDE then use
+ * the exact inverse on Omega (see fl_precond). */
 fl_status fl_solve(fl_op op, const double* f, const uint8_t* mask, double tol, const fl_solve_opts* opts,
                    double* u, fl_info* info);
 

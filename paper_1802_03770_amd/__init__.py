@@ -15,11 +15,11 @@ LIB_PATH = os.path.join(_HERE, "libfraclap.so")
 
 FL_OK, FL_E_INVALID, FL_E_NOMEM, FL_E_HIP, FL_E_NOCONV, FL_E_BREAKDOWN, FL_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FL_F64, FL_F32 = 0, 1
-FL_PC_NONE, FL_PC_FD, FL_PC_LEARNED, FL_PC_SPECTRAL = 0, 1, 2, 3
+FL_PC_NONE, FL_PC_FD, FL_PC_LEARNED, FL_PC_SPECTRAL, FL_PC_MTILDE, FL_PC_FD_BOX, FL_PC_AUTO = 0, 1, 2, 3, 4, 5, 6
 STATUS_NAMES = {0: "ok", -1: "invalid", -2: "nomem", -3: "hip", -4: "noconv", -5: "breakdown", -6: "unsupported"}
 
 EXPORTED = ["fl_make_weights", "fl_op_constants", "fl_op_padded", "fl_op_plan", "fl_op_export", "fl_apply", "fl_precond",
-            "fl_precond_spectral", "fl_solve", "fl_step", "fl_solve_batched", "fl_step_batched", "fl_profile_pass", "fl_op_destroy",
+            "fl_precond_spectral", "fl_precond_any", "fl_solve", "fl_step", "fl_solve_batched", "fl_step_batched", "fl_profile_pass", "fl_op_destroy",
             "fl_last_error", "fl_net_create", "fl_net_nparams", "fl_net_set_params", "fl_net_get_params",
             "fl_net_forward", "fl_net_grad", "fl_net_train", "fl_learned_pairs", "fl_net_profile", "fl_net_destroy"]
 
@@ -71,6 +71,7 @@ def load(path=LIB_PATH):
         "fl_apply": [P, P, P, I, I64, P, D, D],
         "fl_precond": [P, P, P, I, I64, P, D, D],
         "fl_precond_spectral": [P, P, P, I, I64, P, D, D],
+        "fl_precond_any": [P, I, P, P, I, I64, P, D, D],
         "fl_solve": [P, P, P, D, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(Info)],
         "fl_step": [P, P, D, D, P, P, P, D, ctypes.POINTER(SolveOpts), ctypes.POINTER(Info)],
         "fl_solve_batched": [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), D,
@@ -225,17 +226,24 @@ class Op:
         return out
 
     def precond(self, r, mask=None, p0=0.0, p1=1.0, out=None, kind=FL_PC_FD):
-        """z = (p0 I + p1 P)^{-1} r; P the FD Laplacian preconditioner or (kind =
-        FL_PC_SPECTRAL) the sine-basis diagonal of M."""
+        """z = (p0 I + p1 P)^{-1} r; P the FD Laplacian preconditioner (kind =
+        FL_PC_FD, exact on a mask), the sine-basis diagonal of M (FL_PC_SPECTRAL),
+        M~ (FL_PC_MTILDE, exact on a mask) or the box FD inverse restricted to a
+        mask (FL_PC_FD_BOX)."""
         dt = FL_F64 if r.dtype == torch.float64 else FL_F32
         _need(r, r.dtype, name="r")
         _need(mask, torch.uint8, self.N, "mask")
         out = torch.empty_like(r) if out is None else _need(out, r.dtype, r.numel(), "out")
-        fn = {FL_PC_FD: load().fl_precond, FL_PC_SPECTRAL: load().fl_precond_spectral}.get(kind)
-        if fn is None:
-            raise ValueError("kind must be FL_PC_FD or FL_PC_SPECTRAL")
+        if kind not in (FL_PC_FD, FL_PC_SPECTRAL, FL_PC_MTILDE, FL_PC_FD_BOX):
+            raise ValueError("kind must be FL_PC_FD, FL_PC_SPECTRAL, FL_PC_MTILDE or FL_PC_FD_BOX")
         self._enter()
-        _check(fn(self._h, _ptr(r), _ptr(out), dt, self._batch(r), _ptr(mask), p0, p1))
+        if kind == FL_PC_FD:
+            st = load().fl_precond(self._h, _ptr(r), _ptr(out), dt, self._batch(r), _ptr(mask), p0, p1)
+        elif kind == FL_PC_SPECTRAL:
+            st = load().fl_precond_spectral(self._h, _ptr(r), _ptr(out), dt, self._batch(r), _ptr(mask), p0, p1)
+        else:
+            st = load().fl_precond_any(self._h, kind, _ptr(r), _ptr(out), dt, self._batch(r), _ptr(mask), p0, p1)
+        _check(st)
         self._leave()
         return out
 

@@ -32,6 +32,7 @@ UNITS = [
     ("fl_batch.hip", ["-DFL_T=double"]),
     ("fl_batch.hip", ["-DFL_BATCH_HOST"]),
     ("fl_net.hip", []),
+    ("fl_capacity.hip", []),
 ]
 
 

@@ -323,6 +323,7 @@ template <typename T> static Prob make_prob(Batch& bt, int p, const ProbBufs& b,
   pb.s1 = s1;
   pb.p0 = p0;
   pb.p1 = p1;
+  if (bt.pc == FL_PC_MTILDE) (void)set_precond<T>(bt.ops[p], pb, FL_PC_MTILDE);
   pb.W1 = b.W1;
   pb.W2 = b.W2;
   pb.T1 = b.T1;
@@ -468,8 +469,12 @@ static fl_status make_batch(Batch& bt, int nprob, const fl_op* ops, const uint8_
   if (nprob < 1 || !ops) return fail(FL_E_INVALID, "nprob must be >= 1");
   const bool mixed = o && o->mixed;
   bt.pc = o ? o->pc : FL_PC_FD;
-  if (bt.pc == FL_PC_LEARNED) return fail(FL_E_UNSUPPORTED, "batched solves take FL_PC_NONE, FD or SPECTRAL");
-  if (bt.pc != FL_PC_NONE && bt.pc != FL_PC_FD && bt.pc != FL_PC_SPECTRAL)
+  // masked problems of a batch take the box inverse restricted to the domain
+  // (the exact inverse on a mask is built per op by the single-problem calls)
+  if (bt.pc == FL_PC_FD_BOX) bt.pc = FL_PC_FD;
+  if (bt.pc == FL_PC_LEARNED || bt.pc == FL_PC_AUTO)
+    return fail(FL_E_UNSUPPORTED, "batched solves take FL_PC_NONE, FD, FD_BOX, MTILDE or SPECTRAL");
+  if (bt.pc != FL_PC_NONE && bt.pc != FL_PC_FD && bt.pc != FL_PC_SPECTRAL && bt.pc != FL_PC_MTILDE)
     return fail(FL_E_INVALID, "unknown preconditioner");
   if (bt.pc == FL_PC_SPECTRAL)
     for (int p = 0; p < nprob; ++p)

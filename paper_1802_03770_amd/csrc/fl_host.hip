@@ -154,6 +154,7 @@ template <typename T> static fl_status build_axis(fl_op op, int a, int form) {
 }
 
 fl_op_s::~fl_op_s() {
+  cap_destroy(this);
   for (void* p : tables) hipFree(p);
   for (auto& w : ws) {
     for (void* p : {w.W1, w.W2, w.T1, w.x, w.r, w.z, w.p, w.q, w.f}) if (p) hipFree(p);
@@ -373,12 +374,20 @@ fl_status build_tau(fl_op op) {
 // ---------------------------------------------------------------------------
 // Krylov drivers
 // ---------------------------------------------------------------------------
-template <typename T> static fl_status one_iteration(fl_op op, const Prob& pb, int pc, int k) {
+// y *= mask (restriction of a grid function to the domain)
+template <typename T> __global__ void k_mask_mul(T* __restrict__ y, const uint8_t* __restrict__ m, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n && !m[i]) y[i] = (T)0;
+}
+
+template <typename T> static fl_status one_iteration(fl_op op, const Prob& pb, int pc, int k, bool cap) {
   Iter it = {k & 1, k == 0 ? 1 : 0};
   Prob pz = pb;
   if (!pc) pz.z = pb.r;  // z aliases r without a preconditioner
   STCHK((apply_seq<T, PRO_PUPD, EPI_PQ>(op, pz, it, 1)));
-  if (pc) {
+  if (pc && cap) {
+    STCHK((cap_precond_seq<T, DPRO_UPD, DEPI_Z>(op, pb, it, 1)));
+  } else if (pc) {
     STCHK((precond_seq<T, DPRO_UPD, DEPI_Z>(op, pb, it, 1)));
   } else {
     long nb = std::min<long>(2048, (op->N + 255) / 256);
@@ -397,14 +406,15 @@ static fl_status read_scalars(fl_op op, Scalars* dsc) {
 // iterate, sc->ff the squared rhs norm (and sc->rr the squared residual norm
 // if use_rr).  Returns after convergence / cap / breakdown.
 template <typename T> static fl_status krylov(fl_op op, const Prob& pb, int pc, double tol, int maxit,
-                                              int use_rr, int graph, int poll, Scalars* out) {
+                                              int use_rr, int graph, int poll, Scalars* out, bool cap) {
   hipStream_t s = op->stream;
   Workspace& w = op->ws[tix<T>()];
   LAUNCH(k_init<>, dim3(1), dim3(64), 0, s, pb, tol, maxit, use_rr);
   if (pc) {
     Prob p0 = pb;
     p0.in = pb.r;
-    STCHK((precond_seq<T, DPRO_PLAIN, DEPI_Z>(op, p0, Iter{1, 0}, 0)));
+    if (cap) STCHK((cap_precond_seq<T, DPRO_PLAIN, DEPI_Z>(op, p0, Iter{1, 0}, 0)));
+    else STCHK((precond_seq<T, DPRO_PLAIN, DEPI_Z>(op, p0, Iter{1, 0}, 0)));
   } else {
     // rz[0] = r.r
     long nb = std::min<long>(1024, (op->N + 255) / 256);
@@ -413,12 +423,12 @@ template <typename T> static fl_status krylov(fl_op op, const Prob& pb, int pc, 
   if (poll <= 0) poll = 8;
   if (poll & 1) ++poll;
   // iteration 0 eagerly, then blocks of `poll` iterations
-  STCHK(one_iteration<T>(op, pb, pc, 0));
+  STCHK(one_iteration<T>(op, pb, pc, 0, cap));
   int k = 1;
   bool use_graph = graph != 0 && op->stream != nullptr;
   if (use_graph) {
     bool rebuild = !w.gexec || w.gK != poll || w.gpc != pc || w.gs0 != pb.s0 || w.gs1 != pb.s1 ||
-                   w.gp0 != pb.p0 || w.gp1 != pb.p1 || w.gmask != pb.mask;
+                   w.gp0 != pb.p0 || w.gp1 != pb.p1 || w.gmask != pb.mask || w.gcap != (int)cap;
     if (rebuild) {
       if (w.gexec) {
         hipGraphExecDestroy(w.gexec);
@@ -427,7 +437,7 @@ template <typename T> static fl_status krylov(fl_op op, const Prob& pb, int pc, 
       hipGraph_t g;
       HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       fl_status st = FL_OK;
-      for (int j = 0; j < poll && st == FL_OK; ++j) st = one_iteration<T>(op, pb, pc, 1 + j);
+      for (int j = 0; j < poll && st == FL_OK; ++j) st = one_iteration<T>(op, pb, pc, 1 + j, cap);
       hipError_t e = hipStreamEndCapture(s, &g);
       if (st != FL_OK) return st;
       HIPCHK(e);
@@ -440,6 +450,7 @@ template <typename T> static fl_status krylov(fl_op op, const Prob& pb, int pc, 
       w.gp0 = pb.p0;
       w.gp1 = pb.p1;
       w.gmask = pb.mask;
+      w.gcap = (int)cap;
     }
   }
   for (;;) {
@@ -451,7 +462,7 @@ template <typename T> static fl_status krylov(fl_op op, const Prob& pb, int pc, 
       HIPCHK(hipGraphLaunch(w.gexec, s));
       k += poll;
     } else {
-      for (int j = 0; j < poll; ++j, ++k) STCHK(one_iteration<T>(op, pb, pc, k));
+      for (int j = 0; j < poll; ++j, ++k) STCHK(one_iteration<T>(op, pb, pc, k, cap));
     }
   }
   *out = *op->hsc;
@@ -482,9 +493,9 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
                               double tol, const fl_solve_opts* o, int use_x0, fl_info* info) {
   hipStream_t s = op->stream;
   const long N = op->N;
-  const int pc = o ? o->pc : FL_PC_FD;
-  if (pc != FL_PC_NONE && pc != FL_PC_FD && pc != FL_PC_SPECTRAL && pc != FL_PC_LEARNED)
-    return fail(FL_E_INVALID, "unknown preconditioner");
+  int pc = o ? o->pc : FL_PC_FD;
+  if (pc == FL_PC_AUTO) pc = op->alpha < 1.0 ? FL_PC_NONE : FL_PC_FD;  // Sec. 4.1-4.2: none below alpha = 1
+  if (pc != FL_PC_NONE && !pc_is_sine(pc) && pc != FL_PC_LEARNED) return fail(FL_E_INVALID, "unknown preconditioner");
   fl_net net = o ? o->net : nullptr;
   if (pc == FL_PC_LEARNED) {
     if (mask) return fail(FL_E_UNSUPPORTED, "the learned preconditioner is built for the box (no mask)");
@@ -495,19 +506,44 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
   const int poll = (o && o->poll_every > 0) ? o->poll_every : 8;
   int maxit = (o && o->maxit > 0) ? o->maxit : std::max(1000, (int)(10 * std::sqrt((double)N)));
   Workspace& w = op->ws[0];
-  Prob pb = solver_prob<double>(op, mask, s0, s1, p0, p1);
-  STCHK(set_precond<double>(op, pb, pc));
   fl_info inf;
   memset(&inf, 0, sizeof(inf));
   // the mixed loop ends with the true FP64 residual of the returned x in hand
   bool have_final = false;
   double rr_final = 0.0;
-  // ff
-  LAUNCH(k_dot<double>, dim3(std::min<long>(1024, nblocks_vec(N))), dim3(256), 0, s, pb, (const void*)w.f,
-         (const void*)w.f, (int)S_DOT, N);
-  LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, pb, (int)S_DOT, (int)FIN_FF);
-  if (!use_x0) LAUNCH(k_fill<double>, dim3(nblocks_vec(N)), dim3(256), 0, s, (double*)w.x, 0.0, N);
-  STCHK(read_scalars(op, w.sc));
+  // on a mask the system lives on Omega: f and the initial iterate restricted to it
+  const bool cap_want = mask && pc_exact_on_mask(pc);
+  {
+    Prob pm = solver_prob<double>(op, mask, s0, s1, p0, p1);
+    if (mask) {
+      LAUNCH(k_mask_mul<double>, dim3(nblocks_vec(N)), dim3(256), 0, s, (double*)w.f, mask, N);
+      if (use_x0) LAUNCH(k_mask_mul<double>, dim3(nblocks_vec(N)), dim3(256), 0, s, (double*)w.x, mask, N);
+    }
+    if (cap_want) STCHK(cap_hash_launch(op, mask, &w.sc->mhash));
+    // ff
+    LAUNCH(k_dot<double>, dim3(std::min<long>(1024, nblocks_vec(N))), dim3(256), 0, s, pm, (const void*)w.f,
+           (const void*)w.f, (int)S_DOT, N);
+    LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, pm, (int)S_DOT, (int)FIN_FF);
+    if (!use_x0) LAUNCH(k_fill<double>, dim3(nblocks_vec(N)), dim3(256), 0, s, (double*)w.x, 0.0, N);
+    STCHK(read_scalars(op, w.sc));
+  }
+  bool cap = false;
+  if (cap_want) {
+    // the exact preconditioner on Omega: capacitance correction of the box inverse
+    Prob pbox = base_prob<double>(op, 1);
+    pbox.p0 = p0;
+    pbox.p1 = p1;
+    STCHK(set_precond<double>(op, pbox, pc));
+    const unsigned long long key = op->hsc->mhash;
+    STCHK(cap_prepare(op, mask, pbox, key, &cap));
+    STCHK(ensure_ws<double>(op, 1, true));  // the build may have returned its batched workspace
+    if (cap) {
+      STCHK(cap_buffers<double>(op, 1));
+      if (mixed) STCHK(cap_buffers<float>(op, 1));
+    }
+  }
+  Prob pb = solver_prob<double>(op, mask, s0, s1, p0, p1);
+  STCHK(set_precond<double>(op, pb, pc));
   const double ff = op->hsc->ff;
   if (!std::isfinite(ff)) {
     info->status = FL_E_INVALID;
@@ -535,7 +571,7 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
       inf.status = stt == 1 ? FL_OK : stt == 2 ? FL_E_NOCONV : FL_E_BREAKDOWN;
     } else {
       Scalars res;
-      STCHK(krylov<double>(op, pb, pc, tol, maxit, use_x0, graph, poll, &res));
+      STCHK(krylov<double>(op, pb, pc, tol, maxit, use_x0, graph, poll, &res, cap));
       inf.iters = res.itc[0];
       inf.rel_res_recur = ff > 0 ? std::sqrt(res.rr / ff) : 0.0;
       inf.status = res.done == 1 ? FL_OK : res.done == 2 ? FL_E_NOCONV : FL_E_BREAKDOWN;
@@ -595,7 +631,7 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
         LAUNCH(k_dot<float>, dim3(std::min<long>(1024, nblocks_vec(N))), dim3(256), 0, s, p32,
                (const void*)w32.r, (const void*)w32.r, (int)S_DOT, N);
         LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, p32, (int)S_DOT, (int)FIN_FF);
-        STCHK(krylov<float>(op, p32, pc, itol, inner_cap, 0, graph, poll, &res));
+        STCHK(krylov<float>(op, p32, pc, itol, inner_cap, 0, graph, poll, &res, cap));
       }
       inf.iters += res.itc[0];
       inf.rel_res_recur = res.ff > 0 ? std::sqrt(res.rr / res.ff) : 0.0;
@@ -640,12 +676,26 @@ static fl_status apply_t(fl_op op, const void* u, void* Mu, long batch, const ui
 template <typename T>
 static fl_status precond_t(fl_op op, const void* r, void* z, long batch, const uint8_t* mask, double p0, double p1,
                            int kind) {
+  if (!pc_is_sine(kind)) return fail(FL_E_INVALID, "kind must be FL_PC_FD, SPECTRAL, MTILDE or FD_BOX");
   STCHK(ensure_ws<T>(op, batch, false));
+  bool cap = false;
+  if (mask && pc_exact_on_mask(kind)) {
+    Workspace& w0 = op->ws[tix<T>()];
+    STCHK(cap_hash_launch(op, mask, &w0.sc->mhash));
+    STCHK(read_scalars(op, w0.sc));
+    Prob pbox = base_prob<double>(op, 1);
+    pbox.p0 = p0;
+    pbox.p1 = p1;
+    STCHK(set_precond<double>(op, pbox, kind));
+    STCHK(cap_prepare(op, mask, pbox, op->hsc->mhash, &cap));
+    STCHK(ensure_ws<T>(op, batch, false));
+    if (cap) STCHK(cap_buffers<T>(op, batch));
+  }
   Workspace& w = op->ws[tix<T>()];
   Prob pb = base_prob<T>(op, batch);
-  STCHK(set_precond<T>(op, pb, kind));
   pb.p0 = p0;
   pb.p1 = p1;
+  STCHK(set_precond<T>(op, pb, kind));
   pb.in = r;
   pb.out = z;
   pb.T1 = w.T1;
@@ -653,6 +703,7 @@ static fl_status precond_t(fl_op op, const void* r, void* z, long batch, const u
   pb.sc = w.sc;
   pb.part = w.part;
   pb.pstride = w.npart;
+  if (cap) return cap_precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pb, Iter{0, 0}, 0);
   return precond_seq<T, DPRO_PLAIN, DEPI_FINAL>(op, pb, Iter{0, 0}, 0);
 }
 
@@ -773,6 +824,15 @@ fl_status fl_precond_spectral(fl_op op, const void* r, void* z, int dtype, int64
   if (batch < 1) return fail(FL_E_INVALID, "batch must be >= 1");
   if (dtype == FL_F64) return precond_t<double>(op, r, z, batch, mask, p0, p1, FL_PC_SPECTRAL);
   if (dtype == FL_F32) return precond_t<float>(op, r, z, batch, mask, p0, p1, FL_PC_SPECTRAL);
+  return fail(FL_E_INVALID, "dtype must be FL_F64 or FL_F32");
+}
+
+fl_status fl_precond_any(fl_op op, int kind, const void* r, void* z, int dtype, int64_t batch, const uint8_t* mask,
+                          double p0, double p1) {
+  if (!op || !r || !z) return fail(FL_E_INVALID, "NULL argument");
+  if (batch < 1) return fail(FL_E_INVALID, "batch must be >= 1");
+  if (dtype == FL_F64) return precond_t<double>(op, r, z, batch, mask, p0, p1, kind);
+  if (dtype == FL_F32) return precond_t<float>(op, r, z, batch, mask, p0, p1, kind);
   return fail(FL_E_INVALID, "dtype must be FL_F64 or FL_F32");
 }
 

@@ -61,9 +61,28 @@ struct Workspace {
   long npart = 0;
   // graph of `gK` PCG iterations starting at an odd iteration
   hipGraphExec_t gexec = nullptr;
-  int gK = 0, gpc = -1;
+  int gK = 0, gpc = -1, gcap = 0;
   double gs0 = 0, gs1 = 0, gp0 = 0, gp1 = 0;
   const uint8_t* gmask = nullptr;
+};
+
+// Capacitance correction that makes the sine-diagonalised preconditioner
+// exact on an occluded domain (fl_capacity.hip).  One per op, keyed by the
+// mask (pointer and checksum of its points) and the box operator
+// p0 I + p1 pcs T it inverts.
+constexpr long kCapMax = 8192;  // largest number of exterior points next to the domain
+struct CapCache {
+  bool valid = false;
+  unsigned long long key = 0;
+  const uint8_t* mask = nullptr;
+  double p0 = 0, p1 = 0, pcs = 0;
+  long k = 0;                          // |Gamma|
+  int* idx = nullptr;                  // [k] grid indices of Gamma (device)
+  void* cinv[2] = {nullptr, nullptr};  // [k][k] inverse capacitance matrix, FP64 / FP32
+  void* Y[2] = {nullptr, nullptr};     // [cap][N] first box solve
+  void* S[2] = {nullptr, nullptr};     // [cap][N] zero but on Gamma (mu)
+  void* G[2] = {nullptr, nullptr};     // [cap][k] gathered first solve on Gamma
+  long cap[2] = {0, 0};
 };
 
 struct fl_op_s {
@@ -84,6 +103,7 @@ struct fl_op_s {
   Axis ax[2][3];            // per dtype
   std::vector<void*> tables;
   Workspace ws[2];
+  CapCache cap;
   Scalars* hsc = nullptr;   // pinned host mirror of a Scalars
   ~fl_op_s();
 };
@@ -241,15 +261,29 @@ fl_status build_tau(fl_op op);
 
 // Select the preconditioner of a solver Prob: the FD Laplacian keeps pcs =
 // C|B|h^-alpha; the sine-basis diagonal sets the table and pcs = 1.
+// M~ = q0 I + q1 T with q0 = C h^-alpha (Z - 2d), q1 = C h^-alpha (1 - B): the
+// shifted system p0 I + p1 M~ has sine eigenvalues (p0 + p1 q0) + p1 q1 sum_a eig_a.
 template <typename T> inline fl_status set_precond(fl_op op, Prob& pb, int pc) {
   if (pc == FL_PC_SPECTRAL) {
     STCHK(build_tau(op));
     pb.tau = op->tau[tix<T>()];
     pb.pcs = 1.0;
+  } else if (pc == FL_PC_MTILDE) {
+    const double Ch = op->cst[7];
+    pb.tau = nullptr;
+    pb.p0 = pb.p0 + pb.p1 * Ch * (op->cst[1] - 2.0 * op->d);
+    pb.pcs = Ch * (1.0 - op->cst[2]);
   } else {
     pb.tau = nullptr;
   }
   return FL_OK;
+}
+
+// Preconditioners that are made exact on an occluded domain.
+inline bool pc_exact_on_mask(int pc) { return pc == FL_PC_FD || pc == FL_PC_MTILDE; }
+// Anything that applies the sine-transform preconditioner (not plain CG).
+inline bool pc_is_sine(int pc) {
+  return pc == FL_PC_FD || pc == FL_PC_SPECTRAL || pc == FL_PC_MTILDE || pc == FL_PC_FD_BOX;
 }
 
 // Learned preconditioner (fl_net.hip): scratch on op's grid, then flexible CG
@@ -260,6 +294,16 @@ fl_status learned_prepare(fl_op op, fl_net net, size_t elem);
 template <typename T>
 fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxit, double ff, double rr0, int* iters,
                       double* rr_out, int* status, int* fell_back);
+
+// Exact preconditioner on occluded domains (fl_capacity.hip): the mask
+// checksum into *dst (device), the build or reuse of the correction for the
+// box operator of pbox, its per-precision buffers, and the corrected
+// preconditioner sequence (same epilogues as precond_seq).
+fl_status cap_hash_launch(fl_op op, const uint8_t* mask, unsigned long long* dst);
+fl_status cap_prepare(fl_op op, const uint8_t* mask, const Prob& pbox, unsigned long long key, bool* active);
+void cap_destroy(fl_op op);
+template <typename T> fl_status cap_buffers(fl_op op, long nrhs);
+template <typename T, int DPRO, int DEPI> fl_status cap_precond_seq(fl_op op, const Prob& pb, Iter it, int chk);
 
 // Launch sequences (defined per precision in fl_apply.hip / fl_precond.hip).
 template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob& pb, Iter it, int chk);

@@ -707,7 +707,10 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
       T v = ((const T*)pb.in)[e];
       // the domain mask acts on grid functions only: the input of the first
       // pass (or of the single 1D pass), never on a transformed intermediate
-      if (pb.mask && (DEPI == DEPI_STORE || pb.d == 1)) v *= (T)pb.mask[e % nper];
+      if (DEPI == DEPI_STORE || pb.d == 1) {
+        if (pb.mask) v *= (T)pb.mask[e % nper];
+        if (pb.corr) v += ((const T*)pb.corr)[e];
+      }
       return v;
     }
   };
@@ -769,7 +772,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
       if (!(s ? vb : va)) continue;
       long e = (s ? rb : ra) * n + i;
       T v = (s ? sv.y : sv.x) * (T)norm;
-      if (pb.mask && (DEPI != DEPI_STORE || pb.d == 1)) v *= (T)pb.mask[e % nper];
+      if (pb.mask && !pb.nomask_out && (DEPI != DEPI_STORE || pb.d == 1)) v *= (T)pb.mask[e % nper];
       if (DEPI != DEPI_Z) {
         ((T*)pb.out)[e] = v;
       } else {

@@ -93,6 +93,7 @@ template <typename T, int DPRO, int DEPI> fl_status precond_seq(fl_op op, Prob p
 template fl_status precond_seq<FL_T, DPRO_PLAIN, DEPI_FINAL>(fl_op, Prob, Iter, int);
 template fl_status precond_seq<FL_T, DPRO_PLAIN, DEPI_Z>(fl_op, Prob, Iter, int);
 template fl_status precond_seq<FL_T, DPRO_UPD, DEPI_Z>(fl_op, Prob, Iter, int);
+template fl_status precond_seq<FL_T, DPRO_UPD, DEPI_FINAL>(fl_op, Prob, Iter, int);
 
 // One pass of the preconditioner on the op's workspace, launched with the same
 // lane tuning as precond_seq: 3 first sine pass (in -> T1), 4 scaled column

@@ -49,6 +49,7 @@ struct Scalars {
   int itc[2];     // iteration counter ring (written by parity)
   int maxit;
   int cnt[8];     // partial counts per site
+  unsigned long long mhash;  // checksum of a domain mask (identifies the mask a correction was built for)
 };
 
 enum Site { S_PQ = 0, S_RR = 1, S_RZ0 = 2, S_RZ1 = 3, S_DOT = 4, S_AUX = 5, NSITE = 6 };
@@ -73,6 +74,8 @@ struct Prob {
   void* W2;         // complex work, 3D only: [nrhs][n_0][P_1][H_2]
   void* T1;         // real work for the sine transforms  [nrhs][n...]
   const uint8_t* mask;  // optional domain mask (1 inside), [n...]
+  const void* corr;     // optional correction added to the masked input of the first sine pass, [nrhs][n...]
+  int nomask_out;       // 1: the last sine pass leaves its output unmasked
   // Krylov vectors (solver launches)
   void* x;
   void* r;

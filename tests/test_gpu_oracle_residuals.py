@@ -71,7 +71,7 @@ def test_1024_fp64_pcg_and_learned_full_residual(net2d):
     fl = _fl()
     w = workload_elliptic_1024(1.0)
     n, alpha, h, f = w["n"], w["alpha"], w["h"], w["f"]
-    op = fl.Op(2, alpha, h, (n, n))
+    op = fl.Op(2, alpha, h, (n, n), stream=net2d.stream)
     ref = O.Operator(2, alpha, h, (n, n))
     for name, opts in (("fp64_pcg", fl.solve_opts(pc=fl.FL_PC_FD, mixed=0)),
                        ("learned_f32", fl.solve_opts(pc=fl.FL_PC_LEARNED, mixed=1, net=net2d))):

@@ -139,7 +139,9 @@ def test_precond_masked(n):
     op = fl.Op(d, alpha, h, n)
     m = random_mask(n, 4) if d > 1 else (np.arange(n[0]) % 5 != 0).astype(np.uint8)
     r = white_noise(n, 22)
-    got = op.precond(_dev(r), mask=_dev(m, torch.uint8)).cpu().numpy()
+    # FL_PC_FD_BOX: the box inverse restricted to the mask (the exact inverse
+    # on the mask, FL_PC_FD, is tested in test_gpu_occluded.py)
+    got = op.precond(_dev(r), mask=_dev(m, torch.uint8), kind=fl.FL_PC_FD_BOX).cpu().numpy()
     want = m * PC.apply_inverse(r * m, PC.pc_scale(d, alpha, h))
     assert _rel(got, want) <= 1e-12
 
