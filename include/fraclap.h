@@ -210,11 +210,18 @@ fl_status fl_step(fl_op op, double* u, double dt, double theta, const double* f_
  *   u[i]     : device FP64, initial guess when opts->use_x0, solution out
  *   infos[i] : each problem's iterations, status and residuals; ms is the
  *              wall time of the whole batch
- * Per-problem Krylov vectors and work arrays are allocated on each call and
- * freed before it returns.  Returns the status of a failing problem (and its
- * infos entry says which) when any problem misses the tolerance. */
+ *   tol[i]   : host array, the relative residual tolerance of each problem (> 0)
+ * Per-problem Krylov vectors, work arrays and descriptor tables are allocated
+ * on the first call for a set of problems and kept for the next batched call
+ * with the same ops, masks, shifts, precision and preconditioner (one such
+ * set at a time, for fl_solve_batched and fl_step_batched together), which
+ * then allocates nothing; a call for another set, or fl_op_destroy of a
+ * member, releases them.  Returns the status of a failing problem (and its
+ * infos entry says which) when any problem misses its tolerance.
+ * Masked problems take the box preconditioner restricted to the mask
+ * (FL_PC_FD and FL_PC_FD_BOX are the same here). */
 fl_status fl_solve_batched(int nprob, const fl_op* ops, const double* const* f, const uint8_t* const* masks,
-                           double tol, const fl_solve_opts* opts, double* const* u, fl_info* infos);
+                           const double* tol, const fl_solve_opts* opts, double* const* u, fl_info* infos);
 
 /* Advance nprob problems by nsteps implicit theta steps each (Sec. 3.2, the
  * same step as fl_step with zero forcing and no mask), every step one batched
@@ -288,6 +295,10 @@ fl_status fl_op_destroy(fl_op op);
 
 /* Thread-local description of the last failure ("" if none). */
 const char* fl_last_error(void);
+
+/* Measurement aid: the number of device allocations (hipMalloc) the library
+ * has made in this process, over all ops, nets and batches. */
+int64_t fl_device_allocations(void);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "ok", -1: "invalid", -2: "nomem", -3: "hip", -4: "noconv", -5
 
 EXPORTED = ["fl_make_weights", "fl_op_constants", "fl_op_padded", "fl_op_plan", "fl_op_export", "fl_apply", "fl_precond",
             "fl_precond_spectral", "fl_precond_any", "fl_solve", "fl_step", "fl_solve_batched", "fl_step_batched", "fl_profile_pass", "fl_op_destroy",
-            "fl_last_error", "fl_net_create", "fl_net_nparams", "fl_net_set_params", "fl_net_get_params",
+            "fl_last_error", "fl_device_allocations", "fl_net_create", "fl_net_nparams", "fl_net_set_params", "fl_net_get_params",
             "fl_net_forward", "fl_net_grad", "fl_net_train", "fl_learned_pairs", "fl_net_profile", "fl_net_destroy"]
 
 
@@ -74,13 +74,14 @@ def load(path=LIB_PATH):
         "fl_precond_any": [P, I, P, P, I, I64, P, D, D],
         "fl_solve": [P, P, P, D, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(Info)],
         "fl_step": [P, P, D, D, P, P, P, D, ctypes.POINTER(SolveOpts), ctypes.POINTER(Info)],
-        "fl_solve_batched": [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), D,
+        "fl_solve_batched": [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(D),
                              ctypes.POINTER(SolveOpts), ctypes.POINTER(P), ctypes.POINTER(Info)],
         "fl_step_batched": [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(D), D, I, D,
                             ctypes.POINTER(SolveOpts), ctypes.POINTER(Info)],
         "fl_profile_pass": [P, I, I, I, ctypes.POINTER(D)],
         "fl_op_destroy": [P],
         "fl_last_error": [],
+        "fl_device_allocations": [],
         "fl_net_create": [I, P, ctypes.POINTER(P)],
         "fl_net_nparams": [I],
         "fl_net_set_params": [P, P],
@@ -95,9 +96,15 @@ def load(path=LIB_PATH):
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
-        fn.restype = {"fl_last_error": ctypes.c_char_p, "fl_net_nparams": ctypes.c_int64}.get(name, ctypes.c_int)
+        fn.restype = {"fl_last_error": ctypes.c_char_p, "fl_net_nparams": ctypes.c_int64,
+                      "fl_device_allocations": ctypes.c_int64}.get(name, ctypes.c_int)
     _lib = lib
     return lib
+
+
+def device_allocations():
+    """Device allocations the library has made so far in this process."""
+    return int(load().fl_device_allocations())
 
 
 def _check(status):
@@ -294,7 +301,8 @@ def _batch_common(ops):
 
 
 def solve_batched(ops, fs, tol=1e-10, opts=None, masks=None, us=None, check=True):
-    """Solve ops[i] u_i = fs[i] for every i, all problems per launch (FP64 in/out)."""
+    """Solve ops[i] u_i = fs[i] for every i, all problems per launch (FP64 in/out);
+    tol is one tolerance for all or a sequence of one per problem."""
     lib = load()
     k = len(ops)
     if len(fs) != k:
@@ -311,7 +319,11 @@ def solve_batched(ops, fs, tol=1e-10, opts=None, masks=None, us=None, check=True
     hm = (P * k)(*[0 if (masks is None or masks[i] is None) else masks[i].data_ptr() for i in range(k)])
     hu = (P * k)(*[u.data_ptr() for u in us])
     infos = (Info * k)()
-    st = lib.fl_solve_batched(k, hops, hf, hm, tol, ctypes.byref(opts or solve_opts()), hu, infos)
+    tols = [float(t) for t in tol] if hasattr(tol, "__len__") else [float(tol)] * k
+    if len(tols) != k:
+        raise ValueError("one tolerance per problem")
+    htol = (ctypes.c_double * k)(*tols)
+    st = lib.fl_solve_batched(k, hops, hf, hm, htol, ctypes.byref(opts or solve_opts()), hu, infos)
     if check:
         _check(st)
     return us, [i.as_dict() for i in infos]

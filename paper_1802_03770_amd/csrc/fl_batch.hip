@@ -9,6 +9,8 @@
 // and once with FL_BATCH_HOST for the C entry points.
 #include "fl_internal.hpp"
 #include "fl_batch.hpp"
+#include <memory>
+#include <mutex>
 
 // ---------------------------------------------------------------------------
 // per-precision launch sequences
@@ -282,7 +284,15 @@ struct Batch {
   int pc = FL_PC_FD;
   void* d_true = nullptr;
   hipGraphExec_t g[2] = {nullptr, nullptr};
-  int gpc[2] = {-1, -1};
+  int gpc[2] = {-1, -1}, gpoll[2] = {0, 0};
+  double* d_tol = nullptr;      // per-problem tolerances (device)
+  void* d_rhs = nullptr;        // explicit-part role of theta steps (theta < 1)
+  std::vector<double> tolv;     // the same on the host
+  // what the batch was built for (a later call with the same key reuses it)
+  std::vector<const uint8_t*> kmasks;
+  std::vector<double> ks1, kp1;
+  double ks0 = 0, kp0 = 0, ktheta = -1;
+  int kmixed = 0, kpc = -1;
   ~Batch() {
     for (void* p : owned) (void)hipFree(p);
     for (auto& e : g) if (e) (void)hipGraphExecDestroy(e);
@@ -408,10 +418,11 @@ template <typename T> static fl_status per_dot(Batch& bt, BatchT& t, int p, cons
 // Batched Krylov solve on precision T: r holds the initial residuals, x the
 // initial iterates, sc[p].ff the squared rhs norms (and sc[p].rr the squared
 // residual norms if use_rr).
-template <typename T> static fl_status bt_krylov(Batch& bt, BatchT& t, Scalars* dsc, int pc, double tol, int maxit,
-                                                 int use_rr, int graph, int poll, hipStream_t s, int gslot) {
+template <typename T> static fl_status bt_krylov(Batch& bt, BatchT& t, Scalars* dsc, int pc, double tol,
+                                                 const double* d_tols, int maxit, int use_rr, int graph, int poll,
+                                                 hipStream_t s, int gslot) {
   const int np = bt.desc.np;
-  LAUNCH(k_init_b<>, dim3(1, np), dim3(64), 0, s, (const Prob*)t.d_iter, tol, maxit, use_rr);
+  LAUNCH(k_init_b<>, dim3(1, np), dim3(64), 0, s, (const Prob*)t.d_iter, tol, d_tols, maxit, use_rr);
   if (pc) {
     STCHK(bt_initial_precond<T>(t, pc, s));
   } else {
@@ -426,7 +437,7 @@ template <typename T> static fl_status bt_krylov(Batch& bt, BatchT& t, Scalars* 
   if (poll & 1) ++poll;
   STCHK(bt_iteration<T>(t, pc, 0, s));
   bool use_graph = graph && s != nullptr;
-  if (use_graph && (!bt.g[gslot] || bt.gpc[gslot] != pc)) {
+  if (use_graph && (!bt.g[gslot] || bt.gpc[gslot] != pc || bt.gpoll[gslot] != poll)) {
     if (bt.g[gslot]) (void)hipGraphExecDestroy(bt.g[gslot]);
     bt.g[gslot] = nullptr;
     hipGraph_t g;
@@ -439,6 +450,7 @@ template <typename T> static fl_status bt_krylov(Batch& bt, BatchT& t, Scalars* 
     HIPCHK(hipGraphInstantiate(&bt.g[gslot], g, nullptr, nullptr, 0));
     (void)hipGraphDestroy(g);
     bt.gpc[gslot] = pc;
+    bt.gpoll[gslot] = poll;
   }
   int k = 1;
   for (;;) {
@@ -508,12 +520,67 @@ static fl_status make_batch(Batch& bt, int nprob, const fl_op* ops, const uint8_
     STCHK(build_roles<float>(bt, bt.t32, bt.b32, bt.sc32, bt.part32, s0v, s1, p0v, p1, masks));
   }
   if (hipHostMalloc((void**)&bt.hpin, nprob * sizeof(Scalars)) != hipSuccess) return fail(FL_E_NOMEM, "pinned");
+  STCHK(bt.alloc((void**)&bt.d_tol, nprob * sizeof(double)));
+  bt.tolv.assign(nprob, 0.0);
+  bt.kmasks.assign(nprob, nullptr);
+  if (masks)
+    for (int p = 0; p < nprob; ++p) bt.kmasks[p] = masks[p];
+  bt.ks1 = s1;
+  bt.kp1 = p1;
+  bt.ks0 = s0;
+  bt.kp0 = p0;
+  bt.kmixed = mixed ? 1 : 0;
+  bt.kpc = o ? o->pc : FL_PC_FD;
   return FL_OK;
+}
+
+// The batch of the last batched call, kept for the next call with the same
+// problems (ops, masks, shifts, precision and preconditioner): its vectors,
+// work arrays, descriptor tables and captured graphs are reused, so repeated
+// calls allocate nothing.  fl_op_destroy of any member releases it.
+static std::mutex g_batch_mu;
+static std::unique_ptr<Batch> g_batch;
+
+static bool batch_matches(const Batch& bt, int nprob, const fl_op* ops, const uint8_t* const* masks,
+                          const std::vector<double>& s1, const std::vector<double>& p1, double s0, double p0,
+                          const fl_solve_opts* o, double theta) {
+  if (bt.desc.np != nprob || (int)bt.ops.size() != nprob) return false;
+  for (int p = 0; p < nprob; ++p) {
+    if (bt.ops[p] != ops[p]) return false;
+    if (bt.kmasks[p] != (masks ? masks[p] : nullptr)) return false;
+  }
+  return bt.ks1 == s1 && bt.kp1 == p1 && bt.ks0 == s0 && bt.kp0 == p0 && bt.kmixed == ((o && o->mixed) ? 1 : 0) &&
+         bt.kpc == (o ? o->pc : FL_PC_FD) && bt.ktheta == theta;
+}
+
+static fl_status batch_get(Batch** out, int nprob, const fl_op* ops, const uint8_t* const* masks,
+                           const std::vector<double>& s1, const std::vector<double>& p1, double s0, double p0,
+                           const fl_solve_opts* o, double theta) {
+  if (g_batch && batch_matches(*g_batch, nprob, ops, masks, s1, p1, s0, p0, o, theta)) {
+    *out = g_batch.get();
+    return FL_OK;
+  }
+  g_batch.reset();
+  std::unique_ptr<Batch> bt(new Batch());
+  STCHK(make_batch(*bt, nprob, ops, masks, s1, p1, s0, p0, o));
+  bt->ktheta = theta;
+  g_batch = std::move(bt);
+  *out = g_batch.get();
+  return FL_OK;
+}
+
+void batch_forget_op(fl_op op) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  if (g_batch && std::find(g_batch->ops.begin(), g_batch->ops.end(), op) != g_batch->ops.end()) {
+    (void)hipStreamSynchronize(op->stream);
+    g_batch.reset();
+  }
 }
 
 // Solve A_p x_p = f_p for every problem: f in b64[p].f, x in b64[p].x (initial
 // guess when use_x0).  FP64 PCG, or FP32 PCG with FP64 refinement.
-static fl_status batch_solve(Batch& bt, double tol, const fl_solve_opts* o, int use_x0, std::vector<fl_info>& out) {
+static fl_status batch_solve(Batch& bt, const double* tols, const fl_solve_opts* o, int use_x0,
+                             std::vector<fl_info>& out) {
   const int np = bt.desc.np;
   hipStream_t s = bt.ops[0]->stream;
   const int pc = o ? o->pc : FL_PC_FD;
@@ -524,6 +591,8 @@ static fl_status batch_solve(Batch& bt, double tol, const fl_solve_opts* o, int 
   for (auto op : bt.ops) Nmax = std::max(Nmax, op->N);
   const int maxit = (o && o->maxit > 0) ? o->maxit : std::max(1000, (int)(10 * std::sqrt((double)Nmax)));
   out.assign(np, fl_info{});
+  for (int p = 0; p < np; ++p) bt.tolv[p] = tols[p];
+  HIPCHK(hipMemcpyAsync(bt.d_tol, bt.tolv.data(), np * sizeof(double), hipMemcpyHostToDevice, s));
   // ff and initial residuals
   for (int p = 0; p < np; ++p) {
     ProbBufs& b = bt.b64[p];
@@ -552,7 +621,7 @@ static fl_status batch_solve(Batch& bt, double tol, const fl_solve_opts* o, int 
       for (int p = 0; p < np; ++p)
         HIPCHK(hipMemcpyAsync(bt.b64[p].r, bt.b64[p].f, bt.ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    STCHK(bt_krylov<double>(bt, bt.t64, bt.sc64, pc, tol, maxit, use_x0, graph, poll, s, 0));
+    STCHK(bt_krylov<double>(bt, bt.t64, bt.sc64, pc, 0.0, bt.d_tol, maxit, use_x0, graph, poll, s, 0));
     for (int p = 0; p < np; ++p) {
       const Scalars& sc = bt.hsc[p];
       out[p].iters = std::max(sc.itc[0], sc.itc[1]);
@@ -570,7 +639,7 @@ static fl_status batch_solve(Batch& bt, double tol, const fl_solve_opts* o, int 
       bool any = false;
       for (int p = 0; p < np; ++p) {
         if (!active[p]) continue;
-        if (ff[p] == 0.0 || std::sqrt(rr[p] / ff[p]) <= tol) {
+        if (ff[p] == 0.0 || std::sqrt(rr[p] / ff[p]) <= bt.tolv[p]) {
           active[p] = 0;
           out[p].status = FL_OK;
         } else if (!std::isfinite(rr[p])) {
@@ -591,7 +660,7 @@ static fl_status batch_solve(Batch& bt, double tol, const fl_solve_opts* o, int 
         STCHK(per_dot<float>(bt, bt.t32, p, bt.b32[p].r, bt.b32[p].r, FIN_FF, s));
         if (active[p]) out[p].outer_iters = outer + 1;
       }
-      STCHK(bt_krylov<float>(bt, bt.t32, bt.sc32, pc, itol, maxit, 0, graph, poll, s, 1));
+      STCHK(bt_krylov<float>(bt, bt.t32, bt.sc32, pc, itol, nullptr, maxit, 0, graph, poll, s, 1));
       for (int p = 0; p < np; ++p) {
         const Scalars& sc = bt.hsc[p];
         if (!active[p]) continue;
@@ -623,15 +692,18 @@ static fl_status batch_solve(Batch& bt, double tol, const fl_solve_opts* o, int 
 extern "C" {
 
 fl_status fl_solve_batched(int nprob, const fl_op* ops, const double* const* f, const uint8_t* const* masks,
-                           double tol, const fl_solve_opts* opts, double* const* u, fl_info* infos) {
+                           const double* tol, const fl_solve_opts* opts, double* const* u, fl_info* infos) {
   auto t0 = std::chrono::steady_clock::now();
-  if (nprob < 1 || !ops || !f || !u || !infos) return fail(FL_E_INVALID, "NULL argument");
-  if (!(tol > 0.0)) return fail(FL_E_INVALID, "tol must be positive");
-  for (int p = 0; p < nprob; ++p)
+  if (nprob < 1 || !ops || !f || !u || !infos || !tol) return fail(FL_E_INVALID, "NULL argument");
+  for (int p = 0; p < nprob; ++p) {
     if (!ops[p] || !f[p] || !u[p]) return fail(FL_E_INVALID, "NULL problem entry");
-  Batch bt;
+    if (!(tol[p] > 0.0)) return fail(FL_E_INVALID, "tol must be positive");
+  }
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  Batch* bp = nullptr;
   std::vector<double> s1(nprob, 1.0), p1(nprob, 1.0);
-  STCHK(make_batch(bt, nprob, ops, masks, s1, p1, 0.0, 0.0, opts));
+  STCHK(batch_get(&bp, nprob, ops, masks, s1, p1, 0.0, 0.0, opts, -1.0));
+  Batch& bt = *bp;
   hipStream_t s = ops[0]->stream;
   const int use_x0 = opts ? opts->use_x0 : 0;
   for (int p = 0; p < nprob; ++p) {
@@ -661,15 +733,19 @@ fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const d
   if (!(theta > 0.0 && theta <= 1.0) || !(tol > 0.0) || nsteps < 0) return fail(FL_E_INVALID, "theta, tol or nsteps");
   for (int p = 0; p < nprob; ++p)
     if (!ops[p] || !u[p] || !(dt[p] > 0.0)) return fail(FL_E_INVALID, "bad problem entry");
-  Batch bt;
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  Batch* bp = nullptr;
   std::vector<double> s1(nprob), p1(nprob);
   for (int p = 0; p < nprob; ++p) s1[p] = p1[p] = theta * dt[p];
-  STCHK(make_batch(bt, nprob, ops, nullptr, s1, p1, 1.0, 1.0, opts));
+  STCHK(batch_get(&bp, nprob, ops, nullptr, s1, p1, 1.0, 1.0, opts, theta));
+  Batch& bt = *bp;
   hipStream_t s = ops[0]->stream;
-  // explicit part (I - (1-theta) dt M) u for theta < 1: a second role with that shift
+  const std::vector<double> tols(nprob, tol);
+  // explicit part (I - (1-theta) dt M) u for theta < 1: a second role with that
+  // shift, uploaded once per batch
   std::vector<Prob> rhs;
-  void* d_rhs = nullptr;
-  if (theta < 1.0) {
+  void* d_rhs = bt.d_rhs;
+  if (theta < 1.0 && !d_rhs) {
     rhs = bt.t64.h_res;
     for (int p = 0; p < nprob; ++p) {
       rhs[p].s0 = 1.0;
@@ -678,6 +754,7 @@ fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const d
       rhs[p].out = bt.b64[p].f;
     }
     STCHK(upload_vec(bt, rhs.data(), nprob * sizeof(Prob), &d_rhs));
+    bt.d_rhs = d_rhs;
   }
   for (int p = 0; p < nprob; ++p) {
     HIPCHK(hipMemcpyAsync(bt.b64[p].x, u[p], ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -693,7 +770,7 @@ fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const d
         HIPCHK(hipMemcpyAsync(bt.b64[p].f, bt.b64[p].x, ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     std::vector<fl_info> out;
-    STCHK(batch_solve(bt, tol, opts, 1, out));
+    STCHK(batch_solve(bt, tols.data(), opts, 1, out));
     for (int p = 0; p < nprob; ++p) {
       infos[p].iters += out[p].iters;
       infos[p].outer_iters += out[p].outer_iters;

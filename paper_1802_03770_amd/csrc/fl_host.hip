@@ -12,7 +12,9 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #define FL_MISC_KERNELS
@@ -21,6 +23,7 @@
 using namespace fl;
 
 thread_local std::string g_err;
+std::atomic<long long> g_dallocs{0};
 
 // ---------------------------------------------------------------------------
 // plans and tables
@@ -256,6 +259,32 @@ template <typename T> static fl_status autotune_dst(fl_op op) {
   return FL_OK;
 }
 
+// Process-wide record of the autotuners' choices, per device and grid (and
+// the forced options the op was created with).
+struct TuneKey {
+  int dev, d, n[3], dst_mode, col_lanes, sine_col_lanes;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, d, n[0], n[1], n[2], dst_mode, col_lanes, sine_col_lanes) <
+           std::tie(o.dev, o.d, o.n[0], o.n[1], o.n[2], o.dst_mode, o.col_lanes, o.sine_col_lanes);
+  }
+};
+struct TuneVal {
+  int dst_form[2][3], col_tplf[2], dcol_tplf[2];
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneVal> g_tune;
+static bool tune_lookup(const TuneKey& k, TuneVal* v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(k);
+  if (it == g_tune.end()) return false;
+  *v = it->second;
+  return true;
+}
+static void tune_store(const TuneKey& k, const TuneVal& v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[k] = v;
+}
+
 static fl_status make_op(int d, double alpha, double h, const int64_t* n, const fl_weights_opts* o,
                          void* stream, fl_op* out) {
   if (!out) return fail(FL_E_INVALID, "out is NULL");
@@ -312,6 +341,31 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
   if (hipMemcpyAsync(op->cst, op->d_cst, 8 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return bail(fail(FL_E_HIP, "constants readback"));
+  // the plans depend on the grid and the device only: a shape tuned before
+  // on this device takes the recorded choice without timing again
+  TuneKey key;
+  key.dev = 0;
+  (void)hipGetDevice(&key.dev);
+  key.d = d;
+  for (int a = 0; a < 3; ++a) key.n[a] = op->n[a];
+  key.dst_mode = op->dst_mode;
+  key.col_lanes = op->col_lanes;
+  key.sine_col_lanes = op->sine_col_lanes;
+  TuneVal tv;
+  if (tune_lookup(key, &tv)) {
+    for (int p = 0; p < 2; ++p)
+      for (int a = 0; a < d; ++a)
+        if (tv.dst_form[p][a] != op->dst_form[p][a]) {
+          st = p == 0 ? build_axis<double>(op, a, tv.dst_form[p][a]) : build_axis<float>(op, a, tv.dst_form[p][a]);
+          if (st != FL_OK) return bail(st);
+        }
+    for (int p = 0; p < 2; ++p) {
+      op->ax[p][0].col_tplf = tv.col_tplf[p];
+      op->ax[p][0].dcol_tplf = tv.dcol_tplf[p];
+    }
+    *out = op;
+    return FL_OK;
+  }
   if (op->dst_mode == 0) {
     if ((st = autotune_dst<double>(op)) != FL_OK) return bail(st);
     if ((st = autotune_dst<float>(op)) != FL_OK) return bail(st);
@@ -320,6 +374,12 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
   if ((st = autotune_col<float>(op)) != FL_OK) return bail(st);
   if ((st = autotune_dcol<double>(op)) != FL_OK) return bail(st);
   if ((st = autotune_dcol<float>(op)) != FL_OK) return bail(st);
+  for (int p = 0; p < 2; ++p) {
+    for (int a = 0; a < 3; ++a) tv.dst_form[p][a] = op->dst_form[p][a];
+    tv.col_tplf[p] = op->ax[p][0].col_tplf;
+    tv.dcol_tplf[p] = op->ax[p][0].dcol_tplf;
+  }
+  tune_store(key, tv);
   *out = op;
   return FL_OK;
 }
@@ -886,6 +946,7 @@ fl_status fl_step(fl_op op, double* u, double dt, double theta, const double* f_
 
 fl_status fl_op_destroy(fl_op op) {
   if (!op) return FL_OK;
+  batch_forget_op(op);
   hipStreamSynchronize(op->stream);
   delete op;
   return FL_OK;
@@ -899,5 +960,7 @@ fl_status fl_profile_pass(fl_op op, int dtype, int pass, int reps, double* avg_m
 }
 
 const char* fl_last_error(void) { return g_err.c_str(); }
+
+int64_t fl_device_allocations(void) { return (int64_t)g_dallocs.load(); }
 
 }  // extern "C"

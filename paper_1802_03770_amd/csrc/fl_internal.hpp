@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -110,7 +111,11 @@ struct fl_op_s {
 
 template <typename T> constexpr int tix() { return sizeof(T) == 8 ? 0 : 1; }
 
+// Count of device allocations the library has made (fl_device_allocations).
+extern std::atomic<long long> g_dallocs;
+
 inline fl_status dalloc(void** p, size_t bytes) {
+  g_dallocs.fetch_add(1, std::memory_order_relaxed);
   if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
     *p = nullptr;
     return fail(FL_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
@@ -304,6 +309,10 @@ fl_status cap_prepare(fl_op op, const uint8_t* mask, const Prob& pbox, unsigned 
 void cap_destroy(fl_op op);
 template <typename T> fl_status cap_buffers(fl_op op, long nrhs);
 template <typename T, int DPRO, int DEPI> fl_status cap_precond_seq(fl_op op, const Prob& pb, Iter it, int chk);
+
+// Release the cached batch of the batched driver if it holds this op
+// (fl_batch.hip; called by fl_op_destroy).
+void batch_forget_op(fl_op op);
 
 // Launch sequences (defined per precision in fl_apply.hip / fl_precond.hip).
 template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob& pb, Iter it, int chk);

@@ -444,12 +444,22 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
   const cx<T>* src = (const cx<T>*)(cg.src == 1 ? pb.W1 : pb.W2) + grp * cg.gin + c0;
   cx<T>* dst = (cx<T>*)(cg.dst == 1 ? pb.W1 : pb.W2) + grp * cg.gout + c0;
   const int gv = (int)min((long)G, cg.gs - c0);  // valid lines in this tile
-  // coalesced load: consecutive threads take consecutive lines of one element row
-  for (long e = threadIdx.x; e < (long)G * L; e += blockDim.x) {
-    int j = e % G, i = e / G;
-    cx<T> v = {0, 0};
-    if (i < cg.nin && j < gv) v = src[(long)i * cg.ein + j];
-    line_at<T>(smem, j, L)[i] = v;
+  // Coalesced staging: consecutive threads take consecutive lines of one
+  // element row.  With G * tpl threads, thread t always serves line t % G
+  // and elements t / G + m tpl, so the strided loops below step a pointer
+  // and a 32-bit index instead of dividing a flat index every element.
+  const int jt = threadIdx.x % G, i0 = threadIdx.x / G;
+  const bool jv = jt < gv;
+  Line<T> lnt = line_at<T>(smem, jt, L);
+  {
+    const cx<T>* sp = src + (long)i0 * cg.ein + jt;
+    const long sst = (long)tpl * cg.ein;
+    const int nin = cg.nin;
+    for (int i = i0; i < L; i += tpl, sp += sst) {
+      cx<T> v = {0, 0};
+      if (i < nin && jv) v = *sp;
+      lnt[i] = v;
+    }
   }
   __syncthreads();
   Line<T> buf = line_at<T>(smem, g, L);
@@ -462,27 +472,26 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
     for (int a = 0; a < pb.d; ++a) norm *= pb.ax[a].P;
     const T s0 = (T)(pb.s0 / norm), s1 = (T)(pb.s1 / norm);
     const long tailsz = (pb.d == 2) ? pb.ax[1].H : (long)pb.ax[1].H * pb.ax[2].H;
-    for (long e = threadIdx.x; e < (long)G * L; e += blockDim.x) {
-      const int j = (int)(e % G), k = (int)(e / G);
-      if (j >= gv) continue;
-      const long c = c0 + j;
-      long lidx_tail;  // index contribution of the axes after axis 0
-      if (pb.d == 2) {
-        lidx_tail = c;
-      } else {
+    if (jv) {
+      const long c = c0 + jt;
+      long tail = c;  // index contribution of the axes after axis 0
+      if (pb.d != 2) {
         const int H2 = pb.ax[2].H, P1 = pb.ax[1].P;
-        lidx_tail = (long)fold((int)(c / H2), P1) * H2 + c % H2;
+        tail = (long)fold((int)(c / H2), P1) * H2 + c % H2;
       }
-      const T lv = lam[(long)fold(k, L) * tailsz + lidx_tail];
-      Line<T> ln = line_at<T>(smem, j, L);
-      ln[k] = cscale(ln[k], s0 + s1 * lv);
+      const T* lt = lam + tail;
+      for (int k = i0; k < L; k += tpl) {
+        const T lv = lt[(long)fold(k, L) * tailsz];
+        lnt[k] = cscale(lnt[k], s0 + s1 * lv);
+      }
     }
     __syncthreads();
     col_fft<T, true, LF, TPLF>(buf, A.fft, lane);
   }
-  for (long e = threadIdx.x; e < (long)G * cg.nout; e += blockDim.x) {
-    int j = e % G, i = e / G;
-    if (j < gv) dst[(long)i * cg.eout + j] = line_at<T>(smem, j, L)[i];
+  if (jv) {
+    cx<T>* dp = dst + (long)i0 * cg.eout + jt;
+    const long dst_step = (long)tpl * cg.eout;
+    for (int i = i0; i < cg.nout; i += tpl, dp += dst_step) *dp = lnt[i];
   }
 }
 
@@ -815,29 +824,59 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   if (grp >= dg.ngroup) return;
   T* base = (T*)pb.T1 + grp * dg.gstride + c0;
   const int gv = (int)min((long)G, dg.gs - c0);
-  if (direct) {
-    // real line j is component (j & 1) of FFT line j >> 1 (ping-pong lines 2q, 2q+1)
-    for (long e = threadIdx.x; e < (long)G * n; e += blockDim.x) {
-      int j = e % G, i = e / G;
+  // Thread t serves real line t % G, elements t / G + m (blockDim / G), when
+  // the block has at least as many threads as real lines; a block of more
+  // lines than threads (one lane per FFT line of a short direct form) walks a
+  // flat index instead.
+  const bool wide = G > (int)blockDim.x;
+  const int jt = wide ? 0 : threadIdx.x % G, i0 = wide ? 0 : threadIdx.x / G;
+  const int ist = wide ? 1 : blockDim.x / G;
+  const bool jv = jt < gv;
+  if (wide) {
+    for (int e = threadIdx.x; e < G * n; e += blockDim.x) {
+      const int j = e % G, i = e / G;
       T v = 0;
       if (j < gv) v = base[(long)i * dg.estride + j];
-      Line<T> ln = line_at<T>(smem, 2 * (j >> 1), Lf);
+      if (direct) {
+        Line<T> ln = line_at<T>(smem, 2 * (j >> 1), Lf);
+        ((T*)&ln[i + 1])[j & 1] = v;
+        ((T*)&ln[Lf - 1 - i])[j & 1] = -v;
+      } else {
+        line_at<T>(smem, j, Lf)[i] = {v, 0};
+      }
+    }
+    if (direct)
+      for (int q = threadIdx.x; q < GF; q += blockDim.x) {
+        Line<T> lq = line_at<T>(smem, 2 * q, Lf);
+        lq[0] = {0, 0};
+        lq[n + 1] = {0, 0};
+      }
+  } else if (direct) {
+    // real line j is component (j & 1) of FFT line j >> 1 (ping-pong lines 2q, 2q+1)
+    Line<T> ln = line_at<T>(smem, 2 * (jt >> 1), Lf);
+    const T* bp = base + (long)i0 * dg.estride + jt;
+    const long bst = (long)ist * dg.estride;
+    for (int i = i0; i < n; i += ist, bp += bst) {
+      T v = 0;
+      if (jv) v = *bp;
       T* a = (T*)&ln[i + 1];
       T* b = (T*)&ln[Lf - 1 - i];
-      a[j & 1] = v;
-      b[j & 1] = -v;
+      a[jt & 1] = v;
+      b[jt & 1] = -v;
     }
     for (int q = threadIdx.x; q < GF; q += blockDim.x) {
-      Line<T> ln = line_at<T>(smem, 2 * q, Lf);
-      ln[0] = {0, 0};
-      ln[n + 1] = {0, 0};
+      Line<T> lq = line_at<T>(smem, 2 * q, Lf);
+      lq[0] = {0, 0};
+      lq[n + 1] = {0, 0};
     }
   } else {
-    for (long e = threadIdx.x; e < (long)G * n; e += blockDim.x) {
-      int j = e % G, i = e / G;
+    Line<T> ln = line_at<T>(smem, jt, Lf);
+    const T* bp = base + (long)i0 * dg.estride + jt;
+    const long bst = (long)ist * dg.estride;
+    for (int i = i0; i < n; i += ist, bp += bst) {
       T v = 0;
-      if (j < gv) v = base[(long)i * dg.estride + j];
-      line_at<T>(smem, j, Lf)[i] = {v, 0};
+      if (jv) v = *bp;
+      ln[i] = {v, 0};
     }
   }
   __syncthreads();
@@ -895,17 +934,32 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   // every FFT line of the block ends in the same member of its ping-pong pair
   const int rsel = direct ? (res.p == buf.p ? 0 : 1) : 0;
   __syncthreads();
-  for (long e = threadIdx.x; e < (long)G * n; e += blockDim.x) {
-    int j = e % G, i = e / G;
-    if (j >= gv) continue;
-    T v;
-    if (direct) {
-      cx<T> sv = sine_pair_get(line_at<T>(smem, 2 * (j >> 1) + rsel, Lf), i + 1);
-      v = (j & 1) ? sv.y : sv.x;
-    } else {
-      v = line_at<T>(smem, j, Lf)[i].x;
+  if (wide) {
+    for (int e = threadIdx.x; e < G * n; e += blockDim.x) {
+      const int j = e % G, i = e / G;
+      if (j >= gv) continue;
+      T v;
+      if (direct) {
+        const cx<T> sv = sine_pair_get(line_at<T>(smem, 2 * (j >> 1) + rsel, Lf), i + 1);
+        v = (j & 1) ? sv.y : sv.x;
+      } else {
+        v = line_at<T>(smem, j, Lf)[i].x;
+      }
+      base[(long)i * dg.estride + j] = v;
     }
-    base[(long)i * dg.estride + j] = v;
+  } else if (jv) {
+    T* bp = base + (long)i0 * dg.estride + jt;
+    const long bst = (long)ist * dg.estride;
+    if (direct) {
+      Line<T> ln = line_at<T>(smem, 2 * (jt >> 1) + rsel, Lf);
+      for (int i = i0; i < n; i += ist, bp += bst) {
+        const cx<T> sv = sine_pair_get(ln, i + 1);
+        *bp = (jt & 1) ? sv.y : sv.x;
+      }
+    } else {
+      Line<T> ln = line_at<T>(smem, jt, Lf);
+      for (int i = i0; i < n; i += ist, bp += bst) *bp = ln[i].x;
+    }
   }
 }
 
@@ -1071,8 +1125,9 @@ template <typename T> __global__ FL_BOUNDS void k_update_b(const Prob* pbs, Iter
 template <int = 0> __global__ void k_init(Prob pb, double tol, int maxit, int use_rr) {
   init_body(pb, tol, maxit, use_rr);
 }
-template <int = 0> __global__ void k_init_b(const Prob* pbs, double tol, int maxit, int use_rr) {
-  init_body(pbs[blockIdx.y], tol, maxit, use_rr);
+// tols: per-problem tolerances (device), or NULL for tol everywhere
+template <int = 0> __global__ void k_init_b(const Prob* pbs, double tol, const double* tols, int maxit, int use_rr) {
+  init_body(pbs[blockIdx.y], tols ? tols[blockIdx.y] : tol, maxit, use_rr);
 }
 
 }  // namespace fl

@@ -201,3 +201,44 @@ def test_batched_rejects_mixed_dimensions():
     c = fl.Op(2, 1.0, 0.1, (8, 8))  # its own stream
     with pytest.raises(ValueError):
         fl.solve_batched([a, c], [_dev(np.ones((8, 8))), _dev(np.ones((8, 8)))])
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_repeat_batched_calls_allocate_nothing_and_take_per_problem_tol(mixed):
+    # A repeat of a batched call with the same problems reuses every buffer,
+    # descriptor table and captured graph (the library's device allocation
+    # count does not move), and each problem stops at its own tolerance.
+    _say("batched reuse, mixed", mixed)
+    fl = _fl()
+    s = torch.cuda.Stream()
+    ops, refs = _make(fl, PROBS_2D, s)
+    fs = [_dev(white_noise(r.n, 51 + i)) for i, r in enumerate(refs)]
+    tols = [1e-6, 1e-12, 1e-9, 1e-11]
+    opts = fl.solve_opts(pc=fl.FL_PC_FD, mixed=mixed)
+    fl.solve_batched(ops, fs, tol=tols, opts=opts)
+    a0 = fl.device_allocations()
+    us, infos = fl.solve_batched(ops, fs, tol=tols, opts=opts)
+    torch.cuda.synchronize()
+    assert fl.device_allocations() == a0
+    for i, r in enumerate(refs):
+        M = r.dense()
+        f = fs[i].cpu().numpy().ravel()
+        res = np.linalg.norm(f - M @ us[i].cpu().numpy().ravel()) / np.linalg.norm(f)
+        assert res <= tols[i] * 1.5, (i, res, tols[i])
+        assert abs(infos[i]["rel_res_true"] - res) <= 1e-3 * res + 1e-14
+    # the loosest problem needs fewer iterations than the same one at the tightest tolerance
+    _, tight = fl.solve_batched(ops, fs, tol=1e-12, opts=opts)
+    assert infos[0]["iters"] < tight[0]["iters"]
+    # repeated time-step calls with one dt set reuse their batch as well
+    u0 = [_dev(white_noise(r.n, 61 + i)) for i, r in enumerate(refs)]
+    dts = [1e-3, 2e-3, 1e-3, 5e-4]
+    fl.step_batched(ops, u0, dts, theta=0.5, nsteps=1, tol=1e-11)
+    a1 = fl.device_allocations()
+    fl.step_batched(ops, u0, dts, theta=0.5, nsteps=3, tol=1e-11)
+    torch.cuda.synchronize()
+    assert fl.device_allocations() == a1
+    # and single-problem solves of a built op allocate nothing after the first
+    ops[0].solve(fs[0], tol=1e-10, opts=opts)
+    a2 = fl.device_allocations()
+    ops[0].solve(fs[0], tol=1e-10, opts=opts)
+    assert fl.device_allocations() == a2

@@ -323,3 +323,20 @@ def test_solve_after_batched_apply_reuses_no_stale_graph(mixed):
     assert i2["iters"] == i3["iters"]
     assert torch.equal(u2, u3)
     assert torch.equal(u1, u2)
+
+
+def test_autotuned_plans_are_cached_per_shape():
+    # the second op of a shape takes the recorded plans without timing again
+    import time
+    fl = _fl()
+    n = (1024, 1024)
+    t0 = time.perf_counter()
+    a = fl.Op(2, 1.0, 2.0 / 1025, n)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    b = fl.Op(2, 1.5, 2.0 / 1025, n)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    _say("make_weights first", (t1 - t0) * 1e3, "ms, cached", (t2 - t1) * 1e3, "ms")
+    assert a.plan() == b.plan()
+    assert (t2 - t1) * 1e3 <= 40.0
