@@ -145,6 +145,21 @@ fl_status fl_op_export(fl_op op, int which, void* dst);
 fl_status fl_apply(fl_op op, const void* u, void* Mu, int dtype, int64_t batch, const uint8_t* mask,
                    double shift0, double shift1);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as fl_apply, with the complex work arrays in a fixed device array of
+ * 64 MiB that the library holds on each device (not in the op's workspace),
+ * and no allocation of any kind.  The scratch must hold the half spectrum of
+ * the last axis, rows x (P_d/2+1) complex values of dtype, plus in 3D batch x
+ * n_1 x P_2 x (P_3/2+1) complex values (e.g. a 1024 x 1024 FP64 grid needs
+ * 16.8 MB, 128^3 FP32 51 MB); larger requests return FL_E_INVALID before any
+ * work is enqueued.  Every call on a device shares that array: calls that
+ * overlap in time on one device (other streams, other ops, other host
+ * threads) race and must be serialised by the caller.  Arguments, layout and
+ * stream ordering as fl_apply; call it with the op's device current. */
+fl_status fl_apply_noalloc(fl_op op, const void* u, void* Mu, int dtype, int64_t batch, const uint8_t* mask,
+                           double shift0, double shift1);
+
 /* z = (p0 I + p1 C h^d L)^{-1} r, sine transforms along every axis.  p0 = 0,
  * p1 = 1 is the elliptic preconditioner; p0 = 1, p1 = theta dt the time-step
  * one.  Paper Sec. 3.1 ("Preconditioning") and Sec. 3.2.

@@ -19,7 +19,7 @@ FL_PC_NONE, FL_PC_FD, FL_PC_LEARNED, FL_PC_SPECTRAL, FL_PC_MTILDE, FL_PC_FD_BOX,
 STATUS_NAMES = {0: "ok", -1: "invalid", -2: "nomem", -3: "hip", -4: "noconv", -5: "breakdown", -6: "unsupported"}
 
 EXPORTED = ["fl_make_weights", "fl_op_constants", "fl_op_padded", "fl_op_plan", "fl_op_export", "fl_apply", "fl_precond",
-            "fl_precond_spectral", "fl_precond_any", "fl_solve", "fl_step", "fl_solve_batched", "fl_step_batched", "fl_profile_pass", "fl_op_destroy",
+            "fl_precond_spectral", "fl_precond_any", "fl_apply_noalloc", "fl_solve", "fl_step", "fl_solve_batched", "fl_step_batched", "fl_profile_pass", "fl_op_destroy",
             "fl_last_error", "fl_device_allocations", "fl_net_create", "fl_net_nparams", "fl_net_set_params", "fl_net_get_params",
             "fl_net_forward", "fl_net_grad", "fl_net_train", "fl_learned_pairs", "fl_net_profile", "fl_net_destroy"]
 
@@ -72,6 +72,7 @@ def load(path=LIB_PATH):
         "fl_precond": [P, P, P, I, I64, P, D, D],
         "fl_precond_spectral": [P, P, P, I, I64, P, D, D],
         "fl_precond_any": [P, I, P, P, I, I64, P, D, D],
+        "fl_apply_noalloc": [P, P, P, I, I64, P, D, D],
         "fl_solve": [P, P, P, D, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(Info)],
         "fl_step": [P, P, D, D, P, P, P, D, ctypes.POINTER(SolveOpts), ctypes.POINTER(Info)],
         "fl_solve_batched": [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(D),
@@ -229,6 +230,17 @@ class Op:
         out = torch.empty_like(u) if out is None else _need(out, u.dtype, u.numel(), "out")
         self._enter()
         _check(load().fl_apply(self._h, _ptr(u), _ptr(out), dt, self._batch(u), _ptr(mask), shift0, shift1))
+        self._leave()
+        return out
+
+    def apply_noalloc(self, u, out, mask=None, shift0=0.0, shift1=1.0):
+        """As apply, through fl_apply_noalloc (no device allocation; `out` must be given)."""
+        dt = FL_F64 if u.dtype == torch.float64 else FL_F32
+        _need(u, u.dtype, name="u")
+        _need(out, u.dtype, u.numel(), "out")
+        _need(mask, torch.uint8, self.N, "mask")
+        self._enter()
+        _check(load().fl_apply_noalloc(self._h, _ptr(u), _ptr(out), dt, self._batch(u), _ptr(mask), shift0, shift1))
         self._leave()
         return out
 

@@ -811,6 +811,70 @@ template <typename T> static fl_status profile_t(fl_op op, int pass, int reps, d
   return FL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free application: the complex work arrays of one
+// call (W1, then W2 in 3D at the next 256-byte boundary) live in this
+// file-scope device array.  Each device holds its own copy until the process
+// ends; every call on a device shares it (calls that overlap on one device
+// race), and nothing in it needs to start at zero (every element a pass reads
+// was written by the pass before it in the same call).
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[64] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device; the host-side name is not a device address).
+static fl_status scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(FL_E_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(FL_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return FL_OK;
+}
+
+// Bytes of W1 (and W2) one application of `batch` inputs needs.
+template <typename T> static size_t apply_scratch_bytes(fl_op op, long batch, size_t* w2_off) {
+  if (op->d == 1) {
+    *w2_off = 0;
+    return 0;
+  }
+  const size_t w1 = (size_t)rows_of(op, batch) * op->H[op->d - 1] * sizeof(cx<T>);
+  *w2_off = (w1 + 255) / 256 * 256;
+  if (op->d < 3) return w1;
+  return *w2_off + (size_t)batch * op->n[0] * op->P[1] * op->H[2] * sizeof(cx<T>);
+}
+
+template <typename T>
+static fl_status apply_noalloc_t(fl_op op, const void* u, void* Mu, long batch, const uint8_t* mask, double s0,
+                                 double s1) {
+  size_t off = 0;
+  const size_t need = apply_scratch_bytes<T>(op, batch, &off);
+  if (need > kScratchBytes)
+    return fail(FL_E_INVALID, "fl_apply_noalloc: this grid and batch need " + std::to_string(need) +
+                                  " bytes of scratch; the maximum is " + std::to_string(kScratchBytes));
+  void* base = nullptr;
+  STCHK(scratch_address(&base));
+  Prob pb = base_prob<T>(op, batch);
+  pb.s0 = s0;
+  pb.s1 = s1;
+  pb.in = u;
+  pb.out = Mu;
+  pb.W1 = base;
+  pb.W2 = op->d == 3 ? (void*)((unsigned char*)base + off) : nullptr;
+  pb.mask = mask;
+  return apply_seq<T, PRO_PLAIN, EPI_PLAIN>(op, pb, Iter{0, 0}, 0);
+}
+
 extern "C" {
 
 fl_status fl_make_weights(int d, double alpha, double h, const int64_t* n, const fl_weights_opts* o,
@@ -866,6 +930,15 @@ fl_status fl_apply(fl_op op, const void* u, void* Mu, int dtype, int64_t batch, 
   if (batch < 1) return fail(FL_E_INVALID, "batch must be >= 1");
   if (dtype == FL_F64) return apply_t<double>(op, u, Mu, batch, mask, shift0, shift1);
   if (dtype == FL_F32) return apply_t<float>(op, u, Mu, batch, mask, shift0, shift1);
+  return fail(FL_E_INVALID, "dtype must be FL_F64 or FL_F32");
+}
+
+fl_status fl_apply_noalloc(fl_op op, const void* u, void* Mu, int dtype, int64_t batch, const uint8_t* mask,
+                           double shift0, double shift1) {
+  if (!op || !u || !Mu) return fail(FL_E_INVALID, "NULL argument");
+  if (batch < 1) return fail(FL_E_INVALID, "batch must be >= 1");
+  if (dtype == FL_F64) return apply_noalloc_t<double>(op, u, Mu, batch, mask, shift0, shift1);
+  if (dtype == FL_F32) return apply_noalloc_t<float>(op, u, Mu, batch, mask, shift0, shift1);
   return fail(FL_E_INVALID, "dtype must be FL_F64 or FL_F32");
 }
 
