@@ -448,11 +448,19 @@ __device__ __forceinline__ void cstage_split(Line<T> buf, Line<T> aux, const cx<
     sn[m] = -w.y;
   }
   __syncthreads();
-  for (int t = lane; t < NB * NG; t += TPL) {
-    const int j = t / NG, gi = t % NG;
-    const int k = j % NS;
-    const int base = (j / NS) * NS * R + k;
-    split_dispatch<T, R, NS, KG, INV, 0, NG>(gi, aux, buf, j, base, cs, sn);
+  // Phase B takes the output groups one after another, each over the
+  // butterflies padded to whole wavefronts (NBP), so that the group index --
+  // and with it the code path -- is the same for every lane of a wavefront
+  // (lanes of one wavefront are consecutive lanes of one line, or whole
+  // lines at the same offsets when TPL < 64).
+  constexpr int NBP = (NB + 63) / 64 * 64;
+  for (int t = lane; t < NG * NBP; t += TPL) {
+    const int gi = t / NBP, j = t % NBP;
+    if (j < NB) {
+      const int k = j % NS;
+      const int base = (j / NS) * NS * R + k;
+      split_dispatch<T, R, NS, KG, INV, 0, NG>(gi, aux, buf, j, base, cs, sn);
+    }
   }
   __syncthreads();
 }
