@@ -23,17 +23,22 @@ batch 16 (the length that needed the fewest iterations on held-out 1024^2
 right-hand sides at alpha = 0.5, 1.0, 1.5, among 1500 to 6000).  `value` is the time of
 learned_f32; the plain-FP64 baseline is the faster of fp64_pcg and fp64_cg.
 
-Reported beside it (not part of `value`): per-pass timings; the roofline of
-the level-0 network convolution, which the learned solve runs once per inner
-iteration (`roofline`), and of the slowest other pass timed, the FP32 sine
-column pass at 1024^2, which runs as often at about the same duration
-(`roofline_next`); the batched workloads (16 x 256^3 right-hand sides,
-32 uneven 2D backward-Euler problems x 200 steps); the learned preconditioner
-in 3D (trained at 32^3, evaluated at 128^3, alpha = 1.5); the oracle's FP64
-PCG timed on the host for a bounded sample.
+Reported beside it (not part of `value`): per-pass timings of the 1024^2
+application and preconditioner and of every pass at 256^3 (`passes_3d`);
+`roofline`, the kernel with the largest time per solve among those the timed
+solver launches once per inner iteration (FP32 FFT and sine passes, network
+layers), with its HBM traffic from a committed rocprofv3 counter summary when
+one exists, and `roofline_next`, the runner-up; `learned_vs_spectral`, the
+timed solver against the same refinement loop with the sine-basis diagonal
+alone; the batched workloads (16 x 256^3 right-hand sides, 32 uneven 2D
+backward-Euler problems x 200 steps, each with the FD preconditioner and the
+sine-basis diagonal); the learned preconditioner in 3D (trained at 32^3,
+evaluated at 128^3, alpha = 1.5, and at 256^3, alpha = 1.2, against FP64 PCG);
+the oracle's FP64 PCG timed on the host for a bounded number of its
+iterations, and the paper's method with scipy.fft solved in full.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--alpha A] [--no-cpu]
-                       [--no-batched] [--no-learned-3d]
+                       [--no-batched] [--no-learned-3d] [--passes-3d N] [--only a,b]
 """
 import argparse
 import json
@@ -321,23 +326,29 @@ def batched_workloads(fl, torch, args):
     ops = [fl.Op(2, p["alpha"], p["h"], (p["n"], p["n"]), stream=s) for p in probs]
     torch.cuda.synchronize()
     t_make = time.perf_counter() - t0
-    opts = fl.solve_opts(pc=fl.FL_PC_SPECTRAL)
-    us = [torch.from_numpy(p["u0"]).cuda() for p in probs]
-    fl.step_batched(ops, [u.clone() for u in us], [1e-3] * 32, theta=1.0, nsteps=2, tol=1e-10, opts=opts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, infos = fl.step_batched(ops, us, [1e-3] * 32, theta=1.0, nsteps=args.uneven_steps, tol=1e-10, opts=opts)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
     unk = sum(p["n"] ** 2 for p in probs)
+    res = {}
+    for name, pc in (("spectral", fl.FL_PC_SPECTRAL), ("fd", fl.FL_PC_FD)):
+        opts = fl.solve_opts(pc=pc)
+        us = [torch.from_numpy(p["u0"]).cuda() for p in probs]
+        # the first call builds the batch (and the diagonal tables); the timed
+        # call with the same problems and dt reuses it
+        fl.step_batched(ops, [u.clone() for u in us], [1e-3] * 32, theta=1.0, nsteps=2, tol=1e-10, opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, infos = fl.step_batched(ops, us, [1e-3] * 32, theta=1.0, nsteps=args.uneven_steps, tol=1e-10,
+                                   opts=opts)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        res[name] = {"ms_total": round(ms, 1), "ms_per_step": round(ms / args.uneven_steps, 3),
+                     "unknown_steps_per_s": round(unk * args.uneven_steps / (ms * 1e-3), 1),
+                     "iters_per_step_mean": round(sum(i["iters"] for i in infos) / (32 * args.uneven_steps), 2),
+                     "max_rel_res_true": max(i["rel_res_true"] for i in infos)}
+        log(f"[bench] uneven 2D {name}: {args.uneven_steps} steps of 32 uneven problems in {ms:.1f} ms "
+            f"({ms / args.uneven_steps:.2f} ms/step), mean iters/step {res[name]['iters_per_step_mean']}, "
+            f"max true res {res[name]['max_rel_res_true']:.1e}")
     out["uneven_2d_steps"] = {"workload": "32 uneven 2D backward-Euler problems, n in {128,256,384,512}, dt=1e-3",
-                 "steps": args.uneven_steps, "ms_total": round(ms, 1), "ms_per_step": round(ms / args.uneven_steps, 3),
-                 "unknown_steps_per_s": round(unk * args.uneven_steps / (ms * 1e-3), 1),
-                 "iters_per_step_mean": round(sum(i["iters"] for i in infos) / (32 * args.uneven_steps), 2),
-                 "max_rel_res_true": max(i["rel_res_true"] for i in infos), "make_weights_s": round(t_make, 2),
-                 "preconditioner": "sine-basis diagonal"}
-    log(f"[bench] uneven 2D: {args.uneven_steps} steps of 32 uneven problems in {ms:.1f} ms ({ms / args.uneven_steps:.2f} ms/step), "
-        f"mean iters/step {out['uneven_2d_steps']['iters_per_step_mean']}, max true res {out['uneven_2d_steps']['max_rel_res_true']:.1e}")
+                              "steps": args.uneven_steps, "make_weights_s": round(t_make, 2), **res}
     for o in ops:
         o.close()
     del ops, us

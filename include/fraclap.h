@@ -80,7 +80,7 @@ typedef struct {
                            extension of length 2(n+1) when it factors over radices <= 43, else chirp-z;
                            2 = chirp-z with a 5-smooth length >= 2n-1 */
   int col_lanes;        /* symbol column pass at lengths 1024 and 2048: 0 = autotune, -1 = run-time plan,
-                           64 or 128 = lanes per column of the specialised kernel */
+                           64, 128 or 256 (length 2048) = lanes per column of the specialised kernel */
   int sine_col_lanes;   /* sine column pass at direct length 2050: 0 = autotune, -1 = plan, 128 = forced */
   int reserved[3];
 } fl_weights_opts;

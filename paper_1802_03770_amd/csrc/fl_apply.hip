@@ -10,11 +10,11 @@ template <typename T> static fl_status launch_col_conv(const Prob& pc, const Col
                                                         hipStream_t s) {
   const Axis& A = pc.ax[cg.axis];
   int lf = 0, tplf = 0;
-  if (A.fft.fixed && (A.P == 2048 || A.P == 1024) && (A.col_tplf == 64 || A.col_tplf == 128)) {
+  if (A.fft.fixed && (A.P == 2048 || A.P == 1024) && (A.col_tplf == 64 || A.col_tplf == 128 || A.col_tplf == 256)) {
     lf = A.P;
     tplf = A.col_tplf;
-    // FP64 at 2048 with 64 lanes would need 4 x 37 KB of LDS: keep 128
-    if (lf == 2048 && sizeof(T) == 8) tplf = 128;
+    // FP64 at 2048 with 64 lanes would need 4 x 37 KB of LDS: keep 128 or more
+    if (lf == 2048 && sizeof(T) == 8 && tplf == 64) tplf = 128;
     if (lf == 1024) tplf = 64;
   } else if (fft_lf(A) == 512 || fft_lf(A) == 256) {
     lf = A.P;  // the plan's lanes, compile-time
@@ -26,7 +26,9 @@ template <typename T> static fl_status launch_col_conv(const Prob& pc, const Col
   const int nt = block_for(tpl), G = nt / tpl;
   const long grid = cg.ngroup * ((cg.gs + G - 1) / G);
   const size_t sm = (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>);
-  if (lf == 2048 && tplf == 64)
+  if (lf == 2048 && tplf == 256)
+    LAUNCH((k_colpass<T, COL_CONV, 2048, 256>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
+  else if (lf == 2048 && tplf == 64)
     LAUNCH((k_colpass<T, COL_CONV, 2048, 64>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
   else if (lf == 2048)
     LAUNCH((k_colpass<T, COL_CONV, 2048, 128>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);

@@ -210,11 +210,11 @@ template <typename T> static fl_status autotune_col(fl_op op) {
     A.col_tplf = op->col_lanes > 0 ? op->col_lanes : 0;
     return FL_OK;
   }
-  const int opts[3] = {0, 64, 128};
+  const int opts[4] = {0, 64, 128, 256};
   double best = 1e30;
   int pick = 0;
   for (int o : opts) {
-    if (o == 128 && (A.P == 1024)) continue;
+    if ((o == 128 || o == 256) && (A.P == 1024)) continue;
     if (o == 64 && A.P == 2048 && sizeof(T) == 8) continue;
     A.col_tplf = o;
     double ms = 0.0;
@@ -325,7 +325,8 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
     memset(&op->ax[1][a], 0, sizeof(Axis));
   }
   op->dst_mode = (o && o->dst_mode >= 0 && o->dst_mode <= 2) ? o->dst_mode : 0;
-  op->col_lanes = (o && (o->col_lanes == -1 || o->col_lanes == 64 || o->col_lanes == 128)) ? o->col_lanes : 0;
+  op->col_lanes =
+      (o && (o->col_lanes == -1 || o->col_lanes == 64 || o->col_lanes == 128 || o->col_lanes == 256)) ? o->col_lanes : 0;
   op->sine_col_lanes = (o && (o->sine_col_lanes == -1 || o->sine_col_lanes == 128)) ? o->sine_col_lanes : 0;
   for (int a = 0; a < d; ++a) {
     if ((st = build_axis<double>(op, a, op->dst_mode == 2 ? 2 : 1)) != FL_OK) return bail(st);

@@ -277,7 +277,7 @@ def test_full_size_apply_sampled():
         assert abs(got[p] - wv) <= 1e-12 * scale, (p, got[p], wv)
 
 
-@pytest.mark.parametrize("n,lanes", [(512, -1), (512, 64), (1024, -1), (1024, 64), (1024, 128)])
+@pytest.mark.parametrize("n,lanes", [(512, -1), (512, 64), (1024, -1), (1024, 64), (1024, 128), (1024, 256)])
 def test_apply_specialised_column_pass(n, lanes):
     # the symbol column pass at lengths 1024 and 2048 in each of the forms the
     # autotuner chooses from; sampled outputs against the oracle's direct sums
