@@ -62,24 +62,27 @@ def test_table_1d_cg_iterations(row):
         assert abs(g - p) <= max(2, 0.03 * p), (got, (p6, c6, p9, c9))
 
 
-@pytest.mark.parametrize("d", [1, 2])
+@pytest.mark.parametrize("d", [1, 2, 3])
 @pytest.mark.parametrize("alpha", [0.5, 1.0, 1.5])
 def test_gaussian_closed_form_convergence(d, alpha):
     # (-Delta)^{alpha/2} e^{-|x|^2} = 2^alpha Gamma((d+alpha)/2)/Gamma(d/2) 1F1((d+alpha)/2; d/2; -|x|^2)
-    # on (-6, 6)^d; Theorem 1 gives order >= 2 (observed ~ 4 - alpha).
+    # on (-6, 6)^d; Theorem 1 gives order >= 2 (observed ~ 4 - alpha in every d).
+    # 3D takes the oracle's FFT form of the application (itself pinned to the
+    # dense sums on small grids).
     errs = []
-    sizes = (63, 127, 255) if d == 1 else (31, 63, 127)
+    sizes = {1: (63, 127, 255), 2: (31, 63, 127), 3: (15, 31, 63)}[d]
     for n in sizes:
         x, h = O.grid_points(n, -6.0, 6.0)
         g = np.meshgrid(*([x] * d), indexing="ij")
         r2 = sum(v * v for v in g)
         op = O.Operator(d, alpha, h, (n,) * d)
-        Mu = op.apply(np.exp(-r2), method="dense" if d == 1 else "dft")
+        Mu = op.apply(np.exp(-r2), method={1: "dense", 2: "dft", 3: "fft"}[d])
         ex = 2**alpha * math.gamma((d + alpha) / 2) / math.gamma(d / 2) * special.hyp1f1((d + alpha) / 2, d / 2, -r2)
         errs.append(np.abs(Mu - ex).max() / np.abs(ex).max())
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert min(rates) >= 2.0, (errs, rates)
-    assert errs[-1] < 2e-3
+    # the finest 3D grid is h = 12/64, twice the 2D spacing
+    assert errs[-1] < (2e-3 if d < 3 else 6e-3)
 
 
 @pytest.mark.parametrize("n", [(7,), (6, 5), (4, 3, 5)])
