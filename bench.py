@@ -118,10 +118,12 @@ def main():
         t_train = time.perf_counter() - t0
         l0 = float(np.mean(losses[:50]))
         l1 = float(np.mean(losses[-50:]))
+        ms_step = t_train * 1e3 / max(1, len(losses))
         log(f"[bench] learned: {R.shape[0]} pairs at 256^2 in {t_pairs:.1f} s, {len(losses)} Adam steps "
-            f"(batch {args.train_batch}) in {t_train:.1f} s, loss {l0:.3e} -> {l1:.3e}")
+            f"(batch {args.train_batch}) in {t_train:.1f} s ({ms_step:.2f} ms/step), loss {l0:.3e} -> {l1:.3e}")
         train_info = {"pairs": int(R.shape[0]), "grid": 256, "pairs_s": round(t_pairs, 2), "steps": len(losses),
-                      "batch": args.train_batch, "train_s": round(t_train, 2), "loss_first": l0, "loss_last": l1}
+                      "batch": args.train_batch, "train_s": round(t_train, 2), "ms_per_adam_step": round(ms_step, 3),
+                      "loss_first": l0, "loss_last": l1}
         del R, T, A
 
     configs = {
@@ -404,11 +406,13 @@ def learned_3d_workload(fl, torch, args):
     t_train = time.perf_counter() - t0
     l0, l1 = float(np.mean(losses[:20])), float(np.mean(losses[-20:]))
     log(f"[bench] learned 3d: {R.shape[0]} pairs at {args.train3d_n}^3 in {t_pairs:.1f} s, {len(losses)} Adam steps "
-        f"(batch 4) in {t_train:.1f} s, loss {l0:.3e} -> {l1:.3e}")
+        f"(batch 4) in {t_train:.1f} s ({t_train * 1e3 / max(1, len(losses)):.2f} ms/step), "
+        f"loss {l0:.3e} -> {l1:.3e}")
     out = {"workload": "evaluated at 128^3 alpha=1.5 (16 bumps seed 5500) and 256^3 alpha=1.2 (the first of "
                        "the 16 right-hand sides at 256^3)",
            "training": {"pairs": int(R.shape[0]), "grid": args.train3d_n, "pairs_s": round(t_pairs, 2),
-                        "steps": len(losses), "batch": 4, "train_s": round(t_train, 2), "loss_first": l0,
+                        "steps": len(losses), "batch": 4, "train_s": round(t_train, 2),
+                        "ms_per_adam_step": round(t_train * 1e3 / max(1, len(losses)), 3), "loss_first": l0,
                         "loss_last": l1}}
     del R, T, A
     from workloads import workload_rhs_256cubed

@@ -540,47 +540,137 @@ __device__ __forceinline__ void stage_grad(u16* gt, const Stage& sg, const Dims&
   }
 }
 
-// Weight gradient of a 32 -> 32 layer: per-block partials of
-// dW[tap][ci][co] = sum_p X[p + tap][ci] G[p][co] and db[co] = sum_p G[p][co]
-// (X staged by SMI, G by SMG), FP32 accumulation; blocks stride over tiles.
-// blockIdx.y = kz: the block accumulates the nine taps of input slice
-// z + kz - 1 (3D) into rows kz*288 .. of its partial (stride L32SZ).
+// Weight gradient of a 32 -> 32 layer on MFMA: per-block partials of
+// dW[tap][ci][co] = sum_p X[p + off(tap)][ci] G[p][co] and db[co] = sum_p G[p][co]
+// (X staged by SMI, G by SMG), an implicit GEMM with the pixels as the
+// contraction: for each tap C[ci][co] += A[ci][k] B[k][co], A = X and B = G
+// over 16 consecutive pixels of one row per v_mfma_f32_32x32x16_bf16, FP32
+// accumulation.  Both operands are staged channel-first (one plane of BF16
+// pixels per channel) so that a lane's 8 consecutive pixels of one channel
+// are one 16-byte read; the tap's column offset kx of X is taken from the
+// aligned read and the dword after it (a 2-byte shift for kx = 1).  Wave w
+// takes output row w of the 4 x 64 tile for all nine in-plane taps; blocks
+// stride over tiles; the waves' sums meet in LDS at the end.  blockIdx.y = kz:
+// input slice z + kz - 1 (3D), rows kz*288 .. of the partial (stride L32SZ).
+constexpr int WXR = 72;               // X plane row: columns x0-1 .. x0+64, padded
+constexpr int WXP = SY * WXR + 8;     // X plane (channel) stride, BF16 elements
+constexpr int WGP = TY * TX + 8;      // G plane stride
+__device__ __forceinline__ bf16x8 frag_shift(const uint4 a, unsigned nxt, int kx) {
+  uint4 r;
+  if (kx == 0) {
+    r = a;
+  } else if (kx == 2) {
+    r = make_uint4(a.y, a.z, a.w, nxt);
+  } else {  // 2-byte shift: word j = (w[j] >> 16) | (w[j+1] << 16)
+    r = make_uint4(__builtin_amdgcn_alignbit(a.y, a.x, 16), __builtin_amdgcn_alignbit(a.z, a.y, 16),
+                   __builtin_amdgcn_alignbit(a.w, a.z, 16), __builtin_amdgcn_alignbit(nxt, a.w, 16));
+  }
+  return __builtin_bit_cast(bf16x8, r);
+}
+
 template <int SMI, int SMG, int KD>
-__global__ __launch_bounds__(256) void k_conv32_wgrad(Stage si, Stage sg, float* __restrict__ part, Dims g) {
-  __shared__ __align__(16) u16 xt[SY * SX * CP];
-  __shared__ __align__(16) u16 gt[TY * TX * CP];
-  const int co = threadIdx.x & 31, grp = threadIdx.x >> 5;  // 8 groups of 36 (tap, ci)
+__global__ __launch_bounds__(256, 2) void k_conv32_wgrad(Stage si, Stage sg, float* __restrict__ part, Dims g) {
+  __shared__ __align__(16) u16 lds[CH * WXP + CH * WGP];
+  __shared__ float bsum[8][CH];
+  u16* const xs = lds;             // X planes
+  u16* const gs = lds + CH * WXP;  // G planes
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kz = blockIdx.y;
   const long ntiles = (long)g.B * g.D * ((g.H + TY - 1) / TY) * ((g.W + TX - 1) / TX);
-  float acc[36];
+  f32x16 acc[9];
 #pragma unroll
-  for (int j = 0; j < 36; ++j) acc[j] = 0.f;
+  for (int t = 0; t < 9; ++t) acc[t] = f32x16{};
   float accb = 0.f;
   for (long t = blockIdx.x; t < ntiles; t += gridDim.x) {
     int b, z, y0, x0;
     tile_of(t, g, b, z, y0, x0);
-    stage_tile<SMI, KD>(xt, si, g, b, z + kz - (KD == 3 ? 1 : 0), y0, x0);
-    stage_grad<SMG, KD>(gt, sg, g, b, z, y0, x0);
-    __syncthreads();
-    for (int p = 0; p < TY * TX; ++p) {
-      const int ly = p / TX, lx = p % TX;
-      const float gv = bf2f(gt[p * CP + co]);
-      accb += gv;
+    const int zi = z + kz - (KD == 3 ? 1 : 0);
+    const bool zin = zi >= 0 && zi < g.D;  // uniform over the block
+    __syncthreads();                        // the previous tile's planes are read
+    // X: rows y0-1 .. y0+TY, columns x0-1 .. x0+TX (66), four 8-channel chunks
+    if (zin)
+      for (int e = threadIdx.x; e < SY * 4 * (TX + 2); e += blockDim.x) {
+        const int c = e % (TX + 2), rq = e / (TX + 2), q = rq & 3, r = rq >> 2;
+        const int yy = y0 + r - 1, xx = x0 + c - 1;
+        float v[8];
+        if (yy >= 0 && yy < g.H && xx >= 0 && xx < g.W) {
+          stage8<SMI, KD>(si, g, b, zi, yy, xx, q * 8, v);
+        } else {
 #pragma unroll
-      for (int j = 0; j < 36; ++j) {
-        const int q = grp * 36 + j, tap = q >> 5, ci = q & 31;
-        acc[j] += bf2f(xt[((ly + tap / 3) * SX + lx + tap % 3) * CP + ci]) * gv;
+          for (int i = 0; i < 8; ++i) v[i] = 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xs[(q * 8 + i) * WXP + r * WXR + c] = f2bf(v[i]);
       }
+    // G: rows y0 .. y0+TY-1, columns x0 .. x0+TX-1
+    for (int e = threadIdx.x; e < TY * 4 * TX; e += blockDim.x) {
+      const int c = e % TX, rq = e / TX, q = rq & 3, r = rq >> 2;
+      const int yy = y0 + r, xx = x0 + c;
+      float v[8];
+      if (yy < g.H && xx < g.W) {
+        stage8<SMG, KD>(sg, g, b, z, yy, xx, q * 8, v);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) gs[(q * 8 + i) * WGP + r * TX + c] = f2bf(v[i]);
+    }
+    __syncthreads();
+    if (kz == 0) {  // bias: thread (co, part) sums 32 pixels of plane co
+      const u16* gp = gs + (threadIdx.x & 31) * WGP + (threadIdx.x >> 5) * 32;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float v[8];
+        ld8(gp + 8 * j, v);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) accb += v[i];
+      }
+    }
+    if (!zin) continue;
+    const int ch = lane & 31, ko = (lane >> 5) * 8;
+#pragma unroll
+    for (int j = 0; j < TX / 16; ++j) {
+      const bf16x8 bg = *(const bf16x8*)(gs + ch * WGP + wave * TX + 16 * j + ko);
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky) {
+        const u16* xp = xs + ch * WXP + (wave + ky) * WXR + 16 * j + ko;
+        const uint4 a = *(const uint4*)xp;
+        const unsigned nxt = *(const unsigned*)(xp + 8);
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx)
+          acc[ky * 3 + kx] =
+              __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag_shift(a, nxt, kx), bg, acc[ky * 3 + kx], 0, 0, 0);
+      }
+    }
+  }
+  // sum of the four waves in LDS (the planes are free after this barrier)
+  __syncthreads();
+  float* red = (float*)lds;  // [9 * 32][32] floats
+  static_assert(sizeof(float) * 9 * CH * CH <= sizeof(u16) * CH * (WXP + WGP), "wave reduction fits the planes");
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int ci = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3), co = lane & 31;
+          float* d = red + (t * CH + ci) * CH + co;
+          *d = (w == 0 ? 0.f : *d) + acc[t][v];
+        }
     }
     __syncthreads();
   }
+  if (kz == 0) bsum[threadIdx.x >> 5][threadIdx.x & 31] = accb;
+  __syncthreads();
   float* o = part + (long)blockIdx.x * PL<KD>::L32SZ;
+  for (int i = threadIdx.x; i < 9 * CH * CH; i += blockDim.x) o[(long)kz * 9 * CH * CH + i] = red[i];
+  if (kz == 0 && threadIdx.x < CH) {
+    float sb = 0.f;
 #pragma unroll
-  for (int j = 0; j < 36; ++j) {
-    const int q = grp * 36 + j;
-    o[((long)kz * 288 + q) * CH + co] = acc[j];
+    for (int k = 0; k < 8; ++k) sb += bsum[k][threadIdx.x];
+    o[PL<KD>::L32W + threadIdx.x] = sb;
   }
-  if (kz == 0 && grp == 0) o[PL<KD>::L32W + co] = accb;
 }
 
 // ---------------------------------------------------------------------------
@@ -720,6 +810,16 @@ __global__ void k_reduce_part(const float* __restrict__ part, int nblk, int stri
   for (int k = 0; k < nblk; ++k) s += part[(long)k * stride + i];
   dst[i] = s;
 }
+// First stage of a two-stage sum over many blocks: column y of the grid sums
+// blocks y, y + S, y + 2 S, ... (S = gridDim.y, fixed order) into tmp[y][i].
+__global__ void k_reduce_part_s1(const float* __restrict__ part, int nblk, int stride, int nval,
+                                 float* __restrict__ tmp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nval) return;
+  float s = 0.f;
+  for (int k = blockIdx.y; k < nblk; k += gridDim.y) s += part[(long)k * stride + i];
+  tmp[(long)blockIdx.y * nval + i] = s;
+}
 
 // Packed bf16 weights of the 32 -> 32 layers.  Forward (A operand = W^T):
 // fw[L][tap][half][lane][e] = W_L[tap][half*16 + 8*(lane/32) + e][lane%32].
@@ -770,11 +870,18 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const
   if (threadIdx.x == 0) part[blockIdx.x] = red[0] * inv;
 }
 
-__global__ void k_sum_to(const double* __restrict__ part, int n, float* __restrict__ dst) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// sum of n partials (one block of 256 threads: strided sums, then a fixed tree)
+__global__ __launch_bounds__(256) void k_sum_to(const double* __restrict__ part, int n, float* __restrict__ dst) {
+  __shared__ double red[256];
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += part[i];
-  *dst = (float)s;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *dst = (float)red[0];
 }
 
 // Adam (Kingma and Ba 2015): c1 = 1/(1 - b1^k), c2 = 1/(1 - b2^k)
@@ -1087,12 +1194,22 @@ template <int KD> static fl_status net_backward_t(fl_net net, const float* x, co
   u16** gr = net->grd;
   const float* th = net->th;
   auto bw = [&](int L) { return (const u16*)(net->bw + L * P::PACK); };
-  const int maxblk = 1024;
-  STCHK(net_part(net, (long)maxblk * P::L32SZ));
+  const int maxblk = 1024, nsplit = 32;
+  // per-block partials, then the nsplit partial sums of the two-stage reduction
+  STCHK(net_part(net, (long)(maxblk + nsplit) * P::L32SZ));
   auto wgrad_blocks = [&](const Dims& g) { return std::min(maxblk, conv_blocks(g)); };
   auto reduce = [&](int nblk, long stride, long nval, long off) -> fl_status {
-    LAUNCH(k_reduce_part, dim3((unsigned)((nval + 255) / 256)), dim3(256), 0, s, (const float*)net->part, nblk,
-           (int)stride, (int)nval, net->g + off);
+    const unsigned gx = (unsigned)((nval + 255) / 256);
+    if (nblk <= 2 * nsplit) {
+      LAUNCH(k_reduce_part, dim3(gx), dim3(256), 0, s, (const float*)net->part, nblk, (int)stride, (int)nval,
+             net->g + off);
+      return FL_OK;
+    }
+    float* tmp = net->part + (long)maxblk * P::L32SZ;
+    LAUNCH(k_reduce_part_s1, dim3(gx, nsplit), dim3(256), 0, s, (const float*)net->part, nblk, (int)stride,
+           (int)nval, tmp);
+    LAUNCH(k_reduce_part, dim3(gx), dim3(256), 0, s, (const float*)tmp, nsplit, (int)nval, (int)nval,
+           net->g + off);
     return FL_OK;
   };
   // output layer
@@ -1486,7 +1603,7 @@ fl_status fl_net_train(fl_net net, const float* R, const float* T, const float* 
     STCHK(net_forward(net, net->xb, net->ab, batch, D, H, W));
     LAUNCH(k_loss, dim3(lblk), dim3(256), 0, s, (const float*)net->y, (const float*)net->tb, net->gy, net->lpart, n,
            1.0 / (double)n);
-    LAUNCH(k_sum_to, dim3(1), dim3(1), 0, s, (const double*)net->lpart, lblk, net->losses + k);
+    LAUNCH(k_sum_to, dim3(1), dim3(256), 0, s, (const double*)net->lpart, lblk, net->losses + k);
     STCHK(net_backward(net, net->xb, net->ab, batch, D, H, W));
     ++net->step;
     const double c1 = 1.0 / (1.0 - std::pow((double)b1, net->step));
