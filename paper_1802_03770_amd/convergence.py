@@ -16,14 +16,16 @@ Crank-Nicolson steps (eq. timestepping) with dt = 1/(n + 1) (so that T / dt
 is an integer), f = 0 and u_0(x) = prod_i (1 + cos(2 pi nu_i x_i - pi))^2 / 4,
 nu = (3, 11, 2).  `single_step_iterations` counts the CG iterations of one
 such step with a random right-hand side, with and without the preconditioner
-(the paper's single-step table).
+(the paper's single-step table).  `smooth_errors` is the smooth 2D example of
+Sec. 4.2: f = M g_1 on a fine grid (4095^2, padded to 8192 points per axis),
+subsampled to coarser grids, solved there and compared with g_1.
 """
 import math
 
 import numpy as np
 import torch
 
-from . import FL_PC_FD, FL_PC_NONE, Op, solve_opts
+from . import FL_PC_AUTO, FL_PC_FD, FL_PC_NONE, Op, solve_opts
 
 
 def unit_grid(n):
@@ -122,3 +124,36 @@ def single_step_iterations(d, alpha, n, seed=0, tol=1e-9, stream=None):
         out[name] = inf["iters"]
     op.close()
     return out
+
+
+def subsample(v, n_fine, n):
+    """Values of a fine-grid function (n_fine points per axis) at the points of
+    the n-point grid; (n + 1) must divide (n_fine + 1)."""
+    step, rem = divmod(n_fine + 1, n + 1)
+    if rem:
+        raise ValueError("n + 1 must divide n_fine + 1")
+    sl = slice(step - 1, None, step)
+    return np.ascontiguousarray(v[tuple(sl for _ in range(v.ndim))])
+
+
+def smooth_errors(alpha, ns=(127, 255, 511, 1023), n_fine=4095, tol=1e-13, stream=None):
+    """Sec. 4.2, the smooth 2D example: u_true = g_1 on the n_fine^2 grid of
+    [0, 1]^2, f = M^(n_fine) u_true (one FP64 application); for each n, the
+    subsampled f is solved on the n^2 grid (FP64 PCG, the preconditioner chosen
+    by alpha) and e = ||u_true - u|| / ||u_true|| on that grid.  Also the growth
+    rate gamma of e ~ n^gamma, the least-squares slope of log e against log n."""
+    opf = Op(2, alpha, 1.0 / (n_fine + 1), (n_fine, n_fine), stream=stream)
+    uf = bump(n_fine, 2)
+    ff = opf.apply(torch.from_numpy(uf.copy()).cuda()).cpu().numpy()
+    opf.close()
+    errs, solves = [], []
+    for n in ns:
+        f = subsample(ff, n_fine, n)
+        ut = subsample(uf, n_fine, n)
+        op = Op(2, alpha, 1.0 / (n + 1), (n, n), stream=stream)
+        u, inf = op.solve(torch.from_numpy(f).cuda(), tol=tol, opts=solve_opts(pc=FL_PC_AUTO, maxit=20000))
+        op.close()
+        errs.append(float(np.linalg.norm(u.cpu().numpy() - ut) / np.linalg.norm(ut)))
+        solves.append({"n": n, "iters": inf["iters"], "rel_res_true": inf["rel_res_true"]})
+    gamma = float(np.polyfit(np.log(np.asarray(ns, dtype=float)), np.log(errs), 1)[0])
+    return {"errors": errs, "rate": gamma, "solves": solves}

@@ -16,7 +16,7 @@ template <typename T> static fl_status launch_col_conv(const Prob& pc, const Col
     // FP64 at 2048 with 64 lanes would need 4 x 37 KB of LDS: keep 128 or more
     if (lf == 2048 && sizeof(T) == 8 && tplf == 64) tplf = 128;
     if (lf == 1024) tplf = 64;
-  } else if (fft_lf(A) == 512 || fft_lf(A) == 256) {
+  } else if (fft_lf(A) == 8192 || fft_lf(A) == 512 || fft_lf(A) == 256) {
     lf = A.P;  // the plan's lanes, compile-time
     tplf = c_fixed_tpl(lf);
   }
@@ -26,7 +26,9 @@ template <typename T> static fl_status launch_col_conv(const Prob& pc, const Col
   const int nt = block_for(tpl), G = nt / tpl;
   const long grid = cg.ngroup * ((cg.gs + G - 1) / G);
   const size_t sm = (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>);
-  if (lf == 2048 && tplf == 256)
+  if (lf == 8192)
+    LAUNCH((k_colpass<T, COL_CONV, 8192, c_fixed_tpl(8192)>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
+  else if (lf == 2048 && tplf == 256)
     LAUNCH((k_colpass<T, COL_CONV, 2048, 256>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
   else if (lf == 2048 && tplf == 64)
     LAUNCH((k_colpass<T, COL_CONV, 2048, 64>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
@@ -46,6 +48,13 @@ template <typename T> static fl_status launch_col_conv(const Prob& pc, const Col
 // Row passes with the length specialisation of the last axis (fft_lf).
 template <typename T, int PRO>
 static fl_status launch_rowfwd(int lf, dim3 g, dim3 b, size_t sm, hipStream_t s, const Prob& pb, Iter it) {
+  if (lf == 8192) {  // application-only grids: the plain application
+    if constexpr (PRO == PRO_PLAIN) {
+      LAUNCH((k_rowfwd<T, PRO, 8192>), g, b, sm, s, pb, it);
+      return FL_OK;
+    }
+    return fail(FL_E_UNSUPPORTED, "lines of 8192 points support the plain application only");
+  }
   switch (lf) {
     case 2048: LAUNCH((k_rowfwd<T, PRO, 2048>), g, b, sm, s, pb, it); break;
     case 1024: LAUNCH((k_rowfwd<T, PRO, 1024>), g, b, sm, s, pb, it); break;
@@ -57,6 +66,13 @@ static fl_status launch_rowfwd(int lf, dim3 g, dim3 b, size_t sm, hipStream_t s,
 }
 template <typename T, int EPI>
 static fl_status launch_rowinv(int lf, dim3 g, dim3 b, size_t sm, hipStream_t s, const Prob& pb, Iter it, int chk) {
+  if (lf == 8192) {
+    if constexpr (EPI == EPI_PLAIN) {
+      LAUNCH((k_rowinv<T, EPI, 8192>), g, b, sm, s, pb, it, chk);
+      return FL_OK;
+    }
+    return fail(FL_E_UNSUPPORTED, "lines of 8192 points support the plain application only");
+  }
   switch (lf) {
     case 2048: LAUNCH((k_rowinv<T, EPI, 2048>), g, b, sm, s, pb, it, chk); break;
     case 1024: LAUNCH((k_rowinv<T, EPI, 1024>), g, b, sm, s, pb, it, chk); break;

@@ -698,6 +698,7 @@ fl_status fl_solve_batched(int nprob, const fl_op* ops, const double* const* f, 
   for (int p = 0; p < nprob; ++p) {
     if (!ops[p] || !f[p] || !u[p]) return fail(FL_E_INVALID, "NULL problem entry");
     if (!(tol[p] > 0.0)) return fail(FL_E_INVALID, "tol must be positive");
+    STCHK(need_solver_grid(ops[p]));
   }
   std::lock_guard<std::mutex> lk(g_batch_mu);
   Batch* bp = nullptr;
@@ -731,8 +732,10 @@ fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const d
   auto t0 = std::chrono::steady_clock::now();
   if (nprob < 1 || !ops || !u || !dt || !infos) return fail(FL_E_INVALID, "NULL argument");
   if (!(theta > 0.0 && theta <= 1.0) || !(tol > 0.0) || nsteps < 0) return fail(FL_E_INVALID, "theta, tol or nsteps");
-  for (int p = 0; p < nprob; ++p)
+  for (int p = 0; p < nprob; ++p) {
     if (!ops[p] || !u[p] || !(dt[p] > 0.0)) return fail(FL_E_INVALID, "bad problem entry");
+    STCHK(need_solver_grid(ops[p]));
+  }
   std::lock_guard<std::mutex> lk(g_batch_mu);
   Batch* bp = nullptr;
   std::vector<double> s1(nprob), p1(nprob);

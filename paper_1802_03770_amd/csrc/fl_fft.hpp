@@ -274,7 +274,7 @@ __host__ __device__ constexpr int c_fixed_tpl(int L) {
 // lengths with a specialisation (apply / chirp-z / cosine lengths, direct sine lengths)
 __host__ __device__ constexpr bool c_is_fixed(int L) {
   return L == 128 || L == 256 || L == 512 || L == 768 || L == 1024 || L == 2048 || L == 130 || L == 258 ||
-         L == 770 || L == 1026 || L == 2050;
+         L == 770 || L == 1026 || L == 2050 || L == 8192;
 }
 
 // direct DFT of odd prime radix R on registers a[0..R-1] (conjugate-pair form)
@@ -517,6 +517,13 @@ __device__ __forceinline__ bool fft_try_fixed_wide(Line<T> buf, Line<T> aux, con
 template <typename T, bool INV>
 __device__ __forceinline__ void fft_line(Line<T> buf, const FFTPlan pl, int lane) {
   if (fft_try_fixed<T, INV>(buf, pl, lane)) return;
+  if (pl.L > kMaxElems * pl.tpl) {
+    // a line longer than the run-time stages hold (the 8192 plan, which only
+    // its specialised kernels take): NaN out rather than a partial transform
+    for (int i = lane; i < pl.L; i += pl.tpl) buf[i] = {(T)NAN, (T)NAN};
+    __syncthreads();
+    return;
+  }
   const cx<T>* __restrict__ tw = (const cx<T>*)pl.tw;
   int Ns = 1, lg = 0;
   for (int s = 0; s < pl.nst; ++s) {

@@ -66,6 +66,13 @@ static bool make_radices(int L, FFTPlan& pl, bool wide = false) {
     while (radix_of_code(c) != r[i]) ++c;
     pl.radcode |= (unsigned long long)c << (4 * i);
   }
+  if (L == 8192 && !wide) {
+    // the one line longer than 4096: only its compile-time kernels (256 lanes,
+    // four radix-8 butterflies per lane and stage) take it
+    pl.tpl = c_fixed_tpl(L);
+    pl.fixed = 1;
+    return true;
+  }
   int tpl = 1;
   while (tpl * kMaxElems < L) tpl *= 2;
   for (;;) {
@@ -111,8 +118,11 @@ template <typename T> static fl_status build_axis(fl_op op, int a, int form) {
   A.n = n;
   A.P = op->P[a];
   A.H = op->H[a];
-  if (!make_radices(A.P, A.fft)) return fail(FL_E_UNSUPPORTED, "padded length not 2,3,5-smooth");
+  if (!make_radices(A.P, A.fft))
+    return fail(FL_E_UNSUPPORTED, "no FFT plan for padded length " + std::to_string(A.P) +
+                                      " (lengths above 4096 other than 8192 are not supported)");
   STCHK(upload(op, host_twiddles<T>(A.P), &A.fft.tw));
+  if (op->apply_only) return FL_OK;  // no sine transforms on application-only grids
   // sine transform: direct (odd extension of length 2(n+1), two lines per FFT
   // line) when 2(n+1) factors over the wide radix set, else the chirp-z identity
   A.dst_direct = (form != 2 && make_radices(2 * (n + 1), A.dst, true)) ? 1 : 0;
@@ -186,8 +196,13 @@ static fl_status build_symbol(fl_op op) {
     const FFTPlan& pl = op->ax[0][a].fft;
     int nt = block_for(pl.tpl), G = nt / pl.tpl;
     long pairs = (nl + 1) / 2;
-    LAUNCH(k_dct1_axis, dim3((pairs + G - 1) / G), dim3(nt), (size_t)G * Line<double>::stride(op->P[a]) * sizeof(cx<double>), s,
-           (double*)op->lam[0], op->H[a], op->P[a], inner, nl, pl);
+    const size_t sm = (size_t)G * Line<double>::stride(op->P[a]) * sizeof(cx<double>);
+    if (op->P[a] == 8192)
+      LAUNCH(k_dct1_axis<8192>, dim3((pairs + G - 1) / G), dim3(nt), sm, s, (double*)op->lam[0], op->H[a], op->P[a],
+             inner, nl, pl);
+    else
+      LAUNCH(k_dct1_axis<>, dim3((pairs + G - 1) / G), dim3(nt), sm, s, (double*)op->lam[0], op->H[a], op->P[a],
+             inner, nl, pl);
   }
   LAUNCH(k_cast<float, double>, dim3((op->NH + 255) / 256), dim3(256), 0, s, (const double*)op->lam[0],
          (float*)op->lam[1], op->NH, 1.0);
@@ -328,6 +343,12 @@ static fl_status make_op(int d, double alpha, double h, const int64_t* n, const 
   op->col_lanes =
       (o && (o->col_lanes == -1 || o->col_lanes == 64 || o->col_lanes == 128 || o->col_lanes == 256)) ? o->col_lanes : 0;
   op->sine_col_lanes = (o && (o->sine_col_lanes == -1 || o->sine_col_lanes == 128)) ? o->sine_col_lanes : 0;
+  // Grids padded to 8192 points along an axis (n = 4081 .. 4096) are
+  // application-only, in 2D: their FFT lines have compile-time kernels for the
+  // application passes and the symbol, but no sine transforms, solves, steps
+  // or batches.
+  for (int a = 0; a < d; ++a) op->apply_only = op->apply_only || op->P[a] > 4096;
+  if (op->apply_only && d != 2) return bail(fail(FL_E_UNSUPPORTED, "padded lengths above 4096 are supported in 2D only"));
   for (int a = 0; a < d; ++a) {
     if ((st = build_axis<double>(op, a, op->dst_mode == 2 ? 2 : 1)) != FL_OK) return bail(st);
     if ((st = build_axis<float>(op, a, op->dst_mode == 2 ? 2 : 1)) != FL_OK) return bail(st);
@@ -913,6 +934,7 @@ fl_status fl_op_plan(fl_op op, int64_t* out) {
 fl_status fl_op_export(fl_op op, int which, void* dst) {
   if (!op || !dst) return fail(FL_E_INVALID, "NULL argument");
   if (which == 3 || which == 4) {
+    STCHK(need_solver_grid(op));
     STCHK(build_tau(op));
     HIPCHK(hipMemcpyAsync(dst, op->tau[which - 3], op->N * (which == 4 ? sizeof(float) : sizeof(double)),
                           hipMemcpyDeviceToDevice, op->stream));
@@ -947,6 +969,7 @@ fl_status fl_precond(fl_op op, const void* r, void* z, int dtype, int64_t batch,
                      double p1) {
   if (!op || !r || !z) return fail(FL_E_INVALID, "NULL argument");
   if (batch < 1) return fail(FL_E_INVALID, "batch must be >= 1");
+  STCHK(need_solver_grid(op));
   if (dtype == FL_F64) return precond_t<double>(op, r, z, batch, mask, p0, p1, FL_PC_FD);
   if (dtype == FL_F32) return precond_t<float>(op, r, z, batch, mask, p0, p1, FL_PC_FD);
   return fail(FL_E_INVALID, "dtype must be FL_F64 or FL_F32");
@@ -956,6 +979,7 @@ fl_status fl_precond_spectral(fl_op op, const void* r, void* z, int dtype, int64
                      double p1) {
   if (!op || !r || !z) return fail(FL_E_INVALID, "NULL argument");
   if (batch < 1) return fail(FL_E_INVALID, "batch must be >= 1");
+  STCHK(need_solver_grid(op));
   if (dtype == FL_F64) return precond_t<double>(op, r, z, batch, mask, p0, p1, FL_PC_SPECTRAL);
   if (dtype == FL_F32) return precond_t<float>(op, r, z, batch, mask, p0, p1, FL_PC_SPECTRAL);
   return fail(FL_E_INVALID, "dtype must be FL_F64 or FL_F32");
@@ -965,6 +989,7 @@ fl_status fl_precond_any(fl_op op, int kind, const void* r, void* z, int dtype, 
                           double p0, double p1) {
   if (!op || !r || !z) return fail(FL_E_INVALID, "NULL argument");
   if (batch < 1) return fail(FL_E_INVALID, "batch must be >= 1");
+  STCHK(need_solver_grid(op));
   if (dtype == FL_F64) return precond_t<double>(op, r, z, batch, mask, p0, p1, kind);
   if (dtype == FL_F32) return precond_t<float>(op, r, z, batch, mask, p0, p1, kind);
   return fail(FL_E_INVALID, "dtype must be FL_F64 or FL_F32");
@@ -975,6 +1000,7 @@ fl_status fl_solve(fl_op op, const double* f, const uint8_t* mask, double tol, c
   auto t0 = std::chrono::steady_clock::now();
   if (!op || !f || !u || !info) return fail(FL_E_INVALID, "NULL argument");
   if (!(tol > 0.0)) return fail(FL_E_INVALID, "tol must be positive");
+  STCHK(need_solver_grid(op));
   STCHK(ensure_ws<double>(op, 1, true));
   Workspace& w = op->ws[0];
   const long N = op->N;
@@ -995,6 +1021,7 @@ fl_status fl_step(fl_op op, double* u, double dt, double theta, const double* f_
   auto t0 = std::chrono::steady_clock::now();
   if (!op || !u || !info) return fail(FL_E_INVALID, "NULL argument");
   if (!(dt > 0.0) || !(theta > 0.0 && theta <= 1.0) || !(tol > 0.0)) return fail(FL_E_INVALID, "dt, theta or tol");
+  STCHK(need_solver_grid(op));
   if (o && o->pc == FL_PC_LEARNED) return fail(FL_E_UNSUPPORTED, "the learned preconditioner is trained for M, not steps");
   STCHK(ensure_ws<double>(op, 1, true));
   Workspace& w = op->ws[0];
@@ -1028,6 +1055,7 @@ fl_status fl_op_destroy(fl_op op) {
 
 fl_status fl_profile_pass(fl_op op, int dtype, int pass, int reps, double* avg_ms) {
   if (!op || !avg_ms || reps < 1) return fail(FL_E_INVALID, "NULL argument or reps < 1");
+  if (pass >= 3) STCHK(need_solver_grid(op));
   if (dtype == FL_F64) return profile_t<double>(op, pass, reps, avg_ms);
   if (dtype == FL_F32) return profile_t<float>(op, pass, reps, avg_ms);
   return fail(FL_E_INVALID, "dtype");

@@ -90,6 +90,7 @@ struct fl_op_s {
   int d = 0;
   double alpha = 0, h = 0, c = 20;
   int dst_mode = 0;         // 0 autotune, 1 direct when possible, 2 chirp-z
+  bool apply_only = false;  // an axis padded to 8192: the application only (2D)
   int col_lanes = 0;        // 0 autotune, -1 run-time plan, 64 / 128 forced
   int sine_col_lanes = 0;   // 0 autotune, -1 plan, 128 forced
   int dst_form[2][3] = {};  // chosen per precision and axis: 1 direct, 2 chirp-z
@@ -155,10 +156,17 @@ inline int dst_lf(const Axis& A) {
 // Length specialisation of the FFT row and column kernels of the application:
 // the padded lengths 256..2048 of the common grids (lanes c_fixed_tpl(P));
 // 0 = the run-time plan.
+// Entry points beyond the application refuse application-only ops.
+inline fl_status need_solver_grid(fl_op op) {
+  if (op->apply_only)
+    return fail(FL_E_UNSUPPORTED, "grids padded to 8192 points along an axis support fl_apply only");
+  return FL_OK;
+}
+
 inline int fft_lf(const Axis& A) {
   if (!A.fft.fixed) return 0;
   switch (A.P) {
-    case 2048: case 1024: case 512: case 256: return A.P;
+    case 8192: case 2048: case 1024: case 512: case 256: return A.P;
     default: return 0;
   }
 }

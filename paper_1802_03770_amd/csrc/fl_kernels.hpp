@@ -211,9 +211,13 @@ __global__ void k_weights(int d, double alpha, int n0, int n1, int n2, int H0, i
 // of the folded array, in place.  Two lines are packed as x + i y, extended
 // evenly to length P and transformed; x' = Re, y' = Im.  Lines along axis a:
 // index = o * (H_a * inner) + m * inner + c, c in [0, inner).
+// LF > 0: the compile-time FFT of that length (8192, whose line the run-time
+// stages cannot hold).
+template <int LF = 0>
 __global__ __launch_bounds__(256) void k_dct1_axis(double* wf, int H, int P, long inner, long nlines, FFTPlan pl) {
   extern __shared__ __align__(16) char smem[];
-  const int tpl = pl.tpl, G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  const int tpl = LF > 0 ? c_fixed_tpl(LF) : pl.tpl, G = blockDim.x / tpl, g = threadIdx.x / tpl,
+            lane = threadIdx.x % tpl;
   Line<double> buf = line_at<double>(smem, g, P);
   long pair = (long)blockIdx.x * G + g;
   long la = 2 * pair, lb = la + 1;
@@ -227,7 +231,10 @@ __global__ __launch_bounds__(256) void k_dct1_axis(double* wf, int H, int P, lon
     buf[i] = {xa, xb};
   }
   __syncthreads();
-  fft_line<double, false>(buf, pl, lane);
+  if constexpr (LF > 0)
+    fft_fixed<double, LF, false>(buf, buf, (const cx<double>*)pl.tw, lane);
+  else
+    fft_line<double, false>(buf, pl, lane);
   for (int k = lane; k < H; k += tpl) {
     if (va) wf[ba + (long)k * inner] = buf[k].x;
     if (vb) wf[bb + (long)k * inner] = buf[k].y;

@@ -1622,6 +1622,7 @@ fl_status fl_learned_pairs(fl_op op, const double* e, int64_t e_stride, const do
   if (!op || !e || !R || !T) return fail(FL_E_INVALID, "NULL argument");
   if (e_stride != 0 && e_stride != op->N) return fail(FL_E_INVALID, "e_stride must be 0 or the grid size");
   if (op->d != 2 && op->d != 3) return fail(FL_E_UNSUPPORTED, "training pairs are built for d = 2, 3");
+  STCHK(need_solver_grid(op));
   PadGrid q = pad_grid(op);
   q.P0 = Dp;
   q.P1 = Hp;
