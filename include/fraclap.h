@@ -113,7 +113,12 @@ typedef struct {
  * weights (padded length per axis: smallest even 2^a 3^b 5^c >= 2 n_k; lags
  * >= n_k of the embedding are zero), FP64 and FP32 copies, and the transform
  * tables.  Paper: Sec. 2.7 (constants), Sec. 3.1 (M and its FFT application).
- * `opts` may be NULL.  On success *out owns all device memory of the op. */
+ * `opts` may be NULL.  On success *out owns all device memory of the op.
+ * Padded lengths up to 4096 are supported everywhere; a padded length of 8192
+ * (n_k = 4081 .. 4096, e.g. the 4095^2 fine grid of the smooth 2D example of
+ * Sec. 4.2) only in 2D and only for fl_apply: on such an op every other
+ * computing call returns FL_E_UNSUPPORTED.  Other lengths above 4096 fail here
+ * with FL_E_UNSUPPORTED. */
 fl_status fl_make_weights(int d, double alpha, double h, const int64_t* n, const fl_weights_opts* opts,
                           void* hip_stream, fl_op* out);
 
