@@ -9,6 +9,8 @@
 // and once with FL_BATCH_HOST for the C entry points.
 #include "fl_internal.hpp"
 #include "fl_batch.hpp"
+#include <algorithm>
+#include <cstring>
 #include <memory>
 #include <mutex>
 
@@ -24,75 +26,139 @@ template <typename T> fl_status bt_setup(BatchT& bt, const BatchDesc& B, const s
   bt.np = np;
   bt.d = d;
   bt.elem = sizeof(T);
-  auto mk = [&](std::vector<int>& nb) { nb.assign(np, 0); };
+  // per problem (problem order): block counts, geometry, LDS and the length
+  // specialisation of every pass
+  struct One {
+    int nb_rowfwd, nb_dstrow, nb_upd, nb_col[3], nb_dcol[2];
+    ColGeom cg[3];
+    DGeom dg[2];
+    long N;
+    size_t sm_row, sm_dstrow, sm_col[3], sm_dcol[2];
+    int key[6];  // lf_rowfft, lf_col[0..2], lf_row, lf_dcol[0] (lf_dcol[1] = lf_dcol[0] in 3D)
+    int lf_dcol1;
+  };
+  std::vector<One> pr(np);
+  for (int p = 0; p < np; ++p) {
+    One& o = pr[p];
+    memset(&o, 0, sizeof(One));
+    const Prob& pb = base[p];
+    const int* n = B.n[p].data();
+    long rows = 1, N = 1;
+    for (int a = 0; a < d - 1; ++a) rows *= n[a];
+    for (int a = 0; a < d; ++a) N *= n[a];
+    o.N = N;
+    o.nb_upd = (int)std::min<long>(2048, (N + 255) / 256);
+    const Axis& AL = pb.ax[d - 1];
+    const long pairs = (rows + 1) / 2;
+    {
+      const int G = 256 / AL.fft.tpl;
+      o.nb_rowfwd = (int)((pairs + G - 1) / G);
+      o.sm_row = lds_fft<T>(AL.P, G);
+    }
+    if (d == 2) {
+      const long H1 = pb.ax[1].H, n0 = n[0];
+      o.cg[0] = ColGeom{0, (int)n0, (int)n0, H1, 1, H1, n0 * H1, H1, n0 * H1, 1, 1};
+    } else if (d == 3) {
+      const long n0 = n[0], n1 = n[1], P1 = pb.ax[1].P, H2 = pb.ax[2].H;
+      o.cg[0] = ColGeom{1, (int)n1, (int)P1, H2, n0, H2, n1 * H2, H2, P1 * H2, 1, 2};
+      o.cg[1] = ColGeom{0, (int)n0, (int)n0, P1 * H2, 1, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
+      o.cg[2] = ColGeom{1, (int)P1, (int)n1, H2, n0, H2, P1 * H2, H2, n1 * H2, 2, 1};
+    }
+    o.key[0] = fft_lf(AL);
+    const int ncol = d == 3 ? 3 : (d == 2 ? 1 : 0);
+    for (int r = 0; r < ncol; ++r) {
+      const ColGeom& c = o.cg[r];
+      const Axis& A = pb.ax[c.axis];
+      const int lfa = fft_lf(A);
+      o.key[1 + r] = (lfa == 1024 || lfa == 512 || lfa == 256) ? lfa : 0;
+      const int G = 256 / A.fft.tpl;
+      o.nb_col[r] = (int)(c.ngroup * ((c.gs + G - 1) / G));
+      o.sm_col[r] = lds_fft<T>(A.P, G);
+    }
+    // sine transforms
+    {
+      const long rl = AL.dst_direct ? (rows + 1) / 2 : rows;
+      const int G = 256 / AL.dst.tpl;
+      o.nb_dstrow = (int)((rl + G - 1) / G);
+      o.sm_dstrow = lds_fft<T>(AL.dst.L, G) * (AL.dst_direct ? 2 : 1);
+    }
+    if (d == 2) {
+      o.dg[0] = DGeom{0, (long)n[1], 1, (long)n[1], (long)n[0] * n[1]};
+    } else if (d == 3) {
+      o.dg[0] = DGeom{1, (long)n[2], (long)n[0], (long)n[2], (long)n[1] * n[2]};
+      o.dg[1] = DGeom{0, (long)n[1] * n[2], 1, (long)n[1] * n[2], (long)n[0] * n[1] * n[2]};
+    }
+    o.key[4] = dst_lf(AL);
+    const int ndc = d == 3 ? 2 : (d == 2 ? 1 : 0);
+    for (int r = 0; r < ndc; ++r) {
+      const DGeom& g = o.dg[r];
+      const Axis& A = pb.ax[g.axis];
+      if (r == 0) o.key[5] = dst_lf(A);
+      else o.lf_dcol1 = dst_lf(A);
+      const int per = A.dst_direct ? 2 : 1;
+      const int Gf = 256 / A.dst.tpl, G = Gf * per;
+      o.nb_dcol[r] = (int)(g.ngroup * ((g.gs + G - 1) / G));
+      o.sm_dcol[r] = lds_fft<T>(A.dst.L, Gf) * per;
+    }
+  }
+  // group order: problems with equal specialisations next to each other
+  // (stable, so a uniform batch keeps problem order)
+  auto key_of = [&](int p) {
+    std::array<int, 7> k;
+    for (int i = 0; i < 6; ++i) k[i] = pr[p].key[i];
+    k[6] = pr[p].lf_dcol1;
+    return k;
+  };
+  bt.order.resize(np);
+  for (int p = 0; p < np; ++p) bt.order[p] = p;
+  std::stable_sort(bt.order.begin(), bt.order.end(), [&](int a, int b) { return key_of(a) < key_of(b); });
+  auto mk = [&](std::vector<int>& v) { v.assign(np, 0); };
   mk(bt.nb_rowfwd); mk(bt.nb_rowinv); mk(bt.nb_dstrow); mk(bt.nb_upd);
   for (auto& v : bt.nb_col) mk(v);
   for (auto& v : bt.nb_dcol) mk(v);
   bt.cg.assign(3 * np, ColGeom{});
   bt.dg.assign(2 * np, DGeom{});
   bt.N.assign(np, 0);
-  bt.sm_row = bt.sm_dstrow = 0;
-  for (auto& s : bt.sm_col) s = 0;
-  for (auto& s : bt.sm_dcol) s = 0;
-  for (int p = 0; p < np; ++p) {
-    const Prob& pb = base[p];
-    const int* n = B.n[p].data();
-    long rows = 1, N = 1;
-    for (int a = 0; a < d - 1; ++a) rows *= n[a];
-    for (int a = 0; a < d; ++a) N *= n[a];
-    bt.N[p] = N;
-    bt.nb_upd[p] = (int)std::min<long>(2048, (N + 255) / 256);
-    const Axis& AL = pb.ax[d - 1];
-    long pairs = (rows + 1) / 2;
-    {
-      int G = 256 / AL.fft.tpl;
-      bt.nb_rowfwd[p] = bt.nb_rowinv[p] = (int)((pairs + G - 1) / G);
-      bt.sm_row = std::max(bt.sm_row, lds_fft<T>(AL.P, G));
+  bt.groups.clear();
+  for (int q = 0; q < np; ++q) {
+    const int p = bt.order[q];
+    const One& o = pr[p];
+    bt.nb_rowfwd[q] = bt.nb_rowinv[q] = o.nb_rowfwd;
+    bt.nb_dstrow[q] = o.nb_dstrow;
+    bt.nb_upd[q] = o.nb_upd;
+    for (int r = 0; r < 3; ++r) {
+      bt.nb_col[r][q] = o.nb_col[r];
+      bt.cg[r * np + q] = o.cg[r];
     }
-    if (d == 2) {
-      const long H1 = pb.ax[1].H, n0 = n[0];
-      ColGeom c = {0, (int)n0, (int)n0, H1, 1, H1, n0 * H1, H1, n0 * H1, 1, 1};
-      bt.cg[p] = c;
-    } else if (d == 3) {
-      const long n0 = n[0], n1 = n[1], P1 = pb.ax[1].P, H2 = pb.ax[2].H;
-      bt.cg[p] = ColGeom{1, (int)n1, (int)P1, H2, n0, H2, n1 * H2, H2, P1 * H2, 1, 2};
-      bt.cg[np + p] = ColGeom{0, (int)n0, (int)n0, P1 * H2, 1, P1 * H2, n0 * P1 * H2, P1 * H2, n0 * P1 * H2, 2, 2};
-      bt.cg[2 * np + p] = ColGeom{1, (int)P1, (int)n1, H2, n0, H2, P1 * H2, H2, n1 * H2, 2, 1};
+    for (int r = 0; r < 2; ++r) {
+      bt.nb_dcol[r][q] = o.nb_dcol[r];
+      bt.dg[r * np + q] = o.dg[r];
     }
-    bt.lf_rowfft = (p == 0 || bt.lf_rowfft == fft_lf(AL)) ? fft_lf(AL) : 0;
-    const int ncol = d == 3 ? 3 : (d == 2 ? 1 : 0);
-    for (int r = 0; r < ncol; ++r) {
-      const ColGeom& c = bt.cg[r * np + p];
-      const Axis& A = pb.ax[c.axis];
-      const int lfc = (fft_lf(A) == 512 || fft_lf(A) == 256) ? fft_lf(A) : 0;
-      bt.lf_col[r] = (p == 0 || bt.lf_col[r] == lfc) ? lfc : 0;
-      int G = 256 / A.fft.tpl;
-      bt.nb_col[r][p] = (int)(c.ngroup * ((c.gs + G - 1) / G));
-      bt.sm_col[r] = std::max(bt.sm_col[r], lds_fft<T>(A.P, G));
+    bt.N[q] = o.N;
+    if (q == 0 || key_of(p) != key_of(bt.order[q - 1])) {
+      BatchGroup g;
+      g.g0 = q;
+      g.lf_rowfft = o.key[0];
+      for (int r = 0; r < 3; ++r) g.lf_col[r] = o.key[1 + r];
+      g.lf_row = o.key[4];
+      g.lf_dcol[0] = o.key[5];
+      g.lf_dcol[1] = o.lf_dcol1;
+      bt.groups.push_back(g);
     }
-    // sine transforms
-    {
-      const long rl = AL.dst_direct ? (rows + 1) / 2 : rows;
-      int G = 256 / AL.dst.tpl;
-      bt.nb_dstrow[p] = (int)((rl + G - 1) / G);
-      bt.sm_dstrow = std::max(bt.sm_dstrow, lds_fft<T>(AL.dst.L, G) * (AL.dst_direct ? 2 : 1));
+    BatchGroup& g = bt.groups.back();
+    ++g.gn;
+    g.nb_rowfwd = std::max(g.nb_rowfwd, o.nb_rowfwd);
+    g.nb_rowinv = g.nb_rowfwd;
+    g.nb_dstrow = std::max(g.nb_dstrow, o.nb_dstrow);
+    g.sm_row = std::max(g.sm_row, o.sm_row);
+    g.sm_dstrow = std::max(g.sm_dstrow, o.sm_dstrow);
+    for (int r = 0; r < 3; ++r) {
+      g.nb_col[r] = std::max(g.nb_col[r], o.nb_col[r]);
+      g.sm_col[r] = std::max(g.sm_col[r], o.sm_col[r]);
     }
-    if (d == 2) {
-      bt.dg[p] = DGeom{0, (long)n[1], 1, (long)n[1], (long)n[0] * n[1]};
-    } else if (d == 3) {
-      bt.dg[p] = DGeom{1, (long)n[2], (long)n[0], (long)n[2], (long)n[1] * n[2]};
-      bt.dg[np + p] = DGeom{0, (long)n[1] * n[2], 1, (long)n[1] * n[2], (long)n[0] * n[1] * n[2]};
-    }
-    bt.lf_row = (p == 0 || bt.lf_row == dst_lf(AL)) ? dst_lf(AL) : 0;
-    const int ndc = d == 3 ? 2 : (d == 2 ? 1 : 0);
-    for (int r = 0; r < ndc; ++r) {
-      const DGeom& g = bt.dg[r * np + p];
-      const Axis& A = pb.ax[g.axis];
-      bt.lf_dcol[r] = (p == 0 || bt.lf_dcol[r] == dst_lf(A)) ? dst_lf(A) : 0;
-      const int per = A.dst_direct ? 2 : 1;
-      int Gf = 256 / A.dst.tpl, G = Gf * per;
-      bt.nb_dcol[r][p] = (int)(g.ngroup * ((g.gs + G - 1) / G));
-      bt.sm_dcol[r] = std::max(bt.sm_dcol[r], lds_fft<T>(A.dst.L, Gf) * per);
+    for (int r = 0; r < 2; ++r) {
+      g.nb_dcol[r] = std::max(g.nb_dcol[r], o.nb_dcol[r]);
+      g.sm_dcol[r] = std::max(g.sm_dcol[r], o.sm_dcol[r]);
     }
   }
   return FL_OK;
@@ -103,39 +169,43 @@ static int vmax(const std::vector<int>& v) {
   for (int x : v) m = std::max(m, x);
   return m;
 }
-// grid width of the column passes: a multiple of 8, so that their XCD-aware
-// tile mapping holds for every problem (blocks beyond a problem's count exit)
-static int vmax8(const std::vector<int>& v) { return (vmax(v) + 7) & ~7; }
 
 // Batched operator application with prologue PRO / epilogue EPI over the Prob
-// array `pbs` (device).
+// array `pbs` (device, group order): one launch per group and pass.
 template <typename T, int PRO, int EPI> fl_status bt_apply(BatchT& bt, const Prob* pbs, Iter it, int chk,
                                                           hipStream_t s) {
   const int np = bt.np, d = bt.d;
-  if (d == 1) {
-    LAUNCH(k_conv1d_b<T, PRO, EPI>, dim3(vmax(bt.nb_rowfwd), np), dim3(256), bt.sm_row, s, pbs, it,
-           (const int*)bt.d_nb_rowfwd);
-    return FL_OK;
+  for (const BatchGroup& G : bt.groups) {
+    const Prob* pg = pbs + G.g0;
+    if (d == 1) {
+      LAUNCH(k_conv1d_b<T, PRO, EPI>, dim3(G.nb_rowfwd, G.gn), dim3(256), G.sm_row, s, pg, it,
+             (const int*)bt.d_nb_rowfwd + G.g0);
+      continue;
+    }
+    const int* nbf = (const int*)bt.d_nb_rowfwd + G.g0;
+    const dim3 gf(G.nb_rowfwd, G.gn);
+    switch (G.lf_rowfft) {
+      case 2048: LAUNCH((k_rowfwd_b<T, PRO, 2048>), gf, dim3(256), G.sm_row, s, pg, it, nbf); break;
+      case 1024: LAUNCH((k_rowfwd_b<T, PRO, 1024>), gf, dim3(256), G.sm_row, s, pg, it, nbf); break;
+      case 512: LAUNCH((k_rowfwd_b<T, PRO, 512>), gf, dim3(256), G.sm_row, s, pg, it, nbf); break;
+      case 256: LAUNCH((k_rowfwd_b<T, PRO, 256>), gf, dim3(256), G.sm_row, s, pg, it, nbf); break;
+      default: LAUNCH((k_rowfwd_b<T, PRO>), gf, dim3(256), G.sm_row, s, pg, it, nbf); break;
+    }
   }
-  const int* nbf = (const int*)bt.d_nb_rowfwd;
-  const dim3 gf(vmax(bt.nb_rowfwd), np);
-  switch (bt.lf_rowfft) {
-    case 2048: LAUNCH((k_rowfwd_b<T, PRO, 2048>), gf, dim3(256), bt.sm_row, s, pbs, it, nbf); break;
-    case 1024: LAUNCH((k_rowfwd_b<T, PRO, 1024>), gf, dim3(256), bt.sm_row, s, pbs, it, nbf); break;
-    case 512: LAUNCH((k_rowfwd_b<T, PRO, 512>), gf, dim3(256), bt.sm_row, s, pbs, it, nbf); break;
-    case 256: LAUNCH((k_rowfwd_b<T, PRO, 256>), gf, dim3(256), bt.sm_row, s, pbs, it, nbf); break;
-    default: LAUNCH((k_rowfwd_b<T, PRO>), gf, dim3(256), bt.sm_row, s, pbs, it, nbf); break;
-  }
-  auto col = [&](int r, int mode) -> fl_status {
-    const dim3 g(vmax8(bt.nb_col[r]), np);
-    const ColGeom* cg = (const ColGeom*)bt.d_cg + r * np;
-    const int* nb = (const int*)bt.d_nb_col[r];
-    const int lf = bt.lf_col[r];
-#define FL_COLB(M)                                                                                      \
-  switch (lf) {                                                                                         \
-    case 512: LAUNCH((k_colpass_b<T, M, 512>), g, dim3(256), bt.sm_col[r], s, pbs, cg, it, chk, nb); break; \
-    case 256: LAUNCH((k_colpass_b<T, M, 256>), g, dim3(256), bt.sm_col[r], s, pbs, cg, it, chk, nb); break; \
-    default: LAUNCH((k_colpass_b<T, M>), g, dim3(256), bt.sm_col[r], s, pbs, cg, it, chk, nb); break;       \
+  auto col = [&](const BatchGroup& G, int r, int mode) -> fl_status {
+    const Prob* pg = pbs + G.g0;
+    // grid width a multiple of 8, so that the XCD-aware tile mapping holds
+    // for every problem (blocks beyond a problem's count exit)
+    const dim3 g((G.nb_col[r] + 7) & ~7, G.gn);
+    const ColGeom* cg = (const ColGeom*)bt.d_cg + r * np + G.g0;
+    const int* nb = (const int*)bt.d_nb_col[r] + G.g0;
+    const size_t sm = G.sm_col[r];
+#define FL_COLB(M)                                                                                   \
+  switch (G.lf_col[r]) {                                                                             \
+    case 1024: LAUNCH((k_colpass_b<T, M, 1024>), g, dim3(256), sm, s, pg, cg, it, chk, nb); break;  \
+    case 512: LAUNCH((k_colpass_b<T, M, 512>), g, dim3(256), sm, s, pg, cg, it, chk, nb); break;    \
+    case 256: LAUNCH((k_colpass_b<T, M, 256>), g, dim3(256), sm, s, pg, cg, it, chk, nb); break;    \
+    default: LAUNCH((k_colpass_b<T, M>), g, dim3(256), sm, s, pg, cg, it, chk, nb); break;          \
   }
     if (mode == COL_FWD) { FL_COLB(COL_FWD) }
     else if (mode == COL_CONV) { FL_COLB(COL_CONV) }
@@ -143,28 +213,34 @@ template <typename T, int PRO, int EPI> fl_status bt_apply(BatchT& bt, const Pro
 #undef FL_COLB
     return FL_OK;
   };
-  if (d == 2) {
-    STCHK(col(0, COL_CONV));
-  } else {
-    STCHK(col(0, COL_FWD));
-    STCHK(col(1, COL_CONV));
-    STCHK(col(2, COL_INV));
+  if (d == 1) return FL_OK;
+  for (const BatchGroup& G : bt.groups) {
+    if (d == 2) {
+      STCHK(col(G, 0, COL_CONV));
+    } else {
+      STCHK(col(G, 0, COL_FWD));
+      STCHK(col(G, 1, COL_CONV));
+      STCHK(col(G, 2, COL_INV));
+    }
   }
-  const int* nbi = (const int*)bt.d_nb_rowinv;
-  const dim3 gi(vmax(bt.nb_rowinv), np);
-  switch (bt.lf_rowfft) {
-    case 2048: LAUNCH((k_rowinv_b<T, EPI, 2048>), gi, dim3(256), bt.sm_row, s, pbs, it, chk, nbi); break;
-    case 1024: LAUNCH((k_rowinv_b<T, EPI, 1024>), gi, dim3(256), bt.sm_row, s, pbs, it, chk, nbi); break;
-    case 512: LAUNCH((k_rowinv_b<T, EPI, 512>), gi, dim3(256), bt.sm_row, s, pbs, it, chk, nbi); break;
-    case 256: LAUNCH((k_rowinv_b<T, EPI, 256>), gi, dim3(256), bt.sm_row, s, pbs, it, chk, nbi); break;
-    default: LAUNCH((k_rowinv_b<T, EPI>), gi, dim3(256), bt.sm_row, s, pbs, it, chk, nbi); break;
+  for (const BatchGroup& G : bt.groups) {
+    const Prob* pg = pbs + G.g0;
+    const int* nbi = (const int*)bt.d_nb_rowinv + G.g0;
+    const dim3 gi(G.nb_rowinv, G.gn);
+    switch (G.lf_rowfft) {
+      case 2048: LAUNCH((k_rowinv_b<T, EPI, 2048>), gi, dim3(256), G.sm_row, s, pg, it, chk, nbi); break;
+      case 1024: LAUNCH((k_rowinv_b<T, EPI, 1024>), gi, dim3(256), G.sm_row, s, pg, it, chk, nbi); break;
+      case 512: LAUNCH((k_rowinv_b<T, EPI, 512>), gi, dim3(256), G.sm_row, s, pg, it, chk, nbi); break;
+      case 256: LAUNCH((k_rowinv_b<T, EPI, 256>), gi, dim3(256), G.sm_row, s, pg, it, chk, nbi); break;
+      default: LAUNCH((k_rowinv_b<T, EPI>), gi, dim3(256), G.sm_row, s, pg, it, chk, nbi); break;
+    }
   }
   return FL_OK;
 }
 
 // Batched preconditioner.  pfirst: Prob array of the first pass (reads `in`,
 // writes `out` = T1); plast: Prob array of the last pass (reads `in` = T1).
-// Sine-kernel launches with the length specialisation every problem shares.
+// Sine-kernel launches with the length specialisation of each group.
 template <typename T, int DPRO, int DEPI>
 static fl_status bt_dst_rows(int lf, dim3 g, size_t sm, hipStream_t s, const Prob* pbs, Iter it, int chk, const int* nb) {
   switch (lf) {
@@ -200,28 +276,34 @@ static fl_status bt_dst_cols(int lf, dim3 g, size_t sm, hipStream_t s, const Pro
 template <typename T, int DPRO, int DEPI> fl_status bt_precond(BatchT& bt, const Prob* pfirst, const Prob* plast,
                                                               Iter it, int chk, hipStream_t s) {
   const int np = bt.np, d = bt.d;
-  dim3 gr(vmax(bt.nb_dstrow), np);
-  const int* nbr = (const int*)bt.d_nb_dstrow;
+  const DGeom* dg = (const DGeom*)bt.d_dg;
   if (d == 1) {
-    LAUNCH((k_dst_rows_b<T, DPRO, DEPI>), gr, dim3(256), bt.sm_dstrow, s, pfirst, it, chk, nbr);
+    for (const BatchGroup& G : bt.groups)
+      LAUNCH((k_dst_rows_b<T, DPRO, DEPI>), dim3(G.nb_dstrow, G.gn), dim3(256), G.sm_dstrow, s, pfirst + G.g0, it,
+             chk, (const int*)bt.d_nb_dstrow + G.g0);
     return FL_OK;
   }
-  STCHK((bt_dst_rows<T, DPRO, DEPI_STORE>(bt.lf_row, gr, bt.sm_dstrow, s, pfirst, it, chk, nbr)));
-  const DGeom* dg = (const DGeom*)bt.d_dg;
-  auto cols = [&](int r, bool scale) -> fl_status {
-    dim3 g(vmax8(bt.nb_dcol[r]), np);
-    const int* nb = (const int*)bt.d_nb_dcol[r];
-    if (scale) return bt_dst_cols<T, true>(bt.lf_dcol[r], g, bt.sm_dcol[r], s, plast, dg + r * np, chk, nb);
-    return bt_dst_cols<T, false>(bt.lf_dcol[r], g, bt.sm_dcol[r], s, plast, dg + r * np, chk, nb);
+  for (const BatchGroup& G : bt.groups)
+    STCHK((bt_dst_rows<T, DPRO, DEPI_STORE>(G.lf_row, dim3(G.nb_dstrow, G.gn), G.sm_dstrow, s, pfirst + G.g0, it,
+                                             chk, (const int*)bt.d_nb_dstrow + G.g0)));
+  auto cols = [&](const BatchGroup& G, int r, bool scale) -> fl_status {
+    const dim3 g((G.nb_dcol[r] + 7) & ~7, G.gn);
+    const int* nb = (const int*)bt.d_nb_dcol[r] + G.g0;
+    const DGeom* dgr = dg + r * np + G.g0;
+    if (scale) return bt_dst_cols<T, true>(G.lf_dcol[r], g, G.sm_dcol[r], s, plast + G.g0, dgr, chk, nb);
+    return bt_dst_cols<T, false>(G.lf_dcol[r], g, G.sm_dcol[r], s, plast + G.g0, dgr, chk, nb);
   };
   if (d == 2) {
-    STCHK(cols(0, true));
+    for (const BatchGroup& G : bt.groups) STCHK(cols(G, 0, true));
   } else {
-    STCHK(cols(0, false));
-    STCHK(cols(1, true));
-    STCHK(cols(0, false));
+    for (const BatchGroup& G : bt.groups) STCHK(cols(G, 0, false));
+    for (const BatchGroup& G : bt.groups) STCHK(cols(G, 1, true));
+    for (const BatchGroup& G : bt.groups) STCHK(cols(G, 0, false));
   }
-  return bt_dst_rows<T, DPRO_PLAIN, DEPI>(bt.lf_row, gr, bt.sm_dstrow, s, plast, it, chk, nbr);
+  for (const BatchGroup& G : bt.groups)
+    STCHK((bt_dst_rows<T, DPRO_PLAIN, DEPI>(G.lf_row, dim3(G.nb_dstrow, G.gn), G.sm_dstrow, s, plast + G.g0, it, chk,
+                                             (const int*)bt.d_nb_dstrow + G.g0)));
+  return FL_OK;
 }
 
 template <typename T> fl_status bt_iteration(BatchT& bt, int pc, int k, hipStream_t s) {
@@ -259,6 +341,11 @@ template fl_status bt_resid<FL_T>(BatchT&, const Prob*, hipStream_t);
 template fl_status bt_apply_plain<FL_T>(BatchT&, const Prob*, hipStream_t);
 
 #else  // FL_BATCH_HOST
+static int vmax(const std::vector<int>& v) {
+  int m = 0;
+  for (int x : v) m = std::max(m, x);
+  return m;
+}
 // ---------------------------------------------------------------------------
 // host logic and C entry points
 // ---------------------------------------------------------------------------
@@ -285,7 +372,8 @@ struct Batch {
   void* d_true = nullptr;
   hipGraphExec_t g[2] = {nullptr, nullptr};
   int gpc[2] = {-1, -1}, gpoll[2] = {0, 0};
-  double* d_tol = nullptr;      // per-problem tolerances (device)
+  double* d_tol = nullptr;      // per-problem tolerances (device, FP64 group order)
+  std::vector<double> tolq;     // its host staging
   void* d_rhs = nullptr;        // explicit-part role of theta steps (theta < 1)
   std::vector<double> tolv;     // the same on the host
   // what the batch was built for (a later call with the same key reuses it)
@@ -355,6 +443,13 @@ static fl_status upload_vec(Batch& bt, const void* h, size_t bytes, void** d) {
   return FL_OK;
 }
 
+// A per-problem vector (problem order) in the device arrays' group order.
+template <typename V> static std::vector<V> in_group_order(const BatchT& t, const std::vector<V>& v) {
+  std::vector<V> out(v.size());
+  for (size_t q = 0; q < t.order.size(); ++q) out[q] = v[t.order[q]];
+  return out;
+}
+
 // Device arrays of the launch geometry and of the Prob roles for one precision.
 template <typename T> static fl_status build_roles(Batch& bt, BatchT& t, std::vector<ProbBufs>& bufs, Scalars* sc,
                                                    double* part, const std::vector<double>& s0,
@@ -379,10 +474,10 @@ template <typename T> static fl_status build_roles(Batch& bt, BatchT& t, std::ve
     res[p].out = pb.r;
   }
   STCHK((bt_setup<T>(t, bt.desc, iter)));
-  STCHK(upload_vec(bt, iter.data(), np * sizeof(Prob), &t.d_iter));
-  STCHK(upload_vec(bt, iter_nopc.data(), np * sizeof(Prob), &t.d_iter_nopc));
-  STCHK(upload_vec(bt, pc0.data(), np * sizeof(Prob), &t.d_pc0));
-  STCHK(upload_vec(bt, res.data(), np * sizeof(Prob), &t.d_res));
+  STCHK(upload_vec(bt, in_group_order(t, iter).data(), np * sizeof(Prob), &t.d_iter));
+  STCHK(upload_vec(bt, in_group_order(t, iter_nopc).data(), np * sizeof(Prob), &t.d_iter_nopc));
+  STCHK(upload_vec(bt, in_group_order(t, pc0).data(), np * sizeof(Prob), &t.d_pc0));
+  STCHK(upload_vec(bt, in_group_order(t, res).data(), np * sizeof(Prob), &t.d_res));
   t.h_iter = iter;
   t.h_res = res;
   STCHK(upload_vec(bt, t.cg.data(), t.cg.size() * sizeof(ColGeom), &t.d_cg));
@@ -522,6 +617,7 @@ static fl_status make_batch(Batch& bt, int nprob, const fl_op* ops, const uint8_
   if (hipHostMalloc((void**)&bt.hpin, nprob * sizeof(Scalars)) != hipSuccess) return fail(FL_E_NOMEM, "pinned");
   STCHK(bt.alloc((void**)&bt.d_tol, nprob * sizeof(double)));
   bt.tolv.assign(nprob, 0.0);
+  bt.tolq.assign(nprob, 0.0);
   bt.kmasks.assign(nprob, nullptr);
   if (masks)
     for (int p = 0; p < nprob; ++p) bt.kmasks[p] = masks[p];
@@ -592,17 +688,25 @@ static fl_status batch_solve(Batch& bt, const double* tols, const fl_solve_opts*
   const int maxit = (o && o->maxit > 0) ? o->maxit : std::max(1000, (int)(10 * std::sqrt((double)Nmax)));
   out.assign(np, fl_info{});
   for (int p = 0; p < np; ++p) bt.tolv[p] = tols[p];
-  HIPCHK(hipMemcpyAsync(bt.d_tol, bt.tolv.data(), np * sizeof(double), hipMemcpyHostToDevice, s));
-  // ff and initial residuals
+  // group order of the FP64 arrays (the only role k_init_b reads them with)
+  for (int q = 0; q < np; ++q) bt.tolq[q] = tols[bt.t64.order[q]];
+  HIPCHK(hipMemcpyAsync(bt.d_tol, bt.tolq.data(), np * sizeof(double), hipMemcpyHostToDevice, s));
+  // ff (one launch over all problems: aux of the residual role is f) and the
+  // initial residuals; the host reads ff with the next scalar read
   for (int p = 0; p < np; ++p) {
     ProbBufs& b = bt.b64[p];
     const long N = bt.ops[p]->N;
     if (!use_x0) LAUNCH(k_fill<double>, dim3(nblocks_vec(N)), dim3(256), 0, s, (double*)b.x, 0.0, N);
-    STCHK(per_dot<double>(bt, bt.t64, p, b.f, b.f, FIN_FF, s));
   }
-  auto residuals = [&](std::vector<double>& rr) -> fl_status {
+  const dim3 gv(vmax(bt.t64.nb_upd), np);
+  LAUNCH((k_dot_b<double, DOT_AUX>), gv, dim3(256), 0, s, (const Prob*)bt.t64.d_res, (int)S_DOT,
+         (const long*)bt.t64.d_N, (const int*)bt.t64.d_nb_upd);
+  LAUNCH(k_finalize_b<>, dim3(1, np), dim3(256), 0, s, (const Prob*)bt.t64.d_iter, (int)S_DOT, (int)FIN_FF);
+  // r = f - A x and r.r on the device; read: also bring every scalar to the host
+  auto residuals = [&](std::vector<double>& rr, bool read) -> fl_status {
     STCHK(bt_resid<double>(bt.t64, (const Prob*)bt.t64.d_res, s));
-    for (int p = 0; p < np; ++p) LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, bt.t64.h_iter[p], (int)S_DOT, (int)FIN_RR);
+    LAUNCH(k_finalize_b<>, dim3(1, np), dim3(256), 0, s, (const Prob*)bt.t64.d_iter, (int)S_DOT, (int)FIN_RR);
+    if (!read) return FL_OK;
     STCHK(read_all(bt, bt.sc64, s));
     rr.resize(np);
     for (int p = 0; p < np; ++p) rr[p] = bt.hsc[p].rr;
@@ -612,16 +716,15 @@ static fl_status batch_solve(Batch& bt, const double* tols, const fl_solve_opts*
   // the mixed loop ends with the true FP64 residuals of the returned x in rr:
   // its last evaluation precedes every exit, and finished problems keep x
   bool have_final = false;
-  STCHK(read_all(bt, bt.sc64, s));
-  for (int p = 0; p < np; ++p) ff[p] = bt.hsc[p].ff;
   if (!mixed) {
     if (use_x0) {
-      STCHK(residuals(rr));
+      STCHK(residuals(rr, false));  // the Krylov start takes r.r on the device
     } else {
       for (int p = 0; p < np; ++p)
         HIPCHK(hipMemcpyAsync(bt.b64[p].r, bt.b64[p].f, bt.ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     STCHK(bt_krylov<double>(bt, bt.t64, bt.sc64, pc, 0.0, bt.d_tol, maxit, use_x0, graph, poll, s, 0));
+    for (int p = 0; p < np; ++p) ff[p] = bt.hsc[p].ff;
     for (int p = 0; p < np; ++p) {
       const Scalars& sc = bt.hsc[p];
       out[p].iters = std::max(sc.itc[0], sc.itc[1]);
@@ -635,7 +738,9 @@ static fl_status batch_solve(Batch& bt, const double* tols, const fl_solve_opts*
     std::vector<char> active(np, 1);
     for (int p = 0; p < np; ++p) out[p].status = FL_E_NOCONV;
     for (int outer = 0;; ++outer) {
-      STCHK(residuals(rr));
+      STCHK(residuals(rr, true));
+      if (outer == 0)
+        for (int p = 0; p < np; ++p) ff[p] = bt.hsc[p].ff;
       bool any = false;
       for (int p = 0; p < np; ++p) {
         if (!active[p]) continue;
@@ -679,10 +784,10 @@ static fl_status batch_solve(Batch& bt, const double* tols, const fl_solve_opts*
     if (!bt.d_true) {  // residual role writing q, built once per batch
       std::vector<Prob> tr = bt.t64.h_res;
       for (int p = 0; p < np; ++p) tr[p].out = bt.b64[p].q;
-      STCHK(upload_vec(bt, tr.data(), np * sizeof(Prob), &bt.d_true));
+      STCHK(upload_vec(bt, in_group_order(bt.t64, tr).data(), np * sizeof(Prob), &bt.d_true));
     }
     STCHK(bt_resid<double>(bt.t64, (const Prob*)bt.d_true, s));
-    for (int p = 0; p < np; ++p) LAUNCH(k_finalize<>, dim3(1), dim3(256), 0, s, bt.t64.h_iter[p], (int)S_DOT, (int)FIN_RR);
+    LAUNCH(k_finalize_b<>, dim3(1, np), dim3(256), 0, s, (const Prob*)bt.t64.d_iter, (int)S_DOT, (int)FIN_RR);
     STCHK(read_all(bt, bt.sc64, s));
     for (int p = 0; p < np; ++p) out[p].rel_res_true = ff[p] > 0 ? std::sqrt(bt.hsc[p].rr / ff[p]) : 0.0;
   }
@@ -756,7 +861,7 @@ fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const d
       rhs[p].in = bt.b64[p].x;
       rhs[p].out = bt.b64[p].f;
     }
-    STCHK(upload_vec(bt, rhs.data(), nprob * sizeof(Prob), &d_rhs));
+    STCHK(upload_vec(bt, in_group_order(bt.t64, rhs).data(), nprob * sizeof(Prob), &d_rhs));
     bt.d_rhs = d_rhs;
   }
   for (int p = 0; p < nprob; ++p) {
@@ -768,9 +873,9 @@ fl_status fl_step_batched(int nprob, const fl_op* ops, double* const* u, const d
     // right-hand side b = u^k (backward Euler) or (I - (1-theta) dt M) u^k; warm start x = u^k
     if (theta < 1.0) {
       STCHK(bt_apply_plain<double>(bt.t64, (const Prob*)d_rhs, s));
-    } else {
-      for (int p = 0; p < nprob; ++p)
-        HIPCHK(hipMemcpyAsync(bt.b64[p].f, bt.b64[p].x, ops[p]->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {  // f = x for every problem, one launch (in and aux of the residual role)
+      LAUNCH(k_copy_in_aux_b<double>, dim3(vmax(bt.t64.nb_upd), nprob), dim3(256), 0, s,
+             (const Prob*)bt.t64.d_res, (const long*)bt.t64.d_N, (const int*)bt.t64.d_nb_upd);
     }
     std::vector<fl_info> out;
     STCHK(batch_solve(bt, tols.data(), opts, 1, out));

@@ -1122,6 +1122,29 @@ template <typename T> __global__ FL_BOUNDS void k_dot(Prob pb, const void* a, co
 template <int = 0> __global__ FL_BOUNDS void k_finalize(Prob pb, int site, int target) {
   finalize_body(pb, site, target);
 }
+// Batched forms over a device Prob array (blockIdx.y = problem): the total of
+// a site into a scalar slot; r.r (or aux.aux) partials; aux = in (the
+// right-hand side of a backward-Euler step from the state).
+template <int = 0> __global__ FL_BOUNDS void k_finalize_b(const Prob* pbs, int site, int target) {
+  finalize_body(pbs[blockIdx.y], site, target);
+}
+enum { DOT_AUX = 0, DOT_R = 1 };
+template <typename T, int WHICH>
+__global__ FL_BOUNDS void k_dot_b(const Prob* pbs, int site, const long* ns, const int* nb) {
+  if ((int)blockIdx.x >= nb[blockIdx.y]) return;
+  const Prob& pb = pbs[blockIdx.y];
+  const void* a = WHICH == DOT_AUX ? pb.aux : pb.r;
+  dot_body<T>(pb, a, a, site, ns[blockIdx.y], nb[blockIdx.y], blockIdx.x);
+}
+template <typename T> __global__ FL_BOUNDS void k_copy_in_aux_b(const Prob* pbs, const long* ns, const int* nb) {
+  if ((int)blockIdx.x >= nb[blockIdx.y]) return;
+  const Prob& pb = pbs[blockIdx.y];
+  const long n = ns[blockIdx.y];
+  const T* src = (const T*)pb.in;
+  T* dst = (T*)pb.aux;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)nb[blockIdx.y] * blockDim.x)
+    dst[i] = src[i];
+}
 template <typename T> __global__ FL_BOUNDS void k_update(Prob pb, Iter it, long n) {
   update_body<T>(pb, it, n, gridDim.x, blockIdx.x);
 }
