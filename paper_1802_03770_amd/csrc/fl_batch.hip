@@ -370,8 +370,9 @@ struct Batch {
   Scalars* hpin = nullptr;
   int pc = FL_PC_FD;
   void* d_true = nullptr;
-  hipGraphExec_t g[2] = {nullptr, nullptr};
+  hipGraphExec_t g[2] = {nullptr, nullptr}, g2[2] = {nullptr, nullptr};  // poll and 2 iterations
   int gpc[2] = {-1, -1}, gpoll[2] = {0, 0};
+  int last_its[2] = {0, 0};  // iterations of the last solve per graph slot (all problems)
   double* d_tol = nullptr;      // per-problem tolerances (device, FP64 group order)
   std::vector<double> tolq;     // its host staging
   void* d_rhs = nullptr;        // explicit-part role of theta steps (theta < 1)
@@ -384,6 +385,7 @@ struct Batch {
   ~Batch() {
     for (void* p : owned) (void)hipFree(p);
     for (auto& e : g) if (e) (void)hipGraphExecDestroy(e);
+    for (auto& e : g2) if (e) (void)hipGraphExecDestroy(e);
     if (hpin) (void)hipHostFree(hpin);
   }
   fl_status alloc(void** p, size_t bytes) {
@@ -532,22 +534,46 @@ template <typename T> static fl_status bt_krylov(Batch& bt, BatchT& t, Scalars* 
   if (poll & 1) ++poll;
   STCHK(bt_iteration<T>(t, pc, 0, s));
   bool use_graph = graph && s != nullptr;
-  if (use_graph && (!bt.g[gslot] || bt.gpc[gslot] != pc || bt.gpoll[gslot] != poll)) {
-    if (bt.g[gslot]) (void)hipGraphExecDestroy(bt.g[gslot]);
-    bt.g[gslot] = nullptr;
+  auto capture = [&](int len, hipGraphExec_t* ex) -> fl_status {
     hipGraph_t g;
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     fl_status st = FL_OK;
-    for (int j = 0; j < poll && st == FL_OK; ++j) st = bt_iteration<T>(t, pc, 1 + j, s);
+    for (int j = 0; j < len && st == FL_OK; ++j) st = bt_iteration<T>(t, pc, 1 + j, s);
     hipError_t e = hipStreamEndCapture(s, &g);
     if (st != FL_OK) return st;
     HIPCHK(e);
-    HIPCHK(hipGraphInstantiate(&bt.g[gslot], g, nullptr, nullptr, 0));
+    const hipError_t ei = hipGraphInstantiate(ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
+    HIPCHK(ei);
+    return FL_OK;
+  };
+  if (use_graph && (!bt.g[gslot] || bt.gpc[gslot] != pc || bt.gpoll[gslot] != poll)) {
+    for (hipGraphExec_t* e : {&bt.g[gslot], &bt.g2[gslot]})
+      if (*e) {
+        (void)hipGraphExecDestroy(*e);
+        *e = nullptr;
+      }
+    STCHK(capture(poll, &bt.g[gslot]));
     bt.gpc[gslot] = pc;
     bt.gpoll[gslot] = poll;
+    bt.last_its[gslot] = 0;
   }
+  // The first stretch after iteration 0 covers the iteration count of the
+  // previous solve of this batch (time steps repeat it closely) with graphs of
+  // `poll` and of 2 iterations launched back to back: each iteration of a
+  // batch past its stop still dispatches every pass of every group, so
+  // stopping near the count saves those no-op launches.
   int k = 1;
+  if (use_graph && bt.last_its[gslot] > 1) {
+    int left = std::min(bt.last_its[gslot] - 1, maxit);
+    if (left % poll != 0 && !bt.g2[gslot] && poll > 2) STCHK(capture(2, &bt.g2[gslot]));
+    while (left > 0) {
+      const bool whole = left >= poll || poll == 2;
+      HIPCHK(hipGraphLaunch(whole ? bt.g[gslot] : bt.g2[gslot], s));
+      left -= whole ? poll : 2;
+      k += whole ? poll : 2;
+    }
+  }
   for (;;) {
     STCHK(read_all(bt, dsc, s));
     bool all = true;
@@ -556,7 +582,10 @@ template <typename T> static fl_status bt_krylov(Batch& bt, BatchT& t, Scalars* 
       all = all && sc.done;
       mx = std::max(mx, std::max(sc.itc[0], sc.itc[1]));
     }
-    if (all) break;
+    if (all) {
+      bt.last_its[gslot] = mx;
+      break;
+    }
     if (mx >= maxit + 2 * poll) return fail(FL_E_HIP, "batched iteration bookkeeping lost");
     if (use_graph) {
       HIPCHK(hipGraphLaunch(bt.g[gslot], s));
