@@ -77,8 +77,10 @@ typedef struct {
   double delta_over_h;  /* window radius c in grid points (Sec. 4.1 uses 20); <= 0 -> 20 */
   int dst_mode;         /* sine-transform plan per axis: 0 = autotune (time the preconditioner with both
                            forms when the op is built and keep the faster, per precision); 1 = direct odd
-                           extension of length 2(n+1) when it factors over radices <= 43, else chirp-z;
-                           2 = chirp-z with a 5-smooth length >= 2n-1 */
+                           extension of length 2(n+1) when it factors over radices <= 43, the prime form
+                           when n + 1 = 257 (Rader's identity: a real DFT of length 257 as a cyclic
+                           convolution of length 256), else chirp-z; 2 = chirp-z with a 5-smooth length
+                           >= 2n-1 */
   int col_lanes;        /* symbol column pass at lengths 1024 and 2048: 0 = autotune, -1 = run-time plan,
                            64, 128 or 256 (length 2048) = lanes per column of the specialised kernel */
   int sine_col_lanes;   /* sine column pass at direct length 2050: 0 = autotune, -1 = plan, 128 = forced */
@@ -130,7 +132,7 @@ fl_status fl_op_constants(fl_op op, double out[8]);
 fl_status fl_op_padded(fl_op op, int64_t* out);
 
 /* Plans chosen for the op (16 entries), per precision p (0 FP64, 1 FP32):
- * out[3 p + a] = 1 (direct) or 2 (chirp-z) sine transform along axis a < d,
+ * out[3 p + a] = 1 (direct), 2 (chirp-z) or 3 (prime form) sine transform along axis a < d,
  * out[6 + 3 p + a] = its FFT length, out[12 + p] = lanes per column of the
  * symbol column pass (0: run-time plan; 64 or 128: specialised kernel),
  * out[14 + p] = lanes per FFT line of the sine column pass (0: plan; 128). */

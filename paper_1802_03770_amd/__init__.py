@@ -187,7 +187,7 @@ class Op:
 
     def plan(self):
         """Plans: {"f64"/"f32": [(sine form, length) per axis], "col_lanes": lanes per column of the symbol pass};
-        sine form 1 direct, 2 chirp-z; col lanes 0 = run-time plan."""
+        sine form 1 direct, 2 chirp-z, 3 prime form (n + 1 = 257); col lanes 0 = run-time plan."""
         out = (ctypes.c_int64 * 16)()
         _check(load().fl_op_plan(self._h, out))
         plan = {p: [(int(out[3 * i + a]), int(out[6 + 3 * i + a])) for a in range(self.d)]

@@ -249,6 +249,7 @@ static fl_status bt_dst_rows(int lf, dim3 g, size_t sm, hipStream_t s, const Pro
     case 770: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, 770>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
     case 258: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, 258>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
     case 130: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, 130>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
+    case kRaderLF: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, kRaderLF>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
     case -512: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, -512>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
     case -256: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, -256>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
     case -1024: LAUNCH((k_dst_rows_b<T, DPRO, DEPI, -1024>), g, dim3(256), sm, s, pbs, it, chk, nb); break;
@@ -265,6 +266,7 @@ static fl_status bt_dst_cols(int lf, dim3 g, size_t sm, hipStream_t s, const Pro
     case 770: LAUNCH((k_dst_cols_b<T, SCALE, 770>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
     case 258: LAUNCH((k_dst_cols_b<T, SCALE, 258>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
     case 130: LAUNCH((k_dst_cols_b<T, SCALE, 130>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
+    case kRaderLF: LAUNCH((k_dst_cols_b<T, SCALE, kRaderLF>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
     case -512: LAUNCH((k_dst_cols_b<T, SCALE, -512>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
     case -256: LAUNCH((k_dst_cols_b<T, SCALE, -256>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
     case -1024: LAUNCH((k_dst_cols_b<T, SCALE, -1024>), g, dim3(256), sm, s, pbs, dgs, chk, nb); break;
@@ -279,8 +281,8 @@ template <typename T, int DPRO, int DEPI> fl_status bt_precond(BatchT& bt, const
   const DGeom* dg = (const DGeom*)bt.d_dg;
   if (d == 1) {
     for (const BatchGroup& G : bt.groups)
-      LAUNCH((k_dst_rows_b<T, DPRO, DEPI>), dim3(G.nb_dstrow, G.gn), dim3(256), G.sm_dstrow, s, pfirst + G.g0, it,
-             chk, (const int*)bt.d_nb_dstrow + G.g0);
+      STCHK((bt_dst_rows<T, DPRO, DEPI>(G.lf_row, dim3(G.nb_dstrow, G.gn), G.sm_dstrow, s, pfirst + G.g0, it, chk,
+                                         (const int*)bt.d_nb_dstrow + G.g0)));
     return FL_OK;
   }
   for (const BatchGroup& G : bt.groups)

@@ -483,6 +483,91 @@ __device__ __forceinline__ void fft_fixed(Line<T> buf, Line<T> aux, const cx<T>*
   cstages<T, L, c_fixed_tpl(L), INV, 0, 1>(buf, aux, tw, lane);
 }
 
+// Prime form of a packed pair, N = n + 1 an odd prime with N - 1 = RL (the FFT
+// length; lanes c_fixed_tpl(RL) <= 64).  In: buf[k] = (x_a[k], x_b[k]) for
+// k = 1..n.  Out: buf[k] = (S_a[k], S_b[k]), S[k] = sum_j x_j sin(pi j k / N);
+// buf2 is scratch.  Three steps:
+//  1. y_j = s_j (x_j + x_{N-j}) + (x_j - x_{N-j}) / 2, s_j = sin(pi j / N), for
+//     both members at once; the real DFT Y of y then has -Im Y_k = S_{2k} and
+//     Re Y_k = S_{2k+1} - S_{2k-1} (with S_{-1} = -S_1).
+//  2. The DFT of length N of y_a + i y_b by Rader's identity: with a generator
+//     g of the units mod N, Z_{g^q} = sum_p y_{g^-p} b_{q-p}, b_m = e^{-2 pi i
+//     g^m / N}, a cyclic convolution of length RL (y_0 = 0), done as an FFT,
+//     a product with the table bhat = FFT(b) / RL, and an inverse FFT; Z_0 is
+//     the first output of the forward FFT.  The pair (j, N - j) sits at
+//     positions (p, p + RL/2) since g^(RL/2) = -1 mod N.
+//  3. Y_a, Y_b from Z_k and Z_{N-k}; the odd outputs are a running sum of
+//     Re Y over k, taken per lane over a run of consecutive k and then across
+//     the lanes of the line with wavefront shuffles.
+// Tables: gi = int[RL/2] g^-p mod N, then int[RL/2 + 1] log_g k (entry 0
+// unused); sp = T[RL/2] s_{g^-p}; bh = cx<T>[RL]; tw = the FFT's roots of unity.
+template <typename T, int RL>
+__device__ __forceinline__ void rader_sine(Line<T> buf, Line<T> buf2, int n, const int* __restrict__ gi,
+                                           const T* __restrict__ sp, const cx<T>* __restrict__ bh,
+                                           const cx<T>* __restrict__ tw, int lane) {
+  constexpr int N = RL + 1, HALF = RL / 2, TPL = c_fixed_tpl(RL);
+  static_assert(TPL <= 64, "the running sum crosses lanes by wavefront shuffles");
+  const int* lg = gi + HALF;
+  for (int p = lane; p < HALF; p += TPL) {
+    const int j = gi[p];
+    const T sj = sp[p];
+    const cx<T> u = buf[j], w = buf[N - j];
+    const cx<T> a = cadd(u, w), h = cscale(csub(u, w), (T)0.5);
+    buf2[p] = {sj * a.x + h.x, sj * a.y + h.y};
+    buf2[p + HALF] = {sj * a.x - h.x, sj * a.y - h.y};
+  }
+  __syncthreads();
+  fft_fixed<T, RL, false>(buf2, buf2, tw, lane);
+  for (int q = lane; q < RL; q += TPL) {
+    const cx<T> v = buf2[q];
+    if (q == 0) buf[0] = v;  // Z_0 (slot 0 of the input line is free)
+    buf2[q] = cmul(v, bh[q]);
+  }
+  __syncthreads();
+  fft_fixed<T, RL, true>(buf2, buf2, tw, lane);
+  constexpr int C = (HALF + 1 + TPL - 1) / TPL;  // consecutive k per lane
+  const cx<T> z0 = buf[0];
+  T ra[C], rb[C], sa = 0, sb = 0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int k = lane * C + c;
+    T Ra = 0, Rb = 0;
+    if (k <= HALF) {
+      cx<T> P = z0, Q = z0;
+      if (k > 0) {
+        const int q = lg[k];
+        P = buf2[q];
+        Q = buf2[(q + HALF) % RL];
+      }
+      Ra = (T)0.5 * (P.x + Q.x);
+      Rb = (T)0.5 * (P.y + Q.y);
+      if (k > 0 && 2 * k <= n) buf[2 * k] = {(T)0.5 * (Q.y - P.y), (T)0.5 * (P.x - Q.x)};
+    }
+    sa += Ra;
+    sb += Rb;
+    ra[c] = sa;
+    rb[c] = sb;
+  }
+  T ea = sa, eb = sb;  // inclusive scan of the lane totals over the line
+#pragma unroll
+  for (int o = 1; o < TPL; o <<= 1) {
+    const T ta = __shfl_up(ea, o, TPL), tb = __shfl_up(eb, o, TPL);
+    if (lane >= o) {
+      ea += ta;
+      eb += tb;
+    }
+  }
+  ea -= sa + (T)0.5 * z0.x;  // exclusive, less R_0 / 2 (S_1 = R_0 / 2)
+  eb -= sb + (T)0.5 * z0.y;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int k = lane * C + c;
+    if (2 * k + 1 <= n) buf[2 * k + 1] = {ea + ra[c], eb + rb[c]};
+  }
+  __syncthreads();
+}
+
+
 // Dispatch to a specialisation; false when the plan has none.
 template <typename T, bool INV>
 __device__ __forceinline__ bool fft_try_fixed(Line<T> buf, const FFTPlan& pl, int lane) {

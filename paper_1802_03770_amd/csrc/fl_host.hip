@@ -112,6 +112,55 @@ template <typename T> static std::vector<cx<T>> host_twiddles(int L) {
   return t;
 }
 
+// Tables of the prime-form sine transform, N = n + 1 prime (Rader's identity
+// with a generator g of the units mod N; an FFT of length N - 1):
+//   rtab  = int[(N-1)/2] g^-p mod N, then int[(N-1)/2 + 1] with entry k = log_g k
+//   chirp = T[(N-1)/2] sin(pi g^-p / N)
+//   bhat  = cx<T>[N-1] = DFT_{N-1}(b) / (N-1), b_m = e^{-2 pi i g^m / N}
+template <typename T> static fl_status rader_tables(fl_op op, Axis& A, int N) {
+  const int RL = N - 1, HALF = RL / 2;
+  int g = 2;
+  for (;; ++g) {  // smallest generator: g^(RL/q) != 1 for every prime q | RL
+    bool gen = true;
+    for (int q = 2, m = RL; q <= m; ++q) {
+      if (m % q) continue;
+      while (m % q == 0) m /= q;
+      long e = 1, b = g;
+      for (int k = RL / q; k; k >>= 1, b = b * b % N)
+        if (k & 1) e = e * b % N;
+      if (e == 1) gen = false;
+    }
+    if (gen) break;
+  }
+  std::vector<long> pw(RL);  // g^m mod N
+  pw[0] = 1;
+  for (int m = 1; m < RL; ++m) pw[m] = pw[m - 1] * g % N;
+  std::vector<int> tab(HALF + HALF + 1, 0);
+  std::vector<T> sp(HALF);
+  for (int p = 0; p < HALF; ++p) {
+    const long j = pw[(RL - p) % RL];  // g^-p
+    tab[p] = (int)j;
+    sp[p] = (T)sinl(kPiL * (long double)j / (long double)N);
+  }
+  for (int q = 0; q < RL; ++q)
+    if (pw[q] <= HALF) tab[HALF + pw[q]] = q;
+  std::vector<cx<T>> bh(RL);
+  for (int k = 0; k < RL; ++k) {
+    long double re = 0.0L, im = 0.0L;
+    for (int m = 0; m < RL; ++m) {
+      // b_m e^{-2 pi i m k / RL} = e^{-2 pi i (g^m / N + m k / RL)}
+      const long double ph = 2.0L * kPiL * ((long double)pw[m] / N + (long double)((long)m * k % RL) / RL);
+      re += cosl(ph);
+      im -= sinl(ph);
+    }
+    bh[k] = {(T)(re / RL), (T)(im / RL)};
+  }
+  STCHK(upload(op, tab, &A.rtab));
+  STCHK(upload(op, sp, &A.chirp));
+  STCHK(upload(op, bh, &A.bhat));
+  return FL_OK;
+}
+
 template <typename T> static fl_status build_axis(fl_op op, int a, int form) {
   Axis& A = op->ax[tix<T>()][a];
   const int n = op->n[a];
@@ -124,11 +173,18 @@ template <typename T> static fl_status build_axis(fl_op op, int a, int form) {
   STCHK(upload(op, host_twiddles<T>(A.P), &A.fft.tw));
   if (op->apply_only) return FL_OK;  // no sine transforms on application-only grids
   // sine transform: direct (odd extension of length 2(n+1), two lines per FFT
-  // line) when 2(n+1) factors over the wide radix set, else the chirp-z identity
+  // line) when 2(n+1) factors over the wide radix set; the prime form (two lines
+  // per FFT line, Rader's identity with an FFT of length 256) when n + 1 = 257;
+  // else the chirp-z identity
   A.dst_direct = (form != 2 && make_radices(2 * (n + 1), A.dst, true)) ? 1 : 0;
-  op->dst_form[tix<T>()][a] = A.dst_direct ? 1 : 2;
-  const int Lb = A.dst_direct ? 2 * (n + 1) : smooth_at_least(2 * n - 1);
-  if (!A.dst_direct && !make_radices(Lb, A.dst)) return fail(FL_E_UNSUPPORTED, "sine transform length");
+  A.dst_rader = (form != 2 && !A.dst_direct && n + 1 == kRaderLF) ? 1 : 0;
+  if (A.dst_rader) A.dst_direct = 1;
+  op->dst_form[tix<T>()][a] = A.dst_rader ? 3 : (A.dst_direct ? 1 : 2);
+  const int Lb = A.dst_rader ? kRaderLF - 1 : (A.dst_direct ? 2 * (n + 1) : smooth_at_least(2 * n - 1));
+  if ((A.dst_rader || !A.dst_direct) && !make_radices(Lb, A.dst))
+    return fail(FL_E_UNSUPPORTED, "sine transform length");
+  if (A.dst_rader && !(A.dst.fixed && A.dst.tpl == c_fixed_tpl(Lb)))
+    return fail(FL_E_UNSUPPORTED, "prime-form sine transform needs the compile-time FFT of length 256");
   STCHK(upload(op, host_twiddles<T>(Lb), &A.dst.tw));
   const long N1 = n + 1;
   std::vector<T> ev(n);
@@ -137,6 +193,7 @@ template <typename T> static fl_status build_axis(fl_op op, int a, int form) {
     ev[k] = (T)(4.0L * sn * sn);
   }
   STCHK(upload(op, ev, &A.eig));
+  if (A.dst_rader) return rader_tables<T>(op, A, n + 1);
   if (A.dst_direct) return FL_OK;
   std::vector<cx<T>> ch(n + 1);
   std::vector<std::complex<long double>> chl(n + 1);
@@ -263,7 +320,7 @@ template <typename T> static fl_status autotune_dcol(fl_op op) {
 
 template <typename T> static fl_status autotune_dst(fl_op op) {
   bool any = false;
-  for (int a = 0; a < op->d; ++a) any = any || op->dst_form[tix<T>()][a] == 1;
+  for (int a = 0; a < op->d; ++a) any = any || op->dst_form[tix<T>()][a] == 1 || op->dst_form[tix<T>()][a] == 3;
   if (!any) return FL_OK;
   double t_direct = 0.0, t_chirp = 0.0;
   STCHK(profile_t<T>(op, 7, 4, &t_direct));

@@ -93,7 +93,7 @@ struct fl_op_s {
   bool apply_only = false;  // an axis padded to 8192: the application only (2D)
   int col_lanes = 0;        // 0 autotune, -1 run-time plan, 64 / 128 forced
   int sine_col_lanes = 0;   // 0 autotune, -1 plan, 128 forced
-  int dst_form[2][3] = {};  // chosen per precision and axis: 1 direct, 2 chirp-z
+  int dst_form[2][3] = {};  // chosen per precision and axis: 1 direct, 2 chirp-z, 3 prime form
   int n[3] = {1, 1, 1}, P[3] = {2, 2, 2}, H[3] = {1, 1, 1};
   long N = 0, NH = 0;
   hipStream_t stream = nullptr;
@@ -140,6 +140,7 @@ inline int block_for(int) { return 256; }
 // 2(n+1) of the common grids (n = 64, 128, 384, 512, 1024), or minus the FFT
 // length of a chirp-z plan of length 256, 512 or 1024; 0 = the run-time plan.
 inline int dst_lf(const Axis& A) {
+  if (A.dst_rader) return kRaderLF;  // the prime form has no run-time version
   if (!A.dst.fixed) return 0;
   if (A.dst_direct) {
     switch (A.dst.L) {

@@ -672,6 +672,35 @@ __device__ __forceinline__ Line<T> dst_fft(Line<T> a, Line<T> b, const FFTPlan& 
   }
 }
 
+// Length code of the prime form's kernels (N = n + 1 = 257, FFT length 256);
+// odd, so it never equals a direct length 2(n+1).
+constexpr int kRaderLF = 257;
+
+// Transform of a packed pair in either two-line form: the prime form when
+// LF == kRaderLF (result in a), else the direct odd extension.
+template <typename T, int LF, int TPLF = 0>
+__device__ __forceinline__ Line<T> dst_pair(Line<T> a, Line<T> b, const Axis& A, int lane) {
+  if constexpr (LF == kRaderLF) {
+    rader_sine<T, kRaderLF - 1>(a, b, A.n, (const int*)A.rtab, (const T*)A.chirp, (const cx<T>*)A.bhat,
+                                (const cx<T>*)A.dst.tw, lane);
+    return a;
+  } else {
+    return dst_fft<T, false, LF, TPLF>(a, b, A.dst, lane);
+  }
+}
+// Element k (1..n) of a packed pair: in place in the prime form, through the
+// odd extension in the direct form.
+template <typename T, bool RAD>
+__device__ __forceinline__ void pair_put(Line<T> buf, int M, int k, T a, T b) {
+  if constexpr (RAD) buf[k] = {a, b};
+  else sine_pair_put(buf, M, k, a, b);
+}
+template <typename T, bool RAD>
+__device__ __forceinline__ cx<T> pair_get(Line<T> buf, int k) {
+  if constexpr (RAD) return buf[k];
+  else return sine_pair_get(buf, k);
+}
+
 enum { DPRO_PLAIN = 0, DPRO_UPD = 1 };
 enum { DEPI_STORE = 0, DEPI_FINAL = 1, DEPI_Z = 2 };
 
@@ -700,7 +729,9 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[pb.d - 1];
   constexpr int CL = LF < 0 ? -LF : 0;  // chirp-z FFT length of a chirp specialisation
-  const int n = A.n, Lf = CL > 0 ? CL : A.dst.L, tpl = CL > 0 ? c_fixed_tpl(CL) : A.dst.tpl;
+  constexpr bool RAD = LF == kRaderLF;   // prime form
+  const int n = A.n, Lf = RAD ? kRaderLF - 1 : (CL > 0 ? CL : A.dst.L);
+  const int tpl = RAD ? c_fixed_tpl(kRaderLF - 1) : (CL > 0 ? c_fixed_tpl(CL) : A.dst.tpl);
   const bool direct = LF > 0 ? true : (LF < 0 ? false : A.dst_direct);
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   // direct: a ping-pong pair of lines per FFT line
@@ -734,7 +765,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
     for (int i = lane; i < n; i += tpl) {
       T xa = va ? pro(ra * n + i) : (T)0;
       T xb = vb ? pro(rb * n + i) : (T)0;
-      sine_pair_put(buf, Lf, i + 1, xa, xb);
+      pair_put<T, RAD>(buf, Lf, i + 1, xa, xb);
     }
     if (lane == 0) {
       buf[0] = {0, 0};
@@ -747,7 +778,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   __syncthreads();
   Line<T> res = buf;  // line holding the transform result
   if (direct) {
-    res = dst_fft<T, false, LF>(buf, buf2, A.dst, lane);
+    res = dst_pair<T, LF>(buf, buf2, A, lane);
   } else {
     if constexpr (LF <= 0) dst_line<T, CL>(buf, A, lane, tpl);
   }
@@ -756,16 +787,16 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
     if (direct) {
       const T* tau = (const T*)pb.tau;
       for (int k = lane + 1; k <= n; k += tpl) {
-        cx<T> sv = sine_pair_get(res, k);
+        cx<T> sv = pair_get<T, RAD>(res, k);
         T e = (T)(pb.p0 + pb.p1 * pb.pcs * (double)(tau ? tau[k - 1] : ev[k - 1]));
-        sine_pair_put(res, Lf, k, pb.pmul ? sv.x * e : sv.x / e, pb.pmul ? sv.y * e : sv.y / e);
+        pair_put<T, RAD>(res, Lf, k, pb.pmul ? sv.x * e : sv.x / e, pb.pmul ? sv.y * e : sv.y / e);
       }
       if (lane == 0) {
         res[0] = {0, 0};
         res[n + 1] = {0, 0};
       }
       __syncthreads();
-      res = dst_fft<T, false, LF>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
+      res = dst_pair<T, LF>(res, res.p == buf.p ? buf2 : buf, A, lane);
     } else {
       const T* tau = (const T*)pb.tau;
       for (int k = lane; k < n; k += tpl)
@@ -782,7 +813,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
     for (int a = 0; a < pb.d; ++a) norm *= 2.0 / (pb.ax[a].n + 1);
   double acc2 = 0.0;
   for (int i = lane; i < n; i += tpl) {
-    cx<T> sv = direct ? sine_pair_get(res, i + 1) : buf[i];
+    cx<T> sv = direct ? pair_get<T, RAD>(res, i + 1) : buf[i];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       if (!(s ? vb : va)) continue;
@@ -821,8 +852,10 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   extern __shared__ __align__(16) char smem[];
   const Axis& A = pb.ax[dg.axis];
   constexpr int CL = LF < 0 ? -LF : 0;  // chirp-z FFT length of a chirp specialisation
-  const int n = A.n, Lf = LF > 0 ? LF : (CL > 0 ? CL : A.dst.L);
-  const int tpl = (LF > 0 && TPLF > 0) ? TPLF : (CL > 0 ? c_fixed_tpl(CL) : A.dst.tpl);
+  constexpr bool RAD = LF == kRaderLF;   // prime form
+  const int n = A.n, Lf = RAD ? kRaderLF - 1 : (LF > 0 ? LF : (CL > 0 ? CL : A.dst.L));
+  const int tpl = RAD ? c_fixed_tpl(kRaderLF - 1)
+                      : ((LF > 0 && TPLF > 0) ? TPLF : (CL > 0 ? c_fixed_tpl(CL) : A.dst.tpl));
   const bool direct = LF > 0 ? true : (LF < 0 ? false : A.dst_direct);
   const int GF = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   const int G = direct ? 2 * GF : GF;  // real lines per block
@@ -847,7 +880,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
       if (direct) {
         Line<T> ln = line_at<T>(smem, 2 * (j >> 1), Lf);
         ((T*)&ln[i + 1])[j & 1] = v;
-        ((T*)&ln[Lf - 1 - i])[j & 1] = -v;
+        if constexpr (!RAD) ((T*)&ln[Lf - 1 - i])[j & 1] = -v;
       } else {
         line_at<T>(smem, j, Lf)[i] = {v, 0};
       }
@@ -866,10 +899,8 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
     for (int i = i0; i < n; i += ist, bp += bst) {
       T v = 0;
       if (jv) v = *bp;
-      T* a = (T*)&ln[i + 1];
-      T* b = (T*)&ln[Lf - 1 - i];
-      a[jt & 1] = v;
-      b[jt & 1] = -v;
+      ((T*)&ln[i + 1])[jt & 1] = v;
+      if constexpr (!RAD) ((T*)&ln[Lf - 1 - i])[jt & 1] = -v;
     }
     for (int q = threadIdx.x; q < GF; q += blockDim.x) {
       Line<T> lq = line_at<T>(smem, 2 * q, Lf);
@@ -891,7 +922,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   Line<T> buf2 = line_at<T>(smem, 2 * g + 1, Lf);
   Line<T> res = buf;
   if (direct) {
-    res = dst_fft<T, false, LF, TPLF>(buf, buf2, A.dst, lane);
+    res = dst_pair<T, LF, TPLF>(buf, buf2, A, lane);
   } else {
     if constexpr (LF <= 0) dst_line<T, CL>(buf, A, lane, tpl);
   }
@@ -905,7 +936,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
       const double ta = (oka && !tau) ? eig_tail<T>(pb, ca) : 0.0;
       const double tb = (okb && !tau) ? eig_tail<T>(pb, cb) : 0.0;
       for (int k = lane + 1; k <= n; k += tpl) {
-        cx<T> sv = sine_pair_get(res, k);
+        cx<T> sv = pair_get<T, RAD>(res, k);
         double la, lb;
         if (tau) {
           la = oka ? (double)tau[(long)(k - 1) * dg.gs + ca] : 1.0;
@@ -917,14 +948,14 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
         }
         T ea = (T)(pb.p0 + pb.p1 * pb.pcs * la);
         T eb = (T)(pb.p0 + pb.p1 * pb.pcs * lb);
-        sine_pair_put(res, Lf, k, pb.pmul ? sv.x * ea : sv.x / ea, pb.pmul ? sv.y * eb : sv.y / eb);
+        pair_put<T, RAD>(res, Lf, k, pb.pmul ? sv.x * ea : sv.x / ea, pb.pmul ? sv.y * eb : sv.y / eb);
       }
       if (lane == 0) {
         res[0] = {0, 0};
         res[n + 1] = {0, 0};
       }
       __syncthreads();
-      res = dst_fft<T, false, LF, TPLF>(res, res.p == buf.p ? buf2 : buf, A.dst, lane);
+      res = dst_pair<T, LF, TPLF>(res, res.p == buf.p ? buf2 : buf, A, lane);
     } else {
       const long c = c0 + g;
       const bool ok = c < dg.gs;
@@ -947,7 +978,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
       if (j >= gv) continue;
       T v;
       if (direct) {
-        const cx<T> sv = sine_pair_get(line_at<T>(smem, 2 * (j >> 1) + rsel, Lf), i + 1);
+        const cx<T> sv = pair_get<T, RAD>(line_at<T>(smem, 2 * (j >> 1) + rsel, Lf), i + 1);
         v = (j & 1) ? sv.y : sv.x;
       } else {
         v = line_at<T>(smem, j, Lf)[i].x;
@@ -960,7 +991,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
     if (direct) {
       Line<T> ln = line_at<T>(smem, 2 * (jt >> 1) + rsel, Lf);
       for (int i = i0; i < n; i += ist, bp += bst) {
-        const cx<T> sv = sine_pair_get(ln, i + 1);
+        const cx<T> sv = pair_get<T, RAD>(ln, i + 1);
         *bp = (jt & 1) ? sv.y : sv.x;
       }
     } else {

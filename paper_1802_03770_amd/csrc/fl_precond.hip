@@ -12,6 +12,7 @@ static fl_status launch_dst_rows(int lf, dim3 g, dim3 b, size_t sm, hipStream_t 
     case 770: LAUNCH((k_dst_rows<T, DPRO, DEPI, 770>), g, b, sm, s, pb, it, chk); break;
     case 258: LAUNCH((k_dst_rows<T, DPRO, DEPI, 258>), g, b, sm, s, pb, it, chk); break;
     case 130: LAUNCH((k_dst_rows<T, DPRO, DEPI, 130>), g, b, sm, s, pb, it, chk); break;
+    case kRaderLF: LAUNCH((k_dst_rows<T, DPRO, DEPI, kRaderLF>), g, b, sm, s, pb, it, chk); break;
     case -512: LAUNCH((k_dst_rows<T, DPRO, DEPI, -512>), g, b, sm, s, pb, it, chk); break;
     case -256: LAUNCH((k_dst_rows<T, DPRO, DEPI, -256>), g, b, sm, s, pb, it, chk); break;
     case -1024: LAUNCH((k_dst_rows<T, DPRO, DEPI, -1024>), g, b, sm, s, pb, it, chk); break;
@@ -33,6 +34,7 @@ static fl_status launch_dst_cols(int lf, dim3 g, dim3 b, size_t sm, hipStream_t 
     case 770: LAUNCH((k_dst_cols<T, SCALE, 770>), g, b, sm, s, pb, dg, chk); break;
     case 258: LAUNCH((k_dst_cols<T, SCALE, 258>), g, b, sm, s, pb, dg, chk); break;
     case 130: LAUNCH((k_dst_cols<T, SCALE, 130>), g, b, sm, s, pb, dg, chk); break;
+    case kRaderLF: LAUNCH((k_dst_cols<T, SCALE, kRaderLF>), g, b, sm, s, pb, dg, chk); break;
     case -512: LAUNCH((k_dst_cols<T, SCALE, -512>), g, b, sm, s, pb, dg, chk); break;
     case -256: LAUNCH((k_dst_cols<T, SCALE, -256>), g, b, sm, s, pb, dg, chk); break;
     case -1024: LAUNCH((k_dst_cols<T, SCALE, -1024>), g, b, sm, s, pb, dg, chk); break;

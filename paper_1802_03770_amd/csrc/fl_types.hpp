@@ -29,8 +29,13 @@ struct Axis {
   int dst_direct;   // 1: two real lines packed as x + i y in an odd extension of
                     //    length 2(n+1); FFT gives -2i S_x + 2 S_y
                     // 0: one line per FFT line by the chirp-z identity
-  const void* chirp;  // cx<T>[n+1]
-  const void* bhat;   // cx<T>[Lb]  = FFT_Lb(conj chirp, circularly placed) / Lb
+  int dst_rader;    // 1 (with dst_direct = 1): the prime form, n + 1 = 257: two real
+                    //    lines packed as x + i y, transformed by a real DFT of length
+                    //    n + 1 taken by Rader's identity (FFT length 256)
+  const void* chirp;  // cx<T>[n+1]; prime form: T[128] sin(pi g^-p / (n+1))
+  const void* bhat;   // cx<T>[Lb]  = FFT_Lb(conj chirp, circularly placed) / Lb;
+                      // prime form: cx<T>[256] = FFT_256(e^{-2 pi i g^m / (n+1)}) / 256
+  const void* rtab;   // prime form: int[128] g^-p mod (n+1), int[129] log_g k
   const void* eig;    // T[n]       = 4 sin^2(pi k / (2 (n+1))), k = 1..n
 };
 

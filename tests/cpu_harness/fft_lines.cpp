@@ -8,6 +8,8 @@
 
 #include "../../paper_1802_03770_amd/csrc/fl_fft.hpp"
 thread_local std::barrier<>* g_bar;
+thread_local int g_lane;
+double* g_shfl;
 using namespace fl;
 
 template <typename T, int L> double run(bool fixed_path, bool wide) {
@@ -57,6 +59,62 @@ template <typename T, int L> double run(bool fixed_path, bool wide) {
   return err / mx;
 }
 
+// Prime-form sine transform (n = 256, N = 257) of a packed pair, against the
+// sine sums taken directly; the harness builds its own Rader tables.
+template <typename T> double run_rader() {
+  constexpr int RL = 256, N = RL + 1, HALF = RL / 2, n = N - 1, TPL = c_fixed_tpl(RL);
+  const int g = 3;  // a generator of the units mod 257 (3^128 = -1)
+  std::vector<int> pw(RL), tab(2 * HALF + 1, 0);
+  pw[0] = 1;
+  for (int m = 1; m < RL; ++m) pw[m] = pw[m - 1] * g % N;
+  for (int p = 0; p < HALF; ++p) tab[p] = pw[(RL - p) % RL];
+  for (int q = 0; q < RL; ++q)
+    if (pw[q] <= HALF) tab[HALF + pw[q]] = q;
+  std::vector<T> sp(HALF);
+  for (int p = 0; p < HALF; ++p) sp[p] = (T)std::sin(M_PI * tab[p] / N);
+  std::vector<cx<T>> bh(RL), tw(RL);
+  for (int m = 0; m < RL; ++m) tw[m] = {(T)std::cos(2 * M_PI * m / RL), (T)-std::sin(2 * M_PI * m / RL)};
+  for (int k = 0; k < RL; ++k) {
+    std::complex<double> s = 0;
+    for (int m = 0; m < RL; ++m)
+      s += std::polar(1.0, -2 * M_PI * (double)pw[m] / N) * std::polar(1.0, -2 * M_PI * double((long)m * k % RL) / RL);
+    s /= RL;
+    bh[k] = {(T)s.real(), (T)s.imag()};
+  }
+  std::vector<double> xa(n + 1), xb(n + 1);
+  for (int j = 1; j <= n; ++j) {
+    xa[j] = std::sin(0.37 * j * j + 0.1) + 0.2;
+    xb[j] = std::cos(1.7 * j) * (j % 7 - 3);
+  }
+  std::vector<cx<T>> lds(Line<T>::stride(RL)), lds2(Line<T>::stride(RL));
+  Line<T> buf{lds.data()}, buf2{lds2.data()};
+  for (int j = 1; j <= n; ++j) buf[j] = {(T)xa[j], (T)xb[j]};
+  std::vector<double> shfl(TPL);
+  g_shfl = shfl.data();
+  std::barrier<> bar(TPL);
+  std::vector<std::thread> th;
+  for (int lane = 0; lane < TPL; ++lane)
+    th.emplace_back([&, lane] {
+      g_bar = &bar;
+      g_lane = lane;
+      rader_sine<T, RL>(buf, buf2, n, tab.data(), sp.data(), bh.data(), tw.data(), lane);
+    });
+  for (auto& t : th) t.join();
+  double err = 0, mx = 0;
+  for (int k = 1; k <= n; ++k) {
+    double sa = 0, sb = 0;
+    for (int j = 1; j <= n; ++j) {
+      const double sn = std::sin(M_PI * double((long)j * k % (2 * N)) / N);
+      sa += xa[j] * sn;
+      sb += xb[j] * sn;
+    }
+    cx<T> v = buf[k];
+    err = std::max(err, std::max(std::abs(v.x - sa), std::abs(v.y - sb)));
+    mx = std::max(mx, std::max(std::abs(sa), std::abs(sb)));
+  }
+  return err / mx;
+}
+
 int main() {
   struct R { const char* name; double err, tol; };
   std::vector<R> rs = {
@@ -70,6 +128,7 @@ int main() {
       {"wide fixed 2050", run<double, 2050>(true, true), 1e-13}, {"wide generic 76", run<double, 76>(false, true), 1e-13},
       {"f32 wide fixed 2050", run<float, 2050>(true, true), 2e-6},
       {"wide generic 82", run<double, 82>(false, true), 1e-13}, {"wide generic 98", run<double, 98>(false, true), 1e-13},
+      {"prime sine 257", run_rader<double>(), 1e-13}, {"f32 prime sine 257", run_rader<float>(), 2e-6},
   };
   int bad = 0;
   for (auto& r : rs) {

@@ -4,7 +4,8 @@ The row and column FFT kernels of the application have compile-time versions
 for padded lengths 256, 512, 1024 and 2048 (grids of 128, 256, 512, 1024
 points on an axis); the sine kernels have compile-time versions for the
 chirp-z form with FFT length 256, 512 or 1024 (n = 126, 256, 508 here: 2(n+1)
-has a prime factor above 43, so the odd extension is not used).  Each shape
+has a prime factor above 43, so the odd extension is not used) and for the
+prime form of n = 256 (n + 1 = 257 prime: Rader's identity, FFT length 256).  Each shape
 below puts such an axis last (row passes), first (symbol / scaled sine column
 pass) or in the middle of a 3D grid (forward / inverse column passes and the
 unscaled sine column pass).  The batched cases give every member the same
@@ -68,15 +69,20 @@ PRECOND_SHAPES = [(3, 4, 256), (256, 3, 4), (4, 256, 3), (126, 5), (5, 126), (3,
 
 
 @pytest.mark.parametrize("n", PRECOND_SHAPES)
-def test_precond_specialised_chirp_lengths(n):
-    _say("precond specialised", n)
+@pytest.mark.parametrize("mode", [2, 1])
+def test_precond_specialised_chirp_lengths(n, mode):
+    # mode 2: every axis in the chirp-z form; mode 1: n = 256 in the prime form
+    # (n + 1 = 257, Rader's identity with an FFT of length 256), 126 and 508
+    # still chirp-z (2(n+1) = 2 * 127, 2 * 509)
+    _say("precond specialised", n, mode)
     fl = _fl()
     d, alpha, h = len(n), 0.9, 2.0 / (max(n) + 1)
-    op = fl.Op(d, alpha, h, n)
+    op = fl.Op(d, alpha, h, n, dst_mode=mode)
     forms = op.plan()
     for a, k in enumerate(n):
         if k in (126, 256, 508):
-            assert forms["f64"][a][0] == 2 and forms["f32"][a][0] == 2, forms  # chirp-z form
+            want = (3, 256) if (mode == 1 and k == 256) else (2, {126: 256, 256: 512, 508: 1024}[k])
+            assert tuple(forms["f64"][a]) == want and tuple(forms["f32"][a]) == want, forms
     r = white_noise(n, 22)
     for shift in ((0.0, 1.0), (1.0, 0.01)):
         want = PC.apply_inverse(r, PC.pc_scale(d, alpha, h), *shift)
@@ -90,16 +96,17 @@ def test_precond_specialised_chirp_lengths(n):
     assert _rel(got_s32, want_s) <= 2e-5
 
 
-@pytest.mark.parametrize("shape,pc,mixed", [((256, 4, 256), 1, 1), ((256, 256), 3, 0), ((6, 126, 5), 1, 0)])
-def test_batched_uniform_specialised(shape, pc, mixed):
+@pytest.mark.parametrize("shape,pc,mixed,mode", [((256, 4, 256), 1, 1, 2), ((256, 256), 3, 0, 2), ((6, 126, 5), 1, 0, 0),
+                                                 ((256, 4, 256), 1, 1, 1), ((256, 256), 3, 0, 1), ((256,), 1, 0, 1)])
+def test_batched_uniform_specialised(shape, pc, mixed, mode):
     # two right-hand sides of one operator and a third problem of the same
     # shape and another alpha: every launch takes the shared specialisation
-    _say("batched uniform", shape, pc, mixed)
+    _say("batched uniform", shape, pc, mixed, mode)
     fl = _fl()
     s = torch.cuda.Stream()
     d, h = len(shape), 2.0 / (max(shape) + 1)
-    op_a = fl.Op(d, 1.2, h, shape, stream=s)
-    op_b = fl.Op(d, 0.7, h, shape, stream=s)
+    op_a = fl.Op(d, 1.2, h, shape, stream=s, dst_mode=mode)
+    op_b = fl.Op(d, 0.7, h, shape, stream=s, dst_mode=mode)
     refs = [O.Operator(d, 1.2, h, shape), O.Operator(d, 0.7, h, shape)]
     fs = [white_noise(shape, 30), bump_field(shape[0], d, 8, 31)[0] if len(set(shape)) == 1 else
           white_noise(shape, 31), white_noise(shape, 32)]

@@ -153,11 +153,12 @@ def test_full_size_tau_sampled():
         assert abs(got[k0, k1] - want) <= 1e-11 * abs(got).max(), (k0, k1)
 
 
-@pytest.mark.parametrize("n", [(37,), (64, 64), (48, 40), (9, 10, 12), (1024,)])
+@pytest.mark.parametrize("n", [(37,), (64, 64), (48, 40), (9, 10, 12), (1024,), (256,), (256, 37), (5, 256, 7)])
 @pytest.mark.parametrize("mode", [1, 2])
 def test_precond_both_sine_plans(n, mode):
-    # the two sine-transform plans the autotuner chooses between: direct odd
-    # extension (mode 1, where 2(n+1) factors over radices <= 43) and chirp-z
+    # the sine-transform plans the autotuner chooses between: direct odd
+    # extension (mode 1, where 2(n+1) factors over radices <= 43), the prime
+    # form (mode 1, n + 1 = 257) and chirp-z
     _say("sine plan", mode, n)
     fl = _fl()
     from oracle import precond as PCO
@@ -167,6 +168,10 @@ def test_precond_both_sine_plans(n, mode):
     plan = op.plan()
     if mode == 2:
         assert all(f == 2 for f, _ in plan["f64"] + plan["f32"])
+    else:
+        for a, k in enumerate(n):
+            if k == 256:
+                assert tuple(plan["f64"][a]) == (3, 256) and tuple(plan["f32"][a]) == (3, 256), plan
     r = white_noise(n, 8)
     want = PCO.apply_inverse(r, PCO.pc_scale(d, alpha, h))
     assert _rel(op.precond(_dev(r)).cpu().numpy(), want) <= 1e-12
