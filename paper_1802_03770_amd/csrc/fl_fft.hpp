@@ -420,9 +420,29 @@ __device__ __forceinline__ void split_dispatch(int gi, Line<T> aux, Line<T> buf,
 // d_q = a_q - a_{R-q} (q = 1..H) into the auxiliary line (NB * R = L entries);
 // phase B has each lane form KG output pairs of one butterfly from them, with
 // y_k = a_0 + sum_q s_q cos(2 pi q k/R) -+ i sum_q d_q sin(2 pi q k/R).
+// Output pairs per item of a split stage: the butterflies of a group are
+// padded to whole wavefronts (NBP), so a wavefront runs one group's code per
+// round of TPL items; KG is chosen to minimise the rounds of the busiest
+// wavefront times the cost of one round (KG * H complex multiply-adds on the
+// sums and differences, plus reading the 2H + 1 of them from LDS), with at
+// most KGMAX accumulator pairs held per lane.
+__host__ __device__ constexpr int split_kg(int H, int NBP, int TPL, int KGMAX) {
+  int best = 1, bc = 1 << 30;
+  for (int kg = 1; kg <= KGMAX && kg <= H; ++kg) {
+    const int ng = (H + kg - 1) / kg, rounds = (ng * NBP + TPL - 1) / TPL;
+    const int c = rounds * (4 * kg * H + 2 * (2 * H + 1));
+    if (c < bc) {
+      bc = c;
+      best = kg;
+    }
+  }
+  return best;
+}
+
 template <typename T, int R, int L, int NS, int TPL, bool INV>
 __device__ __forceinline__ void cstage_split(Line<T> buf, Line<T> aux, const cx<T>* __restrict__ tw, int lane) {
-  constexpr int NB = L / R, H = (R - 1) / 2, KG = 4, NG = (H + KG - 1) / KG;
+  constexpr int NB = L / R, H = (R - 1) / 2, NBP = (NB + 63) / 64 * 64;
+  constexpr int KG = split_kg(H, NBP, TPL, sizeof(T) == 4 ? 10 : 5), NG = (H + KG - 1) / KG;
   constexpr int TSTEP = L / (NS * R);
   for (int t = lane; t < NB * (H + 1); t += TPL) {
     const int j = t / (H + 1), q = t % (H + 1);
@@ -453,7 +473,6 @@ __device__ __forceinline__ void cstage_split(Line<T> buf, Line<T> aux, const cx<
   // and with it the code path -- is the same for every lane of a wavefront
   // (lanes of one wavefront are consecutive lanes of one line, or whole
   // lines at the same offsets when TPL < 64).
-  constexpr int NBP = (NB + 63) / 64 * 64;
   for (int t = lane; t < NG * NBP; t += TPL) {
     const int gi = t / NBP, j = t % NBP;
     if (j < NB) {
