@@ -117,7 +117,32 @@ template <typename T> static std::vector<cx<T>> host_twiddles(int L) {
 //   rtab  = int[(N-1)/2] g^-p mod N, then int[(N-1)/2 + 1] with entry k = log_g k
 //   chirp = T[(N-1)/2] sin(pi g^-p / N)
 //   bhat  = cx<T>[N-1] = DFT_{N-1}(b) / (N-1), b_m = e^{-2 pi i g^m / N}
+template <typename T> struct RaderHost {
+  std::vector<int> tab;
+  std::vector<T> sp;
+  std::vector<cx<T>> bh;
+};
+template <typename T> static RaderHost<T> rader_host(int N);
+
+// The host tables depend on N and the precision only: computed once per
+// process (the DFT of b is N^2 long-double terms) and uploaded per op.
 template <typename T> static fl_status rader_tables(fl_op op, Axis& A, int N) {
+  static std::mutex mu;
+  static std::map<int, RaderHost<T>> cache;
+  const RaderHost<T>* h;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(N);
+    if (it == cache.end()) it = cache.emplace(N, rader_host<T>(N)).first;
+    h = &it->second;
+  }
+  STCHK(upload(op, h->tab, &A.rtab));
+  STCHK(upload(op, h->sp, &A.chirp));
+  STCHK(upload(op, h->bh, &A.bhat));
+  return FL_OK;
+}
+
+template <typename T> static RaderHost<T> rader_host(int N) {
   const int RL = N - 1, HALF = RL / 2;
   int g = 2;
   for (;; ++g) {  // smallest generator: g^(RL/q) != 1 for every prime q | RL
@@ -155,10 +180,7 @@ template <typename T> static fl_status rader_tables(fl_op op, Axis& A, int N) {
     }
     bh[k] = {(T)(re / RL), (T)(im / RL)};
   }
-  STCHK(upload(op, tab, &A.rtab));
-  STCHK(upload(op, sp, &A.chirp));
-  STCHK(upload(op, bh, &A.bhat));
-  return FL_OK;
+  return RaderHost<T>{std::move(tab), std::move(sp), std::move(bh)};
 }
 
 template <typename T> static fl_status build_axis(fl_op op, int a, int form) {
