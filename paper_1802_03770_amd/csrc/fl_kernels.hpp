@@ -368,11 +368,30 @@ __device__ __forceinline__ T load_input(const Prob& pb, long e, long nper, doubl
   }
 }
 
+// Roots of unity of a compile-time length L copied to LDS by the whole block
+// when they take at most 8 KB (lengths up to 1024 in FP32, 512 in FP64), so
+// the FFT stages read them without a round trip to memory; else the table in
+// memory.  Readable after the caller's next barrier.  Larger tables would cost
+// the long lines an occupancy step, and at 1024^2 the passes measured no gain.
+template <typename T, int L> __host__ __device__ constexpr bool tw_in_lds() {
+  return L > 0 && L * (int)sizeof(cx<T>) <= 8192;
+}
+template <typename T, int L>
+__device__ __forceinline__ const cx<T>* tw_stage(const cx<T>* tw) {
+  __shared__ cx<T> t[tw_in_lds<T, L>() ? L : 1];
+  if constexpr (tw_in_lds<T, L>()) {
+    for (int m = threadIdx.x; m < L; m += blockDim.x) t[m] = tw[m];
+    return t;
+  } else {
+    return tw;
+  }
+}
+
 // Row line FFT: LF = 0 follows the run-time plan; LF > 0 is a kernel
 // specialised for that padded length (lanes c_fixed_tpl(LF)).
 template <typename T, bool INV, int LF>
-__device__ __forceinline__ void row_fft(Line<T> buf, const FFTPlan& pl, int lane) {
-  if constexpr (LF > 0) fft_fixed<T, LF, INV>(buf, buf, (const cx<T>*)pl.tw, lane);
+__device__ __forceinline__ void row_fft(Line<T> buf, const FFTPlan& pl, const cx<T>* tw, int lane) {
+  if constexpr (LF > 0) fft_fixed<T, LF, INV>(buf, buf, tw, lane);
   else fft_line<T, INV>(buf, pl, lane);
 }
 
@@ -391,6 +410,7 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
   const long rows = nrows_of(pb), nper = nper_of(pb);
   const long ra = 2 * ((long)blk * G + g), rb = ra + 1;
   const bool va = ra < rows, vb = rb < rows;
+  const cx<T>* tw = tw_stage<T, LF>((const cx<T>*)A.fft.tw);
   for (int i = lane; i < P; i += tpl) {
     T xa = 0, xb = 0;
     if (i < n) {
@@ -400,7 +420,7 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
     buf[i] = {xa, xb};
   }
   __syncthreads();
-  row_fft<T, false, LF>(buf, A.fft, lane);
+  row_fft<T, false, LF>(buf, A.fft, tw, lane);
   cx<T>* W = (cx<T>*)pb.W1;
   for (int k = lane; k < H; k += tpl) {
     cx<T> zk = buf[k], zm = buf[(P - k) % P];
@@ -429,9 +449,9 @@ enum { COL_FWD = 0, COL_CONV = 1, COL_INV = 2 };
 // specialised for that length with TPLF lanes per line (fewer lanes than the
 // row passes use, so that a block holds several adjacent columns).
 template <typename T, bool INV, int LF, int TPLF>
-__device__ __forceinline__ void col_fft(Line<T> buf, const FFTPlan& pl, int lane) {
+__device__ __forceinline__ void col_fft(Line<T> buf, const FFTPlan& pl, const cx<T>* tw, int lane) {
   if constexpr (LF > 0)
-    cstages<T, LF, TPLF, INV, 0, 1>(buf, buf, (const cx<T>*)pl.tw, lane);
+    cstages<T, LF, TPLF, INV, 0, 1>(buf, buf, tw, lane);
   else
     fft_line<T, INV>(buf, pl, lane);
 }
@@ -458,6 +478,7 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
   const int jt = threadIdx.x % G, i0 = threadIdx.x / G;
   const bool jv = jt < gv;
   Line<T> lnt = line_at<T>(smem, jt, L);
+  const cx<T>* tw = tw_stage<T, LF>((const cx<T>*)A.fft.tw);  // read after the barrier below
   {
     const cx<T>* sp = src + (long)i0 * cg.ein + jt;
     const long sst = (long)tpl * cg.ein;
@@ -470,7 +491,7 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
   }
   __syncthreads();
   Line<T> buf = line_at<T>(smem, g, L);
-  col_fft<T, MODE == COL_INV, LF, TPLF>(buf, A.fft, lane);
+  col_fft<T, MODE == COL_INV, LF, TPLF>(buf, A.fft, tw, lane);
   if (MODE == COL_CONV) {
     // symbol s0 + s1 lambda on the folded octant, times 1/prod(P); consecutive
     // threads take consecutive lines of one frequency (adjacent symbol entries)
@@ -493,7 +514,7 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
       }
     }
     __syncthreads();
-    col_fft<T, true, LF, TPLF>(buf, A.fft, lane);
+    col_fft<T, true, LF, TPLF>(buf, A.fft, tw, lane);
   }
   if (jv) {
     cx<T>* dp = dst + (long)i0 * cg.eout + jt;
@@ -517,6 +538,7 @@ __device__ __forceinline__ void rowinv_body(const Prob& pb, const Iter& it, bool
   const long ra = 2 * ((long)blk * G + g), rb = ra + 1;
   const bool va = ra < rows, vb = rb < rows;
   const cx<T>* W = (const cx<T>*)pb.W1;
+  const cx<T>* tw = tw_stage<T, LF>((const cx<T>*)A.fft.tw);
   for (int k = lane; k < P; k += tpl) {
     int kk = k < H ? k : P - k;
     cx<T> xa = va ? W[ra * H + kk] : cx<T>{0, 0};
@@ -526,7 +548,7 @@ __device__ __forceinline__ void rowinv_body(const Prob& pb, const Iter& it, bool
     buf[k] = {xa.x - xb.y, xa.y + xb.x};
   }
   __syncthreads();
-  row_fft<T, true, LF>(buf, A.fft, lane);
+  row_fft<T, true, LF>(buf, A.fft, tw, lane);
   double acc = 0.0;
   for (int i = lane; i < n; i += tpl) {
     cx<T> y = buf[i];
@@ -679,10 +701,9 @@ constexpr int kRaderLF = 257;
 // Transform of a packed pair in either two-line form: the prime form when
 // LF == kRaderLF (result in a), else the direct odd extension.
 template <typename T, int LF, int TPLF = 0>
-__device__ __forceinline__ Line<T> dst_pair(Line<T> a, Line<T> b, const Axis& A, int lane) {
+__device__ __forceinline__ Line<T> dst_pair(Line<T> a, Line<T> b, const Axis& A, const cx<T>* tw, int lane) {
   if constexpr (LF == kRaderLF) {
-    rader_sine<T, kRaderLF - 1>(a, b, A.n, (const int*)A.rtab, (const T*)A.chirp, (const cx<T>*)A.bhat,
-                                (const cx<T>*)A.dst.tw, lane);
+    rader_sine<T, kRaderLF - 1>(a, b, A.n, (const int*)A.rtab, (const T*)A.chirp, (const cx<T>*)A.bhat, tw, lane);
     return a;
   } else {
     return dst_fft<T, false, LF, TPLF>(a, b, A.dst, lane);
@@ -734,6 +755,8 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   const int tpl = RAD ? c_fixed_tpl(kRaderLF - 1) : (CL > 0 ? c_fixed_tpl(CL) : A.dst.tpl);
   const bool direct = LF > 0 ? true : (LF < 0 ? false : A.dst_direct);
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  const cx<T>* dtw = (const cx<T>*)A.dst.tw;  // prime form: staged in LDS, read after the next barrier
+  if constexpr (RAD) dtw = tw_stage<T, kRaderLF - 1>(dtw);
   // direct: a ping-pong pair of lines per FFT line
   Line<T> buf = line_at<T>(smem, direct ? 2 * g : g, Lf);
   Line<T> buf2 = line_at<T>(smem, 2 * g + 1, Lf);
@@ -778,7 +801,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   __syncthreads();
   Line<T> res = buf;  // line holding the transform result
   if (direct) {
-    res = dst_pair<T, LF>(buf, buf2, A, lane);
+    res = dst_pair<T, LF>(buf, buf2, A, dtw, lane);
   } else {
     if constexpr (LF <= 0) dst_line<T, CL>(buf, A, lane, tpl);
   }
@@ -796,7 +819,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
         res[n + 1] = {0, 0};
       }
       __syncthreads();
-      res = dst_pair<T, LF>(res, res.p == buf.p ? buf2 : buf, A, lane);
+      res = dst_pair<T, LF>(res, res.p == buf.p ? buf2 : buf, A, dtw, lane);
     } else {
       const T* tau = (const T*)pb.tau;
       for (int k = lane; k < n; k += tpl)
@@ -856,6 +879,8 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   const int n = A.n, Lf = RAD ? kRaderLF - 1 : (LF > 0 ? LF : (CL > 0 ? CL : A.dst.L));
   const int tpl = RAD ? c_fixed_tpl(kRaderLF - 1)
                       : ((LF > 0 && TPLF > 0) ? TPLF : (CL > 0 ? c_fixed_tpl(CL) : A.dst.tpl));
+  const cx<T>* dtw = (const cx<T>*)A.dst.tw;  // prime form: staged in LDS, read after the next barrier
+  if constexpr (RAD) dtw = tw_stage<T, kRaderLF - 1>(dtw);
   const bool direct = LF > 0 ? true : (LF < 0 ? false : A.dst_direct);
   const int GF = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   const int G = direct ? 2 * GF : GF;  // real lines per block
@@ -922,7 +947,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   Line<T> buf2 = line_at<T>(smem, 2 * g + 1, Lf);
   Line<T> res = buf;
   if (direct) {
-    res = dst_pair<T, LF, TPLF>(buf, buf2, A, lane);
+    res = dst_pair<T, LF, TPLF>(buf, buf2, A, dtw, lane);
   } else {
     if constexpr (LF <= 0) dst_line<T, CL>(buf, A, lane, tpl);
   }
@@ -955,7 +980,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
         res[n + 1] = {0, 0};
       }
       __syncthreads();
-      res = dst_pair<T, LF, TPLF>(res, res.p == buf.p ? buf2 : buf, A, lane);
+      res = dst_pair<T, LF, TPLF>(res, res.p == buf.p ? buf2 : buf, A, dtw, lane);
     } else {
       const long c = c0 + g;
       const bool ok = c < dg.gs;
