@@ -479,6 +479,29 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
   const bool jv = jt < gv;
   Line<T> lnt = line_at<T>(smem, jt, L);
   const cx<T>* tw = tw_stage<T, LF>((const cx<T>*)A.fft.tw);  // read after the barrier below
+  // Symbol values of this thread's line and frequencies k = i0 + q tpl: for
+  // the compile-time lengths up to 1024 (at most 8 per thread) they are
+  // loaded here, with the line itself, so that one round trip serves both.
+  constexpr int NPF = (MODE == COL_CONV && LF > 0 && LF <= 1024 && TPLF > 0 && LF / TPLF <= 8) ? LF / TPLF : 0;
+  const T* lt = nullptr;
+  long tailsz = 0;
+  T lpf[NPF > 0 ? NPF : 1];
+  if (MODE == COL_CONV) {
+    tailsz = (pb.d == 2) ? pb.ax[1].H : (long)pb.ax[1].H * pb.ax[2].H;
+    const long c = c0 + jt;
+    long tail = c;  // index contribution of the axes after axis 0
+    if (pb.d != 2) {
+      const int H2 = pb.ax[2].H, P1 = pb.ax[1].P;
+      tail = (long)fold((int)(c / H2), P1) * H2 + c % H2;
+    }
+    lt = (const T*)pb.lam + tail;
+    if constexpr (NPF > 0) {
+      if (jv) {
+#pragma unroll
+        for (int q = 0; q < NPF; ++q) lpf[q] = lt[(long)fold(i0 + q * TPLF, LF) * tailsz];
+      }
+    }
+  }
   {
     const cx<T>* sp = src + (long)i0 * cg.ein + jt;
     const long sst = (long)tpl * cg.ein;
@@ -495,22 +518,21 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
   if (MODE == COL_CONV) {
     // symbol s0 + s1 lambda on the folded octant, times 1/prod(P); consecutive
     // threads take consecutive lines of one frequency (adjacent symbol entries)
-    const T* lam = (const T*)pb.lam;
     double norm = 1.0;
     for (int a = 0; a < pb.d; ++a) norm *= pb.ax[a].P;
     const T s0 = (T)(pb.s0 / norm), s1 = (T)(pb.s1 / norm);
-    const long tailsz = (pb.d == 2) ? pb.ax[1].H : (long)pb.ax[1].H * pb.ax[2].H;
     if (jv) {
-      const long c = c0 + jt;
-      long tail = c;  // index contribution of the axes after axis 0
-      if (pb.d != 2) {
-        const int H2 = pb.ax[2].H, P1 = pb.ax[1].P;
-        tail = (long)fold((int)(c / H2), P1) * H2 + c % H2;
-      }
-      const T* lt = lam + tail;
-      for (int k = i0; k < L; k += tpl) {
-        const T lv = lt[(long)fold(k, L) * tailsz];
-        lnt[k] = cscale(lnt[k], s0 + s1 * lv);
+      if constexpr (NPF > 0) {
+#pragma unroll
+        for (int q = 0; q < NPF; ++q) {
+          const int k = i0 + q * TPLF;
+          lnt[k] = cscale(lnt[k], s0 + s1 * lpf[q]);
+        }
+      } else {
+        for (int k = i0; k < L; k += tpl) {
+          const T lv = lt[(long)fold(k, L) * tailsz];
+          lnt[k] = cscale(lnt[k], s0 + s1 * lv);
+        }
       }
     }
     __syncthreads();
