@@ -520,16 +520,48 @@ __device__ __forceinline__ void fft_fixed(Line<T> buf, Line<T> aux, const cx<T>*
 //     the lanes of the line with wavefront shuffles.
 // Tables: gi = int[RL/2] g^-p mod N, then int[RL/2 + 1] log_g k (entry 0
 // unused); sp = T[RL/2] s_{g^-p}; bh = cx<T>[RL]; tw = the FFT's roots of unity.
+// A lane's entries of the first three are held in registers (RaderRegs,
+// loaded once per kernel by rader_load, before the line data).
+template <typename T, int RL> struct RaderRegs {
+  static constexpr int TPL = c_fixed_tpl(RL), HALF = RL / 2;
+  static constexpr int PM = (HALF + TPL - 1) / TPL, QM = (RL + TPL - 1) / TPL, C = (HALF + 1 + TPL - 1) / TPL;
+  int j[PM];     // g^-p for p = lane + m TPL
+  T s[PM];       // sin(pi g^-p / N)
+  cx<T> b[QM];   // bhat[q] for q = lane + m TPL
+  int l[C];      // log_g k for k = lane C + c
+};
 template <typename T, int RL>
-__device__ __forceinline__ void rader_sine(Line<T> buf, Line<T> buf2, int n, const int* __restrict__ gi,
-                                           const T* __restrict__ sp, const cx<T>* __restrict__ bh,
+__device__ __forceinline__ void rader_load(RaderRegs<T, RL>& R, const int* __restrict__ gi,
+                                           const T* __restrict__ sp, const cx<T>* __restrict__ bh, int lane) {
+  using RR = RaderRegs<T, RL>;
+#pragma unroll
+  for (int m = 0; m < RR::PM; ++m) {
+    const int p = lane + m * RR::TPL;
+    R.j[m] = p < RR::HALF ? gi[p] : 1;
+    R.s[m] = p < RR::HALF ? sp[p] : (T)0;
+  }
+#pragma unroll
+  for (int m = 0; m < RR::QM; ++m) {
+    const int q = lane + m * RR::TPL;
+    R.b[m] = q < RL ? bh[q] : cx<T>{0, 0};
+  }
+#pragma unroll
+  for (int c = 0; c < RR::C; ++c) {
+    const int k = lane * RR::C + c;
+    R.l[c] = (k >= 1 && k <= RR::HALF) ? gi[RR::HALF + k] : 0;
+  }
+}
+template <typename T, int RL>
+__device__ __forceinline__ void rader_sine(Line<T> buf, Line<T> buf2, int n, const RaderRegs<T, RL>& R,
                                            const cx<T>* __restrict__ tw, int lane) {
   constexpr int N = RL + 1, HALF = RL / 2, TPL = c_fixed_tpl(RL);
   static_assert(TPL <= 64, "the running sum crosses lanes by wavefront shuffles");
-  const int* lg = gi + HALF;
-  for (int p = lane; p < HALF; p += TPL) {
-    const int j = gi[p];
-    const T sj = sp[p];
+#pragma unroll
+  for (int m = 0; m < RaderRegs<T, RL>::PM; ++m) {
+    const int p = lane + m * TPL;
+    if (p >= HALF) break;
+    const int j = R.j[m];
+    const T sj = R.s[m];
     const cx<T> u = buf[j], w = buf[N - j];
     const cx<T> a = cadd(u, w), h = cscale(csub(u, w), (T)0.5);
     buf2[p] = {sj * a.x + h.x, sj * a.y + h.y};
@@ -537,10 +569,13 @@ __device__ __forceinline__ void rader_sine(Line<T> buf, Line<T> buf2, int n, con
   }
   __syncthreads();
   fft_fixed<T, RL, false>(buf2, buf2, tw, lane);
-  for (int q = lane; q < RL; q += TPL) {
+#pragma unroll
+  for (int m = 0; m < RaderRegs<T, RL>::QM; ++m) {
+    const int q = lane + m * TPL;
+    if (q >= RL) break;
     const cx<T> v = buf2[q];
     if (q == 0) buf[0] = v;  // Z_0 (slot 0 of the input line is free)
-    buf2[q] = cmul(v, bh[q]);
+    buf2[q] = cmul(v, R.b[m]);
   }
   __syncthreads();
   fft_fixed<T, RL, true>(buf2, buf2, tw, lane);
@@ -554,7 +589,7 @@ __device__ __forceinline__ void rader_sine(Line<T> buf, Line<T> buf2, int n, con
     if (k <= HALF) {
       cx<T> P = z0, Q = z0;
       if (k > 0) {
-        const int q = lg[k];
+        const int q = R.l[c];
         P = buf2[q];
         Q = buf2[(q + HALF) % RL];
       }

@@ -722,10 +722,12 @@ constexpr int kRaderLF = 257;
 
 // Transform of a packed pair in either two-line form: the prime form when
 // LF == kRaderLF (result in a), else the direct odd extension.
+template <typename T> using RaderPF = RaderRegs<T, kRaderLF - 1>;
 template <typename T, int LF, int TPLF = 0>
-__device__ __forceinline__ Line<T> dst_pair(Line<T> a, Line<T> b, const Axis& A, const cx<T>* tw, int lane) {
+__device__ __forceinline__ Line<T> dst_pair(Line<T> a, Line<T> b, const Axis& A, const cx<T>* tw,
+                                            const RaderPF<T>& rr, int lane) {
   if constexpr (LF == kRaderLF) {
-    rader_sine<T, kRaderLF - 1>(a, b, A.n, (const int*)A.rtab, (const T*)A.chirp, (const cx<T>*)A.bhat, tw, lane);
+    rader_sine<T, kRaderLF - 1>(a, b, A.n, rr, tw, lane);
     return a;
   } else {
     return dst_fft<T, false, LF, TPLF>(a, b, A.dst, lane);
@@ -778,7 +780,11 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   const bool direct = LF > 0 ? true : (LF < 0 ? false : A.dst_direct);
   const int G = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
   const cx<T>* dtw = (const cx<T>*)A.dst.tw;  // prime form: staged in LDS, read after the next barrier
-  if constexpr (RAD) dtw = tw_stage<T, kRaderLF - 1>(dtw);
+  RaderPF<T> rr;                               // prime form: this lane's table entries
+  if constexpr (RAD) {
+    dtw = tw_stage<T, kRaderLF - 1>(dtw);
+    rader_load(rr, (const int*)A.rtab, (const T*)A.chirp, (const cx<T>*)A.bhat, lane);
+  }
   // direct: a ping-pong pair of lines per FFT line
   Line<T> buf = line_at<T>(smem, direct ? 2 * g : g, Lf);
   Line<T> buf2 = line_at<T>(smem, 2 * g + 1, Lf);
@@ -823,7 +829,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   __syncthreads();
   Line<T> res = buf;  // line holding the transform result
   if (direct) {
-    res = dst_pair<T, LF>(buf, buf2, A, dtw, lane);
+    res = dst_pair<T, LF>(buf, buf2, A, dtw, rr, lane);
   } else {
     if constexpr (LF <= 0) dst_line<T, CL>(buf, A, lane, tpl);
   }
@@ -841,7 +847,7 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
         res[n + 1] = {0, 0};
       }
       __syncthreads();
-      res = dst_pair<T, LF>(res, res.p == buf.p ? buf2 : buf, A, dtw, lane);
+      res = dst_pair<T, LF>(res, res.p == buf.p ? buf2 : buf, A, dtw, rr, lane);
     } else {
       const T* tau = (const T*)pb.tau;
       for (int k = lane; k < n; k += tpl)
@@ -901,10 +907,14 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   const int n = A.n, Lf = RAD ? kRaderLF - 1 : (LF > 0 ? LF : (CL > 0 ? CL : A.dst.L));
   const int tpl = RAD ? c_fixed_tpl(kRaderLF - 1)
                       : ((LF > 0 && TPLF > 0) ? TPLF : (CL > 0 ? c_fixed_tpl(CL) : A.dst.tpl));
-  const cx<T>* dtw = (const cx<T>*)A.dst.tw;  // prime form: staged in LDS, read after the next barrier
-  if constexpr (RAD) dtw = tw_stage<T, kRaderLF - 1>(dtw);
   const bool direct = LF > 0 ? true : (LF < 0 ? false : A.dst_direct);
   const int GF = blockDim.x / tpl, g = threadIdx.x / tpl, lane = threadIdx.x % tpl;
+  const cx<T>* dtw = (const cx<T>*)A.dst.tw;  // prime form: staged in LDS, read after the next barrier
+  RaderPF<T> rr;                               // prime form: this lane's table entries
+  if constexpr (RAD) {
+    dtw = tw_stage<T, kRaderLF - 1>(dtw);
+    rader_load(rr, (const int*)A.rtab, (const T*)A.chirp, (const cx<T>*)A.bhat, lane);
+  }
   const int G = direct ? 2 * GF : GF;  // real lines per block
   const long tiles = (dg.gs + G - 1) / G;
   const long grp = blk / tiles, c0 = (blk % tiles) * G;
@@ -969,7 +979,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   Line<T> buf2 = line_at<T>(smem, 2 * g + 1, Lf);
   Line<T> res = buf;
   if (direct) {
-    res = dst_pair<T, LF, TPLF>(buf, buf2, A, dtw, lane);
+    res = dst_pair<T, LF, TPLF>(buf, buf2, A, dtw, rr, lane);
   } else {
     if constexpr (LF <= 0) dst_line<T, CL>(buf, A, lane, tpl);
   }
@@ -1002,7 +1012,7 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
         res[n + 1] = {0, 0};
       }
       __syncthreads();
-      res = dst_pair<T, LF, TPLF>(res, res.p == buf.p ? buf2 : buf, A, dtw, lane);
+      res = dst_pair<T, LF, TPLF>(res, res.p == buf.p ? buf2 : buf, A, dtw, rr, lane);
     } else {
       const long c = c0 + g;
       const bool ok = c < dg.gs;

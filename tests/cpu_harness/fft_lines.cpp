@@ -97,7 +97,9 @@ template <typename T> double run_rader() {
     th.emplace_back([&, lane] {
       g_bar = &bar;
       g_lane = lane;
-      rader_sine<T, RL>(buf, buf2, n, tab.data(), sp.data(), bh.data(), tw.data(), lane);
+      RaderRegs<T, RL> rr;
+      rader_load(rr, tab.data(), sp.data(), bh.data(), lane);
+      rader_sine<T, RL>(buf, buf2, n, rr, tw.data(), lane);
     });
   for (auto& t : th) t.join();
   double err = 0, mx = 0;
