@@ -387,6 +387,12 @@ __device__ __forceinline__ const cx<T>* tw_stage(const cx<T>* tw) {
   }
 }
 
+// Staging loops load a chunk of a thread's elements into registers before
+// writing any of them to LDS: a load consumed in its own loop iteration makes
+// the wavefront wait for it before the next is issued, which serialised the
+// memory round trips of a line.
+constexpr int kStageChunk = 8;
+
 // Row line FFT: LF = 0 follows the run-time plan; LF > 0 is a kernel
 // specialised for that padded length (lanes c_fixed_tpl(LF)).
 template <typename T, bool INV, int LF>
@@ -411,13 +417,64 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
   const long ra = 2 * ((long)blk * G + g), rb = ra + 1;
   const bool va = ra < rows, vb = rb < rows;
   const cx<T>* tw = tw_stage<T, LF>((const cx<T>*)A.fft.tw);
-  for (int i = lane; i < P; i += tpl) {
-    T xa = 0, xb = 0;
-    if (i < n) {
-      if (va) xa = load_input<T, PRO>(pb, ra * n + i, nper, beta, it.first);
-      if (vb) xb = load_input<T, PRO>(pb, rb * n + i, nper, beta, it.first);
+  // A chunk of a thread's elements of rows a and b: every load first (z and
+  // p of the direction update, or the input with its mask), then the
+  // arithmetic, the update's stores and the LDS writes.
+  for (int i0 = lane; i0 < P; i0 += kStageChunk * tpl) {
+    T v[2][kStageChunk];
+    if (PRO == PRO_PUPD) {
+      const T* z = (const T*)pb.z;
+      T* p = (T*)pb.p;
+      T zs[2][kStageChunk], ps[2][kStageChunk];
+#pragma unroll
+      for (int u = 0; u < kStageChunk; ++u)
+#pragma unroll
+        for (int sr = 0; sr < 2; ++sr) {
+          const int i = i0 + u * tpl;
+          const bool ok = (sr ? vb : va) && i < n;
+          const long e = (sr ? rb : ra) * n + i;
+          zs[sr][u] = ok ? z[e] : (T)0;
+          ps[sr][u] = (ok && !it.first) ? p[e] : (T)0;
+        }
+#pragma unroll
+      for (int u = 0; u < kStageChunk; ++u)
+#pragma unroll
+        for (int sr = 0; sr < 2; ++sr) {
+          const int i = i0 + u * tpl;
+          const bool ok = (sr ? vb : va) && i < n;
+          const T pv = it.first ? zs[sr][u] : (T)(zs[sr][u] + (T)beta * ps[sr][u]);
+          if (ok) p[(sr ? rb : ra) * n + i] = pv;
+          v[sr][u] = ok ? pv : (T)0;
+        }
+    } else {
+      const T* in = (const T*)pb.in;
+#pragma unroll
+      for (int u = 0; u < kStageChunk; ++u)
+#pragma unroll
+        for (int sr = 0; sr < 2; ++sr) {
+          const int i = i0 + u * tpl;
+          const bool ok = (sr ? vb : va) && i < n;
+          v[sr][u] = ok ? in[(sr ? rb : ra) * n + i] : (T)0;
+        }
+      if (pb.mask) {
+        T ms[2][kStageChunk];
+#pragma unroll
+        for (int u = 0; u < kStageChunk; ++u)
+#pragma unroll
+          for (int sr = 0; sr < 2; ++sr) {
+            const int i = i0 + u * tpl;
+            const bool ok = (sr ? vb : va) && i < n;
+            ms[sr][u] = ok ? (T)pb.mask[((sr ? rb : ra) * n + i) % nper] : (T)0;
+          }
+#pragma unroll
+        for (int u = 0; u < kStageChunk; ++u)
+#pragma unroll
+          for (int sr = 0; sr < 2; ++sr) v[sr][u] *= ms[sr][u];
+      }
     }
-    buf[i] = {xa, xb};
+#pragma unroll
+    for (int u = 0; u < kStageChunk; ++u)
+      if (i0 + u * tpl < P) buf[i0 + u * tpl] = {v[0][u], v[1][u]};
   }
   __syncthreads();
   row_fft<T, false, LF>(buf, A.fft, tw, lane);
@@ -444,6 +501,11 @@ struct ColGeom {
 };
 
 enum { COL_FWD = 0, COL_CONV = 1, COL_INV = 2 };
+
+// Lanes per column of the 3D column passes at 512 points: 32, i.e. eight
+// adjacent columns per workgroup (64-byte rows in FP32); 2D grids of that
+// length have too few columns for it and keep the plan's 64.
+constexpr int kCol3DLanes512 = 32;
 
 // Column line FFT: LF = 0 follows the run-time plan; LF > 0 is a kernel
 // specialised for that length with TPLF lanes per line (fewer lanes than the
@@ -482,7 +544,8 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
   // Symbol values of this thread's line and frequencies k = i0 + q tpl: for
   // the compile-time lengths up to 1024 (at most 8 per thread) they are
   // loaded here, with the line itself, so that one round trip serves both.
-  constexpr int NPF = (MODE == COL_CONV && LF > 0 && LF <= 1024 && TPLF > 0 && LF / TPLF <= 8) ? LF / TPLF : 0;
+  constexpr int NPF = (MODE == COL_CONV && LF > 0 && LF <= 1024 && TPLF > 0 && LF / TPLF <= (sizeof(T) == 4 ? 16 : 8))
+                          ? LF / TPLF : 0;
   const T* lt = nullptr;
   long tailsz = 0;
   T lpf[NPF > 0 ? NPF : 1];
@@ -506,10 +569,17 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
     const cx<T>* sp = src + (long)i0 * cg.ein + jt;
     const long sst = (long)tpl * cg.ein;
     const int nin = cg.nin;
-    for (int i = i0; i < L; i += tpl, sp += sst) {
-      cx<T> v = {0, 0};
-      if (i < nin && jv) v = *sp;
-      lnt[i] = v;
+    constexpr int CH = (LF > 0 && TPLF > 0 && LF / TPLF <= 16) ? LF / TPLF : kStageChunk;
+    for (int i = i0; i < L; i += CH * tpl, sp += CH * sst) {
+      cx<T> v[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        v[u] = {0, 0};
+        if (i + u * tpl < nin && jv) v[u] = sp[u * sst];
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (i + u * tpl < L) lnt[i + u * tpl] = v[u];
     }
   }
   __syncthreads();
@@ -561,13 +631,27 @@ __device__ __forceinline__ void rowinv_body(const Prob& pb, const Iter& it, bool
   const bool va = ra < rows, vb = rb < rows;
   const cx<T>* W = (const cx<T>*)pb.W1;
   const cx<T>* tw = tw_stage<T, LF>((const cx<T>*)A.fft.tw);
-  for (int k = lane; k < P; k += tpl) {
-    int kk = k < H ? k : P - k;
-    cx<T> xa = va ? W[ra * H + kk] : cx<T>{0, 0};
-    cx<T> xb = vb ? W[rb * H + kk] : cx<T>{0, 0};
-    if (kk == 0 || 2 * kk == P) { xa.y = 0; xb.y = 0; }
-    if (k >= H) { xa.y = -xa.y; xb.y = -xb.y; }
-    buf[k] = {xa.x - xb.y, xa.y + xb.x};
+  for (int k0 = lane; k0 < P; k0 += kStageChunk * tpl) {
+    cx<T> xa[kStageChunk], xb[kStageChunk];
+#pragma unroll
+    for (int u = 0; u < kStageChunk; ++u) {
+      const int k = k0 + u * tpl, kk = k < H ? k : P - k;
+      xa[u] = {0, 0};
+      xb[u] = {0, 0};
+      if (k < P) {
+        if (va) xa[u] = W[ra * H + kk];
+        if (vb) xb[u] = W[rb * H + kk];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kStageChunk; ++u) {
+      const int k = k0 + u * tpl, kk = k < H ? k : P - k;
+      if (k >= P) continue;
+      cx<T> a = xa[u], b = xb[u];
+      if (kk == 0 || 2 * kk == P) { a.y = 0; b.y = 0; }
+      if (k >= H) { a.y = -a.y; b.y = -b.y; }
+      buf[k] = {a.x - b.y, a.y + b.x};
+    }
   }
   __syncthreads();
   row_fft<T, true, LF>(buf, A.fft, tw, lane);
@@ -720,6 +804,17 @@ __device__ __forceinline__ Line<T> dst_fft(Line<T> a, Line<T> b, const FFTPlan& 
 // odd, so it never equals a direct length 2(n+1).
 constexpr int kRaderLF = 257;
 
+// Elements per chunk of a sine pass's staging loop: a thread's whole share
+// where the length is compile-time (n = LF/2 - 1 direct, 256 prime form; per
+// thread n / lanes in a row pass, 2n / lanes in a column pass, whose lanes hold
+// two columns), at most CMAX; 4 otherwise.
+__host__ __device__ constexpr int dst_chunk(int LF, int lanes, bool cols, int CMAX) {
+  const int n = LF == 257 ? 256 : (LF > 0 ? LF / 2 - 1 : 0);
+  if (n == 0 || lanes == 0) return CMAX < 4 ? CMAX : 4;
+  const int c = ((cols ? 2 * n : n) + lanes - 1) / lanes;
+  return c < 1 ? 1 : (c > CMAX ? CMAX : c);
+}
+
 // Transform of a packed pair in either two-line form: the prime form when
 // LF == kRaderLF (result in a), else the direct odd extension.
 template <typename T> using RaderPF = RaderRegs<T, kRaderLF - 1>;
@@ -792,38 +887,91 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   const long ra = ((long)blk * G + g) * (direct ? 2 : 1), rb = ra + 1;
   const bool va = ra < rows, vb = direct && rb < rows;
   double acc = 0.0;
-  auto pro = [&](long e) -> T {
+  // A chunk of a thread's elements (rows a and b of the pair): every load
+  // first (x, p, r, q of the update, or the input with its mask and
+  // correction), then the arithmetic, the update's stores and the LDS writes.
+  constexpr int CK = dst_chunk(LF, RAD ? c_fixed_tpl(kRaderLF - 1) : (LF > 0 ? c_fixed_tpl(LF) : 0), false,
+                               DPRO == DPRO_UPD ? 4 : 8);
+  for (int i0 = lane; i0 < n; i0 += CK * tpl) {
+    T v[2][CK];
     if (DPRO == DPRO_UPD) {
       T* x = (T*)pb.x;
       T* r = (T*)pb.r;
-      x[e] += (T)alpha * ((const T*)pb.p)[e];
-      T rv = r[e] - (T)alpha * ((const T*)pb.q)[e];
-      r[e] = rv;
-      acc += (double)rv * (double)rv;
-      return rv;
+      const T* p = (const T*)pb.p;
+      const T* q = (const T*)pb.q;
+      T xs[2][CK], ps[2][CK], rs[2][CK], qs[2][CK];
+#pragma unroll
+      for (int u = 0; u < CK; ++u)
+#pragma unroll
+        for (int sr = 0; sr < 2; ++sr) {
+          const int i = i0 + u * tpl;
+          const bool ok = (sr ? vb : va) && i < n;
+          const long e = (sr ? rb : ra) * n + i;
+          xs[sr][u] = ok ? x[e] : (T)0;
+          ps[sr][u] = ok ? p[e] : (T)0;
+          rs[sr][u] = ok ? r[e] : (T)0;
+          qs[sr][u] = ok ? q[e] : (T)0;
+        }
+#pragma unroll
+      for (int u = 0; u < CK; ++u)
+#pragma unroll
+        for (int sr = 0; sr < 2; ++sr) {
+          const int i = i0 + u * tpl;
+          const bool ok = (sr ? vb : va) && i < n;
+          const long e = (sr ? rb : ra) * n + i;
+          v[sr][u] = 0;
+          if (ok) {
+            x[e] = xs[sr][u] + (T)alpha * ps[sr][u];
+            const T rv = rs[sr][u] - (T)alpha * qs[sr][u];
+            r[e] = rv;
+            acc += (double)rv * (double)rv;
+            v[sr][u] = rv;
+          }
+        }
     } else {
-      T v = ((const T*)pb.in)[e];
+      const T* in = (const T*)pb.in;
+#pragma unroll
+      for (int u = 0; u < CK; ++u)
+#pragma unroll
+        for (int sr = 0; sr < 2; ++sr) {
+          const int i = i0 + u * tpl;
+          const bool ok = (sr ? vb : va) && i < n;
+          v[sr][u] = ok ? in[(sr ? rb : ra) * n + i] : (T)0;
+        }
       // the domain mask acts on grid functions only: the input of the first
       // pass (or of the single 1D pass), never on a transformed intermediate
-      if (DEPI == DEPI_STORE || pb.d == 1) {
-        if (pb.mask) v *= (T)pb.mask[e % nper];
-        if (pb.corr) v += ((const T*)pb.corr)[e];
+      if ((DEPI == DEPI_STORE || pb.d == 1) && (pb.mask || pb.corr)) {
+        T ms[2][CK], cs[2][CK];
+#pragma unroll
+        for (int u = 0; u < CK; ++u)
+#pragma unroll
+          for (int sr = 0; sr < 2; ++sr) {
+            const int i = i0 + u * tpl;
+            const bool ok = (sr ? vb : va) && i < n;
+            const long e = (sr ? rb : ra) * n + i;
+            ms[sr][u] = (ok && pb.mask) ? (T)pb.mask[e % nper] : (T)1;
+            cs[sr][u] = (ok && pb.corr) ? ((const T*)pb.corr)[e] : (T)0;
+          }
+#pragma unroll
+        for (int u = 0; u < CK; ++u)
+#pragma unroll
+          for (int sr = 0; sr < 2; ++sr) {
+            if (pb.mask) v[sr][u] *= ms[sr][u];
+            if (pb.corr) v[sr][u] += cs[sr][u];
+          }
       }
-      return v;
     }
-  };
-  if (direct) {
-    for (int i = lane; i < n; i += tpl) {
-      T xa = va ? pro(ra * n + i) : (T)0;
-      T xb = vb ? pro(rb * n + i) : (T)0;
-      pair_put<T, RAD>(buf, Lf, i + 1, xa, xb);
+#pragma unroll
+    for (int u = 0; u < CK; ++u) {
+      const int i = i0 + u * tpl;
+      if (i >= n) continue;
+      if (direct) pair_put<T, RAD>(buf, Lf, i + 1, v[0][u], v[1][u]);
+      else buf[i] = {v[0][u], (T)0};
     }
-    if (lane == 0) {
-      buf[0] = {0, 0};
-      buf[n + 1] = {0, 0};
-    }
-  } else {
-    for (int i = lane; i < n; i += tpl) buf[i] = {va ? pro(ra * n + i) : (T)0, (T)0};
+  }
+  if (direct && lane == 0) {
+    buf[0] = {0, 0};
+    buf[n + 1] = {0, 0};
   }
   if (DPRO == DPRO_UPD) put_partial(pb, S_RR, acc, nblk, blk);
   __syncthreads();
@@ -926,6 +1074,8 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
   // lines than threads (one lane per FFT line of a short direct form) walks a
   // flat index instead.
   const bool wide = G > (int)blockDim.x;
+  constexpr int CKC = dst_chunk(LF, RAD ? c_fixed_tpl(kRaderLF - 1) : (LF > 0 ? (TPLF > 0 ? TPLF : c_fixed_tpl(LF)) : 0),
+                                true, 8);
   const int jt = wide ? 0 : threadIdx.x % G, i0 = wide ? 0 : threadIdx.x / G;
   const int ist = wide ? 1 : blockDim.x / G;
   const bool jv = jt < gv;
@@ -953,11 +1103,20 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
     Line<T> ln = line_at<T>(smem, 2 * (jt >> 1), Lf);
     const T* bp = base + (long)i0 * dg.estride + jt;
     const long bst = (long)ist * dg.estride;
-    for (int i = i0; i < n; i += ist, bp += bst) {
-      T v = 0;
-      if (jv) v = *bp;
-      ((T*)&ln[i + 1])[jt & 1] = v;
-      if constexpr (!RAD) ((T*)&ln[Lf - 1 - i])[jt & 1] = -v;
+    for (int i = i0; i < n; i += CKC * ist, bp += CKC * bst) {
+      T v[CKC];
+#pragma unroll
+      for (int u = 0; u < CKC; ++u) {
+        v[u] = 0;
+        if (jv && i + u * ist < n) v[u] = bp[u * bst];
+      }
+#pragma unroll
+      for (int u = 0; u < CKC; ++u) {
+        const int ii = i + u * ist;
+        if (ii >= n) continue;
+        ((T*)&ln[ii + 1])[jt & 1] = v[u];
+        if constexpr (!RAD) ((T*)&ln[Lf - 1 - ii])[jt & 1] = -v[u];
+      }
     }
     for (int q = threadIdx.x; q < GF; q += blockDim.x) {
       Line<T> lq = line_at<T>(smem, 2 * q, Lf);
@@ -968,10 +1127,16 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
     Line<T> ln = line_at<T>(smem, jt, Lf);
     const T* bp = base + (long)i0 * dg.estride + jt;
     const long bst = (long)ist * dg.estride;
-    for (int i = i0; i < n; i += ist, bp += bst) {
-      T v = 0;
-      if (jv) v = *bp;
-      ln[i] = {v, 0};
+    for (int i = i0; i < n; i += CKC * ist, bp += CKC * bst) {
+      T v[CKC];
+#pragma unroll
+      for (int u = 0; u < CKC; ++u) {
+        v[u] = 0;
+        if (jv && i + u * ist < n) v[u] = bp[u * bst];
+      }
+#pragma unroll
+      for (int u = 0; u < CKC; ++u)
+        if (i + u * ist < n) ln[i + u * ist] = {v[u], 0};
     }
   }
   __syncthreads();
@@ -1163,10 +1328,10 @@ template <typename T, int MODE, int LF = 0, int TPLF = 0>
 __global__ FL_BOUNDS void k_colpass(Prob pb, ColGeom cg, Iter it, int chk) {
   colpass_body<T, MODE, LF, TPLF>(pb, cg, it, chk, blockIdx.x, gridDim.x);
 }
-template <typename T, int MODE, int LF = 0>
+template <typename T, int MODE, int LF = 0, int TPLF = (LF > 0 ? c_fixed_tpl(LF) : 0)>
 __global__ FL_BOUNDS void k_colpass_b(const Prob* pbs, const ColGeom* cgs, Iter it, int chk, const int* nb) {
   if ((int)blockIdx.x >= nb[blockIdx.y]) return;
-  colpass_body<T, MODE, LF, (LF > 0 ? c_fixed_tpl(LF) : 0)>(pbs[blockIdx.y], cgs[blockIdx.y], it, chk, blockIdx.x,
+  colpass_body<T, MODE, LF, TPLF>(pbs[blockIdx.y], cgs[blockIdx.y], it, chk, blockIdx.x,
                                                              nb[blockIdx.y]);
 }
 template <typename T, int EPI, int LF = 0> __global__ FL_BOUNDS void k_rowinv(Prob pb, Iter it, int chk) {
