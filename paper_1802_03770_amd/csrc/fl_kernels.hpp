@@ -656,24 +656,42 @@ __device__ __forceinline__ void rowinv_body(const Prob& pb, const Iter& it, bool
   __syncthreads();
   row_fft<T, true, LF>(buf, A.fft, tw, lane);
   double acc = 0.0;
-  for (int i = lane; i < n; i += tpl) {
-    cx<T> y = buf[i];
+  // per chunk: the epilogue's loads (aux or p, mask) first, then the stores
+  for (int i0 = lane; i0 < n; i0 += kStageChunk * tpl) {
+    T ld[2][kStageChunk], ms[2][kStageChunk];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      long row = s ? rb : ra;
-      if (!(s ? vb : va)) continue;
-      long e = row * n + i;
-      T v = s ? y.y : y.x;
-      if (pb.mask) v *= (T)pb.mask[e % nper];
-      if (EPI == EPI_PLAIN) {
-        ((T*)pb.out)[e] = v;
-      } else if (EPI == EPI_RESID) {
-        T rv = ((const T*)pb.aux)[e] - v;
-        ((T*)pb.out)[e] = rv;
-        acc += (double)rv * (double)rv;
-      } else {  // EPI_PQ: q = M p, accumulate p.q
-        ((T*)pb.q)[e] = v;
-        acc += (double)((const T*)pb.p)[e] * (double)v;
+    for (int u = 0; u < kStageChunk; ++u)
+#pragma unroll
+      for (int sr = 0; sr < 2; ++sr) {
+        const int i = i0 + u * tpl;
+        const bool ok = (sr ? vb : va) && i < n;
+        const long e = (sr ? rb : ra) * n + i;
+        ld[sr][u] = 0;
+        if (EPI == EPI_RESID && ok) ld[sr][u] = ((const T*)pb.aux)[e];
+        if (EPI == EPI_PQ && ok) ld[sr][u] = ((const T*)pb.p)[e];
+        ms[sr][u] = (ok && pb.mask) ? (T)pb.mask[e % nper] : (T)1;
+      }
+#pragma unroll
+    for (int u = 0; u < kStageChunk; ++u) {
+      const int i = i0 + u * tpl;
+      if (i >= n) continue;
+      const cx<T> y = buf[i];
+#pragma unroll
+      for (int sr = 0; sr < 2; ++sr) {
+        if (!(sr ? vb : va)) continue;
+        const long e = (sr ? rb : ra) * n + i;
+        T v = sr ? y.y : y.x;
+        if (pb.mask) v *= ms[sr][u];
+        if (EPI == EPI_PLAIN) {
+          ((T*)pb.out)[e] = v;
+        } else if (EPI == EPI_RESID) {
+          const T rv = ld[sr][u] - v;
+          ((T*)pb.out)[e] = rv;
+          acc += (double)rv * (double)rv;
+        } else {  // EPI_PQ: q = M p, accumulate p.q
+          ((T*)pb.q)[e] = v;
+          acc += (double)ld[sr][u] * (double)v;
+        }
       }
     }
   }
@@ -1011,19 +1029,38 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   if (pb.d == 1 || DEPI != DEPI_STORE)
     for (int a = 0; a < pb.d; ++a) norm *= 2.0 / (pb.ax[a].n + 1);
   double acc2 = 0.0;
-  for (int i = lane; i < n; i += tpl) {
-    cx<T> sv = direct ? pair_get<T, RAD>(res, i + 1) : buf[i];
+  const bool mask_out = pb.mask && !pb.nomask_out && (DEPI != DEPI_STORE || pb.d == 1);
+  constexpr int CKE = dst_chunk(LF, RAD ? c_fixed_tpl(kRaderLF - 1) : (LF > 0 ? c_fixed_tpl(LF) : 0), false, 8);
+  // per chunk: the epilogue's loads (r, mask) first, then the stores
+  for (int i0 = lane; i0 < n; i0 += CKE * tpl) {
+    T rs[2][CKE], ms[2][CKE];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      if (!(s ? vb : va)) continue;
-      long e = (s ? rb : ra) * n + i;
-      T v = (s ? sv.y : sv.x) * (T)norm;
-      if (pb.mask && !pb.nomask_out && (DEPI != DEPI_STORE || pb.d == 1)) v *= (T)pb.mask[e % nper];
-      if (DEPI != DEPI_Z) {
-        ((T*)pb.out)[e] = v;
-      } else {
-        ((T*)pb.z)[e] = v;
-        acc2 += (double)((const T*)pb.r)[e] * (double)v;
+    for (int u = 0; u < CKE; ++u)
+#pragma unroll
+      for (int sr = 0; sr < 2; ++sr) {
+        const int i = i0 + u * tpl;
+        const bool ok = (sr ? vb : va) && i < n;
+        const long e = (sr ? rb : ra) * n + i;
+        rs[sr][u] = (DEPI == DEPI_Z && ok) ? ((const T*)pb.r)[e] : (T)0;
+        ms[sr][u] = (ok && mask_out) ? (T)pb.mask[e % nper] : (T)1;
+      }
+#pragma unroll
+    for (int u = 0; u < CKE; ++u) {
+      const int i = i0 + u * tpl;
+      if (i >= n) continue;
+      const cx<T> sv = direct ? pair_get<T, RAD>(res, i + 1) : buf[i];
+#pragma unroll
+      for (int sr = 0; sr < 2; ++sr) {
+        if (!(sr ? vb : va)) continue;
+        const long e = (sr ? rb : ra) * n + i;
+        T v = (sr ? sv.y : sv.x) * (T)norm;
+        if (mask_out) v *= ms[sr][u];
+        if (DEPI != DEPI_Z) {
+          ((T*)pb.out)[e] = v;
+        } else {
+          ((T*)pb.z)[e] = v;
+          acc2 += (double)rs[sr][u] * (double)v;
+        }
       }
     }
   }
@@ -1157,20 +1194,40 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
       const bool oka = ca < dg.gs, okb = cb < dg.gs;
       const double ta = (oka && !tau) ? eig_tail<T>(pb, ca) : 0.0;
       const double tb = (okb && !tau) ? eig_tail<T>(pb, cb) : 0.0;
-      for (int k = lane + 1; k <= n; k += tpl) {
-        cx<T> sv = pair_get<T, RAD>(res, k);
-        double la, lb;
-        if (tau) {
-          la = oka ? (double)tau[(long)(k - 1) * dg.gs + ca] : 1.0;
-          lb = okb ? (double)tau[(long)(k - 1) * dg.gs + cb] : 1.0;
-        } else {
-          const double ek = (double)ev[k - 1];
-          la = ek + ta;
-          lb = ek + tb;
+      constexpr int CKS = dst_chunk(LF, RAD ? c_fixed_tpl(kRaderLF - 1) : (LF > 0 ? (TPLF > 0 ? TPLF : c_fixed_tpl(LF)) : 0),
+                                    false, RAD ? 2 : 4);
+      // per chunk: the diagonal's entries (table or eigenvalues) loaded first
+      for (int k0 = lane + 1; k0 <= n; k0 += CKS * tpl) {
+        T da[CKS], db[CKS];
+#pragma unroll
+        for (int u = 0; u < CKS; ++u) {
+          const int k = k0 + u * tpl;
+          const bool okk = k <= n;
+          if (tau) {
+            da[u] = (oka && okk) ? tau[(long)(k - 1) * dg.gs + ca] : (T)1;
+            db[u] = (okb && okk) ? tau[(long)(k - 1) * dg.gs + cb] : (T)1;
+          } else {
+            da[u] = okk ? ev[k - 1] : (T)0;
+          }
         }
-        T ea = (T)(pb.p0 + pb.p1 * pb.pcs * la);
-        T eb = (T)(pb.p0 + pb.p1 * pb.pcs * lb);
-        pair_put<T, RAD>(res, Lf, k, pb.pmul ? sv.x * ea : sv.x / ea, pb.pmul ? sv.y * eb : sv.y / eb);
+#pragma unroll
+        for (int u = 0; u < CKS; ++u) {
+          const int k = k0 + u * tpl;
+          if (k > n) continue;
+          const cx<T> sv = pair_get<T, RAD>(res, k);
+          double la, lb;
+          if (tau) {
+            la = (double)da[u];
+            lb = (double)db[u];
+          } else {
+            const double ek = (double)da[u];
+            la = ek + ta;
+            lb = ek + tb;
+          }
+          T ea = (T)(pb.p0 + pb.p1 * pb.pcs * la);
+          T eb = (T)(pb.p0 + pb.p1 * pb.pcs * lb);
+          pair_put<T, RAD>(res, Lf, k, pb.pmul ? sv.x * ea : sv.x / ea, pb.pmul ? sv.y * eb : sv.y / eb);
+        }
       }
       if (lane == 0) {
         res[0] = {0, 0};
