@@ -952,7 +952,25 @@ template <typename T> __global__ __launch_bounds__(256) void k_fcg_dots(Prob pb,
   const T* r = (const T*)pb.r;
   const T* q = (const T*)pb.q;
   double a = 0.0, c = 0.0;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+  const long st = (long)gridDim.x * blockDim.x;
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  // four elements' loads in flight before their products (same summation order)
+  for (; i + 3 * st < n; i += 4 * st) {
+    T zs[4], rs[4], qs[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      zs[u] = z[i + u * st];
+      rs[u] = r[i + u * st];
+      qs[u] = with_q ? q[i + u * st] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double zi = (double)zs[u];
+      a += zi * (double)rs[u];
+      if (with_q) c += zi * (double)qs[u];
+    }
+  }
+  for (; i < n; i += st) {
     const double zi = (double)z[i];
     a += zi * (double)r[i];
     if (with_q) c += zi * (double)q[i];
@@ -978,7 +996,25 @@ __global__ __launch_bounds__(256) void k_fcg_dir(Prob pb, long n, const double* 
   const T* r = (const T*)pb.r;
   T* p = (T*)pb.p;
   double acc = 0.0;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+  const long st = (long)gridDim.x * blockDim.x;
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  // four elements' loads before their stores (same summation order)
+  for (; i + 3 * st < n; i += 4 * st) {
+    T zs[4], ps[4], rs[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      zs[u] = z[i + u * st];
+      ps[u] = beta == 0.0 ? (T)0 : p[i + u * st];
+      rs[u] = r[i + u * st];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T pv = beta == 0.0 ? zs[u] : (T)((double)zs[u] + beta * (double)ps[u]);
+      p[i + u * st] = pv;
+      acc += (double)pv * (double)rs[u];
+    }
+  }
+  for (; i < n; i += st) {
     const T pv = beta == 0.0 ? z[i] : (T)((double)z[i] + beta * (double)p[i]);
     p[i] = pv;
     acc += (double)pv * (double)r[i];
@@ -996,7 +1032,27 @@ template <typename T> __global__ __launch_bounds__(256) void k_fcg_update(Prob p
   const T* p = (const T*)pb.p;
   const T* q = (const T*)pb.q;
   double acc = 0.0;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+  const long st = (long)gridDim.x * blockDim.x;
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  // four elements' loads before their stores (same summation order)
+  for (; i + 3 * st < n; i += 4 * st) {
+    T xs[4], ps[4], rs[4], qs[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      xs[u] = x[i + u * st];
+      ps[u] = p[i + u * st];
+      rs[u] = r[i + u * st];
+      qs[u] = q[i + u * st];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[i + u * st] = xs[u] + (T)alpha * ps[u];
+      const T rv = rs[u] - (T)alpha * qs[u];
+      r[i + u * st] = rv;
+      acc += (double)rv * (double)rv;
+    }
+  }
+  for (; i < n; i += st) {
     x[i] += (T)alpha * p[i];
     const T rv = r[i] - (T)alpha * q[i];
     r[i] = rv;
