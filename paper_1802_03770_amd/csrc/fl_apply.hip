@@ -17,8 +17,8 @@ template <typename T> static fl_status launch_col_conv(const Prob& pc, const Col
     if (lf == 2048 && sizeof(T) == 8 && tplf == 64) tplf = 128;
     if (lf == 1024) tplf = 64;
   } else if (fft_lf(A) == 8192 || fft_lf(A) == 512 || fft_lf(A) == 256) {
-    lf = A.P;  // the plan's lanes, compile-time
-    tplf = c_fixed_tpl(lf);
+    lf = A.P;  // compile-time lanes
+    tplf = lf == 512 ? col_tpl(A, pc.d) : c_fixed_tpl(lf);
   }
   Prob pl = pc;
   if (!lf) pl.ax[cg.axis].fft.tpl = tune_tpl(A.fft.tpl, A.P, cg.gs * cg.ngroup);
@@ -37,7 +37,10 @@ template <typename T> static fl_status launch_col_conv(const Prob& pc, const Col
   else if (lf == 1024)
     LAUNCH((k_colpass<T, COL_CONV, 1024, 64>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
   else if (lf == 512)
-    LAUNCH((k_colpass<T, COL_CONV, 512, c_fixed_tpl(512)>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
+    if (tplf == kCol3DLanes512)
+      LAUNCH((k_colpass<T, COL_CONV, 512, kCol3DLanes512>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
+    else
+      LAUNCH((k_colpass<T, COL_CONV, 512, c_fixed_tpl(512)>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
   else if (lf == 256)
     LAUNCH((k_colpass<T, COL_CONV, 256, c_fixed_tpl(256)>), dim3(grid), dim3(nt), sm, s, pl, cg, it, chk);
   else
@@ -112,17 +115,22 @@ template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob
     Axis& A = pc.ax[cg.axis];
     if (mode == COL_CONV) return launch_col_conv<T>(pc, cg, it, chk, s);
     A.fft.tpl = tune_tpl(A.fft.tpl, A.P, cg.gs * cg.ngroup);
-    int nt = block_for(A.fft.tpl), G = nt / A.fft.tpl;
+    const int lf = fft_lf(A);
+    const int tpl = lf == 512 ? col_tpl(A, d) : A.fft.tpl;
+    int nt = block_for(tpl), G = nt / tpl;
     long grid = cg.ngroup * ((cg.gs + G - 1) / G);
     size_t sm = (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>);
-    const int lf = fft_lf(A);
     if (mode == COL_FWD) {
-      if (lf == 512) LAUNCH((k_colpass<T, COL_FWD, 512, c_fixed_tpl(512)>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+      if (lf == 512 && tpl == kCol3DLanes512)
+        LAUNCH((k_colpass<T, COL_FWD, 512, kCol3DLanes512>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+      else if (lf == 512) LAUNCH((k_colpass<T, COL_FWD, 512, c_fixed_tpl(512)>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
       else if (lf == 256) LAUNCH((k_colpass<T, COL_FWD, 256, c_fixed_tpl(256)>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
       else LAUNCH(k_colpass<T, COL_FWD>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
     }
     if (mode == COL_INV) {
-      if (lf == 512) LAUNCH((k_colpass<T, COL_INV, 512, c_fixed_tpl(512)>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+      if (lf == 512 && tpl == kCol3DLanes512)
+        LAUNCH((k_colpass<T, COL_INV, 512, kCol3DLanes512>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
+      else if (lf == 512) LAUNCH((k_colpass<T, COL_INV, 512, c_fixed_tpl(512)>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
       else if (lf == 256) LAUNCH((k_colpass<T, COL_INV, 256, c_fixed_tpl(256)>), dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
       else LAUNCH(k_colpass<T, COL_INV>, dim3(grid), dim3(nt), sm, s, pc, cg, it, chk);
     }
