@@ -71,7 +71,7 @@ template <typename T> fl_status bt_setup(BatchT& bt, const BatchDesc& B, const s
       const Axis& A = pb.ax[c.axis];
       const int lfa = fft_lf(A);
       o.key[1 + r] = (lfa == 1024 || lfa == 512 || lfa == 256) ? lfa : 0;
-      const int G = 256 / col_tpl(A, d);
+      const int G = 256 / A.fft.tpl;  // batched launches keep the plan's lanes (measured faster there)
       o.nb_col[r] = (int)(c.ngroup * ((c.gs + G - 1) / G));
       o.sm_col[r] = lds_fft<T>(A.P, G);
     }
@@ -203,10 +203,7 @@ template <typename T, int PRO, int EPI> fl_status bt_apply(BatchT& bt, const Pro
 #define FL_COLB(M)                                                                                   \
   switch (G.lf_col[r]) {                                                                             \
     case 1024: LAUNCH((k_colpass_b<T, M, 1024>), g, dim3(256), sm, s, pg, cg, it, chk, nb); break;  \
-    case 512:                                                                                        \
-      if (d == 3) LAUNCH((k_colpass_b<T, M, 512, kCol3DLanes512>), g, dim3(256), sm, s, pg, cg, it, chk, nb); \
-      else LAUNCH((k_colpass_b<T, M, 512>), g, dim3(256), sm, s, pg, cg, it, chk, nb);                \
-      break;                                                                                         \
+    case 512: LAUNCH((k_colpass_b<T, M, 512>), g, dim3(256), sm, s, pg, cg, it, chk, nb); break;    \
     case 256: LAUNCH((k_colpass_b<T, M, 256>), g, dim3(256), sm, s, pg, cg, it, chk, nb); break;    \
     default: LAUNCH((k_colpass_b<T, M>), g, dim3(256), sm, s, pg, cg, it, chk, nb); break;          \
   }
