@@ -502,9 +502,11 @@ struct ColGeom {
 
 enum { COL_FWD = 0, COL_CONV = 1, COL_INV = 2 };
 
-// Lanes per column of the 3D column passes at 512 points: 32, i.e. eight
-// adjacent columns per workgroup (64-byte rows in FP32); 2D grids of that
-// length have too few columns for it and keep the plan's 64.
+// Lanes per column of the single-problem 3D column passes at 512 points: 32,
+// i.e. eight adjacent columns per workgroup (64-byte rows in FP32; the axis-0
+// convolution at 256^3 took 245 us against 285 us with 64 lanes).  2D grids of
+// that length have too few columns for it, and the batched launches, whose
+// grids hold every problem's blocks, measured faster with the plan's 64.
 constexpr int kCol3DLanes512 = 32;
 
 // Column line FFT: LF = 0 follows the run-time plan; LF > 0 is a kernel
@@ -599,9 +601,19 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
           lnt[k] = cscale(lnt[k], s0 + s1 * lpf[q]);
         }
       } else {
-        for (int k = i0; k < L; k += tpl) {
-          const T lv = lt[(long)fold(k, L) * tailsz];
-          lnt[k] = cscale(lnt[k], s0 + s1 * lv);
+        // a chunk's symbol values loaded before any of them is used
+        for (int k0 = i0; k0 < L; k0 += kStageChunk * tpl) {
+          T lv[kStageChunk];
+#pragma unroll
+          for (int u = 0; u < kStageChunk; ++u) {
+            const int k = k0 + u * tpl;
+            lv[u] = k < L ? lt[(long)fold(k, L) * tailsz] : (T)0;
+          }
+#pragma unroll
+          for (int u = 0; u < kStageChunk; ++u) {
+            const int k = k0 + u * tpl;
+            if (k < L) lnt[k] = cscale(lnt[k], s0 + s1 * lv[u]);
+          }
         }
       }
     }
