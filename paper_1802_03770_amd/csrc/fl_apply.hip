@@ -18,7 +18,7 @@ template <typename T> static fl_status launch_col_conv(const Prob& pc, const Col
     if (lf == 1024) tplf = 64;
   } else if (fft_lf(A) == 8192 || fft_lf(A) == 512 || fft_lf(A) == 256) {
     lf = A.P;  // compile-time lanes
-    tplf = lf == 512 ? col_tpl(A, pc.d) : c_fixed_tpl(lf);
+    tplf = lf == 512 ? col_tpl<T>(A, pc.d) : c_fixed_tpl(lf);
   }
   Prob pl = pc;
   if (!lf) pl.ax[cg.axis].fft.tpl = tune_tpl(A.fft.tpl, A.P, cg.gs * cg.ngroup);
@@ -116,7 +116,7 @@ template <typename T, int PRO, int EPI> fl_status apply_seq(fl_op op, const Prob
     if (mode == COL_CONV) return launch_col_conv<T>(pc, cg, it, chk, s);
     A.fft.tpl = tune_tpl(A.fft.tpl, A.P, cg.gs * cg.ngroup);
     const int lf = fft_lf(A);
-    const int tpl = lf == 512 ? col_tpl(A, d) : A.fft.tpl;
+    const int tpl = lf == 512 ? col_tpl<T>(A, d) : A.fft.tpl;
     int nt = block_for(tpl), G = nt / tpl;
     long grid = cg.ngroup * ((cg.gs + G - 1) / G);
     size_t sm = (size_t)G * Line<T>::stride(A.P) * sizeof(cx<T>);

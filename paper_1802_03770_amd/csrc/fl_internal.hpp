@@ -172,9 +172,12 @@ inline int fft_lf(const Axis& A) {
   }
 }
 
-// Lanes per column of a column pass of the application along axis A of a
-// d-dimensional grid (the plan's, but kCol3DLanes512 for 3D lines of 512).
-inline int col_tpl(const Axis& A, int d) { return (d == 3 && fft_lf(A) == 512) ? kCol3DLanes512 : A.fft.tpl; }
+// Lanes per column of a single-problem column pass of the application along
+// axis A of a d-dimensional grid: the plan's, but kCol3DLanes512 for FP32 3D
+// lines of 512 (FP64 needs too many registers for it: 841 against 786 us).
+template <typename T> inline int col_tpl(const Axis& A, int d) {
+  return (sizeof(T) == 4 && d == 3 && fft_lf(A) == 512) ? kCol3DLanes512 : A.fft.tpl;
+}
 
 // More lanes per line (fewer elements per lane) when a pass has too few lines
 // to give every CU two workgroups; the plan's tpl is the minimum.

@@ -502,11 +502,12 @@ struct ColGeom {
 
 enum { COL_FWD = 0, COL_CONV = 1, COL_INV = 2 };
 
-// Lanes per column of the single-problem 3D column passes at 512 points: 32,
-// i.e. eight adjacent columns per workgroup (64-byte rows in FP32; the axis-0
+// Lanes per column of the single-problem FP32 3D column passes at 512 points:
+// 32, i.e. eight adjacent columns per workgroup (64-byte rows; the axis-0
 // convolution at 256^3 took 245 us against 285 us with 64 lanes).  2D grids of
-// that length have too few columns for it, and the batched launches, whose
-// grids hold every problem's blocks, measured faster with the plan's 64.
+// that length have too few columns for it, FP64 too many registers, and the
+// batched launches, whose grids hold every problem's blocks, measured faster
+// with the plan's 64.
 constexpr int kCol3DLanes512 = 32;
 
 // Column line FFT: LF = 0 follows the run-time plan; LF > 0 is a kernel
