@@ -432,9 +432,10 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
         for (int sr = 0; sr < 2; ++sr) {
           const int i = i0 + u * tpl;
           const bool ok = (sr ? vb : va) && i < n;
-          const long e = (sr ? rb : ra) * n + i;
-          zs[sr][u] = ok ? z[e] : (T)0;
-          ps[sr][u] = (ok && !it.first) ? p[e] : (T)0;
+          const long e = ok ? (sr ? rb : ra) * n + i : 0;  // clamped: unconditional loads
+          const T zv = z[e], pv = p[e];
+          zs[sr][u] = ok ? zv : (T)0;
+          ps[sr][u] = (ok && !it.first) ? pv : (T)0;
         }
 #pragma unroll
       for (int u = 0; u < kStageChunk; ++u)
@@ -454,7 +455,8 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
         for (int sr = 0; sr < 2; ++sr) {
           const int i = i0 + u * tpl;
           const bool ok = (sr ? vb : va) && i < n;
-          v[sr][u] = ok ? in[(sr ? rb : ra) * n + i] : (T)0;
+          const T t = in[ok ? (sr ? rb : ra) * n + i : 0];  // clamped: unconditional load
+          v[sr][u] = ok ? t : (T)0;
         }
       if (pb.mask) {
         T ms[2][kStageChunk];
@@ -671,19 +673,31 @@ __device__ __forceinline__ void rowinv_body(const Prob& pb, const Iter& it, bool
   double acc = 0.0;
   // per chunk: the epilogue's loads (aux or p, mask) first, then the stores
   for (int i0 = lane; i0 < n; i0 += kStageChunk * tpl) {
+    // unconditional loads from clamped in-range indices, then a select
     T ld[2][kStageChunk], ms[2][kStageChunk];
+    if (EPI != EPI_PLAIN) {
+      const T* src = EPI == EPI_RESID ? (const T*)pb.aux : (const T*)pb.p;
 #pragma unroll
-    for (int u = 0; u < kStageChunk; ++u)
+      for (int u = 0; u < kStageChunk; ++u)
 #pragma unroll
-      for (int sr = 0; sr < 2; ++sr) {
-        const int i = i0 + u * tpl;
-        const bool ok = (sr ? vb : va) && i < n;
-        const long e = (sr ? rb : ra) * n + i;
-        ld[sr][u] = 0;
-        if (EPI == EPI_RESID && ok) ld[sr][u] = ((const T*)pb.aux)[e];
-        if (EPI == EPI_PQ && ok) ld[sr][u] = ((const T*)pb.p)[e];
-        ms[sr][u] = (ok && pb.mask) ? (T)pb.mask[e % nper] : (T)1;
-      }
+        for (int sr = 0; sr < 2; ++sr) {
+          const int i = i0 + u * tpl;
+          const bool ok = (sr ? vb : va) && i < n;
+          const T t = src[ok ? (sr ? rb : ra) * n + i : 0];
+          ld[sr][u] = ok ? t : (T)0;
+        }
+    }
+    if (pb.mask) {
+#pragma unroll
+      for (int u = 0; u < kStageChunk; ++u)
+#pragma unroll
+        for (int sr = 0; sr < 2; ++sr) {
+          const int i = i0 + u * tpl;
+          const bool ok = (sr ? vb : va) && i < n;
+          const T t = (T)pb.mask[ok ? ((sr ? rb : ra) * n + i) % nper : 0];
+          ms[sr][u] = ok ? t : (T)1;
+        }
+    }
 #pragma unroll
     for (int u = 0; u < kStageChunk; ++u) {
       const int i = i0 + u * tpl;
@@ -937,11 +951,12 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
         for (int sr = 0; sr < 2; ++sr) {
           const int i = i0 + u * tpl;
           const bool ok = (sr ? vb : va) && i < n;
-          const long e = (sr ? rb : ra) * n + i;
-          xs[sr][u] = ok ? x[e] : (T)0;
-          ps[sr][u] = ok ? p[e] : (T)0;
-          rs[sr][u] = ok ? r[e] : (T)0;
-          qs[sr][u] = ok ? q[e] : (T)0;
+          const long e = ok ? (sr ? rb : ra) * n + i : 0;  // clamped: unconditional loads
+          const T xv = x[e], pv = p[e], rv = r[e], qv = q[e];
+          xs[sr][u] = ok ? xv : (T)0;
+          ps[sr][u] = ok ? pv : (T)0;
+          rs[sr][u] = ok ? rv : (T)0;
+          qs[sr][u] = ok ? qv : (T)0;
         }
 #pragma unroll
       for (int u = 0; u < CK; ++u)
@@ -967,29 +982,42 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
         for (int sr = 0; sr < 2; ++sr) {
           const int i = i0 + u * tpl;
           const bool ok = (sr ? vb : va) && i < n;
-          v[sr][u] = ok ? in[(sr ? rb : ra) * n + i] : (T)0;
+          const T t = in[ok ? (sr ? rb : ra) * n + i : 0];  // clamped: unconditional load
+          v[sr][u] = ok ? t : (T)0;
         }
       // the domain mask acts on grid functions only: the input of the first
       // pass (or of the single 1D pass), never on a transformed intermediate
-      if ((DEPI == DEPI_STORE || pb.d == 1) && (pb.mask || pb.corr)) {
-        T ms[2][CK], cs[2][CK];
+      if ((DEPI == DEPI_STORE || pb.d == 1) && pb.mask) {
+        T ms[2][CK];
 #pragma unroll
         for (int u = 0; u < CK; ++u)
 #pragma unroll
           for (int sr = 0; sr < 2; ++sr) {
             const int i = i0 + u * tpl;
             const bool ok = (sr ? vb : va) && i < n;
-            const long e = (sr ? rb : ra) * n + i;
-            ms[sr][u] = (ok && pb.mask) ? (T)pb.mask[e % nper] : (T)1;
-            cs[sr][u] = (ok && pb.corr) ? ((const T*)pb.corr)[e] : (T)0;
+            const T t = (T)pb.mask[ok ? ((sr ? rb : ra) * n + i) % nper : 0];
+            ms[sr][u] = ok ? t : (T)1;
           }
 #pragma unroll
         for (int u = 0; u < CK; ++u)
 #pragma unroll
+          for (int sr = 0; sr < 2; ++sr) v[sr][u] *= ms[sr][u];
+      }
+      if ((DEPI == DEPI_STORE || pb.d == 1) && pb.corr) {
+        T cs[2][CK];
+#pragma unroll
+        for (int u = 0; u < CK; ++u)
+#pragma unroll
           for (int sr = 0; sr < 2; ++sr) {
-            if (pb.mask) v[sr][u] *= ms[sr][u];
-            if (pb.corr) v[sr][u] += cs[sr][u];
+            const int i = i0 + u * tpl;
+            const bool ok = (sr ? vb : va) && i < n;
+            const T t = ((const T*)pb.corr)[ok ? (sr ? rb : ra) * n + i : 0];
+            cs[sr][u] = ok ? t : (T)0;
           }
+#pragma unroll
+        for (int u = 0; u < CK; ++u)
+#pragma unroll
+          for (int sr = 0; sr < 2; ++sr) v[sr][u] += cs[sr][u];
       }
     }
 #pragma unroll
@@ -1046,17 +1074,30 @@ __device__ __forceinline__ void dst_rows_body(const Prob& pb, const Iter& it, bo
   constexpr int CKE = dst_chunk(LF, RAD ? c_fixed_tpl(kRaderLF - 1) : (LF > 0 ? c_fixed_tpl(LF) : 0), false, 8);
   // per chunk: the epilogue's loads (r, mask) first, then the stores
   for (int i0 = lane; i0 < n; i0 += CKE * tpl) {
+    // unconditional loads from clamped in-range indices, then a select
     T rs[2][CKE], ms[2][CKE];
+    if (DEPI == DEPI_Z) {
 #pragma unroll
-    for (int u = 0; u < CKE; ++u)
+      for (int u = 0; u < CKE; ++u)
 #pragma unroll
-      for (int sr = 0; sr < 2; ++sr) {
-        const int i = i0 + u * tpl;
-        const bool ok = (sr ? vb : va) && i < n;
-        const long e = (sr ? rb : ra) * n + i;
-        rs[sr][u] = (DEPI == DEPI_Z && ok) ? ((const T*)pb.r)[e] : (T)0;
-        ms[sr][u] = (ok && mask_out) ? (T)pb.mask[e % nper] : (T)1;
-      }
+        for (int sr = 0; sr < 2; ++sr) {
+          const int i = i0 + u * tpl;
+          const bool ok = (sr ? vb : va) && i < n;
+          const T t = ((const T*)pb.r)[ok ? (sr ? rb : ra) * n + i : 0];
+          rs[sr][u] = ok ? t : (T)0;
+        }
+    }
+    if (mask_out) {
+#pragma unroll
+      for (int u = 0; u < CKE; ++u)
+#pragma unroll
+        for (int sr = 0; sr < 2; ++sr) {
+          const int i = i0 + u * tpl;
+          const bool ok = (sr ? vb : va) && i < n;
+          const T t = (T)pb.mask[ok ? ((sr ? rb : ra) * n + i) % nper : 0];
+          ms[sr][u] = ok ? t : (T)1;
+        }
+    }
 #pragma unroll
     for (int u = 0; u < CKE; ++u) {
       const int i = i0 + u * tpl;
@@ -1211,16 +1252,25 @@ __device__ __forceinline__ void dst_cols_body(const Prob& pb, const DGeom& dg, b
                                     false, RAD ? 2 : 4);
       // per chunk: the diagonal's entries (table or eigenvalues) loaded first
       for (int k0 = lane + 1; k0 <= n; k0 += CKS * tpl) {
+        // unconditional loads from clamped in-range indices, then a select:
+        // no branch around a load, so no wait between them
         T da[CKS], db[CKS];
+        if (tau) {
 #pragma unroll
-        for (int u = 0; u < CKS; ++u) {
-          const int k = k0 + u * tpl;
-          const bool okk = k <= n;
-          if (tau) {
-            da[u] = (oka && okk) ? tau[(long)(k - 1) * dg.gs + ca] : (T)1;
-            db[u] = (okb && okk) ? tau[(long)(k - 1) * dg.gs + cb] : (T)1;
-          } else {
-            da[u] = okk ? ev[k - 1] : (T)0;
+          for (int u = 0; u < CKS; ++u) {
+            const int k = k0 + u * tpl;
+            const bool ua = oka && k <= n, ub = okb && k <= n;
+            const T va_ = tau[ua ? (long)(k - 1) * dg.gs + ca : 0];
+            const T vb_ = tau[ub ? (long)(k - 1) * dg.gs + cb : 0];
+            da[u] = ua ? va_ : (T)1;
+            db[u] = ub ? vb_ : (T)1;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < CKS; ++u) {
+            const int k = k0 + u * tpl;
+            const T e = ev[k <= n ? k - 1 : 0];
+            da[u] = k <= n ? e : (T)0;
           }
         }
 #pragma unroll
