@@ -58,7 +58,18 @@ __device__ __forceinline__ double get_total(const Prob& pb, int site) {
   const int n = pb.sc->cnt[site];
   const double* p = pb.part + site * pb.pstride;
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+  // eight partials' loads in flight before they are added (same order; a
+  // 256^3 pass leaves several thousand partials)
+  const int st = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 7 * st < n; i += 8 * st) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = p[i + u * st];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += a[u];
+  }
+  for (; i < n; i += st) v += p[i];
   return block_sum_all(v);
 }
 
@@ -1351,8 +1362,22 @@ template <typename T>
 __device__ __forceinline__ void dot_body(const Prob& pb, const void* a, const void* b, int site, long n, int nblk,
                                          int blk) {
   double acc = 0.0;
-  for (long i = (long)blk * blockDim.x + threadIdx.x; i < n; i += (long)nblk * blockDim.x)
-    acc += (double)((const T*)a)[i] * (double)((const T*)b)[i];
+  const T* x = (const T*)a;
+  const T* y = (const T*)b;
+  const long st = (long)nblk * blockDim.x;
+  long i = (long)blk * blockDim.x + threadIdx.x;
+  // eight elements' loads in flight before their products (same order)
+  for (; i + 7 * st < n; i += 8 * st) {
+    T xs[8], ys[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      xs[u] = x[i + u * st];
+      ys[u] = y[i + u * st];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (double)xs[u] * (double)ys[u];
+  }
+  for (; i < n; i += st) acc += (double)x[i] * (double)y[i];
   put_partial(pb, site, acc, nblk, blk);
 }
 
@@ -1387,7 +1412,27 @@ __device__ __forceinline__ void update_body(const Prob& pb, const Iter& it, long
   const T* p = (const T*)pb.p;
   const T* q = (const T*)pb.q;
   double acc = 0.0;
-  for (long i = (long)blk * blockDim.x + threadIdx.x; i < n; i += (long)nblk * blockDim.x) {
+  const long st = (long)nblk * blockDim.x;
+  long i = (long)blk * blockDim.x + threadIdx.x;
+  // four elements' loads before their stores (same order)
+  for (; i + 3 * st < n; i += 4 * st) {
+    T xs[4], ps[4], rs[4], qs[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      xs[u] = x[i + u * st];
+      ps[u] = p[i + u * st];
+      rs[u] = r[i + u * st];
+      qs[u] = q[i + u * st];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[i + u * st] = xs[u] + (T)alpha * ps[u];
+      const T rv = rs[u] - (T)alpha * qs[u];
+      r[i + u * st] = rv;
+      acc += (double)rv * (double)rv;
+    }
+  }
+  for (; i < n; i += st) {
     x[i] += (T)alpha * p[i];
     T rv = r[i] - (T)alpha * q[i];
     r[i] = rv;
@@ -1515,8 +1560,16 @@ template <typename T> __global__ FL_BOUNDS void k_copy_in_aux_b(const Prob* pbs,
   const long n = ns[blockIdx.y];
   const T* src = (const T*)pb.in;
   T* dst = (T*)pb.aux;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)nb[blockIdx.y] * blockDim.x)
-    dst[i] = src[i];
+  const long st = (long)nb[blockIdx.y] * blockDim.x;
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * st < n; i += 4 * st) {  // four loads in flight before the stores
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = src[i + u * st];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) dst[i + u * st] = v[u];
+  }
+  for (; i < n; i += st) dst[i] = src[i];
 }
 template <typename T> __global__ FL_BOUNDS void k_update(Prob pb, Iter it, long n) {
   update_body<T>(pb, it, n, gridDim.x, blockIdx.x);
