@@ -68,12 +68,15 @@ __host__ __device__ __forceinline__ int stage_radix(const FFTPlan& pl, int s) {
 
 template <typename T, int R, bool INV> struct Bfly;
 
+// run_half: the same butterfly for inputs whose upper half a[R/2..R-1] is
+// zero (the first stage of a zero-padded line); those entries are not read.
 template <typename T, bool INV> struct Bfly<T, 2, INV> {
   static __device__ __forceinline__ void run(cx<T>* a) {
     cx<T> t = a[1];
     a[1] = csub(a[0], t);
     a[0] = cadd(a[0], t);
   }
+  static __device__ __forceinline__ void run_half(cx<T>* a) { a[1] = a[0]; }
 };
 
 template <typename T, bool INV> struct Bfly<T, 4, INV> {
@@ -85,16 +88,34 @@ template <typename T, bool INV> struct Bfly<T, 4, INV> {
     a[1] = cadd(t1, t3);
     a[3] = csub(t1, t3);
   }
+  static __device__ __forceinline__ void run_half(cx<T>* a) {
+    const cx<T> x0 = a[0], x1 = a[1], t3 = mul_mi<T, INV>(x1);
+    a[0] = cadd(x0, x1);
+    a[2] = csub(x0, x1);
+    a[1] = cadd(x0, t3);
+    a[3] = csub(x0, t3);
+  }
 };
 
 template <typename T, bool INV> struct Bfly<T, 8, INV> {
   static __device__ __forceinline__ void run(cx<T>* a) {
-    const T r2 = (T)0.70710678118654752440084436210484904L;
     // radix-4 on even and odd halves
     cx<T> e[4] = {a[0], a[2], a[4], a[6]};
     cx<T> o[4] = {a[1], a[3], a[5], a[7]};
     Bfly<T, 4, INV>::run(e);
     Bfly<T, 4, INV>::run(o);
+    join(e, o, a);
+  }
+  static __device__ __forceinline__ void run_half(cx<T>* a) {
+    cx<T> e[4] = {a[0], a[2], {0, 0}, {0, 0}};
+    cx<T> o[4] = {a[1], a[3], {0, 0}, {0, 0}};
+    Bfly<T, 4, INV>::run_half(e);
+    Bfly<T, 4, INV>::run_half(o);
+    join(e, o, a);
+  }
+  // outputs from the radix-4 transforms of the even and odd entries
+  static __device__ __forceinline__ void join(const cx<T>* e, const cx<T>* o, cx<T>* a) {
+    const T r2 = (T)0.70710678118654752440084436210484904L;
     // twiddles w8^k, k = 0..3  (w8 = e^{-+2 pi i / 8})
     cx<T> o1 = INV ? cx<T>{r2 * (o[1].x - o[1].y), r2 * (o[1].x + o[1].y)}
                    : cx<T>{r2 * (o[1].x + o[1].y), r2 * (o[1].y - o[1].x)};
@@ -310,8 +331,15 @@ __device__ __forceinline__ void bfly_prime(cx<T>* a, const T* cs, const T* sn) {
   a[0] = y0;
 }
 
-template <typename T, int R, int L, int NS, int TPL, bool INV>
+// ZI: the line's upper half is zero on entry (a first stage of even radix:
+// input r of a butterfly is zero for r >= R/2, and is not read).  ZO: only the
+// lower half of the output is used (a last stage of even radix: outputs
+// r >= R/2 are not written).
+template <typename T, int R, int L, int NS, int TPL, bool INV, bool ZI = false, bool ZO = false>
 __device__ __forceinline__ void cstage(Line<T> buf, const cx<T>* __restrict__ tw, int lane) {
+  static_assert(!(ZI || ZO) || R % 2 == 0, "pruned stages need an even radix");
+  static_assert(!ZI || NS == 1, "input pruning applies to a first stage");
+  static_assert(!ZO || NS * R == L, "output pruning applies to a last stage");
   constexpr int NB = L / R;
   constexpr int MB = (NB + TPL - 1) / TPL;
   constexpr bool FULL = (NB % TPL) == 0;
@@ -334,7 +362,7 @@ __device__ __forceinline__ void cstage(Line<T> buf, const cx<T>* __restrict__ tw
     if (FULL || j < NB) {
       const int k = j % NS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * NB];
+      for (int r = 0; r < (ZI ? R / 2 : R); ++r) v[b][r] = buf[j + r * NB];
       if (NS > 1) {
         const int st = k * TSTEP;
 #pragma unroll
@@ -345,6 +373,8 @@ __device__ __forceinline__ void cstage(Line<T> buf, const cx<T>* __restrict__ tw
       }
       if constexpr (PRIME)
         bfly_prime<T, R, INV>(v[b], cs, sn);
+      else if constexpr (ZI)
+        Bfly<T, R, INV>::run_half(v[b]);
       else
         Bfly<T, R, INV>::run(v[b]);
     }
@@ -357,7 +387,7 @@ __device__ __forceinline__ void cstage(Line<T> buf, const cx<T>* __restrict__ tw
       const int k = j % NS;
       const int base = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base + r * NS] = v[b][r];
+      for (int r = 0; r < (ZO ? R / 2 : R); ++r) buf[base + r * NS] = v[b][r];
     }
   }
   __syncthreads();
@@ -484,23 +514,30 @@ __device__ __forceinline__ void cstage_split(Line<T> buf, Line<T> aux, const cx<
   __syncthreads();
 }
 
-template <typename T, int L, int TPL, bool INV, int S, int NS>
+// ZIN: entries L/2 .. L-1 of the input are zero (a zero-padded line; they
+// need not be in LDS).  ZOUT: only entries 0 .. L/2-1 of the output are used
+// (a cropped line; the others are left unwritten).  Each takes effect where
+// the first (last) stage has an even radix.
+template <typename T, int L, int TPL, bool INV, int S, int NS, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void cstages(Line<T> buf, Line<T> aux, const cx<T>* __restrict__ tw, int lane) {
   if constexpr (S < c_nst(L)) {
     constexpr int R = c_radix(L, S);
+    constexpr bool ZI = ZIN && S == 0 && R % 2 == 0, ZO = ZOUT && S == c_nst(L) - 1 && R % 2 == 0;
     if constexpr (R >= 17)
       cstage_split<T, R, L, NS, TPL, INV>(buf, aux, tw, lane);
     else
-      cstage<T, R, L, NS, TPL, INV>(buf, tw, lane);
-    cstages<T, L, TPL, INV, S + 1, NS * R>(buf, aux, tw, lane);
+      cstage<T, R, L, NS, TPL, INV, ZI, ZO>(buf, tw, lane);
+    cstages<T, L, TPL, INV, S + 1, NS * R, ZIN, ZOUT>(buf, aux, tw, lane);
   }
 }
 
 // aux: a second line of length L, used as scratch by prime stages >= 17
-template <typename T, int L, bool INV>
+template <typename T, int L, bool INV, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void fft_fixed(Line<T> buf, Line<T> aux, const cx<T>* __restrict__ tw, int lane) {
-  cstages<T, L, c_fixed_tpl(L), INV, 0, 1>(buf, aux, tw, lane);
+  cstages<T, L, c_fixed_tpl(L), INV, 0, 1, ZIN, ZOUT>(buf, aux, tw, lane);
 }
+// True when the first stage of length L would skip the upper half of the input.
+__host__ __device__ constexpr bool c_zin_pruned(int L) { return c_nst(L) > 0 && c_radix(L, 0) % 2 == 0; }
 
 // Prime form of a packed pair, N = n + 1 an odd prime with N - 1 = RL (the FFT
 // length; lanes c_fixed_tpl(RL) <= 64).  In: buf[k] = (x_a[k], x_b[k]) for

@@ -405,11 +405,23 @@ __device__ __forceinline__ const cx<T>* tw_stage(const cx<T>* tw) {
 constexpr int kStageChunk = 8;
 
 // Row line FFT: LF = 0 follows the run-time plan; LF > 0 is a kernel
-// specialised for that padded length (lanes c_fixed_tpl(LF)).
-template <typename T, bool INV, int LF>
+// specialised for that padded length (lanes c_fixed_tpl(LF)).  Padded lengths
+// are at least twice the grid's: the forward transform's input is zero from
+// LF/2 on (ZIN) and the inverse's output is cropped below LF/2 (ZOUT), which
+// the specialised kernels use to skip that half at the first (last) stage.
+template <typename T, bool INV, int LF, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void row_fft(Line<T> buf, const FFTPlan& pl, const cx<T>* tw, int lane) {
-  if constexpr (LF > 0) fft_fixed<T, LF, INV>(buf, buf, tw, lane);
+  if constexpr (LF > 0) fft_fixed<T, LF, INV, ZIN, ZOUT>(buf, buf, tw, lane);
   else fft_line<T, INV>(buf, pl, lane);
+}
+
+// Entries of a zero-padded line of compile-time length LF that are staged in
+// LDS: the lower half when the first stage skips the upper one.
+__host__ __device__ constexpr int c_staged_len(int LF) { return LF > 0 && c_zin_pruned(LF) ? LF / 2 : LF; }
+// Elements of a row line per lane and chunk: no more than the staged part holds.
+__host__ __device__ constexpr int c_row_chunk(int LF) {
+  return (c_staged_len(LF) + c_fixed_tpl(LF) - 1) / c_fixed_tpl(LF) < kStageChunk
+             ? (c_staged_len(LF) + c_fixed_tpl(LF) - 1) / c_fixed_tpl(LF) : kStageChunk;
 }
 
 template <typename T, int PRO, int LF = 0>
@@ -428,17 +440,21 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
   const long ra = 2 * ((long)blk * G + g), rb = ra + 1;
   const bool va = ra < rows, vb = rb < rows;
   const cx<T>* tw = tw_stage<T, LF>((const cx<T>*)A.fft.tw);
+  // entries staged: all P, or the lower half that the pruned first stage reads
+  // (n <= P/2 either way, so the direction update still covers every entry)
+  const int PS = LF > 0 ? c_staged_len(LF) : P;
+  constexpr int CH = LF > 0 ? c_row_chunk(LF) : kStageChunk;
   // A chunk of a thread's elements of rows a and b: every load first (z and
   // p of the direction update, or the input with its mask), then the
   // arithmetic, the update's stores and the LDS writes.
-  for (int i0 = lane; i0 < P; i0 += kStageChunk * tpl) {
-    T v[2][kStageChunk];
+  for (int i0 = lane; i0 < PS; i0 += CH * tpl) {
+    T v[2][CH];
     if (PRO == PRO_PUPD) {
       const T* z = (const T*)pb.z;
       T* p = (T*)pb.p;
-      T zs[2][kStageChunk], ps[2][kStageChunk];
+      T zs[2][CH], ps[2][CH];
 #pragma unroll
-      for (int u = 0; u < kStageChunk; ++u)
+      for (int u = 0; u < CH; ++u)
 #pragma unroll
         for (int sr = 0; sr < 2; ++sr) {
           const int i = i0 + u * tpl;
@@ -449,7 +465,7 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
           ps[sr][u] = (ok && !it.first) ? pv : (T)0;
         }
 #pragma unroll
-      for (int u = 0; u < kStageChunk; ++u)
+      for (int u = 0; u < CH; ++u)
 #pragma unroll
         for (int sr = 0; sr < 2; ++sr) {
           const int i = i0 + u * tpl;
@@ -461,7 +477,7 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
     } else {
       const T* in = (const T*)pb.in;
 #pragma unroll
-      for (int u = 0; u < kStageChunk; ++u)
+      for (int u = 0; u < CH; ++u)
 #pragma unroll
         for (int sr = 0; sr < 2; ++sr) {
           const int i = i0 + u * tpl;
@@ -470,9 +486,9 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
           v[sr][u] = ok ? t : (T)0;
         }
       if (pb.mask) {
-        T ms[2][kStageChunk];
+        T ms[2][CH];
 #pragma unroll
-        for (int u = 0; u < kStageChunk; ++u)
+        for (int u = 0; u < CH; ++u)
 #pragma unroll
           for (int sr = 0; sr < 2; ++sr) {
             const int i = i0 + u * tpl;
@@ -480,17 +496,17 @@ __device__ __forceinline__ void rowfwd_body(const Prob& pb, const Iter& it, int 
             ms[sr][u] = ok ? (T)pb.mask[((sr ? rb : ra) * n + i) % nper] : (T)0;
           }
 #pragma unroll
-        for (int u = 0; u < kStageChunk; ++u)
+        for (int u = 0; u < CH; ++u)
 #pragma unroll
           for (int sr = 0; sr < 2; ++sr) v[sr][u] *= ms[sr][u];
       }
     }
 #pragma unroll
-    for (int u = 0; u < kStageChunk; ++u)
-      if (i0 + u * tpl < P) buf[i0 + u * tpl] = {v[0][u], v[1][u]};
+    for (int u = 0; u < CH; ++u)
+      if (i0 + u * tpl < PS) buf[i0 + u * tpl] = {v[0][u], v[1][u]};
   }
   __syncthreads();
-  row_fft<T, false, LF>(buf, A.fft, tw, lane);
+  row_fft<T, false, LF, true, false>(buf, A.fft, tw, lane);
   cx<T>* W = (cx<T>*)pb.W1;
   for (int k = lane; k < H; k += tpl) {
     cx<T> zk = buf[k], zm = buf[(P - k) % P];
@@ -525,11 +541,13 @@ constexpr int kCol3DLanes512 = 32;
 
 // Column line FFT: LF = 0 follows the run-time plan; LF > 0 is a kernel
 // specialised for that length with TPLF lanes per line (fewer lanes than the
-// row passes use, so that a block holds several adjacent columns).
-template <typename T, bool INV, int LF, int TPLF>
+// row passes use, so that a block holds several adjacent columns).  ZIN/ZOUT
+// as for the rows: a transform of a zero-padded column skips the upper half of
+// its input, one whose output is cropped to the grid skips that of its output.
+template <typename T, bool INV, int LF, int TPLF, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void col_fft(Line<T> buf, const FFTPlan& pl, const cx<T>* tw, int lane) {
   if constexpr (LF > 0)
-    cstages<T, LF, TPLF, INV, 0, 1>(buf, buf, tw, lane);
+    cstages<T, LF, TPLF, INV, 0, 1, ZIN, ZOUT>(buf, buf, tw, lane);
   else
     fft_line<T, INV>(buf, pl, lane);
 }
@@ -582,11 +600,16 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
     }
   }
   {
+    // The forward transforms of COL_FWD and COL_CONV take a zero-padded column
+    // (nin <= L/2): with a pruned first stage only its lower half is staged.
+    constexpr bool ZS = MODE != COL_INV && LF > 0 && c_zin_pruned(LF);
+    constexpr int LS = ZS ? LF / 2 : LF;
+    const int Ls = LF > 0 ? LS : L;
     const cx<T>* sp = src + (long)i0 * cg.ein + jt;
     const long sst = (long)tpl * cg.ein;
     const int nin = cg.nin;
-    constexpr int CH = (LF > 0 && TPLF > 0 && LF / TPLF <= 16) ? LF / TPLF : kStageChunk;
-    for (int i = i0; i < L; i += CH * tpl, sp += CH * sst) {
+    constexpr int CH = (LF > 0 && TPLF > 0 && LF / TPLF <= 16) ? (LS + TPLF - 1) / TPLF : kStageChunk;
+    for (int i = i0; i < Ls; i += CH * tpl, sp += CH * sst) {
       cx<T> v[CH];
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
@@ -595,12 +618,12 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u)
-        if (i + u * tpl < L) lnt[i + u * tpl] = v[u];
+        if (i + u * tpl < Ls) lnt[i + u * tpl] = v[u];
     }
   }
   __syncthreads();
   Line<T> buf = line_at<T>(smem, g, L);
-  col_fft<T, MODE == COL_INV, LF, TPLF>(buf, A.fft, tw, lane);
+  col_fft<T, MODE == COL_INV, LF, TPLF, MODE != COL_INV, MODE == COL_INV>(buf, A.fft, tw, lane);
   if (MODE == COL_CONV) {
     // symbol s0 + s1 lambda on the folded octant, times 1/prod(P); consecutive
     // threads take consecutive lines of one frequency (adjacent symbol entries)
@@ -632,7 +655,7 @@ __device__ __forceinline__ void colpass_body(const Prob& pb, const ColGeom& cg, 
       }
     }
     __syncthreads();
-    col_fft<T, true, LF, TPLF>(buf, A.fft, tw, lane);
+    col_fft<T, true, LF, TPLF, false, true>(buf, A.fft, tw, lane);
   }
   if (jv) {
     cx<T>* dp = dst + (long)i0 * cg.eout + jt;
@@ -680,7 +703,7 @@ __device__ __forceinline__ void rowinv_body(const Prob& pb, const Iter& it, bool
     }
   }
   __syncthreads();
-  row_fft<T, true, LF>(buf, A.fft, tw, lane);
+  row_fft<T, true, LF, false, true>(buf, A.fft, tw, lane);
   double acc = 0.0;
   // per chunk: the epilogue's loads (aux or p, mask) first, then the stores
   for (int i0 = lane; i0 < n; i0 += kStageChunk * tpl) {
