@@ -249,10 +249,10 @@ fl_op_s::~fl_op_s() {
   cap_destroy(this);
   for (void* p : tables) hipFree(p);
   for (auto& w : ws) {
+    drop_graph(w);
     for (void* p : {w.W1, w.W2, w.T1, w.x, w.r, w.z, w.p, w.q, w.f}) if (p) hipFree(p);
     if (w.sc) hipFree(w.sc);
     if (w.part) hipFree(w.part);
-    if (w.gexec) hipGraphExecDestroy(w.gexec);
   }
   if (d_cst) hipFree(d_cst);
   if (wf) hipFree(wf);
@@ -725,7 +725,7 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
       }
       int its = 0, stt = 0, fb = 0;
       double rrf = 0.0;
-      STCHK(learned_fcg<double>(op, net, pb, tol, maxit, ff, rr0, &its, &rrf, &stt, &fb));
+      STCHK(learned_fcg<double>(op, net, pb, tol, maxit, ff, rr0, graph, &its, &rrf, &stt, &fb));
       inf.iters = its;
       inf.fell_back = fb;
       inf.rel_res_recur = ff > 0 ? std::sqrt(rrf / ff) : 0.0;
@@ -782,7 +782,7 @@ static fl_status solve_system(fl_op op, const uint8_t* mask, double s0, double s
         const double ff32 = 1.0;
         int its = 0, stt = 0, fb = 0;
         double rrf = 0.0;
-        STCHK(learned_fcg<float>(op, net, p32, itol, inner_cap, ff32, ff32, &its, &rrf, &stt, &fb));
+        STCHK(learned_fcg<float>(op, net, p32, itol, inner_cap, ff32, ff32, graph, &its, &rrf, &stt, &fb));
         res.itc[0] = its;
         res.rr = rrf;
         res.ff = ff32;

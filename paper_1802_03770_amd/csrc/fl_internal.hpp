@@ -65,6 +65,12 @@ struct Workspace {
   int gK = 0, gpc = -1, gcap = 0;
   double gs0 = 0, gs1 = 0, gp0 = 0, gp1 = 0;
   const uint8_t* gmask = nullptr;
+  // graphs of flexible-CG iterations k >= 1 with the learned preconditioner,
+  // one per slot of the host scalar ring (lexec[k & 1]), valid for the
+  // network generation lgen and the solver Prob whose bytes are lkey
+  hipGraphExec_t lexec[2] = {nullptr, nullptr};
+  unsigned long long lgen = 0;
+  std::vector<unsigned char> lkey;
 };
 
 // Capacitance correction that makes the sine-diagonalised preconditioner
@@ -219,6 +225,12 @@ inline void drop_graph(Workspace& w) {
     (void)hipGraphExecDestroy(w.gexec);
     w.gexec = nullptr;
   }
+  for (hipGraphExec_t& g : w.lexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  w.lkey.clear();
 }
 
 template <typename T> inline fl_status ensure_ws(fl_op op, long nrhs, bool solver) {
@@ -313,8 +325,8 @@ inline bool pc_is_sine(int pc) {
 // took over.
 fl_status learned_prepare(fl_op op, fl_net net, size_t elem);
 template <typename T>
-fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxit, double ff, double rr0, int* iters,
-                      double* rr_out, int* status, int* fell_back);
+fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxit, double ff, double rr0, int graph,
+                      int* iters, double* rr_out, int* status, int* fell_back);
 
 // Exact preconditioner on occluded domains (fl_capacity.hip): the mask
 // checksum into *dst (device), the build or reuse of the correction for the

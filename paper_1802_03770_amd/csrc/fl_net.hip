@@ -1060,10 +1060,12 @@ template <typename T> __global__ __launch_bounds__(256) void k_fcg_update(Prob p
   }
   put_partial(pb, S_RR, acc, gridDim.x, blockIdx.x);
 }
-// r.r into fs[4] and the done flag (converged, non-finite, or p.q breakdown)
-__global__ void k_fcg_check(Prob pb, double* __restrict__ fs, double thr) {
+// r.r into fs[4] and the done flag (converged below the threshold fs[6],
+// non-finite, or p.q breakdown)
+__global__ void k_fcg_check(Prob pb, double* __restrict__ fs) {
   const double rr = get_total(pb, S_RR);
   if (threadIdx.x == 0 && fs[5] == 0.0) {
+    const double thr = fs[6];
     fs[4] = rr;
     const double pq = fs[2];
     if (rr <= thr || !isfinite(rr) || !(pq > 0.0) || !isfinite(pq)) {
@@ -1095,8 +1097,13 @@ using namespace fln;
 // ---------------------------------------------------------------------------
 // network object
 // ---------------------------------------------------------------------------
+// Generation counter of network buffers: a graph captured with a network's
+// buffers is replayed only while that network's generation is unchanged.
+static std::atomic<unsigned long long> g_net_gen{0};
+
 struct fl_net_s {
   hipStream_t stream = nullptr;
+  unsigned long long gen = ++g_net_gen;  // renewed by every allocation
   int kd = 1;              // kernel depth: 1 (2D network) or 3 (3D network)
   long nparam = 0, pack = 0;
   float *th = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
@@ -1134,6 +1141,7 @@ struct fl_net_s {
   fl_status alloc(void** p, size_t bytes) {
     STCHK(dalloc(p, bytes));
     owned.push_back(*p);
+    gen = ++g_net_gen;
     return FL_OK;
   }
 };
@@ -1398,10 +1406,13 @@ template <typename T> static fl_status dot_to(fl_op op, const Prob& pb, const vo
 // stay those of iteration k.  r holds the initial residual, x the initial
 // iterate; rr0 = r.r, ff = f.f.  Fallback: the FD preconditioner once
 // r.z <= 0 or 5 iterations fail to cut ||r|| by 1% (from the next iteration
-// enqueued).
+// enqueued).  graph != 0: iterations k >= 1 with the learned preconditioner
+// are replayed from two captured graphs (one per ring slot; kept in the
+// workspace while the Prob and the network's buffers stay the same), so that
+// the host enqueues one launch per iteration instead of some thirty.
 template <typename T>
-fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxit, double ff, double rr0, int* iters,
-                      double* rr_out, int* status, int* fell_back) {
+fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxit, double ff, double rr0, int graph,
+                      int* iters, double* rr_out, int* status, int* fell_back) {
   hipStream_t s = op->stream;
   const long N = op->N;
   const double thr = tol * tol * ff;
@@ -1421,12 +1432,14 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
   double* h = net->hfs;  // [8] seed, then the ring [2][8]
   h[4] = rr0;
   h[5] = 0.0;
-  HIPCHK(hipMemcpyAsync(fs + 4, h + 4, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+  h[6] = thr;
+  HIPCHK(hipMemcpyAsync(fs + 4, h + 4, 3 * sizeof(double), hipMemcpyHostToDevice, s));
   // the passes of an iteration check pb.sc->done (set with fs[5] by k_fcg_check)
   HIPCHK(hipMemsetAsync(&pb.sc->done, 0, sizeof(pb.sc->done), s));
   const int nupd = (int)std::min<long>(2048, nblocks_vec(N));
   const int ndot = (int)std::min<long>(1024, nblocks_vec(N));
-  auto enqueue = [&](int k, bool use_fd) -> fl_status {
+  // the launches of iteration k (its scalars into ring slot k & 1)
+  auto body = [&](int k, bool use_fd) -> fl_status {
     if (!use_fd) STCHK(learned_prec<T>(op, net, pb));
     else STCHK(fd_prec<T>(op, pb));
     LAUNCH(k_fcg_dots<T>, dim3(ndot), dim3(256), 0, s, pb, N, k > 0 ? 1 : 0);
@@ -1437,8 +1450,50 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
     STCHK((apply_seq<T, PRO_PLAIN, EPI_PQ>(op, pa, Iter{0, 0}, 1)));
     LAUNCH(k_totals2, dim3(1), dim3(256), 0, s, pb, (int)S_PQ, (int)S_DOT, fs, 2, 3);
     LAUNCH(k_fcg_update<T>, dim3(nupd), dim3(256), 0, s, pb, N, (const double*)fs);
-    LAUNCH(k_fcg_check, dim3(1), dim3(256), 0, s, pb, fs, thr);
+    LAUNCH(k_fcg_check, dim3(1), dim3(256), 0, s, pb, fs);
     HIPCHK(hipMemcpyAsync(h + 8 + 8 * (k & 1), fs, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    return FL_OK;
+  };
+  Workspace& w = op->ws[tix<T>()];
+  bool use_graph = graph != 0 && s != nullptr;
+  // Captured after iteration 0 has been enqueued eagerly: by then every table
+  // the iteration uses exists, so the capture allocates nothing.
+  auto capture = [&]() -> fl_status {
+    if (w.lexec[0] && w.lexec[1] && w.lgen == net->gen && w.lkey.size() == sizeof(Prob) &&
+        std::memcmp(w.lkey.data(), &pb, sizeof(Prob)) == 0)
+      return FL_OK;
+    for (hipGraphExec_t& g : w.lexec)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+    w.lkey.clear();
+    for (int slot = 0; slot < 2; ++slot) {
+      hipGraph_t g;
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const fl_status st = body(slot == 0 ? 2 : 1, false);
+      const hipError_t e = hipStreamEndCapture(s, &g);
+      if (st != FL_OK) return st;
+      HIPCHK(e);
+      const hipError_t ei = hipGraphInstantiate(&w.lexec[slot], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHK(ei);
+    }
+    w.lgen = net->gen;
+    w.lkey.assign((const unsigned char*)&pb, (const unsigned char*)&pb + sizeof(Prob));
+    return FL_OK;
+  };
+  bool captured = false;
+  auto enqueue = [&](int k, bool use_fd) -> fl_status {
+    if (k > 0 && !use_fd && use_graph) {
+      if (!captured) {
+        STCHK(capture());
+        captured = true;
+      }
+      HIPCHK(hipGraphLaunch(w.lexec[k & 1], s));
+    } else {
+      STCHK(body(k, use_fd));
+    }
     HIPCHK(hipEventRecord(net->ev[k & 1], s));
     return FL_OK;
   };
@@ -1494,9 +1549,9 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
   return FL_OK;
 }
 
-template fl_status learned_fcg<float>(fl_op, fl_net, const Prob&, double, int, double, double, int*, double*, int*,
+template fl_status learned_fcg<float>(fl_op, fl_net, const Prob&, double, int, double, double, int, int*, double*, int*,
                                       int*);
-template fl_status learned_fcg<double>(fl_op, fl_net, const Prob&, double, int, double, double, int*, double*, int*,
+template fl_status learned_fcg<double>(fl_op, fl_net, const Prob&, double, int, double, double, int, int*, double*, int*,
                                        int*);
 
 // scratch of the learned preconditioner on op's grid

@@ -226,6 +226,45 @@ def test_learned_fcg_falls_back_to_fd():
     assert res <= 1e-9
 
 
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_learned_fcg_graph_matches_eager(mixed):
+    # Iterations k >= 1 replayed from captured graphs must give the eager
+    # launches' result bit for bit: on the first solve (graphs captured), on a
+    # second with another right-hand side (graphs reused; the stopping
+    # threshold differs and is read from device memory), and after the
+    # network's weights change in place (graphs reused, new weights read).
+    _say("learned graph vs eager", mixed)
+    fl = _fl()
+    n, alpha = 96, 1.2
+    rhs = [bump_field(n, 2, 16, seed, width=(0.05, 0.2)) for seed in (5, 6)]
+    h = rhs[0][1]
+    rhs = [f for f, _ in rhs]
+    s = torch.cuda.Stream()
+    op = fl.Op(2, alpha, h, (n, n), stream=s)
+    th = (0.05 * NN.init_params(41, 2)).astype(np.float32)
+    net = fl.Net(stream=s, params=th)
+    M = O.Operator(2, alpha, h, (n, n)).dense()
+
+    def run(f_np, graph):
+        f = torch.from_numpy(f_np).cuda()
+        u, info = op.solve(f, tol=1e-9, opts=fl.solve_opts(pc=fl.FL_PC_LEARNED, net=net, mixed=mixed,
+                                                            graph=graph))
+        s.synchronize()
+        return u.cpu().numpy(), info
+
+    for step, f_np in enumerate(rhs + [rhs[0]]):
+        if step == 2:
+            net.set_params((0.04 * NN.init_params(42, 2)).astype(np.float32))
+        ug, ig = run(f_np, 1)
+        ue, ie = run(f_np, 0)
+        _say("step", step, "iters", ig["iters"], ie["iters"], "fell back", ig["fell_back"])
+        assert ig["iters"] == ie["iters"] >= 3
+        assert ig["fell_back"] == ie["fell_back"] == 0
+        assert np.array_equal(ug, ue)
+        res = np.linalg.norm(f_np.ravel() - M @ ug.ravel()) / np.linalg.norm(f_np)
+        assert res <= 2e-9, res
+
+
 def test_learned_rejects_masks_steps_and_3d():
     fl = _fl()
     s = torch.cuda.Stream()
