@@ -65,10 +65,11 @@ struct Workspace {
   int gK = 0, gpc = -1, gcap = 0;
   double gs0 = 0, gs1 = 0, gp0 = 0, gp1 = 0;
   const uint8_t* gmask = nullptr;
-  // graphs of flexible-CG iterations k >= 1 with the learned preconditioner,
-  // one per slot of the host scalar ring (lexec[k & 1]), valid for the
-  // network generation lgen and the solver Prob whose bytes are lkey
-  hipGraphExec_t lexec[2] = {nullptr, nullptr};
+  // graphs of flexible-CG iterations with the learned preconditioner: k >= 1
+  // per slot of the host scalar ring (lexec[k & 1]) and the first iteration
+  // (lexec[2]), valid for the network generation lgen and the solver Prob
+  // whose bytes are lkey
+  hipGraphExec_t lexec[3] = {nullptr, nullptr, nullptr};
   unsigned long long lgen = 0;
   std::vector<unsigned char> lkey;
 };

@@ -1406,10 +1406,11 @@ template <typename T> static fl_status dot_to(fl_op op, const Prob& pb, const vo
 // stay those of iteration k.  r holds the initial residual, x the initial
 // iterate; rr0 = r.r, ff = f.f.  Fallback: the FD preconditioner once
 // r.z <= 0 or 5 iterations fail to cut ||r|| by 1% (from the next iteration
-// enqueued).  graph != 0: iterations k >= 1 with the learned preconditioner
-// are replayed from two captured graphs (one per ring slot; kept in the
-// workspace while the Prob and the network's buffers stay the same), so that
-// the host enqueues one launch per iteration instead of some thirty.
+// enqueued).  graph != 0: iterations with the learned preconditioner are
+// replayed from three captured graphs (the first iteration, and one per ring
+// slot after it; kept in the workspace while the Prob and the network's
+// buffers stay the same), so that the host enqueues one launch per iteration
+// instead of some thirty.
 template <typename T>
 fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxit, double ff, double rr0, int graph,
                       int* iters, double* rr_out, int* status, int* fell_back) {
@@ -1456,10 +1457,10 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
   };
   Workspace& w = op->ws[tix<T>()];
   bool use_graph = graph != 0 && s != nullptr;
-  // Captured after iteration 0 has been enqueued eagerly: by then every table
-  // the iteration uses exists, so the capture allocates nothing.
+  // The sine-basis diagonal is built (once per op) before any capture, so
+  // that the captured launches allocate nothing.
   auto capture = [&]() -> fl_status {
-    if (w.lexec[0] && w.lexec[1] && w.lgen == net->gen && w.lkey.size() == sizeof(Prob) &&
+    if (w.lexec[0] && w.lexec[1] && w.lexec[2] && w.lgen == net->gen && w.lkey.size() == sizeof(Prob) &&
         std::memcmp(w.lkey.data(), &pb, sizeof(Prob)) == 0)
       return FL_OK;
     for (hipGraphExec_t& g : w.lexec)
@@ -1468,10 +1469,11 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
         g = nullptr;
       }
     w.lkey.clear();
-    for (int slot = 0; slot < 2; ++slot) {
+    STCHK(build_tau(op));
+    for (int slot = 0; slot < 3; ++slot) {
       hipGraph_t g;
       HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      const fl_status st = body(slot == 0 ? 2 : 1, false);
+      const fl_status st = body(slot == 0 ? 2 : slot == 1 ? 1 : 0, false);
       const hipError_t e = hipStreamEndCapture(s, &g);
       if (st != FL_OK) return st;
       HIPCHK(e);
@@ -1485,12 +1487,12 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
   };
   bool captured = false;
   auto enqueue = [&](int k, bool use_fd) -> fl_status {
-    if (k > 0 && !use_fd && use_graph) {
+    if (!use_fd && use_graph) {
       if (!captured) {
         STCHK(capture());
         captured = true;
       }
-      HIPCHK(hipGraphLaunch(w.lexec[k & 1], s));
+      HIPCHK(hipGraphLaunch(w.lexec[k == 0 ? 2 : k & 1], s));
     } else {
       STCHK(body(k, use_fd));
     }
