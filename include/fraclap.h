@@ -93,7 +93,9 @@ typedef struct {
   int maxit;         /* iteration cap (FP64 PCG) or inner cap (mixed); <= 0 -> default */
   double inner_tol;  /* mixed: relative tolerance of each inner FP32 solve; <= 0 -> 1e-4 */
   int use_x0;        /* 1: u holds the initial guess on entry */
-  int graph;         /* 1: replay the Krylov iteration as a captured hipGraph */
+  int graph;         /* 1: replay the Krylov iteration as a captured hipGraph (FL_PC_LEARNED: one
+                        graph launch per iteration, the graphs kept with the op's workspace
+                        until its Prob or the network's buffers change) */
   int poll_every;    /* iterations between host polls of the convergence flag (<= 0 -> 8) */
   int max_outer;     /* mixed: cap on refinement steps (<= 0 -> 12) */
   fl_net net;        /* FL_PC_LEARNED: the trained network (same stream as the op); else ignored */
