@@ -115,6 +115,23 @@ struct Dims {
   const double* stop = nullptr;
 };
 __device__ __forceinline__ bool stopped(const Dims& g) { return g.stop && *g.stop != 0.0; }
+
+// Learned-preconditioner input and output on the solver grid m0 x m1 x m2
+// (m0 = 1 in 2D) inside the padded network grid P0 x P1 x P2 (one image).
+struct PadGrid {
+  int m0, m1, m2, P0, P1, P2;
+};
+// The solver-grid glue of the learned preconditioner, done by the network's
+// first and last layers when G = 1 (T = float) or 2 (T = double): the input
+// layer takes x = r / s (zero outside the solver grid), the output layer
+// writes w = r + s y on the solver grid instead of y, with the RMS
+// s = sqrt(rr / N) read from the device (rr = r.r).
+struct NetGlue {
+  const void* r = nullptr;
+  void* w = nullptr;
+  const double* rr = nullptr;
+  PadGrid q = {};
+};
 __device__ __forceinline__ long pix(const Dims& g, int b, int z, int y, int x) {
   return ((((long)b * g.D + z) * g.H + y) * g.W + x) * CH;
 }
@@ -396,10 +413,10 @@ __global__ __launch_bounds__(256) void k_conv32(Stage st, const u16* __restrict_
 // of 16 (2 MFMA steps in 2D, 4 in 3D).  The A fragments (slot NL32 of the
 // packed weights) hold W^T[co][k]; each lane gathers its B fragment
 // X[k][pixel] from the staged (x, alpha - 1) slices.  Bias + ReLU, BF16 out.
-template <int KD>
+template <int KD, int G = 0>
 __global__ __launch_bounds__(256) void k_cin_mfma(const float* __restrict__ x, const float* __restrict__ alpha,
                                                   const u16* __restrict__ wpack, const float* __restrict__ bias,
-                                                  u16* __restrict__ out, Dims g, u16* __restrict__ pout) {
+                                                  u16* __restrict__ out, Dims g, u16* __restrict__ pout, NetGlue gl) {
   constexpr int K = 9 * KD, S = (2 * K + 15) / 16;
   __shared__ __align__(16) u16 tile[TY * TX * CP];  // output staging
   __shared__ unsigned xin[KD][SY * SX];             // bf16 pair (x, alpha - 1) per pixel
@@ -409,11 +426,25 @@ __global__ __launch_bounds__(256) void k_cin_mfma(const float* __restrict__ x, c
   if (b >= g.B) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const unsigned am1 = (unsigned)f2bf(alpha[b] - 1.f) << 16;
+  double inv_s = 0.0;
+  if constexpr (G != 0) {
+    const double ms = *gl.rr / ((double)gl.q.m0 * gl.q.m1 * gl.q.m2);
+    inv_s = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
+  }
   for (int e = threadIdx.x; e < KD * SY * SX; e += blockDim.x) {
     const int kz = e / (SY * SX), p = e % (SY * SX);
     const int zi = z + kz - (KD == 3 ? 1 : 0), yy = y0 + p / SX - 1, xx = x0 + p % SX - 1;
     const bool in = zi >= 0 && zi < g.D && yy >= 0 && yy < g.H && xx >= 0 && xx < g.W;
-    xin[kz][p] = in ? ((unsigned)f2bf(x[(((long)b * g.D + zi) * g.H + yy) * g.W + xx]) | am1) : 0u;
+    float xv = 0.f;
+    if constexpr (G == 0) {
+      if (in) xv = x[(((long)b * g.D + zi) * g.H + yy) * g.W + xx];
+    } else {  // r / s on the solver grid, zero in the padding (one image)
+      const bool inm = in && zi < gl.q.m0 && yy < gl.q.m1 && xx < gl.q.m2;
+      const long si = inm ? ((long)zi * gl.q.m1 + yy) * gl.q.m2 + xx : 0;
+      const double rv = G == 1 ? (double)((const float*)gl.r)[si] : ((const double*)gl.r)[si];
+      if (inm) xv = (float)(rv * inv_s);
+    }
+    xin[kz][p] = in ? ((unsigned)f2bf(xv) | am1) : 0u;
   }
   bf16x8 wf[S];
 #pragma unroll
@@ -454,9 +485,10 @@ __global__ __launch_bounds__(256) void k_cin_mfma(const float* __restrict__ x, c
 // MFMA with the taps as rows (slot NL32 + 1 of the packed weights: fragment
 // 2 kz + s holds W[9 kz + m][16 s + ...] in row m < 9); then each thread sums
 // y[p] += sum_m Z[p + offset(m)][m] for its output pixel.  FP32 out.
-template <int KD>
+template <int KD, int G = 0>
 __global__ __launch_bounds__(256) void k_out_mfma(const u16* __restrict__ c0, const u16* __restrict__ wpack,
-                                                  const float* __restrict__ bias, Dims g, float* __restrict__ yout) {
+                                                  const float* __restrict__ bias, Dims g, float* __restrict__ yout,
+                                                  NetGlue gl) {
   constexpr int NQ = SY * SX, NCH = (NQ + 31) / 32;
   __shared__ __align__(16) u16 tile[SY * SX * CH];  // unpadded: tile + zt fit four blocks per CU
   __shared__ float zt[NQ][9];
@@ -502,7 +534,20 @@ __global__ __launch_bounds__(256) void k_out_mfma(const u16* __restrict__ c0, co
     for (int m = 0; m < 9; ++m) yacc += zt[(ly + m / 3) * SX + lx + m % 3][m];
   }
   const int yo = y0 + ly, xo = x0 + lx;
-  if (yo < g.H && xo < g.W) yout[(((long)b * g.D + z) * g.H + yo) * g.W + xo] = yacc + bias[0];
+  if (yo < g.H && xo < g.W) {
+    const float yv = yacc + bias[0];
+    if constexpr (G == 0) {
+      yout[(((long)b * g.D + z) * g.H + yo) * g.W + xo] = yv;
+    } else if (z < gl.q.m0 && yo < gl.q.m1 && xo < gl.q.m2) {  // w = r + s y on the solver grid
+      const long N = (long)gl.q.m0 * gl.q.m1 * gl.q.m2;
+      const double sc = sqrt(fmax(*gl.rr, 0.0) / (double)N);
+      const long si = ((long)z * gl.q.m1 + yo) * gl.q.m2 + xo;
+      if constexpr (G == 1)
+        ((float*)gl.w)[si] = (float)((double)((const float*)gl.r)[si] + sc * (double)yv);
+      else
+        ((double*)gl.w)[si] = ((const double*)gl.r)[si] + sc * (double)yv;
+    }
+  }
 }
 
 // Pooled activation of a level (3D down path): one 8-channel chunk of one
@@ -910,34 +955,6 @@ __global__ void k_gather(const float* __restrict__ R, const float* __restrict__ 
   if (i % npix == 0) a[k] = A[idx[k]];
 }
 
-// Learned-preconditioner input and output on the solver grid m0 x m1 x m2
-// (m0 = 1 in 2D) inside the padded network grid P0 x P1 x P2: xin = r / s,
-// w = r + s y, with the RMS s = sqrt(rr / N) read from the device (rr = r.r).
-struct PadGrid {
-  int m0, m1, m2, P0, P1, P2;
-};
-template <typename T>
-__global__ void k_net_in(const T* __restrict__ r, float* __restrict__ xin, PadGrid q, const double* __restrict__ rr) {
-  if (rr[1] != 0.0) return;  // flexible CG already done (rr[1] is its flag)
-  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= (long)q.P0 * q.P1 * q.P2) return;
-  const double ms = *rr / ((double)q.m0 * q.m1 * q.m2);
-  const double inv_s = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
-  const int xx = (int)(i % q.P2), yy = (int)((i / q.P2) % q.P1), zz = (int)(i / ((long)q.P1 * q.P2));
-  const bool in = zz < q.m0 && yy < q.m1 && xx < q.m2;
-  xin[i] = in ? (float)((double)r[((long)zz * q.m1 + yy) * q.m2 + xx] * inv_s) : 0.f;
-}
-template <typename T>
-__global__ void k_net_out(const T* __restrict__ r, const float* __restrict__ y, T* __restrict__ w, PadGrid q,
-                          const double* __restrict__ rr) {
-  if (rr[1] != 0.0) return;  // flexible CG already done
-  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long N = (long)q.m0 * q.m1 * q.m2;
-  if (i >= N) return;
-  const double sc = sqrt(fmax(*rr, 0.0) / (double)N);
-  const int xx = (int)(i % q.m2), yy = (int)((i / q.m2) % q.m1), zz = (int)(i / ((long)q.m1 * q.m2));
-  w[i] = (T)((double)r[i] + sc * (double)y[((long)zz * q.P1 + yy) * q.P2 + xx]);
-}
 
 // Flexible CG scalars live on the device: fs[0] = r.z, fs[1] = z.q_old,
 // fs[2] = p.q, fs[3] = p.r, fs[4] = r.r, fs[5] = done flag (1 once r.r is
@@ -1125,7 +1142,6 @@ struct fl_net_s {
   int idx_cap = 0;
   // learned-preconditioner scratch on a solver grid
   long pcap = 0;
-  float* pin = nullptr;  // network input on the padded grid
   void* pw = nullptr;
   float* palpha = nullptr;
   double* fs = nullptr;   // device scalars of flexible CG
@@ -1195,7 +1211,8 @@ static fl_status check_grid(const fl_net net, int B, int D, int H, int W) {
 }
 
 // forward pass on x (FP32 [B][D][H][W]) and alphas (device FP32 [B]) into net->y
-template <int KD> static fl_status net_forward_t(fl_net net, const float* x, const float* alpha, Dims g0) {
+template <int KD, int G> static fl_status net_forward_t(fl_net net, const float* x, const float* alpha, Dims g0,
+                                                        const NetGlue& gl) {
   using P = PL<KD>;
   hipStream_t s = net->stream;
   u16** a = net->act;
@@ -1207,8 +1224,8 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
   // pooled inputs of the down path, p[l] = pool a[l-1]: in 2D every layer
   // writes the next one's from its output tile, in 3D k_pool forms it
   u16* const* pl = net->pool;
-  LAUNCH(k_cin_mfma<KD>, conv_grid(g0), dim3(256), 0, s, x, alpha, fw(NL32), th + P::OFF_CIN_B, a[A0], g0,
-         KD == 1 ? pl[1] : (u16*)nullptr);
+  LAUNCH((k_cin_mfma<KD, G>), conv_grid(g0), dim3(256), 0, s, x, alpha, fw(NL32), th + P::OFF_CIN_B, a[A0], g0,
+         KD == 1 ? pl[1] : (u16*)nullptr, gl);
   Dims g = g0;
   // down path
   const int lay[3] = {LD1, LD2, LD3};
@@ -1236,17 +1253,20 @@ template <int KD> static fl_status net_forward_t(fl_net net, const float* x, con
     LAUNCH((k_conv32<SM_UPADD, EPI_RELU, KD>), conv_grid(g), dim3(256), 0, s, st, fw(ulay[k]), bias(ulay[k]),
            a[adst[k]], g, (u16*)nullptr);
   }
-  LAUNCH(k_out_mfma<KD>, conv_grid(g0), dim3(256), 0, s, (const u16*)a[C0], fw(NL32 + 1),
-         th + P::OFF_OUT + P::K * CH, g0, net->y);
+  LAUNCH((k_out_mfma<KD, G>), conv_grid(g0), dim3(256), 0, s, (const u16*)a[C0], fw(NL32 + 1),
+         th + P::OFF_OUT + P::K * CH, g0, net->y, gl);
   return FL_OK;
 }
 
+// G = 0: input x, output net->y.  G = 1 / 2: the solver-grid glue gl with
+// T = float / double (x unused, B = 1).
+template <int G = 0>
 static fl_status net_forward(fl_net net, const float* x, const float* alpha, int B, int D, int H, int W,
-                             const double* stop = nullptr) {
+                             const double* stop = nullptr, const NetGlue& gl = NetGlue{}) {
   STCHK(check_grid(net, B, D, H, W));
   STCHK(net_reserve(net, B, D, H, W));
   const Dims g{B, D, H, W, stop};
-  return net->kd == 3 ? net_forward_t<3>(net, x, alpha, g) : net_forward_t<1>(net, x, alpha, g);
+  return net->kd == 3 ? net_forward_t<3, G>(net, x, alpha, g, gl) : net_forward_t<1, G>(net, x, alpha, g, gl);
 }
 
 // reverse pass from net->gy (dL/dy) into net->g (parameter gradient), after net_forward on the same input
@@ -1364,14 +1384,13 @@ static PadGrid pad_grid(fl_op op) {
 // z = B (r + s N(r/s, alpha)), B the inverse of the sine-basis diagonal; s
 // from the device value r.r in net->fs[4].
 template <typename T> static fl_status learned_prec(fl_op op, fl_net net, const Prob& pb) {
-  hipStream_t s = op->stream;
   const PadGrid q = pad_grid(op);
-  const long np = (long)q.P0 * q.P1 * q.P2;
-  LAUNCH(k_net_in<T>, dim3(nblocks_vec(np)), dim3(256), 0, s, (const T*)pb.r, net->pin, q,
-         (const double*)(net->fs + 4));
-  STCHK(net_forward(net, net->pin, net->palpha, 1, q.P0, q.P1, q.P2, net->fs + 5));
-  LAUNCH(k_net_out<T>, dim3(nblocks_vec(op->N)), dim3(256), 0, s, (const T*)pb.r, (const float*)net->y, (T*)net->pw, q,
-         (const double*)(net->fs + 4));
+  NetGlue gl;
+  gl.r = pb.r;
+  gl.w = net->pw;
+  gl.rr = net->fs + 4;
+  gl.q = q;
+  STCHK((net_forward<sizeof(T) == 4 ? 1 : 2>(net, nullptr, net->palpha, 1, q.P0, q.P1, q.P2, net->fs + 5, gl)));
   Prob pz = pb;
   STCHK(set_precond<T>(op, pz, FL_PC_SPECTRAL));
   pz.in = net->pw;
@@ -1563,13 +1582,10 @@ fl_status learned_prepare(fl_op op, fl_net net, size_t elem) {
   if ((op->d == 3) != (net->kd == 3)) return fail(FL_E_INVALID, "the network and the op differ in dimension");
   if (net->stream != op->stream) return fail(FL_E_INVALID, "net and op must share one stream");
   const PadGrid q = pad_grid(op);
-  const long np = (long)q.P0 * q.P1 * q.P2;
   STCHK(check_grid(net, 1, q.P0, q.P1, q.P2));
-  const long need = std::max<long>(np, op->N);
-  if (net->pcap < need) {
-    STCHK(net->alloc((void**)&net->pin, (size_t)np * sizeof(float)));
+  if (net->pcap < op->N) {
     STCHK(net->alloc(&net->pw, (size_t)op->N * sizeof(double)));
-    net->pcap = need;
+    net->pcap = op->N;
   }
   if (!net->palpha) STCHK(net->alloc((void**)&net->palpha, sizeof(float)));
   if (!net->fs) STCHK(net->alloc((void**)&net->fs, 8 * sizeof(double)));
@@ -1600,11 +1616,11 @@ template <int KD> static fl_status profile_one(fl_net net, int which, Dims g) {
   }
   if (which == 2) {
     LAUNCH(k_cin_mfma<KD>, conv_grid(g), dim3(256), 0, s, (const float*)net->xb, (const float*)net->ab,
-           (const u16*)(net->fw + NL32 * P::PACK), (const float*)(net->th + P::OFF_CIN_B), a[A0], g, (u16*)nullptr);
+           (const u16*)(net->fw + NL32 * P::PACK), (const float*)(net->th + P::OFF_CIN_B), a[A0], g, (u16*)nullptr, NetGlue{});
     return FL_OK;
   }
   LAUNCH(k_out_mfma<KD>, conv_grid(g), dim3(256), 0, s, (const u16*)a[C0],
-         (const u16*)(net->fw + (NL32 + 1) * P::PACK), (const float*)(net->th + P::OFF_OUT + P::K * CH), g, net->y);
+         (const u16*)(net->fw + (NL32 + 1) * P::PACK), (const float*)(net->th + P::OFF_OUT + P::K * CH), g, net->y, NetGlue{});
   return FL_OK;
 }
 
