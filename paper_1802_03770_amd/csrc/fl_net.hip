@@ -1593,9 +1593,8 @@ fl_status learned_prepare(fl_op op, fl_net net, size_t elem) {
     return fail(FL_E_NOMEM, "pinned host scalars");
   for (hipEvent_t& e : net->ev)
     if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  const float a = (float)op->alpha;
-  HIPCHK(hipMemcpyAsync(net->palpha, &a, sizeof(float), hipMemcpyHostToDevice, op->stream));
-  HIPCHK(hipStreamSynchronize(op->stream));
+  // alpha as a kernel argument: no copy from host memory, so no host wait
+  LAUNCH(k_fill<float>, dim3(1), dim3(64), 0, op->stream, net->palpha, (float)op->alpha, 1L);
   STCHK(net_reserve(net, 1, q.P0, q.P1, q.P2));
   (void)elem;
   return FL_OK;
