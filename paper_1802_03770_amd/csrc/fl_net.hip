@@ -995,20 +995,18 @@ template <typename T> __global__ __launch_bounds__(256) void k_fcg_dots(Prob pb,
   put_partial(pb, S_RZ0, a, gridDim.x, blockIdx.x);
   put_partial(pb, S_RZ1, c, gridDim.x, blockIdx.x);
 }
-// totals of two sites into fs[i0], fs[i1] (one workgroup)
-__global__ void k_totals2(Prob pb, int s0, int s1, double* __restrict__ fs, int i0, int i1) {
-  const double t0 = get_total(pb, s0);
-  const double t1 = get_total(pb, s1);
-  if (threadIdx.x == 0) {
-    fs[i0] = t0;
-    fs[i1] = t1;
-  }
-}
 // p = z + beta p, beta = -z.q_old / p_old.q_old (0 on the first iteration);
-// p.r partials (site S_DOT)
+// p.r partials (site S_DOT).  Every block sums the r.z and z.q_old partials
+// itself (same order in every block); block 0 stores them in fs[0], fs[1].
 template <typename T>
-__global__ __launch_bounds__(256) void k_fcg_dir(Prob pb, long n, const double* __restrict__ fs, int first) {
-  const double beta = (first || !(fs[2] > 0.0)) ? 0.0 : -fs[1] / fs[2];
+__global__ __launch_bounds__(256) void k_fcg_dir(Prob pb, long n, double* __restrict__ fs, int first) {
+  const double rz = get_total(pb, S_RZ0);
+  const double zq = get_total(pb, S_RZ1);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    fs[0] = rz;
+    fs[1] = zq;
+  }
+  const double beta = (first || !(fs[2] > 0.0)) ? 0.0 : -zq / fs[2];
   const T* z = (const T*)pb.z;
   const T* r = (const T*)pb.r;
   T* p = (T*)pb.p;
@@ -1039,11 +1037,18 @@ __global__ __launch_bounds__(256) void k_fcg_dir(Prob pb, long n, const double* 
   put_partial(pb, S_DOT, acc, gridDim.x, blockIdx.x);
 }
 // alpha = p.r / p.q; x += alpha p; r -= alpha q; r.r partials (site S_RR).
-// Nothing happens once the done flag is set (a speculative iteration).
-template <typename T> __global__ __launch_bounds__(256) void k_fcg_update(Prob pb, long n, const double* __restrict__ fs) {
+// Every block sums the p.q and p.r partials itself; block 0 stores them in
+// fs[2], fs[3].  Nothing happens once the done flag is set (a speculative
+// iteration).
+template <typename T> __global__ __launch_bounds__(256) void k_fcg_update(Prob pb, long n, double* __restrict__ fs) {
   if (fs[5] != 0.0) return;  // uniform over the grid
-  const double pq = fs[2];
-  const double alpha = (pq > 0.0 && isfinite(pq)) ? fs[3] / pq : 0.0;
+  const double pq = get_total(pb, S_PQ);
+  const double pr = get_total(pb, S_DOT);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    fs[2] = pq;
+    fs[3] = pr;
+  }
+  const double alpha = (pq > 0.0 && isfinite(pq)) ? pr / pq : 0.0;
   T* x = (T*)pb.x;
   T* r = (T*)pb.r;
   const T* p = (const T*)pb.p;
@@ -1463,13 +1468,11 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
     if (!use_fd) STCHK(learned_prec<T>(op, net, pb));
     else STCHK(fd_prec<T>(op, pb));
     LAUNCH(k_fcg_dots<T>, dim3(ndot), dim3(256), 0, s, pb, N, k > 0 ? 1 : 0);
-    LAUNCH(k_totals2, dim3(1), dim3(256), 0, s, pb, (int)S_RZ0, (int)S_RZ1, fs, 0, 1);
-    LAUNCH(k_fcg_dir<T>, dim3(ndot), dim3(256), 0, s, pb, N, (const double*)fs, k == 0 ? 1 : 0);
+    LAUNCH(k_fcg_dir<T>, dim3(ndot), dim3(256), 0, s, pb, N, fs, k == 0 ? 1 : 0);
     Prob pa = pb;
     pa.in = pb.p;
     STCHK((apply_seq<T, PRO_PLAIN, EPI_PQ>(op, pa, Iter{0, 0}, 1)));
-    LAUNCH(k_totals2, dim3(1), dim3(256), 0, s, pb, (int)S_PQ, (int)S_DOT, fs, 2, 3);
-    LAUNCH(k_fcg_update<T>, dim3(nupd), dim3(256), 0, s, pb, N, (const double*)fs);
+    LAUNCH(k_fcg_update<T>, dim3(nupd), dim3(256), 0, s, pb, N, fs);
     LAUNCH(k_fcg_check, dim3(1), dim3(256), 0, s, pb, fs);
     HIPCHK(hipMemcpyAsync(h + 8 + 8 * (k & 1), fs, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
     return FL_OK;
