@@ -228,11 +228,13 @@ def test_learned_fcg_falls_back_to_fd():
 
 @pytest.mark.parametrize("mixed", [0, 1])
 def test_learned_fcg_graph_matches_eager(mixed):
-    # Iterations k >= 1 replayed from captured graphs must give the eager
-    # launches' result bit for bit: on the first solve (graphs captured), on a
-    # second with another right-hand side (graphs reused; the stopping
-    # threshold differs and is read from device memory), and after the
-    # network's weights change in place (graphs reused, new weights read).
+    # Iterations replayed from captured graphs must give the eager launches'
+    # result bit for bit: on the first solve (graphs captured), on a second
+    # with another right-hand side (graphs reused; the stopping threshold
+    # differs and is read from device memory), after the network's weights
+    # change in place (graphs reused, new weights read), and after a larger
+    # forward pass has reallocated the network's activations (graphs captured
+    # again: the old ones hold the old buffers).
     _say("learned graph vs eager", mixed)
     fl = _fl()
     n, alpha = 96, 1.2
@@ -252,9 +254,13 @@ def test_learned_fcg_graph_matches_eager(mixed):
         s.synchronize()
         return u.cpu().numpy(), info
 
-    for step, f_np in enumerate(rhs + [rhs[0]]):
+    for step, f_np in enumerate(rhs + [rhs[0], rhs[1]]):
         if step == 2:
             net.set_params((0.04 * NN.init_params(42, 2)).astype(np.float32))
+        if step == 3:
+            with torch.cuda.stream(s):
+                net.forward(torch.zeros((4, 256, 256), dtype=torch.float32, device="cuda"), alpha)
+            s.synchronize()
         ug, ig = run(f_np, 1)
         ue, ie = run(f_np, 0)
         _say("step", step, "iters", ig["iters"], ie["iters"], "fell back", ig["fell_back"])
