@@ -1461,8 +1461,8 @@ fl_status learned_fcg(fl_op op, fl_net net, const Prob& pb, double tol, int maxi
   HIPCHK(hipMemcpyAsync(fs + 4, h + 4, 3 * sizeof(double), hipMemcpyHostToDevice, s));
   // the passes of an iteration check pb.sc->done (set with fs[5] by k_fcg_check)
   HIPCHK(hipMemsetAsync(&pb.sc->done, 0, sizeof(pb.sc->done), s));
-  const int nupd = (int)std::min<long>(2048, nblocks_vec(N));
-  const int ndot = (int)std::min<long>(1024, nblocks_vec(N));
+  const int nupd = (int)std::min<long>(1024, nblocks_vec(N));
+  const int ndot = (int)std::min<long>(512, nblocks_vec(N));
   // the launches of iteration k (its scalars into ring slot k & 1)
   auto body = [&](int k, bool use_fd) -> fl_status {
     if (!use_fd) STCHK(learned_prec<T>(op, net, pb));
